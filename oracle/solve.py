@@ -1,0 +1,164 @@
+"""Oracle solver pieces (Sections 4 and 6).
+
+* right-hand side -u_inc = -exp(i k d.x) (Section 2, plane wave; Section 6
+  equation plane wave parameters);
+* the multi-body system (1/2 I + D) mu = -u_inc in block form (Section 4,
+  equation linearsys): diagonal blocks are the self blocks (identical up to
+  rigid motion, so computed in the body frame), off-diagonal blocks are the
+  smooth inter-body kernel;
+* dense LU (numpy / LAPACK) and right-preconditioned restarted GMRES with the
+  block-diagonal preconditioner built from the self blocks (Section 6, the
+  paragraph on the hybrid solver);
+* far field of the double-layer density:
+  u_inf(xhat) = (1/4 pi) sum_j (-i k xhat.n_j) e^{-i k xhat.y_j} mu_j |J_j| w_j
+  (Section 6 defines the single-layer form; the double-layer form follows from
+  the normal derivative of the same asymptotic expansion).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import pairsum
+from . import selfblock
+
+FOUR_PI = 4.0 * math.pi
+
+
+def rhs_planewave(disc, k_per_problem, dirs):
+    """b = -exp(i k d.x); dirs (nrhs, 3).  Returns (N, nrhs)."""
+    k = np.asarray(k_per_problem)[disc.problem]
+    return -np.exp(1j * k[:, None] * (disc.pos @ np.asarray(dirs).T))
+
+
+def self_blocks(disc, k_per_problem, body_ids=None):
+    body_ids = range(len(disc.bodies)) if body_ids is None else body_ids
+    out = {}
+    for b in body_ids:
+        p = disc.problem[disc.offsets[b]]
+        out[b] = selfblock.self_block(disc.bodies[b], float(k_per_problem[p]))
+    return out
+
+
+def dense_matrix(disc, k_per_problem, blocks):
+    """Full (1/2 I + D) as a dense matrix (small problems only)."""
+    n = disc.pos.shape[0]
+    A = np.zeros((n, n), dtype=np.complex128)
+    for j in range(n):
+        e = np.zeros(n, dtype=np.complex128)
+        e[j] = 1.0
+        A[:, j] = pairsum.pair_sum(disc, k_per_problem, e)
+    for b, B in blocks.items():
+        s = slice(disc.offsets[b], disc.offsets[b + 1])
+        A[s, s] = B
+    return A
+
+
+def dense_matrix_fast(disc, k_per_problem, blocks):
+    """Same matrix, off-diagonal entries written directly from the kernel."""
+    n = disc.pos.shape[0]
+    k = np.asarray(k_per_problem)[disc.problem]
+    d = disc.pos[None, :, :] - disc.pos[:, None, :]
+    rho = np.sqrt(np.sum(d * d, axis=-1))
+    same = (disc.body[:, None] == disc.body[None, :]) | (disc.problem[:, None] != disc.problem[None, :])
+    rs = np.where(same, 1.0, rho)
+    kk = k[:, None]
+    A = (1j * kk / rs - 1.0 / rs ** 2) * np.exp(1j * kk * rs) / (FOUR_PI * rs) \
+        * np.sum(disc.aw[None, :, :] * d, axis=-1)
+    A = np.where(same, 0.0, A)
+    for b, B in blocks.items():
+        s = slice(disc.offsets[b], disc.offsets[b + 1])
+        A[s, s] = B
+    return A
+
+
+def apply_operator(disc, k_per_problem, blocks, mu):
+    """(1/2 I + D) mu, matrix-free for the inter-body part."""
+    out = pairsum.pair_sum(disc, k_per_problem, mu)
+    for b, B in blocks.items():
+        s = slice(disc.offsets[b], disc.offsets[b + 1])
+        out[s] += B @ mu[s]
+    return out
+
+
+def gmres(apply_a, apply_minv, b, tol=1e-10, restart=100, maxit=1000):
+    """Right-preconditioned restarted GMRES (x0 = 0), classical Gram-Schmidt
+    with one reorthogonalisation, Givens rotations; stops on the true relative
+    residual ||b - A x|| / ||b|| <= tol.  Returns x, iterations, history."""
+    n = b.shape[0]
+    x = np.zeros(n, dtype=np.complex128)
+    bnorm = np.linalg.norm(b)
+    hist = []
+    its = 0
+    r = b.copy()
+    while its < maxit:
+        beta = np.linalg.norm(r)
+        if beta / bnorm <= tol:
+            break
+        V = np.zeros((restart + 1, n), dtype=np.complex128)
+        H = np.zeros((restart + 1, restart), dtype=np.complex128)
+        cs = np.zeros(restart, dtype=np.complex128)
+        sn = np.zeros(restart, dtype=np.complex128)
+        g = np.zeros(restart + 1, dtype=np.complex128)
+        g[0] = beta
+        V[0] = r / beta
+        j_end = 0
+        for j in range(restart):
+            w = apply_a(apply_minv(V[j]))
+            h = V[: j + 1].conj() @ w
+            w = w - h @ V[: j + 1]
+            h2 = V[: j + 1].conj() @ w
+            w = w - h2 @ V[: j + 1]
+            h = h + h2
+            hn = np.linalg.norm(w)
+            H[: j + 1, j] = h
+            H[j + 1, j] = hn
+            if hn > 0:
+                V[j + 1] = w / hn
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = math.hypot(abs(H[j, j]), abs(H[j + 1, j]))
+            cs[j] = abs(H[j, j]) / den if den > 0 else 1.0
+            sn[j] = (H[j, j] / abs(H[j, j]) * np.conj(H[j + 1, j]) / den) if abs(H[j, j]) > 0 else 1.0
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -np.conj(sn[j]) * g[j]
+            g[j] = cs[j] * g[j]
+            its += 1
+            j_end = j + 1
+            hist.append(abs(g[j + 1]) / bnorm)
+            if abs(g[j + 1]) / bnorm <= tol * 0.5 or its >= maxit:
+                break
+        y = np.linalg.solve(np.triu(H[:j_end, :j_end]), g[:j_end])
+        x = x + apply_minv(y @ V[:j_end])
+        r = b - apply_a(x)
+    return x, its, hist
+
+
+def solve(disc, k_per_problem, blocks, b, method="gmres", tol=1e-10, restart=100, maxit=1000):
+    """Solve (1/2 I + D) mu = b; b is (N,) complex."""
+    if method == "dense":
+        A = dense_matrix_fast(disc, k_per_problem, blocks)
+        return np.linalg.solve(A, b), 0, []
+    inv = {bb: np.linalg.inv(B) for bb, B in blocks.items()}
+
+    def minv(v):
+        out = np.empty_like(v)
+        for bb, Bi in inv.items():
+            s = slice(disc.offsets[bb], disc.offsets[bb + 1])
+            out[s] = Bi @ v[s]
+        return out
+
+    return gmres(lambda v: apply_operator(disc, k_per_problem, blocks, v), minv, b,
+                 tol=tol, restart=restart, maxit=maxit)
+
+
+def far_field(disc, k_per_problem, mu, xhat):
+    """u_inf at unit directions xhat (ndir, 3); mu (N,) -> (ndir,)."""
+    k = float(np.asarray(k_per_problem)[0])
+    ph = np.exp(-1j * k * (xhat @ disc.pos.T))            # (ndir, N)
+    nd = xhat @ disc.aw.T                                  # xhat . n |J| w
+    return (ph * (-1j * k) * nd) @ mu / FOUR_PI
