@@ -1,0 +1,179 @@
+/*
+ * qax.h -- C interface of the MI355X (gfx950) multi-body Helmholtz
+ * double-layer Nystrom solver.
+ *
+ * The operator is the second-kind double-layer equation for sound-soft
+ * scattering by many quasi-axisymmetric bodies,
+ *     (1/2 I + D) mu = -u_inc,                                  (Section 4)
+ * with diagonal (self) blocks built by product integration over modal Green's
+ * functions (Sections 3.1-3.4) and off-diagonal (inter-body) blocks applied
+ * on the fly as a smooth Gauss-Legendre x trapezoidal pair sum (Section 4).
+ *
+ * Conventions shared by every call
+ *  - Every call returns a qax_status; QAX_OK (0) on success.  No C++ exception
+ *    and no abort crosses this interface.  On failure qax_last_error() holds a
+ *    message.
+ *  - Complex arrays are interleaved (re, im) pairs: complex128 = two doubles,
+ *    complex64 = two floats (the memory of torch.complex128 / complex64).
+ *  - Arrays of unknowns are node-major with right-hand sides fastest: element
+ *    (node i, rhs r) is at index i * nrhs + r.  Node order is body, then panel,
+ *    then Gauss-Legendre index, then azimuthal index (azimuth fastest).
+ *  - Pointers named d_* are DEVICE pointers on the handle's device; all other
+ *    pointers are host pointers.  The caller owns every buffer it passes in;
+ *    the library owns the device memory it allocates until qax_destroy().
+ *  - Work is enqueued on the stream given to qax_create; each call returns
+ *    after that stream has completed the call's work.
+ *  - Call order: qax_build -> qax_assemble_self -> apply / solve / far field.
+ *    Calls out of order return QAX_ERR_STATE.
+ *  - One handle per host thread; handles are independent.
+ */
+#ifndef QAX_H
+#define QAX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qax_problem qax_problem;
+
+typedef enum {
+  QAX_OK = 0,
+  QAX_ERR_ARG = 1,     /* invalid argument (sizes, NaN/Inf, null pointers)   */
+  QAX_ERR_DEVICE = 2,  /* HIP runtime error                                   */
+  QAX_ERR_NOMEM = 3,   /* device allocation failed                            */
+  QAX_ERR_NOCONV = 4,  /* iterative solver did not reach the tolerance        */
+  QAX_ERR_STATE = 5    /* call out of order                                   */
+} qax_status;
+
+typedef enum {
+  QAX_FP64 = 0,   /* every step in FP64                                        */
+  QAX_MIXED = 1   /* inter-body pair sum in FP32 with compensated accumulation,
+                     preconditioner in FP32, inside FP64 iterative refinement  */
+} qax_prec;
+
+typedef enum {
+  QAX_SPHERE = 0,   /* r = a cos t, z = a sin t                               */
+  QAX_SPHEROID = 1, /* r = a cos t, z = c sin t                               */
+  QAX_PEANUT = 2    /* polar radius a (1 + c cos 2 psi), psi = polar angle     */
+} qax_shape;
+
+/* One body.  Generating curve over t in [-pi/2, pi/2] (south to north),
+ * centreline bent into the circle of curvature kappa tangent to the z-axis,
+ * p = kappa z^2 / (1 + sqrt(1 - kappa^2 z^2)), q = 0 (the quasi-axisymmetric
+ * surface of Section 2, equation para_quasi).  n_panels uniform panels of 16
+ * Gauss-Legendre nodes in t times n_theta = 2N azimuthal nodes theta_j = j pi/N
+ * (Section 3.1).  World position x = R x0 + centre, R = Rz(theta1) Ry(theta2)
+ * (Section 6.2, Example 5).  `problem` selects the independent scattering
+ * problem (0..n_problems-1) the body belongs to; bodies of one problem must be
+ * contiguous and problems in increasing order. */
+typedef struct {
+  int32_t shape;
+  int32_t n_panels;   /* 1..64                                              */
+  int32_t n_theta;    /* even, 4..64                                        */
+  int32_t problem;
+  double a, c;        /* shape parameters (see qax_shape)                   */
+  double kappa;       /* 0 <= kappa, kappa * max|z| < 1                       */
+  double theta1, theta2;
+  double centre[3];
+} qax_body;
+
+typedef struct {
+  int32_t iters;        /* Krylov iterations, summed over restarts/refinements   */
+  int32_t outer_iters;  /* refinement steps (QAX_MIXED) or restarts (QAX_FP64)   */
+  double rel_res;       /* final true relative residual ||b - A mu|| / ||b||,
+                           maximum over right-hand sides and problems            */
+  double t_setup_s;     /* unused by qax_solve (reported by qax_assemble_self)   */
+  double t_solve_s;     /* wall time of the solve                                */
+} qax_info;
+
+/* Create a handle on HIP device `device`, enqueuing on `hip_stream`
+ * (a hipStream_t, or NULL for the default stream). */
+qax_status qax_create(int device, void* hip_stream, qax_problem** out);
+void qax_destroy(qax_problem* p);
+/* Message of the last failed call on this handle ("" if none). */
+const char* qax_last_error(const qax_problem* p);
+
+/* Build nodes, weights and outward normals of all bodies on the device
+ * (Sections 2, 3.1; rigid motions of Section 6.2).  k_per_problem[n_problems]
+ * are the wavenumbers (k >= 0).  Bodies with identical shape, discretisation
+ * and wavenumber share one self block (Section 4: congruent bodies have equal
+ * diagonal blocks whatever their rigid motion). */
+qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t n_bodies,
+                     const double* k_per_problem, int32_t n_problems);
+
+/* Number of unknowns and, if body_offsets is non-NULL, the n_bodies+1 node
+ * offsets of the bodies (host array). */
+qax_status qax_size(const qax_problem* p, int64_t* n_unknowns, int64_t* body_offsets);
+
+/* Copy out node positions and area-weighted normals n |J| (pi/N) omega (the
+ * smooth-rule weight times the unit normal, Section 3.1 equation sx), each as
+ * (N, 3) row-major FP64 device arrays. */
+qax_status qax_nodes(const qax_problem* p, double* d_pos, double* d_aw);
+
+/* Assemble every distinct self block B = 1/2 I + D_bb in FP64 (Sections
+ * 3.1-3.4: modal Green's functions by recurrence, FFT and convolution; product
+ * integration in s), then its inverse in FP64 and an FP32 copy of the inverse
+ * (the block-diagonal preconditioner of Section 6).  *t_setup_s (may be NULL)
+ * receives the wall time. */
+qax_status qax_assemble_self(qax_problem* p, double* t_setup_s);
+
+/* Copy the self block of body `body` (n_b x n_b complex128, row-major: row =
+ * target node, column = source node) into d_out.  inverse != 0 copies B^-1. */
+qax_status qax_self_block(const qax_problem* p, int32_t body, int32_t inverse, void* d_out);
+
+/* Inter-body pair sum only (Section 4): d_out = D_off d_mu, i.e. for every
+ * node x_i the sum over nodes y_j of other bodies of the same problem of
+ * (ik/r - 1/r^2) e^{ikr}/(4 pi r) n_j.(y_j - x_i) |J_j| (pi/N) omega_j mu_j.
+ * d_mu, d_out: N x nrhs complex128.  Needs only qax_build. */
+qax_status qax_pair_sum(qax_problem* p, qax_prec prec, const void* d_mu, void* d_out, int32_t nrhs);
+
+/* Block-diagonal apply: d_out_b = M_b d_v_b for every body, M_b = B_b
+ * (inverse == 0) or B_b^-1 (inverse != 0); prec QAX_MIXED uses the FP32 copy
+ * of B_b^-1 with FP64 accumulation.  N x nrhs complex128. */
+qax_status qax_block_apply(qax_problem* p, int32_t inverse, qax_prec prec,
+                           const void* d_v, void* d_out, int32_t nrhs);
+
+/* Full operator: d_out = (1/2 I + D) d_mu (self blocks + pair sum). */
+qax_status qax_apply(qax_problem* p, qax_prec prec, const void* d_mu, void* d_out, int32_t nrhs);
+
+/* Right-hand side b = -exp(i k d.x) (Section 2, plane wave).  dirs: host,
+ * n_problems x nrhs x 3 unit vectors.  d_out: N x nrhs complex128. */
+qax_status qax_rhs(qax_problem* p, const double* dirs, int32_t nrhs, void* d_out);
+
+/* Solve (1/2 I + D) mu = -u_inc for nrhs plane waves (dirs as in qax_rhs) by
+ * right-preconditioned restarted GMRES with the block-diagonal preconditioner
+ * (Section 6).  QAX_FP64: FP64 throughout.  QAX_MIXED: FP64 iterative
+ * refinement around an inner GMRES whose operator applies the FP32 pair sum
+ * and the FP32 inverse blocks; residuals and orthogonalisation stay FP64.
+ * Stops when ||b - A mu|| / ||b|| <= tol for every right-hand side and
+ * problem; otherwise returns QAX_ERR_NOCONV after maxit inner iterations with
+ * the best iterate in d_mu_out and info filled.  Single-problem, single-body
+ * systems of at most 4096 unknowns (e.g. two spheres) may instead be solved
+ * directly with qax_solve_dense. */
+qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dirs, int32_t nrhs,
+                     double tol, int32_t maxit, void* d_mu_out, qax_info* info);
+
+/* Dense direct solve of the full system (all blocks assembled on the device,
+ * Gauss-Jordan inversion in FP64) for N <= 8192; d_mu_out N x nrhs. */
+qax_status qax_solve_dense(qax_problem* p, const double* dirs, int32_t nrhs, void* d_mu_out);
+
+/* Far field of the double-layer density (problem 0 only):
+ * u_inf(xhat) = (1/4 pi) sum_j (-i k xhat.n_j) e^{-i k xhat.y_j} mu_j |J_j| w_j.
+ * xhat: host, n_dirs x 3.  d_u_inf: n_dirs x nrhs complex128. */
+qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrhs,
+                        const double* xhat, int32_t n_dirs, void* d_u_inf);
+
+/* Test hook for the modal engine (Section 3.3): phi-frame modes m = 0..nmax of
+ * the source derivatives dr G and dz G of the Helmholtz kernel for n_pts
+ * (r, rt, c, chi - 1, r - rt) tuples (device FP64 arrays), wavenumber k.
+ * d_A, d_B: n_pts x (nmax+1) complex128. */
+qax_status qax_modal_modes(qax_problem* p, int32_t n_pts, const double* d_r, const double* d_rt,
+                           const double* d_c, const double* d_chim1, const double* d_rmrt,
+                           double k, int32_t nmax, void* d_A, void* d_B);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QAX_H */

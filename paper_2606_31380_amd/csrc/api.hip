@@ -1,0 +1,691 @@
+// Host runtime and C interface of libqax (see include/qax.h).
+//
+// The solver of Section 6 (GMRES with the block-diagonal preconditioner built
+// from the self blocks) is written right-preconditioned: with M = blockdiag(B_b),
+// A M^-1 v = v + D_off (M^-1 v), so one Krylov step costs one block-inverse
+// apply and one inter-body pair sum.  Every (problem, right-hand side) pair is
+// an independent GMRES run; all runs advance in lockstep so that their applies
+// share one pair-sum launch.  Restarts recompute the true residual b - A x in
+// FP64 (self blocks + FP64 pair sum); with QAX_MIXED the Krylov steps use the
+// FP32 pair sum and the FP32 inverse blocks, so each restart is one step of
+// FP64 iterative refinement.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "krylov.h"
+
+namespace qax {
+hipError_t launch_dense_system(qax_problem* p, double* A);
+hipError_t launch_dense_solve(qax_problem* p, double* A, const double* b, int nrhs, double* x,
+                              double* work);
+size_t dense_solve_work_bytes(int64_t N);
+size_t invert_blocks_work_bytes(qax_problem* p);
+}  // namespace qax
+
+using namespace qax;
+using cplx = std::complex<double>;
+
+namespace {
+
+struct Buffers {
+  std::map<std::string, std::pair<void*, size_t>> m;
+};
+std::map<const qax_problem*, Buffers>& registry() {
+  static std::map<const qax_problem*, Buffers> r;
+  return r;
+}
+
+}  // namespace
+
+namespace qax {
+
+qax_status fail(qax_problem* p, qax_status s, const std::string& msg) {
+  if (p) p->err = msg;
+  return s;
+}
+
+qax_status hip_check(qax_problem* p, hipError_t e, const char* what) {
+  if (e == hipSuccess) return QAX_OK;
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(p, e == hipErrorOutOfMemory ? QAX_ERR_NOMEM : QAX_ERR_DEVICE, m);
+}
+
+// Grow-only named device buffer owned by the handle.
+static void* dbuf(qax_problem* p, const char* name, size_t bytes, qax_status* st) {
+  auto& b = registry()[p].m[name];
+  if (b.second >= bytes && b.first) return b.first;
+  if (b.first) (void)hipFree(b.first);
+  b.first = nullptr;
+  b.second = 0;
+  void* ptr = nullptr;
+  hipError_t e = hipMalloc(&ptr, std::max<size_t>(bytes, 256));
+  if (e != hipSuccess) {
+    *st = hip_check(p, e, name);
+    return nullptr;
+  }
+  b.first = ptr;
+  b.second = bytes;
+  return ptr;
+}
+
+void* scratch(qax_problem* p, size_t bytes, qax_status* st) { return dbuf(p, "scratch", bytes, st); }
+
+}  // namespace qax
+
+#define QCHECK(expr, what)                                   \
+  do {                                                       \
+    qax_status _s = hip_check(p, (expr), what);              \
+    if (_s != QAX_OK) return _s;                             \
+  } while (0)
+
+#define QBUF(var, type, name, bytes)                         \
+  type* var = nullptr;                                       \
+  do {                                                       \
+    qax_status _s = QAX_OK;                                  \
+    var = (type*)dbuf(p, name, (bytes), &_s);                \
+    if (!var) return _s;                                     \
+  } while (0)
+
+static int cu_count(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return 256;
+  return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+}
+
+static bool is_finite(double v) { return std::isfinite(v); }
+
+// ---------------------------------------------------------------- lifecycle
+extern "C" qax_status qax_create(int device, void* hip_stream, qax_problem** out) {
+  if (!out) return QAX_ERR_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return QAX_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return QAX_ERR_DEVICE;
+  qax_problem* p = new (std::nothrow) qax_problem();
+  if (!p) return QAX_ERR_NOMEM;
+  p->device = device;
+  p->stream = (hipStream_t)hip_stream;
+  *out = p;
+  return QAX_OK;
+}
+
+static void free_geometry(qax_problem* p) {
+  void* ptrs[] = {p->d_bodies, p->d_blocks, p->d_node_body, p->d_pos,  p->d_aw,
+                  p->d_loc32,  p->d_aw32,   p->d_gl,        p->d_B,    p->d_Binv,
+                  p->d_Binv32, p->d_tasks64, p->d_tasks32};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  p->d_bodies = nullptr; p->d_blocks = nullptr; p->d_node_body = nullptr;
+  p->d_pos = nullptr; p->d_aw = nullptr; p->d_loc32 = nullptr; p->d_aw32 = nullptr;
+  p->d_gl = nullptr; p->d_B = nullptr; p->d_Binv = nullptr; p->d_Binv32 = nullptr;
+  p->d_tasks64 = nullptr; p->d_tasks32 = nullptr;
+}
+
+extern "C" void qax_destroy(qax_problem* p) {
+  if (!p) return;
+  (void)hipSetDevice(p->device);
+  if (p->stream) (void)hipStreamSynchronize(p->stream);
+  else (void)hipDeviceSynchronize();
+  free_geometry(p);
+  auto it = registry().find(p);
+  if (it != registry().end()) {
+    for (auto& kv : it->second.m)
+      if (kv.second.first) (void)hipFree(kv.second.first);
+    registry().erase(it);
+  }
+  delete p;
+}
+
+extern "C" const char* qax_last_error(const qax_problem* p) { return p ? p->err.c_str() : "null handle"; }
+
+static qax_status sync(qax_problem* p, const char* what) {
+  return hip_check(p, hipStreamSynchronize(p->stream), what);
+}
+
+// ---------------------------------------------------------------- build
+static void rotation(double t1, double t2, double* R) {
+  const double c1 = std::cos(t1), s1 = std::sin(t1), c2 = std::cos(t2), s2 = std::sin(t2);
+  // Rz(t1) Ry(t2)
+  const double Rz[9] = {c1, -s1, 0, s1, c1, 0, 0, 0, 1};
+  const double Ry[9] = {c2, 0, s2, 0, 1, 0, -s2, 0, c2};
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0;
+      for (int k = 0; k < 3; ++k) s += Rz[3 * i + k] * Ry[3 * k + j];
+      R[3 * i + j] = s;
+    }
+}
+
+extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t n_bodies,
+                                const double* k_per_problem, int32_t n_problems) {
+  if (!p) return QAX_ERR_ARG;
+  if (!bodies || n_bodies <= 0 || !k_per_problem || n_problems <= 0)
+    return fail(p, QAX_ERR_ARG, "qax_build: empty body list or wavenumbers");
+  for (int i = 0; i < n_problems; ++i)
+    if (!is_finite(k_per_problem[i]) || k_per_problem[i] < 0)
+      return fail(p, QAX_ERR_ARG, "qax_build: wavenumbers must be finite and >= 0");
+  int prev = 0;
+  for (int i = 0; i < n_bodies; ++i) {
+    const qax_body& b = bodies[i];
+    if (b.shape < 0 || b.shape > 2) return fail(p, QAX_ERR_ARG, "qax_build: unknown shape");
+    if (b.n_panels < 1 || b.n_panels > 64) return fail(p, QAX_ERR_ARG, "qax_build: n_panels out of range");
+    if (b.n_theta < 4 || b.n_theta > 64 || (b.n_theta & 1))
+      return fail(p, QAX_ERR_ARG, "qax_build: n_theta must be even in [4, 64]");
+    if (b.problem < 0 || b.problem >= n_problems || b.problem < prev || b.problem > prev + 1)
+      return fail(p, QAX_ERR_ARG, "qax_build: problems must be contiguous and increasing");
+    if (i == 0 && b.problem != 0) return fail(p, QAX_ERR_ARG, "qax_build: first body must be in problem 0");
+    prev = b.problem;
+    const double vals[] = {b.a, b.c, b.kappa, b.theta1, b.theta2, b.centre[0], b.centre[1], b.centre[2]};
+    for (double v : vals)
+      if (!is_finite(v)) return fail(p, QAX_ERR_ARG, "qax_build: non-finite body parameter");
+    if (b.a <= 0 || b.c <= 0 || b.kappa < 0) return fail(p, QAX_ERR_ARG, "qax_build: bad shape parameters");
+    const double zmax = b.shape == QAX_PEANUT ? b.a * (1 + b.c) : b.c;
+    if (b.shape == QAX_PEANUT && b.c >= 1.0) return fail(p, QAX_ERR_ARG, "qax_build: peanut needs c < 1");
+    if (b.kappa * zmax >= 1.0) return fail(p, QAX_ERR_ARG, "qax_build: kappa * max|z| must be < 1");
+  }
+  if (prev != n_problems - 1) return fail(p, QAX_ERR_ARG, "qax_build: a problem has no bodies");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  free_geometry(p);
+  p->state = 0;
+  p->n_bodies = n_bodies;
+  p->n_problems = n_problems;
+  p->bodies.assign(bodies, bodies + n_bodies);
+  p->k.assign(k_per_problem, k_per_problem + n_problems);
+  p->off.assign(n_bodies + 1, 0);
+  p->prob_body0.assign(n_problems + 1, n_bodies);
+  p->hbodies.assign(n_bodies, BodyDev{});
+  p->hblocks.clear();
+  // distinct self blocks: equal shape, parameters, discretisation and k
+  std::map<std::vector<double>, int> key2blk;
+  int64_t elems = 0;
+  for (int i = 0; i < n_bodies; ++i) {
+    const qax_body& b = bodies[i];
+    const int n = b.n_panels * GL_ORDER * b.n_theta;
+    p->off[i + 1] = p->off[i] + n;
+    if (i == 0 || bodies[i - 1].problem != b.problem) p->prob_body0[b.problem] = i;
+    BodyDev& d = p->hbodies[i];
+    d.shape = b.shape; d.n_panels = b.n_panels; d.n_theta = b.n_theta; d.problem = b.problem;
+    d.off = p->off[i]; d.n = n;
+    d.a = b.a; d.c = b.c; d.kappa = b.kappa;
+    rotation(b.theta1, b.theta2, d.R);
+    for (int a = 0; a < 3; ++a) d.cen[a] = b.centre[a];
+    d.k = k_per_problem[b.problem];
+    std::vector<double> key = {(double)b.shape, b.a, b.c, b.kappa, (double)b.n_panels,
+                               (double)b.n_theta, d.k};
+    auto it = key2blk.find(key);
+    if (it == key2blk.end()) {
+      BlockDev bk;
+      bk.rep_body = i;
+      bk.n = n;
+      bk.elem_off = elems;
+      elems += (int64_t)n * n;
+      key2blk[key] = (int)p->hblocks.size();
+      d.block = (int)p->hblocks.size();
+      p->hblocks.push_back(bk);
+    } else {
+      d.block = it->second;
+    }
+  }
+  p->prob_body0[n_problems] = n_bodies;
+  p->N = p->off[n_bodies];
+  p->block_elems = elems;
+  const int64_t N = p->N;
+  QCHECK(hipMalloc(&p->d_bodies, sizeof(BodyDev) * n_bodies), "alloc bodies");
+  QCHECK(hipMalloc(&p->d_blocks, sizeof(BlockDev) * p->hblocks.size()), "alloc blocks");
+  QCHECK(hipMalloc(&p->d_node_body, sizeof(int32_t) * N), "alloc node_body");
+  QCHECK(hipMalloc(&p->d_pos, sizeof(double) * 3 * N), "alloc pos");
+  QCHECK(hipMalloc(&p->d_aw, sizeof(double) * 3 * N), "alloc aw");
+  QCHECK(hipMalloc(&p->d_loc32, sizeof(float) * 4 * N), "alloc loc32");
+  QCHECK(hipMalloc(&p->d_aw32, sizeof(float) * 4 * N), "alloc aw32");
+  QCHECK(hipMalloc(&p->d_gl, sizeof(double) * 2 * GL_ORDER), "alloc gl");
+  double gl[2 * GL_ORDER];
+  gauss_legendre_host(GL_ORDER, gl, gl + GL_ORDER);
+  QCHECK(hipMemcpyAsync(p->d_gl, gl, sizeof(gl), hipMemcpyHostToDevice, p->stream), "copy gl");
+  QCHECK(hipMemcpyAsync(p->d_bodies, p->hbodies.data(), sizeof(BodyDev) * n_bodies,
+                        hipMemcpyHostToDevice, p->stream), "copy bodies");
+  QCHECK(hipMemcpyAsync(p->d_blocks, p->hblocks.data(), sizeof(BlockDev) * p->hblocks.size(),
+                        hipMemcpyHostToDevice, p->stream), "copy blocks");
+  QCHECK(launch_build_nodes(p), "build_nodes");
+  const int cus = cu_count(p->device);
+  plan_pair_sum(p, QAX_FP64, cus);
+  plan_pair_sum(p, QAX_MIXED, cus);
+  QCHECK(hipMalloc(&p->d_tasks64, sizeof(PairTask) * p->tasks64.size()), "alloc tasks");
+  QCHECK(hipMalloc(&p->d_tasks32, sizeof(PairTask) * p->tasks32.size()), "alloc tasks");
+  QCHECK(hipMemcpyAsync(p->d_tasks64, p->tasks64.data(), sizeof(PairTask) * p->tasks64.size(),
+                        hipMemcpyHostToDevice, p->stream), "copy tasks");
+  QCHECK(hipMemcpyAsync(p->d_tasks32, p->tasks32.data(), sizeof(PairTask) * p->tasks32.size(),
+                        hipMemcpyHostToDevice, p->stream), "copy tasks");
+  qax_status st = sync(p, "qax_build");
+  if (st != QAX_OK) return st;
+  p->state = 1;
+  p->err.clear();
+  return QAX_OK;
+}
+
+extern "C" qax_status qax_size(const qax_problem* p, int64_t* n_unknowns, int64_t* body_offsets) {
+  if (!p || !n_unknowns) return QAX_ERR_ARG;
+  if (p->state < 1) return QAX_ERR_STATE;
+  *n_unknowns = p->N;
+  if (body_offsets) std::memcpy(body_offsets, p->off.data(), sizeof(int64_t) * (p->n_bodies + 1));
+  return QAX_OK;
+}
+
+extern "C" qax_status qax_nodes(const qax_problem* pc, double* d_pos, double* d_aw) {
+  qax_problem* p = const_cast<qax_problem*>(pc);
+  if (!p || !d_pos || !d_aw) return QAX_ERR_ARG;
+  if (p->state < 1) return fail(p, QAX_ERR_STATE, "qax_nodes: call qax_build first");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  for (int c = 0; c < 3; ++c) {
+    QCHECK(hipMemcpy2DAsync(d_pos + c, 24, p->d_pos + c * p->N, 8, 8, p->N,
+                            hipMemcpyDeviceToDevice, p->stream), "copy pos");
+    QCHECK(hipMemcpy2DAsync(d_aw + c, 24, p->d_aw + c * p->N, 8, 8, p->N,
+                            hipMemcpyDeviceToDevice, p->stream), "copy aw");
+  }
+  return sync(p, "qax_nodes");
+}
+
+// ---------------------------------------------------------------- self blocks
+extern "C" qax_status qax_assemble_self(qax_problem* p, double* t_setup_s) {
+  if (!p) return QAX_ERR_ARG;
+  if (p->state < 1) return fail(p, QAX_ERR_STATE, "qax_assemble_self: call qax_build first");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  auto t0 = std::chrono::steady_clock::now();
+  if (!p->d_B) {
+    QCHECK(hipMalloc(&p->d_B, (size_t)p->block_elems * 16), "alloc self blocks");
+    QCHECK(hipMalloc(&p->d_Binv, (size_t)p->block_elems * 16), "alloc inverse blocks");
+    QCHECK(hipMalloc(&p->d_Binv32, (size_t)p->block_elems * 8), "alloc inverse blocks fp32");
+  }
+  QCHECK(launch_assemble_self(p), "assemble_self");
+  QBUF(work, double, "gj_work", invert_blocks_work_bytes(p));
+  QCHECK(launch_invert_blocks(p, work), "invert_blocks");
+  qax_status st = sync(p, "qax_assemble_self");
+  if (st != QAX_OK) return st;
+  auto t1 = std::chrono::steady_clock::now();
+  if (t_setup_s) *t_setup_s = std::chrono::duration<double>(t1 - t0).count();
+  p->state = 2;
+  return QAX_OK;
+}
+
+extern "C" qax_status qax_self_block(const qax_problem* pc, int32_t body, int32_t inverse, void* d_out) {
+  qax_problem* p = const_cast<qax_problem*>(pc);
+  if (!p || !d_out) return QAX_ERR_ARG;
+  if (p->state < 2) return fail(p, QAX_ERR_STATE, "qax_self_block: call qax_assemble_self first");
+  if (body < 0 || body >= p->n_bodies) return fail(p, QAX_ERR_ARG, "qax_self_block: bad body index");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  const BlockDev& K = p->hblocks[p->hbodies[body].block];
+  const double* src = (inverse ? p->d_Binv : p->d_B) + 2 * K.elem_off;
+  QCHECK(hipMemcpyAsync(d_out, src, (size_t)K.n * K.n * 16, hipMemcpyDeviceToDevice, p->stream),
+         "copy block");
+  return sync(p, "qax_self_block");
+}
+
+// ---------------------------------------------------------------- applies
+static qax_status check_vec_call(qax_problem* p, const void* a, const void* b, int nrhs, int need) {
+  if (!a || !b || nrhs < 1 || nrhs > 256) return fail(p, QAX_ERR_ARG, "null vector or nrhs out of [1, 256]");
+  if (p->state < need) return fail(p, QAX_ERR_STATE, need == 1 ? "call qax_build first" : "call qax_assemble_self first");
+  return QAX_OK;
+}
+
+static qax_status pair_sum_into(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
+                                bool accumulate) {
+  const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;
+  QBUF(partial, double, "pair_partial", (size_t)slots * p->N * nrhs * 16);
+  QCHECK(launch_pair_sum(p, prec, mu, out, nrhs, partial, accumulate), "pair_sum");
+  return QAX_OK;
+}
+
+extern "C" qax_status qax_pair_sum(qax_problem* p, qax_prec prec, const void* d_mu, void* d_out,
+                                   int32_t nrhs) {
+  if (!p) return QAX_ERR_ARG;
+  qax_status st = check_vec_call(p, d_mu, d_out, nrhs, 1);
+  if (st != QAX_OK) return st;
+  if (prec != QAX_FP64 && prec != QAX_MIXED) return fail(p, QAX_ERR_ARG, "bad precision");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  st = pair_sum_into(p, prec, (const double*)d_mu, (double*)d_out, nrhs, false);
+  if (st != QAX_OK) return st;
+  return sync(p, "qax_pair_sum");
+}
+
+extern "C" qax_status qax_block_apply(qax_problem* p, int32_t inverse, qax_prec prec, const void* d_v,
+                                      void* d_out, int32_t nrhs) {
+  if (!p) return QAX_ERR_ARG;
+  qax_status st = check_vec_call(p, d_v, d_out, nrhs, 2);
+  if (st != QAX_OK) return st;
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(launch_block_apply(p, inverse, prec, (const double*)d_v, (double*)d_out, nrhs, false),
+         "block_apply");
+  return sync(p, "qax_block_apply");
+}
+
+static qax_status apply_full(qax_problem* p, int prec, const double* mu, double* out, int nrhs) {
+  QCHECK(launch_block_apply(p, 0, QAX_FP64, mu, out, nrhs, false), "block_apply");
+  return pair_sum_into(p, prec, mu, out, nrhs, true);
+}
+
+extern "C" qax_status qax_apply(qax_problem* p, qax_prec prec, const void* d_mu, void* d_out,
+                                int32_t nrhs) {
+  if (!p) return QAX_ERR_ARG;
+  qax_status st = check_vec_call(p, d_mu, d_out, nrhs, 2);
+  if (st != QAX_OK) return st;
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  st = apply_full(p, prec, (const double*)d_mu, (double*)d_out, nrhs);
+  if (st != QAX_OK) return st;
+  return sync(p, "qax_apply");
+}
+
+static qax_status upload_dirs(qax_problem* p, const double* dirs, int nrhs, double** d_dirs) {
+  const size_t cnt = (size_t)p->n_problems * nrhs * 3;
+  for (size_t i = 0; i < cnt; ++i)
+    if (!is_finite(dirs[i])) return fail(p, QAX_ERR_ARG, "non-finite direction");
+  QBUF(dd, double, "dirs", cnt * 8);
+  QCHECK(hipMemcpyAsync(dd, dirs, cnt * 8, hipMemcpyHostToDevice, p->stream), "copy dirs");
+  *d_dirs = dd;
+  return QAX_OK;
+}
+
+extern "C" qax_status qax_rhs(qax_problem* p, const double* dirs, int32_t nrhs, void* d_out) {
+  if (!p) return QAX_ERR_ARG;
+  qax_status st = check_vec_call(p, dirs, d_out, nrhs, 1);
+  if (st != QAX_OK) return st;
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  double* dd = nullptr;
+  st = upload_dirs(p, dirs, nrhs, &dd);
+  if (st != QAX_OK) return st;
+  QCHECK(launch_rhs(p, dd, nrhs, (double*)d_out), "rhs");
+  return sync(p, "qax_rhs");
+}
+
+extern "C" qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrhs, const double* xhat,
+                                   int32_t n_dirs, void* d_u_inf) {
+  if (!p) return QAX_ERR_ARG;
+  qax_status st = check_vec_call(p, d_mu, d_u_inf, nrhs, 1);
+  if (st != QAX_OK) return st;
+  if (!xhat || n_dirs < 1) return fail(p, QAX_ERR_ARG, "qax_farfield: no directions");
+  for (int i = 0; i < 3 * n_dirs; ++i)
+    if (!is_finite(xhat[i])) return fail(p, QAX_ERR_ARG, "qax_farfield: non-finite direction");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QBUF(dx, double, "xhat", (size_t)n_dirs * 24);
+  QCHECK(hipMemcpyAsync(dx, xhat, (size_t)n_dirs * 24, hipMemcpyHostToDevice, p->stream), "copy xhat");
+  QCHECK(launch_farfield(p, (const double*)d_mu, nrhs, dx, n_dirs, (double*)d_u_inf), "farfield");
+  return sync(p, "qax_farfield");
+}
+
+extern "C" qax_status qax_modal_modes(qax_problem* p, int32_t n_pts, const double* d_r,
+                                      const double* d_rt, const double* d_c, const double* d_chim1,
+                                      const double* d_rmrt, double k, int32_t nmax, void* d_A,
+                                      void* d_B) {
+  if (!p) return QAX_ERR_ARG;
+  if (n_pts < 1 || nmax < 0 || nmax > 160 || !d_r || !d_rt || !d_c || !d_chim1 || !d_rmrt || !d_A || !d_B)
+    return fail(p, QAX_ERR_ARG, "qax_modal_modes: bad arguments");
+  if (!is_finite(k) || k < 0) return fail(p, QAX_ERR_ARG, "qax_modal_modes: bad k");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(launch_modal_modes(p->stream, n_pts, d_r, d_rt, d_c, d_chim1, d_rmrt, k, nmax,
+                            (double*)d_A, (double*)d_B), "modal_modes");
+  return sync(p, "qax_modal_modes");
+}
+
+// ---------------------------------------------------------------- dense solve
+extern "C" qax_status qax_solve_dense(qax_problem* p, const double* dirs, int32_t nrhs, void* d_mu_out) {
+  if (!p) return QAX_ERR_ARG;
+  qax_status st = check_vec_call(p, dirs, d_mu_out, nrhs, 2);
+  if (st != QAX_OK) return st;
+  if (p->N > 8192) return fail(p, QAX_ERR_ARG, "qax_solve_dense: N > 8192");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  const int64_t N = p->N;
+  QBUF(A, double, "dense_A", (size_t)N * N * 16);
+  QBUF(b, double, "dense_b", (size_t)N * nrhs * 16);
+  QBUF(work, double, "dense_work", dense_solve_work_bytes(N));
+  double* dd = nullptr;
+  st = upload_dirs(p, dirs, nrhs, &dd);
+  if (st != QAX_OK) return st;
+  QCHECK(launch_rhs(p, dd, nrhs, b), "rhs");
+  QCHECK(launch_dense_system(p, A), "dense_system");
+  QCHECK(launch_dense_solve(p, A, b, nrhs, (double*)d_mu_out, work), "dense_solve");
+  return sync(p, "qax_solve_dense");
+}
+
+// ---------------------------------------------------------------- GMRES
+namespace {
+
+struct SegGmres {
+  int m;                       // restart length
+  std::vector<cplx> H;         // (m+1) x m, column-major by iteration
+  std::vector<cplx> cs, sn, g;
+  double beta = 0.0;
+  bool frozen = false;
+};
+
+void givens_step(SegGmres& S, int j, const cplx* hcol /* j+2 entries */) {
+  cplx* col = &S.H[(size_t)j * (S.m + 1)];
+  for (int i = 0; i <= j + 1; ++i) col[i] = hcol[i];
+  for (int i = 0; i < j; ++i) {
+    const cplx t = S.cs[i] * col[i] + S.sn[i] * col[i + 1];
+    col[i + 1] = -std::conj(S.sn[i]) * col[i] + S.cs[i] * col[i + 1];
+    col[i] = t;
+  }
+  const double aa = std::abs(col[j]), bb = std::abs(col[j + 1]);
+  const double den = std::hypot(aa, bb);
+  if (den == 0.0) {
+    S.cs[j] = 1.0;
+    S.sn[j] = 0.0;
+  } else if (aa == 0.0) {
+    S.cs[j] = 0.0;
+    S.sn[j] = 1.0;
+  } else {
+    S.cs[j] = aa / den;
+    S.sn[j] = (col[j] / aa) * std::conj(col[j + 1]) / den;
+  }
+  col[j] = S.cs[j] * col[j] + S.sn[j] * col[j + 1];
+  col[j + 1] = 0.0;
+  S.g[j + 1] = -std::conj(S.sn[j]) * S.g[j];
+  S.g[j] = S.cs[j] * S.g[j];
+}
+
+std::vector<cplx> back_solve(const SegGmres& S, int k) {
+  std::vector<cplx> y(k);
+  for (int i = k - 1; i >= 0; --i) {
+    cplx s = S.g[i];
+    for (int l = i + 1; l < k; ++l) s -= S.H[(size_t)l * (S.m + 1) + i] * y[l];
+    const cplx d = S.H[(size_t)i * (S.m + 1) + i];
+    y[i] = (std::abs(d) > 0) ? s / d : cplx(0.0);
+  }
+  return y;
+}
+
+}  // namespace
+
+static qax_status setup_krylov(qax_problem* p, int nrhs, int mmax, Krylov& K) {
+  K.stream = p->stream;
+  K.N = p->N;
+  K.nrhs = nrhs;
+  K.nprob = p->n_problems;
+  const int64_t chunk_nodes = std::max<int64_t>(64, 8192 / nrhs);
+  std::vector<Chunk> ch;
+  std::vector<int32_t> pc0(p->n_problems + 1, 0);
+  for (int pr = 0; pr < p->n_problems; ++pr) {
+    pc0[pr] = (int32_t)ch.size();
+    const int64_t n0 = p->off[p->prob_body0[pr]], n1 = p->off[p->prob_body0[pr + 1]];
+    for (int64_t a = n0; a < n1; a += chunk_nodes) ch.push_back(Chunk{a, std::min(n1, a + chunk_nodes)});
+  }
+  pc0[p->n_problems] = (int32_t)ch.size();
+  K.nchunks = (int)ch.size();
+  std::vector<int32_t> nprob(p->N);
+  for (int b = 0; b < p->n_bodies; ++b)
+    for (int64_t n = p->off[b]; n < p->off[b + 1]; ++n) nprob[n] = p->hbodies[b].problem;
+  QBUF(dch, Chunk, "kry_chunks", ch.size() * sizeof(Chunk));
+  QBUF(dpc, int32_t, "kry_pc0", pc0.size() * 4);
+  QBUF(dnp, int32_t, "kry_nprob", (size_t)p->N * 4);
+  QBUF(dpart, double, "kry_partial", (size_t)(mmax + 2) * ch.size() * nrhs * 16);
+  QCHECK(hipMemcpyAsync(dch, ch.data(), ch.size() * sizeof(Chunk), hipMemcpyHostToDevice, p->stream), "copy");
+  QCHECK(hipMemcpyAsync(dpc, pc0.data(), pc0.size() * 4, hipMemcpyHostToDevice, p->stream), "copy");
+  QCHECK(hipMemcpyAsync(dnp, nprob.data(), (size_t)p->N * 4, hipMemcpyHostToDevice, p->stream), "copy");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  K.d_chunks = dch;
+  K.d_prob_chunk0 = dpc;
+  K.d_node_prob = dnp;
+  K.d_partial = dpart;
+  return QAX_OK;
+}
+
+extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dirs, int32_t nrhs,
+                                double tol, int32_t maxit, void* d_mu_out, qax_info* info) {
+  if (!p) return QAX_ERR_ARG;
+  qax_status st = check_vec_call(p, dirs, d_mu_out, nrhs, 2);
+  if (st != QAX_OK) return st;
+  if (prec != QAX_FP64 && prec != QAX_MIXED) return fail(p, QAX_ERR_ARG, "bad precision");
+  if (!(tol > 0) || !is_finite(tol) || maxit < 1) return fail(p, QAX_ERR_ARG, "qax_solve: bad tol / maxit");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  auto t0 = std::chrono::steady_clock::now();
+
+  const int64_t N = p->N;
+  const int64_t vs = N * nrhs * 2;  // doubles per vector
+  const int nseg = p->n_problems * nrhs;
+  const int m = std::min<int>(maxit, nrhs > 8 ? 40 : 100);
+  Krylov K;
+  st = setup_krylov(p, nrhs, m, K);
+  if (st != QAX_OK) return st;
+  QBUF(V, double, "kry_V", (size_t)(m + 1) * vs * 8);
+  QBUF(w, double, "kry_w", (size_t)vs * 8);
+  QBUF(t, double, "kry_t", (size_t)vs * 8);
+  QBUF(r, double, "kry_r", (size_t)vs * 8);
+  QBUF(b, double, "kry_b", (size_t)vs * 8);
+  QBUF(hd, double, "kry_h", (size_t)(2 * m + 4) * nseg * 16);
+  double* x = (double*)d_mu_out;
+  double* dd = nullptr;
+  st = upload_dirs(p, dirs, nrhs, &dd);
+  if (st != QAX_OK) return st;
+  QCHECK(launch_rhs(p, dd, nrhs, b), "rhs");
+  QCHECK(hipMemsetAsync(x, 0, (size_t)vs * 8, p->stream), "zero x");
+
+  std::vector<cplx> hh((size_t)(2 * m + 4) * nseg);
+  auto fetch = [&](int rows) -> qax_status {
+    QCHECK(hipMemcpyAsync(hh.data(), hd, (size_t)rows * nseg * 16, hipMemcpyDeviceToHost, p->stream),
+           "copy h");
+    return sync(p, "gmres");
+  };
+  // ||b|| per segment
+  K.dots(b, 0, 1, b, hd);
+  if ((st = fetch(1)) != QAX_OK) return st;
+  std::vector<double> bnorm(nseg);
+  for (int s = 0; s < nseg; ++s) bnorm[s] = std::sqrt(std::max(hh[s].real(), 0.0));
+
+  const int inner_prec = prec;
+  int total_its = 0, outer = 0;
+  double relres = 1.0;
+  std::vector<double> rn(nseg);
+  std::vector<cplx> scl(nseg);
+  qax_status result = QAX_ERR_NOCONV;
+  while (true) {
+    // true residual r = b - A x  (FP64)
+    if (outer == 0) {
+      QCHECK(hipMemcpyAsync(r, b, (size_t)vs * 8, hipMemcpyDeviceToDevice, p->stream), "copy");
+    } else {
+      st = apply_full(p, QAX_FP64, x, w, nrhs);
+      if (st != QAX_OK) return st;
+      K.axpby(1.0, b, -1.0, w, r);
+    }
+    K.dots(r, 0, 1, r, hd);
+    if ((st = fetch(1)) != QAX_OK) return st;
+    relres = 0.0;
+    for (int s = 0; s < nseg; ++s) {
+      rn[s] = std::sqrt(std::max(hh[s].real(), 0.0));
+      const double rel = bnorm[s] > 0 ? rn[s] / bnorm[s] : 0.0;
+      relres = std::max(relres, rel);
+    }
+    if (relres <= tol) {
+      result = QAX_OK;
+      break;
+    }
+    if (total_its >= maxit) break;
+    // inner right-preconditioned GMRES cycle on A d = r
+    std::vector<SegGmres> S(nseg);
+    std::vector<double> tin(nseg);
+    for (int s = 0; s < nseg; ++s) {
+      S[s].m = m;
+      S[s].H.assign((size_t)(m + 1) * m, 0.0);
+      S[s].cs.assign(m, 0.0);
+      S[s].sn.assign(m, 0.0);
+      S[s].g.assign(m + 1, 0.0);
+      S[s].beta = rn[s];
+      S[s].g[0] = rn[s];
+      S[s].frozen = !(rn[s] > 0) || (bnorm[s] > 0 && rn[s] <= tol * bnorm[s]);
+      const double need = bnorm[s] > 0 && rn[s] > 0 ? 0.5 * tol * bnorm[s] / rn[s] : 1.0;
+      tin[s] = prec == QAX_MIXED ? std::max(need, 2e-5) : need;
+      scl[s] = S[s].frozen ? 0.0 : 1.0 / rn[s];
+    }
+    QCHECK(hipMemcpyAsync(hd, scl.data(), nseg * 16, hipMemcpyHostToDevice, p->stream), "copy");
+    K.scale(r, hd, V);
+    int j = 0;
+    for (; j < m && total_its < maxit; ++j) {
+      double* Vj = V + (size_t)j * vs;
+      double* Vn = V + (size_t)(j + 1) * vs;
+      QCHECK(launch_block_apply(p, 1, inner_prec, Vj, t, nrhs, false), "precond");
+      st = pair_sum_into(p, inner_prec, t, w, nrhs, false);
+      if (st != QAX_OK) return st;
+      K.axpby(1.0, w, 1.0, Vj, w);
+      // classical Gram-Schmidt, twice
+      double* h1 = hd;
+      double* h2 = hd + (size_t)(m + 2) * nseg * 2;
+      K.dots(V, vs, j + 1, w, h1);
+      K.orth(V, vs, j + 1, h1, w);
+      K.dots(V, vs, j + 1, w, h2);
+      K.orth(V, vs, j + 1, h2, w);
+      K.dots(w, 0, 1, w, h2 + (size_t)(j + 1) * nseg * 2);
+      QCHECK(hipMemcpyAsync(hh.data(), hd, (size_t)(2 * m + 4) * nseg * 16, hipMemcpyDeviceToHost,
+                            p->stream), "copy h");
+      if ((st = sync(p, "gmres")) != QAX_OK) return st;
+      ++total_its;
+      bool all = true;
+      for (int s = 0; s < nseg; ++s) {
+        std::vector<cplx> col(j + 2);
+        for (int i = 0; i <= j; ++i)
+          col[i] = hh[(size_t)i * nseg + s] + hh[(size_t)(m + 2) * nseg + (size_t)i * nseg + s];
+        const double hn = std::sqrt(std::max(hh[(size_t)(m + 2) * nseg + (size_t)(j + 1) * nseg + s].real(), 0.0));
+        col[j + 1] = hn;
+        if (!S[s].frozen) givens_step(S[s], j, col.data());
+        const bool tiny = !(hn > 1e-14 * S[s].beta);
+        scl[s] = (S[s].frozen || tiny) ? 0.0 : 1.0 / hn;
+        const double est = S[s].beta > 0 ? std::abs(S[s].g[j + 1]) / S[s].beta : 0.0;
+        if (!S[s].frozen && est > tin[s] && !tiny) all = false;
+      }
+      QCHECK(hipMemcpyAsync(hd, scl.data(), nseg * 16, hipMemcpyHostToDevice, p->stream), "copy");
+      K.scale(w, hd, Vn);
+      if (all) {
+        ++j;
+        break;
+      }
+    }
+    // d = M^-1 V y;  x += d
+    std::vector<cplx> ys((size_t)j * nseg, 0.0);
+    for (int s = 0; s < nseg; ++s) {
+      if (S[s].frozen) continue;
+      std::vector<cplx> y = back_solve(S[s], j);
+      for (int i = 0; i < j; ++i) ys[(size_t)i * nseg + s] = y[i];
+    }
+    QCHECK(hipMemcpyAsync(hd, ys.data(), ys.size() * 16, hipMemcpyHostToDevice, p->stream), "copy y");
+    K.combine(V, vs, j, hd, t, false);
+    QCHECK(launch_block_apply(p, 1, inner_prec, t, x, nrhs, true), "precond");
+    ++outer;
+  }
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->iters = total_its;
+    info->outer_iters = outer;
+    info->rel_res = relres;
+    info->t_setup_s = 0.0;
+    info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
+  }
+  if (result != QAX_OK)
+    return fail(p, QAX_ERR_NOCONV, "qax_solve: tolerance not reached within maxit iterations");
+  return QAX_OK;
+}

@@ -1,0 +1,359 @@
+// Dense block work: the block-diagonal apply of the self blocks (Section 4,
+// equation linearsys, diagonal blocks D_tt plus 1/2 I), their inversion for the
+// block-diagonal preconditioner (Section 6, the hybrid-solver paragraph: "LU
+// factorization of the single-body self-interaction matrix"), and the dense
+// assembly of the whole system for the direct solve.
+//
+// Block apply with one right-hand side is bound by HBM bandwidth: every matrix
+// element is read once, rows are streamed by one wavefront each with
+// coalesced 16-byte (FP64 complex) or 8-byte (FP32 complex) loads, and the
+// input slice comes from L2.  FP32 storage is accumulated in FP64.
+//
+// Inversion: Gauss-Jordan elimination with partial pivoting, in place, batched
+// over matrices of different orders; one pivot launch and one rank-1 update
+// launch per elimination step.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace qax {
+
+// ---------------------------------------------------------------- block apply
+template <typename MT, int NRC>
+__global__ __launch_bounds__(256) void block_gemv_kernel(
+    const BodyDev* __restrict__ bodies, const BlockDev* __restrict__ blocks,
+    const int32_t* __restrict__ node_body, const MT* __restrict__ pool, int64_t N,
+    const double2* __restrict__ v, int nrhs, double2* __restrict__ out, int accumulate) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int rc0 = blockIdx.y * NRC;
+  if (row >= N) return;
+  const int b = node_body[row];
+  const BodyDev& B = bodies[b];
+  const BlockDev& K = blocks[B.block];
+  const int n = K.n;
+  const int lr = (int)(row - B.off);
+  const MT* a = pool + 2 * (K.elem_off + (int64_t)lr * n);
+  const double2* vb = v + B.off * nrhs;
+  double ar[NRC], ai[NRC];
+#pragma unroll
+  for (int r = 0; r < NRC; ++r) { ar[r] = 0.0; ai[r] = 0.0; }
+  for (int j = lane; j < n; j += 64) {
+    const double mr = (double)a[2 * j], mi = (double)a[2 * j + 1];
+#pragma unroll
+    for (int r = 0; r < NRC; ++r) {
+      if (rc0 + r < nrhs) {
+        const double2 x = vb[(int64_t)j * nrhs + rc0 + r];
+        ar[r] += mr * x.x - mi * x.y;
+        ai[r] += mr * x.y + mi * x.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NRC; ++r) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      ar[r] += __shfl_xor(ar[r], off);
+      ai[r] += __shfl_xor(ai[r], off);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < NRC; ++r) {
+      if (rc0 + r < nrhs) {
+        const int64_t e = row * nrhs + rc0 + r;
+        double2 o = accumulate ? out[e] : make_double2(0.0, 0.0);
+        o.x += ar[r];
+        o.y += ai[r];
+        out[e] = o;
+      }
+    }
+  }
+}
+
+template <typename MT, int NRC>
+static void gemv_launch(qax_problem* p, const MT* pool, const double* v, double* out, int nrhs,
+                        bool acc) {
+  dim3 grid((unsigned)((p->N + 3) / 4), (unsigned)((nrhs + NRC - 1) / NRC));
+  hipLaunchKernelGGL((block_gemv_kernel<MT, NRC>), grid, dim3(256), 0, p->stream, p->d_bodies,
+                     p->d_blocks, p->d_node_body, pool, p->N, (const double2*)v, nrhs,
+                     (double2*)out, acc ? 1 : 0);
+}
+
+hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,
+                              int nrhs, bool accumulate) {
+  if (inverse && prec == QAX_MIXED) {
+    if (nrhs == 1) gemv_launch<float, 1>(p, p->d_Binv32, v, out, nrhs, accumulate);
+    else gemv_launch<float, 4>(p, p->d_Binv32, v, out, nrhs, accumulate);
+  } else {
+    const double* pool = inverse ? p->d_Binv : p->d_B;
+    if (nrhs == 1) gemv_launch<double, 1>(p, pool, v, out, nrhs, accumulate);
+    else gemv_launch<double, 4>(p, pool, v, out, nrhs, accumulate);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- conversion
+__global__ void convert_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
+                                   int64_t count) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) dst[e] = (float)src[e];
+}
+
+hipError_t launch_convert_f32(hipStream_t s, const double* src, float* dst, int64_t count) {
+  hipLaunchKernelGGL(convert_f32_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                     src, dst, count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- Gauss-Jordan
+struct MatDesc {
+  int64_t elem_off;  // complex elements
+  int32_t n;
+};
+
+// Step k, one workgroup per matrix: pivot search in column k (rows >= k),
+// row swap, scaling of row k, and a copy of column k (the multipliers).
+__global__ __launch_bounds__(256) void gj_pivot_kernel(const MatDesc* __restrict__ mats,
+                                                       double2* __restrict__ pool, int k,
+                                                       int32_t* __restrict__ piv,
+                                                       double2* __restrict__ colbuf,
+                                                       int64_t col_stride, int nmax) {
+  const MatDesc M = mats[blockIdx.x];
+  const int n = M.n;
+  if (k >= n) return;
+  double2* A = pool + M.elem_off;
+  __shared__ double best[256];
+  __shared__ int bidx[256];
+  double bv = -1.0;
+  int bi = k;
+  for (int i = k + threadIdx.x; i < n; i += 256) {
+    const double2 a = A[(int64_t)i * n + k];
+    const double m = a.x * a.x + a.y * a.y;
+    if (m > bv) { bv = m; bi = i; }
+  }
+  best[threadIdx.x] = bv;
+  bidx[threadIdx.x] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      const double o = best[threadIdx.x + s];
+      const int oi = bidx[threadIdx.x + s];
+      if (o > best[threadIdx.x] || (o == best[threadIdx.x] && oi < bidx[threadIdx.x])) {
+        best[threadIdx.x] = o;
+        bidx[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int p = bidx[0];
+  if (threadIdx.x == 0) piv[(int64_t)blockIdx.x * nmax + k] = p;
+  if (p != k) {
+    for (int j = threadIdx.x; j < n; j += 256) {
+      const double2 t = A[(int64_t)k * n + j];
+      A[(int64_t)k * n + j] = A[(int64_t)p * n + j];
+      A[(int64_t)p * n + j] = t;
+    }
+  }
+  __syncthreads();
+  const double2 d = A[(int64_t)k * n + k];
+  const double den = d.x * d.x + d.y * d.y;
+  const double2 inv = make_double2(d.x / den, -d.y / den);
+  __syncthreads();
+  // multipliers of column k (before the row scaling touches A[k][k])
+  double2* col = colbuf + (int64_t)blockIdx.x * col_stride;
+  for (int i = threadIdx.x; i < n; i += 256) col[i] = A[(int64_t)i * n + k];
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += 256) {
+    const double2 a = (j == k) ? make_double2(1.0, 0.0) : A[(int64_t)k * n + j];
+    A[(int64_t)k * n + j] = make_double2(a.x * inv.x - a.y * inv.y, a.x * inv.y + a.y * inv.x);
+  }
+}
+
+// Step k: rows i != k: A[i][j] = (j == k ? 0 : A[i][j]) - f_i A[k][j].
+__global__ __launch_bounds__(256) void gj_update_kernel(const MatDesc* __restrict__ mats,
+                                                        double2* __restrict__ pool, int k,
+                                                        const double2* __restrict__ colbuf,
+                                                        int64_t col_stride) {
+  const MatDesc M = mats[blockIdx.z];
+  const int n = M.n;
+  if (k >= n) return;
+  const int i = blockIdx.y;
+  if (i >= n || i == k) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  double2* A = pool + M.elem_off;
+  const double2 f = colbuf[(int64_t)blockIdx.z * col_stride + i];
+  const double2 rk = A[(int64_t)k * n + j];
+  const double2 a = (j == k) ? make_double2(0.0, 0.0) : A[(int64_t)i * n + j];
+  A[(int64_t)i * n + j] = make_double2(a.x - (f.x * rk.x - f.y * rk.y), a.y - (f.x * rk.y + f.y * rk.x));
+}
+
+// Undo the row interchanges as column interchanges, last step first.
+__global__ void gj_unpivot_kernel(const MatDesc* __restrict__ mats, double2* __restrict__ pool,
+                                  const int32_t* __restrict__ piv, int nmax) {
+  const MatDesc M = mats[blockIdx.y];
+  const int n = M.n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double2* row = pool + M.elem_off + (int64_t)i * n;
+  const int32_t* pv = piv + (int64_t)blockIdx.y * nmax;
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = pv[k];
+    if (p != k) {
+      const double2 t = row[k];
+      row[k] = row[p];
+      row[p] = t;
+    }
+  }
+}
+
+// In-place inversion of `batch` matrices described on the device by `mats`
+// (orders up to nmax).  work: nmax*batch complex (multipliers) + nmax*batch
+// int32 (pivots) + batch MatDesc, provided by the caller.
+hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int batch, int nmax,
+                     double* work) {
+  double2* colbuf = (double2*)work;
+  int32_t* piv = (int32_t*)(colbuf + (int64_t)nmax * batch);
+  for (int k = 0; k < nmax; ++k) {
+    hipLaunchKernelGGL(gj_pivot_kernel, dim3(batch), dim3(256), 0, s, d_mats, (double2*)pool, k,
+                       piv, colbuf, (int64_t)nmax, nmax);
+    hipLaunchKernelGGL(gj_update_kernel, dim3((nmax + 255) / 256, nmax, batch), dim3(256), 0, s,
+                       d_mats, (double2*)pool, k, colbuf, (int64_t)nmax);
+  }
+  hipLaunchKernelGGL(gj_unpivot_kernel, dim3((nmax + 255) / 256, batch), dim3(256), 0, s, d_mats,
+                     (double2*)pool, piv, nmax);
+  return hipGetLastError();
+}
+
+size_t gj_work_bytes(int batch, int nmax) {
+  return (size_t)nmax * batch * (sizeof(double2) + sizeof(int32_t)) + 256;
+}
+
+// Invert every distinct self block: copy B into Binv, invert in place, make
+// the FP32 copy.
+hipError_t launch_invert_blocks(qax_problem* p, double* work) {
+  const int nbk = (int)p->hblocks.size();
+  int nmax = 0;
+  std::vector<MatDesc> md(nbk);
+  for (int i = 0; i < nbk; ++i) {
+    md[i].elem_off = p->hblocks[i].elem_off;
+    md[i].n = p->hblocks[i].n;
+    nmax = std::max(nmax, md[i].n);
+  }
+  hipError_t e = hipMemcpyAsync(p->d_Binv, p->d_B, (size_t)p->block_elems * 16,
+                                hipMemcpyDeviceToDevice, p->stream);
+  if (e != hipSuccess) return e;
+  MatDesc* d_md = (MatDesc*)work;
+  double* w2 = (double*)((char*)work + ((nbk * sizeof(MatDesc) + 255) / 256) * 256);
+  e = hipMemcpyAsync(d_md, md.data(), nbk * sizeof(MatDesc), hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) return e;
+  e = gj_invert(p->stream, p->d_Binv, d_md, nbk, nmax, w2);
+  if (e != hipSuccess) return e;
+  return launch_convert_f32(p->stream, p->d_Binv, p->d_Binv32, p->block_elems * 2);
+}
+
+size_t invert_blocks_work_bytes(qax_problem* p) {
+  int nmax = 0;
+  for (auto& b : p->hblocks) nmax = std::max(nmax, b.n);
+  const int nbk = (int)p->hblocks.size();
+  return ((nbk * sizeof(MatDesc) + 255) / 256) * 256 + gj_work_bytes(nbk, nmax);
+}
+
+// ---------------------------------------------------------------- dense system
+constexpr double INV_FOUR_PI_D = 0.0795774715459476678844;
+
+// Off-diagonal entries A[i][j] (different bodies, same problem) of the full
+// system; entries of a body with itself are left untouched.
+__global__ void dense_offdiag_kernel(const BodyDev* __restrict__ bodies,
+                                     const int32_t* __restrict__ node_body,
+                                     const double* __restrict__ pos, const double* __restrict__ aw,
+                                     int64_t N, double2* __restrict__ A) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blockIdx.y;
+  if (j >= N) return;
+  const int bi = node_body[i], bj = node_body[j];
+  if (bi == bj) return;
+  if (bodies[bi].problem != bodies[bj].problem) {
+    A[i * N + j] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double k = bodies[bi].k;
+  const double dx = pos[j] - pos[i], dy = pos[N + j] - pos[N + i], dz = pos[2 * N + j] - pos[2 * N + i];
+  const double r2 = dx * dx + dy * dy + dz * dz;
+  const double ir = rsqrt(r2);
+  const double r = r2 * ir;
+  double s, c;
+  sincos(k * r, &s, &c);
+  const double sc = (aw[j] * dx + aw[N + j] * dy + aw[2 * N + j] * dz) * ir * ir * ir * INV_FOUR_PI_D;
+  A[i * N + j] = make_double2(-(c + k * r * s) * sc, (k * r * c - s) * sc);
+}
+
+// Copy each body's self block into its diagonal block of the dense matrix.
+__global__ void dense_diag_kernel(const BodyDev* __restrict__ bodies,
+                                  const BlockDev* __restrict__ blocks,
+                                  const int32_t* __restrict__ node_body,
+                                  const double2* __restrict__ pool, int64_t N,
+                                  double2* __restrict__ A) {
+  const int64_t i = blockIdx.y;
+  const int b = node_body[i];
+  const BodyDev& B = bodies[b];
+  const BlockDev& K = blocks[B.block];
+  const int jl = blockIdx.x * blockDim.x + threadIdx.x;
+  if (jl >= K.n) return;
+  const int il = (int)(i - B.off);
+  A[i * N + B.off + jl] = pool[K.elem_off + (int64_t)il * K.n + jl];
+}
+
+hipError_t launch_dense_system(qax_problem* p, double* A) {
+  hipLaunchKernelGGL(dense_offdiag_kernel, dim3((unsigned)((p->N + 255) / 256), (unsigned)p->N),
+                     dim3(256), 0, p->stream, p->d_bodies, p->d_node_body, p->d_pos, p->d_aw, p->N,
+                     (double2*)A);
+  int nmax = 0;
+  for (auto& b : p->hblocks) nmax = std::max(nmax, b.n);
+  hipLaunchKernelGGL(dense_diag_kernel, dim3((unsigned)((nmax + 255) / 256), (unsigned)p->N),
+                     dim3(256), 0, p->stream, p->d_bodies, p->d_blocks, p->d_node_body,
+                     (const double2*)p->d_B, p->N, (double2*)A);
+  return hipGetLastError();
+}
+
+// x = Ainv b for a dense N x N inverse and N x nrhs right-hand sides.
+__global__ void dense_matvec_kernel(const double2* __restrict__ A, int64_t N,
+                                    const double2* __restrict__ b, int nrhs,
+                                    double2* __restrict__ x) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int r = blockIdx.y;
+  if (row >= N) return;
+  double ar = 0.0, ai = 0.0;
+  for (int64_t j = lane; j < N; j += 64) {
+    const double2 a = A[row * N + j];
+    const double2 v = b[j * nrhs + r];
+    ar += a.x * v.x - a.y * v.y;
+    ai += a.x * v.y + a.y * v.x;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ar += __shfl_xor(ar, off);
+    ai += __shfl_xor(ai, off);
+  }
+  if (lane == 0) x[row * nrhs + r] = make_double2(ar, ai);
+}
+
+hipError_t launch_dense_solve(qax_problem* p, double* A, const double* b, int nrhs, double* x,
+                              double* work) {
+  MatDesc md{0, (int32_t)p->N};
+  MatDesc* d_md = (MatDesc*)work;
+  double* w2 = (double*)((char*)work + 256);
+  hipError_t e = hipMemcpyAsync(d_md, &md, sizeof(MatDesc), hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) return e;
+  e = gj_invert(p->stream, A, d_md, 1, (int)p->N, w2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dense_matvec_kernel, dim3((unsigned)((p->N + 3) / 4), (unsigned)nrhs),
+                     dim3(256), 0, p->stream, (const double2*)A, p->N, (const double2*)b, nrhs,
+                     (double2*)x);
+  return hipGetLastError();
+}
+
+size_t dense_solve_work_bytes(int64_t N) { return 256 + gj_work_bytes(1, (int)N); }
+
+}  // namespace qax

@@ -1,0 +1,135 @@
+// Internal declarations shared by the HIP translation units of libqax.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/qax.h"
+
+namespace qax {
+
+constexpr int GL_ORDER = 16;
+constexpr double PI = 3.14159265358979323846;
+constexpr double TWO_PI = 6.28318530717958647692;
+constexpr double FOUR_PI = 12.5663706143591729539;
+
+// Per-body record on the device.
+struct BodyDev {
+  int32_t shape, n_panels, n_theta, problem;
+  int64_t off;        // first node
+  int32_t n;          // nodes
+  int32_t block;      // distinct self-block index
+  double a, c, kappa;
+  double R[9];        // rotation, row-major
+  double cen[3];
+  double k;           // wavenumber of the body's problem
+};
+
+// Distinct self block.
+struct BlockDev {
+  int32_t rep_body;   // representative body (its shape parameters)
+  int32_t n;          // order
+  int64_t elem_off;   // offset (in complex elements) in the block pools
+};
+
+// A chunk of pair-sum work: targets [t0, t1) against source bodies
+// [b0, b1) of the same problem, writing partial slot `slot`.
+struct PairTask {
+  int64_t t0;
+  int32_t nt;
+  int32_t b0, b1;
+  int32_t slot;
+  int32_t tbody_lo, tbody_hi;  // bodies spanned by the targets
+  double k;
+};
+
+// Work item of the self-block assembly: one target row x one near panel.
+struct SelfTask {
+  int32_t block;   // distinct block
+  int32_t row;     // target row within the block
+  int32_t panel;   // source panel
+};
+
+}  // namespace qax
+
+struct qax_problem {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int state = 0;  // 0 created, 1 built, 2 assembled
+
+  int32_t n_bodies = 0, n_problems = 0;
+  std::vector<qax_body> bodies;
+  std::vector<double> k;
+  std::vector<int64_t> off;           // n_bodies + 1
+  std::vector<int64_t> prob_body0;    // n_problems + 1 (body index range)
+  std::vector<qax::BodyDev> hbodies;
+  std::vector<qax::BlockDev> hblocks;
+  int64_t N = 0;
+  int64_t block_elems = 0;            // sum of n^2 over distinct blocks
+
+  // device geometry
+  qax::BodyDev* d_bodies = nullptr;
+  qax::BlockDev* d_blocks = nullptr;
+  int32_t* d_node_body = nullptr;
+  double* d_pos = nullptr;      // SoA: x[N], y[N], z[N]
+  double* d_aw = nullptr;       // SoA
+  float* d_loc32 = nullptr;     // float4 per node: local offset from the body centre, |y'|^2
+  float* d_aw32 = nullptr;      // float4 per node: aw, 0
+  double* d_gl = nullptr;       // 16 GL nodes, 16 weights on [-1, 1]
+
+  // self blocks (complex128 / complex64 pools)
+  double* d_B = nullptr;
+  double* d_Binv = nullptr;
+  float* d_Binv32 = nullptr;
+
+  // pair-sum task tables per precision
+  std::vector<qax::PairTask> tasks64, tasks32;
+  qax::PairTask* d_tasks64 = nullptr;
+  qax::PairTask* d_tasks32 = nullptr;
+  int32_t slots64 = 1, slots32 = 1;
+
+  // scratch
+  void* d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+};
+
+namespace qax {
+
+// error helpers
+qax_status fail(qax_problem* p, qax_status s, const std::string& msg);
+qax_status hip_check(qax_problem* p, hipError_t e, const char* what);
+void* scratch(qax_problem* p, size_t bytes, qax_status* st);
+
+// geometry.hip
+void gauss_legendre_host(int n, double* x, double* w);
+hipError_t launch_build_nodes(qax_problem* p);
+
+// pairsum.hip
+hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
+                           double* partial, bool accumulate);
+void plan_pair_sum(qax_problem* p, int prec, int cu_count);
+
+// dense.hip
+hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,
+                              int nrhs, bool accumulate);
+hipError_t launch_invert_blocks(qax_problem* p, double* work);
+hipError_t launch_gj_invert(hipStream_t s, double* A, int n, int batch, int64_t stride, double* work);
+hipError_t launch_convert_f32(hipStream_t s, const double* src, float* dst, int64_t count);
+hipError_t launch_dense_offdiag(qax_problem* p, double* A);
+
+// selfblock.hip
+hipError_t launch_assemble_self(qax_problem* p);
+hipError_t launch_modal_modes(hipStream_t s, int n, const double* r, const double* rt,
+                              const double* c, const double* chim1, const double* rmrt, double k,
+                              int nmax, double* A, double* B);
+
+// krylov.hip
+hipError_t launch_rhs(qax_problem* p, const double* dirs_dev, int nrhs, double* out);
+hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const double* xhat_dev,
+                           int ndir, double* out);
+
+}  // namespace qax

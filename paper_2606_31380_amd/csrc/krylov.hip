@@ -1,0 +1,238 @@
+// Vector kernels of the solver: plane-wave right-hand side (Section 2 and
+// Section 6, equation plane wave parameters), far field of the double-layer
+// density (Section 6: the far-field pattern, with the normal derivative of the
+// kernel for a double-layer density), and the GMRES building blocks.
+//
+// GMRES vectors are N x nrhs complex128 (right-hand sides fastest).  Every
+// (problem, right-hand side) pair is an independent "segment": dot products
+// and norms are segmented by problem node range and right-hand side, and are
+// reduced in a fixed order so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "krylov.h"
+
+namespace qax {
+
+constexpr double INV_FOUR_PI_K = 0.0795774715459476678844;
+
+__global__ void rhs_kernel(const BodyDev* __restrict__ bodies, const int32_t* __restrict__ node_body,
+                           const double* __restrict__ pos, int64_t N, const double* __restrict__ dirs,
+                           int nrhs, double2* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * nrhs) return;
+  const int64_t n = e / nrhs;
+  const int r = (int)(e % nrhs);
+  const BodyDev& B = bodies[node_body[n]];
+  const double* d = dirs + ((int64_t)B.problem * nrhs + r) * 3;
+  const double ph = B.k * (d[0] * pos[n] + d[1] * pos[N + n] + d[2] * pos[2 * N + n]);
+  double s, c;
+  sincos(ph, &s, &c);
+  out[e] = make_double2(-c, -s);
+}
+
+hipError_t launch_rhs(qax_problem* p, const double* dirs_dev, int nrhs, double* out) {
+  const int64_t cnt = p->N * nrhs;
+  hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, p->stream,
+                     p->d_bodies, p->d_node_body, p->d_pos, p->N, dirs_dev, nrhs, (double2*)out);
+  return hipGetLastError();
+}
+
+// u_inf[dir][r] = (1/4pi) sum_{n in problem 0} (-i k xhat.aw_n) e^{-i k xhat.y_n} mu[n][r]
+__global__ __launch_bounds__(256) void farfield_kernel(const double* __restrict__ pos,
+                                                       const double* __restrict__ aw, int64_t N,
+                                                       int64_t n0, double k,
+                                                       const double2* __restrict__ mu, int nrhs,
+                                                       const double* __restrict__ xhat,
+                                                       double2* __restrict__ out) {
+  const int dir = blockIdx.x;
+  const int r = blockIdx.y;
+  const double hx = xhat[3 * dir], hy = xhat[3 * dir + 1], hz = xhat[3 * dir + 2];
+  double ar = 0.0, ai = 0.0;
+  for (int64_t n = threadIdx.x; n < n0; n += 256) {
+    const double ph = -k * (hx * pos[n] + hy * pos[N + n] + hz * pos[2 * N + n]);
+    double s, c;
+    sincos(ph, &s, &c);
+    const double nd = hx * aw[n] + hy * aw[N + n] + hz * aw[2 * N + n];
+    // (-i k nd) (c + i s) = k nd s - i k nd c
+    const double fr = k * nd * s, fi = -k * nd * c;
+    const double2 m = mu[n * nrhs + r];
+    ar += fr * m.x - fi * m.y;
+    ai += fr * m.y + fi * m.x;
+  }
+  __shared__ double sr[256], si[256];
+  sr[threadIdx.x] = ar;
+  si[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sr[threadIdx.x] += sr[threadIdx.x + s];
+      si[threadIdx.x] += si[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    out[(int64_t)dir * nrhs + r] = make_double2(sr[0] * INV_FOUR_PI_K, si[0] * INV_FOUR_PI_K);
+}
+
+hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const double* xhat_dev,
+                           int ndir, double* out) {
+  const int64_t n0 = p->off[p->prob_body0[1]];
+  hipLaunchKernelGGL(farfield_kernel, dim3(ndir, nrhs), dim3(256), 0, p->stream, p->d_pos, p->d_aw,
+                     p->N, n0, p->k[0], (const double2*)mu, nrhs, xhat_dev, (double2*)out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- segmented dots
+// partial[i][chunk][r] = sum_{n in chunk} conj(V_i[n][r]) w[n][r]
+// The block has U*nrhs threads (U = 256/nrhs rounded down); thread t handles
+// right-hand side t % nrhs.
+__global__ __launch_bounds__(256) void mdot_kernel(const double2* __restrict__ V, int64_t vstride,
+                                                   const double2* __restrict__ w, int nrhs,
+                                                   const Chunk* __restrict__ chunks,
+                                                   double2* __restrict__ partial, int nchunks) {
+  const Chunk C = chunks[blockIdx.x];
+  const int i = blockIdx.y;
+  const double2* v = V + (int64_t)i * vstride;
+  const int nthr = blockDim.x;
+  const int U = nthr / nrhs;
+  const int t = threadIdx.x;
+  const int r = t % nrhs;
+  const int u = t / nrhs;
+  double ar = 0.0, ai = 0.0;
+  for (int64_t n = C.n0 + u; n < C.n1; n += U) {
+    const double2 a = v[n * nrhs + r];
+    const double2 b = w[n * nrhs + r];
+    ar += a.x * b.x + a.y * b.y;
+    ai += a.x * b.y - a.y * b.x;
+  }
+  __shared__ double sr[256], si[256];
+  sr[t] = ar;
+  si[t] = ai;
+  __syncthreads();
+  if (t < nrhs) {
+    double xr = 0.0, xi = 0.0;
+    for (int q = 0; q < U; ++q) {
+      xr += sr[t + q * nrhs];
+      xi += si[t + q * nrhs];
+    }
+    partial[((int64_t)i * nchunks + blockIdx.x) * nrhs + t] = make_double2(xr, xi);
+  }
+}
+
+// h[i][problem][r] = sum over the chunks of the problem (in order).
+__global__ void mdot_reduce_kernel(const double2* __restrict__ partial, int nchunks, int nrhs,
+                                   const int32_t* __restrict__ prob_chunk0, int nprob,
+                                   double2* __restrict__ h) {
+  const int i = blockIdx.y;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nprob * nrhs) return;
+  const int pr = e / nrhs, r = e % nrhs;
+  double xr = 0.0, xi = 0.0;
+  for (int c = prob_chunk0[pr]; c < prob_chunk0[pr + 1]; ++c) {
+    const double2 v = partial[((int64_t)i * nchunks + c) * nrhs + r];
+    xr += v.x;
+    xi += v.y;
+  }
+  h[(int64_t)i * nprob * nrhs + e] = make_double2(xr, xi);
+}
+
+// w[n][r] -= sum_{i<m} V_i[n][r] h[i][problem(n)][r]
+__global__ void orth_update_kernel(const double2* __restrict__ V, int64_t vstride, int m,
+                                   const double2* __restrict__ h, const int32_t* __restrict__ node_prob,
+                                   int nprob, int64_t N, int nrhs, double2* __restrict__ w) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * nrhs) return;
+  const int64_t n = e / nrhs;
+  const int r = (int)(e % nrhs);
+  const int pr = node_prob[n];
+  double2 acc = w[e];
+  for (int i = 0; i < m; ++i) {
+    const double2 v = V[(int64_t)i * vstride + e];
+    const double2 c = h[((int64_t)i * nprob + pr) * nrhs + r];
+    acc.x -= v.x * c.x - v.y * c.y;
+    acc.y -= v.x * c.y + v.y * c.x;
+  }
+  w[e] = acc;
+}
+
+// out[n][r] = (accumulate ? out : 0) + sum_{i<m} V_i[n][r] y[i][problem(n)][r]
+__global__ void combine_kernel(const double2* __restrict__ V, int64_t vstride, int m,
+                               const double2* __restrict__ y, const int32_t* __restrict__ node_prob,
+                               int nprob, int64_t N, int nrhs, double2* __restrict__ out,
+                               int accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * nrhs) return;
+  const int64_t n = e / nrhs;
+  const int r = (int)(e % nrhs);
+  const int pr = node_prob[n];
+  double2 acc = accumulate ? out[e] : make_double2(0.0, 0.0);
+  for (int i = 0; i < m; ++i) {
+    const double2 v = V[(int64_t)i * vstride + e];
+    const double2 c = y[((int64_t)i * nprob + pr) * nrhs + r];
+    acc.x += v.x * c.x - v.y * c.y;
+    acc.y += v.x * c.y + v.y * c.x;
+  }
+  out[e] = acc;
+}
+
+// out[n][r] = a[n][r] * s[problem(n)][r]  (complex scale per segment)
+__global__ void seg_scale_kernel(const double2* __restrict__ a, const double2* __restrict__ s,
+                                 const int32_t* __restrict__ node_prob, int64_t N, int nrhs,
+                                 double2* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * nrhs) return;
+  const int64_t n = e / nrhs;
+  const int r = (int)(e % nrhs);
+  const double2 c = s[(int64_t)node_prob[n] * nrhs + r];
+  const double2 v = a[e];
+  out[e] = make_double2(v.x * c.x - v.y * c.y, v.x * c.y + v.y * c.x);
+}
+
+// out = alpha*a + beta*b (real scalars)
+__global__ void axpby_kernel(double alpha, const double2* __restrict__ a, double beta,
+                             const double2* __restrict__ b, int64_t cnt, double2* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cnt) return;
+  const double2 x = a[e];
+  const double2 y = b[e];
+  out[e] = make_double2(alpha * x.x + beta * y.x, alpha * x.y + beta * y.y);
+}
+
+static inline unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// vstride: distance between consecutive vectors of V in doubles (the kernels
+// index complex elements, hence vstride / 2).
+void Krylov::dots(const double* V, int64_t vstride, int m, const double* w, double* h) {
+  const int nthr = (256 / nrhs) * nrhs;
+  hipLaunchKernelGGL(mdot_kernel, dim3(nchunks, m), dim3(nthr), 0, stream, (const double2*)V,
+                     vstride / 2, (const double2*)w, nrhs, d_chunks, (double2*)d_partial, nchunks);
+  hipLaunchKernelGGL(mdot_reduce_kernel, dim3(blocks_for((int64_t)nprob * nrhs), m), dim3(256), 0,
+                     stream, (const double2*)d_partial, nchunks, nrhs, d_prob_chunk0, nprob,
+                     (double2*)h);
+}
+
+void Krylov::orth(const double* V, int64_t vstride, int m, const double* h, double* w) {
+  hipLaunchKernelGGL(orth_update_kernel, dim3(blocks_for(N * nrhs)), dim3(256), 0, stream,
+                     (const double2*)V, vstride / 2, m, (const double2*)h, d_node_prob, nprob, N, nrhs,
+                     (double2*)w);
+}
+
+void Krylov::combine(const double* V, int64_t vstride, int m, const double* y, double* out,
+                     bool accumulate) {
+  hipLaunchKernelGGL(combine_kernel, dim3(blocks_for(N * nrhs)), dim3(256), 0, stream,
+                     (const double2*)V, vstride / 2, m, (const double2*)y, d_node_prob, nprob, N, nrhs,
+                     (double2*)out, accumulate ? 1 : 0);
+}
+
+void Krylov::scale(const double* a, const double* s, double* out) {
+  hipLaunchKernelGGL(seg_scale_kernel, dim3(blocks_for(N * nrhs)), dim3(256), 0, stream,
+                     (const double2*)a, (const double2*)s, d_node_prob, N, nrhs, (double2*)out);
+}
+
+void Krylov::axpby(double alpha, const double* a, double beta, const double* b, double* out) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(blocks_for(N * nrhs)), dim3(256), 0, stream, alpha,
+                     (const double2*)a, beta, (const double2*)b, N * nrhs, (double2*)out);
+}
+
+}  // namespace qax

@@ -1,0 +1,334 @@
+// Inter-body double-layer pair sum (Section 4, the display after the equation
+// for the second part of the multi-body potential):
+//
+//   w_i = 1/(4 pi) sum_{j in other bodies} (ik r - 1) e^{ikr} / r^3
+//                                          (aw_j . (y_j - x_i)) mu_j,
+//   r = |y_j - x_i|,  aw_j = n_j |J_j| (pi/N) omega_j.
+//
+// A tiled N-body kernel on the vector ALUs: source tiles are staged in LDS,
+// every thread owns one target.  Work is cut into tasks (target block x range
+// of source bodies) listed in a table sorted by cost, so that uneven bodies and
+// independent problems share one launch; the partial sums of the tasks of one
+// target row are reduced by a second kernel in a fixed order (deterministic).
+//
+// FP64 path: plain FP64 arithmetic.
+// FP32 path: the phase k r is never formed in FP32.  For target x_i and source
+// body b with centre c_b, D = c_b - x_i is formed in FP64 once per (target,
+// body); per pair only delta = r - |D| is needed, obtained from the FP32
+// estimate r - |D| by one Newton step on delta (2|D| + delta) = 2 D.y' + |y'|^2
+// (y' = y_j - c_b, stored in FP32), so the phase frac(k|D|/2pi) + k delta/2pi
+// stays accurate to FP32 rounding of delta.  Sums are accumulated in FP32 per
+// tile and the tile sums are added with an error-free TwoSum (compensated
+// accumulation).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace qax {
+
+constexpr double INV_FOUR_PI = 0.0795774715459476678844;
+
+template <int TPB, int NRC>
+__global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
+    const PairTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
+    const int32_t* __restrict__ node_body, const double* __restrict__ pos,
+    const double* __restrict__ aw, int64_t N, const double2* __restrict__ mu, int nrhs,
+    double2* __restrict__ partial) {
+  const PairTask T = tasks[blockIdx.x];
+  const int rc0 = blockIdx.y * NRC;  // first right-hand side of this chunk
+  const int tid = threadIdx.x;
+  const bool active = tid < T.nt;
+  const int64_t i = T.t0 + (active ? tid : 0);
+  const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
+  const int mybody = node_body[i];
+  const double k = T.k;
+
+  __shared__ double sx[TPB], sy[TPB], sz[TPB], sax[TPB], say[TPB], saz[TPB];
+  __shared__ double2 smu[TPB * NRC];
+
+  double accr[NRC], acci[NRC];
+#pragma unroll
+  for (int r = 0; r < NRC; ++r) { accr[r] = 0.0; acci[r] = 0.0; }
+
+  for (int b = T.b0; b < T.b1; ++b) {
+    if (T.tbody_lo == b && T.tbody_hi == b) continue;  // every target is in body b
+    const int64_t s0 = bodies[b].off;
+    const int nb = bodies[b].n;
+    const bool own = (mybody == b);
+    for (int base = 0; base < nb; base += TPB) {
+      const int cnt = min(TPB, nb - base);
+      __syncthreads();
+      if (tid < cnt) {
+        const int64_t j = s0 + base + tid;
+        sx[tid] = pos[j]; sy[tid] = pos[N + j]; sz[tid] = pos[2 * N + j];
+        sax[tid] = aw[j]; say[tid] = aw[N + j]; saz[tid] = aw[2 * N + j];
+#pragma unroll
+        for (int r = 0; r < NRC; ++r)
+          smu[tid * NRC + r] = (rc0 + r < nrhs) ? mu[j * nrhs + rc0 + r] : make_double2(0.0, 0.0);
+      }
+      __syncthreads();
+      if (!own) {
+        for (int jj = 0; jj < cnt; ++jj) {
+          const double dx = sx[jj] - xi, dy = sy[jj] - yi, dz = sz[jj] - zi;
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const double ir = rsqrt(r2);
+          const double r = r2 * ir;
+          const double kr = k * r;
+          double s, c;
+          sincos(kr, &s, &c);
+          const double dot = sax[jj] * dx + say[jj] * dy + saz[jj] * dz;
+          const double sc = dot * ir * ir * ir;
+          const double re = -(c + kr * s) * sc;
+          const double im = (kr * c - s) * sc;
+#pragma unroll
+          for (int r_ = 0; r_ < NRC; ++r_) {
+            const double2 m = smu[jj * NRC + r_];
+            accr[r_] += re * m.x - im * m.y;
+            acci[r_] += re * m.y + im * m.x;
+          }
+        }
+      }
+    }
+  }
+  if (active) {
+    double2* dst = partial + (int64_t)T.slot * N * nrhs;
+#pragma unroll
+    for (int r = 0; r < NRC; ++r)
+      if (rc0 + r < nrhs)
+        dst[i * nrhs + rc0 + r] = make_double2(accr[r] * INV_FOUR_PI, acci[r] * INV_FOUR_PI);
+  }
+}
+
+__device__ __forceinline__ void two_sum(float& s, float& c, float a) {
+  const float t = s + a;
+  const float bp = t - s;
+  const float e = (s - (t - bp)) + (a - bp);
+  s = t;
+  c += e;
+}
+
+template <int TPB, int NRC>
+__global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
+    const PairTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
+    const int32_t* __restrict__ node_body, const double* __restrict__ pos,
+    const float4* __restrict__ loc32, const float4* __restrict__ aw32, int64_t N,
+    const double2* __restrict__ mu, int nrhs, double2* __restrict__ partial) {
+  const PairTask T = tasks[blockIdx.x];
+  const int rc0 = blockIdx.y * NRC;
+  const int tid = threadIdx.x;
+  const bool active = tid < T.nt;
+  const int64_t i = T.t0 + (active ? tid : 0);
+  const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
+  const int mybody = node_body[i];
+  const double k = T.k;
+  const float kf = (float)k;
+  const float k2pi = (float)(k / TWO_PI);
+
+  __shared__ float4 sloc[TPB];
+  __shared__ float4 saw[TPB];
+  __shared__ float2 smu[TPB * NRC];
+
+  float sr[NRC], si[NRC], cr[NRC], ci[NRC];
+#pragma unroll
+  for (int r = 0; r < NRC; ++r) { sr[r] = si[r] = cr[r] = ci[r] = 0.0f; }
+
+  for (int b = T.b0; b < T.b1; ++b) {
+    if (T.tbody_lo == b && T.tbody_hi == b) continue;
+    const BodyDev& B = bodies[b];
+    const int64_t s0 = B.off;
+    const int nb = B.n;
+    const bool own = (mybody == b);
+    // per (target, source body) set-up in FP64
+    const double Dx = B.cen[0] - xi, Dy = B.cen[1] - yi, Dz = B.cen[2] - zi;
+    const double Dn = sqrt(Dx * Dx + Dy * Dy + Dz * Dz);
+    double ph0d = k * Dn / TWO_PI;
+    ph0d -= floor(ph0d);
+    const float dxf = (float)Dx, dyf = (float)Dy, dzf = (float)Dz;
+    const float dnf = (float)Dn;
+    const float two_dn = (float)(2.0 * Dn);
+    const float inv2dn = (float)(0.5 / Dn);
+    const float ph0 = (float)ph0d;
+    for (int base = 0; base < nb; base += TPB) {
+      const int cnt = min(TPB, nb - base);
+      __syncthreads();
+      if (tid < cnt) {
+        const int64_t j = s0 + base + tid;
+        sloc[tid] = loc32[j];
+        saw[tid] = aw32[j];
+#pragma unroll
+        for (int r = 0; r < NRC; ++r) {
+          const double2 m = (rc0 + r < nrhs) ? mu[j * nrhs + rc0 + r] : make_double2(0.0, 0.0);
+          smu[tid * NRC + r] = make_float2((float)m.x, (float)m.y);
+        }
+      }
+      __syncthreads();
+      if (!own) {
+        float tr[NRC], ti[NRC];
+#pragma unroll
+        for (int r = 0; r < NRC; ++r) { tr[r] = 0.0f; ti[r] = 0.0f; }
+        for (int jj = 0; jj < cnt; ++jj) {
+          const float4 yl = sloc[jj];
+          const float4 a4 = saw[jj];
+          const float ex = dxf + yl.x, ey = dyf + yl.y, ez = dzf + yl.z;   // y_j - x_i
+          const float r2 = ex * ex + ey * ey + ez * ez;
+          const float ir = __builtin_amdgcn_rsqf(r2);
+          const float r = r2 * ir;
+          const float dy = dxf * yl.x + dyf * yl.y + dzf * yl.z;
+          const float num = 2.0f * dy + yl.w;            // 2 D.y' + |y'|^2
+          const float d0 = r - dnf;                      // FP32 estimate of r - |D|
+          const float res = d0 * (d0 + two_dn) - num;    // Newton residual
+          const float delta = d0 - res * inv2dn;
+          const float ph = ph0 + delta * k2pi;           // revolutions
+          const float s = __builtin_amdgcn_sinf(ph);
+          const float c = __builtin_amdgcn_cosf(ph);
+          const float kr = kf * r;
+          const float dot = a4.x * ex + a4.y * ey + a4.z * ez;
+          const float sc = dot * (ir * ir * ir);
+          const float re = -(c + kr * s) * sc;
+          const float im = (kr * c - s) * sc;
+#pragma unroll
+          for (int r_ = 0; r_ < NRC; ++r_) {
+            const float2 m = smu[jj * NRC + r_];
+            tr[r_] += re * m.x - im * m.y;
+            ti[r_] += re * m.y + im * m.x;
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < NRC; ++r) {
+          two_sum(sr[r], cr[r], tr[r]);
+          two_sum(si[r], ci[r], ti[r]);
+        }
+      }
+    }
+  }
+  if (active) {
+    double2* dst = partial + (int64_t)T.slot * N * nrhs;
+#pragma unroll
+    for (int r = 0; r < NRC; ++r)
+      if (rc0 + r < nrhs)
+        dst[i * nrhs + rc0 + r] =
+            make_double2(((double)sr[r] + (double)cr[r]) * INV_FOUR_PI,
+                         ((double)si[r] + (double)ci[r]) * INV_FOUR_PI);
+  }
+}
+
+// out[e] = (accumulate ? out[e] : 0) + sum_s partial[s][e], fixed order.
+__global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slots, int64_t count,
+                                    double2* __restrict__ out, int accumulate) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double2 acc = accumulate ? out[e] : make_double2(0.0, 0.0);
+  for (int s = 0; s < slots; ++s) {
+    const double2 v = partial[(int64_t)s * count + e];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  out[e] = acc;
+}
+
+// Build the task table: target blocks of `tpb` rows inside one problem, each
+// paired with `slots` contiguous chunks of that problem's source bodies
+// (balanced by node count).  Sorted by decreasing cost so that the hardware
+// dispatcher, which issues workgroups in index order, balances uneven work.
+void plan_pair_sum(qax_problem* p, int prec, int cu_count) {
+  const int tpb = 256;
+  std::vector<PairTask> tasks;
+  int64_t tblocks = 0;
+  for (int pr = 0; pr < p->n_problems; ++pr)
+    tblocks += (p->off[p->prob_body0[pr + 1]] - p->off[p->prob_body0[pr]] + tpb - 1) / tpb;
+  int slots = (int)std::max<int64_t>(1, (8LL * cu_count + tblocks - 1) / std::max<int64_t>(tblocks, 1));
+  slots = std::min(slots, 32);
+  for (int pr = 0; pr < p->n_problems; ++pr) {
+    const int b0 = (int)p->prob_body0[pr], b1 = (int)p->prob_body0[pr + 1];
+    const int64_t n0 = p->off[b0], n1 = p->off[b1];
+    // split bodies into `slots` chunks of similar node counts
+    std::vector<int> cut(slots + 1, b1);
+    cut[0] = b0;
+    {
+      int b = b0;
+      for (int s = 1; s < slots; ++s) {
+        const int64_t target = n0 + (n1 - n0) * s / slots;
+        while (b < b1 && p->off[b + 1] <= target) ++b;
+        cut[s] = std::max(cut[s - 1], b);
+      }
+      cut[slots] = b1;
+    }
+    for (int64_t t0 = n0; t0 < n1; t0 += tpb) {
+      const int nt = (int)std::min<int64_t>(tpb, n1 - t0);
+      // bodies spanned by the targets
+      int lo = b0, hi = b0;
+      while (lo + 1 < b1 && p->off[lo + 1] <= t0) ++lo;
+      hi = lo;
+      while (hi + 1 < b1 && p->off[hi + 1] <= t0 + nt - 1) ++hi;
+      for (int s = 0; s < slots; ++s) {
+        PairTask T;
+        T.t0 = t0;
+        T.nt = nt;
+        T.b0 = cut[s];
+        T.b1 = cut[s + 1];
+        T.slot = s;
+        T.tbody_lo = lo;
+        T.tbody_hi = hi;
+        T.k = p->k[pr];
+        tasks.push_back(T);
+      }
+    }
+  }
+  auto cost = [&](const PairTask& T) {
+    return (double)T.nt * (double)(p->off[T.b1] - p->off[T.b0]);
+  };
+  std::stable_sort(tasks.begin(), tasks.end(),
+                   [&](const PairTask& a, const PairTask& b) { return cost(a) > cost(b); });
+  if (prec == QAX_FP64) {
+    p->tasks64 = tasks;
+    p->slots64 = slots;
+  } else {
+    p->tasks32 = tasks;
+    p->slots32 = slots;
+  }
+}
+
+template <int TPB, int NRC>
+static void launch_f64(qax_problem* p, const double* mu, int nrhs, double* partial) {
+  dim3 grid((unsigned)p->tasks64.size(), (unsigned)((nrhs + NRC - 1) / NRC));
+  hipLaunchKernelGGL((pair_sum_f64_kernel<TPB, NRC>), grid, dim3(TPB), 0, p->stream, p->d_tasks64,
+                     p->d_bodies, p->d_node_body, p->d_pos, p->d_aw, p->N, (const double2*)mu, nrhs,
+                     (double2*)partial);
+}
+
+template <int TPB, int NRC>
+static void launch_f32(qax_problem* p, const double* mu, int nrhs, double* partial) {
+  dim3 grid((unsigned)p->tasks32.size(), (unsigned)((nrhs + NRC - 1) / NRC));
+  hipLaunchKernelGGL((pair_sum_f32_kernel<TPB, NRC>), grid, dim3(TPB), 0, p->stream, p->d_tasks32,
+                     p->d_bodies, p->d_node_body, p->d_pos, (const float4*)p->d_loc32,
+                     (const float4*)p->d_aw32, p->N, (const double2*)mu, nrhs, (double2*)partial);
+}
+
+// partial: slots x N x nrhs complex128 workspace; out = pair sum, or
+// out += pair sum when accumulate is set.
+hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
+                           double* partial, bool accumulate) {
+  const bool f64 = prec == QAX_FP64;
+  if (f64) {
+    if (nrhs == 1) launch_f64<256, 1>(p, mu, nrhs, partial);
+    else if (nrhs <= 4) launch_f64<256, 4>(p, mu, nrhs, partial);
+    else launch_f64<256, 8>(p, mu, nrhs, partial);
+  } else {
+    if (nrhs == 1) launch_f32<256, 1>(p, mu, nrhs, partial);
+    else if (nrhs <= 4) launch_f32<256, 4>(p, mu, nrhs, partial);
+    else if (nrhs <= 8) launch_f32<256, 8>(p, mu, nrhs, partial);
+    else launch_f32<256, 16>(p, mu, nrhs, partial);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;
+  const int64_t count = p->N * nrhs;
+  hipLaunchKernelGGL(reduce_slots_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                     p->stream, (const double2*)partial, slots, count, (double2*)out,
+                     accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace qax

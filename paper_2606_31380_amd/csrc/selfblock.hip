@@ -1,0 +1,632 @@
+// FP64 assembly of the self blocks B = 1/2 I + D_bb (Sections 3.1-3.4).
+//
+// Row T (target x at (t_T, theta_T), panel p), columns (i, l, j):
+//   near panel i (|i - p| <= 1):  int_{panel i} P_l(s) G_j(x, s) ds,
+//     G_j(x, s) = int_0^{2pi} K(x, y(s,theta)) L_j(theta) dtheta,
+//     K = grad_y G^k . (d_theta x d_s)   (the density is interpolated by
+//     P_l(s) L_j(theta); the area normal is kept exact, so its theta
+//     dependence through p', q' becomes the mode shifts m -/+ 1)
+//   far panel i:  K(x, y_ilj) (pi/N) omega_il   (Section 3.1, equation sx).
+//
+// Inner integral G_j, two routes:
+//  * modal route (Section 3.3) when chi - 1 < CHI_SPLIT: toroidal Legendre
+//    functions Q_{m-1/2}(chi) by the recurrence leg_recur (forward where it is
+//    stable, Miller's backward recurrence normalised by Q_{-1/2} = mu K(mu)
+//    otherwise; K and E by the arithmetic-geometric mean), Q' by dleg_recur,
+//    static derivative modes, the smooth factors F = cos k rho + k rho sin k rho
+//    and Hs = (k rho cos k rho - sin k rho)/(4 pi rho^3) sampled on 128 azimuths
+//    and transformed by a radix-2 FFT in LDS, the convolution of F^ with the
+//    static modes, the shift to the theta frame, and the inverse DFT onto the
+//    trigonometric Lagrange basis;
+//  * direct route otherwise: trapezoidal rule on L_d >= 256 azimuths applied to
+//    the kernel itself, folded with L_0 (a circular convolution).
+// Outer integral: the paper's generalized Gaussian tables are not available;
+// this uses the substitution s - e = (s_end - e) u^5 with 64-point
+// Gauss-Legendre in u on each side of the target (self panel) and toward the
+// shared end (adjacent panels), which integrates the logarithmic singularity to
+// about 1e-13.  Geometry near the target uses cancellation-free differences of
+// the generating curve (chi - 1 keeps full relative accuracy).
+//
+// One wavefront (64 lanes) per (target row, panel) work item.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "internal.h"
+#include "shapes.h"
+
+namespace qax {
+
+constexpr int LM = 128;                       // modal FFT length
+constexpr int NF_CAP = 48;                    // largest convolution half-width
+constexpr int NTH_MAX = 64;                   // largest n_theta
+constexpr int MQ_CAP = NTH_MAX / 2 + 2 + NF_CAP;   // highest Q index kept (82)
+constexpr int QB = 16;                        // nodes per recurrence batch
+constexpr int LD_MAX = 320;                   // largest direct-route sample count
+constexpr int NGO = 64;                       // outer Gauss-Legendre order
+constexpr double CHI_SPLIT = 0.02;
+constexpr double INV_4PI = 0.0795774715459476678844;
+
+struct NodeLoc {
+  double r, dr, dz, dp, dq, rt, alpha, c, chim1, rmrt, z, p, q, w, s;
+};
+
+struct ModalScratch {
+  double2 fa[LM];
+  double2 fb[LM];
+  double Fh[LM / 2];
+  double Hrh[NTH_MAX / 2 + 2];
+  double Hh[NTH_MAX / 2 + 2];
+  double A0[MQ_CAP + 1];
+  double B0[MQ_CAP + 1];
+  double2 Am[NTH_MAX / 2 + 2];
+  double2 Bm[NTH_MAX / 2 + 2];
+  double2 Km[NTH_MAX + 1];
+};
+
+struct SelfShared {
+  double Q[MQ_CAP + 1][QB];
+  double2 twf[LM / 2];          // e^{-2 pi i k / LM}
+  double2 tw2n[NTH_MAX];        // e^{i pi m / N}
+  double lam[LD_MAX];           // L_0(2 pi l / L_d)
+  double Pl[16];
+  int modal_idx[64];
+  union {
+    ModalScratch m;
+    double2 K[LD_MAX];
+  } u;
+};
+
+// ---------------------------------------------------------------- elliptic / Q
+// K(k), E(k) (modulus k, complementary modulus kp) by the AGM
+// (Abramowitz & Stegun 17.6.3-17.6.4), c_n = c_{n-1}^2 / (4 a_n).
+__device__ void agm_ke(double kmod, double kp, double& K, double& E) {
+  double a = 1.0, b = kp, c = kmod;
+  double s = 0.5 * c * c, p2 = 0.5;
+  for (int it = 0; it < 40; ++it) {
+    const double an = 0.5 * (a + b);
+    const double bn = sqrt(a * b);
+    const double cn = c * c / (4.0 * an);
+    a = an;
+    b = bn;
+    c = cn;
+    p2 *= 2.0;
+    s += p2 * c * c;
+    if (c <= 1e-17 * a) break;
+  }
+  K = PI / (2.0 * a);
+  E = K * (1.0 - s);
+}
+
+// Q[n][col] = Q_{n-1/2}(chi), n = 0..mq, for one node (one lane).
+__device__ void toroidal_q_lane(double chi, double chim1, int mq, double (*Q)[QB], int col) {
+  const double mu = sqrt(2.0 / (chi + 1.0));
+  const double mup = sqrt(chim1 / (chi + 1.0));
+  double K, E;
+  agm_ke(mu, mup, K, E);
+  const double q0 = mu * K;
+  const double q1 = chi * mu * K - sqrt(2.0 * (chi + 1.0)) * E;
+  const double a = log(chi + sqrt(chim1 * (chi + 1.0)));   // acosh(chi)
+  if (a * (mq + 1) <= 2.5) {
+    double qm = q0, qn = q1;
+    Q[0][col] = q0;
+    Q[1][col] = q1;
+    for (int n = 1; n < mq; ++n) {
+      const double qp = (4.0 * n * chi * qn - (2.0 * n - 1.0) * qm) / (2.0 * n + 1.0);
+      Q[n + 1][col] = qp;
+      qm = qn;
+      qn = qp;
+    }
+  } else {
+    // a > 2.5 / (mq + 1) here, so the start index is bounded (< 1000 for mq = 82)
+    const int start = mq + (int)fmin(ceil(20.0 / a), 4000.0) + 10;
+    double hi = 0.0, lo = 1e-200;
+    for (int n = start; n >= 1; --n) {
+      if (n <= mq) Q[n][col] = lo;
+      const double nw = (4.0 * n * chi * lo - (2.0 * n + 1.0) * hi) / (2.0 * n - 1.0);
+      hi = lo;
+      lo = nw;
+    }
+    const double scale = q0 / lo;
+    Q[0][col] = q0;
+    for (int n = 1; n <= mq; ++n) Q[n][col] *= scale;
+  }
+}
+
+// ---------------------------------------------------------------- FFT in LDS
+__device__ __forceinline__ int bitrev7(int x) { return (int)(__brev((unsigned)x) >> 25); }
+
+// Forward DFT X_k = sum_l x_l e^{-2 pi i k l / LM} of fa and fb, in place,
+// radix-2 decimation in time, one butterfly per lane per stage.
+__device__ void fft2_lm(double2* fa, double2* fb, const double2* twf) {
+  const int lane = threadIdx.x;
+  // bit-reversal permutation
+  {
+    double2 a0 = fa[lane], a1 = fa[lane + 64], b0 = fb[lane], b1 = fb[lane + 64];
+    __syncthreads();
+    fa[bitrev7(lane)] = a0;
+    fa[bitrev7(lane + 64)] = a1;
+    fb[bitrev7(lane)] = b0;
+    fb[bitrev7(lane + 64)] = b1;
+    __syncthreads();
+  }
+  for (int half = 1; half < LM; half <<= 1) {
+    const int grp = lane / half, pos = lane % half;
+    const int i0 = grp * 2 * half + pos, i1 = i0 + half;
+    const double2 w = twf[pos * (LM / 2 / half)];
+    double2 u = fa[i0], v = fa[i1];
+    double2 vw = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
+    fa[i0] = make_double2(u.x + vw.x, u.y + vw.y);
+    fa[i1] = make_double2(u.x - vw.x, u.y - vw.y);
+    u = fb[i0];
+    v = fb[i1];
+    vw = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
+    fb[i0] = make_double2(u.x + vw.x, u.y + vw.y);
+    fb[i1] = make_double2(u.x - vw.x, u.y - vw.y);
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Hs = (x cos x - sin x)/(4 pi rho^3), x = k rho; Taylor series
+// sum_{j>=1} (-1)^j 2j/(2j+1)! x^{2j+1} for x < 0.5.
+__device__ __forceinline__ double smooth_h(double k, double rho) {
+  const double x = k * rho;
+  if (x < 0.5) {
+    const double x2 = x * x;
+    double term = 1.0, ser = 0.0, fact = 1.0;
+    for (int j = 1; j <= 12; ++j) {
+      fact *= (2.0 * j) * (2.0 * j + 1.0);
+      ser += ((j & 1) ? -1.0 : 1.0) * (2.0 * j) / fact * term;
+      term *= x2;
+    }
+    return k * k * k * INV_4PI * ser;
+  }
+  double s, c;
+  sincos(x, &s, &c);
+  return (x * c - s) * INV_4PI / (rho * rho * rho);
+}
+
+// phi-frame modes m = 0..nmax of A = dr G, B = dz G for one node (all lanes),
+// given its Q column.  Results in M.Am, M.Bm.
+__device__ void modal_modes(double k, double r, double rt, double c, double chim1, double rmrt,
+                            int nmax, const double (*Q)[QB], int col, ModalScratch& M,
+                            const double2* twf) {
+  const int lane = threadIdx.x;
+  const double chi = 1.0 + chim1;
+  int nf = 0;
+  if (k != 0.0) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int l = lane + 64 * h;
+      const double phi = TWO_PI * l / LM;
+      const double sh = sin(0.5 * phi);
+      const double rho = sqrt(2.0 * r * rt * (chim1 + 2.0 * sh * sh));
+      double sk, ck;
+      sincos(k * rho, &sk, &ck);
+      const double F = ck + k * rho * sk;
+      const double Hs = smooth_h(k, rho);
+      M.fa[l] = make_double2(F, Hs);
+      M.fb[l] = make_double2(Hs * (r - rt * cos(phi)), 0.0);
+    }
+    __syncthreads();
+    fft2_lm(M.fa, M.fb, twf);
+    const double sc = TWO_PI / LM;
+    M.Fh[lane] = M.fa[lane].x * sc;
+    if (lane < nmax + 1) {
+      M.Hh[lane] = M.fa[lane].y * sc;
+      M.Hrh[lane] = M.fb[lane].x * sc;
+    }
+    const double mag = fabs(M.fa[lane].x * sc);
+    const double mx = wave_max(mag);
+    const bool above = mag > 1e-15 * mx;
+    const unsigned long long bal = __ballot(above);
+    nf = bal ? 63 - __clzll(bal) : 0;
+    nf = min(nf + 1, NF_CAP);
+    nf = min(nf, MQ_CAP - nmax - 1);
+    __syncthreads();
+  }
+  // static modes n = 0..nmax+nf
+  const int mtot = nmax + nf;
+  const double pref = 1.0 / (TWO_PI * sqrt(rt * r));
+  const double chi2m1 = chim1 * (chi + 1.0);
+  const double drchi = (rmrt * (r + rt) - c * c) / (2.0 * rt * r * r);
+  const double dzchi = -c / (r * rt);
+  for (int n = lane; n <= mtot; n += 64) {
+    const double qn = Q[n][col];
+    const double qm = n == 0 ? Q[1][col] : Q[n - 1][col];
+    const double qp = (2.0 * n - 1.0) / (2.0 * chi2m1) * (chi * qn - qm);
+    M.A0[n] = pref * drchi * qp - pref * qn / (2.0 * r);
+    M.B0[n] = pref * dzchi * qp;
+  }
+  __syncthreads();
+  if (lane <= nmax) {
+    double ar, br;
+    if (k == 0.0) {
+      ar = M.A0[lane];
+      br = M.B0[lane];
+      M.Am[lane] = make_double2(ar, 0.0);
+      M.Bm[lane] = make_double2(br, 0.0);
+    } else {
+      ar = 0.0;
+      br = 0.0;
+      for (int n = -nf; n <= nf; ++n) {
+        const double f = M.Fh[abs(n)];
+        const int idx = abs(lane - n);
+        ar += f * M.A0[idx];
+        br += f * M.B0[idx];
+      }
+      M.Am[lane] = make_double2(ar / TWO_PI, M.Hrh[lane]);
+      M.Bm[lane] = make_double2(br / TWO_PI, -c * M.Hh[lane]);
+    }
+  }
+  __syncthreads();
+}
+
+// G_j (returned in lane j < 2N) from the phi-frame modes of one node.
+__device__ double2 modes_to_gj(int N, const NodeLoc& L, ModalScratch& M, const double2* tw2n) {
+  const int lane = threadIdx.x;
+  const double r = L.r;
+  for (int idx = lane; idx <= 2 * N; idx += 64) {
+    const int m = idx - N;
+    double s0, c0, s1, c1, s2, c2;
+    sincos(-m * L.alpha, &s0, &c0);
+    sincos(-(m - 1) * L.alpha, &s1, &c1);
+    sincos(-(m + 1) * L.alpha, &s2, &c2);
+    const double2 A = M.Am[abs(m)], B = M.Bm[abs(m)];
+    const double2 Bm1 = M.Bm[abs(m - 1)], Bp1 = M.Bm[abs(m + 1)];
+    // e^{-i m alpha} (r z' A - r r' B)
+    const double tr = r * L.dz * A.x - r * L.dr * B.x;
+    const double ti = r * L.dz * A.y - r * L.dr * B.y;
+    double kr = c0 * tr - s0 * ti;
+    double ki = c0 * ti + s0 * tr;
+    // - r/2 (p' - i q') e^{-i(m-1) alpha} B_{m-1}
+    {
+      const double er = c1 * Bm1.x - s1 * Bm1.y, ei = c1 * Bm1.y + s1 * Bm1.x;
+      const double fr = 0.5 * r * L.dp, fi = -0.5 * r * L.dq;
+      kr -= fr * er - fi * ei;
+      ki -= fr * ei + fi * er;
+    }
+    // - r/2 (p' + i q') e^{-i(m+1) alpha} B_{m+1}
+    {
+      const double er = c2 * Bp1.x - s2 * Bp1.y, ei = c2 * Bp1.y + s2 * Bp1.x;
+      const double fr = 0.5 * r * L.dp, fi = 0.5 * r * L.dq;
+      kr -= fr * er - fi * ei;
+      ki -= fr * ei + fi * er;
+    }
+    M.Km[idx] = make_double2(kr, ki);
+  }
+  __syncthreads();
+  double2 g = make_double2(0.0, 0.0);
+  if (lane < 2 * N) {
+    const int twoN = 2 * N;
+    for (int idx = 0; idx <= twoN; ++idx) {
+      const int m = idx - N;
+      const double wgt = (idx == 0 || idx == twoN) ? 0.5 : 1.0;
+      const int e = ((m * lane) % twoN + twoN) % twoN;
+      const double2 t = tw2n[e];
+      const double2 K = M.Km[idx];
+      g.x += wgt * (K.x * t.x - K.y * t.y);
+      g.y += wgt * (K.x * t.y + K.y * t.x);
+    }
+    g.x /= twoN;
+    g.y /= twoN;
+  }
+  __syncthreads();
+  return g;
+}
+
+// ---------------------------------------------------------------- per-node geometry
+// Source slice at s = t + dl relative to the target (t, theta_t).
+__device__ NodeLoc node_local(int shape, double a, double c, double kappa, double t, double tht,
+                              double dl) {
+  NodeLoc L;
+  const Curve ct = curve_eval(shape, a, c, kappa, t);
+  const Curve cs = curve_eval(shape, a, c, kappa, t + dl);
+  const CurveDiff d = curve_diff(shape, a, c, kappa, t, dl);
+  double sth, cth;
+  sincos(tht, &sth, &cth);
+  const double ax = ct.r * cth + d.d_p;
+  const double by = ct.r * sth + d.d_q;
+  L.rt = sqrt(ax * ax + by * by);
+  L.alpha = atan2(by, ax);
+  const double drt = (2.0 * ct.r * (cth * d.d_p + sth * d.d_q) + d.d_p * d.d_p + d.d_q * d.d_q) /
+                     (L.rt + ct.r);
+  L.rmrt = d.d_r - drt;
+  L.c = d.d_z;
+  L.r = cs.r;
+  L.dr = cs.dr;
+  L.dz = cs.dz;
+  L.dp = cs.dp;
+  L.dq = cs.dq;
+  L.z = cs.z;
+  L.p = cs.p;
+  L.q = cs.q;
+  L.chim1 = (L.rmrt * L.rmrt + L.c * L.c) / (2.0 * L.r * L.rt);
+  L.s = t + dl;
+  return L;
+}
+
+__device__ __forceinline__ NodeLoc shfl_node(const NodeLoc& v, int src) {
+  NodeLoc o;
+  o.r = __shfl(v.r, src); o.dr = __shfl(v.dr, src); o.dz = __shfl(v.dz, src);
+  o.dp = __shfl(v.dp, src); o.dq = __shfl(v.dq, src); o.rt = __shfl(v.rt, src);
+  o.alpha = __shfl(v.alpha, src); o.c = __shfl(v.c, src); o.chim1 = __shfl(v.chim1, src);
+  o.rmrt = __shfl(v.rmrt, src); o.z = __shfl(v.z, src); o.p = __shfl(v.p, src);
+  o.q = __shfl(v.q, src); o.w = __shfl(v.w, src); o.s = __shfl(v.s, src);
+  return o;
+}
+
+// ---------------------------------------------------------------- assembly kernel
+struct OuterRule {
+  double x[NGO];
+  double w[NGO];
+};
+
+__global__ __launch_bounds__(64) void assemble_self_kernel(
+    const SelfTask* __restrict__ tasks, const BlockDev* __restrict__ blocks,
+    const BodyDev* __restrict__ bodies, const double* __restrict__ gl16,
+    const OuterRule* __restrict__ orule, double2* __restrict__ pool) {
+  __shared__ SelfShared S;
+  const SelfTask task = tasks[blockIdx.x];
+  const BlockDev K = blocks[task.block];
+  const BodyDev& B = bodies[K.rep_body];
+  const int lane = threadIdx.x;
+  const int shape = B.shape;
+  const double a = B.a, cc = B.c, kappa = B.kappa, k = B.k;
+  const int nth = B.n_theta, N = nth / 2, npan = B.n_panels;
+  const int n = K.n;
+  const int T = task.row, ip = task.panel;
+  const int pT = T / (GL_ORDER * nth), lT = (T / nth) % GL_ORDER, jT = T % nth;
+  const double h = PI / npan;
+  const double tT = -0.5 * PI + h * pT + 0.5 * h * (gl16[lT] + 1.0);
+  const double thT = jT * PI / N;
+  double2* row = pool + K.elem_off + (int64_t)T * n;
+
+  // tables
+  for (int q = lane; q < LM / 2; q += 64) {
+    double s, c;
+    sincos(-TWO_PI * q / LM, &s, &c);
+    S.twf[q] = make_double2(c, s);
+  }
+  for (int q = lane; q < 2 * N; q += 64) {
+    double s, c;
+    sincos(PI * q / N, &s, &c);
+    S.tw2n[q] = make_double2(c, s);
+  }
+  const int qr = (255 + 2 * N) / (2 * N);   // L_d = 2N * qr >= 256
+  const int Ld = 2 * N * qr;
+  for (int l = lane; l < Ld; l += 64) {
+    if (l == 0) {
+      S.lam[0] = 1.0;
+    } else {
+      const double sn = sin(TWO_PI * (double)((N * l) % Ld) / Ld);
+      double sh, ch;
+      sincos(PI * l / Ld, &sh, &ch);
+      S.lam[l] = sn * ch / sh / (2.0 * N);
+    }
+  }
+  __syncthreads();
+
+  // target point (body frame)
+  const Curve cT = curve_eval(shape, a, cc, kappa, tT);
+  double sT, cTh;
+  sincos(thT, &sT, &cTh);
+  const double xT = cT.r * cTh + cT.p, yT = cT.r * sT + cT.q, zT = cT.z;
+
+  if (abs(ip - pT) > 1) {
+    // far panel: smooth rule
+    for (int e = lane; e < GL_ORDER * nth; e += 64) {
+      const int l = e / nth, j = e % nth;
+      const double t = -0.5 * PI + h * ip + 0.5 * h * (gl16[l] + 1.0);
+      const double om = 0.5 * h * gl16[GL_ORDER + l];
+      const Curve cv = curve_eval(shape, a, cc, kappa, t);
+      double sj, cj;
+      sincos(j * PI / N, &sj, &cj);
+      const double dx = cv.r * cj + cv.p - xT, dy = cv.r * sj + cv.q - yT, dz = cv.z - zT;
+      const double nx = cv.r * cv.dz * cj, ny = cv.r * cv.dz * sj;
+      const double nz = -cv.r * (cv.dr + cv.dp * cj + cv.dq * sj);
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      const double ir = rsqrt(r2);
+      const double rr = r2 * ir;
+      double s, c;
+      sincos(k * rr, &s, &c);
+      const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI * om * PI / N;
+      row[(int64_t)(ip * GL_ORDER + l) * nth + j] = make_double2(-(c + k * rr * s) * sc, (k * rr * c - s) * sc);
+    }
+    return;
+  }
+
+  double2 acc[GL_ORDER];
+#pragma unroll
+  for (int l = 0; l < GL_ORDER; ++l) acc[l] = make_double2(0.0, 0.0);
+  const double e0 = -0.5 * PI + h * ip, e1 = e0 + h;
+  const int nsides = (ip == pT) ? 2 : 1;
+  for (int side = 0; side < nsides; ++side) {
+    // outer node `lane`: offset dl from tT and weight
+    const double u = orule->x[lane], wu = orule->w[lane];
+    const double u4 = u * u * u * u;
+    double dl, w;
+    if (ip == pT) {
+      const double ell = (side == 0 ? e0 : e1) - tT;
+      dl = ell * u4 * u;
+      w = fabs(ell) * 5.0 * u4 * wu;
+    } else {
+      const double end = (ip < pT) ? e1 : e0;
+      const double far = (ip < pT) ? e0 : e1;
+      dl = (end - tT) + (far - end) * u4 * u;
+      w = fabs(far - end) * 5.0 * u4 * wu;
+    }
+    NodeLoc L = node_local(shape, a, cc, kappa, tT, thT, dl);
+    L.w = w;
+    const bool modal = L.chim1 < CHI_SPLIT;
+    const unsigned long long mmask = __ballot(modal);
+    const int nmodal = __popcll(mmask);
+    {
+      const unsigned long long below = lane ? (mmask & ((1ull << lane) - 1ull)) : 0ull;
+      if (modal) S.modal_idx[__popcll(below)] = lane;
+    }
+    __syncthreads();
+    // ---- modal route, in batches of QB nodes
+    for (int b0 = 0; b0 < nmodal; b0 += QB) {
+      const int src = (lane < QB && b0 + lane < nmodal) ? S.modal_idx[b0 + lane] : 0;
+      const double chim1 = __shfl(L.chim1, src);
+      if (lane < QB && b0 + lane < nmodal)
+        toroidal_q_lane(1.0 + chim1, chim1, MQ_CAP, S.Q, lane);
+      __syncthreads();
+      const int cnt = min(QB, nmodal - b0);
+      for (int q = 0; q < cnt; ++q) {
+        const int sl = S.modal_idx[b0 + q];
+        const NodeLoc Ln = shfl_node(L, sl);
+        modal_modes(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.twf);
+        const double2 g = modes_to_gj(N, Ln, S.u.m, S.tw2n);
+        // P_l(s) on panel ip (product form), times the weight
+        if (lane < GL_ORDER) {
+          const double xs = 2.0 * (Ln.s - e0) / h - 1.0;
+          double pl = 1.0;
+          for (int m2 = 0; m2 < GL_ORDER; ++m2)
+            if (m2 != lane) pl *= (xs - gl16[m2]) / (gl16[lane] - gl16[m2]);
+          S.Pl[lane] = pl * Ln.w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < GL_ORDER; ++l) {
+          acc[l].x += S.Pl[l] * g.x;
+          acc[l].y += S.Pl[l] * g.y;
+        }
+        __syncthreads();
+      }
+    }
+    // ---- direct route
+    const unsigned long long dmask = ~mmask;
+    for (int q = 0; q < 64; ++q) {
+      if (!((dmask >> q) & 1ull)) continue;
+      const NodeLoc Ln = shfl_node(L, q);
+      for (int l = lane; l < Ld; l += 64) {
+        double sth, cth;
+        sincos(TWO_PI * l / Ld, &sth, &cth);
+        const double dx = Ln.r * cth + Ln.p - xT, dy = Ln.r * sth + Ln.q - yT, dz = Ln.z - zT;
+        const double nx = Ln.r * Ln.dz * cth, ny = Ln.r * Ln.dz * sth;
+        const double nz = -Ln.r * (Ln.dr + Ln.dp * cth + Ln.dq * sth);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double ir = rsqrt(r2);
+        const double rr = r2 * ir;
+        double s, c;
+        sincos(k * rr, &s, &c);
+        const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI;
+        S.u.K[l] = make_double2(-(c + k * rr * s) * sc, (k * rr * c - s) * sc);
+      }
+      if (lane < GL_ORDER) {
+        const double xs = 2.0 * (Ln.s - e0) / h - 1.0;
+        double pl = 1.0;
+        for (int m2 = 0; m2 < GL_ORDER; ++m2)
+          if (m2 != lane) pl *= (xs - gl16[m2]) / (gl16[lane] - gl16[m2]);
+        S.Pl[lane] = pl * Ln.w;
+      }
+      __syncthreads();
+      if (lane < 2 * N) {
+        double gr = 0.0, gi = 0.0;
+        int idx = (Ld - qr * lane) % Ld;
+        for (int l = 0; l < Ld; ++l) {
+          const double lam = S.lam[idx];
+          const double2 kv = S.u.K[l];
+          gr += kv.x * lam;
+          gi += kv.y * lam;
+          idx = (idx + 1 == Ld) ? 0 : idx + 1;
+        }
+        const double f = TWO_PI / Ld;
+        gr *= f;
+        gi *= f;
+#pragma unroll
+        for (int l = 0; l < GL_ORDER; ++l) {
+          acc[l].x += S.Pl[l] * gr;
+          acc[l].y += S.Pl[l] * gi;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (lane < 2 * N) {
+    if (ip == pT && lane == jT) acc[lT].x += 0.5;
+#pragma unroll
+    for (int l = 0; l < GL_ORDER; ++l) row[(int64_t)(ip * GL_ORDER + l) * nth + lane] = acc[l];
+  }
+}
+
+// ---------------------------------------------------------------- launch
+static void outer_rule_host(OuterRule& R) {
+  double x[NGO], w[NGO];
+  gauss_legendre_host(NGO, x, w);
+  for (int i = 0; i < NGO; ++i) {
+    R.x[i] = 0.5 * (x[i] + 1.0);
+    R.w[i] = 0.5 * w[i];
+  }
+}
+
+hipError_t launch_assemble_self(qax_problem* p) {
+  std::vector<SelfTask> tasks;
+  for (int bk = 0; bk < (int)p->hblocks.size(); ++bk) {
+    const BodyDev& B = p->hbodies[p->hblocks[bk].rep_body];
+    for (int row = 0; row < p->hblocks[bk].n; ++row)
+      for (int pan = 0; pan < B.n_panels; ++pan) tasks.push_back(SelfTask{bk, row, pan});
+  }
+  OuterRule R;
+  outer_rule_host(R);
+  SelfTask* d_tasks = nullptr;
+  OuterRule* d_rule = nullptr;
+  hipError_t e = hipMalloc(&d_tasks, tasks.size() * sizeof(SelfTask));
+  if (e != hipSuccess) return e;
+  e = hipMalloc(&d_rule, sizeof(OuterRule));
+  if (e != hipSuccess) { (void)hipFree(d_tasks); return e; }
+  e = hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(SelfTask), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_rule, &R, sizeof(R), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(assemble_self_kernel, dim3((unsigned)tasks.size()), dim3(64), 0, p->stream,
+                       d_tasks, p->d_blocks, p->d_bodies, p->d_gl, d_rule, (double2*)p->d_B);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  (void)hipFree(d_tasks);
+  (void)hipFree(d_rule);
+  return e;
+}
+
+// ---------------------------------------------------------------- test hook
+__global__ __launch_bounds__(64) void modal_modes_kernel(const double* __restrict__ r,
+                                                         const double* __restrict__ rt,
+                                                         const double* __restrict__ c,
+                                                         const double* __restrict__ chim1,
+                                                         const double* __restrict__ rmrt, double k,
+                                                         int nmax, double2* __restrict__ A,
+                                                         double2* __restrict__ B) {
+  __shared__ SelfShared S;
+  const int pt = blockIdx.x;
+  const int lane = threadIdx.x;
+  for (int q = lane; q < LM / 2; q += 64) {
+    double s, cc;
+    sincos(-TWO_PI * q / LM, &s, &cc);
+    S.twf[q] = make_double2(cc, s);
+  }
+  if (lane == 0) toroidal_q_lane(1.0 + chim1[pt], chim1[pt], MQ_CAP, S.Q, 0);
+  __syncthreads();
+  modal_modes(k, r[pt], rt[pt], c[pt], chim1[pt], rmrt[pt], nmax, S.Q, 0, S.u.m, S.twf);
+  if (lane <= nmax) {
+    A[(int64_t)pt * (nmax + 1) + lane] = S.u.m.Am[lane];
+    B[(int64_t)pt * (nmax + 1) + lane] = S.u.m.Bm[lane];
+  }
+}
+
+hipError_t launch_modal_modes(hipStream_t s, int n, const double* r, const double* rt,
+                              const double* c, const double* chim1, const double* rmrt, double k,
+                              int nmax, double* A, double* B) {
+  if (nmax > NTH_MAX / 2 + 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(modal_modes_kernel, dim3(n), dim3(64), 0, s, r, rt, c, chim1, rmrt, k, nmax,
+                     (double2*)A, (double2*)B);
+  return hipGetLastError();
+}
+
+}  // namespace qax
