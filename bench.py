@@ -1,0 +1,217 @@
+#!/usr/bin/env python
+"""Benchmark of the multi-body double-layer solver on one MI355X.
+
+One step = one pass of the whole hot path over the 27-body lattice workload
+(27 bent prolate spheroids, 32 GL x 64 azimuthal nodes each, 55,296 unknowns,
+k = 5, paper incident direction): node build, self-block assembly and
+inversion, mixed-precision solve (FP32 pair sum inside FP64 iterative
+refinement) to a relative residual of 1e-8, far field on the 200 x 200 grid.
+
+value = inter-body pair interactions evaluated in the timed steps / their wall
+time (whole-job throughput; inputs are resident on the device).  The FP64
+solve, the achieved error against an FP64 reference, per-kernel timings
+(HIP events on the library stream), the roofline of the dominant kernel and
+the CPU oracle's pair rate on a bounded sample are reported beside it.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic work per inter-body pair and right-hand side: d = y - x (3),
+# r^2 (5), 1/r (1), r (1), k r (1), sin + cos (2), (ikr - 1) e^{ikr} (4),
+# 1/r^3 (2), n.d (5), scaling (3), complex multiply-add (8)
+FLOP_PER_PAIR = 35
+PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
+
+
+def far_grid(n=200):
+    th = np.linspace(0, 2 * math.pi, n, endpoint=False)
+    ph = (np.arange(n) + 0.5) * math.pi / n
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    return np.stack([np.cos(T) * np.sin(P), np.sin(T) * np.sin(P), np.cos(P)], -1).reshape(-1, 3)
+
+
+def cpu_baseline(scen, budget_s=12.0):
+    """The oracle's pair sum, timed on the host on a bounded target sample
+    (one thread: numpy/BLAS pools limited to 1)."""
+    from oracle import geometry as geo
+    from oracle import pairsum as opair
+    d = geo.discretize(scen)
+    n = d.pos.shape[0]
+    rng = np.random.default_rng(0)
+    mu = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        tg = np.arange(0, 64)
+        t0 = time.perf_counter()
+        opair.pair_sum(d, scen.k, mu, targets=tg)
+        dt = time.perf_counter() - t0
+        per_target = dt / tg.shape[0]
+        m = int(max(64, min(n, budget_s / max(per_target, 1e-9))))
+        tg = np.linspace(0, n - 1, m).astype(np.int64)
+        t0 = time.perf_counter()
+        opair.pair_sum(d, scen.k, mu, targets=tg)
+        dt = time.perf_counter() - t0
+    own = np.bincount(d.body, minlength=len(d.bodies))[d.body[tg]]
+    pairs = int(np.sum(n - own))
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"{m} of {n} target rows of the same workload ({pairs:.3e} pairs, {dt:.1f} s, numpy FP64, 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "sharding is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_31380_amd import qax
+    from paper_2606_31380_amd import scenarios as sc
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    scen = sc.lattice27()
+    P = scen.pairs_per_apply()
+    h = qax.qax_create(0, stream.cuda_stream)
+    xhat = far_grid(200)
+    dirs = np.asarray(scen.dirs, dtype=np.float64)
+
+    qax.qax_build(h, scen.bodies, scen.k)
+    N, _ = qax.qax_size(h)
+    mu = torch.zeros(N, dtype=torch.complex128, device=dev)
+    uinf = torch.zeros(xhat.shape[0], dtype=torch.complex128, device=dev)
+
+    def step(prec):
+        qax.qax_build(h, scen.bodies, scen.k)
+        qax.qax_assemble_self(h)
+        info = qax.qax_solve(h, prec, dirs, mu, 1, tol=args.tol, maxit=1000)
+        qax.qax_farfield(h, mu, xhat, uinf)
+        return info
+
+    for _ in range(args.warmup):
+        step(qax.QAX_MIXED)
+    qax.qax_set_timing(h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [step(qax.QAX_MIXED) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ktimes = {qax.KERNEL_NAMES[k]: qax.qax_timing(h, k) for k in range(5)}
+    qax.qax_set_timing(h, False)
+
+    n32 = sum(i["iters"] for i in infos)          # FP32 pair sums (Krylov steps)
+    n64 = sum(i["outer_iters"] for i in infos)     # FP64 pair sums (true residuals)
+    pairs = P * (n32 + n64)
+    value = pairs / wall
+    ms_per_step = 1e3 * wall / args.steps
+
+    # comparison outside the timed region: FP64 and mixed time-to-solve, error
+    ref = torch.zeros_like(mu)
+    qax.qax_solve(h, qax.QAX_FP64, dirs, ref, 1, tol=1e-12, maxit=2000)
+    x64 = torch.zeros_like(mu)
+    i64 = qax.qax_solve(h, qax.QAX_FP64, dirs, x64, 1, tol=args.tol, maxit=1000)
+    xm = torch.zeros_like(mu)
+    im = qax.qax_solve(h, qax.QAX_MIXED, dirs, xm, 1, tol=args.tol, maxit=1000)
+    err64 = (torch.linalg.norm(x64 - ref) / torch.linalg.norm(ref)).item()
+    errm = (torch.linalg.norm(xm - ref) / torch.linalg.norm(ref)).item()
+    # time-to-solve at the 1e-6 error level
+    x6m = torch.zeros_like(mu)
+    i6m = qax.qax_solve(h, qax.QAX_MIXED, dirs, x6m, 1, tol=1e-6, maxit=1000)
+    x66 = torch.zeros_like(mu)
+    i66 = qax.qax_solve(h, qax.QAX_FP64, dirs, x66, 1, tol=1e-6, maxit=1000)
+    e6m = (torch.linalg.norm(x6m - ref) / torch.linalg.norm(ref)).item()
+    e66 = (torch.linalg.norm(x66 - ref) / torch.linalg.norm(ref)).item()
+    # pair-sum kernel rates on their own (HIP events on the library stream)
+    qax.qax_set_timing(h, True)
+    v = torch.randn(N, dtype=torch.complex128, device=dev)
+    o = torch.zeros_like(v)
+    for _ in range(5):
+        qax.qax_pair_sum(h, qax.QAX_FP64, v, o)
+        qax.qax_pair_sum(h, qax.QAX_MIXED, v, o)
+    ps64 = qax.qax_timing(h, qax.QAX_K_PAIRSUM_FP64)
+    ps32 = qax.qax_timing(h, qax.QAX_K_PAIRSUM_FP32)
+    qax.qax_set_timing(h, False)
+
+    # rooflines of the timed kernels; "roofline" is the dominant one
+    nb = scen.nodes_per_body().astype(np.float64)
+    nth = scen.bodies["n_theta"].astype(np.float64)
+    npan = scen.bodies["n_panels"].astype(np.float64)
+    # self-block assembly: per (target row, outer node) an azimuthal integral
+    # against 2N Lagrange functions: 256 kernel samples (35 flop each), a
+    # 256-point FFT (5 L log2 L), the (2N+1) -> 2N inverse DFT (8 flop per
+    # term) and the 16 x 2N contraction (8 flop per term); outer nodes per row:
+    # 128 on the own panel + 64 per adjacent panel
+    per_node = 35 * 256 + 5 * 256 * 8 + 8 * (nth + 1) * nth + 8 * 16 * nth
+    adj = np.where(npan > 1, np.where(npan > 2, 2.0 - 2.0 / npan, 1.0), 0.0)
+    self_flop = float(np.sum(nb * (128 + 64 * adj) * per_node))
+    inv_flop = float(np.sum(8.0 * nb ** 3))
+    work = {"pair_sum_fp32": ("alu", FLOP_PER_PAIR * P, PEAK["fp32"], "TFLOP/s"),
+            "pair_sum_fp64": ("alu", FLOP_PER_PAIR * P, PEAK["fp64"], "TFLOP/s"),
+            "block_apply": ("hbm", float(np.sum(nb * nb)) * 8.0, PEAK["hbm"], "GB/s"),
+            "self_assembly": ("alu", self_flop, PEAK["fp64"], "TFLOP/s"),
+            "invert": ("alu", inv_flop, PEAK["fp64"], "TFLOP/s")}
+    rooflines = {}
+    for name, (cnt, tot) in ktimes.items():
+        if cnt == 0 or tot <= 0:
+            continue
+        bound, units, peak, unit = work[name]
+        avg_s = tot / cnt / 1e3
+        ach = units / avg_s
+        scale = 1e9 if unit == "GB/s" else 1e12
+        rooflines[name] = {"bound": bound, "achieved": ach / scale, "peak": peak / scale,
+                           "unit": unit, "frac": ach / peak, "traffic": None,
+                           "avg_launch_ms": avg_s * 1e3, "launches": cnt}
+    dom = max(ktimes, key=lambda k: ktimes[k][1])
+    roof = dict(rooflines[dom], kernel=dom)
+
+    out = {
+        "metric": "Helmholtz pair-interactions/s + time-to-solve @1e-6 rel err, mixed vs FP64",
+        "value": value, "unit": "pair-interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "lattice27: 27 bent spheroids (0.5,0.5,1.0), 3x3x3 spacing 3, "
+                               "32 GL x 64 azimuths, N=55296, k=5, mixed solve to 1e-8",
+                   "n_unknowns": int(N), "pairs_per_apply": int(P)},
+        "time_to_solve_1e-6": {"mixed_s": i6m["t_solve_s"], "fp64_s": i66["t_solve_s"],
+                               "mixed_err": e6m, "fp64_err": e66,
+                               "mixed_iters": i6m["iters"], "fp64_iters": i66["iters"]},
+        "time_to_solve_tol": {"tol": args.tol, "mixed_s": im["t_solve_s"], "fp64_s": i64["t_solve_s"],
+                              "mixed_err": errm, "fp64_err": err64},
+        "pair_sum_kernel": {
+            "fp32_pairs_per_s": P * ps32[0] / (ps32[1] / 1e3) if ps32[1] > 0 else None,
+            "fp64_pairs_per_s": P * ps64[0] / (ps64[1] / 1e3) if ps64[1] > 0 else None,
+            "fp32_ms": ps32[1] / max(ps32[0], 1), "fp64_ms": ps64[1] / max(ps64[0], 1)},
+        "kernel_ms_per_step": {k: v[1] / args.steps for k, v in ktimes.items()},
+        "solver_iters_per_step": {"fp32_pair_sums": n32 / args.steps, "fp64_pair_sums": n64 / args.steps},
+        "roofline": roof,
+        "kernel_rooflines": rooflines,
+    }
+    qax.qax_destroy(h)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(scen)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

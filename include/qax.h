@@ -70,7 +70,7 @@ typedef enum {
  * contiguous and problems in increasing order. */
 typedef struct {
   int32_t shape;
-  int32_t n_panels;   /* 1..64                                              */
+  int32_t n_panels;   /* 1..8 (at most 8192 nodes per body)                 */
   int32_t n_theta;    /* even, 4..64                                        */
   int32_t problem;
   double a, c;        /* shape parameters (see qax_shape)                   */
@@ -172,6 +172,24 @@ qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrhs,
 qax_status qax_modal_modes(qax_problem* p, int32_t n_pts, const double* d_r, const double* d_rt,
                            const double* d_c, const double* d_chim1, const double* d_rmrt,
                            double k, int32_t nmax, void* d_A, void* d_B);
+
+/* Kernel timing (instrumentation).  When enabled, each launch of the kernels
+ * below is bracketed by HIP events recorded on the handle's stream and its
+ * duration is accumulated per kernel kind.  Disabled by default. */
+typedef enum {
+  QAX_K_PAIRSUM_FP64 = 0,  /* inter-body pair sum, FP64                        */
+  QAX_K_PAIRSUM_FP32 = 1,  /* inter-body pair sum, FP32 compensated            */
+  QAX_K_BLOCK_APPLY = 2,   /* block-diagonal apply (B or B^-1)                 */
+  QAX_K_SELF_ASSEMBLY = 3, /* self-block assembly                              */
+  QAX_K_INVERT = 4,        /* self-block inversion                             */
+  QAX_K_COUNT = 5
+} qax_kernel;
+
+/* enable != 0 turns timing on (and clears the counters). */
+qax_status qax_set_timing(qax_problem* p, int32_t enable);
+/* Launch count and summed duration (milliseconds) of one kernel kind since
+ * timing was enabled. */
+qax_status qax_timing(const qax_problem* p, int32_t kernel, int64_t* launches, double* total_ms);
 
 #ifdef __cplusplus
 }

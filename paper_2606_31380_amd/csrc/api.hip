@@ -77,6 +77,48 @@ static void* dbuf(qax_problem* p, const char* name, size_t bytes, qax_status* st
 
 void* scratch(qax_problem* p, size_t bytes, qax_status* st) { return dbuf(p, "scratch", bytes, st); }
 
+static hipEvent_t take_event(qax_problem* p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void timing_begin(qax_problem* p, int kind) {
+  if (!p->timing) return;
+  qax_problem::Pending pe{kind, take_event(p), nullptr};
+  if (pe.a) (void)hipEventRecord(pe.a, p->stream);
+  p->pending.push_back(pe);
+}
+
+void timing_end(qax_problem* p, int kind) {
+  if (!p->timing) return;
+  for (auto it = p->pending.rbegin(); it != p->pending.rend(); ++it) {
+    if (it->kind == kind && it->b == nullptr) {
+      it->b = take_event(p);
+      if (it->b) (void)hipEventRecord(it->b, p->stream);
+      return;
+    }
+  }
+}
+
+void collect_timing(qax_problem* p) {
+  for (auto& pe : p->pending) {
+    float ms = 0.0f;
+    if (pe.a && pe.b && hipEventElapsedTime(&ms, pe.a, pe.b) == hipSuccess) {
+      p->t_launches[pe.kind] += 1;
+      p->t_ms[pe.kind] += ms;
+    }
+    if (pe.a) p->event_pool.push_back(pe.a);
+    if (pe.b) p->event_pool.push_back(pe.b);
+  }
+  p->pending.clear();
+}
+
 }  // namespace qax
 
 #define QCHECK(expr, what)                                   \
@@ -134,6 +176,8 @@ extern "C" void qax_destroy(qax_problem* p) {
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
   free_geometry(p);
+  collect_timing(p);
+  for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
   auto it = registry().find(p);
   if (it != registry().end()) {
     for (auto& kv : it->second.m)
@@ -146,7 +190,33 @@ extern "C" void qax_destroy(qax_problem* p) {
 extern "C" const char* qax_last_error(const qax_problem* p) { return p ? p->err.c_str() : "null handle"; }
 
 static qax_status sync(qax_problem* p, const char* what) {
-  return hip_check(p, hipStreamSynchronize(p->stream), what);
+  qax_status st = hip_check(p, hipStreamSynchronize(p->stream), what);
+  if (st == QAX_OK && !p->pending.empty()) collect_timing(p);
+  return st;
+}
+
+extern "C" qax_status qax_set_timing(qax_problem* p, int32_t enable) {
+  if (!p) return QAX_ERR_ARG;
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  collect_timing(p);
+  p->timing = enable != 0;
+  for (int i = 0; i < QAX_K_COUNT; ++i) {
+    p->t_launches[i] = 0;
+    p->t_ms[i] = 0.0;
+  }
+  return QAX_OK;
+}
+
+extern "C" qax_status qax_timing(const qax_problem* pc, int32_t kernel, int64_t* launches, double* total_ms) {
+  qax_problem* p = const_cast<qax_problem*>(pc);
+  if (!p || kernel < 0 || kernel >= QAX_K_COUNT || !launches || !total_ms) return QAX_ERR_ARG;
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  collect_timing(p);
+  *launches = p->t_launches[kernel];
+  *total_ms = p->t_ms[kernel];
+  return QAX_OK;
 }
 
 // ---------------------------------------------------------------- build
@@ -175,7 +245,7 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
   for (int i = 0; i < n_bodies; ++i) {
     const qax_body& b = bodies[i];
     if (b.shape < 0 || b.shape > 2) return fail(p, QAX_ERR_ARG, "qax_build: unknown shape");
-    if (b.n_panels < 1 || b.n_panels > 64) return fail(p, QAX_ERR_ARG, "qax_build: n_panels out of range");
+    if (b.n_panels < 1 || b.n_panels > 8) return fail(p, QAX_ERR_ARG, "qax_build: n_panels must be in [1, 8]");
     if (b.n_theta < 4 || b.n_theta > 64 || (b.n_theta & 1))
       return fail(p, QAX_ERR_ARG, "qax_build: n_theta must be even in [4, 64]");
     if (b.problem < 0 || b.problem >= n_problems || b.problem < prev || b.problem > prev + 1)
@@ -676,7 +746,7 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
     QCHECK(launch_block_apply(p, 1, inner_prec, t, x, nrhs, true), "precond");
     ++outer;
   }
-  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  if ((st = sync(p, "qax_solve")) != QAX_OK) return st;
   auto t1 = std::chrono::steady_clock::now();
   if (info) {
     info->iters = total_its;

@@ -9,11 +9,11 @@
 // coalesced 16-byte (FP64 complex) or 8-byte (FP32 complex) loads, and the
 // input slice comes from L2.  FP32 storage is accumulated in FP64.
 //
-// Inversion: Gauss-Jordan elimination with partial pivoting, in place, batched
-// over matrices of different orders; one pivot launch and one rank-1 update
-// launch per elimination step.
+// Inversion: blocked Gauss-Jordan elimination with partial pivoting, in place,
+// batched over matrices of different orders (see gj_invert).
 #include <hip/hip_runtime.h>
 
+#include "fastmath.h"
 #include "internal.h"
 
 namespace qax {
@@ -82,6 +82,7 @@ static void gemv_launch(qax_problem* p, const MT* pool, const double* v, double*
 
 hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,
                               int nrhs, bool accumulate) {
+  timing_begin(p, QAX_K_BLOCK_APPLY);
   if (inverse && prec == QAX_MIXED) {
     if (nrhs == 1) gemv_launch<float, 1>(p, p->d_Binv32, v, out, nrhs, accumulate);
     else gemv_launch<float, 4>(p, p->d_Binv32, v, out, nrhs, accumulate);
@@ -90,6 +91,7 @@ hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const doubl
     if (nrhs == 1) gemv_launch<double, 1>(p, pool, v, out, nrhs, accumulate);
     else gemv_launch<double, 4>(p, pool, v, out, nrhs, accumulate);
   }
+  timing_end(p, QAX_K_BLOCK_APPLY);
   return hipGetLastError();
 }
 
@@ -112,83 +114,6 @@ struct MatDesc {
   int32_t n;
 };
 
-// Step k, one workgroup per matrix: pivot search in column k (rows >= k),
-// row swap, scaling of row k, and a copy of column k (the multipliers).
-__global__ __launch_bounds__(256) void gj_pivot_kernel(const MatDesc* __restrict__ mats,
-                                                       double2* __restrict__ pool, int k,
-                                                       int32_t* __restrict__ piv,
-                                                       double2* __restrict__ colbuf,
-                                                       int64_t col_stride, int nmax) {
-  const MatDesc M = mats[blockIdx.x];
-  const int n = M.n;
-  if (k >= n) return;
-  double2* A = pool + M.elem_off;
-  __shared__ double best[256];
-  __shared__ int bidx[256];
-  double bv = -1.0;
-  int bi = k;
-  for (int i = k + threadIdx.x; i < n; i += 256) {
-    const double2 a = A[(int64_t)i * n + k];
-    const double m = a.x * a.x + a.y * a.y;
-    if (m > bv) { bv = m; bi = i; }
-  }
-  best[threadIdx.x] = bv;
-  bidx[threadIdx.x] = bi;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      const double o = best[threadIdx.x + s];
-      const int oi = bidx[threadIdx.x + s];
-      if (o > best[threadIdx.x] || (o == best[threadIdx.x] && oi < bidx[threadIdx.x])) {
-        best[threadIdx.x] = o;
-        bidx[threadIdx.x] = oi;
-      }
-    }
-    __syncthreads();
-  }
-  const int p = bidx[0];
-  if (threadIdx.x == 0) piv[(int64_t)blockIdx.x * nmax + k] = p;
-  if (p != k) {
-    for (int j = threadIdx.x; j < n; j += 256) {
-      const double2 t = A[(int64_t)k * n + j];
-      A[(int64_t)k * n + j] = A[(int64_t)p * n + j];
-      A[(int64_t)p * n + j] = t;
-    }
-  }
-  __syncthreads();
-  const double2 d = A[(int64_t)k * n + k];
-  const double den = d.x * d.x + d.y * d.y;
-  const double2 inv = make_double2(d.x / den, -d.y / den);
-  __syncthreads();
-  // multipliers of column k (before the row scaling touches A[k][k])
-  double2* col = colbuf + (int64_t)blockIdx.x * col_stride;
-  for (int i = threadIdx.x; i < n; i += 256) col[i] = A[(int64_t)i * n + k];
-  __syncthreads();
-  for (int j = threadIdx.x; j < n; j += 256) {
-    const double2 a = (j == k) ? make_double2(1.0, 0.0) : A[(int64_t)k * n + j];
-    A[(int64_t)k * n + j] = make_double2(a.x * inv.x - a.y * inv.y, a.x * inv.y + a.y * inv.x);
-  }
-}
-
-// Step k: rows i != k: A[i][j] = (j == k ? 0 : A[i][j]) - f_i A[k][j].
-__global__ __launch_bounds__(256) void gj_update_kernel(const MatDesc* __restrict__ mats,
-                                                        double2* __restrict__ pool, int k,
-                                                        const double2* __restrict__ colbuf,
-                                                        int64_t col_stride) {
-  const MatDesc M = mats[blockIdx.z];
-  const int n = M.n;
-  if (k >= n) return;
-  const int i = blockIdx.y;
-  if (i >= n || i == k) return;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  double2* A = pool + M.elem_off;
-  const double2 f = colbuf[(int64_t)blockIdx.z * col_stride + i];
-  const double2 rk = A[(int64_t)k * n + j];
-  const double2 a = (j == k) ? make_double2(0.0, 0.0) : A[(int64_t)i * n + j];
-  A[(int64_t)i * n + j] = make_double2(a.x - (f.x * rk.x - f.y * rk.y), a.y - (f.x * rk.y + f.y * rk.x));
-}
-
 // Undo the row interchanges as column interchanges, last step first.
 __global__ void gj_unpivot_kernel(const MatDesc* __restrict__ mats, double2* __restrict__ pool,
                                   const int32_t* __restrict__ piv, int nmax) {
@@ -208,18 +133,200 @@ __global__ void gj_unpivot_kernel(const MatDesc* __restrict__ mats, double2* __r
   }
 }
 
+// ---------------------------------------------------------------- blocked Gauss-Jordan
+// Panels of GJB columns.  For the panel [k0, k0+w): (1) one workgroup per
+// matrix runs the unblocked elimination with partial pivoting restricted to the
+// panel columns (pivot rows >= k); (2) the panel's row interchanges are applied
+// to every other column and the panel rows are copied to W; (3) every other
+// column is updated, A[i][j] = (i in panel ? 0 : A[i][j]) + sum_p A[i][k0+p] W[p][j]
+// (the block form of the same row operations).  Column interchanges undo the
+// row interchanges at the end.
+constexpr int GJB = 64;
+
+__global__ __launch_bounds__(1024) void gjb_panel_kernel(const MatDesc* __restrict__ mats,
+                                                         double2* __restrict__ pool, int k0,
+                                                         int32_t* __restrict__ piv,
+                                                         double2* __restrict__ colbuf,
+                                                         int64_t col_stride, int nmax) {
+  const MatDesc M = mats[blockIdx.x];
+  const int n = M.n;
+  if (k0 >= n) return;
+  double2* A = pool + M.elem_off;
+  double2* col = colbuf + (int64_t)blockIdx.x * col_stride;
+  const int kend = min(k0 + GJB, n);
+  const int w = kend - k0;
+  const int tid = threadIdx.x;
+  __shared__ double best[1024];
+  __shared__ int bidx[1024];
+  __shared__ double2 rowk[GJB];
+  for (int k = k0; k < kend; ++k) {
+    double bv = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < n; i += 1024) {
+      const double2 a = A[(int64_t)i * n + k];
+      const double m = a.x * a.x + a.y * a.y;
+      if (m > bv) { bv = m; bi = i; }
+    }
+    best[tid] = bv;
+    bidx[tid] = bi;
+    __syncthreads();
+    for (int st = 512; st > 0; st >>= 1) {
+      if (tid < st) {
+        const double o = best[tid + st];
+        const int oi = bidx[tid + st];
+        if (o > best[tid] || (o == best[tid] && oi < bidx[tid])) {
+          best[tid] = o;
+          bidx[tid] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int pr = bidx[0];
+    if (tid == 0) piv[(int64_t)blockIdx.x * nmax + k] = pr;
+    if (pr != k && tid < w) {
+      const int c = k0 + tid;
+      const double2 t = A[(int64_t)k * n + c];
+      A[(int64_t)k * n + c] = A[(int64_t)pr * n + c];
+      A[(int64_t)pr * n + c] = t;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += 1024) col[i] = A[(int64_t)i * n + k];
+    __syncthreads();
+    const double2 d = col[k];
+    const double den = d.x * d.x + d.y * d.y;
+    const double2 inv = make_double2(d.x / den, -d.y / den);
+    if (tid < w) {
+      const int c = k0 + tid;
+      const double2 a = (c == k) ? make_double2(1.0, 0.0) : A[(int64_t)k * n + c];
+      const double2 v = make_double2(a.x * inv.x - a.y * inv.y, a.x * inv.y + a.y * inv.x);
+      A[(int64_t)k * n + c] = v;
+      rowk[tid] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * w; e += 1024) {
+      const int i = e / w;
+      const int cc = e % w;
+      if (i == k) continue;
+      const int c = k0 + cc;
+      const double2 fi = col[i];
+      const double2 rk = rowk[cc];
+      const double2 a = (c == k) ? make_double2(0.0, 0.0) : A[(int64_t)i * n + c];
+      A[(int64_t)i * n + c] = make_double2(a.x - (fi.x * rk.x - fi.y * rk.y),
+                                           a.y - (fi.x * rk.y + fi.y * rk.x));
+    }
+    __syncthreads();
+  }
+}
+
+// Row interchanges of the panel applied to the other columns, then the panel
+// rows copied to W (w x n per matrix).
+__global__ void gjb_swap_copy_kernel(const MatDesc* __restrict__ mats, double2* __restrict__ pool,
+                                     int k0, const int32_t* __restrict__ piv, int nmax,
+                                     double2* __restrict__ W) {
+  const MatDesc M = mats[blockIdx.y];
+  const int n = M.n;
+  if (k0 >= n) return;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int kend = min(k0 + GJB, n);
+  double2* A = pool + M.elem_off;
+  double2* Wm = W + (int64_t)blockIdx.y * GJB * nmax;
+  const bool in_panel = j >= k0 && j < kend;
+  if (!in_panel) {
+    const int32_t* pv = piv + (int64_t)blockIdx.y * nmax;
+    for (int k = k0; k < kend; ++k) {
+      const int pr = pv[k];
+      if (pr != k) {
+        const double2 t = A[(int64_t)k * n + j];
+        A[(int64_t)k * n + j] = A[(int64_t)pr * n + j];
+        A[(int64_t)pr * n + j] = t;
+      }
+    }
+  }
+  for (int k = k0; k < kend; ++k)
+    Wm[(int64_t)(k - k0) * nmax + j] = in_panel ? make_double2(0.0, 0.0) : A[(int64_t)k * n + j];
+}
+
+// A[i][j] = (i in panel ? 0 : A[i][j]) + sum_p A[i][k0+p] W[p][j] for j outside
+// the panel.  64 x 64 output tile per workgroup, 4 x 4 per thread.
+__global__ __launch_bounds__(256) void gjb_update_kernel(const MatDesc* __restrict__ mats,
+                                                         double2* __restrict__ pool, int k0,
+                                                         const double2* __restrict__ W, int nmax) {
+  const MatDesc M = mats[blockIdx.z];
+  const int n = M.n;
+  if (k0 >= n) return;
+  const int kend = min(k0 + GJB, n);
+  const int w = kend - k0;
+  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  if (i0 >= n || j0 >= n) return;
+  if (j0 >= k0 && j0 + 64 <= kend) return;  // tile inside the panel columns
+  double2* A = pool + M.elem_off;
+  const double2* Wm = W + (int64_t)blockIdx.z * GJB * nmax;
+  __shared__ double2 As[16][64];
+  __shared__ double2 Ws[16][64];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double2 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
+  for (int p0 = 0; p0 < w; p0 += 16) {
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int pp = e >> 6, rr = e & 63;
+      const int i = i0 + rr, pcol = p0 + pp;
+      As[pp][rr] = (i < n && pcol < w) ? A[(int64_t)i * n + k0 + pcol] : make_double2(0.0, 0.0);
+      const int j = j0 + rr;
+      Ws[pp][rr] = (j < n && pcol < w) ? Wm[(int64_t)pcol * nmax + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int pp = 0; pp < 16; ++pp) {
+      double2 av[4], wv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[pp][ty + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) wv[b] = Ws[pp][tx + 16 * b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          acc[a][b].x += av[a].x * wv[b].x - av[a].y * wv[b].y;
+          acc[a][b].y += av[a].x * wv[b].y + av[a].y * wv[b].x;
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int i = i0 + ty + 16 * a;
+    if (i >= n) continue;
+    const bool prow = i >= k0 && i < kend;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = j0 + tx + 16 * b;
+      if (j >= n || (j >= k0 && j < kend)) continue;
+      double2* cptr = A + (int64_t)i * n + j;
+      const double2 base = prow ? make_double2(0.0, 0.0) : *cptr;
+      *cptr = make_double2(base.x + acc[a][b].x, base.y + acc[a][b].y);
+    }
+  }
+}
+
 // In-place inversion of `batch` matrices described on the device by `mats`
-// (orders up to nmax).  work: nmax*batch complex (multipliers) + nmax*batch
-// int32 (pivots) + batch MatDesc, provided by the caller.
+// (orders up to nmax).  work: see gj_work_bytes.
 hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int batch, int nmax,
                      double* work) {
   double2* colbuf = (double2*)work;
-  int32_t* piv = (int32_t*)(colbuf + (int64_t)nmax * batch);
-  for (int k = 0; k < nmax; ++k) {
-    hipLaunchKernelGGL(gj_pivot_kernel, dim3(batch), dim3(256), 0, s, d_mats, (double2*)pool, k,
+  double2* W = colbuf + (int64_t)nmax * batch;
+  int32_t* piv = (int32_t*)(W + (int64_t)GJB * nmax * batch);
+  const unsigned tiles = (unsigned)((nmax + 63) / 64);
+  for (int k0 = 0; k0 < nmax; k0 += GJB) {
+    hipLaunchKernelGGL(gjb_panel_kernel, dim3(batch), dim3(1024), 0, s, d_mats, (double2*)pool, k0,
                        piv, colbuf, (int64_t)nmax, nmax);
-    hipLaunchKernelGGL(gj_update_kernel, dim3((nmax + 255) / 256, nmax, batch), dim3(256), 0, s,
-                       d_mats, (double2*)pool, k, colbuf, (int64_t)nmax);
+    hipLaunchKernelGGL(gjb_swap_copy_kernel, dim3((nmax + 255) / 256, batch), dim3(256), 0, s,
+                       d_mats, (double2*)pool, k0, piv, nmax, W);
+    hipLaunchKernelGGL(gjb_update_kernel, dim3(tiles, tiles, batch), dim3(256), 0, s, d_mats,
+                       (double2*)pool, k0, W, nmax);
   }
   hipLaunchKernelGGL(gj_unpivot_kernel, dim3((nmax + 255) / 256, batch), dim3(256), 0, s, d_mats,
                      (double2*)pool, piv, nmax);
@@ -227,7 +334,7 @@ hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int bat
 }
 
 size_t gj_work_bytes(int batch, int nmax) {
-  return (size_t)nmax * batch * (sizeof(double2) + sizeof(int32_t)) + 256;
+  return (size_t)nmax * batch * (sizeof(double2) * (1 + GJB) + sizeof(int32_t)) + 256;
 }
 
 // Invert every distinct self block: copy B into Binv, invert in place, make
@@ -248,7 +355,9 @@ hipError_t launch_invert_blocks(qax_problem* p, double* work) {
   double* w2 = (double*)((char*)work + ((nbk * sizeof(MatDesc) + 255) / 256) * 256);
   e = hipMemcpyAsync(d_md, md.data(), nbk * sizeof(MatDesc), hipMemcpyHostToDevice, p->stream);
   if (e != hipSuccess) return e;
+  timing_begin(p, QAX_K_INVERT);
   e = gj_invert(p->stream, p->d_Binv, d_md, nbk, nmax, w2);
+  timing_end(p, QAX_K_INVERT);
   if (e != hipSuccess) return e;
   return launch_convert_f32(p->stream, p->d_Binv, p->d_Binv32, p->block_elems * 2);
 }
@@ -284,7 +393,7 @@ __global__ void dense_offdiag_kernel(const BodyDev* __restrict__ bodies,
   const double ir = rsqrt(r2);
   const double r = r2 * ir;
   double s, c;
-  sincos(k * r, &s, &c);
+  sincos_cw(k * r, &s, &c);
   const double sc = (aw[j] * dx + aw[N + j] * dy + aw[2 * N + j] * dz) * ir * ir * ir * INV_FOUR_PI_D;
   A[i * N + j] = make_double2(-(c + k * r * s) * sc, (k * r * c - s) * sc);
 }

@@ -92,7 +92,8 @@ __global__ void build_nodes_kernel(const BodyDev* __restrict__ bodies, int nb, i
   aw[2 * N + i] = nl[2];
   loc32[i] = make_float4((float)yl[0], (float)yl[1], (float)yl[2],
                          (float)(yl[0] * yl[0] + yl[1] * yl[1] + yl[2] * yl[2]));
-  aw32[i] = make_float4((float)nl[0], (float)nl[1], (float)nl[2], 0.0f);
+  aw32[i] = make_float4((float)nl[0], (float)nl[1], (float)nl[2],
+                        (float)(nl[0] * yl[0] + nl[1] * yl[1] + nl[2] * yl[2]));
 }
 
 hipError_t launch_build_nodes(qax_problem* p) {

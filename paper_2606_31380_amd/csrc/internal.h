@@ -78,7 +78,7 @@ struct qax_problem {
   double* d_pos = nullptr;      // SoA: x[N], y[N], z[N]
   double* d_aw = nullptr;       // SoA
   float* d_loc32 = nullptr;     // float4 per node: local offset from the body centre, |y'|^2
-  float* d_aw32 = nullptr;      // float4 per node: aw, 0
+  float* d_aw32 = nullptr;      // float4 per node: aw, aw . (local offset)
   double* d_gl = nullptr;       // 16 GL nodes, 16 weights on [-1, 1]
 
   // self blocks (complex128 / complex64 pools)
@@ -95,9 +95,27 @@ struct qax_problem {
   // scratch
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;
+
+  // kernel timing
+  bool timing = false;
+  struct Pending {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> event_pool;
+  int64_t t_launches[QAX_K_COUNT] = {0};
+  double t_ms[QAX_K_COUNT] = {0};
 };
 
 namespace qax {
+
+// timing: begin/end bracket a launch of kernel `kind` on p->stream;
+// collect_timing() folds completed brackets into the counters (call after a
+// stream synchronisation).
+void timing_begin(qax_problem* p, int kind);
+void timing_end(qax_problem* p, int kind);
+void collect_timing(qax_problem* p);
 
 // error helpers
 qax_status fail(qax_problem* p, qax_status s, const std::string& msg);

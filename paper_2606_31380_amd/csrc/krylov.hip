@@ -9,6 +9,7 @@
 // reduced in a fixed order so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include "fastmath.h"
 #include "internal.h"
 #include "krylov.h"
 
@@ -27,7 +28,7 @@ __global__ void rhs_kernel(const BodyDev* __restrict__ bodies, const int32_t* __
   const double* d = dirs + ((int64_t)B.problem * nrhs + r) * 3;
   const double ph = B.k * (d[0] * pos[n] + d[1] * pos[N + n] + d[2] * pos[2 * N + n]);
   double s, c;
-  sincos(ph, &s, &c);
+  sincos_cw(ph, &s, &c);
   out[e] = make_double2(-c, -s);
 }
 
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(256) void farfield_kernel(const double* __restrict_
   for (int64_t n = threadIdx.x; n < n0; n += 256) {
     const double ph = -k * (hx * pos[n] + hy * pos[N + n] + hz * pos[2 * N + n]);
     double s, c;
-    sincos(ph, &s, &c);
+    sincos_cw(ph, &s, &c);
     const double nd = hx * aw[n] + hy * aw[N + n] + hz * aw[2 * N + n];
     // (-i k nd) (c + i s) = k nd s - i k nd c
     const double fr = k * nd * s, fi = -k * nd * c;

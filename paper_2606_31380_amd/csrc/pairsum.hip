@@ -13,17 +13,19 @@
 //
 // FP64 path: plain FP64 arithmetic.
 // FP32 path: the phase k r is never formed in FP32.  For target x_i and source
-// body b with centre c_b, D = c_b - x_i is formed in FP64 once per (target,
-// body); per pair only delta = r - |D| is needed, obtained from the FP32
-// estimate r - |D| by one Newton step on delta (2|D| + delta) = 2 D.y' + |y'|^2
-// (y' = y_j - c_b, stored in FP32), so the phase frac(k|D|/2pi) + k delta/2pi
-// stays accurate to FP32 rounding of delta.  Sums are accumulated in FP32 per
+// body b with centre c_b, D = c_b - x_i, |D| and frac(k|D|/2pi) are formed in
+// FP64 once per (target, body).  Per pair, with y' = y_j - c_b stored in FP32,
+// num = 2 D.y' + |y'|^2 = r^2 - |D|^2 is formed without cancellation, r^2 =
+// |D|^2 + num, and delta = r - |D| = num / (r + |D|); the phase
+// frac(k|D|/2pi) + k delta/2pi then carries only the FP32 rounding of delta
+// (relative), not that of r (absolute, ulp(|D|)).  Sums are accumulated in FP32 per
 // tile and the tile sums are added with an error-free TwoSum (compensated
 // accumulation).
 #include <algorithm>
 #include <cmath>
 #include <vector>
 
+#include "fastmath.h"
 #include "internal.h"
 
 namespace qax {
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
           const double r = r2 * ir;
           const double kr = k * r;
           double s, c;
-          sincos(kr, &s, &c);
+          sincos_cw(kr, &s, &c);
           const double dot = sax[jj] * dx + say[jj] * dy + saz[jj] * dz;
           const double sc = dot * ir * ir * ir;
           const double re = -(c + kr * s) * sc;
@@ -140,15 +142,17 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
     const int64_t s0 = B.off;
     const int nb = B.n;
     const bool own = (mybody == b);
-    // per (target, source body) set-up in FP64
+    // per (target, source body) set-up in FP64: D = c_b - x_i, |D|, |D|^2 and
+    // the phase frac(k |D| / 2 pi)
     const double Dx = B.cen[0] - xi, Dy = B.cen[1] - yi, Dz = B.cen[2] - zi;
-    const double Dn = sqrt(Dx * Dx + Dy * Dy + Dz * Dz);
+    const double D2 = Dx * Dx + Dy * Dy + Dz * Dz;
+    const double Dn = sqrt(D2);
     double ph0d = k * Dn / TWO_PI;
     ph0d -= floor(ph0d);
     const float dxf = (float)Dx, dyf = (float)Dy, dzf = (float)Dz;
+    const float dx2 = 2.0f * dxf, dy2 = 2.0f * dyf, dz2 = 2.0f * dzf;
+    const float d2f = (float)D2;
     const float dnf = (float)Dn;
-    const float two_dn = (float)(2.0 * Dn);
-    const float inv2dn = (float)(0.5 / Dn);
     const float ph0 = (float)ph0d;
     for (int base = 0; base < nb; base += TPB) {
       const int cnt = min(TPB, nb - base);
@@ -168,31 +172,33 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
         float tr[NRC], ti[NRC];
 #pragma unroll
         for (int r = 0; r < NRC; ++r) { tr[r] = 0.0f; ti[r] = 0.0f; }
+#pragma unroll 4
         for (int jj = 0; jj < cnt; ++jj) {
-          const float4 yl = sloc[jj];
-          const float4 a4 = saw[jj];
-          const float ex = dxf + yl.x, ey = dyf + yl.y, ez = dzf + yl.z;   // y_j - x_i
-          const float r2 = ex * ex + ey * ey + ez * ez;
+          const float4 yl = sloc[jj];      // y' = y_j - c_b, |y'|^2
+          const float4 a4 = saw[jj];       // aw_j, aw_j . y'
+          // num = 2 D.y' + |y'|^2 = r^2 - |D|^2 without cancellation
+          const float num = fmaf(dx2, yl.x, fmaf(dy2, yl.y, fmaf(dz2, yl.z, yl.w)));
+          const float r2 = d2f + num;
           const float ir = __builtin_amdgcn_rsqf(r2);
           const float r = r2 * ir;
-          const float dy = dxf * yl.x + dyf * yl.y + dzf * yl.z;
-          const float num = 2.0f * dy + yl.w;            // 2 D.y' + |y'|^2
-          const float d0 = r - dnf;                      // FP32 estimate of r - |D|
-          const float res = d0 * (d0 + two_dn) - num;    // Newton residual
-          const float delta = d0 - res * inv2dn;
-          const float ph = ph0 + delta * k2pi;           // revolutions
+          // delta = r - |D| = num / (r + |D|): the phase is never formed from r
+          const float delta = num * __builtin_amdgcn_rcpf(r + dnf);
+          const float ph = fmaf(delta, k2pi, ph0);            // revolutions
           const float s = __builtin_amdgcn_sinf(ph);
           const float c = __builtin_amdgcn_cosf(ph);
           const float kr = kf * r;
-          const float dot = a4.x * ex + a4.y * ey + a4.z * ez;
+          // aw . (y - x) = aw . D + aw . y'
+          const float dot = fmaf(a4.x, dxf, fmaf(a4.y, dyf, fmaf(a4.z, dzf, a4.w)));
           const float sc = dot * (ir * ir * ir);
-          const float re = -(c + kr * s) * sc;
-          const float im = (kr * c - s) * sc;
+          const float re = -fmaf(kr, s, c) * sc;               // Re (ikr - 1) e^{ikr} / r^3 (.)
+          const float im = fmaf(kr, c, -s) * sc;
 #pragma unroll
           for (int r_ = 0; r_ < NRC; ++r_) {
             const float2 m = smu[jj * NRC + r_];
-            tr[r_] += re * m.x - im * m.y;
-            ti[r_] += re * m.y + im * m.x;
+            tr[r_] = fmaf(re, m.x, tr[r_]);
+            tr[r_] = fmaf(-im, m.y, tr[r_]);
+            ti[r_] = fmaf(re, m.y, ti[r_]);
+            ti[r_] = fmaf(im, m.x, ti[r_]);
           }
         }
 #pragma unroll
@@ -311,6 +317,8 @@ static void launch_f32(qax_problem* p, const double* mu, int nrhs, double* parti
 hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
                            double* partial, bool accumulate) {
   const bool f64 = prec == QAX_FP64;
+  const int kind = f64 ? QAX_K_PAIRSUM_FP64 : QAX_K_PAIRSUM_FP32;
+  timing_begin(p, kind);
   if (f64) {
     if (nrhs == 1) launch_f64<256, 1>(p, mu, nrhs, partial);
     else if (nrhs <= 4) launch_f64<256, 4>(p, mu, nrhs, partial);
@@ -321,6 +329,7 @@ hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* o
     else if (nrhs <= 8) launch_f32<256, 8>(p, mu, nrhs, partial);
     else launch_f32<256, 16>(p, mu, nrhs, partial);
   }
+  timing_end(p, kind);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;

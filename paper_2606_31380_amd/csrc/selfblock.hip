@@ -32,6 +32,7 @@
 
 #include <vector>
 
+#include "fastmath.h"
 #include "internal.h"
 #include "shapes.h"
 
@@ -69,6 +70,7 @@ struct SelfShared {
   double2 twf[LM / 2];          // e^{-2 pi i k / LM}
   double2 tw2n[NTH_MAX];        // e^{i pi m / N}
   double lam[LD_MAX];           // L_0(2 pi l / L_d)
+  double2 cs_th[LD_MAX];        // (cos, sin)(2 pi l / L_d)
   double Pl[16];
   int modal_idx[64];
   union {
@@ -98,6 +100,14 @@ __device__ void agm_ke(double kmod, double kp, double& K, double& E) {
   E = K * (1.0 - s);
 }
 
+// 1/x for exact small integers x: hardware reciprocal + two Newton steps.
+__device__ __forceinline__ double recip(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+
 // Q[n][col] = Q_{n-1/2}(chi), n = 0..mq, for one node (one lane).
 __device__ void toroidal_q_lane(double chi, double chim1, int mq, double (*Q)[QB], int col) {
   const double mu = sqrt(2.0 / (chi + 1.0));
@@ -112,7 +122,7 @@ __device__ void toroidal_q_lane(double chi, double chim1, int mq, double (*Q)[QB
     Q[0][col] = q0;
     Q[1][col] = q1;
     for (int n = 1; n < mq; ++n) {
-      const double qp = (4.0 * n * chi * qn - (2.0 * n - 1.0) * qm) / (2.0 * n + 1.0);
+      const double qp = (4.0 * n * chi * qn - (2.0 * n - 1.0) * qm) * recip(2.0 * n + 1.0);
       Q[n + 1][col] = qp;
       qm = qn;
       qn = qp;
@@ -123,7 +133,7 @@ __device__ void toroidal_q_lane(double chi, double chim1, int mq, double (*Q)[QB
     double hi = 0.0, lo = 1e-200;
     for (int n = start; n >= 1; --n) {
       if (n <= mq) Q[n][col] = lo;
-      const double nw = (4.0 * n * chi * lo - (2.0 * n + 1.0) * hi) / (2.0 * n - 1.0);
+      const double nw = (4.0 * n * chi * lo - (2.0 * n + 1.0) * hi) * recip(2.0 * n - 1.0);
       hi = lo;
       lo = nw;
     }
@@ -172,23 +182,30 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Hs = (x cos x - sin x)/(4 pi rho^3), x = k rho; Taylor series
-// sum_{j>=1} (-1)^j 2j/(2j+1)! x^{2j+1} for x < 0.5.
+// Hs = (x cos x - sin x)/(4 pi rho^3), x = k rho; for x < 0.5 the Taylor
+// series sum_{j>=1} (-1)^j 2j/(2j+1)! x^{2j-2} (times k^3 / 4 pi).
 __device__ __forceinline__ double smooth_h(double k, double rho) {
   const double x = k * rho;
   if (x < 0.5) {
     const double x2 = x * x;
-    double term = 1.0, ser = 0.0, fact = 1.0;
-    for (int j = 1; j <= 12; ++j) {
-      fact *= (2.0 * j) * (2.0 * j + 1.0);
-      ser += ((j & 1) ? -1.0 : 1.0) * (2.0 * j) / fact * term;
-      term *= x2;
-    }
-    return k * k * k * INV_4PI * ser;
+    double p = 1.5472680682522736e-24;
+    p = fma(p, x2, -8.509974375387505e-22);
+    p = fma(p, x2, 3.9145882126782523e-19);
+    p = fma(p, x2, -1.4797143443923793e-16);
+    p = fma(p, x2, 4.498331606952833e-14);
+    p = fma(p, x2, -1.0706029224547743e-11);
+    p = fma(p, x2, 1.9270852604185937e-09);
+    p = fma(p, x2, -2.505210838544172e-07);
+    p = fma(p, x2, 2.2045855379188714e-05);
+    p = fma(p, x2, -0.0011904761904761906);
+    p = fma(p, x2, 0.03333333333333333);
+    p = fma(p, x2, -0.3333333333333333);
+    return k * k * k * INV_4PI * p;
   }
   double s, c;
-  sincos(x, &s, &c);
-  return (x * c - s) * INV_4PI / (rho * rho * rho);
+  sincos_cw(x, &s, &c);
+  const double ir = 1.0 / rho;
+  return (x * c - s) * INV_4PI * ir * ir * ir;
 }
 
 // phi-frame modes m = 0..nmax of A = dr G, B = dz G for one node (all lanes),
@@ -204,14 +221,16 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
     for (int h = 0; h < 2; ++h) {
       const int l = lane + 64 * h;
       const double phi = TWO_PI * l / LM;
-      const double sh = sin(0.5 * phi);
+      double sh, chh;
+      sincos_cw(0.5 * phi, &sh, &chh);
       const double rho = sqrt(2.0 * r * rt * (chim1 + 2.0 * sh * sh));
       double sk, ck;
-      sincos(k * rho, &sk, &ck);
+      sincos_cw(k * rho, &sk, &ck);
       const double F = ck + k * rho * sk;
       const double Hs = smooth_h(k, rho);
+      const double cphi = 1.0 - 2.0 * sh * sh;
       M.fa[l] = make_double2(F, Hs);
-      M.fb[l] = make_double2(Hs * (r - rt * cos(phi)), 0.0);
+      M.fb[l] = make_double2(Hs * (r - rt * cphi), 0.0);
     }
     __syncthreads();
     fft2_lm(M.fa, M.fb, twf);
@@ -233,14 +252,15 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
   // static modes n = 0..nmax+nf
   const int mtot = nmax + nf;
   const double pref = 1.0 / (TWO_PI * sqrt(rt * r));
-  const double chi2m1 = chim1 * (chi + 1.0);
-  const double drchi = (rmrt * (r + rt) - c * c) / (2.0 * rt * r * r);
-  const double dzchi = -c / (r * rt);
+  const double ir = 1.0 / r, irt = 1.0 / rt;
+  const double half_inv_chi2m1 = 0.5 / (chim1 * (chi + 1.0));
+  const double drchi = (rmrt * (r + rt) - c * c) * 0.5 * irt * ir * ir;
+  const double dzchi = -c * ir * irt;
   for (int n = lane; n <= mtot; n += 64) {
     const double qn = Q[n][col];
     const double qm = n == 0 ? Q[1][col] : Q[n - 1][col];
-    const double qp = (2.0 * n - 1.0) / (2.0 * chi2m1) * (chi * qn - qm);
-    M.A0[n] = pref * drchi * qp - pref * qn / (2.0 * r);
+    const double qp = (2.0 * n - 1.0) * half_inv_chi2m1 * (chi * qn - qm);
+    M.A0[n] = pref * (drchi * qp - 0.5 * ir * qn);
     M.B0[n] = pref * dzchi * qp;
   }
   __syncthreads();
@@ -260,8 +280,8 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
         ar += f * M.A0[idx];
         br += f * M.B0[idx];
       }
-      M.Am[lane] = make_double2(ar / TWO_PI, M.Hrh[lane]);
-      M.Bm[lane] = make_double2(br / TWO_PI, -c * M.Hh[lane]);
+      M.Am[lane] = make_double2(ar * (1.0 / TWO_PI), M.Hrh[lane]);
+      M.Bm[lane] = make_double2(br * (1.0 / TWO_PI), -c * M.Hh[lane]);
     }
   }
   __syncthreads();
@@ -273,10 +293,12 @@ __device__ double2 modes_to_gj(int N, const NodeLoc& L, ModalScratch& M, const d
   const double r = L.r;
   for (int idx = lane; idx <= 2 * N; idx += 64) {
     const int m = idx - N;
-    double s0, c0, s1, c1, s2, c2;
-    sincos(-m * L.alpha, &s0, &c0);
-    sincos(-(m - 1) * L.alpha, &s1, &c1);
-    sincos(-(m + 1) * L.alpha, &s2, &c2);
+    double s0, c0, sa, ca;
+    sincos_cw(-m * L.alpha, &s0, &c0);
+    sincos_cw(L.alpha, &sa, &ca);
+    // e^{-i(m-1) alpha} = e^{-i m alpha} e^{i alpha}, e^{-i(m+1) alpha} = e^{-i m alpha} e^{-i alpha}
+    const double c1 = c0 * ca - s0 * sa, s1 = s0 * ca + c0 * sa;
+    const double c2 = c0 * ca + s0 * sa, s2 = s0 * ca - c0 * sa;
     const double2 A = M.Am[abs(m)], B = M.Bm[abs(m)];
     const double2 Bm1 = M.Bm[abs(m - 1)], Bp1 = M.Bm[abs(m + 1)];
     // e^{-i m alpha} (r z' A - r r' B)
@@ -313,8 +335,9 @@ __device__ double2 modes_to_gj(int N, const NodeLoc& L, ModalScratch& M, const d
       g.x += wgt * (K.x * t.x - K.y * t.y);
       g.y += wgt * (K.x * t.y + K.y * t.x);
     }
-    g.x /= twoN;
-    g.y /= twoN;
+    const double inv2n = 1.0 / twoN;
+    g.x *= inv2n;
+    g.y *= inv2n;
   }
   __syncthreads();
   return g;
@@ -329,7 +352,7 @@ __device__ NodeLoc node_local(int shape, double a, double c, double kappa, doubl
   const Curve cs = curve_eval(shape, a, c, kappa, t + dl);
   const CurveDiff d = curve_diff(shape, a, c, kappa, t, dl);
   double sth, cth;
-  sincos(tht, &sth, &cth);
+  sincos_cw(tht, &sth, &cth);
   const double ax = ct.r * cth + d.d_p;
   const double by = ct.r * sth + d.d_q;
   L.rt = sqrt(ax * ax + by * by);
@@ -387,46 +410,21 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   const double thT = jT * PI / N;
   double2* row = pool + K.elem_off + (int64_t)T * n;
 
-  // tables
-  for (int q = lane; q < LM / 2; q += 64) {
-    double s, c;
-    sincos(-TWO_PI * q / LM, &s, &c);
-    S.twf[q] = make_double2(c, s);
-  }
-  for (int q = lane; q < 2 * N; q += 64) {
-    double s, c;
-    sincos(PI * q / N, &s, &c);
-    S.tw2n[q] = make_double2(c, s);
-  }
-  const int qr = (255 + 2 * N) / (2 * N);   // L_d = 2N * qr >= 256
-  const int Ld = 2 * N * qr;
-  for (int l = lane; l < Ld; l += 64) {
-    if (l == 0) {
-      S.lam[0] = 1.0;
-    } else {
-      const double sn = sin(TWO_PI * (double)((N * l) % Ld) / Ld);
-      double sh, ch;
-      sincos(PI * l / Ld, &sh, &ch);
-      S.lam[l] = sn * ch / sh / (2.0 * N);
-    }
-  }
-  __syncthreads();
-
   // target point (body frame)
   const Curve cT = curve_eval(shape, a, cc, kappa, tT);
   double sT, cTh;
-  sincos(thT, &sT, &cTh);
+  sincos_cw(thT, &sT, &cTh);
   const double xT = cT.r * cTh + cT.p, yT = cT.r * sT + cT.q, zT = cT.z;
 
   if (abs(ip - pT) > 1) {
-    // far panel: smooth rule
+    // far panel: smooth rule (Section 3.1, equation sx)
     for (int e = lane; e < GL_ORDER * nth; e += 64) {
       const int l = e / nth, j = e % nth;
       const double t = -0.5 * PI + h * ip + 0.5 * h * (gl16[l] + 1.0);
       const double om = 0.5 * h * gl16[GL_ORDER + l];
       const Curve cv = curve_eval(shape, a, cc, kappa, t);
       double sj, cj;
-      sincos(j * PI / N, &sj, &cj);
+      sincos_cw(j * PI / N, &sj, &cj);
       const double dx = cv.r * cj + cv.p - xT, dy = cv.r * sj + cv.q - yT, dz = cv.z - zT;
       const double nx = cv.r * cv.dz * cj, ny = cv.r * cv.dz * sj;
       const double nz = -cv.r * (cv.dr + cv.dp * cj + cv.dq * sj);
@@ -434,12 +432,41 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       const double ir = rsqrt(r2);
       const double rr = r2 * ir;
       double s, c;
-      sincos(k * rr, &s, &c);
+      sincos_cw(k * rr, &s, &c);
       const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI * om * PI / N;
       row[(int64_t)(ip * GL_ORDER + l) * nth + j] = make_double2(-(c + k * rr * s) * sc, (k * rr * c - s) * sc);
     }
     return;
   }
+
+  // tables
+  for (int q = lane; q < LM / 2; q += 64) {
+    double s, c;
+    sincos_cw(-TWO_PI * q / LM, &s, &c);
+    S.twf[q] = make_double2(c, s);
+  }
+  for (int q = lane; q < 2 * N; q += 64) {
+    double s, c;
+    sincos_cw(PI * q / N, &s, &c);
+    S.tw2n[q] = make_double2(c, s);
+  }
+  const int qr = (255 + 2 * N) / (2 * N);   // L_d = 2N * qr >= 256
+  const int Ld = 2 * N * qr;
+  for (int l = lane; l < Ld; l += 64) {
+    double sl, cl;
+    sincos_cw(TWO_PI * l / Ld, &sl, &cl);
+    S.cs_th[l] = make_double2(cl, sl);
+    if (l == 0) {
+      S.lam[0] = 1.0;
+    } else {
+      // L_0(theta) = sin(N theta) cot(theta / 2) / (2N)
+      double sn, cn, sh, ch;
+      sincos_cw(TWO_PI * (double)((N * l) % Ld) / Ld, &sn, &cn);
+      sincos_cw(PI * l / Ld, &sh, &ch);
+      S.lam[l] = sn * ch / (sh * 2.0 * N);
+    }
+  }
+  __syncthreads();
 
   double2 acc[GL_ORDER];
 #pragma unroll
@@ -447,23 +474,27 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   const double e0 = -0.5 * PI + h * ip, e1 = e0 + h;
   const int nsides = (ip == pT) ? 2 : 1;
   for (int side = 0; side < nsides; ++side) {
-    // outer node `lane`: offset dl from tT and weight
-    const double u = orule->x[lane], wu = orule->w[lane];
-    const double u4 = u * u * u * u;
+    // outer node `lane`: offset dl from tT and weight (u^5 substitution)
     double dl, w;
-    if (ip == pT) {
-      const double ell = (side == 0 ? e0 : e1) - tT;
-      dl = ell * u4 * u;
-      w = fabs(ell) * 5.0 * u4 * wu;
-    } else {
-      const double end = (ip < pT) ? e1 : e0;
-      const double far = (ip < pT) ? e0 : e1;
-      dl = (end - tT) + (far - end) * u4 * u;
-      w = fabs(far - end) * 5.0 * u4 * wu;
+    {
+      const double u = orule->x[lane], wu = orule->w[lane];
+      const double u4 = u * u * u * u;
+      if (ip == pT) {
+        const double ell = (side == 0 ? e0 : e1) - tT;
+        dl = ell * u4 * u;
+        w = fabs(ell) * 5.0 * u4 * wu;
+      } else {
+        const double end = (ip < pT) ? e1 : e0;
+        const double far = (ip < pT) ? e0 : e1;
+        dl = (end - tT) + (far - end) * u4 * u;
+        w = fabs(far - end) * 5.0 * u4 * wu;
+      }
     }
-    NodeLoc L = node_local(shape, a, cc, kappa, tT, thT, dl);
-    L.w = w;
-    const bool modal = L.chim1 < CHI_SPLIT;
+    bool modal;
+    {
+      const NodeLoc L = node_local(shape, a, cc, kappa, tT, thT, dl);
+      modal = L.chim1 < CHI_SPLIT;
+    }
     const unsigned long long mmask = __ballot(modal);
     const int nmodal = __popcll(mmask);
     {
@@ -471,61 +502,68 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       if (modal) S.modal_idx[__popcll(below)] = lane;
     }
     __syncthreads();
-    // ---- modal route, in batches of QB nodes
+    // ---- modal route, in batches of QB nodes (recurrences one node per lane)
     for (int b0 = 0; b0 < nmodal; b0 += QB) {
-      const int src = (lane < QB && b0 + lane < nmodal) ? S.modal_idx[b0 + lane] : 0;
-      const double chim1 = __shfl(L.chim1, src);
-      if (lane < QB && b0 + lane < nmodal)
-        toroidal_q_lane(1.0 + chim1, chim1, MQ_CAP, S.Q, lane);
+      const bool qlane = lane < QB && b0 + lane < nmodal;
+      const int src = qlane ? S.modal_idx[b0 + lane] : 0;
+      const double dls = __shfl(dl, src);
+      if (qlane) {
+        const NodeLoc L = node_local(shape, a, cc, kappa, tT, thT, dls);
+        toroidal_q_lane(1.0 + L.chim1, L.chim1, MQ_CAP, S.Q, lane);
+      }
       __syncthreads();
       const int cnt = min(QB, nmodal - b0);
       for (int q = 0; q < cnt; ++q) {
         const int sl = S.modal_idx[b0 + q];
-        const NodeLoc Ln = shfl_node(L, sl);
+        const double dlq = __shfl(dl, sl);
+        const double wq = __shfl(w, sl);
+        const NodeLoc Ln = node_local(shape, a, cc, kappa, tT, thT, dlq);
         modal_modes(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.twf);
         const double2 g = modes_to_gj(N, Ln, S.u.m, S.tw2n);
-        // P_l(s) on panel ip (product form), times the weight
         if (lane < GL_ORDER) {
+          // P_l(s) on panel ip (product form), times the weight
           const double xs = 2.0 * (Ln.s - e0) / h - 1.0;
           double pl = 1.0;
           for (int m2 = 0; m2 < GL_ORDER; ++m2)
             if (m2 != lane) pl *= (xs - gl16[m2]) / (gl16[lane] - gl16[m2]);
-          S.Pl[lane] = pl * Ln.w;
+          S.Pl[lane] = pl * wq;
         }
         __syncthreads();
 #pragma unroll
         for (int l = 0; l < GL_ORDER; ++l) {
-          acc[l].x += S.Pl[l] * g.x;
-          acc[l].y += S.Pl[l] * g.y;
+          acc[l].x = fma(S.Pl[l], g.x, acc[l].x);
+          acc[l].y = fma(S.Pl[l], g.y, acc[l].y);
         }
         __syncthreads();
       }
     }
-    // ---- direct route
+    // ---- direct route: trapezoidal rule on the kernel, folded with L_0
     const unsigned long long dmask = ~mmask;
     for (int q = 0; q < 64; ++q) {
       if (!((dmask >> q) & 1ull)) continue;
-      const NodeLoc Ln = shfl_node(L, q);
+      const double dlq = __shfl(dl, q);
+      const double wq = __shfl(w, q);
+      const double sq = tT + dlq;
+      const Curve cv = curve_eval(shape, a, cc, kappa, sq);
       for (int l = lane; l < Ld; l += 64) {
-        double sth, cth;
-        sincos(TWO_PI * l / Ld, &sth, &cth);
-        const double dx = Ln.r * cth + Ln.p - xT, dy = Ln.r * sth + Ln.q - yT, dz = Ln.z - zT;
-        const double nx = Ln.r * Ln.dz * cth, ny = Ln.r * Ln.dz * sth;
-        const double nz = -Ln.r * (Ln.dr + Ln.dp * cth + Ln.dq * sth);
+        const double2 cs = S.cs_th[l];
+        const double dx = cv.r * cs.x + cv.p - xT, dy = cv.r * cs.y + cv.q - yT, dz = cv.z - zT;
+        const double nx = cv.r * cv.dz * cs.x, ny = cv.r * cv.dz * cs.y;
+        const double nz = -cv.r * (cv.dr + cv.dp * cs.x + cv.dq * cs.y);
         const double r2 = dx * dx + dy * dy + dz * dz;
         const double ir = rsqrt(r2);
         const double rr = r2 * ir;
         double s, c;
-        sincos(k * rr, &s, &c);
+        sincos_cw(k * rr, &s, &c);
         const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI;
-        S.u.K[l] = make_double2(-(c + k * rr * s) * sc, (k * rr * c - s) * sc);
+        S.u.K[l] = make_double2(-fma(k * rr, s, c) * sc, fma(k * rr, c, -s) * sc);
       }
       if (lane < GL_ORDER) {
-        const double xs = 2.0 * (Ln.s - e0) / h - 1.0;
+        const double xs = 2.0 * (sq - e0) / h - 1.0;
         double pl = 1.0;
         for (int m2 = 0; m2 < GL_ORDER; ++m2)
           if (m2 != lane) pl *= (xs - gl16[m2]) / (gl16[lane] - gl16[m2]);
-        S.Pl[lane] = pl * Ln.w;
+        S.Pl[lane] = pl * wq;
       }
       __syncthreads();
       if (lane < 2 * N) {
@@ -534,8 +572,8 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         for (int l = 0; l < Ld; ++l) {
           const double lam = S.lam[idx];
           const double2 kv = S.u.K[l];
-          gr += kv.x * lam;
-          gi += kv.y * lam;
+          gr = fma(kv.x, lam, gr);
+          gi = fma(kv.y, lam, gi);
           idx = (idx + 1 == Ld) ? 0 : idx + 1;
         }
         const double f = TWO_PI / Ld;
@@ -543,17 +581,21 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         gi *= f;
 #pragma unroll
         for (int l = 0; l < GL_ORDER; ++l) {
-          acc[l].x += S.Pl[l] * gr;
-          acc[l].y += S.Pl[l] * gi;
+          acc[l].x = fma(S.Pl[l], gr, acc[l].x);
+          acc[l].y = fma(S.Pl[l], gi, acc[l].y);
         }
       }
       __syncthreads();
     }
   }
   if (lane < 2 * N) {
-    if (ip == pT && lane == jT) acc[lT].x += 0.5;
+    const bool diag = ip == pT && lane == jT;
 #pragma unroll
-    for (int l = 0; l < GL_ORDER; ++l) row[(int64_t)(ip * GL_ORDER + l) * nth + lane] = acc[l];
+    for (int l = 0; l < GL_ORDER; ++l) {
+      double2 v = acc[l];
+      if (diag && l == lT) v.x += 0.5;     // 1/2 I (compile-time index keeps acc in registers)
+      row[(int64_t)(ip * GL_ORDER + l) * nth + lane] = v;
+    }
   }
 }
 
@@ -585,8 +627,10 @@ hipError_t launch_assemble_self(qax_problem* p) {
   e = hipMemcpyAsync(d_tasks, tasks.data(), tasks.size() * sizeof(SelfTask), hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(d_rule, &R, sizeof(R), hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) {
+    timing_begin(p, QAX_K_SELF_ASSEMBLY);
     hipLaunchKernelGGL(assemble_self_kernel, dim3((unsigned)tasks.size()), dim3(64), 0, p->stream,
                        d_tasks, p->d_blocks, p->d_bodies, p->d_gl, d_rule, (double2*)p->d_B);
+    timing_end(p, QAX_K_SELF_ASSEMBLY);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
@@ -608,7 +652,7 @@ __global__ __launch_bounds__(64) void modal_modes_kernel(const double* __restric
   const int lane = threadIdx.x;
   for (int q = lane; q < LM / 2; q += 64) {
     double s, cc;
-    sincos(-TWO_PI * q / LM, &s, &cc);
+    sincos_cw(-TWO_PI * q / LM, &s, &cc);
     S.twf[q] = make_double2(cc, s);
   }
   if (lane == 0) toroidal_q_lane(1.0 + chim1[pt], chim1[pt], MQ_CAP, S.Q, 0);

@@ -10,6 +10,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "fastmath.h"
+
 namespace qax {
 
 struct Curve {
@@ -19,10 +21,9 @@ struct Curve {
 __device__ __forceinline__ Curve curve_eval(int shape, double a, double c, double kappa, double t) {
   Curve o;
   double st, ct;
-  sincos(t, &st, &ct);
+  sincos_cw(t, &st, &ct);
   if (shape == QAX_PEANUT) {
-    double s2, c2;
-    sincos(2.0 * t, &s2, &c2);
+    const double s2 = 2.0 * st * ct, c2 = 1.0 - 2.0 * st * st;
     const double rho = a * (1.0 - c * c2);
     const double drho = 2.0 * a * c * s2;
     o.r = rho * ct;
@@ -60,27 +61,33 @@ __device__ __forceinline__ CurveDiff curve_diff(int shape, double a, double c, d
   CurveDiff o;
   const double s = t + dl;
   const double sig = t + 0.5 * dl;
-  const double sh = sin(0.5 * dl);
+  double sh, chh;
+  sincos_cw(0.5 * dl, &sh, &chh);
   double ssig, csig;
-  sincos(sig, &ssig, &csig);
+  sincos_cw(sig, &ssig, &csig);
   double z_t, z_s;
   if (shape == QAX_PEANUT) {
-    const double rho_t = a * (1.0 - c * cos(2.0 * t));
-    const double rho_s = a * (1.0 - c * cos(2.0 * s));
-    const double d_rho = 2.0 * a * c * sin(2.0 * sig) * sin(dl);
-    double ss, cs;
-    sincos(s, &ss, &cs);
+    double st, ct, ss, cs;
+    sincos_cw(t, &st, &ct);
+    sincos_cw(s, &ss, &cs);
+    const double rho_t = a * (1.0 - c * (1.0 - 2.0 * st * st));
+    const double rho_s = a * (1.0 - c * (1.0 - 2.0 * ss * ss));
+    // rho(s) - rho(t) = 2 a c sin(2 sig) sin(dl), sin(dl) = 2 sin(dl/2) cos(dl/2)
+    const double d_rho = 2.0 * a * c * (2.0 * ssig * csig) * (2.0 * sh * chh);
     const double dcos = -2.0 * ssig * sh;   // cos s - cos t
     const double dsin = -2.0 * csig * sh;   // sin t - sin s
     o.d_r = d_rho * cs + rho_t * dcos;
     o.d_z = rho_t * dsin - d_rho * ss;
-    z_t = rho_t * sin(t);
+    z_t = rho_t * st;
     z_s = rho_s * ss;
   } else {
     o.d_r = -2.0 * a * ssig * sh;
     o.d_z = -2.0 * c * csig * sh;
-    z_t = c * sin(t);
-    z_s = c * sin(s);
+    double st, ct, ss, cs;
+    sincos_cw(t, &st, &ct);
+    sincos_cw(s, &ss, &cs);
+    z_t = c * st;
+    z_s = c * ss;
   }
   if (kappa != 0.0) {
     const double Rt = sqrt(1.0 - kappa * kappa * z_t * z_t);

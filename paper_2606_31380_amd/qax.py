@@ -42,7 +42,10 @@ class QaxError(RuntimeError):
 _LIB = None
 EXPORTS = ["qax_create", "qax_destroy", "qax_last_error", "qax_build", "qax_size", "qax_nodes",
            "qax_assemble_self", "qax_self_block", "qax_pair_sum", "qax_block_apply", "qax_apply",
-           "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes"]
+           "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes",
+           "qax_set_timing", "qax_timing"]
+QAX_K_PAIRSUM_FP64, QAX_K_PAIRSUM_FP32, QAX_K_BLOCK_APPLY, QAX_K_SELF_ASSEMBLY, QAX_K_INVERT = range(5)
+KERNEL_NAMES = ["pair_sum_fp64", "pair_sum_fp32", "block_apply", "self_assembly", "invert"]
 
 
 def lib():
@@ -52,6 +55,9 @@ def lib():
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2606_31380_amd.build`")
+    # torch first: its HIP runtime (same SONAME as the system one) is then the
+    # single runtime of the process, shared with the library's kernels.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     pd = C.POINTER(C.c_double)
@@ -72,6 +78,8 @@ def lib():
         "qax_solve_dense": (C.c_int, [vp, pd, i32, vp]),
         "qax_farfield": (C.c_int, [vp, vp, i32, pd, i32, vp]),
         "qax_modal_modes": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, d, i32, vp, vp]),
+        "qax_set_timing": (C.c_int, [vp, i32]),
+        "qax_timing": (C.c_int, [vp, i32, C.POINTER(i64), pd]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -193,6 +201,17 @@ def qax_farfield(h, mu, xhat, u_inf, nrhs=1):
 def qax_modal_modes(h, r, rt, c, chim1, rmrt, k, nmax, A, B):
     _check(h, lib().qax_modal_modes(h, int(r.shape[0]), _ptr(r), _ptr(rt), _ptr(c), _ptr(chim1),
                                     _ptr(rmrt), float(k), int(nmax), _ptr(A), _ptr(B)))
+
+
+def qax_set_timing(h, enable=True):
+    _check(h, lib().qax_set_timing(h, int(bool(enable))))
+
+
+def qax_timing(h, kernel):
+    n = C.c_int64()
+    ms = C.c_double()
+    _check(h, lib().qax_timing(h, int(kernel), C.byref(n), C.byref(ms)))
+    return n.value, ms.value
 
 
 class Problem:
