@@ -168,6 +168,9 @@ static void free_geometry(qax_problem* p) {
   p->d_pos = nullptr; p->d_aw = nullptr; p->d_loc32 = nullptr; p->d_aw32 = nullptr;
   p->d_gl = nullptr; p->d_B = nullptr; p->d_Binv = nullptr; p->d_Binv32 = nullptr;
   p->d_tasks64 = nullptr; p->d_tasks32 = nullptr;
+  if (p->d_gemm_tasks) (void)hipFree(p->d_gemm_tasks);
+  p->d_gemm_tasks = nullptr;
+  p->gemm_tasks.clear();
 }
 
 extern "C" void qax_destroy(qax_problem* p) {
@@ -314,9 +317,15 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
   QCHECK(hipMalloc(&p->d_aw, sizeof(double) * 3 * N), "alloc aw");
   QCHECK(hipMalloc(&p->d_loc32, sizeof(float) * 4 * N), "alloc loc32");
   QCHECK(hipMalloc(&p->d_aw32, sizeof(float) * 4 * N), "alloc aw32");
-  QCHECK(hipMalloc(&p->d_gl, sizeof(double) * 2 * GL_ORDER), "alloc gl");
-  double gl[2 * GL_ORDER];
+  QCHECK(hipMalloc(&p->d_gl, sizeof(double) * 3 * GL_ORDER), "alloc gl");
+  double gl[3 * GL_ORDER];   // nodes, weights, barycentric weights on [-1, 1]
   gauss_legendre_host(GL_ORDER, gl, gl + GL_ORDER);
+  for (int l = 0; l < GL_ORDER; ++l) {
+    double prod = 1.0;
+    for (int m = 0; m < GL_ORDER; ++m)
+      if (m != l) prod *= gl[l] - gl[m];
+    gl[2 * GL_ORDER + l] = 1.0 / prod;
+  }
   QCHECK(hipMemcpyAsync(p->d_gl, gl, sizeof(gl), hipMemcpyHostToDevice, p->stream), "copy gl");
   QCHECK(hipMemcpyAsync(p->d_bodies, p->hbodies.data(), sizeof(BodyDev) * n_bodies,
                         hipMemcpyHostToDevice, p->stream), "copy bodies");

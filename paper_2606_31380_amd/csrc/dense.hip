@@ -80,8 +80,18 @@ static void gemv_launch(qax_problem* p, const MT* pool, const double* v, double*
                      (double2*)out, acc ? 1 : 0);
 }
 
+hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double* v, double* out,
+                             int nrhs, bool accumulate);
+
 hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,
                               int nrhs, bool accumulate) {
+  if (nrhs >= 4) {
+    // several right-hand sides: batched complex GEMM on the matrix cores
+    timing_begin(p, QAX_K_BLOCK_APPLY);
+    hipError_t e = launch_block_gemm(p, inverse, prec, v, out, nrhs, accumulate);
+    timing_end(p, QAX_K_BLOCK_APPLY);
+    return e;
+  }
   timing_begin(p, QAX_K_BLOCK_APPLY);
   if (inverse && prec == QAX_MIXED) {
     if (nrhs == 1) gemv_launch<float, 1>(p, p->d_Binv32, v, out, nrhs, accumulate);
@@ -92,6 +102,142 @@ hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const doubl
     else gemv_launch<double, 4>(p, pool, v, out, nrhs, accumulate);
   }
   timing_end(p, QAX_K_BLOCK_APPLY);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- block apply, several RHS (MFMA)
+// Y_b = M_b V_b for every body with V, Y node-major (RHS fastest).  The
+// complex product is the real product A' B' with A' = M_b viewed as a real
+// n x 2n matrix (interleaved storage, read in place) and B' the 2n x 2nrhs
+// expansion of V: B'[2j] = (Re V_j0, Im V_j0, ...), B'[2j+1] = (-Im V_j0,
+// Re V_j0, ...), built while staging V in LDS.  64 x 64 real output tiles per
+// workgroup of 4 wavefronts (32 x 32 each = 2 x 2 MFMA 16x16 tiles), K steps
+// of 16 staged through LDS; MFMA 16x16x4 in FP64 (B) or FP32 (FP32 inverse).
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+  typedef __attribute__((__vector_size__(4 * sizeof(double)))) double v4;
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // D[i][j] of the 16 x 16 tile: lane j + 16 (i % 4), element i / 4
+  static __device__ __forceinline__ int row(int lane, int e) { return (lane >> 4) + 4 * e; }
+};
+template <>
+struct MfmaAcc<float> {
+  typedef __attribute__((__vector_size__(4 * sizeof(float)))) float v4;
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // D[i][j] of the 16 x 16 tile: lane j + 16 (i / 4), element i % 4
+  static __device__ __forceinline__ int row(int lane, int e) { return 4 * (lane >> 4) + e; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void block_gemm_kernel(
+    const GemmTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
+    const BlockDev* __restrict__ blocks, const T* __restrict__ pool,
+    const double* __restrict__ v, int nrhs, double* __restrict__ out, int accumulate) {
+  typedef typename MfmaAcc<T>::v4 v4;
+  const GemmTask task = tasks[blockIdx.x];
+  const BodyDev& Bd = bodies[task.body];
+  const BlockDev& K = blocks[Bd.block];
+  const int n = K.n;
+  const int ncol = 2 * nrhs;                  // real columns of V and Y
+  const int c0 = blockIdx.y * 64;
+  const int row0 = task.row0;
+  const T* A = pool + 2 * K.elem_off;         // real n x 2n, row stride 2n
+  const double* Vb = v + 2 * Bd.off * nrhs;   // real n x 2 nrhs
+  double* Yb = out + 2 * Bd.off * nrhs;
+  __shared__ T As[16][64 + 1];
+  __shared__ T Bs[16][64 + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  v4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[a][b][e] = 0;
+  for (int k0 = 0; k0 < 2 * n; k0 += 16) {
+    // A tile: rows row0..row0+63, real columns k0..k0+15
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e >> 4, kk = e & 15;
+      const int i = row0 + rr;
+      As[kk][rr] = (i < n) ? A[(int64_t)i * 2 * n + k0 + kk] : (T)0;
+    }
+    // B' tile: real rows k0..k0+15 (complex rows k0/2..k0/2+7), columns c0..c0+63
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int e = tid + 256 * q;             // 512 = 8 complex rows x 64 columns
+      const int jr = e >> 6, cc = e & 63;
+      const int c = c0 + cc;
+      const int j = k0 / 2 + jr;
+      T re = 0, alt = 0;
+      if (c < ncol) {
+        const double x = Vb[(int64_t)j * ncol + c];
+        const double y = Vb[(int64_t)j * ncol + (c ^ 1)];
+        re = (T)x;
+        alt = (c & 1) ? (T)y : (T)(-y);        // row 2j+1: (-Im, Re) pairs
+      }
+      Bs[2 * jr][cc] = re;
+      Bs[2 * jr + 1][cc] = alt;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4), ci = lane & 15;
+      T af[2], bf[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = As[kr][wr + 16 * a + ci];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bf[b] = Bs[kr][wc + 16 * b + ci];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = MfmaAcc<T>::mma(af[a], bf[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  // accumulator element e of the lane holds column lane % 16 of the tile
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = row0 + wr + 16 * a + MfmaAcc<T>::row(lane, e);
+        const int c = c0 + wc + 16 * b + (lane & 15);
+        if (i < n && c < ncol) {
+          double* y = Yb + (int64_t)i * ncol + c;
+          *y = (accumulate ? *y : 0.0) + (double)acc[a][b][e];
+        }
+      }
+}
+
+hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double* v, double* out,
+                             int nrhs, bool accumulate) {
+  if (p->gemm_tasks.empty()) {
+    for (int b = 0; b < p->n_bodies; ++b)
+      for (int r0 = 0; r0 < p->hbodies[b].n; r0 += 64) p->gemm_tasks.push_back(GemmTask{b, r0});
+    hipError_t e = hipMalloc(&p->d_gemm_tasks, p->gemm_tasks.size() * sizeof(GemmTask));
+    if (e != hipSuccess) return e;
+    e = hipMemcpy(p->d_gemm_tasks, p->gemm_tasks.data(), p->gemm_tasks.size() * sizeof(GemmTask),
+                  hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+  }
+  dim3 grid((unsigned)p->gemm_tasks.size(), (unsigned)((2 * nrhs + 63) / 64));
+  const GemmTask* t = (const GemmTask*)p->d_gemm_tasks;
+  if (inverse && prec == QAX_MIXED)
+    hipLaunchKernelGGL(block_gemm_kernel<float>, grid, dim3(256), 0, p->stream, t, p->d_bodies,
+                       p->d_blocks, p->d_Binv32, v, nrhs, out, accumulate ? 1 : 0);
+  else
+    hipLaunchKernelGGL(block_gemm_kernel<double>, grid, dim3(256), 0, p->stream, t, p->d_bodies,
+                       p->d_blocks, inverse ? p->d_Binv : p->d_B, v, nrhs, out, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -46,6 +46,12 @@ struct PairTask {
   double k;
 };
 
+// Row tile of the several-RHS block apply: 64 rows of one body from row0.
+struct GemmTask {
+  int32_t body;
+  int32_t row0;
+};
+
 // Work item of the self-block assembly: one target row x one near panel.
 struct SelfTask {
   int32_t block;   // distinct block
@@ -79,7 +85,7 @@ struct qax_problem {
   double* d_aw = nullptr;       // SoA
   float* d_loc32 = nullptr;     // float4 per node: local offset from the body centre, |y'|^2
   float* d_aw32 = nullptr;      // float4 per node: aw, aw . (local offset)
-  double* d_gl = nullptr;       // 16 GL nodes, 16 weights on [-1, 1]
+  double* d_gl = nullptr;       // 16 GL nodes, weights, barycentric weights on [-1, 1]
 
   // self blocks (complex128 / complex64 pools)
   double* d_B = nullptr;
@@ -92,6 +98,9 @@ struct qax_problem {
   qax::PairTask* d_tasks32 = nullptr;
   int32_t slots64 = 1, slots32 = 1;
 
+  // block GEMM row tiles (several right-hand sides)
+  std::vector<qax::GemmTask> gemm_tasks;
+  void* d_gemm_tasks = nullptr;
   // scratch
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;

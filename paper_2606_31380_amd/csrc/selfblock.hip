@@ -18,8 +18,9 @@
 //    and transformed by a radix-2 FFT in LDS, the convolution of F^ with the
 //    static modes, the shift to the theta frame, and the inverse DFT onto the
 //    trigonometric Lagrange basis;
-//  * direct route otherwise: trapezoidal rule on L_d >= 256 azimuths applied to
-//    the kernel itself, folded with L_0 (a circular convolution).
+//  * direct route otherwise: trapezoidal rule on 256 azimuths applied to the
+//    kernel itself, its modes |m| <= N by a 256-point FFT in LDS, and the same
+//    inverse DFT onto the Lagrange basis.
 // Outer integral: the paper's generalized Gaussian tables are not available;
 // this uses the substitution s - e = (s_end - e) u^5 with 64-point
 // Gauss-Legendre in u on each side of the target (self panel) and toward the
@@ -30,6 +31,7 @@
 // One wavefront (64 lanes) per (target row, panel) work item.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <vector>
 
 #include "fastmath.h"
@@ -43,7 +45,7 @@ constexpr int NF_CAP = 48;                    // largest convolution half-width
 constexpr int NTH_MAX = 64;                   // largest n_theta
 constexpr int MQ_CAP = NTH_MAX / 2 + 2 + NF_CAP;   // highest Q index kept (82)
 constexpr int QB = 16;                        // nodes per recurrence batch
-constexpr int LD_MAX = 320;                   // largest direct-route sample count
+constexpr int LD = 256;                       // direct-route azimuthal samples (FFT length)
 constexpr int NGO = 64;                       // outer Gauss-Legendre order
 constexpr double CHI_SPLIT = 0.02;
 constexpr double INV_4PI = 0.0795774715459476678844;
@@ -67,15 +69,14 @@ struct ModalScratch {
 
 struct SelfShared {
   double Q[MQ_CAP + 1][QB];
-  double2 twf[LM / 2];          // e^{-2 pi i k / LM}
+  double2 tw[LD / 2];           // e^{-2 pi i k / LD}, k < LD/2 (FFT twiddles, azimuth table)
   double2 tw2n[NTH_MAX];        // e^{i pi m / N}
-  double lam[LD_MAX];           // L_0(2 pi l / L_d)
-  double2 cs_th[LD_MAX];        // (cos, sin)(2 pi l / L_d)
   double Pl[16];
   int modal_idx[64];
+  double2 acc[GL_ORDER][64];    // Itilde_{l j}, lane j
   union {
     ModalScratch m;
-    double2 K[LD_MAX];
+    double2 K[LD];
   } u;
 };
 
@@ -144,35 +145,56 @@ __device__ void toroidal_q_lane(double chi, double chim1, int mq, double (*Q)[QB
 }
 
 // ---------------------------------------------------------------- FFT in LDS
-__device__ __forceinline__ int bitrev7(int x) { return (int)(__brev((unsigned)x) >> 25); }
+// Forward DFT X_k = sum_l x_l e^{-2 pi i k l / L} in place for L = 128 (two
+// arrays) and L = 256 (one array): radix-2 decimation in time after a
+// bit-reversal permutation; the 64 lanes share the L/2 butterflies of each
+// stage.  tw[q] = e^{-2 pi i q / LD}, q < LD/2.
+__device__ __forceinline__ void butterfly(double2* x, int i0, int i1, double2 w) {
+  const double2 u = x[i0], v = x[i1];
+  const double2 vw = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
+  x[i0] = make_double2(u.x + vw.x, u.y + vw.y);
+  x[i1] = make_double2(u.x - vw.x, u.y - vw.y);
+}
 
-// Forward DFT X_k = sum_l x_l e^{-2 pi i k l / LM} of fa and fb, in place,
-// radix-2 decimation in time, one butterfly per lane per stage.
-__device__ void fft2_lm(double2* fa, double2* fb, const double2* twf) {
+__device__ void fft128x2(double2* xa, double2* xb, const double2* tw) {
   const int lane = threadIdx.x;
-  // bit-reversal permutation
-  {
-    double2 a0 = fa[lane], a1 = fa[lane + 64], b0 = fb[lane], b1 = fb[lane + 64];
-    __syncthreads();
-    fa[bitrev7(lane)] = a0;
-    fa[bitrev7(lane + 64)] = a1;
-    fb[bitrev7(lane)] = b0;
-    fb[bitrev7(lane + 64)] = b1;
-    __syncthreads();
-  }
-  for (int half = 1; half < LM; half <<= 1) {
+  const int r0 = (int)(__brev((unsigned)lane) >> 25), r1 = (int)(__brev((unsigned)(lane + 64)) >> 25);
+  const double2 a0 = xa[r0], a1 = xa[r1], b0 = xb[r0], b1 = xb[r1];
+  __syncthreads();
+  xa[lane] = a0;
+  xa[lane + 64] = a1;
+  xb[lane] = b0;
+  xb[lane + 64] = b1;
+  __syncthreads();
+  for (int half = 1; half < 128; half <<= 1) {
     const int grp = lane / half, pos = lane % half;
     const int i0 = grp * 2 * half + pos, i1 = i0 + half;
-    const double2 w = twf[pos * (LM / 2 / half)];
-    double2 u = fa[i0], v = fa[i1];
-    double2 vw = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
-    fa[i0] = make_double2(u.x + vw.x, u.y + vw.y);
-    fa[i1] = make_double2(u.x - vw.x, u.y - vw.y);
-    u = fb[i0];
-    v = fb[i1];
-    vw = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
-    fb[i0] = make_double2(u.x + vw.x, u.y + vw.y);
-    fb[i1] = make_double2(u.x - vw.x, u.y - vw.y);
+    const double2 w = tw[pos * (LD / 2 / half)];
+    butterfly(xa, i0, i1, w);
+    butterfly(xb, i0, i1, w);
+    __syncthreads();
+  }
+}
+
+__device__ void fft256(double2* x, const double2* tw) {
+  const int lane = threadIdx.x;
+  double2 v0 = x[(int)(__brev((unsigned)lane) >> 24)];
+  double2 v1 = x[(int)(__brev((unsigned)(lane + 64)) >> 24)];
+  double2 v2 = x[(int)(__brev((unsigned)(lane + 128)) >> 24)];
+  double2 v3 = x[(int)(__brev((unsigned)(lane + 192)) >> 24)];
+  __syncthreads();
+  x[lane] = v0;
+  x[lane + 64] = v1;
+  x[lane + 128] = v2;
+  x[lane + 192] = v3;
+  __syncthreads();
+  for (int half = 1; half < 256; half <<= 1) {
+    for (int hh = 0; hh < 2; ++hh) {
+      const int bf = lane + 64 * hh;
+      const int grp = bf / half, pos = bf % half;
+      const int i0 = grp * 2 * half + pos, i1 = i0 + half;
+      butterfly(x, i0, i1, tw[pos * (LD / 2 / half)]);
+    }
     __syncthreads();
   }
 }
@@ -212,7 +234,7 @@ __device__ __forceinline__ double smooth_h(double k, double rho) {
 // given its Q column.  Results in M.Am, M.Bm.
 __device__ void modal_modes(double k, double r, double rt, double c, double chim1, double rmrt,
                             int nmax, const double (*Q)[QB], int col, ModalScratch& M,
-                            const double2* twf) {
+                            const double2* tw) {
   const int lane = threadIdx.x;
   const double chi = 1.0 + chim1;
   int nf = 0;
@@ -233,7 +255,7 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
       M.fb[l] = make_double2(Hs * (r - rt * cphi), 0.0);
     }
     __syncthreads();
-    fft2_lm(M.fa, M.fb, twf);
+    fft128x2(M.fa, M.fb, tw);
     const double sc = TWO_PI / LM;
     M.Fh[lane] = M.fa[lane].x * sc;
     if (lane < nmax + 1) {
@@ -287,6 +309,29 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
   __syncthreads();
 }
 
+// G_j = (1/2N) sum'_{|m|<=N} Km[m + N] e^{i m theta_j} in lane j < 2N (+-N halved).
+__device__ __forceinline__ double2 inverse_dft_2n(int N, const double2* Km, const double2* tw2n) {
+  const int lane = threadIdx.x;
+  double2 g = make_double2(0.0, 0.0);
+  if (lane < 2 * N) {
+    const int twoN = 2 * N;
+    int e = ((-N * lane) % twoN + twoN) % twoN;   // (m * lane) mod 2N at m = -N
+    for (int idx = 0; idx <= twoN; ++idx) {
+      const double wgt = (idx == 0 || idx == twoN) ? 0.5 : 1.0;
+      const double2 t = tw2n[e];
+      const double2 K = Km[idx];
+      g.x = fma(wgt, K.x * t.x - K.y * t.y, g.x);
+      g.y = fma(wgt, K.x * t.y + K.y * t.x, g.y);
+      e += lane;
+      if (e >= twoN) e -= twoN;
+    }
+    const double inv2n = 1.0 / twoN;
+    g.x *= inv2n;
+    g.y *= inv2n;
+  }
+  return g;
+}
+
 // G_j (returned in lane j < 2N) from the phi-frame modes of one node.
 __device__ double2 modes_to_gj(int N, const NodeLoc& L, ModalScratch& M, const double2* tw2n) {
   const int lane = threadIdx.x;
@@ -323,22 +368,7 @@ __device__ double2 modes_to_gj(int N, const NodeLoc& L, ModalScratch& M, const d
     M.Km[idx] = make_double2(kr, ki);
   }
   __syncthreads();
-  double2 g = make_double2(0.0, 0.0);
-  if (lane < 2 * N) {
-    const int twoN = 2 * N;
-    for (int idx = 0; idx <= twoN; ++idx) {
-      const int m = idx - N;
-      const double wgt = (idx == 0 || idx == twoN) ? 0.5 : 1.0;
-      const int e = ((m * lane) % twoN + twoN) % twoN;
-      const double2 t = tw2n[e];
-      const double2 K = M.Km[idx];
-      g.x += wgt * (K.x * t.x - K.y * t.y);
-      g.y += wgt * (K.x * t.y + K.y * t.x);
-    }
-    const double inv2n = 1.0 / twoN;
-    g.x *= inv2n;
-    g.y *= inv2n;
-  }
+  const double2 g = inverse_dft_2n(N, M.Km, tw2n);
   __syncthreads();
   return g;
 }
@@ -385,6 +415,16 @@ __device__ __forceinline__ NodeLoc shfl_node(const NodeLoc& v, int src) {
 }
 
 // ---------------------------------------------------------------- assembly kernel
+// Lagrange basis polynomial P_l(x) on the 16 Gauss-Legendre nodes of [-1, 1]
+// (gl[0..15]) with barycentric weights gl[32 + l] = 1 / prod_{m != l}(x_l - x_m).
+__device__ __forceinline__ double lagrange_gl(const double* __restrict__ gl, double x, int l) {
+  double p = gl[32 + l];
+#pragma unroll
+  for (int m = 0; m < GL_ORDER; ++m)
+    if (m != l) p *= (x - gl[m]);
+  return p;
+}
+
 struct OuterRule {
   double x[NGO];
   double w[NGO];
@@ -439,38 +479,21 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     return;
   }
 
-  // tables
-  for (int q = lane; q < LM / 2; q += 64) {
+  // tables: FFT twiddles (also the azimuth samples) and e^{i pi m / N}
+  for (int q = lane; q < LD / 2; q += 64) {
     double s, c;
-    sincos_cw(-TWO_PI * q / LM, &s, &c);
-    S.twf[q] = make_double2(c, s);
+    sincos_cw(-TWO_PI * q / LD, &s, &c);
+    S.tw[q] = make_double2(c, s);
   }
   for (int q = lane; q < 2 * N; q += 64) {
     double s, c;
     sincos_cw(PI * q / N, &s, &c);
     S.tw2n[q] = make_double2(c, s);
   }
-  const int qr = (255 + 2 * N) / (2 * N);   // L_d = 2N * qr >= 256
-  const int Ld = 2 * N * qr;
-  for (int l = lane; l < Ld; l += 64) {
-    double sl, cl;
-    sincos_cw(TWO_PI * l / Ld, &sl, &cl);
-    S.cs_th[l] = make_double2(cl, sl);
-    if (l == 0) {
-      S.lam[0] = 1.0;
-    } else {
-      // L_0(theta) = sin(N theta) cot(theta / 2) / (2N)
-      double sn, cn, sh, ch;
-      sincos_cw(TWO_PI * (double)((N * l) % Ld) / Ld, &sn, &cn);
-      sincos_cw(PI * l / Ld, &sh, &ch);
-      S.lam[l] = sn * ch / (sh * 2.0 * N);
-    }
-  }
   __syncthreads();
 
-  double2 acc[GL_ORDER];
 #pragma unroll
-  for (int l = 0; l < GL_ORDER; ++l) acc[l] = make_double2(0.0, 0.0);
+  for (int l = 0; l < GL_ORDER; ++l) S.acc[l][lane] = make_double2(0.0, 0.0);
   const double e0 = -0.5 * PI + h * ip, e1 = e0 + h;
   const int nsides = (ip == pT) ? 2 : 1;
   for (int side = 0; side < nsides; ++side) {
@@ -518,26 +541,21 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         const double dlq = __shfl(dl, sl);
         const double wq = __shfl(w, sl);
         const NodeLoc Ln = node_local(shape, a, cc, kappa, tT, thT, dlq);
-        modal_modes(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.twf);
+        modal_modes(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.tw);
         const double2 g = modes_to_gj(N, Ln, S.u.m, S.tw2n);
-        if (lane < GL_ORDER) {
-          // P_l(s) on panel ip (product form), times the weight
-          const double xs = 2.0 * (Ln.s - e0) / h - 1.0;
-          double pl = 1.0;
-          for (int m2 = 0; m2 < GL_ORDER; ++m2)
-            if (m2 != lane) pl *= (xs - gl16[m2]) / (gl16[lane] - gl16[m2]);
-          S.Pl[lane] = pl * wq;
-        }
+        if (lane < GL_ORDER) S.Pl[lane] = lagrange_gl(gl16, 2.0 * (Ln.s - e0) / h - 1.0, lane) * wq;
         __syncthreads();
-#pragma unroll
         for (int l = 0; l < GL_ORDER; ++l) {
-          acc[l].x = fma(S.Pl[l], g.x, acc[l].x);
-          acc[l].y = fma(S.Pl[l], g.y, acc[l].y);
+          double2 v = S.acc[l][lane];
+          v.x = fma(S.Pl[l], g.x, v.x);
+          v.y = fma(S.Pl[l], g.y, v.y);
+          S.acc[l][lane] = v;
         }
         __syncthreads();
       }
     }
-    // ---- direct route: trapezoidal rule on the kernel, folded with L_0
+    // ---- direct route: trapezoidal rule on LD azimuths of the kernel itself,
+    // its modes by FFT, then the inverse DFT onto the Lagrange basis
     const unsigned long long dmask = ~mmask;
     for (int q = 0; q < 64; ++q) {
       if (!((dmask >> q) & 1ull)) continue;
@@ -545,11 +563,16 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       const double wq = __shfl(w, q);
       const double sq = tT + dlq;
       const Curve cv = curve_eval(shape, a, cc, kappa, sq);
-      for (int l = lane; l < Ld; l += 64) {
-        const double2 cs = S.cs_th[l];
-        const double dx = cv.r * cs.x + cv.p - xT, dy = cv.r * cs.y + cv.q - yT, dz = cv.z - zT;
-        const double nx = cv.r * cv.dz * cs.x, ny = cv.r * cv.dz * cs.y;
-        const double nz = -cv.r * (cv.dr + cv.dp * cs.x + cv.dq * cs.y);
+#pragma unroll
+      for (int hh = 0; hh < LD / 64; ++hh) {
+        const int l = lane + 64 * hh;
+        // (cos, sin)(2 pi l / LD) from the twiddle table
+        const double2 t = S.tw[l & (LD / 2 - 1)];
+        const double sg = (l < LD / 2) ? 1.0 : -1.0;
+        const double cth = sg * t.x, sth = -sg * t.y;
+        const double dx = cv.r * cth + cv.p - xT, dy = cv.r * sth + cv.q - yT, dz = cv.z - zT;
+        const double nx = cv.r * cv.dz * cth, ny = cv.r * cv.dz * sth;
+        const double nz = -cv.r * (cv.dr + cv.dp * cth + cv.dq * sth);
         const double r2 = dx * dx + dy * dy + dz * dz;
         const double ir = rsqrt(r2);
         const double rr = r2 * ir;
@@ -558,42 +581,39 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI;
         S.u.K[l] = make_double2(-fma(k * rr, s, c) * sc, fma(k * rr, c, -s) * sc);
       }
-      if (lane < GL_ORDER) {
-        const double xs = 2.0 * (sq - e0) / h - 1.0;
-        double pl = 1.0;
-        for (int m2 = 0; m2 < GL_ORDER; ++m2)
-          if (m2 != lane) pl *= (xs - gl16[m2]) / (gl16[lane] - gl16[m2]);
-        S.Pl[lane] = pl * wq;
+      if (lane < GL_ORDER) S.Pl[lane] = lagrange_gl(gl16, 2.0 * (sq - e0) / h - 1.0, lane) * wq;
+      __syncthreads();
+      fft256(S.u.K, S.tw);
+      // modes K_m = (2 pi / LD) X[m mod LD], m = -N..N, gathered into Km order
+      double2 km0 = make_double2(0.0, 0.0), km1 = km0;
+      const double f = TWO_PI / LD;
+      if (lane <= 2 * N) {
+        const double2 v = S.u.K[(lane - N + LD) % LD];
+        km0 = make_double2(v.x * f, v.y * f);
+      }
+      if (lane + 64 <= 2 * N) {
+        const double2 v = S.u.K[(lane + 64 - N + LD) % LD];
+        km1 = make_double2(v.x * f, v.y * f);
       }
       __syncthreads();
-      if (lane < 2 * N) {
-        double gr = 0.0, gi = 0.0;
-        int idx = (Ld - qr * lane) % Ld;
-        for (int l = 0; l < Ld; ++l) {
-          const double lam = S.lam[idx];
-          const double2 kv = S.u.K[l];
-          gr = fma(kv.x, lam, gr);
-          gi = fma(kv.y, lam, gi);
-          idx = (idx + 1 == Ld) ? 0 : idx + 1;
-        }
-        const double f = TWO_PI / Ld;
-        gr *= f;
-        gi *= f;
-#pragma unroll
-        for (int l = 0; l < GL_ORDER; ++l) {
-          acc[l].x = fma(S.Pl[l], gr, acc[l].x);
-          acc[l].y = fma(S.Pl[l], gi, acc[l].y);
-        }
+      if (lane <= 2 * N) S.u.K[lane] = km0;
+      if (lane + 64 <= 2 * N) S.u.K[lane + 64] = km1;
+      __syncthreads();
+      const double2 g = inverse_dft_2n(N, S.u.K, S.tw2n);
+      for (int l = 0; l < GL_ORDER; ++l) {
+        double2 v = S.acc[l][lane];
+        v.x = fma(S.Pl[l], g.x, v.x);
+        v.y = fma(S.Pl[l], g.y, v.y);
+        S.acc[l][lane] = v;
       }
       __syncthreads();
     }
   }
   if (lane < 2 * N) {
     const bool diag = ip == pT && lane == jT;
-#pragma unroll
     for (int l = 0; l < GL_ORDER; ++l) {
-      double2 v = acc[l];
-      if (diag && l == lT) v.x += 0.5;     // 1/2 I (compile-time index keeps acc in registers)
+      double2 v = S.acc[l][lane];
+      if (diag && l == lT) v.x += 0.5;     // 1/2 I
       row[(int64_t)(ip * GL_ORDER + l) * nth + lane] = v;
     }
   }
@@ -650,14 +670,14 @@ __global__ __launch_bounds__(64) void modal_modes_kernel(const double* __restric
   __shared__ SelfShared S;
   const int pt = blockIdx.x;
   const int lane = threadIdx.x;
-  for (int q = lane; q < LM / 2; q += 64) {
+  for (int q = lane; q < LD / 2; q += 64) {
     double s, cc;
-    sincos_cw(-TWO_PI * q / LM, &s, &cc);
-    S.twf[q] = make_double2(cc, s);
+    sincos_cw(-TWO_PI * q / LD, &s, &cc);
+    S.tw[q] = make_double2(cc, s);
   }
   if (lane == 0) toroidal_q_lane(1.0 + chim1[pt], chim1[pt], MQ_CAP, S.Q, 0);
   __syncthreads();
-  modal_modes(k, r[pt], rt[pt], c[pt], chim1[pt], rmrt[pt], nmax, S.Q, 0, S.u.m, S.twf);
+  modal_modes(k, r[pt], rt[pt], c[pt], chim1[pt], rmrt[pt], nmax, S.Q, 0, S.u.m, S.tw);
   if (lane <= nmax) {
     A[(int64_t)pt * (nmax + 1) + lane] = S.u.m.Am[lane];
     B[(int64_t)pt * (nmax + 1) + lane] = S.u.m.Bm[lane];
