@@ -289,8 +289,11 @@ __global__ void gj_unpivot_kernel(const MatDesc* __restrict__ mats, double2* __r
 // row interchanges at the end.
 constexpr int GJB = 64;
 
+// Unblocked elimination with partial pivoting on the columns [k0, k0 + wcols)
+// only (pivot rows >= k); row interchanges are applied to these columns only.
 __global__ __launch_bounds__(1024) void gjb_panel_kernel(const MatDesc* __restrict__ mats,
                                                          double2* __restrict__ pool, int k0,
+                                                         int wcols,
                                                          int32_t* __restrict__ piv,
                                                          double2* __restrict__ colbuf,
                                                          int64_t col_stride, int nmax) {
@@ -299,7 +302,7 @@ __global__ __launch_bounds__(1024) void gjb_panel_kernel(const MatDesc* __restri
   if (k0 >= n) return;
   double2* A = pool + M.elem_off;
   double2* col = colbuf + (int64_t)blockIdx.x * col_stride;
-  const int kend = min(k0 + GJB, n);
+  const int kend = min(k0 + wcols, n);
   const int w = kend - k0;
   const int tid = threadIdx.x;
   __shared__ double best[1024];
@@ -362,6 +365,65 @@ __global__ __launch_bounds__(1024) void gjb_panel_kernel(const MatDesc* __restri
     }
     __syncthreads();
   }
+}
+
+// Recursive panel factorization helpers: the row operations of the columns
+// [s0, s0 + ws) (already eliminated) applied to the sibling columns
+// [d0, d0 + wd): (1) their row interchanges, then the pivot rows copied to W;
+// (2) A[i][d0+j] = (i in [s0, s0+ws) ? 0 : A[i][d0+j]) + sum_p A[i][s0+p] W[p][j].
+__global__ void gjn_swap_copy_kernel(const MatDesc* __restrict__ mats, double2* __restrict__ pool,
+                                     int s0, int ws, int d0, int wd,
+                                     const int32_t* __restrict__ piv, int nmax,
+                                     double2* __restrict__ W) {
+  const MatDesc M = mats[blockIdx.x];
+  const int n = M.n;
+  const int j = d0 + threadIdx.x;
+  if (s0 >= n || threadIdx.x >= wd || j >= n) return;
+  double2* A = pool + M.elem_off;
+  double2* Wm = W + (int64_t)blockIdx.x * GJB * GJB;
+  const int send = min(s0 + ws, n);
+  const int32_t* pv = piv + (int64_t)blockIdx.x * nmax;
+  for (int k = s0; k < send; ++k) {
+    const int pr = pv[k];
+    if (pr != k) {
+      const double2 t = A[(int64_t)k * n + j];
+      A[(int64_t)k * n + j] = A[(int64_t)pr * n + j];
+      A[(int64_t)pr * n + j] = t;
+    }
+  }
+  for (int k = s0; k < send; ++k) Wm[(k - s0) * GJB + threadIdx.x] = A[(int64_t)k * n + j];
+}
+
+__global__ __launch_bounds__(256) void gjn_update_kernel(const MatDesc* __restrict__ mats,
+                                                         double2* __restrict__ pool, int s0,
+                                                         int ws, int d0, int wd,
+                                                         const double2* __restrict__ W) {
+  const MatDesc M = mats[blockIdx.y];
+  const int n = M.n;
+  if (s0 >= n) return;
+  const int send = min(s0 + ws, n);
+  const int wsv = send - s0;
+  const int wdv = min(d0 + wd, n) - d0;
+  __shared__ double2 Ws[GJB / 2][GJB / 2];
+  const double2* Wm = W + (int64_t)blockIdx.y * GJB * GJB;
+  for (int e = threadIdx.x; e < wsv * wdv; e += 256) Ws[e / wdv][e % wdv] = Wm[(e / wdv) * GJB + e % wdv];
+  __syncthreads();
+  const int rows = 256 / wd;
+  const int i = blockIdx.x * rows + threadIdx.x / wd;
+  const int j = threadIdx.x % wd;
+  if (i >= n || j >= wdv) return;
+  double2* A = pool + M.elem_off;
+  const double2* ar = A + (int64_t)i * n + s0;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int p = 0; p < wsv; ++p) {
+    const double2 a = ar[p], w = Ws[p][j];
+    acc.x = fma(a.x, w.x, fma(-a.y, w.y, acc.x));
+    acc.y = fma(a.x, w.y, fma(a.y, w.x, acc.y));
+  }
+  double2* cptr = A + (int64_t)i * n + d0 + j;
+  const bool prow = i >= s0 && i < send;
+  const double2 base = prow ? make_double2(0.0, 0.0) : *cptr;
+  *cptr = make_double2(base.x + acc.x, base.y + acc.y);
 }
 
 // Row interchanges of the panel applied to the other columns, then the panel
@@ -458,6 +520,32 @@ __global__ __launch_bounds__(256) void gjb_update_kernel(const MatDesc* __restri
   }
 }
 
+constexpr int GJ_LEAF = 8;
+
+// Factor the panel columns [c0, c0 + w) (w a power of two, <= GJB) by halves:
+// left half, its row operations on the right half, right half, its row
+// operations on the left half; leaves of GJ_LEAF columns run unblocked.
+static void gj_factor_panel(hipStream_t s, double2* pool, const MatDesc* d_mats, int batch, int nmax,
+                            int c0, int w, int32_t* piv, double2* colbuf, double2* Wn) {
+  if (w <= GJ_LEAF) {
+    hipLaunchKernelGGL(gjb_panel_kernel, dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv,
+                       colbuf, (int64_t)nmax, nmax);
+    return;
+  }
+  const int h = w / 2;
+  const unsigned rows_blocks = (unsigned)((nmax + (256 / h) - 1) / (256 / h));
+  gj_factor_panel(s, pool, d_mats, batch, nmax, c0, h, piv, colbuf, Wn);
+  hipLaunchKernelGGL(gjn_swap_copy_kernel, dim3(batch), dim3(h), 0, s, d_mats, pool, c0, h, c0 + h,
+                     h, piv, nmax, Wn);
+  hipLaunchKernelGGL(gjn_update_kernel, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool, c0,
+                     h, c0 + h, h, Wn);
+  gj_factor_panel(s, pool, d_mats, batch, nmax, c0 + h, h, piv, colbuf, Wn);
+  hipLaunchKernelGGL(gjn_swap_copy_kernel, dim3(batch), dim3(h), 0, s, d_mats, pool, c0 + h, h, c0,
+                     h, piv, nmax, Wn);
+  hipLaunchKernelGGL(gjn_update_kernel, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool,
+                     c0 + h, h, c0, h, Wn);
+}
+
 // In-place inversion of `batch` matrices described on the device by `mats`
 // (orders up to nmax).  work: see gj_work_bytes.
 hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int batch, int nmax,
@@ -465,10 +553,10 @@ hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int bat
   double2* colbuf = (double2*)work;
   double2* W = colbuf + (int64_t)nmax * batch;
   int32_t* piv = (int32_t*)(W + (int64_t)GJB * nmax * batch);
+  double2* Wn = (double2*)(piv + (int64_t)nmax * batch + 64);
   const unsigned tiles = (unsigned)((nmax + 63) / 64);
   for (int k0 = 0; k0 < nmax; k0 += GJB) {
-    hipLaunchKernelGGL(gjb_panel_kernel, dim3(batch), dim3(1024), 0, s, d_mats, (double2*)pool, k0,
-                       piv, colbuf, (int64_t)nmax, nmax);
+    gj_factor_panel(s, (double2*)pool, d_mats, batch, nmax, k0, GJB, piv, colbuf, Wn);
     hipLaunchKernelGGL(gjb_swap_copy_kernel, dim3((nmax + 255) / 256, batch), dim3(256), 0, s,
                        d_mats, (double2*)pool, k0, piv, nmax, W);
     hipLaunchKernelGGL(gjb_update_kernel, dim3(tiles, tiles, batch), dim3(256), 0, s, d_mats,
@@ -480,7 +568,8 @@ hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int bat
 }
 
 size_t gj_work_bytes(int batch, int nmax) {
-  return (size_t)nmax * batch * (sizeof(double2) * (1 + GJB) + sizeof(int32_t)) + 256;
+  return (size_t)nmax * batch * (sizeof(double2) * (1 + GJB) + sizeof(int32_t)) + 256 + 64 * 4 +
+         (size_t)batch * GJB * GJB * sizeof(double2) + 256;
 }
 
 // Invert every distinct self block: copy B into Binv, invert in place, make
