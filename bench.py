@@ -156,14 +156,15 @@ def main():
     nb = scen.nodes_per_body().astype(np.float64)
     nth = scen.bodies["n_theta"].astype(np.float64)
     npan = scen.bodies["n_panels"].astype(np.float64)
-    # self-block assembly: per (target row, outer node) an azimuthal integral
-    # against 2N Lagrange functions: 256 kernel samples (35 flop each), a
-    # 256-point FFT (5 L log2 L), the (2N+1) -> 2N inverse DFT (8 flop per
-    # term) and the 16 x 2N contraction (8 flop per term); outer nodes per row:
-    # 128 on the own panel + 64 per adjacent panel
-    per_node = 35 * 256 + 5 * 256 * 8 + 8 * (nth + 1) * nth + 8 * 16 * nth
+    # self-block assembly: per (target row, outer node) the azimuthal modes of
+    # the kernel at the minimal grid (L = 128 samples at 35 flop, a 128-point
+    # FFT at 5 L log2 L) and the 16 x 2N weighted accumulation (8 flop per
+    # term); per (row, panel) one 2N x 2N inverse DFT for 16 functions; outer
+    # nodes per row: 128 on the own panel + 64 per adjacent panel
+    per_node = 35 * 128 + 5 * 128 * 7 + 8 * 16 * nth
+    per_item = 8 * 16 * nth * nth
     adj = np.where(npan > 1, np.where(npan > 2, 2.0 - 2.0 / npan, 1.0), 0.0)
-    self_flop = float(np.sum(nb * (128 + 64 * adj) * per_node))
+    self_flop = float(np.sum(nb * ((128 + 64 * adj) * per_node + (1 + adj) * per_item)))
     inv_flop = float(np.sum(8.0 * nb ** 3))
     work = {"pair_sum_fp32": ("alu", FLOP_PER_PAIR * P, PEAK["fp32"], "TFLOP/s"),
             "pair_sum_fp64": ("alu", FLOP_PER_PAIR * P, PEAK["fp64"], "TFLOP/s"),

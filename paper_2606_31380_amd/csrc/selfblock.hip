@@ -8,19 +8,24 @@
 //     dependence through p', q' becomes the mode shifts m -/+ 1)
 //   far panel i:  K(x, y_ilj) (pi/N) omega_il   (Section 3.1, equation sx).
 //
-// Inner integral G_j, two routes:
+// Inner integral G_j, two routes, both producing the theta-frame modes K_m,
+// |m| <= N, of the kernel on the source slice:
 //  * modal route (Section 3.3) when chi - 1 < CHI_SPLIT: toroidal Legendre
 //    functions Q_{m-1/2}(chi) by the recurrence leg_recur (forward where it is
 //    stable, Miller's backward recurrence normalised by Q_{-1/2} = mu K(mu)
 //    otherwise; K and E by the arithmetic-geometric mean), Q' by dleg_recur,
 //    static derivative modes, the smooth factors F = cos k rho + k rho sin k rho
 //    and Hs = (k rho cos k rho - sin k rho)/(4 pi rho^3) sampled on 128 azimuths
-//    and transformed by a radix-2 FFT in LDS, the convolution of F^ with the
-//    static modes, the shift to the theta frame, and the inverse DFT onto the
-//    trigonometric Lagrange basis;
-//  * direct route otherwise: trapezoidal rule on 256 azimuths applied to the
-//    kernel itself, its modes |m| <= N by a 256-point FFT in LDS, and the same
-//    inverse DFT onto the Lagrange basis.
+//    and transformed by FFT in LDS, the convolution of F^ with the static modes
+//    and the shift to the theta frame;
+//  * direct route otherwise: trapezoidal rule on L = 128 or 256 azimuths
+//    (chosen from the decay rate acosh(chi) of the modes so that aliasing stays
+//    below rounding) applied to the kernel itself, its modes by FFT in LDS.
+// The map from modes to the Lagrange basis (inverse DFT, G_j = (1/2N) sum'_m
+// K_m e^{i m theta_j}, +-N halved) is linear, so the outer sum
+// sum_q w_q P_l(s_q) K_m(s_q) is accumulated in registers (lane = mode) and the
+// inverse DFT is applied once per work item.  FFTs are radix-4 Stockham
+// (self-sorting) passes with a final radix-2 pass where L = 128.
 // Outer integral: the paper's generalized Gaussian tables are not available;
 // this uses the substitution s - e = (s_end - e) u^5 with 64-point
 // Gauss-Legendre in u on each side of the target (self panel) and toward the
@@ -60,20 +65,17 @@ struct ModalScratch {
   double Fh[LM / 2];
   double Hrh[NTH_MAX / 2 + 2];
   double Hh[NTH_MAX / 2 + 2];
-  double A0[MQ_CAP + 1];
-  double B0[MQ_CAP + 1];
+  double2 AB0[MQ_CAP + 1];      // static modes (dr, dz) of the kernel, n = 0..nmax+nf
   double2 Am[NTH_MAX / 2 + 2];
   double2 Bm[NTH_MAX / 2 + 2];
-  double2 Km[NTH_MAX + 1];
 };
 
 struct SelfShared {
   double Q[MQ_CAP + 1][QB];
-  double2 tw[LD / 2];           // e^{-2 pi i k / LD}, k < LD/2 (FFT twiddles, azimuth table)
+  double2 tw[LD];               // e^{-2 pi i q / LD} (FFT twiddles, azimuth table)
   double2 tw2n[NTH_MAX];        // e^{i pi m / N}
-  double Pl[16];
   int modal_idx[64];
-  double2 acc[GL_ORDER][64];    // Itilde_{l j}, lane j
+  double2 acc[GL_ORDER][64];    // accumulated modes (final inverse DFT)
   union {
     ModalScratch m;
     double2 K[LD];
@@ -145,58 +147,94 @@ __device__ void toroidal_q_lane(double chi, double chim1, int mq, double (*Q)[QB
 }
 
 // ---------------------------------------------------------------- FFT in LDS
-// Forward DFT X_k = sum_l x_l e^{-2 pi i k l / L} in place for L = 128 (two
-// arrays) and L = 256 (one array): radix-2 decimation in time after a
-// bit-reversal permutation; the 64 lanes share the L/2 butterflies of each
-// stage.  tw[q] = e^{-2 pi i q / LD}, q < LD/2.
-__device__ __forceinline__ void butterfly(double2* x, int i0, int i1, double2 w) {
-  const double2 u = x[i0], v = x[i1];
-  const double2 vw = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
-  x[i0] = make_double2(u.x + vw.x, u.y + vw.y);
-  x[i1] = make_double2(u.x - vw.x, u.y - vw.y);
+// Forward DFT X_q = sum_l x_l e^{-2 pi i q l / L}, in place, natural order in
+// and out: Stockham self-sorting passes.  A pass over sub-transforms of length
+// Ns takes butterfly j (inputs x[j + i L/r], i < r), multiplies input i by
+// e^{-2 pi i i (j mod Ns) / (r Ns)}, applies the r-point DFT and stores output i
+// at (j - j mod Ns) r + (j mod Ns) + i Ns.  Every lane reads its inputs before a
+// barrier and writes after it, so one buffer serves as source and target.
+// tw[q] = e^{-2 pi i q / LD}, q < LD.
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// 4-point forward DFT in place: y_q = sum_n a_n (-i)^{n q}
+__device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, double2& a3) {
+  const double2 t0 = make_double2(a0.x + a2.x, a0.y + a2.y);
+  const double2 t1 = make_double2(a0.x - a2.x, a0.y - a2.y);
+  const double2 t2 = make_double2(a1.x + a3.x, a1.y + a3.y);
+  const double2 t3 = make_double2(a1.x - a3.x, a1.y - a3.y);
+  a0 = make_double2(t0.x + t2.x, t0.y + t2.y);
+  a2 = make_double2(t0.x - t2.x, t0.y - t2.y);
+  a1 = make_double2(t1.x + t3.y, t1.y - t3.x);   // t1 - i t3
+  a3 = make_double2(t1.x - t3.y, t1.y + t3.x);   // t1 + i t3
+}
+
+// One radix-4 pass of an L-point transform; butterfly j in lanes with `active`.
+template <int L>
+__device__ __forceinline__ void r4_pass(double2* x, int j, int Ns, bool active, const double2* tw) {
+  double2 a0, a1, a2, a3;
+  if (active) {
+    a0 = x[j];
+    a1 = x[j + L / 4];
+    a2 = x[j + L / 2];
+    a3 = x[j + 3 * L / 4];
+  }
+  __syncthreads();
+  if (active) {
+    const int k = j & (Ns - 1);
+    const int step = LD / (4 * Ns);
+    a1 = cmul(a1, tw[k * step]);
+    a2 = cmul(a2, tw[2 * k * step]);
+    a3 = cmul(a3, tw[3 * k * step]);
+    dft4(a0, a1, a2, a3);
+    const int o = 4 * (j - k) + k;
+    x[o] = a0;
+    x[o + Ns] = a1;
+    x[o + 2 * Ns] = a2;
+    x[o + 3 * Ns] = a3;
+  }
+  __syncthreads();
+}
+
+// Last pass of a 128-point transform (radix 2, Ns = 64): butterfly j = lane
+// reads and writes x[j], x[j + 64] only.
+__device__ __forceinline__ void r2_last128(double2* x, int j, const double2* tw) {
+  const double2 a0 = x[j];
+  const double2 a1 = cmul(x[j + 64], tw[2 * j]);
+  x[j] = make_double2(a0.x + a1.x, a0.y + a1.y);
+  x[j + 64] = make_double2(a0.x - a1.x, a0.y - a1.y);
+}
+
+// Two 128-point transforms at once: lanes 0-31 take xa, lanes 32-63 take xb in
+// the radix-4 passes; every lane finishes one butterfly of each.
 __device__ void fft128x2(double2* xa, double2* xb, const double2* tw) {
   const int lane = threadIdx.x;
-  const int r0 = (int)(__brev((unsigned)lane) >> 25), r1 = (int)(__brev((unsigned)(lane + 64)) >> 25);
-  const double2 a0 = xa[r0], a1 = xa[r1], b0 = xb[r0], b1 = xb[r1];
+  double2* x = lane < 32 ? xa : xb;
+  const int j = lane & 31;
+  r4_pass<128>(x, j, 1, true, tw);
+  r4_pass<128>(x, j, 4, true, tw);
+  r4_pass<128>(x, j, 16, true, tw);
+  r2_last128(xa, lane, tw);
+  r2_last128(xb, lane, tw);
   __syncthreads();
-  xa[lane] = a0;
-  xa[lane + 64] = a1;
-  xb[lane] = b0;
-  xb[lane + 64] = b1;
+}
+
+__device__ void fft128(double2* x, const double2* tw) {
+  const int lane = threadIdx.x;
+  r4_pass<128>(x, lane, 1, lane < 32, tw);
+  r4_pass<128>(x, lane, 4, lane < 32, tw);
+  r4_pass<128>(x, lane, 16, lane < 32, tw);
+  r2_last128(x, lane, tw);
   __syncthreads();
-  for (int half = 1; half < 128; half <<= 1) {
-    const int grp = lane / half, pos = lane % half;
-    const int i0 = grp * 2 * half + pos, i1 = i0 + half;
-    const double2 w = tw[pos * (LD / 2 / half)];
-    butterfly(xa, i0, i1, w);
-    butterfly(xb, i0, i1, w);
-    __syncthreads();
-  }
 }
 
 __device__ void fft256(double2* x, const double2* tw) {
   const int lane = threadIdx.x;
-  double2 v0 = x[(int)(__brev((unsigned)lane) >> 24)];
-  double2 v1 = x[(int)(__brev((unsigned)(lane + 64)) >> 24)];
-  double2 v2 = x[(int)(__brev((unsigned)(lane + 128)) >> 24)];
-  double2 v3 = x[(int)(__brev((unsigned)(lane + 192)) >> 24)];
-  __syncthreads();
-  x[lane] = v0;
-  x[lane + 64] = v1;
-  x[lane + 128] = v2;
-  x[lane + 192] = v3;
-  __syncthreads();
-  for (int half = 1; half < 256; half <<= 1) {
-    for (int hh = 0; hh < 2; ++hh) {
-      const int bf = lane + 64 * hh;
-      const int grp = bf / half, pos = bf % half;
-      const int i0 = grp * 2 * half + pos, i1 = i0 + half;
-      butterfly(x, i0, i1, tw[pos * (LD / 2 / half)]);
-    }
-    __syncthreads();
-  }
+  r4_pass<256>(x, lane, 1, true, tw);
+  r4_pass<256>(x, lane, 4, true, tw);
+  r4_pass<256>(x, lane, 16, true, tw);
+  r4_pass<256>(x, lane, 64, true, tw);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
@@ -282,25 +320,22 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
     const double qn = Q[n][col];
     const double qm = n == 0 ? Q[1][col] : Q[n - 1][col];
     const double qp = (2.0 * n - 1.0) * half_inv_chi2m1 * (chi * qn - qm);
-    M.A0[n] = pref * (drchi * qp - 0.5 * ir * qn);
-    M.B0[n] = pref * dzchi * qp;
+    M.AB0[n] = make_double2(pref * (drchi * qp - 0.5 * ir * qn), pref * dzchi * qp);
   }
   __syncthreads();
   if (lane <= nmax) {
-    double ar, br;
+    const double2 ab = M.AB0[lane];
     if (k == 0.0) {
-      ar = M.A0[lane];
-      br = M.B0[lane];
-      M.Am[lane] = make_double2(ar, 0.0);
-      M.Bm[lane] = make_double2(br, 0.0);
+      M.Am[lane] = make_double2(ab.x, 0.0);
+      M.Bm[lane] = make_double2(ab.y, 0.0);
     } else {
-      ar = 0.0;
-      br = 0.0;
-      for (int n = -nf; n <= nf; ++n) {
-        const double f = M.Fh[abs(n)];
-        const int idx = abs(lane - n);
-        ar += f * M.A0[idx];
-        br += f * M.B0[idx];
+      // F^ is even in n: (F^ * g)_m = F^_0 g_m + sum_{n>=1} F^_n (g_{|m-n|} + g_{m+n})
+      double ar = M.Fh[0] * ab.x, br = M.Fh[0] * ab.y;
+      for (int n = 1; n <= nf; ++n) {
+        const double f = M.Fh[n];
+        const double2 u = M.AB0[abs(lane - n)], v = M.AB0[lane + n];
+        ar = fma(f, u.x + v.x, ar);
+        br = fma(f, u.y + v.y, br);
       }
       M.Am[lane] = make_double2(ar * (1.0 / TWO_PI), M.Hrh[lane]);
       M.Bm[lane] = make_double2(br * (1.0 / TWO_PI), -c * M.Hh[lane]);
@@ -309,68 +344,72 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
   __syncthreads();
 }
 
-// G_j = (1/2N) sum'_{|m|<=N} Km[m + N] e^{i m theta_j} in lane j < 2N (+-N halved).
-__device__ __forceinline__ double2 inverse_dft_2n(int N, const double2* Km, const double2* tw2n) {
-  const int lane = threadIdx.x;
-  double2 g = make_double2(0.0, 0.0);
-  if (lane < 2 * N) {
-    const int twoN = 2 * N;
-    int e = ((-N * lane) % twoN + twoN) % twoN;   // (m * lane) mod 2N at m = -N
-    for (int idx = 0; idx <= twoN; ++idx) {
-      const double wgt = (idx == 0 || idx == twoN) ? 0.5 : 1.0;
-      const double2 t = tw2n[e];
-      const double2 K = Km[idx];
-      g.x = fma(wgt, K.x * t.x - K.y * t.y, g.x);
-      g.y = fma(wgt, K.x * t.y + K.y * t.x, g.y);
-      e += lane;
-      if (e >= twoN) e -= twoN;
-    }
-    const double inv2n = 1.0 / twoN;
-    g.x *= inv2n;
-    g.y *= inv2n;
+// theta-frame mode m of the kernel from the phi-frame modes A = dr G, B = dz G
+// (even in m), with e^{-i m alpha} = (c0, s0) and e^{i alpha} = (ca, sa):
+//   e^{-i m alpha} (r z' A_m - r r' B_m)
+//   - r/2 (p' - i q') e^{-i(m-1) alpha} B_{m-1} - r/2 (p' + i q') e^{-i(m+1) alpha} B_{m+1}
+__device__ __forceinline__ double2 theta_mode(int m, double c0, double s0, double ca, double sa,
+                                              const NodeLoc& L, const ModalScratch& M) {
+  const double r = L.r;
+  const double c1 = c0 * ca - s0 * sa, s1 = s0 * ca + c0 * sa;   // e^{-i(m-1) alpha}
+  const double c2 = c0 * ca + s0 * sa, s2 = s0 * ca - c0 * sa;   // e^{-i(m+1) alpha}
+  const double2 A = M.Am[abs(m)], B = M.Bm[abs(m)];
+  const double2 Bm1 = M.Bm[abs(m - 1)], Bp1 = M.Bm[abs(m + 1)];
+  const double tr = r * L.dz * A.x - r * L.dr * B.x;
+  const double ti = r * L.dz * A.y - r * L.dr * B.y;
+  double kr = c0 * tr - s0 * ti;
+  double ki = c0 * ti + s0 * tr;
+  const double fr = 0.5 * r * L.dp, fq = 0.5 * r * L.dq;
+  {
+    const double er = c1 * Bm1.x - s1 * Bm1.y, ei = c1 * Bm1.y + s1 * Bm1.x;
+    kr -= fr * er + fq * ei;
+    ki -= fr * ei - fq * er;
   }
-  return g;
+  {
+    const double er = c2 * Bp1.x - s2 * Bp1.y, ei = c2 * Bp1.y + s2 * Bp1.x;
+    kr -= fr * er - fq * ei;
+    ki -= fr * ei + fq * er;
+  }
+  return make_double2(kr, ki);
 }
 
-// G_j (returned in lane j < 2N) from the phi-frame modes of one node.
-__device__ double2 modes_to_gj(int N, const NodeLoc& L, ModalScratch& M, const double2* tw2n) {
+// Mode slot of lane s < 2N: m = s - N, with slot 0 holding K_{-N} + K_{N}
+// (the inverse DFT weighs both by 1/2 and e^{+-i N theta_j} agree).
+__device__ __forceinline__ double2 modal_slot(int N, const NodeLoc& L, const ModalScratch& M) {
   const int lane = threadIdx.x;
-  const double r = L.r;
-  for (int idx = lane; idx <= 2 * N; idx += 64) {
-    const int m = idx - N;
-    double s0, c0, sa, ca;
+  double2 out = make_double2(0.0, 0.0);
+  double sa, ca;
+  sincos_cw(L.alpha, &sa, &ca);
+  if (lane < 2 * N) {
+    const int m = lane - N;
+    double s0, c0;
     sincos_cw(-m * L.alpha, &s0, &c0);
-    sincos_cw(L.alpha, &sa, &ca);
-    // e^{-i(m-1) alpha} = e^{-i m alpha} e^{i alpha}, e^{-i(m+1) alpha} = e^{-i m alpha} e^{-i alpha}
-    const double c1 = c0 * ca - s0 * sa, s1 = s0 * ca + c0 * sa;
-    const double c2 = c0 * ca + s0 * sa, s2 = s0 * ca - c0 * sa;
-    const double2 A = M.Am[abs(m)], B = M.Bm[abs(m)];
-    const double2 Bm1 = M.Bm[abs(m - 1)], Bp1 = M.Bm[abs(m + 1)];
-    // e^{-i m alpha} (r z' A - r r' B)
-    const double tr = r * L.dz * A.x - r * L.dr * B.x;
-    const double ti = r * L.dz * A.y - r * L.dr * B.y;
-    double kr = c0 * tr - s0 * ti;
-    double ki = c0 * ti + s0 * tr;
-    // - r/2 (p' - i q') e^{-i(m-1) alpha} B_{m-1}
-    {
-      const double er = c1 * Bm1.x - s1 * Bm1.y, ei = c1 * Bm1.y + s1 * Bm1.x;
-      const double fr = 0.5 * r * L.dp, fi = -0.5 * r * L.dq;
-      kr -= fr * er - fi * ei;
-      ki -= fr * ei + fi * er;
+    out = theta_mode(m, c0, s0, ca, sa, L, M);
+    if (lane == 0) {
+      const double2 o2 = theta_mode(N, c0, -s0, ca, sa, L, M);
+      out.x += o2.x;
+      out.y += o2.y;
     }
-    // - r/2 (p' + i q') e^{-i(m+1) alpha} B_{m+1}
-    {
-      const double er = c2 * Bp1.x - s2 * Bp1.y, ei = c2 * Bp1.y + s2 * Bp1.x;
-      const double fr = 0.5 * r * L.dp, fi = 0.5 * r * L.dq;
-      kr -= fr * er - fi * ei;
-      ki -= fr * ei + fi * er;
-    }
-    M.Km[idx] = make_double2(kr, ki);
   }
-  __syncthreads();
-  const double2 g = inverse_dft_2n(N, M.Km, tw2n);
-  __syncthreads();
-  return g;
+  return out;
+}
+
+// Uniform copy of lane l's value (v_readlane on both halves).
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// acc[l] += P_l(s_q) w_q K (lane l < 16 holds pw = P_l(s_q) w_q)
+__device__ __forceinline__ void accumulate_modes(double2 (&acc)[GL_ORDER], double pw, double2 K) {
+#pragma unroll
+  for (int l = 0; l < GL_ORDER; ++l) {
+    const double p = readlane_f64(pw, l);
+    acc[l].x = fma(p, K.x, acc[l].x);
+    acc[l].y = fma(p, K.y, acc[l].y);
+  }
 }
 
 // ---------------------------------------------------------------- per-node geometry
@@ -480,7 +519,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   }
 
   // tables: FFT twiddles (also the azimuth samples) and e^{i pi m / N}
-  for (int q = lane; q < LD / 2; q += 64) {
+  for (int q = lane; q < LD; q += 64) {
     double s, c;
     sincos_cw(-TWO_PI * q / LD, &s, &c);
     S.tw[q] = make_double2(c, s);
@@ -492,8 +531,10 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   }
   __syncthreads();
 
+  // lane s < 2N accumulates sum_q w_q P_l(s_q) K_{s-N}(s_q), l < 16
+  double2 acc[GL_ORDER];
 #pragma unroll
-  for (int l = 0; l < GL_ORDER; ++l) S.acc[l][lane] = make_double2(0.0, 0.0);
+  for (int l = 0; l < GL_ORDER; ++l) acc[l] = make_double2(0.0, 0.0);
   const double e0 = -0.5 * PI + h * ip, e1 = e0 + h;
   const int nsides = (ip == pT) ? 2 : 1;
   for (int side = 0; side < nsides; ++side) {
@@ -513,10 +554,16 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         w = fabs(far - end) * 5.0 * u4 * wu;
       }
     }
-    bool modal;
+    bool modal, wide;
     {
       const NodeLoc L = node_local(shape, a, cc, kappa, tT, thT, dl);
       modal = L.chim1 < CHI_SPLIT;
+      // direct route: modes decay like e^{-acosh(chi) |m|} beyond the width of
+      // the oscillatory factor (about k rho_max); 128 samples when the aliased
+      // modes |m| >= 128 - N are below 1e-17 of the leading ones
+      const double acosh_chi = log1p(L.chim1 + sqrt(L.chim1 * (L.chim1 + 2.0)));
+      const double rho_max = sqrt((L.r + L.rt) * (L.r + L.rt) + L.c * L.c);
+      wide = acosh_chi * ((LD / 2) - N - (k * rho_max + 10.0)) < 40.0;
     }
     const unsigned long long mmask = __ballot(modal);
     const int nmodal = __popcll(mmask);
@@ -542,23 +589,21 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         const double wq = __shfl(w, sl);
         const NodeLoc Ln = node_local(shape, a, cc, kappa, tT, thT, dlq);
         modal_modes(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.tw);
-        const double2 g = modes_to_gj(N, Ln, S.u.m, S.tw2n);
-        if (lane < GL_ORDER) S.Pl[lane] = lagrange_gl(gl16, 2.0 * (Ln.s - e0) / h - 1.0, lane) * wq;
-        __syncthreads();
-        for (int l = 0; l < GL_ORDER; ++l) {
-          double2 v = S.acc[l][lane];
-          v.x = fma(S.Pl[l], g.x, v.x);
-          v.y = fma(S.Pl[l], g.y, v.y);
-          S.acc[l][lane] = v;
-        }
+        const double2 K = modal_slot(N, Ln, S.u.m);
+        const double pw = lane < GL_ORDER ? lagrange_gl(gl16, 2.0 * (Ln.s - e0) / h - 1.0, lane) * wq : 0.0;
+        accumulate_modes(acc, pw, K);
         __syncthreads();
       }
     }
-    // ---- direct route: trapezoidal rule on LD azimuths of the kernel itself,
-    // its modes by FFT, then the inverse DFT onto the Lagrange basis
+    // ---- direct route: trapezoidal rule on L azimuths of the kernel itself,
+    // its modes by FFT
     const unsigned long long dmask = ~mmask;
+    const unsigned long long wmask = __ballot(wide);
     for (int q = 0; q < 64; ++q) {
       if (!((dmask >> q) & 1ull)) continue;
+      const bool w256 = (wmask >> q) & 1ull;
+      const int L = w256 ? LD : LD / 2;
+      const int tstep = LD / L;
       const double dlq = __shfl(dl, q);
       const double wq = __shfl(w, q);
       const double sq = tT + dlq;
@@ -566,53 +611,72 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
 #pragma unroll
       for (int hh = 0; hh < LD / 64; ++hh) {
         const int l = lane + 64 * hh;
-        // (cos, sin)(2 pi l / LD) from the twiddle table
-        const double2 t = S.tw[l & (LD / 2 - 1)];
-        const double sg = (l < LD / 2) ? 1.0 : -1.0;
-        const double cth = sg * t.x, sth = -sg * t.y;
-        const double dx = cv.r * cth + cv.p - xT, dy = cv.r * sth + cv.q - yT, dz = cv.z - zT;
-        const double nx = cv.r * cv.dz * cth, ny = cv.r * cv.dz * sth;
-        const double nz = -cv.r * (cv.dr + cv.dp * cth + cv.dq * sth);
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const double ir = rsqrt(r2);
-        const double rr = r2 * ir;
-        double s, c;
-        sincos_cw(k * rr, &s, &c);
-        const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI;
-        S.u.K[l] = make_double2(-fma(k * rr, s, c) * sc, fma(k * rr, c, -s) * sc);
+        if (l < L) {
+          // (cos, sin)(2 pi l / L) from the twiddle table
+          const double2 t = S.tw[l * tstep];
+          const double cth = t.x, sth = -t.y;
+          const double dx = cv.r * cth + cv.p - xT, dy = cv.r * sth + cv.q - yT, dz = cv.z - zT;
+          const double nx = cv.r * cv.dz * cth, ny = cv.r * cv.dz * sth;
+          const double nz = -cv.r * (cv.dr + cv.dp * cth + cv.dq * sth);
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const double ir = rsqrt(r2);
+          const double rr = r2 * ir;
+          double s, c;
+          sincos_cw(k * rr, &s, &c);
+          const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI;
+          S.u.K[l] = make_double2(-fma(k * rr, s, c) * sc, fma(k * rr, c, -s) * sc);
+        }
       }
-      if (lane < GL_ORDER) S.Pl[lane] = lagrange_gl(gl16, 2.0 * (sq - e0) / h - 1.0, lane) * wq;
+      const double pw = lane < GL_ORDER ? lagrange_gl(gl16, 2.0 * (sq - e0) / h - 1.0, lane) * wq : 0.0;
       __syncthreads();
-      fft256(S.u.K, S.tw);
-      // modes K_m = (2 pi / LD) X[m mod LD], m = -N..N, gathered into Km order
-      double2 km0 = make_double2(0.0, 0.0), km1 = km0;
-      const double f = TWO_PI / LD;
-      if (lane <= 2 * N) {
-        const double2 v = S.u.K[(lane - N + LD) % LD];
-        km0 = make_double2(v.x * f, v.y * f);
+      if (w256) fft256(S.u.K, S.tw); else fft128(S.u.K, S.tw);
+      // mode slot s = lane: m = s - N (slot 0 also takes m = +N), K_m = (2 pi / L) X[m mod L]
+      double2 K = make_double2(0.0, 0.0);
+      if (lane < 2 * N) {
+        K = S.u.K[(lane - N + L) & (L - 1)];
+        if (lane == 0) {
+          const double2 v = S.u.K[N];
+          K.x += v.x;
+          K.y += v.y;
+        }
+        const double f = TWO_PI / L;
+        K.x *= f;
+        K.y *= f;
       }
-      if (lane + 64 <= 2 * N) {
-        const double2 v = S.u.K[(lane + 64 - N + LD) % LD];
-        km1 = make_double2(v.x * f, v.y * f);
-      }
-      __syncthreads();
-      if (lane <= 2 * N) S.u.K[lane] = km0;
-      if (lane + 64 <= 2 * N) S.u.K[lane + 64] = km1;
-      __syncthreads();
-      const double2 g = inverse_dft_2n(N, S.u.K, S.tw2n);
-      for (int l = 0; l < GL_ORDER; ++l) {
-        double2 v = S.acc[l][lane];
-        v.x = fma(S.Pl[l], g.x, v.x);
-        v.y = fma(S.Pl[l], g.y, v.y);
-        S.acc[l][lane] = v;
-      }
+      accumulate_modes(acc, pw, K);
       __syncthreads();
     }
   }
+  // inverse DFT onto the Lagrange basis: lane j < 2N,
+  // G_lj = (1/2N) sum_s acc_l[s] e^{i (s - N) theta_j}, slot 0 weighted 1/2;
+  // e^{i (s - N) j pi / N} = (-1)^j e^{i pi s j / N}
+#pragma unroll
+  for (int l = 0; l < GL_ORDER; ++l) {
+    const double f = lane == 0 ? 0.5 : 1.0;
+    S.acc[l][lane] = make_double2(acc[l].x * f, acc[l].y * f);
+  }
+  __syncthreads();
   if (lane < 2 * N) {
+    double2 g[GL_ORDER];
+#pragma unroll
+    for (int l = 0; l < GL_ORDER; ++l) g[l] = make_double2(0.0, 0.0);
+    int e = 0;
+    for (int sl = 0; sl < 2 * N; ++sl) {
+      const double2 t = S.tw2n[e];
+      e += lane;
+      if (e >= 2 * N) e -= 2 * N;
+#pragma unroll
+      for (int l = 0; l < GL_ORDER; ++l) {
+        const double2 v = S.acc[l][sl];
+        g[l].x = fma(v.x, t.x, fma(-v.y, t.y, g[l].x));
+        g[l].y = fma(v.x, t.y, fma(v.y, t.x, g[l].y));
+      }
+    }
+    const double scale = ((lane & 1) ? -1.0 : 1.0) / (2 * N);
     const bool diag = ip == pT && lane == jT;
+#pragma unroll
     for (int l = 0; l < GL_ORDER; ++l) {
-      double2 v = S.acc[l][lane];
+      double2 v = make_double2(g[l].x * scale, g[l].y * scale);
       if (diag && l == lT) v.x += 0.5;     // 1/2 I
       row[(int64_t)(ip * GL_ORDER + l) * nth + lane] = v;
     }
@@ -670,7 +734,7 @@ __global__ __launch_bounds__(64) void modal_modes_kernel(const double* __restric
   __shared__ SelfShared S;
   const int pt = blockIdx.x;
   const int lane = threadIdx.x;
-  for (int q = lane; q < LD / 2; q += 64) {
+  for (int q = lane; q < LD; q += 64) {
     double s, cc;
     sincos_cw(-TWO_PI * q / LD, &s, &cc);
     S.tw[q] = make_double2(cc, s);
