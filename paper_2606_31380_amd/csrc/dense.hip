@@ -289,81 +289,138 @@ __global__ void gj_unpivot_kernel(const MatDesc* __restrict__ mats, double2* __r
 // row interchanges at the end.
 constexpr int GJB = 64;
 
-// Unblocked elimination with partial pivoting on the columns [k0, k0 + wcols)
-// only (pivot rows >= k); row interchanges are applied to these columns only.
-__global__ __launch_bounds__(1024) void gjb_panel_kernel(const MatDesc* __restrict__ mats,
-                                                         double2* __restrict__ pool, int k0,
-                                                         int wcols,
-                                                         int32_t* __restrict__ piv,
-                                                         double2* __restrict__ colbuf,
-                                                         int64_t col_stride, int nmax) {
+// Unblocked elimination with partial pivoting on the columns [c0, c0 + wcols)
+// only (pivot rows >= k; row interchanges applied to these columns only), one
+// workgroup of 1024 threads per matrix with the columns held in registers:
+// thread t owns rows t + 1024 r, r < R, and WL <= 16 / R columns.  Per column:
+// arg-max of |a_ik|^2 by wavefront shuffles and one LDS pass (ties to the
+// lower row), the row interchange through LDS, the pivot row scaled by its
+// owner, and the rank-1 elimination of the other rows.
+template <int R, int WL>
+__global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restrict__ mats,
+                                                        double2* __restrict__ pool, int c0,
+                                                        int wcols, int32_t* __restrict__ piv,
+                                                        int nmax) {
   const MatDesc M = mats[blockIdx.x];
   const int n = M.n;
-  if (k0 >= n) return;
+  if (c0 >= n) return;
   double2* A = pool + M.elem_off;
-  double2* col = colbuf + (int64_t)blockIdx.x * col_stride;
-  const int kend = min(k0 + wcols, n);
-  const int w = kend - k0;
-  const int tid = threadIdx.x;
-  __shared__ double best[1024];
-  __shared__ int bidx[1024];
-  __shared__ double2 rowk[GJB];
-  for (int k = k0; k < kend; ++k) {
+  const int w = min(c0 + wcols, n) - c0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double red_v[16];
+  __shared__ int red_i[16];
+  __shared__ double2 swap_buf[2][WL];
+  __shared__ double2 rowk[WL];
+  double2 a[R][WL];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + 1024 * r;
+#pragma unroll
+    for (int c = 0; c < WL; ++c)
+      a[r][c] = (i < n && c < w) ? A[(int64_t)i * n + c0 + c] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int kk = 0; kk < WL; ++kk) {
+    if (kk >= w) break;
+    const int k = c0 + kk;
     double bv = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < n; i += 1024) {
-      const double2 a = A[(int64_t)i * n + k];
-      const double m = a.x * a.x + a.y * a.y;
-      if (m > bv) { bv = m; bi = i; }
+    int bi = n;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 1024 * r;
+      const double m = a[r][kk].x * a[r][kk].x + a[r][kk].y * a[r][kk].y;
+      if (i >= k && i < n && m > bv) {
+        bv = m;
+        bi = i;
+      }
     }
-    best[tid] = bv;
-    bidx[tid] = bi;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      red_v[wave] = bv;
+      red_i[wave] = bi;
+    }
     __syncthreads();
-    for (int st = 512; st > 0; st >>= 1) {
-      if (tid < st) {
-        const double o = best[tid + st];
-        const int oi = bidx[tid + st];
-        if (o > best[tid] || (o == best[tid] && oi < bidx[tid])) {
-          best[tid] = o;
-          bidx[tid] = oi;
-        }
+    bv = red_v[0];
+    bi = red_i[0];
+#pragma unroll
+    for (int q = 1; q < 16; ++q) {
+      const double ov = red_v[q];
+      const int oi = red_i[q];
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    const int pr = bi;
+    if (tid == 0) piv[(int64_t)blockIdx.x * nmax + k] = pr;
+    if (pr != k) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + 1024 * r;
+        if (i == pr)
+#pragma unroll
+          for (int c = 0; c < WL; ++c) swap_buf[0][c] = a[r][c];
+        if (i == k)
+#pragma unroll
+          for (int c = 0; c < WL; ++c) swap_buf[1][c] = a[r][c];
       }
       __syncthreads();
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = tid + 1024 * r;
+        if (i == k)
+#pragma unroll
+          for (int c = 0; c < WL; ++c) a[r][c] = swap_buf[0][c];
+        if (i == pr)
+#pragma unroll
+          for (int c = 0; c < WL; ++c) a[r][c] = swap_buf[1][c];
+      }
     }
-    const int pr = bidx[0];
-    if (tid == 0) piv[(int64_t)blockIdx.x * nmax + k] = pr;
-    if (pr != k && tid < w) {
-      const int c = k0 + tid;
-      const double2 t = A[(int64_t)k * n + c];
-      A[(int64_t)k * n + c] = A[(int64_t)pr * n + c];
-      A[(int64_t)pr * n + c] = t;
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += 1024) col[i] = A[(int64_t)i * n + k];
-    __syncthreads();
-    const double2 d = col[k];
-    const double den = d.x * d.x + d.y * d.y;
-    const double2 inv = make_double2(d.x / den, -d.y / den);
-    if (tid < w) {
-      const int c = k0 + tid;
-      const double2 a = (c == k) ? make_double2(1.0, 0.0) : A[(int64_t)k * n + c];
-      const double2 v = make_double2(a.x * inv.x - a.y * inv.y, a.x * inv.y + a.y * inv.x);
-      A[(int64_t)k * n + c] = v;
-      rowk[tid] = v;
-    }
-    __syncthreads();
-    for (int e = tid; e < n * w; e += 1024) {
-      const int i = e / w;
-      const int cc = e % w;
-      if (i == k) continue;
-      const int c = k0 + cc;
-      const double2 fi = col[i];
-      const double2 rk = rowk[cc];
-      const double2 a = (c == k) ? make_double2(0.0, 0.0) : A[(int64_t)i * n + c];
-      A[(int64_t)i * n + c] = make_double2(a.x - (fi.x * rk.x - fi.y * rk.y),
-                                           a.y - (fi.x * rk.y + fi.y * rk.x));
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (tid + 1024 * r == k) {
+        const double2 d = a[r][kk];
+        const double den = d.x * d.x + d.y * d.y;
+        const double2 inv = make_double2(d.x / den, -d.y / den);
+#pragma unroll
+        for (int c = 0; c < WL; ++c) {
+          const double2 x = (c == kk) ? make_double2(1.0, 0.0) : a[r][c];
+          const double2 v = make_double2(x.x * inv.x - x.y * inv.y, x.x * inv.y + x.y * inv.x);
+          a[r][c] = v;
+          rowk[c] = v;
+        }
+      }
     }
     __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 1024 * r;
+      if (i != k && i < n) {
+        const double2 f = a[r][kk];
+#pragma unroll
+        for (int c = 0; c < WL; ++c) {
+          const double2 x = (c == kk) ? make_double2(0.0, 0.0) : a[r][c];
+          const double2 rk = rowk[c];
+          a[r][c] = make_double2(x.x - (f.x * rk.x - f.y * rk.y), x.y - (f.x * rk.y + f.y * rk.x));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + 1024 * r;
+    if (i < n)
+#pragma unroll
+      for (int c = 0; c < WL; ++c)
+        if (c < w) A[(int64_t)i * n + c0 + c] = a[r][c];
   }
 }
 
@@ -456,10 +513,15 @@ __global__ void gjb_swap_copy_kernel(const MatDesc* __restrict__ mats, double2* 
 }
 
 // A[i][j] = (i in panel ? 0 : A[i][j]) + sum_p A[i][k0+p] W[p][j] for j outside
-// the panel.  64 x 64 output tile per workgroup, 4 x 4 per thread.
-__global__ __launch_bounds__(256) void gjb_update_kernel(const MatDesc* __restrict__ mats,
+// the panel, on the matrix cores: the complex product as a real one,
+// [Re a, Im a] x [[Re w, Im w], [-Im w, Re w]], with v_mfma_f64_16x16x4f64.
+// 64 x 64 complex output tile per workgroup (64 x 128 real); each of the four
+// wavefronts owns 32 rows x 64 real columns (2 x 4 MFMA tiles); the panel
+// columns and rows are staged through LDS 16 complex columns at a time.
+__global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restrict__ mats,
                                                          double2* __restrict__ pool, int k0,
                                                          const double2* __restrict__ W, int nmax) {
+  typedef MfmaAcc<double>::v4 v4;
   const MatDesc M = mats[blockIdx.z];
   const int n = M.n;
   if (k0 >= n) return;
@@ -470,76 +532,134 @@ __global__ __launch_bounds__(256) void gjb_update_kernel(const MatDesc* __restri
   if (j0 >= k0 && j0 + 64 <= kend) return;  // tile inside the panel columns
   double2* A = pool + M.elem_off;
   const double2* Wm = W + (int64_t)blockIdx.z * GJB * nmax;
-  __shared__ double2 As[16][64];
-  __shared__ double2 Ws[16][64];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double2 acc[4][4];
+  __shared__ double As[32][64 + 1];   // real k x rows
+  __shared__ double Bs[32][128 + 1];  // real k x real columns
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 64;
+  // accumulators start from the tile of A (zero on the panel rows and for
+  // entries outside the matrix or inside the panel columns, which are not stored)
+  v4 acc[2][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = make_double2(0.0, 0.0);
+    for (int e = 0; e < 4; ++e) {
+      const int i = i0 + wr + 16 * x + MfmaAcc<double>::row(lane, e);
+      const bool prow = i >= k0 && i < kend;
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int c = wc + 16 * y + (lane & 15);
+        const int j = j0 + (c >> 1);
+        const bool keep = i < n && j < n && !(j >= k0 && j < kend) && !prow;
+        acc[x][y][e] = keep ? ((const double*)(A + (int64_t)i * n + j))[c & 1] : 0.0;
+      }
+    }
+  // panel columns of A and rows of W, 16 at a time, the next chunk loaded into
+  // registers while the current one is multiplied
+  double2 ra[4], rw[4];
+  auto load_chunk = [&](int p0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e >> 4, pp = e & 15;
+      const int i = i0 + rr, pc = p0 + pp;
+      ra[q] = (i < n && pc < w) ? A[(int64_t)i * n + k0 + pc] : make_double2(0.0, 0.0);
+      const int pw = e >> 6, jj = e & 63;
+      const int j = j0 + jj, pcw = p0 + pw;
+      rw[q] = (j < n && pcw < w) ? Wm[(int64_t)pcw * nmax + j] : make_double2(0.0, 0.0);
+    }
+  };
+  load_chunk(0);
   for (int p0 = 0; p0 < w; p0 += 16) {
-    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      const int pp = e >> 6, rr = e & 63;
-      const int i = i0 + rr, pcol = p0 + pp;
-      As[pp][rr] = (i < n && pcol < w) ? A[(int64_t)i * n + k0 + pcol] : make_double2(0.0, 0.0);
-      const int j = j0 + rr;
-      Ws[pp][rr] = (j < n && pcol < w) ? Wm[(int64_t)pcol * nmax + j] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e >> 4, pp = e & 15;
+      As[2 * pp][rr] = ra[q].x;
+      As[2 * pp + 1][rr] = ra[q].y;
+      const int pw = e >> 6, jj = e & 63;
+      Bs[2 * pw][2 * jj] = rw[q].x;
+      Bs[2 * pw][2 * jj + 1] = rw[q].y;
+      Bs[2 * pw + 1][2 * jj] = -rw[q].y;
+      Bs[2 * pw + 1][2 * jj + 1] = rw[q].x;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int pp = 0; pp < 16; ++pp) {
-      double2 av[4], wv[4];
+    if (p0 + 16 < w) load_chunk(p0 + 16);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = As[pp][ty + 16 * a];
+    for (int kk = 0; kk < 32; kk += 4) {
+      const int kr = kk + (lane >> 4), ci = lane & 15;
+      double af[2], bf[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) wv[b] = Ws[pp][tx + 16 * b];
+      for (int x = 0; x < 2; ++x) af[x] = As[kr][wr + 16 * x + ci];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int y = 0; y < 4; ++y) bf[y] = Bs[kr][wc + 16 * y + ci];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          acc[a][b].x += av[a].x * wv[b].x - av[a].y * wv[b].y;
-          acc[a][b].y += av[a].x * wv[b].y + av[a].y * wv[b].x;
-        }
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = MfmaAcc<double>::mma(af[x], bf[y], acc[x][y]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = i0 + ty + 16 * a;
-    if (i >= n) continue;
-    const bool prow = i >= k0 && i < kend;
+  for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = j0 + tx + 16 * b;
-      if (j >= n || (j >= k0 && j < kend)) continue;
-      double2* cptr = A + (int64_t)i * n + j;
-      const double2 base = prow ? make_double2(0.0, 0.0) : *cptr;
-      *cptr = make_double2(base.x + acc[a][b].x, base.y + acc[a][b].y);
+    for (int e = 0; e < 4; ++e) {
+      const int i = i0 + wr + 16 * x + MfmaAcc<double>::row(lane, e);
+      if (i >= n) continue;
+#pragma unroll
+      for (int y = 0; y < 4; ++y) {
+        const int c = wc + 16 * y + (lane & 15);   // real column in the tile
+        const int j = j0 + (c >> 1);
+        if (j >= n || (j >= k0 && j < kend)) continue;
+        ((double*)(A + (int64_t)i * n + j))[c & 1] = acc[x][y][e];
+      }
     }
+}
+
+// Leaf shape of the recursive panel factorization for matrices of order <= nmax:
+// R rows per thread (1024 threads), WL = min(8, 16 / R) columns.
+static int gj_leaf_rows(int nmax) {
+  int r = 1;
+  while (1024 * r < nmax) r *= 2;
+  return r;
+}
+
+static int gj_leaf_cols(int nmax) { return gj_leaf_rows(nmax) == 1 ? 8 : 16 / gj_leaf_rows(nmax); }
+
+static void launch_leaf(hipStream_t s, double2* pool, const MatDesc* d_mats, int batch, int nmax,
+                        int c0, int w, int32_t* piv) {
+  switch (gj_leaf_rows(nmax)) {
+    case 1:
+      hipLaunchKernelGGL((gjr_leaf_kernel<1, 8>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      break;
+    case 2:
+      hipLaunchKernelGGL((gjr_leaf_kernel<2, 8>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      break;
+    case 4:
+      hipLaunchKernelGGL((gjr_leaf_kernel<4, 4>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      break;
+    default:
+      hipLaunchKernelGGL((gjr_leaf_kernel<8, 2>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      break;
   }
 }
 
-constexpr int GJ_LEAF = 8;
-
 // Factor the panel columns [c0, c0 + w) (w a power of two, <= GJB) by halves:
 // left half, its row operations on the right half, right half, its row
-// operations on the left half; leaves of GJ_LEAF columns run unblocked.
+// operations on the left half; leaves of gj_leaf_cols columns run unblocked.
 static void gj_factor_panel(hipStream_t s, double2* pool, const MatDesc* d_mats, int batch, int nmax,
-                            int c0, int w, int32_t* piv, double2* colbuf, double2* Wn) {
-  if (w <= GJ_LEAF) {
-    hipLaunchKernelGGL(gjb_panel_kernel, dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv,
-                       colbuf, (int64_t)nmax, nmax);
+                            int c0, int w, int32_t* piv, double2* Wn) {
+  if (w <= gj_leaf_cols(nmax)) {
+    launch_leaf(s, pool, d_mats, batch, nmax, c0, w, piv);
     return;
   }
   const int h = w / 2;
   const unsigned rows_blocks = (unsigned)((nmax + (256 / h) - 1) / (256 / h));
-  gj_factor_panel(s, pool, d_mats, batch, nmax, c0, h, piv, colbuf, Wn);
+  gj_factor_panel(s, pool, d_mats, batch, nmax, c0, h, piv, Wn);
   hipLaunchKernelGGL(gjn_swap_copy_kernel, dim3(batch), dim3(h), 0, s, d_mats, pool, c0, h, c0 + h,
                      h, piv, nmax, Wn);
   hipLaunchKernelGGL(gjn_update_kernel, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool, c0,
                      h, c0 + h, h, Wn);
-  gj_factor_panel(s, pool, d_mats, batch, nmax, c0 + h, h, piv, colbuf, Wn);
+  gj_factor_panel(s, pool, d_mats, batch, nmax, c0 + h, h, piv, Wn);
   hipLaunchKernelGGL(gjn_swap_copy_kernel, dim3(batch), dim3(h), 0, s, d_mats, pool, c0 + h, h, c0,
                      h, piv, nmax, Wn);
   hipLaunchKernelGGL(gjn_update_kernel, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool,
@@ -547,19 +667,20 @@ static void gj_factor_panel(hipStream_t s, double2* pool, const MatDesc* d_mats,
 }
 
 // In-place inversion of `batch` matrices described on the device by `mats`
-// (orders up to nmax).  work: see gj_work_bytes.
+// (orders up to nmax, at most 8192).  work: see gj_work_bytes.
 hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int batch, int nmax,
                      double* work) {
-  double2* colbuf = (double2*)work;
-  double2* W = colbuf + (int64_t)nmax * batch;
+  if (nmax > 8192) return hipErrorInvalidValue;
+  double2* W = (double2*)work;
   int32_t* piv = (int32_t*)(W + (int64_t)GJB * nmax * batch);
-  double2* Wn = (double2*)(piv + (int64_t)nmax * batch + 64);
+  const size_t piv_bytes = (((size_t)nmax * batch * sizeof(int32_t)) + 255) / 256 * 256;
+  double2* Wn = (double2*)((char*)piv + piv_bytes);
   const unsigned tiles = (unsigned)((nmax + 63) / 64);
   for (int k0 = 0; k0 < nmax; k0 += GJB) {
-    gj_factor_panel(s, (double2*)pool, d_mats, batch, nmax, k0, GJB, piv, colbuf, Wn);
+    gj_factor_panel(s, (double2*)pool, d_mats, batch, nmax, k0, GJB, piv, Wn);
     hipLaunchKernelGGL(gjb_swap_copy_kernel, dim3((nmax + 255) / 256, batch), dim3(256), 0, s,
                        d_mats, (double2*)pool, k0, piv, nmax, W);
-    hipLaunchKernelGGL(gjb_update_kernel, dim3(tiles, tiles, batch), dim3(256), 0, s, d_mats,
+    hipLaunchKernelGGL(gjm_update_kernel, dim3(tiles, tiles, batch), dim3(256), 0, s, d_mats,
                        (double2*)pool, k0, W, nmax);
   }
   hipLaunchKernelGGL(gj_unpivot_kernel, dim3((nmax + 255) / 256, batch), dim3(256), 0, s, d_mats,
@@ -568,8 +689,9 @@ hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int bat
 }
 
 size_t gj_work_bytes(int batch, int nmax) {
-  return (size_t)nmax * batch * (sizeof(double2) * (1 + GJB) + sizeof(int32_t)) + 256 + 64 * 4 +
-         (size_t)batch * GJB * GJB * sizeof(double2) + 256;
+  return (size_t)nmax * batch * sizeof(double2) * GJB +
+         (((size_t)nmax * batch * sizeof(int32_t)) + 255) / 256 * 256 +
+         (size_t)batch * GJB * GJB * sizeof(double2);
 }
 
 // Invert every distinct self block: copy B into Binv, invert in place, make

@@ -144,7 +144,6 @@ void plan_pair_sum(qax_problem* p, int prec, int cu_count);
 hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,
                               int nrhs, bool accumulate);
 hipError_t launch_invert_blocks(qax_problem* p, double* work);
-hipError_t launch_gj_invert(hipStream_t s, double* A, int n, int batch, int64_t stride, double* work);
 hipError_t launch_convert_f32(hipStream_t s, const double* src, float* dst, int64_t count);
 hipError_t launch_dense_offdiag(qax_problem* p, double* A);
 
