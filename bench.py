@@ -36,6 +36,25 @@ FLOP_PER_PAIR = 35
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "lattice27_counters.json")
+
+
+def counter_traffic(kind):
+    """HBM bytes per launch of the kernel behind timing kind `kind`, from the
+    committed FETCH_SIZE / WRITE_SIZE passes (scaled by the copy calibration),
+    or None when they are missing or the kernel's source changed since."""
+    import hashlib
+    try:
+        with open(COUNTERS) as f:
+            rec = json.load(f)["kernels"][kind]
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return rec["fetch_bytes"] + rec["write_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def far_grid(n=200):
     th = np.linspace(0, 2 * math.pi, n, endpoint=False)
     ph = (np.arange(n) + 0.5) * math.pi / n
@@ -116,7 +135,7 @@ def main():
     infos = [step(qax.QAX_MIXED) for _ in range(args.steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ktimes = {qax.KERNEL_NAMES[k]: qax.qax_timing(h, k) for k in range(5)}
+    ktimes = {name: qax.qax_timing(h, k) for k, name in enumerate(qax.KERNEL_NAMES)}
     qax.qax_set_timing(h, False)
 
     n32 = sum(i["iters"] for i in infos)          # FP32 pair sums (Krylov steps)
@@ -166,11 +185,15 @@ def main():
     adj = np.where(npan > 1, np.where(npan > 2, 2.0 - 2.0 / npan, 1.0), 0.0)
     self_flop = float(np.sum(nb * ((128 + 64 * adj) * per_node + (1 + adj) * per_item)))
     inv_flop = float(np.sum(8.0 * nb ** 3))
+    # one trailing update of the inversion: rank-64 complex update of every block
+    upd_flop = float(np.sum(8.0 * nb * nb * 64))
     work = {"pair_sum_fp32": ("alu", FLOP_PER_PAIR * P, PEAK["fp32"], "TFLOP/s"),
             "pair_sum_fp64": ("alu", FLOP_PER_PAIR * P, PEAK["fp64"], "TFLOP/s"),
-            "block_apply": ("hbm", float(np.sum(nb * nb)) * 8.0, PEAK["hbm"], "GB/s"),
+            "block_apply": ("hbm", float(np.sum(nb * nb)) * 16.0, PEAK["hbm"], "GB/s"),
+            "block_apply_f32": ("hbm", float(np.sum(nb * nb)) * 8.0, PEAK["hbm"], "GB/s"),
             "self_assembly": ("alu", self_flop, PEAK["fp64"], "TFLOP/s"),
-            "invert": ("alu", inv_flop, PEAK["fp64"], "TFLOP/s")}
+            "invert": ("alu", inv_flop, PEAK["fp64"], "TFLOP/s"),
+            "invert_update": ("mfma", upd_flop, PEAK["fp64"], "TFLOP/s")}
     rooflines = {}
     for name, (cnt, tot) in ktimes.items():
         if cnt == 0 or tot <= 0:
@@ -180,10 +203,16 @@ def main():
         ach = units / avg_s
         scale = 1e9 if unit == "GB/s" else 1e12
         rooflines[name] = {"bound": bound, "achieved": ach / scale, "peak": peak / scale,
-                           "unit": unit, "frac": ach / peak, "traffic": None,
+                           "unit": unit, "frac": ach / peak, "traffic": counter_traffic(name),
                            "avg_launch_ms": avg_s * 1e3, "launches": cnt}
-    dom = max(ktimes, key=lambda k: ktimes[k][1])
+    # dominant single kernel by time per step ("invert" spans several kernels)
+    dom = max((k for k in ktimes if k != "invert"), key=lambda k: ktimes[k][1])
     roof = dict(rooflines[dom], kernel=dom)
+    if dom == "pair_sum_fp32":
+        # packed FP32 instructions are disabled in this build: one FP32 FMA per
+        # lane and cycle, 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+        roof["peak_without_packed_fp32"] = PEAK["fp32"] / 2 / 1e12
+        roof["frac_without_packed_fp32"] = roof["achieved"] / roof["peak_without_packed_fp32"]
 
     out = {
         "metric": "Helmholtz pair-interactions/s + time-to-solve @1e-6 rel err, mixed vs FP64",

@@ -179,10 +179,12 @@ qax_status qax_modal_modes(qax_problem* p, int32_t n_pts, const double* d_r, con
 typedef enum {
   QAX_K_PAIRSUM_FP64 = 0,  /* inter-body pair sum, FP64                        */
   QAX_K_PAIRSUM_FP32 = 1,  /* inter-body pair sum, FP32 compensated            */
-  QAX_K_BLOCK_APPLY = 2,   /* block-diagonal apply (B or B^-1)                 */
+  QAX_K_BLOCK_APPLY = 2,   /* block-diagonal apply, FP64 (B or B^-1)           */
   QAX_K_SELF_ASSEMBLY = 3, /* self-block assembly                              */
-  QAX_K_INVERT = 4,        /* self-block inversion                             */
-  QAX_K_COUNT = 5
+  QAX_K_INVERT = 4,        /* self-block inversion (all of its launches)       */
+  QAX_K_INVERT_UPDATE = 5, /* inversion: trailing update of one 64-column panel */
+  QAX_K_BLOCK_APPLY_F32 = 6, /* block-diagonal apply of the FP32 copy of B^-1   */
+  QAX_K_COUNT = 7
 } qax_kernel;
 
 /* enable != 0 turns timing on (and clears the counters). */

@@ -85,14 +85,15 @@ hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double
 
 hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,
                               int nrhs, bool accumulate) {
+  const int kind = (inverse && prec == QAX_MIXED) ? QAX_K_BLOCK_APPLY_F32 : QAX_K_BLOCK_APPLY;
   if (nrhs >= 4) {
     // several right-hand sides: batched complex GEMM on the matrix cores
-    timing_begin(p, QAX_K_BLOCK_APPLY);
+    timing_begin(p, kind);
     hipError_t e = launch_block_gemm(p, inverse, prec, v, out, nrhs, accumulate);
-    timing_end(p, QAX_K_BLOCK_APPLY);
+    timing_end(p, kind);
     return e;
   }
-  timing_begin(p, QAX_K_BLOCK_APPLY);
+  timing_begin(p, kind);
   if (inverse && prec == QAX_MIXED) {
     if (nrhs == 1) gemv_launch<float, 1>(p, p->d_Binv32, v, out, nrhs, accumulate);
     else gemv_launch<float, 4>(p, p->d_Binv32, v, out, nrhs, accumulate);
@@ -101,7 +102,7 @@ hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const doubl
     if (nrhs == 1) gemv_launch<double, 1>(p, pool, v, out, nrhs, accumulate);
     else gemv_launch<double, 4>(p, pool, v, out, nrhs, accumulate);
   }
-  timing_end(p, QAX_K_BLOCK_APPLY);
+  timing_end(p, kind);
   return hipGetLastError();
 }
 
@@ -667,9 +668,10 @@ static void gj_factor_panel(hipStream_t s, double2* pool, const MatDesc* d_mats,
 }
 
 // In-place inversion of `batch` matrices described on the device by `mats`
-// (orders up to nmax, at most 8192).  work: see gj_work_bytes.
+// (orders up to nmax, at most 8192).  work: see gj_work_bytes.  With tp set,
+// the trailing updates are timed on tp's counters.
 hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int batch, int nmax,
-                     double* work) {
+                     double* work, qax_problem* tp) {
   if (nmax > 8192) return hipErrorInvalidValue;
   double2* W = (double2*)work;
   int32_t* piv = (int32_t*)(W + (int64_t)GJB * nmax * batch);
@@ -680,8 +682,10 @@ hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int bat
     gj_factor_panel(s, (double2*)pool, d_mats, batch, nmax, k0, GJB, piv, Wn);
     hipLaunchKernelGGL(gjb_swap_copy_kernel, dim3((nmax + 255) / 256, batch), dim3(256), 0, s,
                        d_mats, (double2*)pool, k0, piv, nmax, W);
+    if (tp) timing_begin(tp, QAX_K_INVERT_UPDATE);
     hipLaunchKernelGGL(gjm_update_kernel, dim3(tiles, tiles, batch), dim3(256), 0, s, d_mats,
                        (double2*)pool, k0, W, nmax);
+    if (tp) timing_end(tp, QAX_K_INVERT_UPDATE);
   }
   hipLaunchKernelGGL(gj_unpivot_kernel, dim3((nmax + 255) / 256, batch), dim3(256), 0, s, d_mats,
                      (double2*)pool, piv, nmax);
@@ -713,7 +717,7 @@ hipError_t launch_invert_blocks(qax_problem* p, double* work) {
   e = hipMemcpyAsync(d_md, md.data(), nbk * sizeof(MatDesc), hipMemcpyHostToDevice, p->stream);
   if (e != hipSuccess) return e;
   timing_begin(p, QAX_K_INVERT);
-  e = gj_invert(p->stream, p->d_Binv, d_md, nbk, nmax, w2);
+  e = gj_invert(p->stream, p->d_Binv, d_md, nbk, nmax, w2, p);
   timing_end(p, QAX_K_INVERT);
   if (e != hipSuccess) return e;
   return launch_convert_f32(p->stream, p->d_Binv, p->d_Binv32, p->block_elems * 2);
@@ -812,7 +816,7 @@ hipError_t launch_dense_solve(qax_problem* p, double* A, const double* b, int nr
   double* w2 = (double*)((char*)work + 256);
   hipError_t e = hipMemcpyAsync(d_md, &md, sizeof(MatDesc), hipMemcpyHostToDevice, p->stream);
   if (e != hipSuccess) return e;
-  e = gj_invert(p->stream, A, d_md, 1, (int)p->N, w2);
+  e = gj_invert(p->stream, A, d_md, 1, (int)p->N, w2, nullptr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(dense_matvec_kernel, dim3((unsigned)((p->N + 3) / 4), (unsigned)nrhs),
                      dim3(256), 0, p->stream, (const double2*)A, p->N, (const double2*)b, nrhs,
