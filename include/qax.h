@@ -193,6 +193,48 @@ qax_status qax_set_timing(qax_problem* p, int32_t enable);
  * timing was enabled. */
 qax_status qax_timing(const qax_problem* p, int32_t kernel, int64_t* launches, double* total_ms);
 
+/* Autotuner (the batching pattern's tile and schedule choices).  Tunable:
+ *  - pair sum, per precision: targets per workgroup, which is also the source
+ *    tile staged in LDS (128, 256, 512), and the number of workgroups per
+ *    compute unit that the split of the source bodies into chunks aims at
+ *    (4, 8, 16; sets how many partial sums each target row gets); with
+ *    several right-hand sides, right-hand sides per pass (1 ... 16);
+ *  - block apply with one right-hand side, per storage precision: complex
+ *    entries per lane and load (1, 2; 4 for the FP32 copy).
+ * Every candidate is timed on this problem's own data (HIP events, the
+ * fastest of a few launches after a warm-up) and the fastest is kept for the
+ * handle until the next qax_autotune.  Results do not depend on the choices
+ * beyond the order of floating-point additions.
+ * nrhs_max: largest number of right-hand sides to tune for (1 ... 1024).
+ * cache_path: text file of earlier results (NULL: none); a line whose device
+ * and problem signature (N, bodies, problems, largest block, nrhs_max) match
+ * is used instead of timing, and new results are written back.
+ * Requires qax_build; the block-apply part needs qax_assemble_self (skipped
+ * before it).  Errors: QAX_ERR_ARG, QAX_ERR_STATE, QAX_ERR_DEVICE. */
+qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char* cache_path);
+
+typedef struct {
+  int32_t tuned;              /* 1 once qax_autotune has run on this handle   */
+  int32_t from_cache;         /* 1 if the last choices came from cache_path   */
+  int32_t pair_tpb[2];        /* [0] FP64, [1] FP32 pair sum: workgroup size  */
+  int32_t pair_slot_mult[2];  /* workgroups per CU of the source-chunk split  */
+  int32_t pair_nrc[2][4];     /* RHS per pass for nrhs 2-4, 5-8, 9-16, > 16   */
+  int32_t gemv_vec[2];        /* block apply, 1 RHS: [0] FP64, [1] FP32 copy  */
+  double pair_ms[2];          /* chosen single-RHS pair sum, ms (timed runs)  */
+  double default_pair_ms[2];  /* the built-in default choice, ms             */
+} qax_tuning_info;
+
+/* Current launch choices (defaults before any qax_autotune). */
+qax_status qax_tuning(const qax_problem* p, qax_tuning_info* out);
+
+/* Set the launch choices by hand (pair_tpb, pair_slot_mult, pair_nrc,
+ * gemv_vec of `in`; the other fields are ignored).  Requires qax_build.
+ * QAX_ERR_ARG if a choice is not one the kernels support (pair_tpb 128, 256
+ * or 512; pair_slot_mult 1 ... 64; pair_nrc 1, 2, 4, 8 (FP64) or ... 16
+ * (FP32) with the LDS of the workgroup within 64 KB; gemv_vec 1, 2 (FP64) or
+ * 1, 2, 4 (FP32)). */
+qax_status qax_set_tuning(qax_problem* p, const qax_tuning_info* in);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,6 +13,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <string>
@@ -333,14 +334,8 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
                         hipMemcpyHostToDevice, p->stream), "copy blocks");
   QCHECK(launch_build_nodes(p), "build_nodes");
   const int cus = cu_count(p->device);
-  plan_pair_sum(p, QAX_FP64, cus);
-  plan_pair_sum(p, QAX_MIXED, cus);
-  QCHECK(hipMalloc(&p->d_tasks64, sizeof(PairTask) * p->tasks64.size()), "alloc tasks");
-  QCHECK(hipMalloc(&p->d_tasks32, sizeof(PairTask) * p->tasks32.size()), "alloc tasks");
-  QCHECK(hipMemcpyAsync(p->d_tasks64, p->tasks64.data(), sizeof(PairTask) * p->tasks64.size(),
-                        hipMemcpyHostToDevice, p->stream), "copy tasks");
-  QCHECK(hipMemcpyAsync(p->d_tasks32, p->tasks32.data(), sizeof(PairTask) * p->tasks32.size(),
-                        hipMemcpyHostToDevice, p->stream), "copy tasks");
+  QCHECK(upload_pair_plan(p, QAX_FP64, cus), "pair-sum plan");
+  QCHECK(upload_pair_plan(p, QAX_MIXED, cus), "pair-sum plan");
   qax_status st = sync(p, "qax_build");
   if (st != QAX_OK) return st;
   p->state = 1;
@@ -766,5 +761,277 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
   }
   if (result != QAX_OK)
     return fail(p, QAX_ERR_NOCONV, "qax_solve: tolerance not reached within maxit iterations");
+  return QAX_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+namespace {
+
+// Median-free timing: the fastest of `reps` launches after one warm-up.
+template <typename F>
+static double time_best(qax_problem* p, int reps, F&& launch, hipError_t* err) {
+  hipEvent_t a = nullptr, b = nullptr;
+  *err = hipEventCreate(&a);
+  if (*err == hipSuccess) *err = hipEventCreate(&b);
+  double best = 1e300;
+  if (*err == hipSuccess) *err = launch();
+  if (*err == hipSuccess) *err = hipStreamSynchronize(p->stream);
+  for (int r = 0; r < reps && *err == hipSuccess; ++r) {
+    *err = hipEventRecord(a, p->stream);
+    if (*err == hipSuccess) *err = launch();
+    if (*err == hipSuccess) *err = hipEventRecord(b, p->stream);
+    if (*err == hipSuccess) *err = hipEventSynchronize(b);
+    float ms = 0.0f;
+    if (*err == hipSuccess) *err = hipEventElapsedTime(&ms, a, b);
+    if (*err == hipSuccess) best = std::min(best, (double)ms);
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return best;
+}
+
+static std::string tune_key(qax_problem* p, int nrhs_max) {
+  hipDeviceProp_t prop;
+  std::string dev = "unknown";
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+    dev = prop.gcnArchName;
+    dev += "/" + std::to_string(prop.multiProcessorCount) + "cu";
+  }
+  int nmax = 0;
+  for (auto& b : p->hblocks) nmax = std::max(nmax, b.n);
+  for (char& c : dev)
+    if (c == ' ' || c == '|') c = '_';
+  return "qax-tune v1 dev=" + dev + " N=" + std::to_string(p->N) + " bodies=" +
+         std::to_string(p->n_bodies) + " problems=" + std::to_string(p->n_problems) +
+         " nmax=" + std::to_string(nmax) + " nrhs_max=" + std::to_string(nrhs_max) +
+         " assembled=" + std::to_string(p->state >= 2 ? 1 : 0);
+}
+
+static std::string tune_value(const qax::Tune& t) {
+  char buf[512];
+  std::snprintf(buf, sizeof(buf),
+                "pair_tpb=%d,%d pair_mult=%d,%d pair_nrc=%d,%d,%d,%d;%d,%d,%d,%d gemv_vec=%d,%d "
+                "pair_ms=%.6g,%.6g default_ms=%.6g,%.6g",
+                t.pair_tpb[0], t.pair_tpb[1], t.pair_mult[0], t.pair_mult[1], t.pair_nrc[0][0],
+                t.pair_nrc[0][1], t.pair_nrc[0][2], t.pair_nrc[0][3], t.pair_nrc[1][0],
+                t.pair_nrc[1][1], t.pair_nrc[1][2], t.pair_nrc[1][3], t.gemv_vec[0], t.gemv_vec[1],
+                t.pair_ms[0], t.pair_ms[1], t.default_pair_ms[0], t.default_pair_ms[1]);
+  return buf;
+}
+
+static int clamp_nrc(int prec, int tpb, int nrc) {
+  while (nrc > 1 && !pair_config_ok(prec, tpb, nrc)) nrc /= 2;
+  return nrc;
+}
+
+static bool parse_tune(const std::string& v, qax::Tune& t) {
+  qax::Tune o;
+  const int n = std::sscanf(v.c_str(),
+                            "pair_tpb=%d,%d pair_mult=%d,%d pair_nrc=%d,%d,%d,%d;%d,%d,%d,%d "
+                            "gemv_vec=%d,%d pair_ms=%lf,%lf default_ms=%lf,%lf",
+                            &o.pair_tpb[0], &o.pair_tpb[1], &o.pair_mult[0], &o.pair_mult[1],
+                            &o.pair_nrc[0][0], &o.pair_nrc[0][1], &o.pair_nrc[0][2],
+                            &o.pair_nrc[0][3], &o.pair_nrc[1][0], &o.pair_nrc[1][1],
+                            &o.pair_nrc[1][2], &o.pair_nrc[1][3], &o.gemv_vec[0], &o.gemv_vec[1],
+                            &o.pair_ms[0], &o.pair_ms[1], &o.default_pair_ms[0],
+                            &o.default_pair_ms[1]);
+  if (n != 18) return false;
+  for (int pi = 0; pi < 2; ++pi) {
+    const int prec = pi == 0 ? QAX_FP64 : QAX_MIXED;
+    if (!pair_config_ok(prec, o.pair_tpb[pi], 1) || o.pair_mult[pi] < 1 || o.pair_mult[pi] > 64)
+      return false;
+    for (int c = 0; c < 4; ++c) {
+      o.pair_nrc[pi][c] = clamp_nrc(prec, o.pair_tpb[pi], o.pair_nrc[pi][c]);
+      if (!pair_config_ok(prec, o.pair_tpb[pi], o.pair_nrc[pi][c])) return false;
+    }
+  }
+  if (o.gemv_vec[0] != 1 && o.gemv_vec[0] != 2) return false;
+  if (o.gemv_vec[1] != 1 && o.gemv_vec[1] != 2 && o.gemv_vec[1] != 4) return false;
+  t = o;
+  return true;
+}
+
+static std::vector<std::string> read_lines(const char* path) {
+  std::vector<std::string> out;
+  if (!path) return out;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return out;
+  char buf[2048];
+  while (std::fgets(buf, sizeof(buf), f)) {
+    std::string s(buf);
+    while (!s.empty() && (s.back() == '\n' || s.back() == '\r')) s.pop_back();
+    if (!s.empty()) out.push_back(s);
+  }
+  std::fclose(f);
+  return out;
+}
+
+}  // namespace
+
+extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char* cache_path) {
+  if (!p) return QAX_ERR_ARG;
+  if (p->state < 1) return fail(p, QAX_ERR_STATE, "qax_autotune: call qax_build first");
+  if (nrhs_max < 1 || nrhs_max > 1024) return fail(p, QAX_ERR_ARG, "qax_autotune: nrhs_max out of range");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  const int cus = cu_count(p->device);
+  const std::string key = tune_key(p, nrhs_max);
+  // cached result for this device and problem signature
+  std::vector<std::string> lines = read_lines(cache_path);
+  for (const std::string& l : lines) {
+    const size_t bar = l.find(" | ");
+    if (bar == std::string::npos || l.compare(0, bar, key) != 0) continue;
+    qax::Tune t;
+    if (parse_tune(l.substr(bar + 3), t)) {
+      t.tuned = true;
+      t.from_cache = true;
+      p->tune = t;
+      QCHECK(upload_pair_plan(p, QAX_FP64, cus), "pair-sum plan");
+      QCHECK(upload_pair_plan(p, QAX_MIXED, cus), "pair-sum plan");
+      return QAX_OK;
+    }
+  }
+  const bool was_timing = p->timing;
+  p->timing = false;
+  QBUF(mu, double, "tune_mu", (size_t)p->N * nrhs_max * 16);
+  QBUF(out, double, "tune_out", (size_t)p->N * nrhs_max * 16);
+  QCHECK(hipMemsetAsync(mu, 0, (size_t)p->N * nrhs_max * 16, p->stream), "zero");
+  qax::Tune t = p->tune;
+  const qax::Tune defaults;
+  hipError_t err = hipSuccess;
+  for (int pi = 0; pi < 2; ++pi) {
+    const int prec = pi == 0 ? QAX_FP64 : QAX_MIXED;
+    auto run = [&](int nrhs) -> hipError_t {
+      const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;
+      qax_status s = QAX_OK;
+      double* part = (double*)dbuf(p, "pair_partial", (size_t)slots * p->N * nrhs * 16, &s);
+      if (!part) return hipErrorOutOfMemory;
+      return launch_pair_sum(p, prec, mu, out, nrhs, part, false);
+    };
+    // workgroup size and source-chunk schedule, one right-hand side
+    double best = 1e300, dflt = 0.0;
+    int btpb = t.pair_tpb[pi], bmult = t.pair_mult[pi];
+    for (int tpb : {128, 256, 512}) {
+      for (int mult : {4, 8, 16}) {
+        p->tune.pair_tpb[pi] = tpb;
+        p->tune.pair_mult[pi] = mult;
+        QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
+        const double ms = time_best(p, 2, [&] { return run(1); }, &err);
+        QCHECK(err, "autotune pair sum");
+        if (tpb == defaults.pair_tpb[pi] && mult == defaults.pair_mult[pi]) dflt = ms;
+        if (ms < best) {
+          best = ms;
+          btpb = tpb;
+          bmult = mult;
+        }
+      }
+    }
+    p->tune.pair_tpb[pi] = t.pair_tpb[pi] = btpb;
+    p->tune.pair_mult[pi] = t.pair_mult[pi] = bmult;
+    for (int c = 0; c < 4; ++c)
+      p->tune.pair_nrc[pi][c] = t.pair_nrc[pi][c] = clamp_nrc(prec, btpb, t.pair_nrc[pi][c]);
+    t.pair_ms[pi] = best;
+    t.default_pair_ms[pi] = dflt;
+    QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
+    // right-hand sides per pass, for each class that nrhs_max reaches
+    const int lo[4] = {2, 5, 9, 17}, rep[4] = {4, 8, 16, 64};
+    for (int c = 0; c < 4; ++c) {
+      if (nrhs_max < lo[c]) continue;
+      const int nrhs = std::min(nrhs_max, rep[c]);
+      double bc = 1e300;
+      int bn = t.pair_nrc[pi][c];
+      for (int nrc : {1, 2, 4, 8, 16}) {
+        if (!pair_config_ok(prec, btpb, nrc) || nrc > 2 * nrhs) continue;
+        p->tune.pair_nrc[pi][c] = nrc;
+        const double ms = time_best(p, 1, [&] { return run(nrhs); }, &err);
+        QCHECK(err, "autotune pair sum (several right-hand sides)");
+        if (ms < bc) {
+          bc = ms;
+          bn = nrc;
+        }
+      }
+      p->tune.pair_nrc[pi][c] = t.pair_nrc[pi][c] = bn;
+    }
+  }
+  // block apply, one right-hand side (after assembly)
+  if (p->state >= 2) {
+    for (int pi = 0; pi < 2; ++pi) {
+      const int prec = pi == 0 ? QAX_FP64 : QAX_MIXED;
+      double best = 1e300;
+      int bv = t.gemv_vec[pi];
+      for (int vec : {1, 2, 4}) {
+        if (pi == 0 && vec == 4) continue;
+        p->tune.gemv_vec[pi] = vec;
+        const double ms = time_best(p, 3, [&] { return launch_block_apply(p, 1, prec, mu, out, 1, false); }, &err);
+        QCHECK(err, "autotune block apply");
+        if (ms < best) {
+          best = ms;
+          bv = vec;
+        }
+      }
+      p->tune.gemv_vec[pi] = t.gemv_vec[pi] = bv;
+    }
+  }
+  p->timing = was_timing;
+  t.tuned = true;
+  t.from_cache = false;
+  p->tune = t;
+  if (cache_path) {
+    std::vector<std::string> keep;
+    for (const std::string& l : lines)
+      if (l.compare(0, key.size() + 3, key + " | ") != 0) keep.push_back(l);
+    keep.push_back(key + " | " + tune_value(t));
+    FILE* f = std::fopen(cache_path, "w");
+    if (f) {
+      for (const std::string& l : keep) std::fprintf(f, "%s\n", l.c_str());
+      std::fclose(f);
+    }
+  }
+  return sync(p, "qax_autotune");
+}
+
+extern "C" qax_status qax_tuning(const qax_problem* pc, qax_tuning_info* out) {
+  if (!pc || !out) return QAX_ERR_ARG;
+  const qax::Tune& t = pc->tune;
+  out->tuned = t.tuned ? 1 : 0;
+  out->from_cache = t.from_cache ? 1 : 0;
+  for (int pi = 0; pi < 2; ++pi) {
+    out->pair_tpb[pi] = t.pair_tpb[pi];
+    out->pair_slot_mult[pi] = t.pair_mult[pi];
+    for (int c = 0; c < 4; ++c) out->pair_nrc[pi][c] = t.pair_nrc[pi][c];
+    out->gemv_vec[pi] = t.gemv_vec[pi];
+    out->pair_ms[pi] = t.pair_ms[pi];
+    out->default_pair_ms[pi] = t.default_pair_ms[pi];
+  }
+  return QAX_OK;
+}
+
+extern "C" qax_status qax_set_tuning(qax_problem* p, const qax_tuning_info* in) {
+  if (!p || !in) return QAX_ERR_ARG;
+  if (p->state < 1) return fail(p, QAX_ERR_STATE, "qax_set_tuning: call qax_build first");
+  qax::Tune t = p->tune;
+  for (int pi = 0; pi < 2; ++pi) {
+    const int prec = pi == 0 ? QAX_FP64 : QAX_MIXED;
+    if (!pair_config_ok(prec, in->pair_tpb[pi], 1) || in->pair_slot_mult[pi] < 1 ||
+        in->pair_slot_mult[pi] > 64)
+      return fail(p, QAX_ERR_ARG, "qax_set_tuning: unsupported pair-sum choice");
+    for (int c = 0; c < 4; ++c)
+      if (!pair_config_ok(prec, in->pair_tpb[pi], in->pair_nrc[pi][c]))
+        return fail(p, QAX_ERR_ARG, "qax_set_tuning: unsupported right-hand sides per pass");
+    t.pair_tpb[pi] = in->pair_tpb[pi];
+    t.pair_mult[pi] = in->pair_slot_mult[pi];
+    for (int c = 0; c < 4; ++c) t.pair_nrc[pi][c] = in->pair_nrc[pi][c];
+  }
+  if ((in->gemv_vec[0] != 1 && in->gemv_vec[0] != 2) ||
+      (in->gemv_vec[1] != 1 && in->gemv_vec[1] != 2 && in->gemv_vec[1] != 4))
+    return fail(p, QAX_ERR_ARG, "qax_set_tuning: unsupported block-apply choice");
+  t.gemv_vec[0] = in->gemv_vec[0];
+  t.gemv_vec[1] = in->gemv_vec[1];
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  p->tune = t;
+  const int cus = cu_count(p->device);
+  QCHECK(upload_pair_plan(p, QAX_FP64, cus), "pair-sum plan");
+  QCHECK(upload_pair_plan(p, QAX_MIXED, cus), "pair-sum plan");
   return QAX_OK;
 }

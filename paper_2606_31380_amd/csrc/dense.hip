@@ -19,11 +19,14 @@
 namespace qax {
 
 // ---------------------------------------------------------------- block apply
-template <typename MT, int NRC>
+// One wavefront per row; each lane loads VEC consecutive complex entries per
+// step (block orders are multiples of 16, so rows split evenly).
+template <typename MT, int NRC, int VEC>
 __global__ __launch_bounds__(256) void block_gemv_kernel(
     const BodyDev* __restrict__ bodies, const BlockDev* __restrict__ blocks,
     const int32_t* __restrict__ node_body, const MT* __restrict__ pool, int64_t N,
     const double2* __restrict__ v, int nrhs, double2* __restrict__ out, int accumulate) {
+  typedef MT vec_t __attribute__((ext_vector_type(2 * VEC)));
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int rc0 = blockIdx.y * NRC;
@@ -38,14 +41,19 @@ __global__ __launch_bounds__(256) void block_gemv_kernel(
   double ar[NRC], ai[NRC];
 #pragma unroll
   for (int r = 0; r < NRC; ++r) { ar[r] = 0.0; ai[r] = 0.0; }
-  for (int j = lane; j < n; j += 64) {
-    const double mr = (double)a[2 * j], mi = (double)a[2 * j + 1];
+  for (int j0 = lane * VEC; j0 < n; j0 += 64 * VEC) {
+    const vec_t av = *(const vec_t*)(a + 2 * j0);
 #pragma unroll
-    for (int r = 0; r < NRC; ++r) {
-      if (rc0 + r < nrhs) {
-        const double2 x = vb[(int64_t)j * nrhs + rc0 + r];
-        ar[r] += mr * x.x - mi * x.y;
-        ai[r] += mr * x.y + mi * x.x;
+    for (int q = 0; q < VEC; ++q) {
+      const double mr = (double)av[2 * q], mi = (double)av[2 * q + 1];
+      const int j = j0 + q;
+#pragma unroll
+      for (int r = 0; r < NRC; ++r) {
+        if (rc0 + r < nrhs) {
+          const double2 x = vb[(int64_t)j * nrhs + rc0 + r];
+          ar[r] += mr * x.x - mi * x.y;
+          ai[r] += mr * x.y + mi * x.x;
+        }
       }
     }
   }
@@ -71,11 +79,11 @@ __global__ __launch_bounds__(256) void block_gemv_kernel(
   }
 }
 
-template <typename MT, int NRC>
+template <typename MT, int NRC, int VEC>
 static void gemv_launch(qax_problem* p, const MT* pool, const double* v, double* out, int nrhs,
                         bool acc) {
   dim3 grid((unsigned)((p->N + 3) / 4), (unsigned)((nrhs + NRC - 1) / NRC));
-  hipLaunchKernelGGL((block_gemv_kernel<MT, NRC>), grid, dim3(256), 0, p->stream, p->d_bodies,
+  hipLaunchKernelGGL((block_gemv_kernel<MT, NRC, VEC>), grid, dim3(256), 0, p->stream, p->d_bodies,
                      p->d_blocks, p->d_node_body, pool, p->N, (const double2*)v, nrhs,
                      (double2*)out, acc ? 1 : 0);
 }
@@ -95,12 +103,16 @@ hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const doubl
   }
   timing_begin(p, kind);
   if (inverse && prec == QAX_MIXED) {
-    if (nrhs == 1) gemv_launch<float, 1>(p, p->d_Binv32, v, out, nrhs, accumulate);
-    else gemv_launch<float, 4>(p, p->d_Binv32, v, out, nrhs, accumulate);
+    const float* pool = p->d_Binv32;
+    if (nrhs > 1) gemv_launch<float, 4, 1>(p, pool, v, out, nrhs, accumulate);
+    else if (p->tune.gemv_vec[1] == 4) gemv_launch<float, 1, 4>(p, pool, v, out, nrhs, accumulate);
+    else if (p->tune.gemv_vec[1] == 2) gemv_launch<float, 1, 2>(p, pool, v, out, nrhs, accumulate);
+    else gemv_launch<float, 1, 1>(p, pool, v, out, nrhs, accumulate);
   } else {
     const double* pool = inverse ? p->d_Binv : p->d_B;
-    if (nrhs == 1) gemv_launch<double, 1>(p, pool, v, out, nrhs, accumulate);
-    else gemv_launch<double, 4>(p, pool, v, out, nrhs, accumulate);
+    if (nrhs > 1) gemv_launch<double, 4, 1>(p, pool, v, out, nrhs, accumulate);
+    else if (p->tune.gemv_vec[0] == 2) gemv_launch<double, 1, 2>(p, pool, v, out, nrhs, accumulate);
+    else gemv_launch<double, 1, 1>(p, pool, v, out, nrhs, accumulate);
   }
   timing_end(p, kind);
   return hipGetLastError();

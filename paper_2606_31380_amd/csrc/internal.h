@@ -61,6 +61,20 @@ struct SelfTask {
 
 }  // namespace qax
 
+namespace qax {
+// Launch choices of the tunable kernels (defaults until qax_autotune runs).
+// Index 0: FP64 pair sum / FP64 blocks, 1: FP32 pair sum / FP32 inverse copy.
+struct Tune {
+  int pair_tpb[2] = {256, 256};    // targets per workgroup (= source tile in LDS)
+  int pair_mult[2] = {8, 8};       // workgroups per CU aimed at by the source-chunk split
+  int pair_nrc[2][4] = {{4, 8, 8, 8}, {4, 8, 16, 16}};  // RHS per pass, nrhs in 2-4, 5-8, 9-16, >16
+  int gemv_vec[2] = {1, 1};        // complex elements per lane and load, one RHS
+  bool tuned = false, from_cache = false;
+  double pair_ms[2] = {0.0, 0.0}, default_pair_ms[2] = {0.0, 0.0};
+};
+inline int nrhs_class(int nrhs) { return nrhs <= 4 ? 0 : nrhs <= 8 ? 1 : nrhs <= 16 ? 2 : 3; }
+}  // namespace qax
+
 struct qax_problem {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -97,6 +111,8 @@ struct qax_problem {
   qax::PairTask* d_tasks64 = nullptr;
   qax::PairTask* d_tasks32 = nullptr;
   int32_t slots64 = 1, slots32 = 1;
+  int32_t plan_tpb[2] = {0, 0};       // workgroup size the task tables were planned for
+  qax::Tune tune;
 
   // block GEMM row tiles (several right-hand sides)
   std::vector<qax::GemmTask> gemm_tasks;
@@ -139,6 +155,10 @@ hipError_t launch_build_nodes(qax_problem* p);
 hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
                            double* partial, bool accumulate);
 void plan_pair_sum(qax_problem* p, int prec, int cu_count);
+// plan_pair_sum + device copy of the task table (synchronous).
+hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count);
+// launch choices the kernels support (LDS within 64 KB)
+bool pair_config_ok(int prec, int tpb, int nrc);
 
 // dense.hip
 hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,

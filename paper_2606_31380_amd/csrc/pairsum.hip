@@ -239,12 +239,14 @@ __global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slo
 // (balanced by node count).  Sorted by decreasing cost so that the hardware
 // dispatcher, which issues workgroups in index order, balances uneven work.
 void plan_pair_sum(qax_problem* p, int prec, int cu_count) {
-  const int tpb = 256;
+  const int pi = prec == QAX_FP64 ? 0 : 1;
+  const int tpb = p->tune.pair_tpb[pi];
+  const int64_t mult = p->tune.pair_mult[pi];
   std::vector<PairTask> tasks;
   int64_t tblocks = 0;
   for (int pr = 0; pr < p->n_problems; ++pr)
     tblocks += (p->off[p->prob_body0[pr + 1]] - p->off[p->prob_body0[pr]] + tpb - 1) / tpb;
-  int slots = (int)std::max<int64_t>(1, (8LL * cu_count + tblocks - 1) / std::max<int64_t>(tblocks, 1));
+  int slots = (int)std::max<int64_t>(1, (mult * cu_count + tblocks - 1) / std::max<int64_t>(tblocks, 1));
   slots = std::min(slots, 32);
   for (int pr = 0; pr < p->n_problems; ++pr) {
     const int b0 = (int)p->prob_body0[pr], b1 = (int)p->prob_body0[pr + 1];
@@ -294,40 +296,102 @@ void plan_pair_sum(qax_problem* p, int prec, int cu_count) {
     p->tasks32 = tasks;
     p->slots32 = slots;
   }
+  p->plan_tpb[pi] = tpb;
+}
+
+hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count) {
+  plan_pair_sum(p, prec, cu_count);
+  std::vector<PairTask>& t = prec == QAX_FP64 ? p->tasks64 : p->tasks32;
+  PairTask*& d = prec == QAX_FP64 ? p->d_tasks64 : p->d_tasks32;
+  if (d) {
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return e;
+    (void)hipFree(d);
+    d = nullptr;
+  }
+  hipError_t e = hipMalloc(&d, sizeof(PairTask) * t.size());
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(d, t.data(), sizeof(PairTask) * t.size(), hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(p->stream);
+}
+
+// LDS per workgroup: FP64 6 TPB doubles + TPB NRC complex128; FP32 2 TPB float4
+// + TPB NRC complex64
+bool pair_config_ok(int prec, int tpb, int nrc) {
+  if (tpb != 128 && tpb != 256 && tpb != 512) return false;
+  if (prec == QAX_FP64) {
+    if (nrc != 1 && nrc != 2 && nrc != 4 && nrc != 8) return false;
+    return (size_t)tpb * (48 + 16 * nrc) <= 65536;
+  }
+  if (nrc != 1 && nrc != 2 && nrc != 4 && nrc != 8 && nrc != 16) return false;
+  return (size_t)tpb * (32 + 8 * nrc) <= 65536;
 }
 
 template <int TPB, int NRC>
 static void launch_f64(qax_problem* p, const double* mu, int nrhs, double* partial) {
-  dim3 grid((unsigned)p->tasks64.size(), (unsigned)((nrhs + NRC - 1) / NRC));
-  hipLaunchKernelGGL((pair_sum_f64_kernel<TPB, NRC>), grid, dim3(TPB), 0, p->stream, p->d_tasks64,
-                     p->d_bodies, p->d_node_body, p->d_pos, p->d_aw, p->N, (const double2*)mu, nrhs,
-                     (double2*)partial);
+  if constexpr ((size_t)TPB * (48 + 16 * NRC) <= 65536) {
+    dim3 grid((unsigned)p->tasks64.size(), (unsigned)((nrhs + NRC - 1) / NRC));
+    hipLaunchKernelGGL((pair_sum_f64_kernel<TPB, NRC>), grid, dim3(TPB), 0, p->stream, p->d_tasks64,
+                       p->d_bodies, p->d_node_body, p->d_pos, p->d_aw, p->N, (const double2*)mu,
+                       nrhs, (double2*)partial);
+  }
 }
 
 template <int TPB, int NRC>
 static void launch_f32(qax_problem* p, const double* mu, int nrhs, double* partial) {
-  dim3 grid((unsigned)p->tasks32.size(), (unsigned)((nrhs + NRC - 1) / NRC));
-  hipLaunchKernelGGL((pair_sum_f32_kernel<TPB, NRC>), grid, dim3(TPB), 0, p->stream, p->d_tasks32,
-                     p->d_bodies, p->d_node_body, p->d_pos, (const float4*)p->d_loc32,
-                     (const float4*)p->d_aw32, p->N, (const double2*)mu, nrhs, (double2*)partial);
+  if constexpr ((size_t)TPB * (32 + 8 * NRC) <= 65536) {
+    dim3 grid((unsigned)p->tasks32.size(), (unsigned)((nrhs + NRC - 1) / NRC));
+    hipLaunchKernelGGL((pair_sum_f32_kernel<TPB, NRC>), grid, dim3(TPB), 0, p->stream,
+                       p->d_tasks32, p->d_bodies, p->d_node_body, p->d_pos,
+                       (const float4*)p->d_loc32, (const float4*)p->d_aw32, p->N,
+                       (const double2*)mu, nrhs, (double2*)partial);
+  }
+}
+
+template <int TPB>
+static void launch_f64_nrc(qax_problem* p, int nrc, const double* mu, int nrhs, double* partial) {
+  switch (nrc) {
+    case 1: launch_f64<TPB, 1>(p, mu, nrhs, partial); break;
+    case 2: launch_f64<TPB, 2>(p, mu, nrhs, partial); break;
+    case 4: launch_f64<TPB, 4>(p, mu, nrhs, partial); break;
+    default: launch_f64<TPB, 8>(p, mu, nrhs, partial); break;
+  }
+}
+
+template <int TPB>
+static void launch_f32_nrc(qax_problem* p, int nrc, const double* mu, int nrhs, double* partial) {
+  switch (nrc) {
+    case 1: launch_f32<TPB, 1>(p, mu, nrhs, partial); break;
+    case 2: launch_f32<TPB, 2>(p, mu, nrhs, partial); break;
+    case 4: launch_f32<TPB, 4>(p, mu, nrhs, partial); break;
+    case 8: launch_f32<TPB, 8>(p, mu, nrhs, partial); break;
+    default: launch_f32<TPB, 16>(p, mu, nrhs, partial); break;
+  }
 }
 
 // partial: slots x N x nrhs complex128 workspace; out = pair sum, or
-// out += pair sum when accumulate is set.
+// out += pair sum when accumulate is set.  The workgroup size is the one the
+// task table was planned with; right-hand sides per pass from the tuning
+// (clamped to a supported configuration).
 hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
                            double* partial, bool accumulate) {
   const bool f64 = prec == QAX_FP64;
+  const int pi = f64 ? 0 : 1;
   const int kind = f64 ? QAX_K_PAIRSUM_FP64 : QAX_K_PAIRSUM_FP32;
+  const int tpb = p->tune.pair_tpb[pi];
+  int nrc = nrhs == 1 ? 1 : p->tune.pair_nrc[pi][nrhs_class(nrhs)];
+  while (nrc > 1 && !pair_config_ok(prec, tpb, nrc)) nrc /= 2;
+  if (!pair_config_ok(prec, tpb, nrc) || p->plan_tpb[pi] != tpb) return hipErrorInvalidConfiguration;
   timing_begin(p, kind);
   if (f64) {
-    if (nrhs == 1) launch_f64<256, 1>(p, mu, nrhs, partial);
-    else if (nrhs <= 4) launch_f64<256, 4>(p, mu, nrhs, partial);
-    else launch_f64<256, 8>(p, mu, nrhs, partial);
+    if (tpb == 128) launch_f64_nrc<128>(p, nrc, mu, nrhs, partial);
+    else if (tpb == 256) launch_f64_nrc<256>(p, nrc, mu, nrhs, partial);
+    else launch_f64_nrc<512>(p, nrc, mu, nrhs, partial);
   } else {
-    if (nrhs == 1) launch_f32<256, 1>(p, mu, nrhs, partial);
-    else if (nrhs <= 4) launch_f32<256, 4>(p, mu, nrhs, partial);
-    else if (nrhs <= 8) launch_f32<256, 8>(p, mu, nrhs, partial);
-    else launch_f32<256, 16>(p, mu, nrhs, partial);
+    if (tpb == 128) launch_f32_nrc<128>(p, nrc, mu, nrhs, partial);
+    else if (tpb == 256) launch_f32_nrc<256>(p, nrc, mu, nrhs, partial);
+    else launch_f32_nrc<512>(p, nrc, mu, nrhs, partial);
   }
   timing_end(p, kind);
   hipError_t e = hipGetLastError();

@@ -1,14 +1,16 @@
 """Fixed sequence of library calls on the 27-body lattice workload, for
 hardware-counter and kernel-trace runs under rocprofv3:
 
-    rocprofv3 --pmc FETCH_SIZE -d out -- python3 -m paper_2606_31380_amd.profile_workload
+    rocprofv3 --pmc FETCH_SIZE -d out -- python3 -m paper_2606_31380_amd.profile_workload [tune_cache]
 
 It first runs one plain elementwise kernel of known traffic (y = 2 x over
 2^27 doubles: 1 GiB read, 1 GiB written) so that the memory counters can be
-scaled, then: node build, self-block assembly and inversion, one FP64 and one
-FP32 pair sum, block applies (B and B^-1 in FP64, B^-1 in FP32; one and eight
-right-hand sides), one eight-column FP32 pair sum and the far field on
-the 200 x 200 direction grid.  Every step prints a line.
+scaled, then: node build, self-block assembly and inversion, the autotuner
+(as bench.py runs it; with a cache file written by `bench.py --tune-cache`
+the launch choices are those of the benchmark, not re-timed under the
+profiler), one FP64 and one FP32 pair sum, block applies (B and B^-1 in FP64,
+B^-1 in FP32; one and eight right-hand sides), one eight-column FP32 pair sum
+and the far field on the 200 x 200 direction grid.  Every step prints a line.
 """
 from __future__ import annotations
 
@@ -18,7 +20,7 @@ import sys
 import numpy as np
 
 
-def main() -> int:
+def main(tune_cache=None) -> int:
     import torch
 
     from paper_2606_31380_amd import qax
@@ -42,6 +44,8 @@ def main() -> int:
         print(f"build: N = {N}", flush=True)
         qax.qax_assemble_self(h)
         print("assemble_self (assembly + inversion)", flush=True)
+        qax.qax_autotune(h, nrhs_max=1, cache_path=tune_cache)
+        print(f"autotune: {qax.qax_tuning(h)}", flush=True)
         g = torch.Generator(device="cpu").manual_seed(0)
         v1 = torch.randn(N, dtype=torch.complex128, generator=g).to(dev)
         o1 = torch.zeros_like(v1)
@@ -77,4 +81,4 @@ def main() -> int:
 
 
 if __name__ == "__main__":
-    sys.exit(main())
+    sys.exit(main(sys.argv[1] if len(sys.argv) > 1 else None))

@@ -33,6 +33,13 @@ class qax_info(C.Structure):
                 ("t_setup_s", C.c_double), ("t_solve_s", C.c_double)]
 
 
+class qax_tuning_info(C.Structure):
+    _fields_ = [("tuned", C.c_int32), ("from_cache", C.c_int32), ("pair_tpb", C.c_int32 * 2),
+                ("pair_slot_mult", C.c_int32 * 2), ("pair_nrc", (C.c_int32 * 4) * 2),
+                ("gemv_vec", C.c_int32 * 2), ("pair_ms", C.c_double * 2),
+                ("default_pair_ms", C.c_double * 2)]
+
+
 class QaxError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
@@ -43,7 +50,7 @@ _LIB = None
 EXPORTS = ["qax_create", "qax_destroy", "qax_last_error", "qax_build", "qax_size", "qax_nodes",
            "qax_assemble_self", "qax_self_block", "qax_pair_sum", "qax_block_apply", "qax_apply",
            "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes",
-           "qax_set_timing", "qax_timing"]
+           "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning"]
 (QAX_K_PAIRSUM_FP64, QAX_K_PAIRSUM_FP32, QAX_K_BLOCK_APPLY, QAX_K_SELF_ASSEMBLY, QAX_K_INVERT,
  QAX_K_INVERT_UPDATE, QAX_K_BLOCK_APPLY_F32) = range(7)
 KERNEL_NAMES = ["pair_sum_fp64", "pair_sum_fp32", "block_apply", "self_assembly", "invert",
@@ -82,6 +89,9 @@ def lib():
         "qax_modal_modes": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, d, i32, vp, vp]),
         "qax_set_timing": (C.c_int, [vp, i32]),
         "qax_timing": (C.c_int, [vp, i32, C.POINTER(i64), pd]),
+        "qax_autotune": (C.c_int, [vp, i32, C.c_char_p]),
+        "qax_tuning": (C.c_int, [vp, C.POINTER(qax_tuning_info)]),
+        "qax_set_tuning": (C.c_int, [vp, C.POINTER(qax_tuning_info)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -214,6 +224,36 @@ def qax_timing(h, kernel):
     ms = C.c_double()
     _check(h, lib().qax_timing(h, int(kernel), C.byref(n), C.byref(ms)))
     return n.value, ms.value
+
+
+def qax_autotune(h, nrhs_max=1, cache_path=None):
+    cp = None if cache_path is None else os.fsencode(cache_path)
+    _check(h, lib().qax_autotune(h, int(nrhs_max), cp))
+
+
+def qax_tuning(h):
+    t = qax_tuning_info()
+    _check(h, lib().qax_tuning(h, C.byref(t)))
+    return {"tuned": bool(t.tuned), "from_cache": bool(t.from_cache),
+            "pair_tpb": {"fp64": t.pair_tpb[0], "fp32": t.pair_tpb[1]},
+            "pair_slot_mult": {"fp64": t.pair_slot_mult[0], "fp32": t.pair_slot_mult[1]},
+            "pair_nrc": {"fp64": list(t.pair_nrc[0]), "fp32": list(t.pair_nrc[1])},
+            "gemv_vec": {"fp64": t.gemv_vec[0], "fp32": t.gemv_vec[1]},
+            "pair_ms": {"fp64": t.pair_ms[0], "fp32": t.pair_ms[1]},
+            "default_pair_ms": {"fp64": t.default_pair_ms[0], "fp32": t.default_pair_ms[1]}}
+
+
+def qax_set_tuning(h, pair_tpb=(256, 256), pair_slot_mult=(8, 8),
+                   pair_nrc=((4, 8, 8, 8), (4, 8, 16, 16)), gemv_vec=(1, 1)):
+    """Set the launch choices by hand ([FP64, FP32] pairs, as qax_tuning reports)."""
+    t = qax_tuning_info()
+    for i in range(2):
+        t.pair_tpb[i] = int(pair_tpb[i])
+        t.pair_slot_mult[i] = int(pair_slot_mult[i])
+        for c in range(4):
+            t.pair_nrc[i][c] = int(pair_nrc[i][c])
+        t.gemv_vec[i] = int(gemv_vec[i])
+    _check(h, lib().qax_set_tuning(h, C.byref(t)))
 
 
 class Problem:
