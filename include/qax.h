@@ -173,6 +173,15 @@ qax_status qax_modal_modes(qax_problem* p, int32_t n_pts, const double* d_r, con
                            const double* d_c, const double* d_chim1, const double* d_rmrt,
                            double k, int32_t nmax, void* d_A, void* d_B);
 
+/* Captured solver steps.  With enable != 0 (the default) qax_solve captures
+ * each Arnoldi step (block apply, pair sum, two Gram-Schmidt passes, norm,
+ * Givens update, next basis vector, convergence count) once per step index
+ * into a HIP graph and replays it; the graphs stay with the handle while the
+ * buffers, sizes and launch choices are unchanged.  enable = 0 enqueues the
+ * same kernels one by one (identical results).  While kernel timing is on,
+ * the steps are always enqueued one by one. */
+qax_status qax_set_graphs(qax_problem* p, int32_t enable);
+
 /* Kernel timing (instrumentation).  When enabled, each launch of the kernels
  * below is bracketed by HIP events recorded on the handle's stream and its
  * duration is accumulated per kernel kind.  Disabled by default. */

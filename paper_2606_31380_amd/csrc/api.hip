@@ -179,6 +179,13 @@ extern "C" void qax_destroy(qax_problem* p) {
   (void)hipSetDevice(p->device);
   if (p->stream) (void)hipStreamSynchronize(p->stream);
   else (void)hipDeviceSynchronize();
+  for (hipGraphExec_t g : p->graphs)
+    if (g) (void)hipGraphExecDestroy(g);
+  p->graphs.clear();
+  if (p->h_flags) (void)hipHostFree(p->h_flags);
+  p->h_flags = nullptr;
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  p->cap_stream = nullptr;
   free_geometry(p);
   collect_timing(p);
   for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
@@ -197,6 +204,12 @@ static qax_status sync(qax_problem* p, const char* what) {
   qax_status st = hip_check(p, hipStreamSynchronize(p->stream), what);
   if (st == QAX_OK && !p->pending.empty()) collect_timing(p);
   return st;
+}
+
+extern "C" qax_status qax_set_graphs(qax_problem* p, int32_t enable) {
+  if (!p) return QAX_ERR_ARG;
+  p->use_graphs = enable != 0;
+  return QAX_OK;
 }
 
 extern "C" qax_status qax_set_timing(qax_problem* p, int32_t enable) {
@@ -385,6 +398,7 @@ extern "C" qax_status qax_assemble_self(qax_problem* p, double* t_setup_s) {
   auto t1 = std::chrono::steady_clock::now();
   if (t_setup_s) *t_setup_s = std::chrono::duration<double>(t1 - t0).count();
   p->state = 2;
+  ++p->generation;
   return QAX_OK;
 }
 
@@ -527,54 +541,6 @@ extern "C" qax_status qax_solve_dense(qax_problem* p, const double* dirs, int32_
 }
 
 // ---------------------------------------------------------------- GMRES
-namespace {
-
-struct SegGmres {
-  int m;                       // restart length
-  std::vector<cplx> H;         // (m+1) x m, column-major by iteration
-  std::vector<cplx> cs, sn, g;
-  double beta = 0.0;
-  bool frozen = false;
-};
-
-void givens_step(SegGmres& S, int j, const cplx* hcol /* j+2 entries */) {
-  cplx* col = &S.H[(size_t)j * (S.m + 1)];
-  for (int i = 0; i <= j + 1; ++i) col[i] = hcol[i];
-  for (int i = 0; i < j; ++i) {
-    const cplx t = S.cs[i] * col[i] + S.sn[i] * col[i + 1];
-    col[i + 1] = -std::conj(S.sn[i]) * col[i] + S.cs[i] * col[i + 1];
-    col[i] = t;
-  }
-  const double aa = std::abs(col[j]), bb = std::abs(col[j + 1]);
-  const double den = std::hypot(aa, bb);
-  if (den == 0.0) {
-    S.cs[j] = 1.0;
-    S.sn[j] = 0.0;
-  } else if (aa == 0.0) {
-    S.cs[j] = 0.0;
-    S.sn[j] = 1.0;
-  } else {
-    S.cs[j] = aa / den;
-    S.sn[j] = (col[j] / aa) * std::conj(col[j + 1]) / den;
-  }
-  col[j] = S.cs[j] * col[j] + S.sn[j] * col[j + 1];
-  col[j + 1] = 0.0;
-  S.g[j + 1] = -std::conj(S.sn[j]) * S.g[j];
-  S.g[j] = S.cs[j] * S.g[j];
-}
-
-std::vector<cplx> back_solve(const SegGmres& S, int k) {
-  std::vector<cplx> y(k);
-  for (int i = k - 1; i >= 0; --i) {
-    cplx s = S.g[i];
-    for (int l = i + 1; l < k; ++l) s -= S.H[(size_t)l * (S.m + 1) + i] * y[l];
-    const cplx d = S.H[(size_t)i * (S.m + 1) + i];
-    y[i] = (std::abs(d) > 0) ? s / d : cplx(0.0);
-  }
-  return y;
-}
-
-}  // namespace
 
 static qax_status setup_krylov(qax_problem* p, int nrhs, int mmax, Krylov& K) {
   K.stream = p->stream;
@@ -640,23 +606,124 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
   QCHECK(launch_rhs(p, dd, nrhs, b), "rhs");
   QCHECK(hipMemsetAsync(x, 0, (size_t)vs * 8, p->stream), "zero x");
 
+  const int inner_prec = prec;
   std::vector<cplx> hh((size_t)(2 * m + 4) * nseg);
   auto fetch = [&](int rows) -> qax_status {
     QCHECK(hipMemcpyAsync(hh.data(), hd, (size_t)rows * nseg * 16, hipMemcpyDeviceToHost, p->stream),
            "copy h");
     return sync(p, "gmres");
   };
+  // least-squares state on the device
+  GivensState G;
+  {
+    QBUF(gH, double2, "kry_gH", (size_t)nseg * m * (m + 1) * 16);
+    QBUF(gcs, double, "kry_gcs", (size_t)nseg * m * 8);
+    QBUF(gsn, double2, "kry_gsn", (size_t)nseg * m * 16);
+    QBUF(gg, double2, "kry_gg", (size_t)nseg * (m + 1) * 16);
+    QBUF(gpar, double, "kry_gpar", (size_t)nseg * 16 + 256);
+    QBUF(gfz, int32_t, "kry_gfrozen", (size_t)nseg * 4 + (size_t)(m + 1) * 4);
+    QBUF(gscl, double2, "kry_gscl", (size_t)nseg * 16);
+    G.H = gH;
+    G.cs = gcs;
+    G.sn = gsn;
+    G.g = gg;
+    G.beta = gpar;
+    G.tin = gpar + nseg;
+    G.frozen = gfz;
+    G.notdone = gfz + nseg;
+    G.scl = gscl;
+  }
+  QBUF(ydev, double2, "kry_y", (size_t)m * nseg * 16);
+  // pair-sum workspace sized before any capture (no allocation inside a graph)
+  const int pslots = inner_prec == QAX_FP64 ? p->slots64 : p->slots32;
+  QBUF(ppart, double, "pair_partial", (size_t)pslots * N * nrhs * 16);
+  if (p->h_flags_n < m + 1) {
+    if (p->h_flags) (void)hipHostFree(p->h_flags);
+    p->h_flags = nullptr;
+    p->h_flags_n = 0;
+    QCHECK(hipHostMalloc((void**)&p->h_flags, (size_t)(m + 1) * 4, hipHostMallocDefault), "pinned flags");
+    p->h_flags_n = m + 1;
+  }
   // ||b|| per segment
   K.dots(b, 0, 1, b, hd);
   if ((st = fetch(1)) != QAX_OK) return st;
   std::vector<double> bnorm(nseg);
   for (int s = 0; s < nseg; ++s) bnorm[s] = std::sqrt(std::max(hh[s].real(), 0.0));
 
-  const int inner_prec = prec;
+  // One Arnoldi step j for all segments: z = M^-1 v_j, w = v_j + D_off z,
+  // classical Gram-Schmidt twice, |w|^2, the Givens update on the device,
+  // v_{j+1} = w / h_{j+1,j}, and the step's count of unconverged segments
+  // copied to pinned host memory.  Enqueued directly, or captured once per j
+  // into an executable graph and replayed.
+  double* h1 = hd;
+  double* h2 = hd + (size_t)(m + 2) * nseg * 2;
+  auto enqueue_step = [&](int j) -> hipError_t {
+    double* Vj = V + (size_t)j * vs;
+    double* Vn = V + (size_t)(j + 1) * vs;
+    hipError_t e = launch_block_apply(p, 1, inner_prec, Vj, t, nrhs, false);
+    if (e == hipSuccess) e = launch_pair_sum(p, inner_prec, t, w, nrhs, ppart, false);
+    if (e != hipSuccess) return e;
+    K.axpby(1.0, w, 1.0, Vj, w);
+    K.dots(V, vs, j + 1, w, h1);
+    K.orth(V, vs, j + 1, h1, w);
+    K.dots(V, vs, j + 1, w, h2);
+    K.orth(V, vs, j + 1, h2, w);
+    K.dots(w, 0, 1, w, h2 + (size_t)(j + 1) * nseg * 2);
+    K.givens(nseg, j, m, h1, h2, h2 + (size_t)(j + 1) * nseg * 2, G);
+    K.scale(w, (const double*)G.scl, Vn);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(p->h_flags + j, G.notdone + j, 4, hipMemcpyDeviceToHost, p->stream);
+  };
+  const bool graphs = p->use_graphs && !p->timing;
+  if (nrhs >= 4) QCHECK(ensure_gemm_tasks(p), "block GEMM tiles");
+  if (graphs) {
+    char key[512];
+    std::snprintf(key, sizeof(key), "%llu %d %d %d %d %p %p %p %p %p %p %p %p %p %p %p %p",
+                  (unsigned long long)p->generation, inner_prec, nrhs, m, nseg, (void*)V, (void*)w,
+                  (void*)t, (void*)hd, (void*)ppart, (void*)G.H, (void*)G.g, (void*)G.scl,
+                  (void*)G.notdone, (void*)p->h_flags, (void*)K.d_partial, (void*)K.d_chunks);
+    if (p->graph_key != key) {
+      for (hipGraphExec_t g : p->graphs)
+        if (g) (void)hipGraphExecDestroy(g);
+      p->graphs.clear();
+      p->graph_key = key;
+    }
+    if ((int)p->graphs.size() < m) p->graphs.resize(m, nullptr);
+  }
+  auto run_step = [&](int j) -> qax_status {
+    if (!graphs) {
+      QCHECK(enqueue_step(j), "gmres step");
+      return QAX_OK;
+    }
+    if (!p->graphs[j]) {
+      // capture on the handle's own stream (the caller's may be the legacy
+      // default stream, which cannot be captured); replays go to the caller's
+      if (!p->cap_stream)
+        QCHECK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "capture stream");
+      const hipStream_t user = p->stream;
+      QCHECK(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+      p->stream = K.stream = p->cap_stream;
+      const hipError_t e = enqueue_step(j);
+      p->stream = K.stream = user;
+      hipGraph_t gr = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(p->cap_stream, &gr);
+      if (e != hipSuccess && gr) (void)hipGraphDestroy(gr);
+      QCHECK(e, "gmres step (capture)");
+      QCHECK(e2, "end capture");
+      hipGraphExec_t ex = nullptr;
+      const hipError_t e3 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(gr);
+      QCHECK(e3, "instantiate graph");
+      p->graphs[j] = ex;
+    }
+    QCHECK(hipGraphLaunch(p->graphs[j], p->stream), "graph launch");
+    return QAX_OK;
+  };
+
   int total_its = 0, outer = 0;
   double relres = 1.0;
   std::vector<double> rn(nseg);
-  std::vector<cplx> scl(nseg);
   qax_status result = QAX_ERR_NOCONV;
   while (true) {
     // true residual r = b - A x  (FP64)
@@ -680,73 +747,37 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
       break;
     }
     if (total_its >= maxit) break;
-    // inner right-preconditioned GMRES cycle on A d = r
-    std::vector<SegGmres> S(nseg);
-    std::vector<double> tin(nseg);
+    // inner right-preconditioned GMRES cycle on A d = r: per-segment start
+    std::vector<double> par(2 * nseg);
+    std::vector<int32_t> fz(nseg + m + 1, 0);
+    std::vector<cplx> g0((size_t)nseg * (m + 1), 0.0), scl(nseg);
     for (int s = 0; s < nseg; ++s) {
-      S[s].m = m;
-      S[s].H.assign((size_t)(m + 1) * m, 0.0);
-      S[s].cs.assign(m, 0.0);
-      S[s].sn.assign(m, 0.0);
-      S[s].g.assign(m + 1, 0.0);
-      S[s].beta = rn[s];
-      S[s].g[0] = rn[s];
-      S[s].frozen = !(rn[s] > 0) || (bnorm[s] > 0 && rn[s] <= tol * bnorm[s]);
+      const bool frozen = !(rn[s] > 0) || (bnorm[s] > 0 && rn[s] <= tol * bnorm[s]);
       const double need = bnorm[s] > 0 && rn[s] > 0 ? 0.5 * tol * bnorm[s] / rn[s] : 1.0;
-      tin[s] = prec == QAX_MIXED ? std::max(need, 2e-5) : need;
-      scl[s] = S[s].frozen ? 0.0 : 1.0 / rn[s];
+      par[s] = rn[s];
+      par[nseg + s] = prec == QAX_MIXED ? std::max(need, 2e-5) : need;
+      fz[s] = frozen ? 1 : 0;
+      g0[(size_t)s * (m + 1)] = rn[s];
+      scl[s] = frozen ? 0.0 : 1.0 / rn[s];
     }
-    QCHECK(hipMemcpyAsync(hd, scl.data(), nseg * 16, hipMemcpyHostToDevice, p->stream), "copy");
-    K.scale(r, hd, V);
+    QCHECK(hipMemcpyAsync(G.beta, par.data(), par.size() * 8, hipMemcpyHostToDevice, p->stream), "copy");
+    QCHECK(hipMemcpyAsync(G.frozen, fz.data(), fz.size() * 4, hipMemcpyHostToDevice, p->stream), "copy");
+    QCHECK(hipMemcpyAsync(G.g, g0.data(), g0.size() * 16, hipMemcpyHostToDevice, p->stream), "copy");
+    QCHECK(hipMemcpyAsync(G.scl, scl.data(), nseg * 16, hipMemcpyHostToDevice, p->stream), "copy");
+    K.scale(r, (const double*)G.scl, V);
     int j = 0;
     for (; j < m && total_its < maxit; ++j) {
-      double* Vj = V + (size_t)j * vs;
-      double* Vn = V + (size_t)(j + 1) * vs;
-      QCHECK(launch_block_apply(p, 1, inner_prec, Vj, t, nrhs, false), "precond");
-      st = pair_sum_into(p, inner_prec, t, w, nrhs, false);
-      if (st != QAX_OK) return st;
-      K.axpby(1.0, w, 1.0, Vj, w);
-      // classical Gram-Schmidt, twice
-      double* h1 = hd;
-      double* h2 = hd + (size_t)(m + 2) * nseg * 2;
-      K.dots(V, vs, j + 1, w, h1);
-      K.orth(V, vs, j + 1, h1, w);
-      K.dots(V, vs, j + 1, w, h2);
-      K.orth(V, vs, j + 1, h2, w);
-      K.dots(w, 0, 1, w, h2 + (size_t)(j + 1) * nseg * 2);
-      QCHECK(hipMemcpyAsync(hh.data(), hd, (size_t)(2 * m + 4) * nseg * 16, hipMemcpyDeviceToHost,
-                            p->stream), "copy h");
+      if ((st = run_step(j)) != QAX_OK) return st;
       if ((st = sync(p, "gmres")) != QAX_OK) return st;
       ++total_its;
-      bool all = true;
-      for (int s = 0; s < nseg; ++s) {
-        std::vector<cplx> col(j + 2);
-        for (int i = 0; i <= j; ++i)
-          col[i] = hh[(size_t)i * nseg + s] + hh[(size_t)(m + 2) * nseg + (size_t)i * nseg + s];
-        const double hn = std::sqrt(std::max(hh[(size_t)(m + 2) * nseg + (size_t)(j + 1) * nseg + s].real(), 0.0));
-        col[j + 1] = hn;
-        if (!S[s].frozen) givens_step(S[s], j, col.data());
-        const bool tiny = !(hn > 1e-14 * S[s].beta);
-        scl[s] = (S[s].frozen || tiny) ? 0.0 : 1.0 / hn;
-        const double est = S[s].beta > 0 ? std::abs(S[s].g[j + 1]) / S[s].beta : 0.0;
-        if (!S[s].frozen && est > tin[s] && !tiny) all = false;
-      }
-      QCHECK(hipMemcpyAsync(hd, scl.data(), nseg * 16, hipMemcpyHostToDevice, p->stream), "copy");
-      K.scale(w, hd, Vn);
-      if (all) {
+      if (p->h_flags[j] == 0) {
         ++j;
         break;
       }
     }
     // d = M^-1 V y;  x += d
-    std::vector<cplx> ys((size_t)j * nseg, 0.0);
-    for (int s = 0; s < nseg; ++s) {
-      if (S[s].frozen) continue;
-      std::vector<cplx> y = back_solve(S[s], j);
-      for (int i = 0; i < j; ++i) ys[(size_t)i * nseg + s] = y[i];
-    }
-    QCHECK(hipMemcpyAsync(hd, ys.data(), ys.size() * 16, hipMemcpyHostToDevice, p->stream), "copy y");
-    K.combine(V, vs, j, hd, t, false);
+    K.back_solve(nseg, j, m, G, (double*)ydev);
+    K.combine(V, vs, j, (const double*)ydev, t, false);
     QCHECK(launch_block_apply(p, 1, inner_prec, t, x, nrhs, true), "precond");
     ++outer;
   }

@@ -232,17 +232,25 @@ __global__ __launch_bounds__(256) void block_gemm_kernel(
       }
 }
 
+// Row tiles of the block GEMM (built once per geometry; synchronous copy, so
+// not to be first called inside a stream capture).
+hipError_t ensure_gemm_tasks(qax_problem* p) {
+  if (!p->gemm_tasks.empty()) return hipSuccess;
+  for (int b = 0; b < p->n_bodies; ++b)
+    for (int r0 = 0; r0 < p->hbodies[b].n; r0 += 64) p->gemm_tasks.push_back(GemmTask{b, r0});
+  hipError_t e = hipMalloc(&p->d_gemm_tasks, p->gemm_tasks.size() * sizeof(GemmTask));
+  if (e != hipSuccess) {
+    p->gemm_tasks.clear();
+    return e;
+  }
+  return hipMemcpy(p->d_gemm_tasks, p->gemm_tasks.data(), p->gemm_tasks.size() * sizeof(GemmTask),
+                   hipMemcpyHostToDevice);
+}
+
 hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double* v, double* out,
                              int nrhs, bool accumulate) {
-  if (p->gemm_tasks.empty()) {
-    for (int b = 0; b < p->n_bodies; ++b)
-      for (int r0 = 0; r0 < p->hbodies[b].n; r0 += 64) p->gemm_tasks.push_back(GemmTask{b, r0});
-    hipError_t e = hipMalloc(&p->d_gemm_tasks, p->gemm_tasks.size() * sizeof(GemmTask));
-    if (e != hipSuccess) return e;
-    e = hipMemcpy(p->d_gemm_tasks, p->gemm_tasks.data(), p->gemm_tasks.size() * sizeof(GemmTask),
-                  hipMemcpyHostToDevice);
-    if (e != hipSuccess) return e;
-  }
+  hipError_t e = ensure_gemm_tasks(p);
+  if (e != hipSuccess) return e;
   dim3 grid((unsigned)p->gemm_tasks.size(), (unsigned)((2 * nrhs + 63) / 64));
   const GemmTask* t = (const GemmTask*)p->d_gemm_tasks;
   if (inverse && prec == QAX_MIXED)

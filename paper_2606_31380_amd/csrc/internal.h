@@ -121,6 +121,16 @@ struct qax_problem {
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;
 
+  // captured GMRES steps: one executable graph per Arnoldi step index, valid
+  // while `graph_key` (buffers, sizes, launch choices) is unchanged
+  bool use_graphs = true;
+  uint64_t generation = 0;            // bumped by build, assembly and tuning changes
+  std::string graph_key;
+  std::vector<hipGraphExec_t> graphs;
+  hipStream_t cap_stream = nullptr;   // the handle's own stream for captures
+  int32_t* h_flags = nullptr;         // pinned host copies of the per-step counters
+  int h_flags_n = 0;
+
   // kernel timing
   bool timing = false;
   struct Pending {
@@ -159,6 +169,7 @@ void plan_pair_sum(qax_problem* p, int prec, int cu_count);
 hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count);
 // launch choices the kernels support (LDS within 64 KB)
 bool pair_config_ok(int prec, int tpb, int nrc);
+hipError_t ensure_gemm_tasks(qax_problem* p);
 
 // dense.hip
 hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,

@@ -301,6 +301,7 @@ void plan_pair_sum(qax_problem* p, int prec, int cu_count) {
 
 hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count) {
   plan_pair_sum(p, prec, cu_count);
+  ++p->generation;   // captured solver steps hold the old launch sizes
   std::vector<PairTask>& t = prec == QAX_FP64 ? p->tasks64 : p->tasks32;
   PairTask*& d = prec == QAX_FP64 ? p->d_tasks64 : p->d_tasks32;
   if (d) {

@@ -50,7 +50,7 @@ _LIB = None
 EXPORTS = ["qax_create", "qax_destroy", "qax_last_error", "qax_build", "qax_size", "qax_nodes",
            "qax_assemble_self", "qax_self_block", "qax_pair_sum", "qax_block_apply", "qax_apply",
            "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes",
-           "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning"]
+           "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning", "qax_set_graphs"]
 (QAX_K_PAIRSUM_FP64, QAX_K_PAIRSUM_FP32, QAX_K_BLOCK_APPLY, QAX_K_SELF_ASSEMBLY, QAX_K_INVERT,
  QAX_K_INVERT_UPDATE, QAX_K_BLOCK_APPLY_F32) = range(7)
 KERNEL_NAMES = ["pair_sum_fp64", "pair_sum_fp32", "block_apply", "self_assembly", "invert",
@@ -88,6 +88,7 @@ def lib():
         "qax_farfield": (C.c_int, [vp, vp, i32, pd, i32, vp]),
         "qax_modal_modes": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, d, i32, vp, vp]),
         "qax_set_timing": (C.c_int, [vp, i32]),
+        "qax_set_graphs": (C.c_int, [vp, i32]),
         "qax_timing": (C.c_int, [vp, i32, C.POINTER(i64), pd]),
         "qax_autotune": (C.c_int, [vp, i32, C.c_char_p]),
         "qax_tuning": (C.c_int, [vp, C.POINTER(qax_tuning_info)]),
@@ -213,6 +214,10 @@ def qax_farfield(h, mu, xhat, u_inf, nrhs=1):
 def qax_modal_modes(h, r, rt, c, chim1, rmrt, k, nmax, A, B):
     _check(h, lib().qax_modal_modes(h, int(r.shape[0]), _ptr(r), _ptr(rt), _ptr(c), _ptr(chim1),
                                     _ptr(rmrt), float(k), int(nmax), _ptr(A), _ptr(B)))
+
+
+def qax_set_graphs(h, enable=True):
+    _check(h, lib().qax_set_graphs(h, int(bool(enable))))
 
 
 def qax_set_timing(h, enable=True):
