@@ -207,7 +207,8 @@ qax_status qax_timing(const qax_problem* p, int32_t kernel, int64_t* launches, d
  *    tile staged in LDS (128, 256, 512), and the number of workgroups per
  *    compute unit that the split of the source bodies into chunks aims at
  *    (4, 8, 16; sets how many partial sums each target row gets); with
- *    several right-hand sides, right-hand sides per pass (1 ... 16);
+ *    several right-hand sides, right-hand sides per pass (2 ... 32), chosen
+ *    together with the workgroup size for the largest class nrhs_max reaches;
  *  - block apply with one right-hand side, per storage precision: complex
  *    entries per lane and load (1, 2; 4 for the FP32 copy).
  * Every candidate is timed on this problem's own data (HIP events, the
@@ -239,7 +240,7 @@ qax_status qax_tuning(const qax_problem* p, qax_tuning_info* out);
 /* Set the launch choices by hand (pair_tpb, pair_slot_mult, pair_nrc,
  * gemv_vec of `in`; the other fields are ignored).  Requires qax_build.
  * QAX_ERR_ARG if a choice is not one the kernels support (pair_tpb 128, 256
- * or 512; pair_slot_mult 1 ... 64; pair_nrc 1, 2, 4, 8 (FP64) or ... 16
+ * or 512; pair_slot_mult 1 ... 64; pair_nrc 1, 2, 4, 8 (FP64) or ... 32
  * (FP32) with the LDS of the workgroup within 64 KB; gemv_vec 1, 2 (FP64) or
  * 1, 2, 4 (FP32)). */
 qax_status qax_set_tuning(qax_problem* p, const qax_tuning_info* in);

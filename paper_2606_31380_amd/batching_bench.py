@@ -1,0 +1,192 @@
+"""Measurements of the batching pattern on one GPU (each prints one JSON line):
+
+    python -m paper_2606_31380_amd.batching_bench multi_rhs [--loop-sample 8]
+    python -m paper_2606_31380_amd.batching_bench batch
+
+multi_rhs -- 200 bent spheroids (32 GL x 64 azimuthal nodes, N = 409,600),
+k = 6, 64 incident directions: one FP32 / FP64 pair sum over all 64
+right-hand sides against 64 single-right-hand-side pair sums; the block apply
+of B^-1 with 64 right-hand sides (batched complex GEMM on the matrix cores)
+against 64 single-right-hand-side applies; time to solve to 1e-6 with all 64
+directions in one lockstep GMRES against one solve per direction (the
+per-direction loop is run on the first `--loop-sample` directions and its
+total is that time x 64 / sample, stated as such).
+
+batch -- 32 independent problems (1-100 bent spheroids each, 16-32 GL x
+16-64 azimuthal nodes per body, own k in [1, 10], one direction each,
+N = 1,746,400 in total): one handle holding all problems (one launch per
+kernel for all of them, captured GMRES steps) against 32 handles solved one
+after the other; time to solve to 1e-6 (mixed and FP64) and set-up time.
+
+Inputs are synthetic and seeded (paper_2606_31380_amd.scenarios).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _timed(fn):
+    _sync()
+    t0 = time.perf_counter()
+    out = fn()
+    _sync()
+    return time.perf_counter() - t0, out
+
+
+def multi_rhs(loop_sample: int) -> dict:
+    import torch
+
+    from paper_2606_31380_amd import qax
+    from paper_2606_31380_amd import scenarios as sc
+
+    dev = torch.device("cuda", 0)
+    s = sc.lattice_like_random()
+    nrhs = s.dirs.shape[0]
+    P = s.pairs_per_apply()
+    res = {"workload": "200 bent spheroids (0.5, 0.5, 1.0), 32 GL x 64 azimuths, N = 409,600, "
+                       "k = 6, 64 directions", "pairs_per_apply": int(P), "nrhs": nrhs}
+    print("multi_rhs: building", flush=True)
+    with qax.Problem(s) as Pr:
+        t_setup, _ = _timed(lambda: qax.qax_assemble_self(Pr.h))
+        res["setup_assemble_invert_s"] = t_setup
+        qax.qax_autotune(Pr.h, nrhs_max=nrhs)
+        res["tuning"] = qax.qax_tuning(Pr.h)
+        print(f"multi_rhs: assembled in {t_setup:.2f} s, tuned", flush=True)
+        N = Pr.N
+        g = torch.Generator(device="cpu").manual_seed(0)
+        V = torch.randn(N * nrhs, dtype=torch.complex128, generator=g).to(dev)
+        O = torch.zeros_like(V)
+        v1 = torch.zeros(N, dtype=torch.complex128, device=dev)
+        o1 = torch.zeros_like(v1)
+        Vm = V.view(N, nrhs)
+        for prec, name in ((qax.QAX_MIXED, "fp32"), (qax.QAX_FP64, "fp64")):
+            qax.qax_pair_sum(Pr.h, prec, V, O, nrhs)                       # warm-up
+            tb, _ = _timed(lambda: qax.qax_pair_sum(Pr.h, prec, V, O, nrhs))
+
+            def loop():
+                for r in range(nrhs):
+                    v1.copy_(Vm[:, r])
+                    qax.qax_pair_sum(Pr.h, prec, v1, o1, 1)
+            tl, _ = _timed(loop)
+            res[f"pair_sum_{name}"] = {"block_s": tb, "per_rhs_loop_s": tl, "speedup": tl / tb,
+                                       "block_pairs_rhs_per_s": P * nrhs / tb}
+            qax.qax_block_apply(Pr.h, 1, prec, V, O, nrhs)
+            tb, _ = _timed(lambda: qax.qax_block_apply(Pr.h, 1, prec, V, O, nrhs))
+
+            def loop_apply():
+                for r in range(nrhs):
+                    v1.copy_(Vm[:, r])
+                    qax.qax_block_apply(Pr.h, 1, prec, v1, o1, 1)
+            tl, _ = _timed(loop_apply)
+            res[f"block_apply_inverse_{name}"] = {"block_gemm_s": tb, "per_rhs_loop_s": tl,
+                                                  "speedup": tl / tb}
+            print(f"multi_rhs: {name} applies done", flush=True)
+        # time to solve, all directions in lockstep
+        X = torch.zeros(N * nrhs, dtype=torch.complex128, device=dev)
+        info = qax.qax_solve(Pr.h, qax.QAX_MIXED, s.dirs, X, nrhs, tol=1e-6, maxit=400)
+        res["solve_block_mixed"] = {"s": info["t_solve_s"], "iters": info["iters"],
+                                    "outer_iters": info["outer_iters"], "rel_res": info["rel_res"]}
+        print(f"multi_rhs: block solve {info['t_solve_s']:.2f} s", flush=True)
+        # one solve per direction, on a sample of the directions
+        ts, its = 0.0, []
+        x1 = torch.zeros(N, dtype=torch.complex128, device=dev)
+        for r in range(loop_sample):
+            inf = qax.qax_solve(Pr.h, qax.QAX_MIXED, s.dirs[r:r + 1], x1, 1, tol=1e-6, maxit=400)
+            ts += inf["t_solve_s"]
+            its.append(inf["iters"])
+            # the lockstep solution of this direction agrees with its own solve
+            if r == 0:
+                xb = X.view(N, nrhs)[:, 0]
+                res["block_vs_single_first_direction_rel_diff"] = (
+                    torch.linalg.norm(xb - x1) / torch.linalg.norm(x1)).item()
+        res["solve_per_rhs_loop_mixed"] = {"sample": loop_sample, "sample_s": ts,
+                                           "estimated_total_s": ts * nrhs / loop_sample,
+                                           "iters": its}
+        res["solve_speedup_block_vs_loop"] = ts * nrhs / loop_sample / info["t_solve_s"]
+        print("multi_rhs: per-direction solves done", flush=True)
+    return res
+
+
+def batch() -> dict:
+    import torch
+
+    from paper_2606_31380_amd import qax
+    from paper_2606_31380_amd import scenarios as sc
+
+    dev = torch.device("cuda", 0)
+    s = sc.uneven_batch()
+    npb = s.bodies["problem"]
+    dirs = s.notes["dirs"]
+    res = {"workload": "32 independent problems, 1-100 bent spheroids each, 16-32 GL x 16-64 "
+                       "azimuths per body, k in [1, 10], one direction each",
+           "n_unknowns": int(s.nodes_per_body().sum()), "pairs_per_apply": int(s.pairs_per_apply())}
+    print(f"batch: {len(s.bodies)} bodies, N = {res['n_unknowns']}", flush=True)
+    with qax.Problem(s) as Pr:
+        t_setup, _ = _timed(lambda: qax.qax_assemble_self(Pr.h))
+        qax.qax_autotune(Pr.h, nrhs_max=1)
+        print(f"batch: batched set-up {t_setup:.2f} s", flush=True)
+        out = {"setup_s": t_setup}
+        for prec, name in ((qax.QAX_MIXED, "mixed"), (qax.QAX_FP64, "fp64")):
+            x = torch.zeros(Pr.N, dtype=torch.complex128, device=dev)
+            info = qax.qax_solve(Pr.h, prec, dirs, x, 1, tol=1e-6, maxit=400)
+            out[name] = {"s": info["t_solve_s"], "iters": info["iters"],
+                         "outer_iters": info["outer_iters"], "rel_res": info["rel_res"]}
+            print(f"batch: batched {name} solve {info['t_solve_s']:.2f} s", flush=True)
+            if name == "mixed":
+                xb = x.cpu().numpy()
+        res["batched"] = out
+        offsets = Pr.offsets
+    seq = {"setup_s": 0.0, "mixed": {"s": 0.0, "iters": []}, "fp64": {"s": 0.0, "iters": []}}
+    worst = 0.0
+    for p in range(len(s.k)):
+        rows = s.bodies[npb == p].copy()
+        rows["problem"] = 0
+        sp = sc.Scenario(f"p{p}", rows, np.array([s.k[p]]), dirs[p:p + 1])
+        with qax.Problem(sp) as Pp:
+            t, _ = _timed(lambda: qax.qax_assemble_self(Pp.h))
+            seq["setup_s"] += t
+            for prec, name in ((qax.QAX_MIXED, "mixed"), (qax.QAX_FP64, "fp64")):
+                x = torch.zeros(Pp.N, dtype=torch.complex128, device=dev)
+                info = qax.qax_solve(Pp.h, prec, dirs[p:p + 1], x, 1, tol=1e-6, maxit=400)
+                seq[name]["s"] += info["t_solve_s"]
+                seq[name]["iters"].append(info["iters"])
+                if name == "mixed":
+                    b0 = int(np.nonzero(npb == p)[0][0])
+                    b1 = int(np.nonzero(npb == p)[0][-1]) + 1
+                    seg = xb[offsets[b0]:offsets[b1]]
+                    xs = x.cpu().numpy()
+                    worst = max(worst, float(np.linalg.norm(seg - xs) / np.linalg.norm(xs)))
+        print(f"batch: sequential problem {p} done", flush=True)
+    res["sequential"] = seq
+    res["batched_vs_sequential_max_rel_diff_mixed"] = worst
+    res["solve_speedup_batched_vs_sequential"] = {
+        "mixed": seq["mixed"]["s"] / res["batched"]["mixed"]["s"],
+        "fp64": seq["fp64"]["s"] / res["batched"]["fp64"]["s"]}
+    return res
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["multi_rhs", "batch"])
+    ap.add_argument("--loop-sample", type=int, default=8)
+    args = ap.parse_args()
+    import torch
+    torch.cuda.set_device(0)
+    r = multi_rhs(args.loop_sample) if args.which == "multi_rhs" else batch()
+    r["measurement"] = args.which
+    print(json.dumps(r))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -621,7 +621,7 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
     QBUF(gsn, double2, "kry_gsn", (size_t)nseg * m * 16);
     QBUF(gg, double2, "kry_gg", (size_t)nseg * (m + 1) * 16);
     QBUF(gpar, double, "kry_gpar", (size_t)nseg * 16 + 256);
-    QBUF(gfz, int32_t, "kry_gfrozen", (size_t)nseg * 4 + (size_t)(m + 1) * 4);
+    QBUF(gfz, int32_t, "kry_gfrozen", (size_t)nseg * 12 + (size_t)(m + 1) * 4);
     QBUF(gscl, double2, "kry_gscl", (size_t)nseg * 16);
     G.H = gH;
     G.cs = gcs;
@@ -630,7 +630,9 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
     G.beta = gpar;
     G.tin = gpar + nseg;
     G.frozen = gfz;
-    G.notdone = gfz + nseg;
+    G.active = gfz + nseg;
+    G.kconv = gfz + 2 * nseg;
+    G.notdone = gfz + 3 * nseg;
     G.scl = gscl;
   }
   QBUF(ydev, double2, "kry_y", (size_t)m * nseg * 16);
@@ -660,8 +662,10 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
   auto enqueue_step = [&](int j) -> hipError_t {
     double* Vj = V + (size_t)j * vs;
     double* Vn = V + (size_t)(j + 1) * vs;
+    p->seg_active = G.active;   // operator work of stopped segments is skipped
     hipError_t e = launch_block_apply(p, 1, inner_prec, Vj, t, nrhs, false);
     if (e == hipSuccess) e = launch_pair_sum(p, inner_prec, t, w, nrhs, ppart, false);
+    p->seg_active = nullptr;
     if (e != hipSuccess) return e;
     K.axpby(1.0, w, 1.0, Vj, w);
     K.dots(V, vs, j + 1, w, h1);
@@ -749,7 +753,7 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
     if (total_its >= maxit) break;
     // inner right-preconditioned GMRES cycle on A d = r: per-segment start
     std::vector<double> par(2 * nseg);
-    std::vector<int32_t> fz(nseg + m + 1, 0);
+    std::vector<int32_t> fz(3 * nseg + m + 1, 0);   // frozen, active, kconv, notdone
     std::vector<cplx> g0((size_t)nseg * (m + 1), 0.0), scl(nseg);
     for (int s = 0; s < nseg; ++s) {
       const bool frozen = !(rn[s] > 0) || (bnorm[s] > 0 && rn[s] <= tol * bnorm[s]);
@@ -757,6 +761,7 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
       par[s] = rn[s];
       par[nseg + s] = prec == QAX_MIXED ? std::max(need, 2e-5) : need;
       fz[s] = frozen ? 1 : 0;
+      fz[nseg + s] = frozen ? 0 : 1;
       g0[(size_t)s * (m + 1)] = rn[s];
       scl[s] = frozen ? 0.0 : 1.0 / rn[s];
     }
@@ -798,14 +803,14 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
 // ---------------------------------------------------------------- autotuner
 namespace {
 
-// Median-free timing: the fastest of `reps` launches after one warm-up.
+// The fastest of `reps` launches (after one warm-up launch when `warm`).
 template <typename F>
-static double time_best(qax_problem* p, int reps, F&& launch, hipError_t* err) {
+static double time_best(qax_problem* p, int reps, F&& launch, hipError_t* err, bool warm = true) {
   hipEvent_t a = nullptr, b = nullptr;
   *err = hipEventCreate(&a);
   if (*err == hipSuccess) *err = hipEventCreate(&b);
   double best = 1e300;
-  if (*err == hipSuccess) *err = launch();
+  if (*err == hipSuccess && warm) *err = launch();
   if (*err == hipSuccess) *err = hipStreamSynchronize(p->stream);
   for (int r = 0; r < reps && *err == hipSuccess; ++r) {
     *err = hipEventRecord(a, p->stream);
@@ -939,20 +944,59 @@ extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char*
       if (!part) return hipErrorOutOfMemory;
       return launch_pair_sum(p, prec, mu, out, nrhs, part, false);
     };
-    // workgroup size and source-chunk schedule, one right-hand side
-    double best = 1e300, dflt = 0.0;
+    const int lo[4] = {2, 5, 9, 17}, rep[4] = {4, 8, 16, 64};
+    auto nrc_ok = [&](int tpb, int nrc, int c, int nrhs) {
+      return pair_config_ok(prec, tpb, nrc) && nrc <= 2 * nrhs && !(c > 0 && nrc < 4);
+    };
+    double best = 1e300;
     int btpb = t.pair_tpb[pi], bmult = t.pair_mult[pi];
-    for (int tpb : {128, 256, 512}) {
-      for (int mult : {4, 8, 16}) {
+    if (nrhs_max == 1) {
+      // workgroup size and source-chunk schedule for one right-hand side
+      for (int tpb : {128, 256, 512}) {
+        for (int mult : {4, 8, 16}) {
+          p->tune.pair_tpb[pi] = tpb;
+          p->tune.pair_mult[pi] = mult;
+          QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
+          const double ms = time_best(p, 2, [&] { return run(1); }, &err);
+          QCHECK(err, "autotune pair sum");
+          if (ms < best) {
+            best = ms;
+            btpb = tpb;
+            bmult = mult;
+          }
+        }
+      }
+    } else {
+      // several right-hand sides: workgroup size and right-hand sides per
+      // pass together for the largest class, then the schedule
+      const int ctop = qax::nrhs_class(nrhs_max), nr = std::min(nrhs_max, rep[ctop]);
+      int bn = t.pair_nrc[pi][ctop];
+      for (int tpb : {128, 256, 512}) {
         p->tune.pair_tpb[pi] = tpb;
+        p->tune.pair_mult[pi] = defaults.pair_mult[pi];
+        QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
+        for (int nrc : {2, 4, 8, 16, 32}) {
+          if (!nrc_ok(tpb, nrc, ctop, nr)) continue;
+          p->tune.pair_nrc[pi][ctop] = nrc;
+          const double ms = time_best(p, 1, [&] { return run(nr); }, &err, false);
+          QCHECK(err, "autotune pair sum (several right-hand sides)");
+          if (ms < best) {
+            best = ms;
+            btpb = tpb;
+            bn = nrc;
+          }
+        }
+      }
+      p->tune.pair_tpb[pi] = btpb;
+      p->tune.pair_nrc[pi][ctop] = t.pair_nrc[pi][ctop] = bn;
+      bmult = defaults.pair_mult[pi];
+      for (int mult : {4, 16}) {
         p->tune.pair_mult[pi] = mult;
         QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
-        const double ms = time_best(p, 2, [&] { return run(1); }, &err);
-        QCHECK(err, "autotune pair sum");
-        if (tpb == defaults.pair_tpb[pi] && mult == defaults.pair_mult[pi]) dflt = ms;
+        const double ms = time_best(p, 1, [&] { return run(nr); }, &err, false);
+        QCHECK(err, "autotune pair sum (several right-hand sides)");
         if (ms < best) {
           best = ms;
-          btpb = tpb;
           bmult = mult;
         }
       }
@@ -961,20 +1005,29 @@ extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char*
     p->tune.pair_mult[pi] = t.pair_mult[pi] = bmult;
     for (int c = 0; c < 4; ++c)
       p->tune.pair_nrc[pi][c] = t.pair_nrc[pi][c] = clamp_nrc(prec, btpb, t.pair_nrc[pi][c]);
-    t.pair_ms[pi] = best;
-    t.default_pair_ms[pi] = dflt;
-    QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
-    // right-hand sides per pass, for each class that nrhs_max reaches
-    const int lo[4] = {2, 5, 9, 17}, rep[4] = {4, 8, 16, 64};
+    // single-right-hand-side times of the choice and of the default (report)
+    {
+      p->tune.pair_tpb[pi] = defaults.pair_tpb[pi];
+      p->tune.pair_mult[pi] = defaults.pair_mult[pi];
+      QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
+      t.default_pair_ms[pi] = time_best(p, 2, [&] { return run(1); }, &err);
+      QCHECK(err, "autotune pair sum");
+      p->tune.pair_tpb[pi] = btpb;
+      p->tune.pair_mult[pi] = bmult;
+      QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
+      t.pair_ms[pi] = time_best(p, 2, [&] { return run(1); }, &err);
+      QCHECK(err, "autotune pair sum");
+    }
+    // right-hand sides per pass for the other classes that nrhs_max reaches
     for (int c = 0; c < 4; ++c) {
-      if (nrhs_max < lo[c]) continue;
+      if (nrhs_max < lo[c] || (nrhs_max > 1 && c == qax::nrhs_class(nrhs_max))) continue;
       const int nrhs = std::min(nrhs_max, rep[c]);
       double bc = 1e300;
       int bn = t.pair_nrc[pi][c];
-      for (int nrc : {1, 2, 4, 8, 16}) {
-        if (!pair_config_ok(prec, btpb, nrc) || nrc > 2 * nrhs) continue;
+      for (int nrc : {2, 4, 8, 16, 32}) {
+        if (!nrc_ok(btpb, nrc, c, nrhs)) continue;
         p->tune.pair_nrc[pi][c] = nrc;
-        const double ms = time_best(p, 1, [&] { return run(nrhs); }, &err);
+        const double ms = time_best(p, 1, [&] { return run(nrhs); }, &err, false);
         QCHECK(err, "autotune pair sum (several right-hand sides)");
         if (ms < bc) {
           bc = ms;

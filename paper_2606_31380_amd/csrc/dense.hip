@@ -25,7 +25,8 @@ template <typename MT, int NRC, int VEC>
 __global__ __launch_bounds__(256) void block_gemv_kernel(
     const BodyDev* __restrict__ bodies, const BlockDev* __restrict__ blocks,
     const int32_t* __restrict__ node_body, const MT* __restrict__ pool, int64_t N,
-    const double2* __restrict__ v, int nrhs, double2* __restrict__ out, int accumulate) {
+    const double2* __restrict__ v, int nrhs, double2* __restrict__ out, int accumulate,
+    const int32_t* __restrict__ seg_active) {
   typedef MT vec_t __attribute__((ext_vector_type(2 * VEC)));
   const int lane = threadIdx.x & 63;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -33,6 +34,16 @@ __global__ __launch_bounds__(256) void block_gemv_kernel(
   if (row >= N) return;
   const int b = node_body[row];
   const BodyDev& B = bodies[b];
+  if (seg_active) {
+    // converged lockstep segments: their input is zero, so is the output
+    bool any = false;
+    for (int r = rc0; r < rc0 + NRC && r < nrhs; ++r) any = any || seg_active[B.problem * nrhs + r] != 0;
+    if (!any) {
+      if (lane == 0 && !accumulate)
+        for (int r = rc0; r < rc0 + NRC && r < nrhs; ++r) out[row * nrhs + r] = make_double2(0.0, 0.0);
+      return;
+    }
+  }
   const BlockDev& K = blocks[B.block];
   const int n = K.n;
   const int lr = (int)(row - B.off);
@@ -85,7 +96,7 @@ static void gemv_launch(qax_problem* p, const MT* pool, const double* v, double*
   dim3 grid((unsigned)((p->N + 3) / 4), (unsigned)((nrhs + NRC - 1) / NRC));
   hipLaunchKernelGGL((block_gemv_kernel<MT, NRC, VEC>), grid, dim3(256), 0, p->stream, p->d_bodies,
                      p->d_blocks, p->d_node_body, pool, p->N, (const double2*)v, nrhs,
-                     (double2*)out, acc ? 1 : 0);
+                     (double2*)out, acc ? 1 : 0, p->seg_active);
 }
 
 hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double* v, double* out,

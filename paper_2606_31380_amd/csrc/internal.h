@@ -124,6 +124,7 @@ struct qax_problem {
   // captured GMRES steps: one executable graph per Arnoldi step index, valid
   // while `graph_key` (buffers, sizes, launch choices) is unchanged
   bool use_graphs = true;
+  const int32_t* seg_active = nullptr;  // set while a lockstep solve enqueues its steps
   uint64_t generation = 0;            // bumped by build, assembly and tuning changes
   std::string graph_key;
   std::vector<hipGraphExec_t> graphs;

@@ -23,6 +23,8 @@ struct GivensState {
   int32_t* frozen = nullptr;  // nseg: 1 = segment not iterated in this cycle
   double2* scl = nullptr;     // nseg: scale of the next basis vector (0 for stopped ones)
   int32_t* notdone = nullptr; // m: per step, number of segments still above tolerance
+  int32_t* active = nullptr;  // nseg: 1 while the segment is iterated (0: frozen or converged)
+  int32_t* kconv = nullptr;   // nseg: steps taken when the segment converged (0: not yet)
 };
 
 // Launch helpers over N x nrhs complex vectors whose segments are

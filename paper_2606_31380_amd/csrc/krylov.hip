@@ -209,12 +209,20 @@ __device__ __forceinline__ double2 conj_k(double2 a) { return make_double2(a.x, 
 // One thread per segment: column j of the Hessenberg matrix (h1 + h2 for rows
 // <= j, |w| below), the earlier rotations applied to it, the rotation that
 // annihilates the subdiagonal (cs real, sn complex), g updated, the scale
-// 1/h_{j+1,j} of the next basis vector, and the convergence count.
+// 1/h_{j+1,j} of the next basis vector, and the convergence count.  A
+// segment that reaches its tolerance (or a breakdown, |w| ~ 0) stops: its
+// step count is kept for the back substitution, its next basis vectors are
+// zero and its `active` flag lets the operator skip it.
 __global__ void givens_kernel(int nseg, int j, int m, const double2* __restrict__ h1,
                               const double2* __restrict__ h2, const double2* __restrict__ hn2,
                               GivensState G) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nseg) return;
+  const bool stopped = G.frozen[s] != 0 || G.kconv[s] != 0;
+  if (stopped) {
+    G.scl[s] = make_double2(0.0, 0.0);
+    return;
+  }
   double2* col = G.H + ((int64_t)s * m + j) * (m + 1);
   for (int i = 0; i <= j; ++i) {
     const double2 a = h1[(int64_t)i * nseg + s], b = h2[(int64_t)i * nseg + s];
@@ -222,51 +230,54 @@ __global__ void givens_kernel(int nseg, int j, int m, const double2* __restrict_
   }
   const double hn = sqrt(fmax(hn2[s].x, 0.0));
   col[j + 1] = make_double2(hn, 0.0);
-  const bool frozen = G.frozen[s] != 0;
   double* cs = G.cs + (int64_t)s * m;
   double2* sn = G.sn + (int64_t)s * m;
   double2* g = G.g + (int64_t)s * (m + 1);
-  if (!frozen) {
-    for (int i = 0; i < j; ++i) {
-      const double2 a = col[i], b = col[i + 1];
-      const double2 sb = cmul_k(sn[i], b);
-      const double2 t = make_double2(cs[i] * a.x + sb.x, cs[i] * a.y + sb.y);
-      const double2 na = cmul_k(conj_k(sn[i]), a);
-      col[i + 1] = make_double2(cs[i] * b.x - na.x, cs[i] * b.y - na.y);
-      col[i] = t;
-    }
-    const double2 a = col[j], b = col[j + 1];
-    const double aa = hypot(a.x, a.y), bb = hypot(b.x, b.y);
-    const double den = hypot(aa, bb);
-    double c;
-    double2 sv;
-    if (den == 0.0) {
-      c = 1.0;
-      sv = make_double2(0.0, 0.0);
-    } else if (aa == 0.0) {
-      c = 0.0;
-      sv = make_double2(1.0, 0.0);
-    } else {
-      c = aa / den;
-      const double2 u = make_double2(a.x / aa, a.y / aa);
-      const double2 q = cmul_k(u, conj_k(b));
-      sv = make_double2(q.x / den, q.y / den);
-    }
-    cs[j] = c;
-    sn[j] = sv;
-    const double2 sb = cmul_k(sv, b);
-    col[j] = make_double2(c * a.x + sb.x, c * a.y + sb.y);
-    col[j + 1] = make_double2(0.0, 0.0);
-    const double2 gj = g[j];
-    const double2 ng = cmul_k(conj_k(sv), gj);
-    g[j + 1] = make_double2(-ng.x, -ng.y);
-    g[j] = make_double2(c * gj.x, c * gj.y);
+  for (int i = 0; i < j; ++i) {
+    const double2 a = col[i], b = col[i + 1];
+    const double2 sb = cmul_k(sn[i], b);
+    const double2 t = make_double2(cs[i] * a.x + sb.x, cs[i] * a.y + sb.y);
+    const double2 na = cmul_k(conj_k(sn[i]), a);
+    col[i + 1] = make_double2(cs[i] * b.x - na.x, cs[i] * b.y - na.y);
+    col[i] = t;
   }
+  const double2 a = col[j], b = col[j + 1];
+  const double aa = hypot(a.x, a.y), bb = hypot(b.x, b.y);
+  const double den = hypot(aa, bb);
+  double c;
+  double2 sv;
+  if (den == 0.0) {
+    c = 1.0;
+    sv = make_double2(0.0, 0.0);
+  } else if (aa == 0.0) {
+    c = 0.0;
+    sv = make_double2(1.0, 0.0);
+  } else {
+    c = aa / den;
+    const double2 u = make_double2(a.x / aa, a.y / aa);
+    const double2 q = cmul_k(u, conj_k(b));
+    sv = make_double2(q.x / den, q.y / den);
+  }
+  cs[j] = c;
+  sn[j] = sv;
+  const double2 sb = cmul_k(sv, b);
+  col[j] = make_double2(c * a.x + sb.x, c * a.y + sb.y);
+  col[j + 1] = make_double2(0.0, 0.0);
+  const double2 gj = g[j];
+  const double2 ng = cmul_k(conj_k(sv), gj);
+  g[j + 1] = make_double2(-ng.x, -ng.y);
+  g[j] = make_double2(c * gj.x, c * gj.y);
   const double beta = G.beta[s];
   const bool tiny = !(hn > 1e-14 * beta);
-  G.scl[s] = (frozen || tiny) ? make_double2(0.0, 0.0) : make_double2(1.0 / hn, 0.0);
   const double est = beta > 0.0 ? hypot(g[j + 1].x, g[j + 1].y) / beta : 0.0;
-  if (!frozen && est > G.tin[s] && !tiny) atomicAdd(G.notdone + j, 1);
+  if (est > G.tin[s] && !tiny) {
+    G.scl[s] = make_double2(1.0 / hn, 0.0);
+    atomicAdd(G.notdone + j, 1);
+  } else {
+    G.scl[s] = make_double2(0.0, 0.0);
+    G.kconv[s] = j + 1;
+    G.active[s] = 0;
+  }
 }
 
 // One thread per segment: back substitution R y = g over the first k columns.
@@ -276,9 +287,11 @@ __global__ void back_solve_kernel(int nseg, int k, int m, GivensState G, double2
   const double2* H = G.H + (int64_t)s * m * (m + 1);
   const double2* g = G.g + (int64_t)s * (m + 1);
   const bool frozen = G.frozen[s] != 0;
-  for (int i = k - 1; i >= 0; --i) {
+  const int ks = G.kconv[s] > 0 ? min(G.kconv[s], k) : k;
+  for (int i = k - 1; i >= ks; --i) y[(int64_t)i * nseg + s] = make_double2(0.0, 0.0);
+  for (int i = ks - 1; i >= 0; --i) {
     double2 acc = g[i];
-    for (int l = i + 1; l < k; ++l) {
+    for (int l = i + 1; l < ks; ++l) {
       const double2 t = cmul_k(H[(int64_t)l * (m + 1) + i], y[(int64_t)l * nseg + s]);
       acc.x -= t.x;
       acc.y -= t.y;

@@ -32,17 +32,39 @@ namespace qax {
 
 constexpr double INV_FOUR_PI = 0.0795774715459476678844;
 
+// Lockstep solves pass seg_active[problem * nrhs + r] (0 once that GMRES
+// segment has converged in the current cycle; its basis vectors are then
+// zero).  A task none of whose right-hand sides is active writes zeros to its
+// partial sums and does no pair work.  The test is uniform over the block.
+template <int NRC>
+__device__ __forceinline__ bool skip_task(const PairTask& T, const BodyDev* __restrict__ bodies,
+                                          const int32_t* __restrict__ seg_active, int nrhs, int rc0,
+                                          bool active, int64_t i, int64_t N,
+                                          double2* __restrict__ partial) {
+  if (!seg_active) return false;
+  const int pr = bodies[T.tbody_lo].problem;
+  bool any = false;
+  for (int r = rc0; r < rc0 + NRC && r < nrhs; ++r) any = any || seg_active[pr * nrhs + r] != 0;
+  if (any) return false;
+  if (active) {
+    double2* dst = partial + (int64_t)T.slot * N * nrhs;
+    for (int r = rc0; r < rc0 + NRC && r < nrhs; ++r) dst[i * nrhs + r] = make_double2(0.0, 0.0);
+  }
+  return true;
+}
+
 template <int TPB, int NRC>
 __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
     const PairTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
     const int32_t* __restrict__ node_body, const double* __restrict__ pos,
     const double* __restrict__ aw, int64_t N, const double2* __restrict__ mu, int nrhs,
-    double2* __restrict__ partial) {
+    const int32_t* __restrict__ seg_active, double2* __restrict__ partial) {
   const PairTask T = tasks[blockIdx.x];
   const int rc0 = blockIdx.y * NRC;  // first right-hand side of this chunk
   const int tid = threadIdx.x;
   const bool active = tid < T.nt;
   const int64_t i = T.t0 + (active ? tid : 0);
+  if (skip_task<NRC>(T, bodies, seg_active, nrhs, rc0, active, i, N, partial)) return;
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
   const int mybody = node_body[i];
   const double k = T.k;
@@ -116,12 +138,14 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
     const PairTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
     const int32_t* __restrict__ node_body, const double* __restrict__ pos,
     const float4* __restrict__ loc32, const float4* __restrict__ aw32, int64_t N,
-    const double2* __restrict__ mu, int nrhs, double2* __restrict__ partial) {
+    const double2* __restrict__ mu, int nrhs, const int32_t* __restrict__ seg_active,
+    double2* __restrict__ partial) {
   const PairTask T = tasks[blockIdx.x];
   const int rc0 = blockIdx.y * NRC;
   const int tid = threadIdx.x;
   const bool active = tid < T.nt;
   const int64_t i = T.t0 + (active ? tid : 0);
+  if (skip_task<NRC>(T, bodies, seg_active, nrhs, rc0, active, i, N, partial)) return;
   const double xi = pos[i], yi = pos[N + i], zi = pos[2 * N + i];
   const int mybody = node_body[i];
   const double k = T.k;
@@ -325,7 +349,7 @@ bool pair_config_ok(int prec, int tpb, int nrc) {
     if (nrc != 1 && nrc != 2 && nrc != 4 && nrc != 8) return false;
     return (size_t)tpb * (48 + 16 * nrc) <= 65536;
   }
-  if (nrc != 1 && nrc != 2 && nrc != 4 && nrc != 8 && nrc != 16) return false;
+  if (nrc != 1 && nrc != 2 && nrc != 4 && nrc != 8 && nrc != 16 && nrc != 32) return false;
   return (size_t)tpb * (32 + 8 * nrc) <= 65536;
 }
 
@@ -335,7 +359,7 @@ static void launch_f64(qax_problem* p, const double* mu, int nrhs, double* parti
     dim3 grid((unsigned)p->tasks64.size(), (unsigned)((nrhs + NRC - 1) / NRC));
     hipLaunchKernelGGL((pair_sum_f64_kernel<TPB, NRC>), grid, dim3(TPB), 0, p->stream, p->d_tasks64,
                        p->d_bodies, p->d_node_body, p->d_pos, p->d_aw, p->N, (const double2*)mu,
-                       nrhs, (double2*)partial);
+                       nrhs, p->seg_active, (double2*)partial);
   }
 }
 
@@ -346,7 +370,7 @@ static void launch_f32(qax_problem* p, const double* mu, int nrhs, double* parti
     hipLaunchKernelGGL((pair_sum_f32_kernel<TPB, NRC>), grid, dim3(TPB), 0, p->stream,
                        p->d_tasks32, p->d_bodies, p->d_node_body, p->d_pos,
                        (const float4*)p->d_loc32, (const float4*)p->d_aw32, p->N,
-                       (const double2*)mu, nrhs, (double2*)partial);
+                       (const double2*)mu, nrhs, p->seg_active, (double2*)partial);
   }
 }
 
@@ -367,7 +391,8 @@ static void launch_f32_nrc(qax_problem* p, int nrc, const double* mu, int nrhs, 
     case 2: launch_f32<TPB, 2>(p, mu, nrhs, partial); break;
     case 4: launch_f32<TPB, 4>(p, mu, nrhs, partial); break;
     case 8: launch_f32<TPB, 8>(p, mu, nrhs, partial); break;
-    default: launch_f32<TPB, 16>(p, mu, nrhs, partial); break;
+    case 16: launch_f32<TPB, 16>(p, mu, nrhs, partial); break;
+    default: launch_f32<TPB, 32>(p, mu, nrhs, partial); break;
   }
 }
 

@@ -209,9 +209,11 @@ def lattice_like_random(n_bodies=200, seed=0, side=20.0, k=6.0, nrhs=64,
 def uneven_batch(n_problems=32, seed=0, max_bodies=100) -> Scenario:
     """Independent problems: each has 1..max_bodies bent spheroids, its own
     k ~ U[1, 10], 16-32 GL x 16-64 azimuthal nodes per body, centres in a cube
-    of side max(6, 20 (n/200)^(1/3)), one random direction per problem (all
-    problems share the direction array of the first; per-problem directions are
-    listed in notes['dirs'])."""
+    with gaps of at least half a wavelength: side 2 R + (n v)^(1/3), where the
+    volume per body v makes the spheres of diameter d = 2 R + pi/k fill a
+    quarter of it (v = (pi/6) d^3 / 0.25; R the largest bounding radius), one
+    random direction per problem (all problems share the direction array of
+    the first; per-problem directions are listed in notes['dirs'])."""
     rng = np.random.Generator(np.random.PCG64(seed))
     rows = []
     ks = rng.uniform(1.0, 10.0, n_problems)
@@ -223,7 +225,9 @@ def uneven_batch(n_problems=32, seed=0, max_bodies=100) -> Scenario:
         npan = rng.integers(1, 3, nb)
         nth = 2 * rng.integers(8, 33, nb)
         radii = np.array([bounding_radius(SPHEROID, 0.5, 1.0, x) for x in kap])
-        side = max(6.0, 20.0 * (nb / 200.0) ** (1.0 / 3.0))
+        rmax = float(radii.max())
+        dex = 2 * rmax + math.pi / ks[p]
+        side = 2 * rmax + (nb * (math.pi / 6.0) * dex ** 3 / 0.25) ** (1.0 / 3.0)
         cs = _rejection_centres(rng, nb, radii, side / 2, math.pi / ks[p])
         bb = make_bodies(nb)
         for i in range(nb):
