@@ -49,7 +49,7 @@ constexpr int LM = 128;                       // modal FFT length
 constexpr int NF_CAP = 48;                    // largest convolution half-width
 constexpr int NTH_MAX = 64;                   // largest n_theta
 constexpr int MQ_CAP = NTH_MAX / 2 + 2 + NF_CAP;   // highest Q index kept (82)
-constexpr int QB = 16;                        // nodes per recurrence batch
+constexpr int QB = 32;                        // nodes per recurrence batch
 constexpr int LD = 256;                       // direct-route azimuthal samples (FFT length)
 constexpr int NGO = 64;                       // outer Gauss-Legendre order
 constexpr double CHI_SPLIT = 0.02;
@@ -71,11 +71,13 @@ struct ModalScratch {
 };
 
 struct SelfShared {
-  double Q[MQ_CAP + 1][QB];
+  union {
+    double Q[MQ_CAP + 1][QB];     // toroidal functions of one recurrence batch
+    double2 acc[GL_ORDER][64];    // accumulated modes (final inverse DFT)
+  };
   double2 tw[LD];               // e^{-2 pi i q / LD} (FFT twiddles, azimuth table)
   double2 tw2n[NTH_MAX];        // e^{i pi m / N}
   int modal_idx[64];
-  double2 acc[GL_ORDER][64];    // accumulated modes (final inverse DFT)
   union {
     ModalScratch m;
     double2 K[LD];
@@ -413,33 +415,41 @@ __device__ __forceinline__ void accumulate_modes(double2 (&acc)[GL_ORDER], doubl
 }
 
 // ---------------------------------------------------------------- per-node geometry
+// Target-side quantities shared by every outer node of a work item.
+struct TargetGeom {
+  double t, st, ct;      // parameter of the target slice and its sine / cosine
+  double r;              // r(t)
+  double sth, cth;       // sin / cos of the target azimuth
+};
+
 // Source slice at s = t + dl relative to the target (t, theta_t).
-__device__ NodeLoc node_local(int shape, double a, double c, double kappa, double t, double tht,
+__device__ NodeLoc node_local(int shape, double a, double c, double kappa, const TargetGeom& T,
                               double dl) {
   NodeLoc L;
-  const Curve ct = curve_eval(shape, a, c, kappa, t);
-  const Curve cs = curve_eval(shape, a, c, kappa, t + dl);
-  const CurveDiff d = curve_diff(shape, a, c, kappa, t, dl);
-  double sth, cth;
-  sincos_cw(tht, &sth, &cth);
-  const double ax = ct.r * cth + d.d_p;
-  const double by = ct.r * sth + d.d_q;
+  double sh, chh, ssig, csig, ss, cs;
+  sincos_cw(0.5 * dl, &sh, &chh);
+  sincos_cw(T.t + 0.5 * dl, &ssig, &csig);
+  sincos_cw(T.t + dl, &ss, &cs);
+  const Curve cv = curve_from_sincos(shape, a, c, kappa, ss, cs);
+  const CurveDiff d = curve_diff_sc(shape, a, c, kappa, T.st, T.ct, ss, cs, sh, chh, ssig, csig);
+  const double ax = T.r * T.cth + d.d_p;
+  const double by = T.r * T.sth + d.d_q;
   L.rt = sqrt(ax * ax + by * by);
   L.alpha = atan2(by, ax);
-  const double drt = (2.0 * ct.r * (cth * d.d_p + sth * d.d_q) + d.d_p * d.d_p + d.d_q * d.d_q) /
-                     (L.rt + ct.r);
+  const double drt = (2.0 * T.r * (T.cth * d.d_p + T.sth * d.d_q) + d.d_p * d.d_p + d.d_q * d.d_q) /
+                     (L.rt + T.r);
   L.rmrt = d.d_r - drt;
   L.c = d.d_z;
-  L.r = cs.r;
-  L.dr = cs.dr;
-  L.dz = cs.dz;
-  L.dp = cs.dp;
-  L.dq = cs.dq;
-  L.z = cs.z;
-  L.p = cs.p;
-  L.q = cs.q;
+  L.r = cv.r;
+  L.dr = cv.dr;
+  L.dz = cv.dz;
+  L.dp = cv.dp;
+  L.dq = cv.dq;
+  L.z = cv.z;
+  L.p = cv.p;
+  L.q = cv.q;
   L.chim1 = (L.rmrt * L.rmrt + L.c * L.c) / (2.0 * L.r * L.rt);
-  L.s = t + dl;
+  L.s = T.t + dl;
   return L;
 }
 
@@ -454,14 +464,21 @@ __device__ __forceinline__ NodeLoc shfl_node(const NodeLoc& v, int src) {
 }
 
 // ---------------------------------------------------------------- assembly kernel
-// Lagrange basis polynomial P_l(x) on the 16 Gauss-Legendre nodes of [-1, 1]
-// (gl[0..15]) with barycentric weights gl[32 + l] = 1 / prod_{m != l}(x_l - x_m).
-__device__ __forceinline__ double lagrange_gl(const double* __restrict__ gl, double x, int l) {
-  double p = gl[32 + l];
+// Lagrange basis polynomial P_l(x) on the 16 Gauss-Legendre nodes x_m of
+// [-1, 1] for l = lane < 16 (0 in the other lanes): with barycentric weight
+// b_l = 1 / prod_{m != l}(x_l - x_m), P_l(x) = b_l prod_m (x - x_m) / (x - x_l);
+// the product over the 16 lanes by xor-shuffles; x on a node gives the unit
+// vector.  xl, bl: the lane's node and weight (registers).
+__device__ __forceinline__ double lagrange_lane(double x, double xl, double bl) {
+  const int lane = threadIdx.x;
+  const double d = lane < GL_ORDER ? x - xl : 1.0;
+  double prod = d;
 #pragma unroll
-  for (int m = 0; m < GL_ORDER; ++m)
-    if (m != l) p *= (x - gl[m]);
-  return p;
+  for (int off = 1; off < GL_ORDER; off <<= 1) prod *= __shfl_xor(prod, off);
+  const unsigned long long hit = __ballot(lane < GL_ORDER && d == 0.0);
+  if (lane >= GL_ORDER) return 0.0;
+  if (hit) return d == 0.0 ? 1.0 : 0.0;
+  return bl * prod / d;
 }
 
 struct OuterRule {
@@ -490,10 +507,13 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   double2* row = pool + K.elem_off + (int64_t)T * n;
 
   // target point (body frame)
-  const Curve cT = curve_eval(shape, a, cc, kappa, tT);
-  double sT, cTh;
-  sincos_cw(thT, &sT, &cTh);
-  const double xT = cT.r * cTh + cT.p, yT = cT.r * sT + cT.q, zT = cT.z;
+  TargetGeom TG;
+  TG.t = tT;
+  sincos_cw(tT, &TG.st, &TG.ct);
+  const Curve cT = curve_from_sincos(shape, a, cc, kappa, TG.st, TG.ct);
+  TG.r = cT.r;
+  sincos_cw(thT, &TG.sth, &TG.cth);
+  const double xT = cT.r * TG.cth + cT.p, yT = cT.r * TG.sth + cT.q, zT = cT.z;
 
   if (abs(ip - pT) > 1) {
     // far panel: smooth rule (Section 3.1, equation sx)
@@ -531,6 +551,9 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   }
   __syncthreads();
 
+  // GL node and barycentric weight of lane l < 16
+  const double glx = lane < GL_ORDER ? gl16[lane] : 0.0;
+  const double glb = lane < GL_ORDER ? gl16[32 + lane] : 0.0;
   // lane s < 2N accumulates sum_q w_q P_l(s_q) K_{s-N}(s_q), l < 16
   double2 acc[GL_ORDER];
 #pragma unroll
@@ -556,7 +579,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     }
     bool modal, wide;
     {
-      const NodeLoc L = node_local(shape, a, cc, kappa, tT, thT, dl);
+      const NodeLoc L = node_local(shape, a, cc, kappa, TG, dl);
       modal = L.chim1 < CHI_SPLIT;
       // direct route: modes decay like e^{-acosh(chi) |m|} beyond the width of
       // the oscillatory factor (about k rho_max); 128 samples when the aliased
@@ -578,7 +601,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       const int src = qlane ? S.modal_idx[b0 + lane] : 0;
       const double dls = __shfl(dl, src);
       if (qlane) {
-        const NodeLoc L = node_local(shape, a, cc, kappa, tT, thT, dls);
+        const NodeLoc L = node_local(shape, a, cc, kappa, TG, dls);
         toroidal_q_lane(1.0 + L.chim1, L.chim1, MQ_CAP, S.Q, lane);
       }
       __syncthreads();
@@ -587,10 +610,10 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         const int sl = S.modal_idx[b0 + q];
         const double dlq = __shfl(dl, sl);
         const double wq = __shfl(w, sl);
-        const NodeLoc Ln = node_local(shape, a, cc, kappa, tT, thT, dlq);
+        const NodeLoc Ln = node_local(shape, a, cc, kappa, TG, dlq);
         modal_modes(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.tw);
         const double2 K = modal_slot(N, Ln, S.u.m);
-        const double pw = lane < GL_ORDER ? lagrange_gl(gl16, 2.0 * (Ln.s - e0) / h - 1.0, lane) * wq : 0.0;
+        const double pw = lagrange_lane(2.0 * (Ln.s - e0) / h - 1.0, glx, glb) * wq;
         accumulate_modes(acc, pw, K);
         __syncthreads();
       }
@@ -627,7 +650,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
           S.u.K[l] = make_double2(-fma(k * rr, s, c) * sc, fma(k * rr, c, -s) * sc);
         }
       }
-      const double pw = lane < GL_ORDER ? lagrange_gl(gl16, 2.0 * (sq - e0) / h - 1.0, lane) * wq : 0.0;
+      const double pw = lagrange_lane(2.0 * (sq - e0) / h - 1.0, glx, glb) * wq;
       __syncthreads();
       if (w256) fft256(S.u.K, S.tw); else fft128(S.u.K, S.tw);
       // mode slot s = lane: m = s - N (slot 0 also takes m = +N), K_m = (2 pi / L) X[m mod L]
@@ -647,6 +670,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       __syncthreads();
     }
   }
+  __syncthreads();   // the recurrence batches are done with S.Q (shares S.acc)
   // inverse DFT onto the Lagrange basis: lane j < 2N,
   // G_lj = (1/2N) sum_s acc_l[s] e^{i (s - N) theta_j}, slot 0 weighted 1/2;
   // e^{i (s - N) j pi / N} = (-1)^j e^{i pi s j / N}

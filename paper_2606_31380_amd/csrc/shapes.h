@@ -18,10 +18,10 @@ struct Curve {
   double r, dr, z, dz, p, dp, q, dq;
 };
 
-__device__ __forceinline__ Curve curve_eval(int shape, double a, double c, double kappa, double t) {
+// Curve at parameter t from st = sin t, ct = cos t.
+__device__ __forceinline__ Curve curve_from_sincos(int shape, double a, double c, double kappa,
+                                                   double st, double ct) {
   Curve o;
-  double st, ct;
-  sincos_cw(t, &st, &ct);
   if (shape == QAX_PEANUT) {
     const double s2 = 2.0 * st * ct, c2 = 1.0 - 2.0 * st * st;
     const double rho = a * (1.0 - c * c2);
@@ -49,6 +49,12 @@ __device__ __forceinline__ Curve curve_eval(int shape, double a, double c, doubl
   return o;
 }
 
+__device__ __forceinline__ Curve curve_eval(int shape, double a, double c, double kappa, double t) {
+  double st, ct;
+  sincos_cw(t, &st, &ct);
+  return curve_from_sincos(shape, a, c, kappa, st, ct);
+}
+
 // Differences between the slice at s = t + dl and the slice at t, written with
 // product-to-sum identities so they keep full relative accuracy as dl -> 0:
 // d_r = r(s) - r(t), d_z = z(t) - z(s), d_p = p(t) - p(s), d_q = q(t) - q(s).
@@ -56,20 +62,13 @@ struct CurveDiff {
   double d_r, d_z, d_p, d_q;
 };
 
-__device__ __forceinline__ CurveDiff curve_diff(int shape, double a, double c, double kappa,
-                                                double t, double dl) {
+// From sin/cos of t, s = t + dl, dl/2 and sig = t + dl/2.
+__device__ __forceinline__ CurveDiff curve_diff_sc(int shape, double a, double c, double kappa,
+                                                   double st, double ct, double ss, double cs,
+                                                   double sh, double chh, double ssig, double csig) {
   CurveDiff o;
-  const double s = t + dl;
-  const double sig = t + 0.5 * dl;
-  double sh, chh;
-  sincos_cw(0.5 * dl, &sh, &chh);
-  double ssig, csig;
-  sincos_cw(sig, &ssig, &csig);
   double z_t, z_s;
   if (shape == QAX_PEANUT) {
-    double st, ct, ss, cs;
-    sincos_cw(t, &st, &ct);
-    sincos_cw(s, &ss, &cs);
     const double rho_t = a * (1.0 - c * (1.0 - 2.0 * st * st));
     const double rho_s = a * (1.0 - c * (1.0 - 2.0 * ss * ss));
     // rho(s) - rho(t) = 2 a c sin(2 sig) sin(dl), sin(dl) = 2 sin(dl/2) cos(dl/2)
@@ -83,9 +82,6 @@ __device__ __forceinline__ CurveDiff curve_diff(int shape, double a, double c, d
   } else {
     o.d_r = -2.0 * a * ssig * sh;
     o.d_z = -2.0 * c * csig * sh;
-    double st, ct, ss, cs;
-    sincos_cw(t, &st, &ct);
-    sincos_cw(s, &ss, &cs);
     z_t = c * st;
     z_s = c * ss;
   }
@@ -98,6 +94,16 @@ __device__ __forceinline__ CurveDiff curve_diff(int shape, double a, double c, d
   }
   o.d_q = 0.0;
   return o;
+}
+
+__device__ __forceinline__ CurveDiff curve_diff(int shape, double a, double c, double kappa,
+                                                double t, double dl) {
+  double sh, chh, ssig, csig, st, ct, ss, cs;
+  sincos_cw(0.5 * dl, &sh, &chh);
+  sincos_cw(t + 0.5 * dl, &ssig, &csig);
+  sincos_cw(t, &st, &ct);
+  sincos_cw(t + dl, &ss, &cs);
+  return curve_diff_sc(shape, a, c, kappa, st, ct, ss, cs, sh, chh, ssig, csig);
 }
 
 }  // namespace qax
