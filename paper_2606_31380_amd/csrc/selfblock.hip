@@ -113,8 +113,36 @@ __device__ __forceinline__ double recip(double x) {
   return y;
 }
 
-// Q[n][col] = Q_{n-1/2}(chi), n = 0..mq, for one node (one lane).
-__device__ void toroidal_q_lane(double chi, double chim1, int mq, double (*Q)[QB], int col) {
+__device__ __forceinline__ int wave_max_int(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return v;
+}
+
+// Uniform copy of lane l's value (v_readlane on both halves); l uniform.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Q[n][col] = Q_{n-1/2}(chi), n = 0..mq, for the node of each lane with `act`
+// (one batch of nodes, one node per lane).  Starting values Q_{-1/2} = mu K,
+// Q_{1/2} = chi mu K - sqrt(2 (chi + 1)) E (K, E of modulus mu by the AGM).
+// Where m acosh(chi) stays small the recurrence leg_recur runs forward; else
+// Miller's backward recurrence from one common start index for the batch
+// (20 / acosh(chi) + 10 beyond mq for the slowest-decaying lane, which only
+// adds accuracy for the others; values above 1e150 are rescaled while no
+// entry is stored yet), normalised by Q_{-1/2}.  The recurrence index is the
+// same in every lane, so the reciprocals 1/(2n +- 1) are computed 64 at a time
+// across lanes and read back with v_readlane.
+__device__ void toroidal_q_batch(bool act, double chi, double chim1, int mq, double (*Q)[QB],
+                                 int col) {
+  const int lane = threadIdx.x;
+  if (!act) {
+    chi = 2.0;
+    chim1 = 1.0;
+  }
   const double mu = sqrt(2.0 / (chi + 1.0));
   const double mup = sqrt(chim1 / (chi + 1.0));
   double K, E;
@@ -122,29 +150,55 @@ __device__ void toroidal_q_lane(double chi, double chim1, int mq, double (*Q)[QB
   const double q0 = mu * K;
   const double q1 = chi * mu * K - sqrt(2.0 * (chi + 1.0)) * E;
   const double a = log(chi + sqrt(chim1 * (chi + 1.0)));   // acosh(chi)
-  if (a * (mq + 1) <= 2.5) {
-    double qm = q0, qn = q1;
-    Q[0][col] = q0;
-    Q[1][col] = q1;
-    for (int n = 1; n < mq; ++n) {
-      const double qp = (4.0 * n * chi * qn - (2.0 * n - 1.0) * qm) * recip(2.0 * n + 1.0);
-      Q[n + 1][col] = qp;
-      qm = qn;
-      qn = qp;
+  const bool fwd = act && a * (mq + 1) <= 2.5;
+  const bool bwd = act && !fwd;
+  if (__ballot(fwd)) {
+    if (fwd) {
+      Q[0][col] = q0;
+      Q[1][col] = q1;
     }
-  } else {
-    // a > 2.5 / (mq + 1) here, so the start index is bounded (< 1000 for mq = 82)
-    const int start = mq + (int)fmin(ceil(20.0 / a), 4000.0) + 10;
-    double hi = 0.0, lo = 1e-200;
-    for (int n = start; n >= 1; --n) {
-      if (n <= mq) Q[n][col] = lo;
-      const double nw = (4.0 * n * chi * lo - (2.0 * n + 1.0) * hi) * recip(2.0 * n - 1.0);
-      hi = lo;
-      lo = nw;
+    double qm = q0, qn = q1, dn = 1.0;
+    // 1/(2n + 1) for 64 consecutive n at a time, one per lane, read back
+    // lane by lane (the index is the same in every lane)
+    for (int nb = 1; nb < mq; nb += 64) {
+      const double invl = recip(2.0 * (nb + lane) + 1.0);
+      const int cnt = min(64, mq - nb);
+      for (int q = 0; q < cnt; ++q) {
+        const double qp = (4.0 * dn * chi * qn - (2.0 * dn - 1.0) * qm) * readlane_f64(invl, q);
+        if (fwd) Q[nb + q + 1][col] = qp;
+        qm = qn;
+        qn = qp;
+        dn += 1.0;
+      }
     }
-    const double scale = q0 / lo;
-    Q[0][col] = q0;
-    for (int n = 1; n <= mq; ++n) Q[n][col] *= scale;
+  }
+  // backward lanes: a > 2.5 / (mq + 1), so 20 / a + 10 < 8 (mq + 1) + 10
+  int start = bwd ? mq + (int)ceil(20.0 / a) + 10 : 0;
+  start = wave_max_int(start);
+  if (start > 0) {
+    double hi = 0.0, lo = 1e-200, dn = start;
+    for (int nb = start; nb >= 1; nb -= 64) {
+      // 1/(2n - 1) for n = nb, nb - 1, ..., one per lane
+      const double invl = recip(2.0 * (nb - lane) - 1.0);
+      const int cnt = min(64, nb);
+      for (int q = 0; q < cnt; ++q) {
+        const int n = nb - q;
+        if (n <= mq && bwd) Q[n][col] = lo;
+        const double nw = (4.0 * dn * chi * lo - (2.0 * dn + 1.0) * hi) * readlane_f64(invl, q);
+        hi = lo;
+        lo = nw;
+        dn -= 1.0;
+      }
+      if (nb - cnt > mq && fabs(lo) > 1e150) {   // nothing stored yet: rescale
+        lo *= 1e-150;
+        hi *= 1e-150;
+      }
+    }
+    if (bwd) {
+      const double scale = q0 / lo;
+      Q[0][col] = q0;
+      for (int n = 1; n <= mq; ++n) Q[n][col] *= scale;
+    }
   }
 }
 
@@ -244,9 +298,10 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Hs = (x cos x - sin x)/(4 pi rho^3), x = k rho; for x < 0.5 the Taylor
-// series sum_{j>=1} (-1)^j 2j/(2j+1)! x^{2j-2} (times k^3 / 4 pi).
-__device__ __forceinline__ double smooth_h(double k, double rho) {
+// Hs = (x cos x - sin x)/(4 pi rho^3), x = k rho, given sx = sin x, cx = cos x;
+// for x < 0.5 the Taylor series sum_{j>=1} (-1)^j 2j/(2j+1)! x^{2j-2} (times
+// k^3 / 4 pi), which avoids the cancellation.
+__device__ __forceinline__ double smooth_h(double k, double rho, double sx, double cx) {
   const double x = k * rho;
   if (x < 0.5) {
     const double x2 = x * x;
@@ -264,10 +319,8 @@ __device__ __forceinline__ double smooth_h(double k, double rho) {
     p = fma(p, x2, -0.3333333333333333);
     return k * k * k * INV_4PI * p;
   }
-  double s, c;
-  sincos_cw(x, &s, &c);
   const double ir = 1.0 / rho;
-  return (x * c - s) * INV_4PI * ir * ir * ir;
+  return (x * cx - sx) * INV_4PI * ir * ir * ir;
 }
 
 // phi-frame modes m = 0..nmax of A = dr G, B = dz G for one node (all lanes),
@@ -282,14 +335,13 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int l = lane + 64 * h;
-      const double phi = TWO_PI * l / LM;
-      double sh, chh;
-      sincos_cw(0.5 * phi, &sh, &chh);
+      // sin(phi/2) with phi = 2 pi l / LM from the table e^{-2 pi i q / LD}
+      const double sh = -tw[l * (LD / (2 * LM))].y;
       const double rho = sqrt(2.0 * r * rt * (chim1 + 2.0 * sh * sh));
       double sk, ck;
       sincos_cw(k * rho, &sk, &ck);
       const double F = ck + k * rho * sk;
-      const double Hs = smooth_h(k, rho);
+      const double Hs = smooth_h(k, rho, sk, ck);
       const double cphi = 1.0 - 2.0 * sh * sh;
       M.fa[l] = make_double2(F, Hs);
       M.fb[l] = make_double2(Hs * (r - rt * cphi), 0.0);
@@ -394,14 +446,6 @@ __device__ __forceinline__ double2 modal_slot(int N, const NodeLoc& L, const Mod
     }
   }
   return out;
-}
-
-// Uniform copy of lane l's value (v_readlane on both halves).
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffull), l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // acc[l] += P_l(s_q) w_q K (lane l < 16 holds pw = P_l(s_q) w_q)
@@ -600,10 +644,9 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       const bool qlane = lane < QB && b0 + lane < nmodal;
       const int src = qlane ? S.modal_idx[b0 + lane] : 0;
       const double dls = __shfl(dl, src);
-      if (qlane) {
-        const NodeLoc L = node_local(shape, a, cc, kappa, TG, dls);
-        toroidal_q_lane(1.0 + L.chim1, L.chim1, MQ_CAP, S.Q, lane);
-      }
+      double qchim1 = 1.0;
+      if (qlane) qchim1 = node_local(shape, a, cc, kappa, TG, dls).chim1;
+      toroidal_q_batch(qlane, 1.0 + qchim1, qchim1, MQ_CAP, S.Q, lane & (QB - 1));
       __syncthreads();
       const int cnt = min(QB, nmodal - b0);
       for (int q = 0; q < cnt; ++q) {
@@ -763,7 +806,7 @@ __global__ __launch_bounds__(64) void modal_modes_kernel(const double* __restric
     sincos_cw(-TWO_PI * q / LD, &s, &cc);
     S.tw[q] = make_double2(cc, s);
   }
-  if (lane == 0) toroidal_q_lane(1.0 + chim1[pt], chim1[pt], MQ_CAP, S.Q, 0);
+  toroidal_q_batch(lane == 0, 1.0 + chim1[pt], chim1[pt], MQ_CAP, S.Q, lane & (QB - 1));
   __syncthreads();
   modal_modes(k, r[pt], rt[pt], c[pt], chim1[pt], rmrt[pt], nmax, S.Q, 0, S.u.m, S.tw);
   if (lane <= nmax) {
