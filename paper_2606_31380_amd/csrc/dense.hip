@@ -326,8 +326,9 @@ constexpr int GJB = 64;
 // workgroup of 1024 threads per matrix with the columns held in registers:
 // thread t owns rows t + 1024 r, r < R, and WL <= 16 / R columns.  Per column:
 // arg-max of |a_ik|^2 by wavefront shuffles and one LDS pass (ties to the
-// lower row), the row interchange through LDS, the pivot row scaled by its
-// owner, and the rank-1 elimination of the other rows.
+// lower row), then one LDS exchange that carries both the pivot row scaled
+// by its owner and the row it displaces, and the rank-1 elimination of the
+// other rows: two barriers per column.
 template <int R, int WL>
 __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restrict__ mats,
                                                         double2* __restrict__ pool, int c0,
@@ -341,7 +342,7 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   __shared__ double red_v[16];
   __shared__ int red_i[16];
-  __shared__ double2 swap_buf[2][WL];
+  __shared__ double2 swap_buf[1][WL];
   __shared__ double2 rowk[WL];
   double2 a[R][WL];
 #pragma unroll
@@ -393,49 +394,37 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
     }
     const int pr = bi;
     if (tid == 0) piv[(int64_t)blockIdx.x * nmax + k] = pr;
-    if (pr != k) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = tid + 1024 * r;
-        if (i == pr)
-#pragma unroll
-          for (int c = 0; c < WL; ++c) swap_buf[0][c] = a[r][c];
-        if (i == k)
-#pragma unroll
-          for (int c = 0; c < WL; ++c) swap_buf[1][c] = a[r][c];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int i = tid + 1024 * r;
-        if (i == k)
-#pragma unroll
-          for (int c = 0; c < WL; ++c) a[r][c] = swap_buf[0][c];
-        if (i == pr)
-#pragma unroll
-          for (int c = 0; c < WL; ++c) a[r][c] = swap_buf[1][c];
-      }
-    }
+    // one exchange through LDS: the owner of row pr publishes the scaled
+    // pivot row (it becomes row k), the owner of row k its old row (it
+    // becomes row pr)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (tid + 1024 * r == k) {
+      const int i = tid + 1024 * r;
+      if (i == pr) {
         const double2 d = a[r][kk];
         const double den = d.x * d.x + d.y * d.y;
         const double2 inv = make_double2(d.x / den, -d.y / den);
 #pragma unroll
         for (int c = 0; c < WL; ++c) {
           const double2 x = (c == kk) ? make_double2(1.0, 0.0) : a[r][c];
-          const double2 v = make_double2(x.x * inv.x - x.y * inv.y, x.x * inv.y + x.y * inv.x);
-          a[r][c] = v;
-          rowk[c] = v;
+          rowk[c] = make_double2(x.x * inv.x - x.y * inv.y, x.x * inv.y + x.y * inv.x);
         }
       }
+      if (i == k && pr != k)
+#pragma unroll
+        for (int c = 0; c < WL; ++c) swap_buf[0][c] = a[r][c];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = tid + 1024 * r;
-      if (i != k && i < n) {
+      if (i == k) {
+#pragma unroll
+        for (int c = 0; c < WL; ++c) a[r][c] = rowk[c];
+      } else if (i < n) {
+        if (i == pr)
+#pragma unroll
+          for (int c = 0; c < WL; ++c) a[r][c] = swap_buf[0][c];
         const double2 f = a[r][kk];
 #pragma unroll
         for (int c = 0; c < WL; ++c) {
