@@ -1,0 +1,144 @@
+"""Parity at the full sizes of the larger workloads, in the launch
+configuration the benchmark uses (autotuned), on sampled outputs the oracle
+can compute one by one:
+
+* 1000 bodies of three shapes (N = 582,592): FP64 / FP32 pair sums on sampled
+  targets, sampled self-block rows of two shapes, and a mixed solve to 1e-6
+  whose true residual is recomputed with the (sample-validated) FP64 apply;
+* 200 bent spheroids with 64 directions (N = 409,600): the 64-column FP32
+  and FP64 pair sums on sampled targets and columns (default launch choices);
+* 32 independent problems (N = 1,746,400): the batched mixed solve against
+  separate solves of sampled problems, and per-problem residuals.
+
+Tolerances: FP64 apply 1e-12, FP32 apply 1e-5 (relative over the sample),
+self-block rows 2e-11 of the row maximum, solutions 1e-6 relative residual.
+"""
+import numpy as np
+import pytest
+
+from oracle import geometry as geo
+from oracle import pairsum as opair
+from oracle import selfblock as oself
+from paper_2606_31380_amd import scenarios as sc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2606_31380_amd import qax  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def sample(n, m, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, m, replace=False))
+
+
+def true_residual(P, dirs, x, nrhs=1):
+    """||b - A x|| / ||b|| per column with the GPU FP64 operator."""
+    b = P.vec(nrhs)
+    qax.qax_rhs(P.h, dirs, b, nrhs)
+    ax = P.vec(nrhs)
+    qax.qax_apply(P.h, qax.QAX_FP64, x, ax, nrhs)
+    r = (b - ax).cpu().numpy().reshape(-1, nrhs)
+    bb = b.cpu().numpy().reshape(-1, nrhs)
+    return np.linalg.norm(r, axis=0) / np.linalg.norm(bb, axis=0)
+
+
+def test_thousand_bodies():
+    s = sc.random_mixed()
+    d = geo.discretize(s)
+    n = d.pos.shape[0]
+    rng = np.random.default_rng(0)
+    mu = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    tg = sample(n, 64, 1)
+    want = opair.pair_sum(d, s.k, mu, targets=tg, chunk=8)
+    with qax.Problem(s) as P:
+        assert P.N == n == 582592
+        qax.qax_assemble_self(P.h)
+        qax.qax_autotune(P.h, nrhs_max=1)
+        out = P.vec()
+        v = torch.from_numpy(mu).to(DEV)
+        qax.qax_pair_sum(P.h, qax.QAX_FP64, v, out)
+        assert rel(out.cpu().numpy()[tg], want) < 1e-12
+        qax.qax_pair_sum(P.h, qax.QAX_MIXED, v, out)
+        assert rel(out.cpu().numpy()[tg], want) < 1e-5
+        # self-block rows: a peanut and a sphere of the batch
+        shapes = s.bodies["shape"]
+        for bi in (int(np.nonzero(shapes == sc.PEANUT)[0][0]), int(np.nonzero(shapes == sc.SPHERE)[0][0])):
+            body = d.bodies[bi]
+            nb = body.n
+            t = torch.zeros(nb * nb, dtype=torch.complex128, device=DEV)
+            qax.qax_self_block(P.h, bi, t)
+            rows = np.array([0, nb // 2 + 3])
+            ref = oself.self_block(body, float(s.k[0]), rows=rows)
+            got = t.cpu().numpy().reshape(nb, nb)[rows]
+            assert np.abs(got - ref).max() < 2e-11 * np.abs(ref).max()
+        # mixed solve to 1e-6, true residual with the FP64 operator
+        x = P.vec()
+        info = qax.qax_solve(P.h, qax.QAX_MIXED, s.dirs, x, 1, tol=1e-6, maxit=400)
+        assert info["rel_res"] <= 1e-6
+        assert true_residual(P, s.dirs, x)[0] <= 1.05e-6
+
+
+def test_sixty_four_directions_pair_sum():
+    s = sc.lattice_like_random()
+    d = geo.discretize(s)
+    n = d.pos.shape[0]
+    nrhs = s.dirs.shape[0]
+    rng = np.random.default_rng(2)
+    mu = rng.standard_normal((n, nrhs)) + 1j * rng.standard_normal((n, nrhs))
+    tg = sample(n, 24, 3)
+    cols = np.array([0, 17, 40, 63])
+    want = opair.pair_sum(d, s.k, mu[:, cols], targets=tg, chunk=8)
+    with qax.Problem(s) as P:
+        assert P.N == n == 409600
+        v = torch.from_numpy(np.ascontiguousarray(mu.ravel())).to(DEV)
+        out = P.vec(nrhs)
+        for prec, tol in ((qax.QAX_MIXED, 1e-5), (qax.QAX_FP64, 1e-12)):
+            qax.qax_pair_sum(P.h, prec, v, out, nrhs)
+            got = out.cpu().numpy().reshape(n, nrhs)[np.ix_(tg, cols)]
+            assert rel(got, want) < tol
+
+
+def test_thirty_two_problems_batched():
+    s = sc.uneven_batch()
+    dirs = s.notes["dirs"]
+    npb = s.bodies["problem"]
+    with qax.Problem(s) as P:
+        assert P.N == 1746400
+        qax.qax_assemble_self(P.h)
+        x = P.vec()
+        info = qax.qax_solve(P.h, qax.QAX_MIXED, dirs, x, 1, tol=1e-6, maxit=400)
+        assert info["rel_res"] <= 1e-6
+        xb = x.cpu().numpy()
+        off = P.offsets
+        # per-problem true residuals (segments of the one operator)
+        b = P.vec()
+        qax.qax_rhs(P.h, dirs, b, 1)
+        ax = P.vec()
+        qax.qax_apply(P.h, qax.QAX_FP64, x, ax, 1)
+        r = (b - ax).cpu().numpy()
+        bb = b.cpu().numpy()
+        for p in range(len(s.k)):
+            idx = np.nonzero(npb == p)[0]
+            seg = slice(off[idx[0]], off[idx[-1] + 1])
+            assert np.linalg.norm(r[seg]) <= 1.05e-6 * np.linalg.norm(bb[seg])
+    # sampled problems solved alone agree with their segment of the batch
+    for p in (3, 17, 31):
+        rows = s.bodies[npb == p].copy()
+        rows["problem"] = 0
+        sp = sc.Scenario(f"p{p}", rows, np.array([s.k[p]]), dirs[p:p + 1])
+        idx = np.nonzero(npb == p)[0]
+        seg = xb[off[idx[0]]:off[idx[-1] + 1]]
+        with qax.Problem(sp) as P1:
+            qax.qax_assemble_self(P1.h)
+            x1 = P1.vec()
+            qax.qax_solve(P1.h, qax.QAX_MIXED, dirs[p:p + 1], x1, 1, tol=1e-6, maxit=400)
+            assert rel(seg, x1.cpu().numpy()) < 2e-5
