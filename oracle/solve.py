@@ -162,3 +162,44 @@ def far_field(disc, k_per_problem, mu, xhat):
     ph = np.exp(-1j * k * (xhat @ disc.pos.T))            # (ndir, N)
     nd = xhat @ disc.aw.T                                  # xhat . n |J| w
     return (ph * (-1j * k) * nd) @ mu / FOUR_PI
+
+
+def near_field(disc, k_per_problem, mu, points, problem=0, chunk=64):
+    """Double-layer potential u(x) = sum_j dG/dn_y(x, y_j) mu_j |J_j| w_j of the
+    bodies of `problem` at points (M, 3) away from every surface: the smooth
+    product rule of Section 3.1 (equation sx) applied to the representation
+    of Section 4 (equation multi-double).  mu (N,) or (N, nrhs)."""
+    mu = np.asarray(mu, dtype=np.complex128)
+    squeeze = mu.ndim == 1
+    if squeeze:
+        mu = mu[:, None]
+    k = float(np.asarray(k_per_problem)[problem])
+    src = np.nonzero(disc.problem == problem)[0]
+    pts = np.asarray(points, dtype=np.float64)
+    out = np.zeros((pts.shape[0], mu.shape[1]), dtype=np.complex128)
+    for c0 in range(0, pts.shape[0], chunk):
+        x = pts[c0:c0 + chunk]
+        d = disc.pos[src][None, :, :] - x[:, None, :]                 # y - x
+        rho = np.sqrt(np.sum(d * d, axis=-1))
+        kern = (1j * k / rho - 1.0 / rho ** 2) * np.exp(1j * k * rho) / (FOUR_PI * rho) \
+            * np.sum(disc.aw[src][None, :, :] * d, axis=-1)
+        out[c0:c0 + chunk] = kern @ mu[src]
+    return out[:, 0] if squeeze else out
+
+
+def point_source_field(k, sources, x):
+    """sum_s e^{i k |x - z_s|} / (4 pi |x - z_s|): a radiating solution outside
+    the bodies when every z_s lies inside one (the artificial solutions of the
+    numerical section).  sources (S, 3), x (M, 3) -> (M,)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros(x.shape[0], dtype=np.complex128)
+    for z in np.atleast_2d(sources):
+        r = np.linalg.norm(x - z, axis=1)
+        out += np.exp(1j * k * r) / (FOUR_PI * r)
+    return out
+
+
+def point_source_far_field(k, sources, xhat):
+    """Far-field pattern of point_source_field with u = e^{ik|x|}/|x| u_inf:
+    sum_s e^{-i k xhat.z_s} / (4 pi)."""
+    return np.exp(-1j * k * (np.asarray(xhat) @ np.atleast_2d(sources).T)).sum(axis=1) / FOUR_PI

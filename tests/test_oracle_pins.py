@@ -219,6 +219,47 @@ def test_pair_sum_exterior_sphere_closed_form():
         assert np.abs(out - ref).max() < 1e-12 * max(1.0, np.abs(ref).max())
 
 
+def test_near_field_exterior_sphere_closed_form():
+    # D[P_n](x) at points off the sphere, as the pair sum at nodes above
+    s = sc.single_sphere(0.5, 2, 32, 2.0)
+    d = geo.discretize(s)
+    a, k = 0.5, 2.0
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal((40, 3))
+    pts = u / np.linalg.norm(u, axis=1)[:, None] * rng.uniform(1.2, 4.0, (40, 1)) + d.centres[0]
+    loc = d.pos - d.centres[0]
+    for n in (0, 2, 5):
+        mu = eval_legendre(n, loc[:, 2] / a).astype(np.complex128)
+        out = solve.near_field(d, s.k, mu, pts)
+        x = pts - d.centres[0]
+        rx = np.linalg.norm(x, axis=1)
+        h = spherical_jn(n, k * rx) + 1j * spherical_yn(n, k * rx)
+        ref = 1j * k * k * a * a * spherical_jn(n, k * a, derivative=True) * h * eval_legendre(n, x[:, 2] / rx)
+        assert np.abs(out - ref).max() < 1e-11 * max(1.0, np.abs(ref).max())
+
+
+def test_artificial_point_source_solution():
+    # exterior Dirichlet data of a point source inside each body: the solved
+    # double-layer density reproduces the source field outside and its far
+    # field (end to end: self blocks, pair sums, near and far field)
+    s = sc.tiny(n_bodies=2, n_panels=2, n_theta=16, k=2.0, spacing=2.5)
+    s.bodies["kappa"] = 0.2            # congruent bodies (different rotations): one self block
+    d = geo.discretize(s)
+    z = d.centres + np.array([0.05, -0.03, 0.1])
+    b = solve.point_source_field(2.0, z, d.pos)
+    blk = solve.self_blocks(d, s.k, body_ids=[0])[0]
+    blocks = {0: blk, 1: blk}
+    mu = np.linalg.solve(solve.dense_matrix_fast(d, s.k, blocks), b)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((30, 3))
+    pts = u / np.linalg.norm(u, axis=1)[:, None] * 6.0 + d.centres.mean(axis=0)
+    err = solve.near_field(d, s.k, mu, pts) - solve.point_source_field(2.0, z, pts)
+    assert np.abs(err).max() < 1e-8 * np.abs(solve.point_source_field(2.0, z, pts)).max()
+    xhat = u / np.linalg.norm(u, axis=1)[:, None]
+    ff = solve.far_field(d, s.k, mu, xhat)
+    assert np.abs(ff - solve.point_source_far_field(2.0, z, xhat)).max() < 1e-8
+
+
 def test_pair_sum_rigid_motion_invariance():
     s = sc.tiny(n_bodies=3, n_panels=1, n_theta=8, k=4.0)
     d1 = geo.discretize(s)
