@@ -89,6 +89,44 @@ def cpu_baseline(scen, budget_s=12.0):
             "sample": f"{m} of {n} target rows of the same workload ({pairs:.3e} pairs, {dt:.1f} s, numpy FP64, 1 thread)"}
 
 
+def artificial_solution_error(qax, h, scen, N, dev):
+    """Relative error of the near and far field recovered from the boundary
+    values of point sources inside the bodies (FP64 solve at 1e-12, mixed at
+    1e-8), on 200 points of a shell around the bodies."""
+    import torch
+    k = float(scen.k[0])
+    pos = torch.zeros(N * 3, dtype=torch.float64, device=dev)
+    aw = torch.zeros_like(pos)
+    qax.qax_nodes(h, pos, aw)
+    y = pos.cpu().numpy().reshape(-1, 3)
+    cen = np.stack([scen.bodies["cx"], scen.bodies["cy"], scen.bodies["cz"]], 1)
+    z = cen + np.array([0.04, -0.03, 0.08])
+
+    def field(x):
+        r = np.linalg.norm(x[:, None, :] - z[None, :, :], axis=2)
+        return (np.exp(1j * k * r) / (4 * math.pi * r)).sum(axis=1)
+    b = torch.from_numpy(field(y)).to(dev)
+    c = cen.mean(axis=0)
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal((200, 3))
+    xhat = u / np.linalg.norm(u, axis=1)[:, None]
+    pts = c + xhat * (np.abs(cen - c).max() + 6.0)
+    exact = field(pts)
+    ff_exact = np.exp(-1j * k * (xhat @ z.T)).sum(axis=1) / (4 * math.pi)
+    out = {}
+    for prec, tol, name in ((qax.QAX_FP64, 1e-12, "fp64"), (qax.QAX_MIXED, 1e-8, "mixed")):
+        mu = torch.zeros(N, dtype=torch.complex128, device=dev)
+        qax.qax_solve_rhs(h, prec, b, mu, 1, tol=tol, maxit=1000)
+        un = torch.zeros(pts.shape[0], dtype=torch.complex128, device=dev)
+        qax.qax_nearfield(h, mu, pts, un)
+        ff = torch.zeros(pts.shape[0], dtype=torch.complex128, device=dev)
+        qax.qax_farfield(h, mu, xhat, ff)
+        out[name] = {"tol": tol,
+                     "near_rel_err": float(np.linalg.norm(un.cpu().numpy() - exact) / np.linalg.norm(exact)),
+                     "far_rel_err": float(np.linalg.norm(ff.cpu().numpy() - ff_exact) / np.linalg.norm(ff_exact))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +215,18 @@ def main():
     ps64 = qax.qax_timing(h, qax.QAX_K_PAIRSUM_FP64)
     ps32 = qax.qax_timing(h, qax.QAX_K_PAIRSUM_FP32)
     qax.qax_set_timing(h, False)
+    # accuracy against an exact solution: boundary values of point sources
+    # inside the bodies, the solved density's field on a shell around them
+    art = artificial_solution_error(qax, h, scen, N, dev)
+    # near-field throughput on a 200 x 200 grid of points on a shell
+    pts = 10.0 * far_grid(200)
+    un = torch.zeros(pts.shape[0], dtype=torch.complex128, device=dev)
+    qax.qax_nearfield(h, v, pts, un)
+    torch.cuda.synchronize()
+    t0n = time.perf_counter()
+    qax.qax_nearfield(h, v, pts, un)
+    torch.cuda.synchronize()
+    t_near = time.perf_counter() - t0n
 
     # rooflines of the timed kernels; "roofline" is the dominant one
     nb = scen.nodes_per_body().astype(np.float64)
@@ -240,6 +290,8 @@ def main():
             "fp64_pairs_per_s": P * ps64[0] / (ps64[1] / 1e3) if ps64[1] > 0 else None,
             "fp32_ms": ps32[1] / max(ps32[0], 1), "fp64_ms": ps64[1] / max(ps64[0], 1)},
         "kernel_ms_per_step": {k: v[1] / args.steps for k, v in ktimes.items()},
+        "artificial_solution": art,
+        "nearfield_40000_points": {"s": t_near, "point_source_pairs_per_s": pts.shape[0] * N / t_near},
         "solver_iters_per_step": {"fp32_pair_sums": n32 / args.steps, "fp64_pair_sums": n64 / args.steps},
         "roofline": roof,
         "tuning": tuning,

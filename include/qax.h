@@ -155,6 +155,14 @@ qax_status qax_rhs(qax_problem* p, const double* dirs, int32_t nrhs, void* d_out
 qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dirs, int32_t nrhs,
                      double tol, int32_t maxit, void* d_mu_out, qax_info* info);
 
+/* As qax_solve with the right-hand side given by the caller instead of plane
+ * waves: d_rhs (device, N x nrhs complex128, not aliasing d_mu_out), e.g. the
+ * boundary values of a known radiating field (the artificial solutions of
+ * Section 6: solving with them and evaluating qax_nearfield / qax_farfield
+ * recovers the field). */
+qax_status qax_solve_rhs(qax_problem* p, qax_prec prec, const void* d_rhs, int32_t nrhs,
+                         double tol, int32_t maxit, void* d_mu_out, qax_info* info);
+
 /* Dense direct solve of the full system (all blocks assembled on the device,
  * Gauss-Jordan inversion in FP64) for N <= 8192; d_mu_out N x nrhs. */
 qax_status qax_solve_dense(qax_problem* p, const double* dirs, int32_t nrhs, void* d_mu_out);
@@ -164,6 +172,16 @@ qax_status qax_solve_dense(qax_problem* p, const double* dirs, int32_t nrhs, voi
  * xhat: host, n_dirs x 3.  d_u_inf: n_dirs x nrhs complex128. */
 qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrhs,
                         const double* xhat, int32_t n_dirs, void* d_u_inf);
+
+/* Scattered field at points off the surfaces: the double-layer potential of
+ * the density of one problem, u(x) = sum_j dG/dn_y(x, y_j) mu_j |J_j| w_j
+ * (Section 4, equation multi-double, with the smooth rule of Section 3.1,
+ * equation sx).  Accurate for points whose distance to every surface is at
+ * least about one panel length (no near-singular quadrature).  pts: host,
+ * n_pts x 3 (finite); problem: 0 .. n_problems - 1; d_mu: N x nrhs, d_u:
+ * n_pts x nrhs complex128 (device).  FP64. */
+qax_status qax_nearfield(qax_problem* p, const void* d_mu, int32_t nrhs, const double* pts,
+                         int64_t n_pts, int32_t problem, void* d_u);
 
 /* Test hook for the modal engine (Section 3.3): phi-frame modes m = 0..nmax of
  * the source derivatives dr G and dz G of the Helmholtz kernel for n_pts

@@ -506,6 +506,30 @@ extern "C" qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrh
   return sync(p, "qax_farfield");
 }
 
+extern "C" qax_status qax_nearfield(qax_problem* p, const void* d_mu, int32_t nrhs, const double* pts,
+                                    int64_t n_pts, int32_t problem, void* d_u) {
+  if (!p) return QAX_ERR_ARG;
+  qax_status st = check_vec_call(p, d_mu, d_u, nrhs, 1);
+  if (st != QAX_OK) return st;
+  if (!pts || n_pts < 1 || n_pts > (int64_t)1 << 28) return fail(p, QAX_ERR_ARG, "qax_nearfield: no points");
+  if (problem < 0 || problem >= p->n_problems) return fail(p, QAX_ERR_ARG, "qax_nearfield: bad problem index");
+  std::vector<double> soa((size_t)n_pts * 3);
+  for (int64_t i = 0; i < n_pts; ++i)
+    for (int c = 0; c < 3; ++c) {
+      const double v = pts[3 * i + c];
+      if (!is_finite(v)) return fail(p, QAX_ERR_ARG, "qax_nearfield: non-finite point");
+      soa[(size_t)c * n_pts + i] = v;
+    }
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  const int slots = nearfield_slots(n_pts, cu_count(p->device));
+  QBUF(dp, double, "nf_points", soa.size() * 8);
+  QBUF(part, double, "nf_partial", (size_t)slots * n_pts * nrhs * 16);
+  QCHECK(hipMemcpyAsync(dp, soa.data(), soa.size() * 8, hipMemcpyHostToDevice, p->stream), "copy points");
+  QCHECK(launch_nearfield(p, (const double*)d_mu, nrhs, dp, n_pts, problem, slots, part, (double*)d_u),
+         "nearfield");
+  return sync(p, "qax_nearfield");
+}
+
 extern "C" qax_status qax_modal_modes(qax_problem* p, int32_t n_pts, const double* d_r,
                                       const double* d_rt, const double* d_c, const double* d_chim1,
                                       const double* d_rmrt, double k, int32_t nmax, void* d_A,
@@ -575,10 +599,11 @@ static qax_status setup_krylov(qax_problem* p, int nrhs, int mmax, Krylov& K) {
   return QAX_OK;
 }
 
-extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dirs, int32_t nrhs,
-                                double tol, int32_t maxit, void* d_mu_out, qax_info* info) {
-  if (!p) return QAX_ERR_ARG;
-  qax_status st = check_vec_call(p, dirs, d_mu_out, nrhs, 2);
+// Solve with the plane-wave right-hand sides of `dirs` (host) or, when dirs is
+// null, the caller's device right-hand side d_rhs.
+static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, const double* d_rhs,
+                             int32_t nrhs, double tol, int32_t maxit, void* d_mu_out, qax_info* info) {
+  qax_status st = check_vec_call(p, dirs ? (const void*)dirs : (const void*)d_rhs, d_mu_out, nrhs, 2);
   if (st != QAX_OK) return st;
   if (prec != QAX_FP64 && prec != QAX_MIXED) return fail(p, QAX_ERR_ARG, "bad precision");
   if (!(tol > 0) || !is_finite(tol) || maxit < 1) return fail(p, QAX_ERR_ARG, "qax_solve: bad tol / maxit");
@@ -600,10 +625,14 @@ extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dir
   QBUF(b, double, "kry_b", (size_t)vs * 8);
   QBUF(hd, double, "kry_h", (size_t)(2 * m + 4) * nseg * 16);
   double* x = (double*)d_mu_out;
-  double* dd = nullptr;
-  st = upload_dirs(p, dirs, nrhs, &dd);
-  if (st != QAX_OK) return st;
-  QCHECK(launch_rhs(p, dd, nrhs, b), "rhs");
+  if (dirs) {
+    double* dd = nullptr;
+    st = upload_dirs(p, dirs, nrhs, &dd);
+    if (st != QAX_OK) return st;
+    QCHECK(launch_rhs(p, dd, nrhs, b), "rhs");
+  } else {
+    QCHECK(hipMemcpyAsync(b, d_rhs, (size_t)vs * 8, hipMemcpyDeviceToDevice, p->stream), "copy rhs");
+  }
   QCHECK(hipMemsetAsync(x, 0, (size_t)vs * 8, p->stream), "zero x");
 
   const int inner_prec = prec;
@@ -1118,4 +1147,19 @@ extern "C" qax_status qax_set_tuning(qax_problem* p, const qax_tuning_info* in) 
   QCHECK(upload_pair_plan(p, QAX_FP64, cus), "pair-sum plan");
   QCHECK(upload_pair_plan(p, QAX_MIXED, cus), "pair-sum plan");
   return QAX_OK;
+}
+
+extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dirs, int32_t nrhs,
+                                double tol, int32_t maxit, void* d_mu_out, qax_info* info) {
+  if (!p) return QAX_ERR_ARG;
+  if (!dirs) return fail(p, QAX_ERR_ARG, "qax_solve: null directions");
+  return solve_core(p, prec, dirs, nullptr, nrhs, tol, maxit, d_mu_out, info);
+}
+
+extern "C" qax_status qax_solve_rhs(qax_problem* p, qax_prec prec, const void* d_rhs, int32_t nrhs,
+                                    double tol, int32_t maxit, void* d_mu_out, qax_info* info) {
+  if (!p) return QAX_ERR_ARG;
+  if (!d_rhs) return fail(p, QAX_ERR_ARG, "qax_solve_rhs: null right-hand side");
+  if (d_rhs == d_mu_out) return fail(p, QAX_ERR_ARG, "qax_solve_rhs: rhs and solution must not alias");
+  return solve_core(p, prec, nullptr, (const double*)d_rhs, nrhs, tol, maxit, d_mu_out, info);
 }

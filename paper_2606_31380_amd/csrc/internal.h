@@ -170,6 +170,9 @@ void plan_pair_sum(qax_problem* p, int prec, int cu_count);
 hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count);
 // launch choices the kernels support (LDS within 64 KB)
 bool pair_config_ok(int prec, int tpb, int nrc);
+int nearfield_slots(int64_t M, int cu_count);
+hipError_t launch_nearfield(qax_problem* p, const double* mu, int nrhs, const double* pts, int64_t M,
+                            int problem, int slots, double* partial, double* u);
 hipError_t ensure_gemm_tasks(qax_problem* p);
 
 // dense.hip

@@ -50,7 +50,8 @@ _LIB = None
 EXPORTS = ["qax_create", "qax_destroy", "qax_last_error", "qax_build", "qax_size", "qax_nodes",
            "qax_assemble_self", "qax_self_block", "qax_pair_sum", "qax_block_apply", "qax_apply",
            "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes",
-           "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning", "qax_set_graphs"]
+           "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning", "qax_set_graphs",
+           "qax_solve_rhs", "qax_nearfield"]
 (QAX_K_PAIRSUM_FP64, QAX_K_PAIRSUM_FP32, QAX_K_BLOCK_APPLY, QAX_K_SELF_ASSEMBLY, QAX_K_INVERT,
  QAX_K_INVERT_UPDATE, QAX_K_BLOCK_APPLY_F32) = range(7)
 KERNEL_NAMES = ["pair_sum_fp64", "pair_sum_fp32", "block_apply", "self_assembly", "invert",
@@ -85,6 +86,8 @@ def lib():
         "qax_rhs": (C.c_int, [vp, pd, i32, vp]),
         "qax_solve": (C.c_int, [vp, C.c_int, pd, i32, d, i32, vp, C.POINTER(qax_info)]),
         "qax_solve_dense": (C.c_int, [vp, pd, i32, vp]),
+        "qax_solve_rhs": (C.c_int, [vp, C.c_int, vp, i32, d, i32, vp, C.POINTER(qax_info)]),
+        "qax_nearfield": (C.c_int, [vp, vp, i32, pd, i64, i32, vp]),
         "qax_farfield": (C.c_int, [vp, vp, i32, pd, i32, vp]),
         "qax_modal_modes": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, d, i32, vp, vp]),
         "qax_set_timing": (C.c_int, [vp, i32]),
@@ -199,6 +202,21 @@ def qax_solve(h, prec, dirs, mu_out, nrhs=1, tol=1e-8, maxit=500, raise_noconv=T
         _check(h, st)
     return {"status": st, "iters": info.iters, "outer_iters": info.outer_iters,
             "rel_res": info.rel_res, "t_solve_s": info.t_solve_s}
+
+
+def qax_solve_rhs(h, prec, rhs, mu_out, nrhs=1, tol=1e-8, maxit=500, raise_noconv=True):
+    info = qax_info()
+    st = lib().qax_solve_rhs(h, int(prec), _ptr(rhs), int(nrhs), float(tol), int(maxit),
+                             _ptr(mu_out), C.byref(info))
+    if st != QAX_OK and (st != QAX_ERR_NOCONV or raise_noconv):
+        _check(h, st)
+    return {"status": st, "iters": info.iters, "outer_iters": info.outer_iters,
+            "rel_res": info.rel_res, "t_solve_s": info.t_solve_s}
+
+
+def qax_nearfield(h, mu, pts, u, nrhs=1, problem=0):
+    x = np.ascontiguousarray(pts, dtype=np.float64)
+    _check(h, lib().qax_nearfield(h, _ptr(mu), int(nrhs), _dptr(x), x.shape[0], int(problem), _ptr(u)))
 
 
 def qax_solve_dense(h, dirs, mu_out, nrhs=1):
