@@ -334,6 +334,41 @@ def _gj_from_modes(N, A, B, alpha, r, dr, dz, dp, dq):
     return (Km @ E) / (2.0 * N)
 
 
+def gj_sl_modal(k, N, loc, L=256):
+    """G^S_j(x, s) = int G^k(x, y(s, theta)) L_j(theta) dtheta for the
+    single-layer kernel G^k = e^{ik rho}/(4 pi rho) (Section 3.3, equations
+    modalgreen, conv, I1): phi-frame modes of G (helmholtz_g_modes), the shift
+    to the theta frame by e^{-i m alpha}, the inverse DFT as for the double
+    layer (the density times |J| is what the basis interpolates)."""
+    r, rt, c, chim1 = loc["r"], loc["rt"], loc["c"], loc["chim1"]
+    G = helmholtz_g_modes(k, r, rt, c, 1.0 + chim1, chim1, N, L=L)
+    ms = np.arange(-N, N + 1)
+    Km = np.exp(-1j * ms[None, :] * loc["alpha"][:, None]) * G[:, np.abs(ms)]
+    wts = np.ones(2 * N + 1)
+    wts[0] = wts[-1] = 0.5
+    thj = np.arange(2 * N) * math.pi / N
+    E = np.exp(1j * ms[:, None] * thj[None, :]) * wts[:, None]
+    return (Km @ E) / (2.0 * N)
+
+
+def sl_kernel(k, x, y):
+    """G^k(x, y) = e^{ik rho}/(4 pi rho) (Section 2, the Green's function)."""
+    d = y - x
+    rho = np.sqrt(np.sum(d * d, axis=-1))
+    return np.exp(1j * k * rho) / (FOUR_PI * rho)
+
+
+def gj_sl_direct(k, N, x, sgeo, L=512):
+    """G^S_j by the trapezoidal rule on L azimuthal points (target away from
+    the source ring)."""
+    th = TWO_PI * np.arange(L) / L
+    ct, st = np.cos(th)[None, :], np.sin(th)[None, :]
+    g = {kk: v[:, None] for kk, v in sgeo.items()}
+    y = np.stack(np.broadcast_arrays(g["r"] * ct + g["p"], g["r"] * st + g["q"], g["z"] + 0 * ct), axis=-1)
+    K = sl_kernel(k, x[:, None, :], y)
+    return (TWO_PI / L) * (K @ lagrange_trig(N, th))
+
+
 def dl_kernel_area(k, x, y, n_area):
     """K(x, y) = grad_y G^k(x, y) . N = e^{ik rho}(ik rho - 1)/(4 pi rho^3) (y - x).N
     (Section 3.2, equations normal-derivative and dgdrho)."""

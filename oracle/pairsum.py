@@ -15,8 +15,10 @@ import numpy as np
 FOUR_PI = 4.0 * math.pi
 
 
-def pair_sum(disc, k_per_problem, mu, targets=None, chunk=256):
-    """mu: (N,) or (N, nrhs) complex.  Returns w at the requested targets."""
+def pair_sum(disc, k_per_problem, mu, targets=None, chunk=256, eta=None):
+    """mu: (N,) or (N, nrhs) complex.  Returns w at the requested targets.
+    With eta, the combined-field kernel: double layer - i eta single layer,
+    the single layer as G(x, y_j) |J_j| w_j (|J| w = |aw|)."""
     mu = np.asarray(mu, dtype=np.complex128)
     squeeze = mu.ndim == 1
     if squeeze:
@@ -37,6 +39,9 @@ def pair_sum(disc, k_per_problem, mu, targets=None, chunk=256):
             rho_safe = np.where(same, 1.0, rho)
             kern = (1j * k / rho_safe - 1.0 / rho_safe ** 2) * np.exp(1j * k * rho_safe) \
                 / (FOUR_PI * rho_safe) * np.sum(disc.aw[src][None, :, :] * d, axis=-1)
+            if eta is not None:
+                w = np.linalg.norm(disc.aw[src], axis=1)[None, :]
+                kern = kern - 1j * eta * np.exp(1j * k * rho_safe) / (FOUR_PI * rho_safe) * w
             kern = np.where(same, 0.0, kern)
             out[c0 + sel] = kern @ mu[src]
     return out[:, 0] if squeeze else out

@@ -113,8 +113,26 @@ def gj(k, N, disc, t_t, th_t, dl):
     return out
 
 
-def self_block(disc: geo.BodyDisc, k: float, rows=None, chunk=4000):
-    """Rows of B = 1/2 I + D for one body in its own frame (complex128)."""
+def gj_sl(k, N, disc, t_t, th_t, dl):
+    """Single-layer G^S_j for many (target, s) pairs, routes as in gj."""
+    loc = modal.local_frame_rel(disc.shape, disc.a, disc.c, disc.kappa, t_t, th_t, dl)
+    out = np.zeros((t_t.shape[0], 2 * N), dtype=np.complex128)
+    near = loc["chim1"] < CHI_SPLIT
+    if np.any(near):
+        out[near] = modal.gj_sl_modal(k, N, {kk: v[near] for kk, v in loc.items()}, L=L_MODAL)
+    if np.any(~near):
+        far = ~near
+        x, _ = geo.surface_point_normal(disc.shape, disc.a, disc.c, disc.kappa, t_t[far], th_t[far])
+        sg = slice_geometry(disc, t_t[far] + dl[far])
+        out[far] = modal.gj_sl_direct(k, N, x, sg, L=L_DIRECT)
+    return out
+
+
+def self_block(disc: geo.BodyDisc, k: float, rows=None, chunk=4000, kind="dl"):
+    """Rows of B = 1/2 I + D (kind "dl") or of the single-layer block S
+    (kind "sl": the density times |J| is interpolated, so column (i, l, j)
+    carries |J| at its node; far panels use G |J| (pi/N) omega) for one body
+    in its own frame (complex128)."""
     n = disc.n
     nth = disc.n_theta
     N = nth // 2
@@ -136,8 +154,12 @@ def self_block(disc: geo.BodyDisc, k: float, rows=None, chunk=4000):
                 rec_w.append(w)
             else:
                 cols = slice(i * per_panel, (i + 1) * per_panel)
-                out[ri, cols] = modal.dl_kernel_area(
-                    k, disc.y0[T][None, :], disc.y0[cols], disc.n0[cols]) * disc.w[cols]
+                if kind == "sl":
+                    # |J| of the column is applied to the whole row below
+                    out[ri, cols] = modal.sl_kernel(k, disc.y0[T][None, :], disc.y0[cols]) * disc.w[cols]
+                else:
+                    out[ri, cols] = modal.dl_kernel_area(
+                        k, disc.y0[T][None, :], disc.y0[cols], disc.n0[cols]) * disc.w[cols]
     rr = np.concatenate(rec_row)
     pp = np.concatenate(rec_pan)
     ss = np.concatenate(rec_s)      # offsets dl = s - t_T
@@ -147,7 +169,7 @@ def self_block(disc: geo.BodyDisc, k: float, rows=None, chunk=4000):
     for c0 in range(0, rr.shape[0], chunk):
         sl = slice(c0, c0 + chunk)
         tt = t_row[rr[sl]]
-        G = gj(k, N, disc, tt, th_row[rr[sl]], ss[sl])              # (P, 2N)
+        G = (gj_sl if kind == "sl" else gj)(k, N, disc, tt, th_row[rr[sl]], ss[sl])   # (P, 2N)
         s_abs = tt + ss[sl]
         for i in np.unique(pp[sl]):
             m = pp[sl] == i
@@ -159,5 +181,14 @@ def self_block(disc: geo.BodyDisc, k: float, rows=None, chunk=4000):
             blk = np.zeros((rows.shape[0], per_panel), dtype=np.complex128)
             np.add.at(blk, rows_i, contrib.reshape(contrib.shape[0], -1))
             out[:, cols] += blk
+    if kind == "sl":
+        out *= np.linalg.norm(disc.n0, axis=1)[None, :]       # |J| of the column node
+        return out
     out[np.arange(rows.shape[0]), rows] += 0.5
     return out
+
+
+def self_block_cf(disc: geo.BodyDisc, k: float, eta: float, rows=None):
+    """Rows of the combined-field block 1/2 I + D - i eta S (the remark on
+    combined fields in Section 2)."""
+    return self_block(disc, k, rows) - 1j * eta * self_block(disc, k, rows, kind="sl")

@@ -9,6 +9,8 @@
 * dense LU (numpy / LAPACK) and right-preconditioned restarted GMRES with the
   block-diagonal preconditioner built from the self blocks (Section 6, the
   paragraph on the hybrid solver);
+* the combined-field variant 1/2 I + D - i eta S (eta given): single-layer
+  self blocks with the density times |J| interpolated, G |J| w between bodies;
 * far field of the double-layer density:
   u_inf(xhat) = (1/4 pi) sum_j (-i k xhat.n_j) e^{-i k xhat.y_j} mu_j |J_j| w_j
   (Section 6 defines the single-layer form; the double-layer form follows from
@@ -32,12 +34,17 @@ def rhs_planewave(disc, k_per_problem, dirs):
     return -np.exp(1j * k[:, None] * (disc.pos @ np.asarray(dirs).T))
 
 
-def self_blocks(disc, k_per_problem, body_ids=None):
+def self_blocks(disc, k_per_problem, body_ids=None, eta=None):
+    """Self blocks 1/2 I + D (eta None) or 1/2 I + D - i eta S."""
     body_ids = range(len(disc.bodies)) if body_ids is None else body_ids
     out = {}
     for b in body_ids:
         p = disc.problem[disc.offsets[b]]
-        out[b] = selfblock.self_block(disc.bodies[b], float(k_per_problem[p]))
+        kp = float(k_per_problem[p])
+        if eta is None:
+            out[b] = selfblock.self_block(disc.bodies[b], kp)
+        else:
+            out[b] = selfblock.self_block_cf(disc.bodies[b], kp, eta)
     return out
 
 
@@ -55,8 +62,9 @@ def dense_matrix(disc, k_per_problem, blocks):
     return A
 
 
-def dense_matrix_fast(disc, k_per_problem, blocks):
-    """Same matrix, off-diagonal entries written directly from the kernel."""
+def dense_matrix_fast(disc, k_per_problem, blocks, eta=None):
+    """Same matrix, off-diagonal entries written directly from the kernel
+    (combined field with eta)."""
     n = disc.pos.shape[0]
     k = np.asarray(k_per_problem)[disc.problem]
     d = disc.pos[None, :, :] - disc.pos[:, None, :]
@@ -66,6 +74,8 @@ def dense_matrix_fast(disc, k_per_problem, blocks):
     kk = k[:, None]
     A = (1j * kk / rs - 1.0 / rs ** 2) * np.exp(1j * kk * rs) / (FOUR_PI * rs) \
         * np.sum(disc.aw[None, :, :] * d, axis=-1)
+    if eta is not None:
+        A = A - 1j * eta * np.exp(1j * kk * rs) / (FOUR_PI * rs) * np.linalg.norm(disc.aw, axis=1)[None, :]
     A = np.where(same, 0.0, A)
     for b, B in blocks.items():
         s = slice(disc.offsets[b], disc.offsets[b + 1])
@@ -73,9 +83,9 @@ def dense_matrix_fast(disc, k_per_problem, blocks):
     return A
 
 
-def apply_operator(disc, k_per_problem, blocks, mu):
-    """(1/2 I + D) mu, matrix-free for the inter-body part."""
-    out = pairsum.pair_sum(disc, k_per_problem, mu)
+def apply_operator(disc, k_per_problem, blocks, mu, eta=None):
+    """(1/2 I + D) mu (or the combined field), matrix-free between bodies."""
+    out = pairsum.pair_sum(disc, k_per_problem, mu, eta=eta)
     for b, B in blocks.items():
         s = slice(disc.offsets[b], disc.offsets[b + 1])
         out[s] += B @ mu[s]
@@ -138,10 +148,12 @@ def gmres(apply_a, apply_minv, b, tol=1e-10, restart=100, maxit=1000):
     return x, its, hist
 
 
-def solve(disc, k_per_problem, blocks, b, method="gmres", tol=1e-10, restart=100, maxit=1000):
-    """Solve (1/2 I + D) mu = b; b is (N,) complex."""
+def solve(disc, k_per_problem, blocks, b, method="gmres", tol=1e-10, restart=100, maxit=1000,
+          eta=None):
+    """Solve (1/2 I + D) mu = b (combined field with eta; blocks to match);
+    b is (N,) complex."""
     if method == "dense":
-        A = dense_matrix_fast(disc, k_per_problem, blocks)
+        A = dense_matrix_fast(disc, k_per_problem, blocks, eta=eta)
         return np.linalg.solve(A, b), 0, []
     inv = {bb: np.linalg.inv(B) for bb, B in blocks.items()}
 
@@ -152,19 +164,23 @@ def solve(disc, k_per_problem, blocks, b, method="gmres", tol=1e-10, restart=100
             out[s] = Bi @ v[s]
         return out
 
-    return gmres(lambda v: apply_operator(disc, k_per_problem, blocks, v), minv, b,
+    return gmres(lambda v: apply_operator(disc, k_per_problem, blocks, v, eta=eta), minv, b,
                  tol=tol, restart=restart, maxit=maxit)
 
 
-def far_field(disc, k_per_problem, mu, xhat):
-    """u_inf at unit directions xhat (ndir, 3); mu (N,) -> (ndir,)."""
+def far_field(disc, k_per_problem, mu, xhat, eta=None):
+    """u_inf at unit directions xhat (ndir, 3); mu (N,) -> (ndir,).  With eta
+    the combined field adds - i eta (1/4 pi) sum_j e^{-i k xhat.y_j} mu_j |J_j| w_j."""
     k = float(np.asarray(k_per_problem)[0])
     ph = np.exp(-1j * k * (xhat @ disc.pos.T))            # (ndir, N)
     nd = xhat @ disc.aw.T                                  # xhat . n |J| w
-    return (ph * (-1j * k) * nd) @ mu / FOUR_PI
+    f = (-1j * k) * nd
+    if eta is not None:
+        f = f - 1j * eta * np.linalg.norm(disc.aw, axis=1)[None, :]
+    return (ph * f) @ mu / FOUR_PI
 
 
-def near_field(disc, k_per_problem, mu, points, problem=0, chunk=64):
+def near_field(disc, k_per_problem, mu, points, problem=0, chunk=64, eta=None):
     """Double-layer potential u(x) = sum_j dG/dn_y(x, y_j) mu_j |J_j| w_j of the
     bodies of `problem` at points (M, 3) away from every surface: the smooth
     product rule of Section 3.1 (equation sx) applied to the representation
@@ -183,6 +199,9 @@ def near_field(disc, k_per_problem, mu, points, problem=0, chunk=64):
         rho = np.sqrt(np.sum(d * d, axis=-1))
         kern = (1j * k / rho - 1.0 / rho ** 2) * np.exp(1j * k * rho) / (FOUR_PI * rho) \
             * np.sum(disc.aw[src][None, :, :] * d, axis=-1)
+        if eta is not None:
+            kern = kern - 1j * eta * np.exp(1j * k * rho) / (FOUR_PI * rho) \
+                * np.linalg.norm(disc.aw[src], axis=1)[None, :]
         out[c0:c0 + chunk] = kern @ mu[src]
     return out[:, 0] if squeeze else out
 

@@ -296,6 +296,112 @@ def test_mie_sound_soft_sphere():
     assert np.abs(u - _mie_far(2.0, 0.5, g)).max() < 1e-10
 
 
+# ---------------------------------------------------------------- combined field
+def _axisym_block(body, k, kind="dl"):
+    """Full self block of an axisymmetric body (kappa = 0) from its rows at
+    azimuth 0: rotating the target by theta_j shifts every column's azimuth."""
+    nth = body.n_theta
+    rows0 = np.arange(0, body.n, nth)
+    B0 = selfblock.self_block(body, k, rows=rows0, kind=kind)       # (n / nth, n)
+    nrow = rows0.shape[0]
+    out = np.zeros((body.n, body.n), dtype=np.complex128)
+    cols = np.arange(body.n)
+    base, cj = cols - cols % nth, cols % nth
+    for j in range(nth):
+        out[j::nth, :] = B0[:, base + (cj - j) % nth]
+    assert out.shape[0] == nrow * nth
+    return out
+
+
+def test_axisymmetric_block_expansion():
+    # the shift rule used below against directly computed rows
+    body = geo.discretize(sc.single_sphere(0.5, 1, 8, 2.0)).bodies[0]
+    full = _axisym_block(body, 2.0, kind="sl")
+    rows = np.array([3, 21, 77])
+    assert np.abs(full[rows] - selfblock.self_block(body, 2.0, rows=rows, kind="sl")).max() < 1e-13
+
+
+def test_sphere_single_layer_eigenvalues():
+    # S[P_n] = i k a^2 j_n(ka) h_n(ka) P_n on a sphere (zonal harmonics)
+    a, k = 0.5, 2.0
+    d = geo.discretize(sc.single_sphere(a, 2, 16, k))
+    body = d.bodies[0]
+    rows = np.arange(0, body.n, 29)
+    S = selfblock.self_block(body, k, rows=rows, kind="sl")
+    for n in range(4):
+        v = eval_legendre(n, body.y0[:, 2] / a)
+        lam = 1j * k * a * a * spherical_jn(n, k * a) * (spherical_jn(n, k * a) + 1j * spherical_yn(n, k * a))
+        assert np.abs(S @ v - lam * v[rows]).max() < 1e-10 * np.abs(lam * v[rows]).max()
+
+
+def _interior_neumann_k(a=0.5):
+    # first zero of j_1' (an interior Neumann eigenvalue of the sphere)
+    from scipy.optimize import brentq
+    return brentq(lambda x: spherical_jn(1, x, derivative=True), 1.5, 2.5) / a
+
+
+def test_combined_field_mie_and_interior_resonance():
+    # at an interior Neumann eigenvalue the double-layer system is singular
+    # (its n = 1 eigenvalue i (ka)^2 j_1'(ka) h_1(ka) vanishes); the combined
+    # field D - i eta S still reproduces the Mie far field
+    a = 0.5
+    k = _interior_neumann_k(a)
+    s = sc.single_sphere(a, 2, 16, k)
+    d = geo.discretize(s)
+    b = solve.rhs_planewave(d, s.k, s.dirs)[:, 0]
+    g = np.array([0.0, 0.7, math.pi / 2, 2.5, math.pi])
+    xh = np.stack([np.sin(g), 0 * g, np.cos(g)], axis=1)
+    D = _axisym_block(d.bodies[0], k)
+    cf = D - 1j * k * _axisym_block(d.bodies[0], k, kind="sl")
+    bl = {0: cf}
+    mu, _, _ = solve.solve(d, s.k, bl, b, method="dense", eta=k)
+    u = solve.far_field(d, s.k, mu, xh, eta=k)
+    assert np.abs(u - _mie_far(k, a, g)).max() < 1e-9
+    sv = np.linalg.svd(D, compute_uv=False)
+    svc = np.linalg.svd(cf, compute_uv=False)
+    assert sv.min() < 1e-6 * sv.max() and svc.min() > 0.05 * svc.max()
+
+
+def test_combined_field_artificial_solution():
+    s = sc.tiny(n_bodies=2, n_panels=2, n_theta=16, k=2.0, spacing=2.5)
+    s.bodies["kappa"] = 0.0            # axisymmetric (rotated) spheroids: blocks by shifts
+    d = geo.discretize(s)
+    eta = 2.0
+    z = d.centres + np.array([0.05, -0.03, 0.1])
+    b = solve.point_source_field(2.0, z, d.pos)
+    blk = _axisym_block(d.bodies[0], 2.0) - 1j * eta * _axisym_block(d.bodies[0], 2.0, kind="sl")
+    rows = np.array([5, 300])           # the shortcut against direct rows of the combined block
+    assert np.abs(blk[rows] - selfblock.self_block_cf(d.bodies[0], 2.0, eta, rows=rows)).max() < 1e-12
+    mu = np.linalg.solve(solve.dense_matrix_fast(d, s.k, {0: blk, 1: blk}, eta=eta), b)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((30, 3))
+    xhat = u / np.linalg.norm(u, axis=1)[:, None]
+    pts = xhat * 6.0 + d.centres.mean(axis=0)
+    exact = solve.point_source_field(2.0, z, pts)
+    assert np.abs(solve.near_field(d, s.k, mu, pts, eta=eta) - exact).max() < 1e-8 * np.abs(exact).max()
+    ff = solve.far_field(d, s.k, mu, xhat, eta=eta)
+    assert np.abs(ff - solve.point_source_far_field(2.0, z, xhat)).max() < 1e-8
+
+
+def test_combined_pair_sum_brute_force():
+    s = sc.tiny(n_bodies=3, n_panels=1, n_theta=8, k=3.0)
+    d = geo.discretize(s)
+    mu = np.cos(np.arange(d.pos.shape[0]) * 0.3) + 0.4j
+    eta = 1.7
+    out = pairsum.pair_sum(d, s.k, mu, eta=eta)
+    ref = np.zeros_like(out)
+    for i in range(d.pos.shape[0]):
+        for j in range(d.pos.shape[0]):
+            if d.body[i] == d.body[j]:
+                continue
+            dx = d.pos[j] - d.pos[i]
+            r = math.sqrt(float(dx @ dx))
+            g = complex(math.cos(3.0 * r), math.sin(3.0 * r)) / (4 * math.pi * r)
+            dl = g * (1j * 3.0 * r - 1.0) / (r * r) * float(d.aw[j] @ dx)
+            ref[i] += (dl - 1j * eta * g * math.sqrt(float(d.aw[j] @ d.aw[j]))) * mu[j]
+    assert np.abs(out - ref).max() < 1e-13 * np.abs(ref).max()
+
+
 @pytest.fixture(scope="module")
 def two_body():
     s = sc.tiny(n_bodies=2, n_panels=1, n_theta=12, k=2.0, spacing=2.5)
