@@ -200,6 +200,20 @@ qax_status qax_modal_modes(qax_problem* p, int32_t n_pts, const double* d_r, con
  * the steps are always enqueued one by one. */
 qax_status qax_set_graphs(qax_problem* p, int32_t enable);
 
+/* Boundary-integral formulation.  QAX_DOUBLE_LAYER (default): the paper's
+ * multi-body system (1/2 I + D) mu = -u_inc (Section 4).  QAX_COMBINED_FIELD:
+ * (1/2 I + D - i eta S) mu = -u_inc with the single-layer operator S (Section
+ * 2, the remark on combined fields; uniquely solvable at interior resonances,
+ * where the double-layer system is singular); S is discretised with the
+ * density times |J| interpolated (Section 3.1) and its modal Green's function
+ * by convolution and FFT (Section 3.3).  eta > 0: that coupling for every
+ * problem; eta <= 0: eta = k of each problem.  Applies to the self blocks,
+ * pair sums, near and far field.  May be called at any time; on a built
+ * handle it updates the per-node weights and drops the handle back to the
+ * built state (qax_assemble_self is needed again).  Errors: QAX_ERR_ARG. */
+typedef enum { QAX_DOUBLE_LAYER = 0, QAX_COMBINED_FIELD = 1 } qax_formulation;
+qax_status qax_set_formulation(qax_problem* p, int32_t formulation, double eta);
+
 /* Kernel timing (instrumentation).  When enabled, each launch of the kernels
  * below is bracketed by HIP events recorded on the handle's stream and its
  * duration is accumulated per kernel kind.  Disabled by default. */

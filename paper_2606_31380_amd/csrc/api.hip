@@ -162,13 +162,14 @@ extern "C" qax_status qax_create(int device, void* hip_stream, qax_problem** out
 static void free_geometry(qax_problem* p) {
   void* ptrs[] = {p->d_bodies, p->d_blocks, p->d_node_body, p->d_pos,  p->d_aw,
                   p->d_loc32,  p->d_aw32,   p->d_gl,        p->d_B,    p->d_Binv,
-                  p->d_Binv32, p->d_tasks64, p->d_tasks32};
+                  p->d_Binv32, p->d_tasks64, p->d_tasks32, p->d_ew, p->d_ew32};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   p->d_bodies = nullptr; p->d_blocks = nullptr; p->d_node_body = nullptr;
   p->d_pos = nullptr; p->d_aw = nullptr; p->d_loc32 = nullptr; p->d_aw32 = nullptr;
   p->d_gl = nullptr; p->d_B = nullptr; p->d_Binv = nullptr; p->d_Binv32 = nullptr;
   p->d_tasks64 = nullptr; p->d_tasks32 = nullptr;
+  p->d_ew = nullptr; p->d_ew32 = nullptr;
   if (p->d_gemm_tasks) (void)hipFree(p->d_gemm_tasks);
   p->d_gemm_tasks = nullptr;
   p->gemm_tasks.clear();
@@ -204,6 +205,27 @@ static qax_status sync(qax_problem* p, const char* what) {
   qax_status st = hip_check(p, hipStreamSynchronize(p->stream), what);
   if (st == QAX_OK && !p->pending.empty()) collect_timing(p);
   return st;
+}
+
+extern "C" qax_status qax_set_formulation(qax_problem* p, int32_t formulation, double eta) {
+  if (!p) return QAX_ERR_ARG;
+  if ((formulation != QAX_DOUBLE_LAYER && formulation != QAX_COMBINED_FIELD) || !is_finite(eta))
+    return fail(p, QAX_ERR_ARG, "qax_set_formulation: bad formulation or eta");
+  p->formulation = formulation;
+  p->eta_param = eta;
+  if (p->state < 1) return QAX_OK;
+  // built handle: couplings, weights and task tables follow; blocks are stale
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  for (auto& d : p->hbodies) d.eta = p->eta_of(d.k);
+  QCHECK(hipMemcpyAsync(p->d_bodies, p->hbodies.data(), sizeof(BodyDev) * p->hbodies.size(),
+                        hipMemcpyHostToDevice, p->stream), "copy bodies");
+  QCHECK(launch_node_weights(p), "node weights");
+  const int cus = cu_count(p->device);
+  QCHECK(upload_pair_plan(p, QAX_FP64, cus), "pair-sum plan");
+  QCHECK(upload_pair_plan(p, QAX_MIXED, cus), "pair-sum plan");
+  p->state = std::min(p->state, 1);
+  return sync(p, "qax_set_formulation");
 }
 
 extern "C" qax_status qax_set_graphs(qax_problem* p, int32_t enable) {
@@ -304,8 +326,9 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
     rotation(b.theta1, b.theta2, d.R);
     for (int a = 0; a < 3; ++a) d.cen[a] = b.centre[a];
     d.k = k_per_problem[b.problem];
+    d.eta = p->eta_of(d.k);
     std::vector<double> key = {(double)b.shape, b.a, b.c, b.kappa, (double)b.n_panels,
-                               (double)b.n_theta, d.k};
+                               (double)b.n_theta, d.k, d.eta};
     auto it = key2blk.find(key);
     if (it == key2blk.end()) {
       BlockDev bk;
@@ -331,6 +354,8 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
   QCHECK(hipMalloc(&p->d_aw, sizeof(double) * 3 * N), "alloc aw");
   QCHECK(hipMalloc(&p->d_loc32, sizeof(float) * 4 * N), "alloc loc32");
   QCHECK(hipMalloc(&p->d_aw32, sizeof(float) * 4 * N), "alloc aw32");
+  QCHECK(hipMalloc(&p->d_ew, sizeof(double) * N), "alloc ew");
+  QCHECK(hipMalloc(&p->d_ew32, sizeof(float) * N), "alloc ew32");
   QCHECK(hipMalloc(&p->d_gl, sizeof(double) * 3 * GL_ORDER), "alloc gl");
   double gl[3 * GL_ORDER];   // nodes, weights, barycentric weights on [-1, 1]
   gauss_legendre_host(GL_ORDER, gl, gl + GL_ORDER);
@@ -346,6 +371,7 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
   QCHECK(hipMemcpyAsync(p->d_blocks, p->hblocks.data(), sizeof(BlockDev) * p->hblocks.size(),
                         hipMemcpyHostToDevice, p->stream), "copy blocks");
   QCHECK(launch_build_nodes(p), "build_nodes");
+  QCHECK(launch_node_weights(p), "node weights");
   const int cus = cu_count(p->device);
   QCHECK(upload_pair_plan(p, QAX_FP64, cus), "pair-sum plan");
   QCHECK(upload_pair_plan(p, QAX_MIXED, cus), "pair-sum plan");

@@ -96,6 +96,27 @@ __global__ void build_nodes_kernel(const BodyDev* __restrict__ bodies, int nb, i
                         (float)(nl[0] * yl[0] + nl[1] * yl[1] + nl[2] * yl[2]));
 }
 
+// Combined-field weights eta |aw| per node (|aw| = |J| (pi/N) omega, the
+// single-layer smooth-rule weight); zero for the double layer.
+__global__ void node_weights_kernel(const BodyDev* __restrict__ bodies,
+                                    const int32_t* __restrict__ node_body, int64_t N,
+                                    const double* __restrict__ aw, double* __restrict__ ew,
+                                    float* __restrict__ ew32) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double eta = bodies[node_body[i]].eta;
+  const double w = sqrt(aw[i] * aw[i] + aw[N + i] * aw[N + i] + aw[2 * N + i] * aw[2 * N + i]);
+  ew[i] = eta * w;
+  ew32[i] = (float)(eta * w);
+}
+
+hipError_t launch_node_weights(qax_problem* p) {
+  const int64_t blocks = (p->N + 255) / 256;
+  hipLaunchKernelGGL(node_weights_kernel, dim3((unsigned)blocks), dim3(256), 0, p->stream,
+                     p->d_bodies, p->d_node_body, p->N, p->d_aw, p->d_ew, p->d_ew32);
+  return hipGetLastError();
+}
+
 hipError_t launch_build_nodes(qax_problem* p) {
   const int tpb = 256;
   const int64_t blocks = (p->N + tpb - 1) / tpb;

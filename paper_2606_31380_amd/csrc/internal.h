@@ -26,6 +26,7 @@ struct BodyDev {
   double R[9];        // rotation, row-major
   double cen[3];
   double k;           // wavenumber of the body's problem
+  double eta;         // combined-field coupling (0: double layer only)
 };
 
 // Distinct self block.
@@ -44,6 +45,7 @@ struct PairTask {
   int32_t slot;
   int32_t tbody_lo, tbody_hi;  // bodies spanned by the targets
   double k;
+  double eta;                  // combined-field coupling of the problem (0: none)
 };
 
 // Row tile of the several-RHS block apply: 64 rows of one body from row0.
@@ -80,6 +82,9 @@ struct qax_problem {
   hipStream_t stream = nullptr;
   std::string err;
   int state = 0;  // 0 created, 1 built, 2 assembled
+  int formulation = QAX_DOUBLE_LAYER;
+  double eta_param = 0.0;          // > 0 fixed coupling, <= 0 k of each problem
+  double eta_of(double k) const { return formulation == QAX_COMBINED_FIELD ? (eta_param > 0 ? eta_param : k) : 0.0; }
 
   int32_t n_bodies = 0, n_problems = 0;
   std::vector<qax_body> bodies;
@@ -99,6 +104,8 @@ struct qax_problem {
   double* d_aw = nullptr;       // SoA
   float* d_loc32 = nullptr;     // float4 per node: local offset from the body centre, |y'|^2
   float* d_aw32 = nullptr;      // float4 per node: aw, aw . (local offset)
+  double* d_ew = nullptr;       // per node eta |aw| (combined field; 0 otherwise)
+  float* d_ew32 = nullptr;
   double* d_gl = nullptr;       // 16 GL nodes, weights, barycentric weights on [-1, 1]
 
   // self blocks (complex128 / complex64 pools)
@@ -161,6 +168,7 @@ void* scratch(qax_problem* p, size_t bytes, qax_status* st);
 // geometry.hip
 void gauss_legendre_host(int n, double* x, double* w);
 hipError_t launch_build_nodes(qax_problem* p);
+hipError_t launch_node_weights(qax_problem* p);
 
 // pairsum.hip
 hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,

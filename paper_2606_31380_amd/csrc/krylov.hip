@@ -1,7 +1,8 @@
 // Vector kernels of the solver: plane-wave right-hand side (Section 2 and
 // Section 6, equation plane wave parameters), far field of the double-layer
 // density (Section 6: the far-field pattern, with the normal derivative of the
-// kernel for a double-layer density), and the GMRES building blocks.
+// kernel for a double-layer density; plus the single-layer term for the
+// combined field), and the GMRES building blocks.
 //
 // GMRES vectors are N x nrhs complex128 (right-hand sides fastest).  Every
 // (problem, right-hand side) pair is an independent "segment": dot products
@@ -41,8 +42,9 @@ hipError_t launch_rhs(qax_problem* p, const double* dirs_dev, int nrhs, double* 
 
 // u_inf[dir][r] = (1/4pi) sum_{n in problem 0} (-i k xhat.aw_n) e^{-i k xhat.y_n} mu[n][r]
 __global__ __launch_bounds__(256) void farfield_kernel(const double* __restrict__ pos,
-                                                       const double* __restrict__ aw, int64_t N,
-                                                       int64_t n0, double k,
+                                                       const double* __restrict__ aw,
+                                                       const double* __restrict__ ew, int cf,
+                                                       int64_t N, int64_t n0, double k,
                                                        const double2* __restrict__ mu, int nrhs,
                                                        const double* __restrict__ xhat,
                                                        double2* __restrict__ out) {
@@ -55,8 +57,13 @@ __global__ __launch_bounds__(256) void farfield_kernel(const double* __restrict_
     double s, c;
     sincos_cw(ph, &s, &c);
     const double nd = hx * aw[n] + hy * aw[N + n] + hz * aw[2 * N + n];
-    // (-i k nd) (c + i s) = k nd s - i k nd c
-    const double fr = k * nd * s, fi = -k * nd * c;
+    // (-i k nd) (c + i s) = k nd s - i k nd c; combined field adds
+    // (-i eta |aw|)(c + i s) = eta |aw| s - i eta |aw| c
+    double fr = k * nd * s, fi = -k * nd * c;
+    if (cf) {
+      fr = fma(ew[n], s, fr);
+      fi = fma(-ew[n], c, fi);
+    }
     const double2 m = mu[n * nrhs + r];
     ar += fr * m.x - fi * m.y;
     ai += fr * m.y + fi * m.x;
@@ -80,7 +87,8 @@ hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const dou
                            int ndir, double* out) {
   const int64_t n0 = p->off[p->prob_body0[1]];
   hipLaunchKernelGGL(farfield_kernel, dim3(ndir, nrhs), dim3(256), 0, p->stream, p->d_pos, p->d_aw,
-                     p->N, n0, p->k[0], (const double2*)mu, nrhs, xhat_dev, (double2*)out);
+                     p->d_ew, p->formulation == QAX_COMBINED_FIELD ? 1 : 0, p->N, n0, p->k[0],
+                     (const double2*)mu, nrhs, xhat_dev, (double2*)out);
   return hipGetLastError();
 }
 

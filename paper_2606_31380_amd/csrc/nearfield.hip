@@ -1,5 +1,6 @@
 // Scattered field at points off the surfaces: the double-layer potential of
-// the density (Section 4, equation multi-double) by the smooth product rule of
+// the density (Section 4, equation multi-double; minus i eta times the
+// single-layer potential for the combined field) by the smooth product rule of
 // Section 3.1 (equation sx), the same kernel as the inter-body pair sum, for
 // evaluation points that are not nodes (the near-field part of the error
 // study of Section 6).  FP64.
@@ -25,7 +26,8 @@ __global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slo
 template <int TPB>
 __global__ __launch_bounds__(TPB) void nearfield_kernel(
     const double* __restrict__ pts, int64_t M, const double* __restrict__ pos,
-    const double* __restrict__ aw, int64_t N, int64_t s0, int64_t s1, int slots, double k,
+    const double* __restrict__ aw, const double* __restrict__ ew, int cf, int64_t N, int64_t s0,
+    int64_t s1, int slots, double k,
     const double2* __restrict__ mu, int nrhs, double2* __restrict__ partial) {
   const int tid = threadIdx.x;
   const int64_t i = (int64_t)blockIdx.x * TPB + tid;
@@ -35,7 +37,7 @@ __global__ __launch_bounds__(TPB) void nearfield_kernel(
                zi = active ? pts[2 * M + i] : 0.0;
   const int64_t len = s1 - s0;
   const int64_t c0 = s0 + len * blockIdx.y / slots, c1 = s0 + len * (blockIdx.y + 1) / slots;
-  __shared__ double sx[TPB], sy[TPB], sz[TPB], sax[TPB], say[TPB], saz[TPB];
+  __shared__ double sx[TPB], sy[TPB], sz[TPB], sax[TPB], say[TPB], saz[TPB], sew[TPB];
   __shared__ double2 smu[TPB];
   double ar = 0.0, ai = 0.0;
   for (int64_t base = c0; base < c1; base += TPB) {
@@ -45,6 +47,7 @@ __global__ __launch_bounds__(TPB) void nearfield_kernel(
       const int64_t j = base + tid;
       sx[tid] = pos[j]; sy[tid] = pos[N + j]; sz[tid] = pos[2 * N + j];
       sax[tid] = aw[j]; say[tid] = aw[N + j]; saz[tid] = aw[2 * N + j];
+      sew[tid] = cf ? ew[j] : 0.0;
       smu[tid] = mu[j * nrhs + r];
     }
     __syncthreads();
@@ -57,7 +60,10 @@ __global__ __launch_bounds__(TPB) void nearfield_kernel(
       double sn, cs;
       sincos_cw(kr, &sn, &cs);
       const double sc = (sax[jj] * dx + say[jj] * dy + saz[jj] * dz) * ir * ir * ir;
-      const double re = -(cs + kr * sn) * sc, im = (kr * cs - sn) * sc;
+      double re = -(cs + kr * sn) * sc, im = (kr * cs - sn) * sc;
+      const double t = sew[jj] * ir;      // combined field: (eta |aw| / r)(sin kr - i cos kr)
+      re = fma(t, sn, re);
+      im = fma(-t, cs, im);
       const double2 m = smu[jj];
       ar += re * m.x - im * m.y;
       ai += re * m.y + im * m.x;
@@ -78,8 +84,8 @@ hipError_t launch_nearfield(qax_problem* p, const double* mu, int nrhs, const do
   const int64_t s0 = p->off[p->prob_body0[problem]], s1 = p->off[p->prob_body0[problem + 1]];
   dim3 grid((unsigned)((M + 255) / 256), (unsigned)slots, (unsigned)nrhs);
   hipLaunchKernelGGL((nearfield_kernel<256>), grid, dim3(256), 0, p->stream, pts, M, p->d_pos,
-                     p->d_aw, p->N, s0, s1, slots, p->k[problem], (const double2*)mu, nrhs,
-                     (double2*)partial);
+                     p->d_aw, p->d_ew, p->formulation == QAX_COMBINED_FIELD ? 1 : 0, p->N, s0, s1,
+                     slots, p->k[problem], (const double2*)mu, nrhs, (double2*)partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t count = M * nrhs;

@@ -1,5 +1,6 @@
 // Inter-body double-layer pair sum (Section 4, the display after the equation
-// for the second part of the multi-body potential):
+// for the second part of the multi-body potential); with the combined field
+// the single-layer term - i eta G(x_i, y_j) |aw_j| mu_j is added per pair:
 //
 //   w_i = 1/(4 pi) sum_{j in other bodies} (ik r - 1) e^{ikr} / r^3
 //                                          (aw_j . (y_j - x_i)) mu_j,
@@ -53,11 +54,12 @@ __device__ __forceinline__ bool skip_task(const PairTask& T, const BodyDev* __re
   return true;
 }
 
-template <int TPB, int NRC>
+template <int TPB, int NRC, bool CF>
 __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
     const PairTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
     const int32_t* __restrict__ node_body, const double* __restrict__ pos,
-    const double* __restrict__ aw, int64_t N, const double2* __restrict__ mu, int nrhs,
+    const double* __restrict__ aw, const double* __restrict__ ew, int64_t N,
+    const double2* __restrict__ mu, int nrhs,
     const int32_t* __restrict__ seg_active, double2* __restrict__ partial) {
   const PairTask T = tasks[blockIdx.x];
   const int rc0 = blockIdx.y * NRC;  // first right-hand side of this chunk
@@ -70,6 +72,7 @@ __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
   const double k = T.k;
 
   __shared__ double sx[TPB], sy[TPB], sz[TPB], sax[TPB], say[TPB], saz[TPB];
+  __shared__ double sew[CF ? TPB : 1];
   __shared__ double2 smu[TPB * NRC];
 
   double accr[NRC], acci[NRC];
@@ -88,6 +91,7 @@ __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
         const int64_t j = s0 + base + tid;
         sx[tid] = pos[j]; sy[tid] = pos[N + j]; sz[tid] = pos[2 * N + j];
         sax[tid] = aw[j]; say[tid] = aw[N + j]; saz[tid] = aw[2 * N + j];
+        if (CF) sew[tid] = ew[j];
 #pragma unroll
         for (int r = 0; r < NRC; ++r)
           smu[tid * NRC + r] = (rc0 + r < nrhs) ? mu[j * nrhs + rc0 + r] : make_double2(0.0, 0.0);
@@ -104,8 +108,13 @@ __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
           sincos_cw(kr, &s, &c);
           const double dot = sax[jj] * dx + say[jj] * dy + saz[jj] * dz;
           const double sc = dot * ir * ir * ir;
-          const double re = -(c + kr * s) * sc;
-          const double im = (kr * c - s) * sc;
+          double re = -(c + kr * s) * sc;
+          double im = (kr * c - s) * sc;
+          if (CF) {   // - i eta G |aw|: (eta |aw| / r)(sin kr - i cos kr)
+            const double t = sew[jj] * ir;
+            re = fma(t, s, re);
+            im = fma(-t, c, im);
+          }
 #pragma unroll
           for (int r_ = 0; r_ < NRC; ++r_) {
             const double2 m = smu[jj * NRC + r_];
@@ -133,11 +142,12 @@ __device__ __forceinline__ void two_sum(float& s, float& c, float a) {
   c += e;
 }
 
-template <int TPB, int NRC>
+template <int TPB, int NRC, bool CF>
 __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
     const PairTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
     const int32_t* __restrict__ node_body, const double* __restrict__ pos,
-    const float4* __restrict__ loc32, const float4* __restrict__ aw32, int64_t N,
+    const float4* __restrict__ loc32, const float4* __restrict__ aw32,
+    const float* __restrict__ ew32, int64_t N,
     const double2* __restrict__ mu, int nrhs, const int32_t* __restrict__ seg_active,
     double2* __restrict__ partial) {
   const PairTask T = tasks[blockIdx.x];
@@ -154,6 +164,7 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
 
   __shared__ float4 sloc[TPB];
   __shared__ float4 saw[TPB];
+  __shared__ float sew[CF ? TPB : 1];
   __shared__ float2 smu[TPB * NRC];
 
   float sr[NRC], si[NRC], cr[NRC], ci[NRC];
@@ -185,6 +196,7 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
         const int64_t j = s0 + base + tid;
         sloc[tid] = loc32[j];
         saw[tid] = aw32[j];
+        if (CF) sew[tid] = ew32[j];
 #pragma unroll
         for (int r = 0; r < NRC; ++r) {
           const double2 m = (rc0 + r < nrhs) ? mu[j * nrhs + rc0 + r] : make_double2(0.0, 0.0);
@@ -214,8 +226,13 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
           // aw . (y - x) = aw . D + aw . y'
           const float dot = fmaf(a4.x, dxf, fmaf(a4.y, dyf, fmaf(a4.z, dzf, a4.w)));
           const float sc = dot * (ir * ir * ir);
-          const float re = -fmaf(kr, s, c) * sc;               // Re (ikr - 1) e^{ikr} / r^3 (.)
-          const float im = fmaf(kr, c, -s) * sc;
+          float re = -fmaf(kr, s, c) * sc;                     // Re (ikr - 1) e^{ikr} / r^3 (.)
+          float im = fmaf(kr, c, -s) * sc;
+          if (CF) {   // - i eta G |aw|: (eta |aw| / r)(sin kr - i cos kr)
+            const float t = sew[jj] * ir;
+            re = fmaf(t, s, re);
+            im = fmaf(-t, c, im);
+          }
 #pragma unroll
           for (int r_ = 0; r_ < NRC; ++r_) {
             const float2 m = smu[jj * NRC + r_];
@@ -304,6 +321,7 @@ void plan_pair_sum(qax_problem* p, int prec, int cu_count) {
         T.tbody_lo = lo;
         T.tbody_hi = hi;
         T.k = p->k[pr];
+        T.eta = p->eta_of(p->k[pr]);
         tasks.push_back(T);
       }
     }
@@ -341,58 +359,75 @@ hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count) {
   return hipStreamSynchronize(p->stream);
 }
 
-// LDS per workgroup: FP64 6 TPB doubles + TPB NRC complex128; FP32 2 TPB float4
-// + TPB NRC complex64
+// LDS per workgroup (with the combined-field weights): FP64 7 TPB doubles +
+// TPB NRC complex128; FP32 2 TPB float4 + TPB floats + TPB NRC complex64
+constexpr size_t lds_f64(int tpb, int nrc) { return (size_t)tpb * (56 + 16 * nrc); }
+constexpr size_t lds_f32(int tpb, int nrc) { return (size_t)tpb * (36 + 8 * nrc); }
+
 bool pair_config_ok(int prec, int tpb, int nrc) {
   if (tpb != 128 && tpb != 256 && tpb != 512) return false;
   if (prec == QAX_FP64) {
     if (nrc != 1 && nrc != 2 && nrc != 4 && nrc != 8) return false;
-    return (size_t)tpb * (48 + 16 * nrc) <= 65536;
+    return lds_f64(tpb, nrc) <= 65536;
   }
   if (nrc != 1 && nrc != 2 && nrc != 4 && nrc != 8 && nrc != 16 && nrc != 32) return false;
-  return (size_t)tpb * (32 + 8 * nrc) <= 65536;
+  return lds_f32(tpb, nrc) <= 65536;
 }
 
-template <int TPB, int NRC>
+template <int TPB, int NRC, bool CF>
 static void launch_f64(qax_problem* p, const double* mu, int nrhs, double* partial) {
-  if constexpr ((size_t)TPB * (48 + 16 * NRC) <= 65536) {
+  if constexpr (lds_f64(TPB, NRC) <= 65536) {
     dim3 grid((unsigned)p->tasks64.size(), (unsigned)((nrhs + NRC - 1) / NRC));
-    hipLaunchKernelGGL((pair_sum_f64_kernel<TPB, NRC>), grid, dim3(TPB), 0, p->stream, p->d_tasks64,
-                       p->d_bodies, p->d_node_body, p->d_pos, p->d_aw, p->N, (const double2*)mu,
-                       nrhs, p->seg_active, (double2*)partial);
-  }
-}
-
-template <int TPB, int NRC>
-static void launch_f32(qax_problem* p, const double* mu, int nrhs, double* partial) {
-  if constexpr ((size_t)TPB * (32 + 8 * NRC) <= 65536) {
-    dim3 grid((unsigned)p->tasks32.size(), (unsigned)((nrhs + NRC - 1) / NRC));
-    hipLaunchKernelGGL((pair_sum_f32_kernel<TPB, NRC>), grid, dim3(TPB), 0, p->stream,
-                       p->d_tasks32, p->d_bodies, p->d_node_body, p->d_pos,
-                       (const float4*)p->d_loc32, (const float4*)p->d_aw32, p->N,
+    hipLaunchKernelGGL((pair_sum_f64_kernel<TPB, NRC, CF>), grid, dim3(TPB), 0, p->stream,
+                       p->d_tasks64, p->d_bodies, p->d_node_body, p->d_pos, p->d_aw, p->d_ew, p->N,
                        (const double2*)mu, nrhs, p->seg_active, (double2*)partial);
   }
 }
 
-template <int TPB>
-static void launch_f64_nrc(qax_problem* p, int nrc, const double* mu, int nrhs, double* partial) {
-  switch (nrc) {
-    case 1: launch_f64<TPB, 1>(p, mu, nrhs, partial); break;
-    case 2: launch_f64<TPB, 2>(p, mu, nrhs, partial); break;
-    case 4: launch_f64<TPB, 4>(p, mu, nrhs, partial); break;
-    default: launch_f64<TPB, 8>(p, mu, nrhs, partial); break;
+template <int TPB, int NRC, bool CF>
+static void launch_f32(qax_problem* p, const double* mu, int nrhs, double* partial) {
+  if constexpr (lds_f32(TPB, NRC) <= 65536) {
+    dim3 grid((unsigned)p->tasks32.size(), (unsigned)((nrhs + NRC - 1) / NRC));
+    hipLaunchKernelGGL((pair_sum_f32_kernel<TPB, NRC, CF>), grid, dim3(TPB), 0, p->stream,
+                       p->d_tasks32, p->d_bodies, p->d_node_body, p->d_pos,
+                       (const float4*)p->d_loc32, (const float4*)p->d_aw32, p->d_ew32, p->N,
+                       (const double2*)mu, nrhs, p->seg_active, (double2*)partial);
   }
 }
 
-template <int TPB>
+template <int TPB, bool CF>
+static void launch_f64_nrc(qax_problem* p, int nrc, const double* mu, int nrhs, double* partial) {
+  switch (nrc) {
+    case 1: launch_f64<TPB, 1, CF>(p, mu, nrhs, partial); break;
+    case 2: launch_f64<TPB, 2, CF>(p, mu, nrhs, partial); break;
+    case 4: launch_f64<TPB, 4, CF>(p, mu, nrhs, partial); break;
+    default: launch_f64<TPB, 8, CF>(p, mu, nrhs, partial); break;
+  }
+}
+
+template <int TPB, bool CF>
 static void launch_f32_nrc(qax_problem* p, int nrc, const double* mu, int nrhs, double* partial) {
   switch (nrc) {
-    case 1: launch_f32<TPB, 1>(p, mu, nrhs, partial); break;
-    case 2: launch_f32<TPB, 2>(p, mu, nrhs, partial); break;
-    case 4: launch_f32<TPB, 4>(p, mu, nrhs, partial); break;
-    case 8: launch_f32<TPB, 8>(p, mu, nrhs, partial); break;
-    case 16: launch_f32<TPB, 16>(p, mu, nrhs, partial); break;
-    default: launch_f32<TPB, 32>(p, mu, nrhs, partial); break;
+    case 1: launch_f32<TPB, 1, CF>(p, mu, nrhs, partial); break;
+    case 2: launch_f32<TPB, 2, CF>(p, mu, nrhs, partial); break;
+    case 4: launch_f32<TPB, 4, CF>(p, mu, nrhs, partial); break;
+    case 8: launch_f32<TPB, 8, CF>(p, mu, nrhs, partial); break;
+    case 16: launch_f32<TPB, 16, CF>(p, mu, nrhs, partial); break;
+    default: launch_f32<TPB, 32, CF>(p, mu, nrhs, partial); break;
+  }
+}
+
+template <bool CF>
+static void launch_any(qax_problem* p, bool f64, int tpb, int nrc, const double* mu, int nrhs,
+                       double* partial) {
+  if (f64) {
+    if (tpb == 128) launch_f64_nrc<128, CF>(p, nrc, mu, nrhs, partial);
+    else if (tpb == 256) launch_f64_nrc<256, CF>(p, nrc, mu, nrhs, partial);
+    else launch_f64_nrc<512, CF>(p, nrc, mu, nrhs, partial);
+  } else {
+    if (tpb == 128) launch_f32_nrc<128, CF>(p, nrc, mu, nrhs, partial);
+    else if (tpb == 256) launch_f32_nrc<256, CF>(p, nrc, mu, nrhs, partial);
+    else launch_f32_nrc<512, CF>(p, nrc, mu, nrhs, partial);
   }
 }
 
@@ -410,15 +445,8 @@ hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* o
   while (nrc > 1 && !pair_config_ok(prec, tpb, nrc)) nrc /= 2;
   if (!pair_config_ok(prec, tpb, nrc) || p->plan_tpb[pi] != tpb) return hipErrorInvalidConfiguration;
   timing_begin(p, kind);
-  if (f64) {
-    if (tpb == 128) launch_f64_nrc<128>(p, nrc, mu, nrhs, partial);
-    else if (tpb == 256) launch_f64_nrc<256>(p, nrc, mu, nrhs, partial);
-    else launch_f64_nrc<512>(p, nrc, mu, nrhs, partial);
-  } else {
-    if (tpb == 128) launch_f32_nrc<128>(p, nrc, mu, nrhs, partial);
-    else if (tpb == 256) launch_f32_nrc<256>(p, nrc, mu, nrhs, partial);
-    else launch_f32_nrc<512>(p, nrc, mu, nrhs, partial);
-  }
+  if (p->formulation == QAX_COMBINED_FIELD) launch_any<true>(p, f64, tpb, nrc, mu, nrhs, partial);
+  else launch_any<false>(p, f64, tpb, nrc, mu, nrhs, partial);
   timing_end(p, kind);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -59,6 +59,8 @@ struct NodeLoc {
   double r, dr, dz, dp, dq, rt, alpha, c, chim1, rmrt, z, p, q, w, s;
 };
 
+// CF: the single-layer arrays are only sized for the combined-field kernel.
+template <bool CF>
 struct ModalScratch {
   double2 fa[LM];
   double2 fb[LM];
@@ -68,8 +70,15 @@ struct ModalScratch {
   double2 AB0[MQ_CAP + 1];      // static modes (dr, dz) of the kernel, n = 0..nmax+nf
   double2 Am[NTH_MAX / 2 + 2];
   double2 Bm[NTH_MAX / 2 + 2];
+  // single layer (combined field only)
+  double2 fc[CF ? LM : 1];               // sin(k rho) / (4 pi rho) samples, then transform
+  double Ch[CF ? LM / 2 : 1];            // modes of cos(k rho)
+  double Sh[CF ? NTH_MAX / 2 + 2 : 1];   // modes of sin(k rho) / (4 pi rho)
+  double G0[CF ? MQ_CAP + 1 : 1];        // static modes of G
+  double2 Gm[CF ? NTH_MAX / 2 + 2 : 1];  // phi-frame modes of G
 };
 
+template <bool CF>
 struct SelfShared {
   union {
     double Q[MQ_CAP + 1][QB];     // toroidal functions of one recurrence batch
@@ -79,8 +88,8 @@ struct SelfShared {
   double2 tw2n[NTH_MAX];        // e^{i pi m / N}
   int modal_idx[64];
   union {
-    ModalScratch m;
-    double2 K[LD];
+    ModalScratch<CF> m;
+    double2 K[CF ? 2 : 1][LD];   // direct-route samples: double layer (, single layer)
   } u;
 };
 
@@ -325,8 +334,12 @@ __device__ __forceinline__ double smooth_h(double k, double rho, double sx, doub
 
 // phi-frame modes m = 0..nmax of A = dr G, B = dz G for one node (all lanes),
 // given its Q column.  Results in M.Am, M.Bm.
+// CF: also the modes of G itself (the single layer, Section 3.3 equations
+// conv and I1): cos(k rho) convolved with the static modes of G plus
+// i times the modes of sin(k rho) / (4 pi rho).
+template <bool CF>
 __device__ void modal_modes(double k, double r, double rt, double c, double chim1, double rmrt,
-                            int nmax, const double (*Q)[QB], int col, ModalScratch& M,
+                            int nmax, const double (*Q)[QB], int col, ModalScratch<CF>& M,
                             const double2* tw) {
   const int lane = threadIdx.x;
   const double chi = 1.0 + chim1;
@@ -344,15 +357,24 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
       const double Hs = smooth_h(k, rho, sk, ck);
       const double cphi = 1.0 - 2.0 * sh * sh;
       M.fa[l] = make_double2(F, Hs);
-      M.fb[l] = make_double2(Hs * (r - rt * cphi), 0.0);
+      M.fb[l] = make_double2(Hs * (r - rt * cphi), CF ? ck : 0.0);
+      if constexpr (CF) {
+        const double x = k * rho;
+        // sin(x) / (4 pi rho) = (k / 4 pi) sin(x) / x
+        const double sx = x < 1e-3 ? 1.0 - x * x * (1.0 / 6.0 - x * x * (1.0 / 120.0)) : sk / x;
+        M.fc[l] = make_double2(k * INV_4PI * sx, 0.0);
+      }
     }
     __syncthreads();
     fft128x2(M.fa, M.fb, tw);
+    if constexpr (CF) fft128(M.fc, tw);
     const double sc = TWO_PI / LM;
     M.Fh[lane] = M.fa[lane].x * sc;
+    if constexpr (CF) M.Ch[lane] = M.fb[lane].y * sc;
     if (lane < nmax + 1) {
       M.Hh[lane] = M.fa[lane].y * sc;
       M.Hrh[lane] = M.fb[lane].x * sc;
+      if constexpr (CF) M.Sh[lane] = M.fc[lane].x * sc;
     }
     const double mag = fabs(M.fa[lane].x * sc);
     const double mx = wave_max(mag);
@@ -375,6 +397,7 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
     const double qm = n == 0 ? Q[1][col] : Q[n - 1][col];
     const double qp = (2.0 * n - 1.0) * half_inv_chi2m1 * (chi * qn - qm);
     M.AB0[n] = make_double2(pref * (drchi * qp - 0.5 * ir * qn), pref * dzchi * qp);
+    if constexpr (CF) M.G0[n] = pref * qn;
   }
   __syncthreads();
   if (lane <= nmax) {
@@ -382,6 +405,7 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
     if (k == 0.0) {
       M.Am[lane] = make_double2(ab.x, 0.0);
       M.Bm[lane] = make_double2(ab.y, 0.0);
+      if constexpr (CF) M.Gm[lane] = make_double2(M.G0[lane], 0.0);
     } else {
       // F^ is even in n: (F^ * g)_m = F^_0 g_m + sum_{n>=1} F^_n (g_{|m-n|} + g_{m+n})
       double ar = M.Fh[0] * ab.x, br = M.Fh[0] * ab.y;
@@ -393,6 +417,11 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
       }
       M.Am[lane] = make_double2(ar * (1.0 / TWO_PI), M.Hrh[lane]);
       M.Bm[lane] = make_double2(br * (1.0 / TWO_PI), -c * M.Hh[lane]);
+      if constexpr (CF) {
+        double gr = M.Ch[0] * M.G0[lane];
+        for (int n = 1; n <= nf; ++n) gr = fma(M.Ch[n], M.G0[abs(lane - n)] + M.G0[lane + n], gr);
+        M.Gm[lane] = make_double2(gr * (1.0 / TWO_PI), M.Sh[lane]);
+      }
     }
   }
   __syncthreads();
@@ -402,8 +431,9 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
 // (even in m), with e^{-i m alpha} = (c0, s0) and e^{i alpha} = (ca, sa):
 //   e^{-i m alpha} (r z' A_m - r r' B_m)
 //   - r/2 (p' - i q') e^{-i(m-1) alpha} B_{m-1} - r/2 (p' + i q') e^{-i(m+1) alpha} B_{m+1}
+template <bool CF>
 __device__ __forceinline__ double2 theta_mode(int m, double c0, double s0, double ca, double sa,
-                                              const NodeLoc& L, const ModalScratch& M) {
+                                              const NodeLoc& L, const ModalScratch<CF>& M) {
   const double r = L.r;
   const double c1 = c0 * ca - s0 * sa, s1 = s0 * ca + c0 * sa;   // e^{-i(m-1) alpha}
   const double c2 = c0 * ca + s0 * sa, s2 = s0 * ca - c0 * sa;   // e^{-i(m+1) alpha}
@@ -429,9 +459,14 @@ __device__ __forceinline__ double2 theta_mode(int m, double c0, double s0, doubl
 
 // Mode slot of lane s < 2N: m = s - N, with slot 0 holding K_{-N} + K_{N}
 // (the inverse DFT weighs both by 1/2 and e^{+-i N theta_j} agree).
-__device__ __forceinline__ double2 modal_slot(int N, const NodeLoc& L, const ModalScratch& M) {
+// CF: ks receives the single-layer slot, e^{-i m alpha} G_|m| (the same
+// pairing of -N and N in slot 0).
+template <bool CF>
+__device__ __forceinline__ double2 modal_slot(int N, const NodeLoc& L, const ModalScratch<CF>& M,
+                                              double2& ks) {
   const int lane = threadIdx.x;
   double2 out = make_double2(0.0, 0.0);
+  ks = make_double2(0.0, 0.0);
   double sa, ca;
   sincos_cw(L.alpha, &sa, &ca);
   if (lane < 2 * N) {
@@ -439,10 +474,16 @@ __device__ __forceinline__ double2 modal_slot(int N, const NodeLoc& L, const Mod
     double s0, c0;
     sincos_cw(-m * L.alpha, &s0, &c0);
     out = theta_mode(m, c0, s0, ca, sa, L, M);
+    if constexpr (CF) ks = cmul(make_double2(c0, s0), M.Gm[abs(m)]);
     if (lane == 0) {
       const double2 o2 = theta_mode(N, c0, -s0, ca, sa, L, M);
       out.x += o2.x;
       out.y += o2.y;
+      if constexpr (CF) {
+        const double2 k2 = cmul(make_double2(c0, -s0), M.Gm[N]);
+        ks.x += k2.x;
+        ks.y += k2.y;
+      }
     }
   }
   return out;
@@ -530,17 +571,60 @@ struct OuterRule {
   double w[NGO];
 };
 
+// Inverse DFT of the accumulated mode slots (S.acc) onto the Lagrange basis
+// for lane j < 2N: g_l = (1/2N) sum_s acc_l[s] e^{i (s - N) theta_j}, slot 0
+// weighted 1/2 (applied when the slots were stored);
+// e^{i (s - N) j pi / N} = (-1)^j e^{i pi s j / N}.
+template <bool CF>
+__device__ __forceinline__ void slots_to_nodes(const SelfShared<CF>& S, int N,
+                                               double2 (&g)[GL_ORDER]) {
+  const int lane = threadIdx.x;
+#pragma unroll
+  for (int l = 0; l < GL_ORDER; ++l) g[l] = make_double2(0.0, 0.0);
+  int e = 0;
+  for (int sl = 0; sl < 2 * N; ++sl) {
+    const double2 t = S.tw2n[e];
+    e += lane;
+    if (e >= 2 * N) e -= 2 * N;
+#pragma unroll
+    for (int l = 0; l < GL_ORDER; ++l) {
+      const double2 v = S.acc[l][sl];
+      g[l].x = fma(v.x, t.x, fma(-v.y, t.y, g[l].x));
+      g[l].y = fma(v.x, t.y, fma(v.y, t.x, g[l].y));
+    }
+  }
+  const double scale = ((lane & 1) ? -1.0 : 1.0) / (2 * N);
+#pragma unroll
+  for (int l = 0; l < GL_ORDER; ++l) g[l] = make_double2(g[l].x * scale, g[l].y * scale);
+}
+
+template <bool CF>
+__device__ __forceinline__ void store_slots(SelfShared<CF>& S, const double2 (&acc)[GL_ORDER]) {
+  const int lane = threadIdx.x;
+  const double f = lane == 0 ? 0.5 : 1.0;
+#pragma unroll
+  for (int l = 0; l < GL_ORDER; ++l) S.acc[l][lane] = make_double2(acc[l].x * f, acc[l].y * f);
+}
+
+// One work item = one target row T and one source panel ip of a block.
+// CF = false: row of 1/2 I + D (Section 3.1, equations muJ and coef_ele, with
+// the double-layer modes of Section 3.3).  CF = true: row of the combined
+// field 1/2 I + D - i eta S (the combined-field remark of Section 2), where
+// the single layer interpolates the density times |J|, so its column
+// (ip, l, j) carries |J| at that node.
+template <bool CF>
 __global__ __launch_bounds__(64) void assemble_self_kernel(
     const SelfTask* __restrict__ tasks, const BlockDev* __restrict__ blocks,
     const BodyDev* __restrict__ bodies, const double* __restrict__ gl16,
     const OuterRule* __restrict__ orule, double2* __restrict__ pool) {
-  __shared__ SelfShared S;
+  __shared__ SelfShared<CF> S;
   const SelfTask task = tasks[blockIdx.x];
   const BlockDev K = blocks[task.block];
   const BodyDev& B = bodies[K.rep_body];
   const int lane = threadIdx.x;
   const int shape = B.shape;
   const double a = B.a, cc = B.c, kappa = B.kappa, k = B.k;
+  const double eta = CF ? B.eta : 0.0;
   const int nth = B.n_theta, N = nth / 2, npan = B.n_panels;
   const int n = K.n;
   const int T = task.row, ip = task.panel;
@@ -576,8 +660,16 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       const double rr = r2 * ir;
       double s, c;
       sincos_cw(k * rr, &s, &c);
-      const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI * om * PI / N;
-      row[(int64_t)(ip * GL_ORDER + l) * nth + j] = make_double2(-(c + k * rr * s) * sc, (k * rr * c - s) * sc);
+      const double wq = om * PI / N;
+      const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI * wq;
+      double2 v = make_double2(-(c + k * rr * s) * sc, (k * rr * c - s) * sc);
+      if constexpr (CF) {
+        // - i eta e^{i k rho} / (4 pi rho) |J| w
+        const double g = eta * sqrt(nx * nx + ny * ny + nz * nz) * ir * INV_4PI * wq;
+        v.x += s * g;
+        v.y -= c * g;
+      }
+      row[(int64_t)(ip * GL_ORDER + l) * nth + j] = v;
     }
     return;
   }
@@ -599,9 +691,15 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   const double glx = lane < GL_ORDER ? gl16[lane] : 0.0;
   const double glb = lane < GL_ORDER ? gl16[32 + lane] : 0.0;
   // lane s < 2N accumulates sum_q w_q P_l(s_q) K_{s-N}(s_q), l < 16
+  // (CF: the single-layer modes in acs)
   double2 acc[GL_ORDER];
+  double2 acs[CF ? GL_ORDER : 1];
 #pragma unroll
   for (int l = 0; l < GL_ORDER; ++l) acc[l] = make_double2(0.0, 0.0);
+  if constexpr (CF) {
+#pragma unroll
+    for (int l = 0; l < GL_ORDER; ++l) acs[l] = make_double2(0.0, 0.0);
+  }
   const double e0 = -0.5 * PI + h * ip, e1 = e0 + h;
   const int nsides = (ip == pT) ? 2 : 1;
   for (int side = 0; side < nsides; ++side) {
@@ -654,10 +752,12 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         const double dlq = __shfl(dl, sl);
         const double wq = __shfl(w, sl);
         const NodeLoc Ln = node_local(shape, a, cc, kappa, TG, dlq);
-        modal_modes(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.tw);
-        const double2 K = modal_slot(N, Ln, S.u.m);
+        modal_modes<CF>(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.tw);
+        double2 ks;
+        const double2 Kq = modal_slot<CF>(N, Ln, S.u.m, ks);
         const double pw = lagrange_lane(2.0 * (Ln.s - e0) / h - 1.0, glx, glb) * wq;
-        accumulate_modes(acc, pw, K);
+        accumulate_modes(acc, pw, Kq);
+        if constexpr (CF) accumulate_modes(acs, pw, ks);
         __syncthreads();
       }
     }
@@ -690,60 +790,69 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
           double s, c;
           sincos_cw(k * rr, &s, &c);
           const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI;
-          S.u.K[l] = make_double2(-fma(k * rr, s, c) * sc, fma(k * rr, c, -s) * sc);
+          S.u.K[0][l] = make_double2(-fma(k * rr, s, c) * sc, fma(k * rr, c, -s) * sc);
+          if constexpr (CF) S.u.K[CF ? 1 : 0][l] = make_double2(c * ir * INV_4PI, s * ir * INV_4PI);
         }
       }
       const double pw = lagrange_lane(2.0 * (sq - e0) / h - 1.0, glx, glb) * wq;
       __syncthreads();
-      if (w256) fft256(S.u.K, S.tw); else fft128(S.u.K, S.tw);
-      // mode slot s = lane: m = s - N (slot 0 also takes m = +N), K_m = (2 pi / L) X[m mod L]
-      double2 K = make_double2(0.0, 0.0);
-      if (lane < 2 * N) {
-        K = S.u.K[(lane - N + L) & (L - 1)];
-        if (lane == 0) {
-          const double2 v = S.u.K[N];
-          K.x += v.x;
-          K.y += v.y;
-        }
-        const double f = TWO_PI / L;
-        K.x *= f;
-        K.y *= f;
+      if (w256) fft256(S.u.K[0], S.tw); else fft128(S.u.K[0], S.tw);
+      if constexpr (CF) {
+        if (w256) fft256(S.u.K[CF ? 1 : 0], S.tw); else fft128(S.u.K[CF ? 1 : 0], S.tw);
       }
-      accumulate_modes(acc, pw, K);
+      // mode slot s = lane: m = s - N (slot 0 also takes m = +N), K_m = (2 pi / L) X[m mod L]
+#pragma unroll
+      for (int part = 0; part < (CF ? 2 : 1); ++part) {
+        double2 Kq = make_double2(0.0, 0.0);
+        if (lane < 2 * N) {
+          Kq = S.u.K[part][(lane - N + L) & (L - 1)];
+          if (lane == 0) {
+            const double2 v = S.u.K[part][N];
+            Kq.x += v.x;
+            Kq.y += v.y;
+          }
+          const double f = TWO_PI / L;
+          Kq.x *= f;
+          Kq.y *= f;
+        }
+        if (part == 0) accumulate_modes(acc, pw, Kq);
+        else if constexpr (CF) accumulate_modes(acs, pw, Kq);
+      }
       __syncthreads();
     }
   }
   __syncthreads();   // the recurrence batches are done with S.Q (shares S.acc)
-  // inverse DFT onto the Lagrange basis: lane j < 2N,
-  // G_lj = (1/2N) sum_s acc_l[s] e^{i (s - N) theta_j}, slot 0 weighted 1/2;
-  // e^{i (s - N) j pi / N} = (-1)^j e^{i pi s j / N}
-#pragma unroll
-  for (int l = 0; l < GL_ORDER; ++l) {
-    const double f = lane == 0 ? 0.5 : 1.0;
-    S.acc[l][lane] = make_double2(acc[l].x * f, acc[l].y * f);
-  }
+  store_slots(S, acc);
   __syncthreads();
-  if (lane < 2 * N) {
-    double2 g[GL_ORDER];
-#pragma unroll
-    for (int l = 0; l < GL_ORDER; ++l) g[l] = make_double2(0.0, 0.0);
-    int e = 0;
-    for (int sl = 0; sl < 2 * N; ++sl) {
-      const double2 t = S.tw2n[e];
-      e += lane;
-      if (e >= 2 * N) e -= 2 * N;
+  double2 g[GL_ORDER];
+  if (lane < 2 * N) slots_to_nodes(S, N, g);
+  if constexpr (CF) {
+    // single layer: second inverse DFT, then - i eta |J| at the column node
+    __syncthreads();
+    store_slots(S, acs);
+    __syncthreads();
+    if (lane < 2 * N) {
+      double2 gs[GL_ORDER];
+      slots_to_nodes(S, N, gs);
+      double sj, cj;
+      sincos_cw(lane * PI / N, &sj, &cj);
 #pragma unroll
       for (int l = 0; l < GL_ORDER; ++l) {
-        const double2 v = S.acc[l][sl];
-        g[l].x = fma(v.x, t.x, fma(-v.y, t.y, g[l].x));
-        g[l].y = fma(v.x, t.y, fma(v.y, t.x, g[l].y));
+        const double t = e0 + 0.5 * h * (gl16[l] + 1.0);
+        const Curve cv = curve_eval(shape, a, cc, kappa, t);
+        const double dn = cv.dr + cv.dp * cj + cv.dq * sj;
+        const double jac = cv.r * sqrt(cv.dz * cv.dz + dn * dn);
+        const double f = eta * jac;
+        g[l].x = fma(f, gs[l].y, g[l].x);
+        g[l].y = fma(-f, gs[l].x, g[l].y);
       }
     }
-    const double scale = ((lane & 1) ? -1.0 : 1.0) / (2 * N);
+  }
+  if (lane < 2 * N) {
     const bool diag = ip == pT && lane == jT;
 #pragma unroll
     for (int l = 0; l < GL_ORDER; ++l) {
-      double2 v = make_double2(g[l].x * scale, g[l].y * scale);
+      double2 v = g[l];
       if (diag && l == lT) v.x += 0.5;     // 1/2 I
       row[(int64_t)(ip * GL_ORDER + l) * nth + lane] = v;
     }
@@ -779,8 +888,14 @@ hipError_t launch_assemble_self(qax_problem* p) {
   if (e == hipSuccess) e = hipMemcpyAsync(d_rule, &R, sizeof(R), hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) {
     timing_begin(p, QAX_K_SELF_ASSEMBLY);
-    hipLaunchKernelGGL(assemble_self_kernel, dim3((unsigned)tasks.size()), dim3(64), 0, p->stream,
-                       d_tasks, p->d_blocks, p->d_bodies, p->d_gl, d_rule, (double2*)p->d_B);
+    if (p->formulation == QAX_COMBINED_FIELD)
+      hipLaunchKernelGGL(assemble_self_kernel<true>, dim3((unsigned)tasks.size()), dim3(64), 0,
+                         p->stream, d_tasks, p->d_blocks, p->d_bodies, p->d_gl, d_rule,
+                         (double2*)p->d_B);
+    else
+      hipLaunchKernelGGL(assemble_self_kernel<false>, dim3((unsigned)tasks.size()), dim3(64), 0,
+                         p->stream, d_tasks, p->d_blocks, p->d_bodies, p->d_gl, d_rule,
+                         (double2*)p->d_B);
     timing_end(p, QAX_K_SELF_ASSEMBLY);
     e = hipGetLastError();
   }
@@ -798,7 +913,7 @@ __global__ __launch_bounds__(64) void modal_modes_kernel(const double* __restric
                                                          const double* __restrict__ rmrt, double k,
                                                          int nmax, double2* __restrict__ A,
                                                          double2* __restrict__ B) {
-  __shared__ SelfShared S;
+  __shared__ SelfShared<false> S;
   const int pt = blockIdx.x;
   const int lane = threadIdx.x;
   for (int q = lane; q < LD; q += 64) {
@@ -808,7 +923,7 @@ __global__ __launch_bounds__(64) void modal_modes_kernel(const double* __restric
   }
   toroidal_q_batch(lane == 0, 1.0 + chim1[pt], chim1[pt], MQ_CAP, S.Q, lane & (QB - 1));
   __syncthreads();
-  modal_modes(k, r[pt], rt[pt], c[pt], chim1[pt], rmrt[pt], nmax, S.Q, 0, S.u.m, S.tw);
+  modal_modes<false>(k, r[pt], rt[pt], c[pt], chim1[pt], rmrt[pt], nmax, S.Q, 0, S.u.m, S.tw);
   if (lane <= nmax) {
     A[(int64_t)pt * (nmax + 1) + lane] = S.u.m.Am[lane];
     B[(int64_t)pt * (nmax + 1) + lane] = S.u.m.Bm[lane];

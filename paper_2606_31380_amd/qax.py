@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libqax.so")
 
 QAX_OK, QAX_ERR_ARG, QAX_ERR_DEVICE, QAX_ERR_NOMEM, QAX_ERR_NOCONV, QAX_ERR_STATE = range(6)
 QAX_FP64, QAX_MIXED = 0, 1
+QAX_DOUBLE_LAYER, QAX_COMBINED_FIELD = 0, 1
 STATUS_NAMES = {0: "QAX_OK", 1: "QAX_ERR_ARG", 2: "QAX_ERR_DEVICE", 3: "QAX_ERR_NOMEM",
                 4: "QAX_ERR_NOCONV", 5: "QAX_ERR_STATE"}
 
@@ -51,7 +52,7 @@ EXPORTS = ["qax_create", "qax_destroy", "qax_last_error", "qax_build", "qax_size
            "qax_assemble_self", "qax_self_block", "qax_pair_sum", "qax_block_apply", "qax_apply",
            "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes",
            "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning", "qax_set_graphs",
-           "qax_solve_rhs", "qax_nearfield"]
+           "qax_solve_rhs", "qax_nearfield", "qax_set_formulation"]
 (QAX_K_PAIRSUM_FP64, QAX_K_PAIRSUM_FP32, QAX_K_BLOCK_APPLY, QAX_K_SELF_ASSEMBLY, QAX_K_INVERT,
  QAX_K_INVERT_UPDATE, QAX_K_BLOCK_APPLY_F32) = range(7)
 KERNEL_NAMES = ["pair_sum_fp64", "pair_sum_fp32", "block_apply", "self_assembly", "invert",
@@ -92,6 +93,7 @@ def lib():
         "qax_modal_modes": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, d, i32, vp, vp]),
         "qax_set_timing": (C.c_int, [vp, i32]),
         "qax_set_graphs": (C.c_int, [vp, i32]),
+        "qax_set_formulation": (C.c_int, [vp, i32, C.c_double]),
         "qax_timing": (C.c_int, [vp, i32, C.POINTER(i64), pd]),
         "qax_autotune": (C.c_int, [vp, i32, C.c_char_p]),
         "qax_tuning": (C.c_int, [vp, C.POINTER(qax_tuning_info)]),
@@ -238,6 +240,11 @@ def qax_set_graphs(h, enable=True):
     _check(h, lib().qax_set_graphs(h, int(bool(enable))))
 
 
+def qax_set_formulation(h, formulation, eta=0.0):
+    """QAX_DOUBLE_LAYER or QAX_COMBINED_FIELD; eta > 0 fixed coupling, else k."""
+    _check(h, lib().qax_set_formulation(h, int(formulation), float(eta)))
+
+
 def qax_set_timing(h, enable=True):
     _check(h, lib().qax_set_timing(h, int(bool(enable))))
 
@@ -282,13 +289,15 @@ def qax_set_tuning(h, pair_tpb=(256, 256), pair_slot_mult=(8, 8),
 class Problem:
     """Handle + scenario convenience wrapper (marshalling only)."""
 
-    def __init__(self, scenario, device=0):
+    def __init__(self, scenario, device=0, formulation=None, eta=0.0):
         import torch
         self.torch = torch
         self.scenario = scenario
         self.dev = torch.device("cuda", device)
         stream = torch.cuda.current_stream(self.dev).cuda_stream
         self.h = qax_create(device, stream)
+        if formulation is not None:
+            qax_set_formulation(self.h, formulation, eta)
         qax_build(self.h, scenario.bodies, scenario.k)
         self.N, self.offsets = qax_size(self.h, len(scenario.bodies))
 
