@@ -257,6 +257,35 @@ def tiny(n_bodies=2, n_panels=1, n_theta=8, k=2.0, seed=0, shapes=(SPHEROID,),
     return Scenario("tiny", b, np.array([k]), paper_direction(), tol=1e-10)
 
 
+def identical_array(dims=(2, 2, 3), spacing=(3.0, 2.5, 3.5), shape=SPHEROID, a=0.5, c=1.0,
+                    kappa=0.2, n_panels=1, n_theta=8, angles=(0.4, 0.9), k=2.0, seed=0,
+                    shuffle=True) -> Scenario:
+    """Identical bodies (same shape, curvature, orientation and
+    discretisation) on a regular P x Q x R array with the given spacing per
+    axis, listed in a seeded random order when `shuffle` is set."""
+    P, Q, R = dims
+    n = P * Q * R
+    b = make_bodies(n)
+    order = np.arange(n)
+    if shuffle:
+        order = np.random.Generator(np.random.PCG64(seed)).permutation(n)
+    for slot, site in enumerate(order):
+        i, rem = divmod(int(site), Q * R)
+        j, l = divmod(rem, R)
+        _fill(b[slot], shape, a, c, kappa, n_panels, n_theta, angles[0], angles[1],
+              (spacing[0] * i, spacing[1] * j, spacing[2] * l))
+    return Scenario("identical_array", b, np.array([k]), paper_direction(), tol=1e-10)
+
+
+def cubic_array(P=10, n_panels=1, n_theta=6, k=2.0, spacing=3.0) -> Scenario:
+    """Regular cubic array of P^3 identical bent spheroids (0.5, 0.5, 1.0),
+    kappa = 0.2, one orientation, spacing 3 (gap >= 1): the block-reuse
+    configuration of Example 4 (1000 bodies, 16 x 6 = 96 nodes per body),
+    with bodies of this build's shape family."""
+    return identical_array((P, P, P), (spacing,) * 3, n_panels=n_panels, n_theta=n_theta, k=k,
+                           shuffle=False)
+
+
 WORKLOADS = {
     "two_spheres": two_spheres,
     "lattice27": lattice27,
