@@ -214,6 +214,27 @@ qax_status qax_set_graphs(qax_problem* p, int32_t enable);
 typedef enum { QAX_DOUBLE_LAYER = 0, QAX_COMBINED_FIELD = 1 } qax_formulation;
 qax_status qax_set_formulation(qax_problem* p, int32_t formulation, double eta);
 
+/* Block-Toeplitz inter-body apply for a regular array of identical bodies
+ * (Section 4, the paragraph on identical scatterers on a P x Q x R array:
+ * the interaction block of two bodies depends only on the displacement of
+ * their centres, so there are (2P-1)(2Q-1)(2R-1) - 1 distinct blocks; Table
+ * 7).  enable != 0: checks that the built handle holds one problem whose
+ * bodies share shape, curvature, discretisation and orientation and whose
+ * centres fill a P x Q x R array aligned with the coordinate axes (uniform
+ * spacing per axis, any listing order), then computes one block per
+ * displacement on the device, transforms them over the array's circulant
+ * embedding of size (2P-1)(2Q-1)(2R-1) = F, and keeps the F frequency
+ * tables (F n_b^2 complex128 plus a complex64 copy, n_b nodes per body).
+ * From then on every inter-body sum of the handle (qax_pair_sum, qax_apply,
+ * the solvers; QAX_MIXED uses the complex64 tables) is evaluated as: forward
+ * transform of the density over the array, one n_b x n_b product per
+ * frequency (batched; matrix cores for 4 or more right-hand sides), inverse
+ * transform.  enable = 0 frees the tables and returns to the direct pair
+ * sum; qax_build and qax_set_formulation also free them.  dims (host, 3
+ * int32, may be null) receives P, Q, R.  Errors: QAX_ERR_STATE (not built),
+ * QAX_ERR_ARG (not such an array, or F > 65535), QAX_ERR_NOMEM. */
+qax_status qax_lattice(qax_problem* p, int32_t enable, int32_t* dims);
+
 /* Kernel timing (instrumentation).  When enabled, each launch of the kernels
  * below is bracketed by HIP events recorded on the handle's stream and its
  * duration is accumulated per kernel kind.  Disabled by default. */
@@ -225,7 +246,9 @@ typedef enum {
   QAX_K_INVERT = 4,        /* self-block inversion (all of its launches)       */
   QAX_K_INVERT_UPDATE = 5, /* inversion: trailing update of one 64-column panel */
   QAX_K_BLOCK_APPLY_F32 = 6, /* block-diagonal apply of the FP32 copy of B^-1   */
-  QAX_K_COUNT = 7
+  QAX_K_LATTICE_F64 = 7,   /* lattice apply: per-frequency products, FP64 tables */
+  QAX_K_LATTICE_F32 = 8,   /* lattice apply: per-frequency products, FP32 tables */
+  QAX_K_COUNT = 9
 } qax_kernel;
 
 /* enable != 0 turns timing on (and clears the counters). */

@@ -18,8 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqax.so")
-SOURCES = ["geometry.hip", "pairsum.hip", "nearfield.hip", "dense.hip", "krylov.hip", "selfblock.hip",
-           "api.hip"]
+SOURCES = ["geometry.hip", "pairsum.hip", "nearfield.hip", "lattice.hip", "dense.hip", "krylov.hip",
+           "selfblock.hip", "api.hip"]
 ARCH = "gfx950"
 
 

@@ -173,6 +173,7 @@ static void free_geometry(qax_problem* p) {
   if (p->d_gemm_tasks) (void)hipFree(p->d_gemm_tasks);
   p->d_gemm_tasks = nullptr;
   p->gemm_tasks.clear();
+  lattice_free(p);
 }
 
 extern "C" void qax_destroy(qax_problem* p) {
@@ -214,9 +215,11 @@ extern "C" qax_status qax_set_formulation(qax_problem* p, int32_t formulation, d
   p->formulation = formulation;
   p->eta_param = eta;
   if (p->state < 1) return QAX_OK;
-  // built handle: couplings, weights and task tables follow; blocks are stale
+  // built handle: couplings, weights and task tables follow; blocks and the
+  // lattice tables are stale
   QCHECK(hipSetDevice(p->device), "hipSetDevice");
   QCHECK(hipStreamSynchronize(p->stream), "sync");
+  lattice_free(p);
   for (auto& d : p->hbodies) d.eta = p->eta_of(d.k);
   QCHECK(hipMemcpyAsync(p->d_bodies, p->hbodies.data(), sizeof(BodyDev) * p->hbodies.size(),
                         hipMemcpyHostToDevice, p->stream), "copy bodies");
@@ -226,6 +229,19 @@ extern "C" qax_status qax_set_formulation(qax_problem* p, int32_t formulation, d
   QCHECK(upload_pair_plan(p, QAX_MIXED, cus), "pair-sum plan");
   p->state = std::min(p->state, 1);
   return sync(p, "qax_set_formulation");
+}
+
+extern "C" qax_status qax_lattice(qax_problem* p, int32_t enable, int32_t* dims) {
+  if (!p) return QAX_ERR_ARG;
+  if (p->state < 1) return fail(p, QAX_ERR_STATE, "qax_lattice: build first");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  lattice_free(p);
+  ++p->generation;
+  if (!enable) return QAX_OK;
+  const qax_status st = lattice_enable(p, dims);
+  if (st != QAX_OK) lattice_free(p);
+  return st;
 }
 
 extern "C" qax_status qax_set_graphs(qax_problem* p, int32_t enable) {
@@ -450,8 +466,7 @@ static qax_status check_vec_call(qax_problem* p, const void* a, const void* b, i
 
 static qax_status pair_sum_into(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
                                 bool accumulate) {
-  const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;
-  QBUF(partial, double, "pair_partial", (size_t)slots * p->N * nrhs * 16);
+  QBUF(partial, double, "pair_partial", pair_work_bytes(p, prec, nrhs));
   QCHECK(launch_pair_sum(p, prec, mu, out, nrhs, partial, accumulate), "pair_sum");
   return QAX_OK;
 }
@@ -691,9 +706,11 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
     G.scl = gscl;
   }
   QBUF(ydev, double2, "kry_y", (size_t)m * nseg * 16);
-  // pair-sum workspace sized before any capture (no allocation inside a graph)
-  const int pslots = inner_prec == QAX_FP64 ? p->slots64 : p->slots32;
-  QBUF(ppart, double, "pair_partial", (size_t)pslots * N * nrhs * 16);
+  // pair-sum workspace sized before any capture (no allocation inside a
+  // graph), large enough for the FP64 residual's pair sum too, so that the
+  // shared buffer is never reallocated under the captured steps
+  QBUF(ppart, double, "pair_partial",
+       std::max(pair_work_bytes(p, inner_prec, nrhs), pair_work_bytes(p, QAX_FP64, nrhs)));
   if (p->h_flags_n < m + 1) {
     if (p->h_flags) (void)hipHostFree(p->h_flags);
     p->h_flags = nullptr;
@@ -984,6 +1001,13 @@ extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char*
   }
   const bool was_timing = p->timing;
   p->timing = false;
+  // the launch choices concern the direct pair sum: lattice tables off while tuning
+  struct LatticeOff {
+    qax_problem* q;
+    bool on;
+    explicit LatticeOff(qax_problem* h) : q(h), on(h->lat.active) { h->lat.active = false; }
+    ~LatticeOff() { q->lat.active = on; }
+  } lattice_off(p);
   QBUF(mu, double, "tune_mu", (size_t)p->N * nrhs_max * 16);
   QBUF(out, double, "tune_out", (size_t)p->N * nrhs_max * 16);
   QCHECK(hipMemsetAsync(mu, 0, (size_t)p->N * nrhs_max * 16, p->stream), "zero");

@@ -273,6 +273,48 @@ hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double
   return hipGetLastError();
 }
 
+// Block-diagonal products over caller-built tables (the lattice apply's
+// per-frequency matrices): rows = sum of the orders, every order a multiple
+// of 16.
+hipError_t launch_gemv_tables(hipStream_t s, const BodyDev* bodies, const BlockDev* blocks,
+                              const int32_t* node_body, const void* pool, bool f32, int64_t rows,
+                              const double* v, int nrhs, double* out, bool accumulate) {
+  const int nrc = nrhs == 1 ? 1 : 4;
+  dim3 grid((unsigned)((rows + 3) / 4), (unsigned)((nrhs + nrc - 1) / nrc));
+  const double2* vv = (const double2*)v;
+  double2* oo = (double2*)out;
+  const int acc = accumulate ? 1 : 0;
+  if (f32) {
+    if (nrc == 1)
+      hipLaunchKernelGGL((block_gemv_kernel<float, 1, 2>), grid, dim3(256), 0, s, bodies, blocks,
+                         node_body, (const float*)pool, rows, vv, nrhs, oo, acc, nullptr);
+    else
+      hipLaunchKernelGGL((block_gemv_kernel<float, 4, 1>), grid, dim3(256), 0, s, bodies, blocks,
+                         node_body, (const float*)pool, rows, vv, nrhs, oo, acc, nullptr);
+  } else {
+    if (nrc == 1)
+      hipLaunchKernelGGL((block_gemv_kernel<double, 1, 1>), grid, dim3(256), 0, s, bodies, blocks,
+                         node_body, (const double*)pool, rows, vv, nrhs, oo, acc, nullptr);
+    else
+      hipLaunchKernelGGL((block_gemv_kernel<double, 4, 1>), grid, dim3(256), 0, s, bodies, blocks,
+                         node_body, (const double*)pool, rows, vv, nrhs, oo, acc, nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_tables(hipStream_t s, const GemmTask* tasks, int ntasks,
+                              const BodyDev* bodies, const BlockDev* blocks, const void* pool,
+                              bool f32, const double* v, int nrhs, double* out, bool accumulate) {
+  dim3 grid((unsigned)ntasks, (unsigned)((2 * nrhs + 63) / 64));
+  if (f32)
+    hipLaunchKernelGGL(block_gemm_kernel<float>, grid, dim3(256), 0, s, tasks, bodies, blocks,
+                       (const float*)pool, v, nrhs, out, accumulate ? 1 : 0);
+  else
+    hipLaunchKernelGGL(block_gemm_kernel<double>, grid, dim3(256), 0, s, tasks, bodies, blocks,
+                       (const double*)pool, v, nrhs, out, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- conversion
 __global__ void convert_f32_kernel(const double* __restrict__ src, float* __restrict__ dst,
                                    int64_t count) {

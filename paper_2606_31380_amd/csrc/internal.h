@@ -121,6 +121,24 @@ struct qax_problem {
   int32_t plan_tpb[2] = {0, 0};       // workgroup size the task tables were planned for
   qax::Tune tune;
 
+  // block-Toeplitz apply of the inter-body sum on a regular array of
+  // identical bodies (tables per frequency of the circulant embedding)
+  struct Lattice {
+    bool active = false;
+    int dims[3] = {1, 1, 1};            // P, Q, R
+    int L[3] = {1, 1, 1};               // 2P - 1, 2Q - 1, 2R - 1
+    int64_t F = 0;                      // L0 L1 L2 frequencies
+    int nb = 0;                         // nodes per body
+    double* T64 = nullptr;              // F x nb x nb complex128
+    float* T32 = nullptr;               // complex64 copy
+    qax::BodyDev* d_fbodies = nullptr;  // one "body" per frequency (batched products)
+    qax::BlockDev* d_fblocks = nullptr;
+    int32_t* d_frow = nullptr;          // row -> frequency
+    qax::GemmTask* d_ftasks = nullptr;
+    int nftasks = 0;
+    int64_t* d_site_node = nullptr;     // first node of the body at each site
+  } lat;
+
   // block GEMM row tiles (several right-hand sides)
   std::vector<qax::GemmTask> gemm_tasks;
   void* d_gemm_tasks = nullptr;
@@ -170,7 +188,23 @@ void gauss_legendre_host(int n, double* x, double* w);
 hipError_t launch_build_nodes(qax_problem* p);
 hipError_t launch_node_weights(qax_problem* p);
 
+// lattice.hip
+void lattice_free(qax_problem* p);
+qax_status lattice_enable(qax_problem* p, int32_t* dims);
+hipError_t launch_lattice_apply(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
+                                double* work, bool accumulate);
+size_t lattice_work_bytes(const qax_problem* p, int nrhs);
+
+// dense.hip: block-diagonal products over explicit tables
+hipError_t launch_gemv_tables(hipStream_t s, const BodyDev* bodies, const BlockDev* blocks,
+                              const int32_t* node_body, const void* pool, bool f32, int64_t rows,
+                              const double* v, int nrhs, double* out, bool accumulate);
+hipError_t launch_gemm_tables(hipStream_t s, const GemmTask* tasks, int ntasks,
+                              const BodyDev* bodies, const BlockDev* blocks, const void* pool,
+                              bool f32, const double* v, int nrhs, double* out, bool accumulate);
+
 // pairsum.hip
+size_t pair_work_bytes(const qax_problem* p, int prec, int nrhs);
 hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
                            double* partial, bool accumulate);
 void plan_pair_sum(qax_problem* p, int prec, int cu_count);

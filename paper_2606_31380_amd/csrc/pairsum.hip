@@ -435,8 +435,21 @@ static void launch_any(qax_problem* p, bool f64, int tpb, int nrc, const double*
 // out += pair sum when accumulate is set.  The workgroup size is the one the
 // task table was planned with; right-hand sides per pass from the tuning
 // (clamped to a supported configuration).
+size_t pair_work_bytes(const qax_problem* p, int prec, int nrhs) {
+  const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;
+  return std::max((size_t)slots * p->N * nrhs * 16, lattice_work_bytes(p, nrhs));
+}
+
 hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
                            double* partial, bool accumulate) {
+  if (p->lat.active) {
+    // regular array of identical bodies: block-Toeplitz apply
+    const int kind = prec == QAX_FP64 ? QAX_K_PAIRSUM_FP64 : QAX_K_PAIRSUM_FP32;
+    timing_begin(p, kind);
+    hipError_t e = launch_lattice_apply(p, prec, mu, out, nrhs, partial, accumulate);
+    timing_end(p, kind);
+    return e;
+  }
   const bool f64 = prec == QAX_FP64;
   const int pi = f64 ? 0 : 1;
   const int kind = f64 ? QAX_K_PAIRSUM_FP64 : QAX_K_PAIRSUM_FP32;

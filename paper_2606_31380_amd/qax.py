@@ -52,11 +52,11 @@ EXPORTS = ["qax_create", "qax_destroy", "qax_last_error", "qax_build", "qax_size
            "qax_assemble_self", "qax_self_block", "qax_pair_sum", "qax_block_apply", "qax_apply",
            "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes",
            "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning", "qax_set_graphs",
-           "qax_solve_rhs", "qax_nearfield", "qax_set_formulation"]
+           "qax_solve_rhs", "qax_nearfield", "qax_set_formulation", "qax_lattice"]
 (QAX_K_PAIRSUM_FP64, QAX_K_PAIRSUM_FP32, QAX_K_BLOCK_APPLY, QAX_K_SELF_ASSEMBLY, QAX_K_INVERT,
- QAX_K_INVERT_UPDATE, QAX_K_BLOCK_APPLY_F32) = range(7)
+ QAX_K_INVERT_UPDATE, QAX_K_BLOCK_APPLY_F32, QAX_K_LATTICE_F64, QAX_K_LATTICE_F32) = range(9)
 KERNEL_NAMES = ["pair_sum_fp64", "pair_sum_fp32", "block_apply", "self_assembly", "invert",
-                "invert_update", "block_apply_f32"]
+                "invert_update", "block_apply_f32", "lattice_f64", "lattice_f32"]
 
 
 def lib():
@@ -94,6 +94,7 @@ def lib():
         "qax_set_timing": (C.c_int, [vp, i32]),
         "qax_set_graphs": (C.c_int, [vp, i32]),
         "qax_set_formulation": (C.c_int, [vp, i32, C.c_double]),
+        "qax_lattice": (C.c_int, [vp, i32, C.POINTER(i32)]),
         "qax_timing": (C.c_int, [vp, i32, C.POINTER(i64), pd]),
         "qax_autotune": (C.c_int, [vp, i32, C.c_char_p]),
         "qax_tuning": (C.c_int, [vp, C.POINTER(qax_tuning_info)]),
@@ -238,6 +239,14 @@ def qax_modal_modes(h, r, rt, c, chim1, rmrt, k, nmax, A, B):
 
 def qax_set_graphs(h, enable=True):
     _check(h, lib().qax_set_graphs(h, int(bool(enable))))
+
+
+def qax_lattice(h, enable=True):
+    """Block-Toeplitz inter-body apply on a regular array of identical bodies;
+    returns (P, Q, R) when enabled."""
+    dims = (C.c_int32 * 3)()
+    _check(h, lib().qax_lattice(h, int(bool(enable)), dims))
+    return tuple(int(v) for v in dims) if enable else None
 
 
 def qax_set_formulation(h, formulation, eta=0.0):
