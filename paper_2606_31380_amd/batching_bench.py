@@ -2,6 +2,7 @@
 
     python -m paper_2606_31380_amd.batching_bench multi_rhs [--loop-sample 8]
     python -m paper_2606_31380_amd.batching_bench batch
+    python -m paper_2606_31380_amd.batching_bench lattice
 
 multi_rhs -- 200 bent spheroids (32 GL x 64 azimuthal nodes, N = 409,600),
 k = 6, 64 incident directions: one FP32 / FP64 pair sum over all 64
@@ -17,6 +18,12 @@ batch -- 32 independent problems (1-100 bent spheroids each, 16-32 GL x
 N = 1,746,400 in total): one handle holding all problems (one launch per
 kernel for all of them, captured GMRES steps) against 32 handles solved one
 after the other; time to solve to 1e-6 (mixed and FP64) and set-up time.
+
+lattice -- regular 10 x 10 x 10 arrays of identical bent spheroids (the
+block-reuse configuration of Example 4: 96 nodes per body, and 512 nodes per
+body), k = 2: the direct pair sum against the block-Toeplitz apply
+(qax_lattice), 1 and 16 right-hand sides, FP64 and FP32 tables, the
+per-frequency product's share and bandwidth, and the time to solve to 1e-6.
 
 Inputs are synthetic and seeded (paper_2606_31380_amd.scenarios).
 """
@@ -175,14 +182,93 @@ def batch() -> dict:
     return res
 
 
+def lattice() -> dict:
+    """Regular cubic arrays of identical bent spheroids (Example 4's block
+    reuse configuration): direct pair sum against the block-Toeplitz apply."""
+    import torch
+
+    from paper_2606_31380_amd import qax
+    from paper_2606_31380_amd import scenarios as sc
+
+    dev = torch.device("cuda", 0)
+    out = []
+    for n_panels, n_theta in ((1, 6), (2, 16)):
+        s = sc.cubic_array(10, n_panels=n_panels, n_theta=n_theta, k=2.0)
+        rec = {"workload": f"10x10x10 identical bent spheroids (0.5, 0.5, 1.0), kappa 0.2, spacing 3, "
+                           f"{16 * n_panels} GL x {n_theta} azimuths, k = 2",
+               "pairs_per_apply": int(s.pairs_per_apply())}
+        with qax.Problem(s) as Pr:
+            N = Pr.N
+            rec["n_unknowns"] = N
+            nb = N // 1000
+            t_asm, _ = _timed(lambda: qax.qax_assemble_self(Pr.h))
+            rec["setup_assemble_invert_s"] = t_asm
+            g = torch.Generator(device="cpu").manual_seed(0)
+            for nrhs in (1, 16):
+                V = torch.randn(N * nrhs, dtype=torch.complex128, generator=g).to(dev)
+                O = torch.zeros_like(V)
+                for prec, name in ((qax.QAX_FP64, "fp64"), (qax.QAX_MIXED, "fp32")):
+                    qax.qax_pair_sum(Pr.h, prec, V, O, nrhs)
+                    t, _ = _timed(lambda: qax.qax_pair_sum(Pr.h, prec, V, O, nrhs))
+                    rec[f"direct_pair_sum_{name}_nrhs{nrhs}_s"] = t
+            solve = n_panels == 1      # the direct solve of the finer array takes minutes
+            if solve:
+                x = torch.zeros(N, dtype=torch.complex128, device=dev)
+                info = qax.qax_solve(Pr.h, qax.QAX_MIXED, s.dirs, x, 1, tol=1e-6, maxit=3000)
+                rec["direct_solve_mixed_1e-6"] = {"s": info["t_solve_s"], "iters": info["iters"]}
+            print(f"lattice {nb}: direct done", flush=True)
+            t_lat, _ = _timed(lambda: qax.qax_lattice(Pr.h))
+            rec["lattice_setup_s"] = t_lat
+            F = 19 ** 3
+            rec["frequencies"] = F
+            for nrhs in (1, 16):
+                V = torch.randn(N * nrhs, dtype=torch.complex128, generator=g).to(dev)
+                O = torch.zeros_like(V)
+                for prec, name, kind, eb in ((qax.QAX_FP64, "fp64", qax.QAX_K_LATTICE_F64, 16),
+                                             (qax.QAX_MIXED, "fp32", qax.QAX_K_LATTICE_F32, 8)):
+                    qax.qax_pair_sum(Pr.h, prec, V, O, nrhs)
+                    reps = 20
+                    t, _ = _timed(lambda: [qax.qax_pair_sum(Pr.h, prec, V, O, nrhs) for _ in range(reps)])
+                    qax.qax_set_timing(Pr.h, True)
+                    for _ in range(reps):
+                        qax.qax_pair_sum(Pr.h, prec, V, O, nrhs)
+                    cnt, tot = qax.qax_timing(Pr.h, kind)
+                    qax.qax_set_timing(Pr.h, False)
+                    prod_ms = tot / max(cnt, 1)
+                    table_bytes = F * nb * nb * eb
+                    r = {"apply_s": t / reps, "product_ms": prod_ms,
+                         "speedup_vs_direct": rec[f"direct_pair_sum_{name}_nrhs{nrhs}_s"] / (t / reps)}
+                    if nrhs == 1:
+                        r["product_table_GBps"] = table_bytes / (prod_ms * 1e-3) / 1e9
+                        r["product_hbm_frac"] = r["product_table_GBps"] / 8000.0
+                    else:
+                        flop = 8.0 * F * nb * nb * nrhs
+                        r["product_TFLOPs"] = flop / (prod_ms * 1e-3) / 1e12
+                    rec[f"lattice_{name}_nrhs{nrhs}"] = r
+            x2 = torch.zeros(N, dtype=torch.complex128, device=dev)
+            info = qax.qax_solve(Pr.h, qax.QAX_MIXED, s.dirs, x2, 1, tol=1e-6, maxit=3000)
+            rec["lattice_solve_mixed_1e-6"] = {"s": info["t_solve_s"], "iters": info["iters"]}
+            if solve:
+                rec["solve_speedup"] = rec["direct_solve_mixed_1e-6"]["s"] / info["t_solve_s"]
+                rec["solution_rel_diff"] = (torch.linalg.norm(x2 - x) / torch.linalg.norm(x)).item()
+            print(f"lattice {nb}: lattice done", flush=True)
+        out.append(rec)
+    return {"arrays": out}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("which", choices=["multi_rhs", "batch"])
+    ap.add_argument("which", choices=["multi_rhs", "batch", "lattice"])
     ap.add_argument("--loop-sample", type=int, default=8)
     args = ap.parse_args()
     import torch
     torch.cuda.set_device(0)
-    r = multi_rhs(args.loop_sample) if args.which == "multi_rhs" else batch()
+    if args.which == "multi_rhs":
+        r = multi_rhs(args.loop_sample)
+    elif args.which == "batch":
+        r = batch()
+    else:
+        r = lattice()
     r["measurement"] = args.which
     print(json.dumps(r))
     return 0
