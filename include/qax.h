@@ -56,27 +56,38 @@ typedef enum {
 typedef enum {
   QAX_SPHERE = 0,   /* r = a cos t, z = a sin t                               */
   QAX_SPHEROID = 1, /* r = a cos t, z = c sin t                               */
-  QAX_PEANUT = 2    /* polar radius a (1 + c cos 2 psi), psi = polar angle     */
+  QAX_PEANUT = 2,   /* polar radius a (1 + c cos 2 psi), psi = polar angle     */
+  /* The geometries of Section 6.1, Example 2, scaled by a (c unused, kappa 0): */
+  QAX_QUASI_ELLIPSOID = 3, /* r = 2a cos t, z = 3a sin t, p = a cos t, q = 0 */
+  QAX_SPIRAL = 4,   /* r = 1.5a cos t, z = 2a sin t, p = 0.05a cos 4 pi t,
+                       q = 0.1a sin 4 pi t                                     */
+  QAX_CONCH = 5     /* r = a cos t, z = 1.5a sin t, p = a f cos t, q = a f sin t,
+                       f = 0.2 + 0.1 sin 8t                                    */
 } qax_shape;
 
-/* One body.  Generating curve over t in [-pi/2, pi/2] (south to north),
- * centreline bent into the circle of curvature kappa tangent to the z-axis,
- * p = kappa z^2 / (1 + sqrt(1 - kappa^2 z^2)), q = 0 (the quasi-axisymmetric
- * surface of Section 2, equation para_quasi).  n_panels uniform panels of 16
- * Gauss-Legendre nodes in t times n_theta = 2N azimuthal nodes theta_j = j pi/N
- * (Section 3.1).  World position x = R x0 + centre, R = Rz(theta1) Ry(theta2)
- * (Section 6.2, Example 5).  `problem` selects the independent scattering
- * problem (0..n_problems-1) the body belongs to; bodies of one problem must be
- * contiguous and problems in increasing order. */
+/* One body.  Generating curve over t in [-pi/2, pi/2] (south to north); for
+ * shapes 0-2 the centreline is bent into the circle of curvature kappa tangent
+ * to the z-axis, p = kappa z^2 / (1 + sqrt(1 - kappa^2 z^2)), q = 0 (the
+ * quasi-axisymmetric surface of Section 2, equation para_quasi).  Panels of
+ * 16 Gauss-Legendre nodes in t: n_panels uniform panels, then the panel at
+ * each pole halved n_ref times toward the pole (dyadic refinement, the N_ref
+ * of Section 6), n_panels + 2 n_ref panels in all; times n_theta = 2N
+ * azimuthal nodes theta_j = j pi/N (Section 3.1).  World position
+ * x = R x0 + centre, R = Rz(theta1) Ry(theta2) (Section 6.2, Example 5).
+ * `problem` selects the independent scattering problem (0..n_problems-1) the
+ * body belongs to; bodies of one problem must be contiguous and problems in
+ * increasing order. */
 typedef struct {
   int32_t shape;
-  int32_t n_panels;   /* 1..8 (at most 8192 nodes per body)                 */
+  int32_t n_panels;   /* uniform panels, 1..32                               */
   int32_t n_theta;    /* even, 4..64                                        */
   int32_t problem;
   double a, c;        /* shape parameters (see qax_shape)                   */
   double kappa;       /* 0 <= kappa, kappa * max|z| < 1                       */
   double theta1, theta2;
   double centre[3];
+  int32_t n_ref;      /* 0..8 refinements per pole (n_panels >= 2 when > 0);
+                         at most 8192 nodes per body in all                 */
 } qax_body;
 
 typedef struct {

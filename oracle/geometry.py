@@ -22,6 +22,7 @@ import numpy as np
 
 GL_ORDER = 16
 SPHERE, SPHEROID, PEANUT = 0, 1, 2
+QUASI_ELLIPSOID, SPIRAL, CONCH = 3, 4, 5
 T0, T1 = -0.5 * math.pi, 0.5 * math.pi
 
 
@@ -38,8 +39,31 @@ def curve(shape: int, a: float, c: float, kappa: float, t):
     sphere/spheroid: r = a cos t, z = c sin t.
     peanut: polar radius a (1 + c cos 2 psi), psi = pi/2 - t the polar angle,
             i.e. rho(t) = a (1 - c cos 2t), r = rho cos t, z = rho sin t.
+    The three geometries of Section 6.1, Example 2 (equations quasiellipsoid,
+    spiral, conch), scaled by a (c and kappa unused):
+    quasi-ellipsoid: r = 2a cos t, z = 3a sin t, p = a cos t, q = 0;
+    spiral: r = 1.5a cos t, z = 2a sin t, p = 0.05a cos 4 pi t, q = 0.1a sin 4 pi t;
+    conch: r = a cos t, z = 1.5a sin t, p = a f cos t, q = a f sin t,
+           f = 0.2 + 0.1 sin 8t.
     """
     t = np.asarray(t, dtype=np.float64)
+    if shape in (QUASI_ELLIPSOID, SPIRAL, CONCH):
+        ct, st = np.cos(t), np.sin(t)
+        if shape == QUASI_ELLIPSOID:
+            r, dr, z, dz = 2 * a * ct, -2 * a * st, 3 * a * st, 3 * a * ct
+            p, dp = a * ct, -a * st
+            q, dq = np.zeros_like(t), np.zeros_like(t)
+        elif shape == SPIRAL:
+            w = 4 * np.pi
+            r, dr, z, dz = 1.5 * a * ct, -1.5 * a * st, 2 * a * st, 2 * a * ct
+            p, dp = 0.05 * a * np.cos(w * t), -0.05 * a * w * np.sin(w * t)
+            q, dq = 0.1 * a * np.sin(w * t), 0.1 * a * w * np.cos(w * t)
+        else:
+            f, df = 0.2 + 0.1 * np.sin(8 * t), 0.8 * np.cos(8 * t)
+            r, dr, z, dz = a * ct, -a * st, 1.5 * a * st, 1.5 * a * ct
+            p, dp = a * f * ct, a * (df * ct - f * st)
+            q, dq = a * f * st, a * (df * st + f * ct)
+        return r, dr, z, dz, p, dp, q, dq
     if shape in (SPHERE, SPHEROID):
         r = a * np.cos(t)
         dr = -a * np.sin(t)
@@ -78,6 +102,22 @@ def curve_differences(shape: int, a: float, c: float, kappa: float, t, dl):
     s = t + dl
     sig = t + 0.5 * dl
     sh = np.sin(0.5 * dl)
+    dcos = -2.0 * np.sin(sig) * sh                       # cos s - cos t
+    dsin = -2.0 * np.cos(sig) * sh                       # sin t - sin s
+    if shape == QUASI_ELLIPSOID:
+        return 2 * a * dcos, 3 * a * dsin, -a * dcos, np.zeros_like(dcos)
+    if shape == SPIRAL:
+        w = 4 * np.pi
+        # cos wt - cos ws = 2 sin(w sig) sin(w dl / 2); sin wt - sin ws = -2 cos(w sig) sin(w dl / 2)
+        sw = np.sin(0.5 * w * dl)
+        return (1.5 * a * dcos, 2 * a * dsin, 0.1 * a * np.sin(w * sig) * sw,
+                -0.2 * a * np.cos(w * sig) * sw)
+    if shape == CONCH:
+        f_s = 0.2 + 0.1 * np.sin(8 * s)
+        df = -0.2 * np.cos(8 * sig) * np.sin(4 * dl)      # f(t) - f(s)
+        d_p = a * (df * np.cos(t) - f_s * dcos)
+        d_q = a * (df * np.sin(t) + f_s * dsin)
+        return a * dcos, 1.5 * a * dsin, d_p, d_q
     if shape in (SPHERE, SPHEROID):
         d_r = -2.0 * a * np.sin(sig) * sh                 # a (cos s - cos t)
         d_z = -2.0 * c * np.cos(sig) * sh                 # c (sin t - sin s)
@@ -86,8 +126,6 @@ def curve_differences(shape: int, a: float, c: float, kappa: float, t, dl):
         rho_t = a * (1.0 - c * np.cos(2 * t))
         rho_s = a * (1.0 - c * np.cos(2 * s))
         d_rho = 2.0 * a * c * np.sin(2 * sig) * np.sin(dl)   # rho(s) - rho(t)
-        dcos = -2.0 * np.sin(sig) * sh                       # cos s - cos t
-        dsin = -2.0 * np.cos(sig) * sh                       # sin t - sin s
         d_r = d_rho * np.cos(s) + rho_t * dcos
         d_z = rho_t * dsin - d_rho * np.sin(s)
         z_t, z_s = rho_t * np.sin(t), rho_s * np.sin(s)
@@ -134,7 +172,7 @@ class BodyDisc:
     a: float
     c: float
     kappa: float
-    n_panels: int
+    n_panels: int            # panels after refinement
     n_theta: int
     t_nodes: np.ndarray      # (n_panels*16,) GL parameters, panel-major
     omega: np.ndarray        # (n_panels*16,) scaled GL weights
@@ -149,13 +187,31 @@ class BodyDisc:
         return self.y0.shape[0]
 
 
-def discretize_body(shape, a, c, kappa, n_panels, n_theta) -> BodyDisc:
-    """Panels x 16 GL nodes in t, 2N = n_theta trapezoid nodes in theta."""
-    xg, wg = gauss_legendre(GL_ORDER)
-    edges = np.linspace(T0, T1, n_panels + 1)
+def panel_edges(n_panels: int, n_ref: int = 0) -> np.ndarray:
+    """Breakpoints of the generating curve's parameter interval: n_panels
+    uniform panels, then the panel at each end halved n_ref times toward
+    the pole (dyadic refinement, the N_ref of the notation table of
+    Section 6), n_panels + 2 n_ref panels in all."""
     h = (T1 - T0) / n_panels
-    t_nodes = (edges[:-1, None] + 0.5 * h * (xg[None, :] + 1.0)).ravel()
-    omega = np.tile(0.5 * h * wg, n_panels)
+    uni = T0 + h * np.arange(n_panels + 1)
+    if n_ref == 0:
+        return uni
+    if n_panels < 2:
+        raise ValueError("dyadic refinement needs at least two uniform panels")
+    low = T0 + h * 2.0 ** -np.arange(n_ref, 0, -1)      # T0 + h/2^n_ref, ..., T0 + h/2
+    high = T1 - h * 2.0 ** -np.arange(1, n_ref + 1)     # T1 - h/2, ..., T1 - h/2^n_ref
+    return np.concatenate([[T0], low, uni[1:-1], high, [T1]])
+
+
+def discretize_body(shape, a, c, kappa, n_panels, n_theta, n_ref=0) -> BodyDisc:
+    """Panels x 16 GL nodes in t (n_panels uniform panels, each end panel
+    refined n_ref times), 2N = n_theta trapezoid nodes in theta."""
+    xg, wg = gauss_legendre(GL_ORDER)
+    edges = panel_edges(n_panels, n_ref)
+    n_panels = len(edges) - 1
+    hp = np.diff(edges)
+    t_nodes = (edges[:-1, None] + 0.5 * hp[:, None] * (xg[None, :] + 1.0)).ravel()
+    omega = (0.5 * hp[:, None] * wg[None, :]).ravel()
     N = n_theta // 2
     theta = np.arange(n_theta) * math.pi / N
     tt, th = np.meshgrid(t_nodes, theta, indexing="ij")
@@ -183,8 +239,9 @@ def discretize(scenario) -> Discretization:
     pos, aw, bid, pid, discs, rots = [], [], [], [], [], []
     off = [0]
     for i in range(len(b)):
+        n_ref = int(b["n_ref"][i]) if "n_ref" in b.dtype.names else 0
         d = discretize_body(int(b["shape"][i]), float(b["a"][i]), float(b["c"][i]),
-                            float(b["kappa"][i]), int(b["n_panels"][i]), int(b["n_theta"][i]))
+                            float(b["kappa"][i]), int(b["n_panels"][i]), int(b["n_theta"][i]), n_ref)
         R = rotation(float(b["theta1"][i]), float(b["theta2"][i]))
         cen = np.array([b["cx"][i], b["cy"][i], b["cz"][i]], dtype=np.float64)
         pos.append(d.y0 @ R.T + cen)

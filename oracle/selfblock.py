@@ -2,8 +2,10 @@
 
 Row T (target x on panel p), column (i, l, j) (panel, GL node, azimuth):
 
-  near panels i in {p-1, p, p+1}  (Section 3.1, equations muJ / coef_ele,
-  Section 3.4):  E = int_{gamma_i} P_il(s) G_j(x, s) ds,
+  near panels: i in {p-1, p, p+1}, and any panel on whose rings the smooth
+  rule's trapezoid in theta would not resolve the kernel (see panel_is_near)
+  (Section 3.1, equations muJ / coef_ele, Section 3.4):
+                 E = int_{gamma_i} P_il(s) G_j(x, s) ds,
                  G_j(x, s) = int_0^{2pi} K(x, y(s, theta)) L_j(theta) dtheta,
                  K = grad_y G^k . (d_theta x d_s)   (density mu interpolated);
   far panels     (Section 3.1, equation sx): E = K(x, y_ilj) (pi/N) omega_il.
@@ -34,6 +36,7 @@ L_MODAL = 256
 RATIO = 0.25
 N_SUB = 16
 H_MAX = 0.1           # longest graded subinterval (resolves the azimuthal structure of G_j)
+NEAR_EXP = 40.0       # smooth rule only where the trapezoid's aliased modes are below e^-40
 
 
 def lagrange_gl(nodes, s):
@@ -68,6 +71,26 @@ def graded_rule(s0, s1, levels, ratio=RATIO, n=N_SUB, hmax=H_MAX):
     return np.concatenate(S), np.concatenate(W)
 
 
+def panel_is_near(disc: geo.BodyDisc, pT: int, tT: float, thT: float, i: int) -> bool:
+    """Product integration for panel i (target at (tT, thT) on panel pT): the
+    adjacent panels always, and any panel on which the smooth rule of
+    Section 3.1 (equation sx) would fail in theta.  The kernel's azimuthal
+    modes on a ring decay like e^{-|m| acosh chi}, so the trapezoidal rule on
+    2N points is exact to e^{-2N acosh chi}; near a pole of a dyadically
+    refined curve, panels two or more apart can still have chi - 1 = O(1)
+    (the rings shrink with the panels).  Reading: the paper only names
+    adjacent panels as near; this criterion keeps its smooth rule where it is
+    accurate and extends product integration where it is not."""
+    if abs(i - pT) <= 1:
+        return True
+    s = disc.t_nodes[i * geo.GL_ORDER:(i + 1) * geo.GL_ORDER]
+    loc = modal.local_frame_rel(disc.shape, disc.a, disc.c, disc.kappa, np.full(s.shape, tT),
+                                np.full(s.shape, thT), s - tT)
+    chim1 = loc["chim1"]
+    acosh = np.log1p(chim1 + np.sqrt(chim1 * (chim1 + 2.0)))
+    return bool(np.any(disc.n_theta * acosh < NEAR_EXP))
+
+
 def outer_rule(disc: geo.BodyDisc, pT: int, tT: float, i: int):
     """Outer nodes on near panel i for the target at tT: offsets dl = s - tT and
     weights.  Self panel: split at tT, graded toward tT down to 1e-14 of the
@@ -82,7 +105,7 @@ def outer_rule(disc: geo.BodyDisc, pT: int, tT: float, i: int):
             out_s.append(u)
             out_w.append(w)
         return np.concatenate(out_s), np.concatenate(out_w)
-    if i == pT - 1:
+    if i < pT:
         end, far = e[i + 1], e[i]
     else:
         end, far = e[i], e[i + 1]
@@ -145,8 +168,9 @@ def self_block(disc: geo.BodyDisc, k: float, rows=None, chunk=4000, kind="dl"):
         pT = T // per_panel
         lT = (T // nth) % geo.GL_ORDER
         tT = disc.t_nodes[pT * geo.GL_ORDER + lT]
+        thT = disc.theta[T % nth]
         for i in range(disc.n_panels):
-            if abs(i - pT) <= 1:
+            if panel_is_near(disc, pT, tT, thT, i):
                 s, w = outer_rule(disc, pT, tT, i)
                 rec_row.append(np.full(s.shape, ri))
                 rec_pan.append(np.full(s.shape, i))

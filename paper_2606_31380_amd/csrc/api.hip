@@ -299,10 +299,14 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
   int prev = 0;
   for (int i = 0; i < n_bodies; ++i) {
     const qax_body& b = bodies[i];
-    if (b.shape < 0 || b.shape > 2) return fail(p, QAX_ERR_ARG, "qax_build: unknown shape");
-    if (b.n_panels < 1 || b.n_panels > 8) return fail(p, QAX_ERR_ARG, "qax_build: n_panels must be in [1, 8]");
+    if (b.shape < 0 || b.shape > QAX_CONCH) return fail(p, QAX_ERR_ARG, "qax_build: unknown shape");
+    if (b.n_panels < 1 || b.n_panels > 32) return fail(p, QAX_ERR_ARG, "qax_build: n_panels must be in [1, 32]");
+    if (b.n_ref < 0 || b.n_ref > 8 || (b.n_ref > 0 && b.n_panels < 2))
+      return fail(p, QAX_ERR_ARG, "qax_build: n_ref must be in [0, 8], with n_panels >= 2 when refined");
     if (b.n_theta < 4 || b.n_theta > 64 || (b.n_theta & 1))
       return fail(p, QAX_ERR_ARG, "qax_build: n_theta must be even in [4, 64]");
+    if ((int64_t)(b.n_panels + 2 * b.n_ref) * GL_ORDER * b.n_theta > 8192)
+      return fail(p, QAX_ERR_ARG, "qax_build: more than 8192 nodes in one body");
     if (b.problem < 0 || b.problem >= n_problems || b.problem < prev || b.problem > prev + 1)
       return fail(p, QAX_ERR_ARG, "qax_build: problems must be contiguous and increasing");
     if (i == 0 && b.problem != 0) return fail(p, QAX_ERR_ARG, "qax_build: first body must be in problem 0");
@@ -310,6 +314,11 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
     const double vals[] = {b.a, b.c, b.kappa, b.theta1, b.theta2, b.centre[0], b.centre[1], b.centre[2]};
     for (double v : vals)
       if (!is_finite(v)) return fail(p, QAX_ERR_ARG, "qax_build: non-finite body parameter");
+    if (b.shape >= QAX_QUASI_ELLIPSOID) {
+      if (b.a <= 0 || b.kappa != 0.0)
+        return fail(p, QAX_ERR_ARG, "qax_build: shapes 3-5 need a > 0 and kappa = 0");
+      continue;
+    }
     if (b.a <= 0 || b.c <= 0 || b.kappa < 0) return fail(p, QAX_ERR_ARG, "qax_build: bad shape parameters");
     const double zmax = b.shape == QAX_PEANUT ? b.a * (1 + b.c) : b.c;
     if (b.shape == QAX_PEANUT && b.c >= 1.0) return fail(p, QAX_ERR_ARG, "qax_build: peanut needs c < 1");
@@ -332,19 +341,22 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
   int64_t elems = 0;
   for (int i = 0; i < n_bodies; ++i) {
     const qax_body& b = bodies[i];
-    const int n = b.n_panels * GL_ORDER * b.n_theta;
+    const int n = (b.n_panels + 2 * b.n_ref) * GL_ORDER * b.n_theta;
     p->off[i + 1] = p->off[i] + n;
     if (i == 0 || bodies[i - 1].problem != b.problem) p->prob_body0[b.problem] = i;
     BodyDev& d = p->hbodies[i];
-    d.shape = b.shape; d.n_panels = b.n_panels; d.n_theta = b.n_theta; d.problem = b.problem;
+    d.shape = b.shape; d.n_panels = b.n_panels + 2 * b.n_ref; d.n_theta = b.n_theta;
+    d.problem = b.problem;
+    d.n_uni = b.n_panels; d.n_ref = b.n_ref;
     d.off = p->off[i]; d.n = n;
     d.a = b.a; d.c = b.c; d.kappa = b.kappa;
     rotation(b.theta1, b.theta2, d.R);
     for (int a = 0; a < 3; ++a) d.cen[a] = b.centre[a];
     d.k = k_per_problem[b.problem];
     d.eta = p->eta_of(d.k);
-    std::vector<double> key = {(double)b.shape, b.a, b.c, b.kappa, (double)b.n_panels,
-                               (double)b.n_theta, d.k, d.eta};
+    std::vector<double> key = {(double)b.shape, b.a, b.shape >= QAX_QUASI_ELLIPSOID ? 0.0 : b.c,
+                               b.kappa, (double)b.n_panels, (double)b.n_ref, (double)b.n_theta,
+                               d.k, d.eta};
     auto it = key2blk.find(key);
     if (it == key2blk.end()) {
       BlockDev bk;

@@ -64,8 +64,9 @@ __global__ void build_nodes_kernel(const BodyDev* __restrict__ bodies, int nb, i
   const int panel = li / (GL_ORDER * nth);
   const int l = (li / nth) % GL_ORDER;
   const int j = li % nth;
-  const double h = PI / B.n_panels;
-  const double t = -0.5 * PI + h * panel + 0.5 * h * (gl[l] + 1.0);
+  const double e0 = panel_edge(B.n_uni, B.n_ref, panel);
+  const double h = panel_edge(B.n_uni, B.n_ref, panel + 1) - e0;
+  const double t = e0 + 0.5 * h * (gl[l] + 1.0);
   const double omega = 0.5 * h * gl[GL_ORDER + l];
   const int Nh = nth / 2;
   const double th = j * PI / Nh;

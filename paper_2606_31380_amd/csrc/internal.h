@@ -18,7 +18,8 @@ constexpr double FOUR_PI = 12.5663706143591729539;
 
 // Per-body record on the device.
 struct BodyDev {
-  int32_t shape, n_panels, n_theta, problem;
+  int32_t shape, n_panels, n_theta, problem;   // n_panels: after refinement
+  int32_t n_uni, n_ref;                        // uniform panels, refinements per pole
   int64_t off;        // first node
   int32_t n;          // nodes
   int32_t block;      // distinct self-block index

@@ -191,7 +191,8 @@ qax_status lattice_enable(qax_problem* p, int32_t* dims_out) {
   const qax_body& b0 = p->bodies[0];
   double scale = 1.0;
   for (const auto& b : p->bodies) {
-    if (b.shape != b0.shape || b.n_panels != b0.n_panels || b.n_theta != b0.n_theta ||
+    if (b.shape != b0.shape || b.n_panels != b0.n_panels || b.n_ref != b0.n_ref ||
+        b.n_theta != b0.n_theta ||
         b.a != b0.a || b.c != b0.c || b.kappa != b0.kappa || b.theta1 != b0.theta1 ||
         b.theta2 != b0.theta2)
       return fail(p, QAX_ERR_ARG, "qax_lattice: bodies differ in shape, discretisation or orientation");

@@ -53,6 +53,7 @@ constexpr int QB = 32;                        // nodes per recurrence batch
 constexpr int LD = 256;                       // direct-route azimuthal samples (FFT length)
 constexpr int NGO = 64;                       // outer Gauss-Legendre order
 constexpr double CHI_SPLIT = 0.02;
+constexpr double NEAR_EXP = 40.0;   // smooth rule where 2N acosh(chi) >= 40 on the whole panel
 constexpr double INV_4PI = 0.0795774715459476678844;
 
 struct NodeLoc {
@@ -302,6 +303,11 @@ __device__ void fft256(double2* x, const double2* tw) {
   r4_pass<256>(x, lane, 64, true, tw);
 }
 
+__device__ __forceinline__ double wave_min(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off));
+  return v;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
   return v;
@@ -515,8 +521,9 @@ __device__ NodeLoc node_local(int shape, double a, double c, double kappa, const
   sincos_cw(0.5 * dl, &sh, &chh);
   sincos_cw(T.t + 0.5 * dl, &ssig, &csig);
   sincos_cw(T.t + dl, &ss, &cs);
-  const Curve cv = curve_from_sincos(shape, a, c, kappa, ss, cs);
-  const CurveDiff d = curve_diff_sc(shape, a, c, kappa, T.st, T.ct, ss, cs, sh, chh, ssig, csig);
+  const Curve cv = curve_from_sincos(shape, a, c, kappa, T.t + dl, ss, cs);
+  const CurveDiff d = curve_diff_sc(shape, a, c, kappa, T.t, dl, T.st, T.ct, ss, cs, sh, chh, ssig,
+                                    csig);
   const double ax = T.r * T.cth + d.d_p;
   const double by = T.r * T.sth + d.d_q;
   L.rt = sqrt(ax * ax + by * by);
@@ -625,12 +632,16 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   const int shape = B.shape;
   const double a = B.a, cc = B.c, kappa = B.kappa, k = B.k;
   const double eta = CF ? B.eta : 0.0;
-  const int nth = B.n_theta, N = nth / 2, npan = B.n_panels;
+  const int nth = B.n_theta, N = nth / 2;
   const int n = K.n;
   const int T = task.row, ip = task.panel;
   const int pT = T / (GL_ORDER * nth), lT = (T / nth) % GL_ORDER, jT = T % nth;
-  const double h = PI / npan;
-  const double tT = -0.5 * PI + h * pT + 0.5 * h * (gl16[lT] + 1.0);
+  const double eT0 = panel_edge(B.n_uni, B.n_ref, pT);
+  const double hT = panel_edge(B.n_uni, B.n_ref, pT + 1) - eT0;
+  const double tT = eT0 + 0.5 * hT * (gl16[lT] + 1.0);
+  // source panel ip: [e0, e1], length h
+  const double e0 = panel_edge(B.n_uni, B.n_ref, ip), e1 = panel_edge(B.n_uni, B.n_ref, ip + 1);
+  const double h = e1 - e0;
   const double thT = jT * PI / N;
   double2* row = pool + K.elem_off + (int64_t)T * n;
 
@@ -638,16 +649,30 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   TargetGeom TG;
   TG.t = tT;
   sincos_cw(tT, &TG.st, &TG.ct);
-  const Curve cT = curve_from_sincos(shape, a, cc, kappa, TG.st, TG.ct);
+  const Curve cT = curve_from_sincos(shape, a, cc, kappa, tT, TG.st, TG.ct);
   TG.r = cT.r;
   sincos_cw(thT, &TG.sth, &TG.cth);
   const double xT = cT.r * TG.cth + cT.p, yT = cT.r * TG.sth + cT.q, zT = cT.z;
 
-  if (abs(ip - pT) > 1) {
+  // near panel: adjacent, or one whose rings are close enough for the smooth
+  // rule's trapezoid in theta to alias (modes decay like e^{-|m| acosh chi};
+  // 2N points resolve them to e^{-2N acosh chi}); happens near the poles of
+  // dyadically refined curves, where the rings shrink with the panels
+  bool near = abs(ip - pT) <= 1;
+  if (!near) {
+    double v = 1e300;
+    if (lane < GL_ORDER) {
+      const double s = e0 + 0.5 * h * (gl16[lane] + 1.0);
+      const NodeLoc L = node_local(shape, a, cc, kappa, TG, s - tT);
+      v = nth * log1p(L.chim1 + sqrt(L.chim1 * (L.chim1 + 2.0)));
+    }
+    near = wave_min(v) < NEAR_EXP;
+  }
+  if (!near) {
     // far panel: smooth rule (Section 3.1, equation sx)
     for (int e = lane; e < GL_ORDER * nth; e += 64) {
       const int l = e / nth, j = e % nth;
-      const double t = -0.5 * PI + h * ip + 0.5 * h * (gl16[l] + 1.0);
+      const double t = e0 + 0.5 * h * (gl16[l] + 1.0);
       const double om = 0.5 * h * gl16[GL_ORDER + l];
       const Curve cv = curve_eval(shape, a, cc, kappa, t);
       double sj, cj;
@@ -700,7 +725,6 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
 #pragma unroll
     for (int l = 0; l < GL_ORDER; ++l) acs[l] = make_double2(0.0, 0.0);
   }
-  const double e0 = -0.5 * PI + h * ip, e1 = e0 + h;
   const int nsides = (ip == pT) ? 2 : 1;
   for (int side = 0; side < nsides; ++side) {
     // outer node `lane`: offset dl from tT and weight (u^5 substitution)

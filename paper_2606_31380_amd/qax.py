@@ -26,7 +26,7 @@ class qax_body(C.Structure):
     _fields_ = [("shape", C.c_int32), ("n_panels", C.c_int32), ("n_theta", C.c_int32),
                 ("problem", C.c_int32), ("a", C.c_double), ("c", C.c_double),
                 ("kappa", C.c_double), ("theta1", C.c_double), ("theta2", C.c_double),
-                ("centre", C.c_double * 3)]
+                ("centre", C.c_double * 3), ("n_ref", C.c_int32)]
 
 
 class qax_info(C.Structure):
@@ -132,6 +132,7 @@ def bodies_to_c(bodies) -> "C.Array":
         arr[i].a, arr[i].c, arr[i].kappa = float(b["a"]), float(b["c"]), float(b["kappa"])
         arr[i].theta1, arr[i].theta2 = float(b["theta1"]), float(b["theta2"])
         arr[i].centre[0], arr[i].centre[1], arr[i].centre[2] = float(b["cx"]), float(b["cy"]), float(b["cz"])
+        arr[i].n_ref = int(b["n_ref"]) if "n_ref" in b.dtype.names else 0
     return arr
 
 

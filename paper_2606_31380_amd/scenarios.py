@@ -11,12 +11,17 @@ Every generator uses numpy's PCG64 with an explicit seed.
 
 Body descriptor fields (one row of ``BODY_DTYPE``):
 
-``shape``      0 = sphere, 1 = spheroid, 2 = peanut
+``shape``      0 = sphere, 1 = spheroid, 2 = peanut, 3 = quasi-ellipsoid,
+               4 = spiral, 5 = conch (the last three: Section 6.1, Example 2)
 ``a``, ``c``   sphere: radius ``a`` (``c`` = ``a``); spheroid: radial semi-axis
                ``a`` and axial semi-axis ``c``; peanut: polar radius
-               ``a (1 + c cos 2 psi)`` with ``psi`` the polar angle
-``kappa``      curvature of the circular-arc centreline (0 = straight axis)
-``n_panels``   Gauss-Legendre panels along the generating curve (16 nodes each)
+               ``a (1 + c cos 2 psi)`` with ``psi`` the polar angle;
+               shapes 3-5: scale ``a`` (``c`` unused)
+``kappa``      curvature of the circular-arc centreline (0 = straight axis;
+               shapes 3-5: 0)
+``n_panels``   uniform Gauss-Legendre panels along the generating curve (16
+               nodes each)
+``n_ref``      dyadic refinements of the panel at each pole (adds 2 n_ref panels)
 ``n_theta``    azimuthal trapezoidal nodes (even, 2N)
 ``theta1``, ``theta2``  rotation angles of R = Rz(theta1) Ry(theta2)
 ``cx, cy, cz`` body centre
@@ -35,6 +40,7 @@ from typing import List
 import numpy as np
 
 SPHERE, SPHEROID, PEANUT = 0, 1, 2
+QUASI_ELLIPSOID, SPIRAL, CONCH = 3, 4, 5
 GL_ORDER = 16
 
 BODY_DTYPE = np.dtype([
@@ -42,7 +48,7 @@ BODY_DTYPE = np.dtype([
     ("kappa", np.float64), ("n_panels", np.int32), ("n_theta", np.int32),
     ("theta1", np.float64), ("theta2", np.float64),
     ("cx", np.float64), ("cy", np.float64), ("cz", np.float64),
-    ("problem", np.int32),
+    ("problem", np.int32), ("n_ref", np.int32),
 ])
 
 
@@ -61,8 +67,8 @@ class Scenario:
         return int(self.k.shape[0])
 
     def nodes_per_body(self) -> np.ndarray:
-        return (self.bodies["n_panels"].astype(np.int64) * GL_ORDER
-                * self.bodies["n_theta"].astype(np.int64))
+        panels = self.bodies["n_panels"].astype(np.int64) + 2 * self.bodies["n_ref"].astype(np.int64)
+        return panels * GL_ORDER * self.bodies["n_theta"].astype(np.int64)
 
     def n_unknowns(self) -> int:
         return int(self.nodes_per_body().sum())
