@@ -77,7 +77,7 @@ def reuse_ratio(P, Q, R):
     return 1.0 - len(distinct_displacements(P, Q, R)) / (n * (n - 1))
 
 
-def displacement_block(disc, k, d_vec, ref=0, eta=None):
+def displacement_block(disc, k, d_vec, ref=0, eta=None, single=False):
     """D_d[i, j]: the pair-sum kernel from source node j of body `ref` to
     target node i of the same body translated by d_vec (smooth rule, the
     weights in aw)."""
@@ -85,6 +85,8 @@ def displacement_block(disc, k, d_vec, ref=0, eta=None):
     y = disc.pos[o0:o1]
     aw = disc.aw[o0:o1]
     x = y + np.asarray(d_vec, dtype=np.float64)[None, :]
+    if single:
+        return modal.sl_kernel(k, x[:, None, :], y[None, :, :]) * np.linalg.norm(aw, axis=1)[None, :]
     D = modal.dl_kernel_area(k, x[:, None, :], y[None, :, :], aw[None, :, :])
     if eta is not None:
         D = D - 1j * eta * modal.sl_kernel(k, x[:, None, :], y[None, :, :]) \
@@ -92,13 +94,13 @@ def displacement_block(disc, k, d_vec, ref=0, eta=None):
     return D
 
 
-def block_table(disc, k, dims, spacing, eta=None):
+def block_table(disc, k, dims, spacing, eta=None, single=False):
     """{d: D_d} for every distinct displacement of the array."""
-    return {d: displacement_block(disc, k, np.array(d) * spacing, eta=eta)
+    return {d: displacement_block(disc, k, np.array(d) * spacing, eta=eta, single=single)
             for d in distinct_displacements(*dims)}
 
 
-def lattice_apply(disc, k, mu, eta=None):
+def lattice_apply(disc, k, mu, eta=None, single=False):
     """w_t' = sum_{t != t'} D_{c_t' - c_t} mu_t with the blocks from the table.
     mu (N,) or (N, nrhs)."""
     mu = np.asarray(mu, dtype=np.complex128)
@@ -106,7 +108,7 @@ def lattice_apply(disc, k, mu, eta=None):
     if squeeze:
         mu = mu[:, None]
     sites, dims, spacing = lattice_sites(disc.centres)
-    table = block_table(disc, k, dims, spacing, eta=eta)
+    table = block_table(disc, k, dims, spacing, eta=eta, single=single)
     off = disc.offsets
     out = np.zeros_like(mu)
     nb = len(off) - 1

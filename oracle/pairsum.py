@@ -15,8 +15,10 @@ import numpy as np
 FOUR_PI = 4.0 * math.pi
 
 
-def pair_sum(disc, k_per_problem, mu, targets=None, chunk=256, eta=None):
+def pair_sum(disc, k_per_problem, mu, targets=None, chunk=256, eta=None, single=False):
     """mu: (N,) or (N, nrhs) complex.  Returns w at the requested targets.
+    single: the single-layer kernel G(x, y_j) |J_j| w_j alone (the first-kind
+    equation of Section 2).
     With eta, the combined-field kernel: double layer - i eta single layer,
     the single layer as G(x, y_j) |J_j| w_j (|J| w = |aw|)."""
     mu = np.asarray(mu, dtype=np.complex128)
@@ -37,9 +39,13 @@ def pair_sum(disc, k_per_problem, mu, targets=None, chunk=256, eta=None):
             rho = np.sqrt(np.sum(d * d, axis=-1))
             same = disc.body[tsel][:, None] == disc.body[src][None, :]
             rho_safe = np.where(same, 1.0, rho)
-            kern = (1j * k / rho_safe - 1.0 / rho_safe ** 2) * np.exp(1j * k * rho_safe) \
-                / (FOUR_PI * rho_safe) * np.sum(disc.aw[src][None, :, :] * d, axis=-1)
-            if eta is not None:
+            if single:
+                kern = np.exp(1j * k * rho_safe) / (FOUR_PI * rho_safe) \
+                    * np.linalg.norm(disc.aw[src], axis=1)[None, :]
+            else:
+                kern = (1j * k / rho_safe - 1.0 / rho_safe ** 2) * np.exp(1j * k * rho_safe) \
+                    / (FOUR_PI * rho_safe) * np.sum(disc.aw[src][None, :, :] * d, axis=-1)
+            if eta is not None and not single:
                 w = np.linalg.norm(disc.aw[src], axis=1)[None, :]
                 kern = kern - 1j * eta * np.exp(1j * k * rho_safe) / (FOUR_PI * rho_safe) * w
             kern = np.where(same, 0.0, kern)

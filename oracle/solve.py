@@ -11,6 +11,9 @@
   paragraph on the hybrid solver);
 * the combined-field variant 1/2 I + D - i eta S (eta given): single-layer
   self blocks with the density times |J| interpolated, G |J| w between bodies;
+* the first-kind single-layer equation S mu = -u_inc (Section 2, equation
+  single-layer-bie; `single`), the same single-layer pieces alone, far field
+  (1/4 pi) sum_j e^{-i k xhat.y_j} mu_j |J_j| w_j (Section 6);
 * far field of the double-layer density:
   u_inf(xhat) = (1/4 pi) sum_j (-i k xhat.n_j) e^{-i k xhat.y_j} mu_j |J_j| w_j
   (Section 6 defines the single-layer form; the double-layer form follows from
@@ -34,14 +37,16 @@ def rhs_planewave(disc, k_per_problem, dirs):
     return -np.exp(1j * k[:, None] * (disc.pos @ np.asarray(dirs).T))
 
 
-def self_blocks(disc, k_per_problem, body_ids=None, eta=None):
-    """Self blocks 1/2 I + D (eta None) or 1/2 I + D - i eta S."""
+def self_blocks(disc, k_per_problem, body_ids=None, eta=None, single=False):
+    """Self blocks 1/2 I + D (eta None), 1/2 I + D - i eta S, or S (single)."""
     body_ids = range(len(disc.bodies)) if body_ids is None else body_ids
     out = {}
     for b in body_ids:
         p = disc.problem[disc.offsets[b]]
         kp = float(k_per_problem[p])
-        if eta is None:
+        if single:
+            out[b] = selfblock.self_block(disc.bodies[b], kp, kind="sl")
+        elif eta is None:
             out[b] = selfblock.self_block(disc.bodies[b], kp)
         else:
             out[b] = selfblock.self_block_cf(disc.bodies[b], kp, eta)
@@ -62,9 +67,9 @@ def dense_matrix(disc, k_per_problem, blocks):
     return A
 
 
-def dense_matrix_fast(disc, k_per_problem, blocks, eta=None):
+def dense_matrix_fast(disc, k_per_problem, blocks, eta=None, single=False):
     """Same matrix, off-diagonal entries written directly from the kernel
-    (combined field with eta)."""
+    (combined field with eta, single layer alone with single)."""
     n = disc.pos.shape[0]
     k = np.asarray(k_per_problem)[disc.problem]
     d = disc.pos[None, :, :] - disc.pos[:, None, :]
@@ -72,9 +77,12 @@ def dense_matrix_fast(disc, k_per_problem, blocks, eta=None):
     same = (disc.body[:, None] == disc.body[None, :]) | (disc.problem[:, None] != disc.problem[None, :])
     rs = np.where(same, 1.0, rho)
     kk = k[:, None]
-    A = (1j * kk / rs - 1.0 / rs ** 2) * np.exp(1j * kk * rs) / (FOUR_PI * rs) \
-        * np.sum(disc.aw[None, :, :] * d, axis=-1)
-    if eta is not None:
+    if single:
+        A = np.exp(1j * kk * rs) / (FOUR_PI * rs) * np.linalg.norm(disc.aw, axis=1)[None, :]
+    else:
+        A = (1j * kk / rs - 1.0 / rs ** 2) * np.exp(1j * kk * rs) / (FOUR_PI * rs) \
+            * np.sum(disc.aw[None, :, :] * d, axis=-1)
+    if eta is not None and not single:
         A = A - 1j * eta * np.exp(1j * kk * rs) / (FOUR_PI * rs) * np.linalg.norm(disc.aw, axis=1)[None, :]
     A = np.where(same, 0.0, A)
     for b, B in blocks.items():
@@ -83,9 +91,9 @@ def dense_matrix_fast(disc, k_per_problem, blocks, eta=None):
     return A
 
 
-def apply_operator(disc, k_per_problem, blocks, mu, eta=None):
-    """(1/2 I + D) mu (or the combined field), matrix-free between bodies."""
-    out = pairsum.pair_sum(disc, k_per_problem, mu, eta=eta)
+def apply_operator(disc, k_per_problem, blocks, mu, eta=None, single=False):
+    """(1/2 I + D) mu (or the combined field, or S), matrix-free between bodies."""
+    out = pairsum.pair_sum(disc, k_per_problem, mu, eta=eta, single=single)
     for b, B in blocks.items():
         s = slice(disc.offsets[b], disc.offsets[b + 1])
         out[s] += B @ mu[s]
@@ -149,11 +157,11 @@ def gmres(apply_a, apply_minv, b, tol=1e-10, restart=100, maxit=1000):
 
 
 def solve(disc, k_per_problem, blocks, b, method="gmres", tol=1e-10, restart=100, maxit=1000,
-          eta=None):
-    """Solve (1/2 I + D) mu = b (combined field with eta; blocks to match);
-    b is (N,) complex."""
+          eta=None, single=False):
+    """Solve (1/2 I + D) mu = b (combined field with eta, S mu = b with
+    single; blocks to match); b is (N,) complex."""
     if method == "dense":
-        A = dense_matrix_fast(disc, k_per_problem, blocks, eta=eta)
+        A = dense_matrix_fast(disc, k_per_problem, blocks, eta=eta, single=single)
         return np.linalg.solve(A, b), 0, []
     inv = {bb: np.linalg.inv(B) for bb, B in blocks.items()}
 
@@ -164,15 +172,18 @@ def solve(disc, k_per_problem, blocks, b, method="gmres", tol=1e-10, restart=100
             out[s] = Bi @ v[s]
         return out
 
-    return gmres(lambda v: apply_operator(disc, k_per_problem, blocks, v, eta=eta), minv, b,
+    return gmres(lambda v: apply_operator(disc, k_per_problem, blocks, v, eta=eta, single=single), minv, b,
                  tol=tol, restart=restart, maxit=maxit)
 
 
-def far_field(disc, k_per_problem, mu, xhat, eta=None):
+def far_field(disc, k_per_problem, mu, xhat, eta=None, single=False):
     """u_inf at unit directions xhat (ndir, 3); mu (N,) -> (ndir,).  With eta
-    the combined field adds - i eta (1/4 pi) sum_j e^{-i k xhat.y_j} mu_j |J_j| w_j."""
+    the combined field adds - i eta (1/4 pi) sum_j e^{-i k xhat.y_j} mu_j |J_j| w_j;
+    single: that single-layer term alone with coefficient 1."""
     k = float(np.asarray(k_per_problem)[0])
     ph = np.exp(-1j * k * (xhat @ disc.pos.T))            # (ndir, N)
+    if single:
+        return (ph * np.linalg.norm(disc.aw, axis=1)[None, :]) @ mu / FOUR_PI
     nd = xhat @ disc.aw.T                                  # xhat . n |J| w
     f = (-1j * k) * nd
     if eta is not None:
@@ -180,7 +191,7 @@ def far_field(disc, k_per_problem, mu, xhat, eta=None):
     return (ph * f) @ mu / FOUR_PI
 
 
-def near_field(disc, k_per_problem, mu, points, problem=0, chunk=64, eta=None):
+def near_field(disc, k_per_problem, mu, points, problem=0, chunk=64, eta=None, single=False):
     """Double-layer potential u(x) = sum_j dG/dn_y(x, y_j) mu_j |J_j| w_j of the
     bodies of `problem` at points (M, 3) away from every surface: the smooth
     product rule of Section 3.1 (equation sx) applied to the representation
@@ -197,9 +208,12 @@ def near_field(disc, k_per_problem, mu, points, problem=0, chunk=64, eta=None):
         x = pts[c0:c0 + chunk]
         d = disc.pos[src][None, :, :] - x[:, None, :]                 # y - x
         rho = np.sqrt(np.sum(d * d, axis=-1))
-        kern = (1j * k / rho - 1.0 / rho ** 2) * np.exp(1j * k * rho) / (FOUR_PI * rho) \
-            * np.sum(disc.aw[src][None, :, :] * d, axis=-1)
-        if eta is not None:
+        if single:
+            kern = np.exp(1j * k * rho) / (FOUR_PI * rho) * np.linalg.norm(disc.aw[src], axis=1)[None, :]
+        else:
+            kern = (1j * k / rho - 1.0 / rho ** 2) * np.exp(1j * k * rho) / (FOUR_PI * rho) \
+                * np.sum(disc.aw[src][None, :, :] * d, axis=-1)
+        if eta is not None and not single:
             kern = kern - 1j * eta * np.exp(1j * k * rho) / (FOUR_PI * rho) \
                 * np.linalg.norm(disc.aw[src], axis=1)[None, :]
         out[c0:c0 + chunk] = kern @ mu[src]

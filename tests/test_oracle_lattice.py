@@ -44,13 +44,13 @@ def test_lattice_sites_recovers_shuffled_array():
         lattice.lattice_sites(np.array([[0.0, 0, 0], [1.0, 0, 0], [0.0, 1.0, 0]]))
 
 
-@pytest.mark.parametrize("eta", [None, 1.4])
-def test_block_table_apply_equals_pair_sum(eta):
+@pytest.mark.parametrize("eta,single", [(None, False), (1.4, False), (None, True)])
+def test_block_table_apply_equals_pair_sum(eta, single):
     s = sc.identical_array((2, 2, 3), (3.0, 2.5, 3.5), seed=1)
     d = geo.discretize(s)
     n = d.pos.shape[0]
     rng = np.random.default_rng(2)
     mu = rng.standard_normal((n, 2)) + 1j * rng.standard_normal((n, 2))
-    got = lattice.lattice_apply(d, 2.0, mu, eta=eta)
-    want = pairsum.pair_sum(d, s.k, mu, eta=eta)
+    got = lattice.lattice_apply(d, 2.0, mu, eta=eta, single=single)
+    want = pairsum.pair_sum(d, s.k, mu, eta=eta, single=single)
     assert np.abs(got - want).max() < 1e-13 * np.abs(want).max()

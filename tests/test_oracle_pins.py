@@ -383,6 +383,51 @@ def test_combined_field_artificial_solution():
     assert np.abs(ff - solve.point_source_far_field(2.0, z, xhat)).max() < 1e-8
 
 
+def test_single_layer_first_kind_mie():
+    # S mu = -u_inc on a sphere (k a = 1, away from interior Dirichlet
+    # eigenvalues) reproduces the Mie far field of the sound-soft sphere
+    a, k = 0.5, 2.0
+    s = sc.single_sphere(a, 2, 16, k)
+    d = geo.discretize(s)
+    b = solve.rhs_planewave(d, s.k, s.dirs)[:, 0]
+    S = _axisym_block(d.bodies[0], k, kind="sl")
+    mu, _, _ = solve.solve(d, s.k, {0: S}, b, method="dense", single=True)
+    g = np.array([0.0, 0.7, math.pi / 2, 2.5, math.pi])
+    xh = np.stack([np.sin(g), 0 * g, np.cos(g)], axis=1)
+    assert np.abs(solve.far_field(d, s.k, mu, xh, single=True) - _mie_far(k, a, g)).max() < 1e-10
+
+
+def test_single_layer_artificial_solution_and_brute_force():
+    s = sc.tiny(n_bodies=2, n_panels=2, n_theta=16, k=2.0, spacing=2.5)
+    s.bodies["kappa"] = 0.0
+    d = geo.discretize(s)
+    z = d.centres + np.array([0.05, -0.03, 0.1])
+    b = solve.point_source_field(2.0, z, d.pos)
+    S = _axisym_block(d.bodies[0], 2.0, kind="sl")
+    mu = np.linalg.solve(solve.dense_matrix_fast(d, s.k, {0: S, 1: S}, single=True), b)
+    rng = np.random.default_rng(6)
+    u = rng.standard_normal((30, 3))
+    xhat = u / np.linalg.norm(u, axis=1)[:, None]
+    pts = xhat * 6.0 + d.centres.mean(axis=0)
+    exact = solve.point_source_field(2.0, z, pts)
+    assert np.abs(solve.near_field(d, s.k, mu, pts, single=True) - exact).max() < 1e-8 * np.abs(exact).max()
+    ff = solve.far_field(d, s.k, mu, xhat, single=True)
+    assert np.abs(ff - solve.point_source_far_field(2.0, z, xhat)).max() < 1e-8
+    # the single-layer pair sum against a plain double loop
+    t = sc.tiny(n_bodies=3, n_panels=1, n_theta=8, k=3.0)
+    dt = geo.discretize(t)
+    m = np.cos(np.arange(dt.pos.shape[0]) * 0.7) - 0.2j
+    out = pairsum.pair_sum(dt, t.k, m, single=True)
+    ref = np.zeros_like(out)
+    for i in range(dt.pos.shape[0]):
+        for j in range(dt.pos.shape[0]):
+            if dt.body[i] != dt.body[j]:
+                r = math.sqrt(float((dt.pos[j] - dt.pos[i]) @ (dt.pos[j] - dt.pos[i])))
+                ref[i] += complex(math.cos(3.0 * r), math.sin(3.0 * r)) / (4 * math.pi * r) \
+                    * math.sqrt(float(dt.aw[j] @ dt.aw[j])) * m[j]
+    assert np.abs(out - ref).max() < 1e-13 * np.abs(ref).max()
+
+
 def test_combined_pair_sum_brute_force():
     s = sc.tiny(n_bodies=3, n_panels=1, n_theta=8, k=3.0)
     d = geo.discretize(s)
