@@ -212,7 +212,10 @@ qax_status qax_modal_modes(qax_problem* p, int32_t n_pts, const double* d_r, con
 qax_status qax_set_graphs(qax_problem* p, int32_t enable);
 
 /* Boundary-integral formulation.  QAX_DOUBLE_LAYER (default): the paper's
- * multi-body system (1/2 I + D) mu = -u_inc (Section 4).  QAX_COMBINED_FIELD:
+ * multi-body system (1/2 I + D) mu = -u_inc (Section 4).  QAX_SINGLE_LAYER:
+ * the first-kind equation S mu = -u_inc (Section 2, equation
+ * single-layer-bie; eta ignored), the field represented by the single-layer
+ * potential.  QAX_COMBINED_FIELD:
  * (1/2 I + D - i eta S) mu = -u_inc with the single-layer operator S (Section
  * 2, the remark on combined fields; uniquely solvable at interior resonances,
  * where the double-layer system is singular); S is discretised with the
@@ -222,7 +225,11 @@ qax_status qax_set_graphs(qax_problem* p, int32_t enable);
  * pair sums, near and far field.  May be called at any time; on a built
  * handle it updates the per-node weights and drops the handle back to the
  * built state (qax_assemble_self is needed again).  Errors: QAX_ERR_ARG. */
-typedef enum { QAX_DOUBLE_LAYER = 0, QAX_COMBINED_FIELD = 1 } qax_formulation;
+typedef enum {
+  QAX_DOUBLE_LAYER = 0,
+  QAX_COMBINED_FIELD = 1,
+  QAX_SINGLE_LAYER = 2
+} qax_formulation;
 qax_status qax_set_formulation(qax_problem* p, int32_t formulation, double eta);
 
 /* Block-Toeplitz inter-body apply for a regular array of identical bodies

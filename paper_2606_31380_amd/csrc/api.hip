@@ -210,7 +210,8 @@ static qax_status sync(qax_problem* p, const char* what) {
 
 extern "C" qax_status qax_set_formulation(qax_problem* p, int32_t formulation, double eta) {
   if (!p) return QAX_ERR_ARG;
-  if ((formulation != QAX_DOUBLE_LAYER && formulation != QAX_COMBINED_FIELD) || !is_finite(eta))
+  if ((formulation != QAX_DOUBLE_LAYER && formulation != QAX_COMBINED_FIELD &&
+       formulation != QAX_SINGLE_LAYER) || !is_finite(eta))
     return fail(p, QAX_ERR_ARG, "qax_set_formulation: bad formulation or eta");
   p->formulation = formulation;
   p->eta_param = eta;

@@ -85,7 +85,13 @@ struct qax_problem {
   int state = 0;  // 0 created, 1 built, 2 assembled
   int formulation = QAX_DOUBLE_LAYER;
   double eta_param = 0.0;          // > 0 fixed coupling, <= 0 k of each problem
-  double eta_of(double k) const { return formulation == QAX_COMBINED_FIELD ? (eta_param > 0 ? eta_param : k) : 0.0; }
+  // per-node single-layer weight factor: eta (combined field), 1 (single layer), 0
+  double eta_of(double k) const {
+    if (formulation == QAX_SINGLE_LAYER) return 1.0;
+    return formulation == QAX_COMBINED_FIELD ? (eta_param > 0 ? eta_param : k) : 0.0;
+  }
+  // kernel variant: 0 double layer, 1 combined field, 2 single layer
+  int form() const { return formulation == QAX_COMBINED_FIELD ? 1 : formulation == QAX_SINGLE_LAYER ? 2 : 0; }
 
   int32_t n_bodies = 0, n_problems = 0;
   std::vector<qax_body> bodies;

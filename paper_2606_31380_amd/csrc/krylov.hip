@@ -43,7 +43,7 @@ hipError_t launch_rhs(qax_problem* p, const double* dirs_dev, int nrhs, double* 
 // u_inf[dir][r] = (1/4pi) sum_{n in problem 0} (-i k xhat.aw_n) e^{-i k xhat.y_n} mu[n][r]
 __global__ __launch_bounds__(256) void farfield_kernel(const double* __restrict__ pos,
                                                        const double* __restrict__ aw,
-                                                       const double* __restrict__ ew, int cf,
+                                                       const double* __restrict__ ew, int form,
                                                        int64_t N, int64_t n0, double k,
                                                        const double2* __restrict__ mu, int nrhs,
                                                        const double* __restrict__ xhat,
@@ -59,8 +59,12 @@ __global__ __launch_bounds__(256) void farfield_kernel(const double* __restrict_
     const double nd = hx * aw[n] + hy * aw[N + n] + hz * aw[2 * N + n];
     // (-i k nd) (c + i s) = k nd s - i k nd c; combined field adds
     // (-i eta |aw|)(c + i s) = eta |aw| s - i eta |aw| c
+    // single layer: |aw| (c + i s)
     double fr = k * nd * s, fi = -k * nd * c;
-    if (cf) {
+    if (form == 2) {
+      fr = ew[n] * c;
+      fi = ew[n] * s;
+    } else if (form == 1) {
       fr = fma(ew[n], s, fr);
       fi = fma(-ew[n], c, fi);
     }
@@ -87,7 +91,7 @@ hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const dou
                            int ndir, double* out) {
   const int64_t n0 = p->off[p->prob_body0[1]];
   hipLaunchKernelGGL(farfield_kernel, dim3(ndir, nrhs), dim3(256), 0, p->stream, p->d_pos, p->d_aw,
-                     p->d_ew, p->formulation == QAX_COMBINED_FIELD ? 1 : 0, p->N, n0, p->k[0],
+                     p->d_ew, p->form(), p->N, n0, p->k[0],
                      (const double2*)mu, nrhs, xhat_dev, (double2*)out);
   return hipGetLastError();
 }

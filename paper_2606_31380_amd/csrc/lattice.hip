@@ -41,12 +41,13 @@ constexpr int64_t LAT_FMAX = 65535;   // frequencies (one grid dimension)
 
 // D[a][i][j] = kernel from source node j of the reference body to target
 // node i of the body displaced by d(a) (the pair-sum kernel of Section 4 with
-// the smooth-rule weights in aw; minus i eta G |aw| for the combined field),
+// the smooth-rule weights in aw; minus i eta G |aw| for the combined field;
+// G |aw| alone for the single layer),
 // a = (a0, a1, a2) in the L0 x L1 x L2 grid, d = a or a - L per axis; zero
 // block for d = 0 (the self block is applied separately).
 __global__ __launch_bounds__(256) void lattice_blocks_kernel(
     const double* __restrict__ pos, const double* __restrict__ aw, const double* __restrict__ ew,
-    int cf, int64_t N, int64_t off, int nb, int L0, int L1, int L2, int P0, int P1, int P2,
+    int form, int64_t N, int64_t off, int nb, int L0, int L1, int L2, int P0, int P1, int P2,
     double h0, double h1, double h2, double k, double2* __restrict__ D) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t nn = (int64_t)nb * nb;
@@ -70,14 +71,21 @@ __global__ __launch_bounds__(256) void lattice_blocks_kernel(
     const double kr = k * r;
     double s, c;
     sincos_cw(kr, &s, &c);
-    const double dot = aw[sj] * dx + aw[N + sj] * dy + aw[2 * N + sj] * dz;
-    const double sc = dot * ir * ir * ir;
-    double re = -(c + kr * s) * sc;
-    double im = (kr * c - s) * sc;
-    if (cf) {
+    double re, im;
+    if (form == 2) {   // single layer: (|aw| / r) e^{ikr}
       const double t = ew[sj] * ir;
-      re = fma(t, s, re);
-      im = fma(-t, c, im);
+      re = c * t;
+      im = s * t;
+    } else {
+      const double dot = aw[sj] * dx + aw[N + sj] * dy + aw[2 * N + sj] * dz;
+      const double sc = dot * ir * ir * ir;
+      re = -(c + kr * s) * sc;
+      im = (kr * c - s) * sc;
+      if (form == 1) {
+        const double t = ew[sj] * ir;
+        re = fma(t, s, re);
+        im = fma(-t, c, im);
+      }
     }
     v = make_double2(re * INV_FOUR_PI_LAT, im * INV_FOUR_PI_LAT);
   }
@@ -244,7 +252,7 @@ qax_status lattice_enable(qax_problem* p, int32_t* dims_out) {
   const int64_t off0 = site_node[0];
   const BodyDev& B0 = p->hbodies[0];
   hipLaunchKernelGGL(lattice_blocks_kernel, dim3((unsigned)((nn + 255) / 256), (unsigned)F), dim3(256),
-                     0, s, p->d_pos, p->d_aw, p->d_ew, p->formulation == QAX_COMBINED_FIELD ? 1 : 0,
+                     0, s, p->d_pos, p->d_aw, p->d_ew, p->form(),
                      p->N, off0, nb, L[0], L[1], L[2], n[0], n[1], n[2], h[0], h[1], h[2], B0.k, tmp);
   hipError_t e = hipGetLastError();
   // T = DFT over the three displacement axes (tmp -> T64 -> tmp -> T64)

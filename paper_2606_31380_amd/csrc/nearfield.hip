@@ -26,7 +26,7 @@ __global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slo
 template <int TPB>
 __global__ __launch_bounds__(TPB) void nearfield_kernel(
     const double* __restrict__ pts, int64_t M, const double* __restrict__ pos,
-    const double* __restrict__ aw, const double* __restrict__ ew, int cf, int64_t N, int64_t s0,
+    const double* __restrict__ aw, const double* __restrict__ ew, int form, int64_t N, int64_t s0,
     int64_t s1, int slots, double k,
     const double2* __restrict__ mu, int nrhs, double2* __restrict__ partial) {
   const int tid = threadIdx.x;
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(TPB) void nearfield_kernel(
       const int64_t j = base + tid;
       sx[tid] = pos[j]; sy[tid] = pos[N + j]; sz[tid] = pos[2 * N + j];
       sax[tid] = aw[j]; say[tid] = aw[N + j]; saz[tid] = aw[2 * N + j];
-      sew[tid] = cf ? ew[j] : 0.0;
+      sew[tid] = form ? ew[j] : 0.0;
       smu[tid] = mu[j * nrhs + r];
     }
     __syncthreads();
@@ -59,11 +59,18 @@ __global__ __launch_bounds__(TPB) void nearfield_kernel(
       const double kr = k * rr;
       double sn, cs;
       sincos_cw(kr, &sn, &cs);
-      const double sc = (sax[jj] * dx + say[jj] * dy + saz[jj] * dz) * ir * ir * ir;
-      double re = -(cs + kr * sn) * sc, im = (kr * cs - sn) * sc;
-      const double t = sew[jj] * ir;      // combined field: (eta |aw| / r)(sin kr - i cos kr)
-      re = fma(t, sn, re);
-      im = fma(-t, cs, im);
+      const double t = sew[jj] * ir;
+      double re, im;
+      if (form == 2) {                    // single layer: (|aw| / r)(cos kr + i sin kr)
+        re = cs * t;
+        im = sn * t;
+      } else {
+        const double sc = (sax[jj] * dx + say[jj] * dy + saz[jj] * dz) * ir * ir * ir;
+        re = -(cs + kr * sn) * sc;
+        im = (kr * cs - sn) * sc;
+        re = fma(t, sn, re);              // combined field: (eta |aw| / r)(sin kr - i cos kr)
+        im = fma(-t, cs, im);
+      }
       const double2 m = smu[jj];
       ar += re * m.x - im * m.y;
       ai += re * m.y + im * m.x;
@@ -84,7 +91,7 @@ hipError_t launch_nearfield(qax_problem* p, const double* mu, int nrhs, const do
   const int64_t s0 = p->off[p->prob_body0[problem]], s1 = p->off[p->prob_body0[problem + 1]];
   dim3 grid((unsigned)((M + 255) / 256), (unsigned)slots, (unsigned)nrhs);
   hipLaunchKernelGGL((nearfield_kernel<256>), grid, dim3(256), 0, p->stream, pts, M, p->d_pos,
-                     p->d_aw, p->d_ew, p->formulation == QAX_COMBINED_FIELD ? 1 : 0, p->N, s0, s1,
+                     p->d_aw, p->d_ew, p->form(), p->N, s0, s1,
                      slots, p->k[problem], (const double2*)mu, nrhs, (double2*)partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -54,7 +54,7 @@ __device__ __forceinline__ bool skip_task(const PairTask& T, const BodyDev* __re
   return true;
 }
 
-template <int TPB, int NRC, bool CF>
+template <int TPB, int NRC, int FORM>
 __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
     const PairTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
     const int32_t* __restrict__ node_body, const double* __restrict__ pos,
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
   const double k = T.k;
 
   __shared__ double sx[TPB], sy[TPB], sz[TPB], sax[TPB], say[TPB], saz[TPB];
-  __shared__ double sew[CF ? TPB : 1];
+  __shared__ double sew[FORM ? TPB : 1];
   __shared__ double2 smu[TPB * NRC];
 
   double accr[NRC], acci[NRC];
@@ -91,7 +91,7 @@ __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
         const int64_t j = s0 + base + tid;
         sx[tid] = pos[j]; sy[tid] = pos[N + j]; sz[tid] = pos[2 * N + j];
         sax[tid] = aw[j]; say[tid] = aw[N + j]; saz[tid] = aw[2 * N + j];
-        if (CF) sew[tid] = ew[j];
+        if (FORM) sew[tid] = ew[j];
 #pragma unroll
         for (int r = 0; r < NRC; ++r)
           smu[tid * NRC + r] = (rc0 + r < nrhs) ? mu[j * nrhs + rc0 + r] : make_double2(0.0, 0.0);
@@ -106,14 +106,21 @@ __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
           const double kr = k * r;
           double s, c;
           sincos_cw(kr, &s, &c);
-          const double dot = sax[jj] * dx + say[jj] * dy + saz[jj] * dz;
-          const double sc = dot * ir * ir * ir;
-          double re = -(c + kr * s) * sc;
-          double im = (kr * c - s) * sc;
-          if (CF) {   // - i eta G |aw|: (eta |aw| / r)(sin kr - i cos kr)
+          double re, im;
+          if constexpr (FORM == 2) {   // G |aw|: (|aw| / r)(cos kr + i sin kr)
             const double t = sew[jj] * ir;
-            re = fma(t, s, re);
-            im = fma(-t, c, im);
+            re = c * t;
+            im = s * t;
+          } else {
+            const double dot = sax[jj] * dx + say[jj] * dy + saz[jj] * dz;
+            const double sc = dot * ir * ir * ir;
+            re = -(c + kr * s) * sc;
+            im = (kr * c - s) * sc;
+            if constexpr (FORM == 1) {   // - i eta G |aw|: (eta |aw| / r)(sin kr - i cos kr)
+              const double t = sew[jj] * ir;
+              re = fma(t, s, re);
+              im = fma(-t, c, im);
+            }
           }
 #pragma unroll
           for (int r_ = 0; r_ < NRC; ++r_) {
@@ -142,7 +149,7 @@ __device__ __forceinline__ void two_sum(float& s, float& c, float a) {
   c += e;
 }
 
-template <int TPB, int NRC, bool CF>
+template <int TPB, int NRC, int FORM>
 __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
     const PairTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
     const int32_t* __restrict__ node_body, const double* __restrict__ pos,
@@ -164,7 +171,7 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
 
   __shared__ float4 sloc[TPB];
   __shared__ float4 saw[TPB];
-  __shared__ float sew[CF ? TPB : 1];
+  __shared__ float sew[FORM ? TPB : 1];
   __shared__ float2 smu[TPB * NRC];
 
   float sr[NRC], si[NRC], cr[NRC], ci[NRC];
@@ -196,7 +203,7 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
         const int64_t j = s0 + base + tid;
         sloc[tid] = loc32[j];
         saw[tid] = aw32[j];
-        if (CF) sew[tid] = ew32[j];
+        if (FORM) sew[tid] = ew32[j];
 #pragma unroll
         for (int r = 0; r < NRC; ++r) {
           const double2 m = (rc0 + r < nrhs) ? mu[j * nrhs + rc0 + r] : make_double2(0.0, 0.0);
@@ -222,16 +229,23 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
           const float ph = fmaf(delta, k2pi, ph0);            // revolutions
           const float s = __builtin_amdgcn_sinf(ph);
           const float c = __builtin_amdgcn_cosf(ph);
-          const float kr = kf * r;
-          // aw . (y - x) = aw . D + aw . y'
-          const float dot = fmaf(a4.x, dxf, fmaf(a4.y, dyf, fmaf(a4.z, dzf, a4.w)));
-          const float sc = dot * (ir * ir * ir);
-          float re = -fmaf(kr, s, c) * sc;                     // Re (ikr - 1) e^{ikr} / r^3 (.)
-          float im = fmaf(kr, c, -s) * sc;
-          if (CF) {   // - i eta G |aw|: (eta |aw| / r)(sin kr - i cos kr)
+          float re, im;
+          if constexpr (FORM == 2) {   // G |aw|: (|aw| / r)(cos kr + i sin kr)
             const float t = sew[jj] * ir;
-            re = fmaf(t, s, re);
-            im = fmaf(-t, c, im);
+            re = c * t;
+            im = s * t;
+          } else {
+            const float kr = kf * r;
+            // aw . (y - x) = aw . D + aw . y'
+            const float dot = fmaf(a4.x, dxf, fmaf(a4.y, dyf, fmaf(a4.z, dzf, a4.w)));
+            const float sc = dot * (ir * ir * ir);
+            re = -fmaf(kr, s, c) * sc;                         // Re (ikr - 1) e^{ikr} / r^3 (.)
+            im = fmaf(kr, c, -s) * sc;
+            if constexpr (FORM == 1) {   // - i eta G |aw|: (eta |aw| / r)(sin kr - i cos kr)
+              const float t = sew[jj] * ir;
+              re = fmaf(t, s, re);
+              im = fmaf(-t, c, im);
+            }
           }
 #pragma unroll
           for (int r_ = 0; r_ < NRC; ++r_) {
@@ -374,60 +388,60 @@ bool pair_config_ok(int prec, int tpb, int nrc) {
   return lds_f32(tpb, nrc) <= 65536;
 }
 
-template <int TPB, int NRC, bool CF>
+template <int TPB, int NRC, int FORM>
 static void launch_f64(qax_problem* p, const double* mu, int nrhs, double* partial) {
   if constexpr (lds_f64(TPB, NRC) <= 65536) {
     dim3 grid((unsigned)p->tasks64.size(), (unsigned)((nrhs + NRC - 1) / NRC));
-    hipLaunchKernelGGL((pair_sum_f64_kernel<TPB, NRC, CF>), grid, dim3(TPB), 0, p->stream,
+    hipLaunchKernelGGL((pair_sum_f64_kernel<TPB, NRC, FORM>), grid, dim3(TPB), 0, p->stream,
                        p->d_tasks64, p->d_bodies, p->d_node_body, p->d_pos, p->d_aw, p->d_ew, p->N,
                        (const double2*)mu, nrhs, p->seg_active, (double2*)partial);
   }
 }
 
-template <int TPB, int NRC, bool CF>
+template <int TPB, int NRC, int FORM>
 static void launch_f32(qax_problem* p, const double* mu, int nrhs, double* partial) {
   if constexpr (lds_f32(TPB, NRC) <= 65536) {
     dim3 grid((unsigned)p->tasks32.size(), (unsigned)((nrhs + NRC - 1) / NRC));
-    hipLaunchKernelGGL((pair_sum_f32_kernel<TPB, NRC, CF>), grid, dim3(TPB), 0, p->stream,
+    hipLaunchKernelGGL((pair_sum_f32_kernel<TPB, NRC, FORM>), grid, dim3(TPB), 0, p->stream,
                        p->d_tasks32, p->d_bodies, p->d_node_body, p->d_pos,
                        (const float4*)p->d_loc32, (const float4*)p->d_aw32, p->d_ew32, p->N,
                        (const double2*)mu, nrhs, p->seg_active, (double2*)partial);
   }
 }
 
-template <int TPB, bool CF>
+template <int TPB, int FORM>
 static void launch_f64_nrc(qax_problem* p, int nrc, const double* mu, int nrhs, double* partial) {
   switch (nrc) {
-    case 1: launch_f64<TPB, 1, CF>(p, mu, nrhs, partial); break;
-    case 2: launch_f64<TPB, 2, CF>(p, mu, nrhs, partial); break;
-    case 4: launch_f64<TPB, 4, CF>(p, mu, nrhs, partial); break;
-    default: launch_f64<TPB, 8, CF>(p, mu, nrhs, partial); break;
+    case 1: launch_f64<TPB, 1, FORM>(p, mu, nrhs, partial); break;
+    case 2: launch_f64<TPB, 2, FORM>(p, mu, nrhs, partial); break;
+    case 4: launch_f64<TPB, 4, FORM>(p, mu, nrhs, partial); break;
+    default: launch_f64<TPB, 8, FORM>(p, mu, nrhs, partial); break;
   }
 }
 
-template <int TPB, bool CF>
+template <int TPB, int FORM>
 static void launch_f32_nrc(qax_problem* p, int nrc, const double* mu, int nrhs, double* partial) {
   switch (nrc) {
-    case 1: launch_f32<TPB, 1, CF>(p, mu, nrhs, partial); break;
-    case 2: launch_f32<TPB, 2, CF>(p, mu, nrhs, partial); break;
-    case 4: launch_f32<TPB, 4, CF>(p, mu, nrhs, partial); break;
-    case 8: launch_f32<TPB, 8, CF>(p, mu, nrhs, partial); break;
-    case 16: launch_f32<TPB, 16, CF>(p, mu, nrhs, partial); break;
-    default: launch_f32<TPB, 32, CF>(p, mu, nrhs, partial); break;
+    case 1: launch_f32<TPB, 1, FORM>(p, mu, nrhs, partial); break;
+    case 2: launch_f32<TPB, 2, FORM>(p, mu, nrhs, partial); break;
+    case 4: launch_f32<TPB, 4, FORM>(p, mu, nrhs, partial); break;
+    case 8: launch_f32<TPB, 8, FORM>(p, mu, nrhs, partial); break;
+    case 16: launch_f32<TPB, 16, FORM>(p, mu, nrhs, partial); break;
+    default: launch_f32<TPB, 32, FORM>(p, mu, nrhs, partial); break;
   }
 }
 
-template <bool CF>
+template <int FORM>
 static void launch_any(qax_problem* p, bool f64, int tpb, int nrc, const double* mu, int nrhs,
                        double* partial) {
   if (f64) {
-    if (tpb == 128) launch_f64_nrc<128, CF>(p, nrc, mu, nrhs, partial);
-    else if (tpb == 256) launch_f64_nrc<256, CF>(p, nrc, mu, nrhs, partial);
-    else launch_f64_nrc<512, CF>(p, nrc, mu, nrhs, partial);
+    if (tpb == 128) launch_f64_nrc<128, FORM>(p, nrc, mu, nrhs, partial);
+    else if (tpb == 256) launch_f64_nrc<256, FORM>(p, nrc, mu, nrhs, partial);
+    else launch_f64_nrc<512, FORM>(p, nrc, mu, nrhs, partial);
   } else {
-    if (tpb == 128) launch_f32_nrc<128, CF>(p, nrc, mu, nrhs, partial);
-    else if (tpb == 256) launch_f32_nrc<256, CF>(p, nrc, mu, nrhs, partial);
-    else launch_f32_nrc<512, CF>(p, nrc, mu, nrhs, partial);
+    if (tpb == 128) launch_f32_nrc<128, FORM>(p, nrc, mu, nrhs, partial);
+    else if (tpb == 256) launch_f32_nrc<256, FORM>(p, nrc, mu, nrhs, partial);
+    else launch_f32_nrc<512, FORM>(p, nrc, mu, nrhs, partial);
   }
 }
 
@@ -458,8 +472,11 @@ hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* o
   while (nrc > 1 && !pair_config_ok(prec, tpb, nrc)) nrc /= 2;
   if (!pair_config_ok(prec, tpb, nrc) || p->plan_tpb[pi] != tpb) return hipErrorInvalidConfiguration;
   timing_begin(p, kind);
-  if (p->formulation == QAX_COMBINED_FIELD) launch_any<true>(p, f64, tpb, nrc, mu, nrhs, partial);
-  else launch_any<false>(p, f64, tpb, nrc, mu, nrhs, partial);
+  switch (p->form()) {
+    case 1: launch_any<1>(p, f64, tpb, nrc, mu, nrhs, partial); break;
+    case 2: launch_any<2>(p, f64, tpb, nrc, mu, nrhs, partial); break;
+    default: launch_any<0>(p, f64, tpb, nrc, mu, nrhs, partial); break;
+  }
   timing_end(p, kind);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

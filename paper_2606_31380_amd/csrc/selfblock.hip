@@ -619,11 +619,12 @@ __device__ __forceinline__ void store_slots(SelfShared<CF>& S, const double2 (&a
 // field 1/2 I + D - i eta S (the combined-field remark of Section 2), where
 // the single layer interpolates the density times |J|, so its column
 // (ip, l, j) carries |J| at that node.
-template <bool CF>
+template <int FORM>
 __global__ __launch_bounds__(64) void assemble_self_kernel(
     const SelfTask* __restrict__ tasks, const BlockDev* __restrict__ blocks,
     const BodyDev* __restrict__ bodies, const double* __restrict__ gl16,
     const OuterRule* __restrict__ orule, double2* __restrict__ pool) {
+  constexpr bool CF = FORM != 0;   // single-layer modes needed
   __shared__ SelfShared<CF> S;
   const SelfTask task = tasks[blockIdx.x];
   const BlockDev K = blocks[task.block];
@@ -688,11 +689,15 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       const double wq = om * PI / N;
       const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI * wq;
       double2 v = make_double2(-(c + k * rr * s) * sc, (k * rr * c - s) * sc);
-      if constexpr (CF) {
+      if constexpr (FORM == 1) {
         // - i eta e^{i k rho} / (4 pi rho) |J| w
         const double g = eta * sqrt(nx * nx + ny * ny + nz * nz) * ir * INV_4PI * wq;
         v.x += s * g;
         v.y -= c * g;
+      } else if constexpr (FORM == 2) {
+        // e^{i k rho} / (4 pi rho) |J| w alone
+        const double g = sqrt(nx * nx + ny * ny + nz * nz) * ir * INV_4PI * wq;
+        v = make_double2(c * g, s * g);
       }
       row[(int64_t)(ip * GL_ORDER + l) * nth + j] = v;
     }
@@ -851,7 +856,8 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   double2 g[GL_ORDER];
   if (lane < 2 * N) slots_to_nodes(S, N, g);
   if constexpr (CF) {
-    // single layer: second inverse DFT, then - i eta |J| at the column node
+    // single layer: second inverse DFT, then - i eta |J| (combined field) or
+    // |J| (single layer) at the column node
     __syncthreads();
     store_slots(S, acs);
     __syncthreads();
@@ -866,18 +872,22 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         const Curve cv = curve_eval(shape, a, cc, kappa, t);
         const double dn = cv.dr + cv.dp * cj + cv.dq * sj;
         const double jac = cv.r * sqrt(cv.dz * cv.dz + dn * dn);
-        const double f = eta * jac;
-        g[l].x = fma(f, gs[l].y, g[l].x);
-        g[l].y = fma(-f, gs[l].x, g[l].y);
+        if constexpr (FORM == 2) {
+          g[l] = make_double2(jac * gs[l].x, jac * gs[l].y);
+        } else {
+          const double f = eta * jac;
+          g[l].x = fma(f, gs[l].y, g[l].x);
+          g[l].y = fma(-f, gs[l].x, g[l].y);
+        }
       }
     }
   }
   if (lane < 2 * N) {
-    const bool diag = ip == pT && lane == jT;
+    const bool diag = FORM != 2 && ip == pT && lane == jT;
 #pragma unroll
     for (int l = 0; l < GL_ORDER; ++l) {
       double2 v = g[l];
-      if (diag && l == lT) v.x += 0.5;     // 1/2 I
+      if (diag && l == lT) v.x += 0.5;     // 1/2 I (second-kind formulations)
       row[(int64_t)(ip * GL_ORDER + l) * nth + lane] = v;
     }
   }
@@ -912,14 +922,11 @@ hipError_t launch_assemble_self(qax_problem* p) {
   if (e == hipSuccess) e = hipMemcpyAsync(d_rule, &R, sizeof(R), hipMemcpyHostToDevice, p->stream);
   if (e == hipSuccess) {
     timing_begin(p, QAX_K_SELF_ASSEMBLY);
-    if (p->formulation == QAX_COMBINED_FIELD)
-      hipLaunchKernelGGL(assemble_self_kernel<true>, dim3((unsigned)tasks.size()), dim3(64), 0,
-                         p->stream, d_tasks, p->d_blocks, p->d_bodies, p->d_gl, d_rule,
-                         (double2*)p->d_B);
-    else
-      hipLaunchKernelGGL(assemble_self_kernel<false>, dim3((unsigned)tasks.size()), dim3(64), 0,
-                         p->stream, d_tasks, p->d_blocks, p->d_bodies, p->d_gl, d_rule,
-                         (double2*)p->d_B);
+    const int form = p->form();
+    auto kern = form == 1 ? assemble_self_kernel<1> : form == 2 ? assemble_self_kernel<2>
+                                                                  : assemble_self_kernel<0>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)tasks.size()), dim3(64), 0, p->stream, d_tasks,
+                       p->d_blocks, p->d_bodies, p->d_gl, d_rule, (double2*)p->d_B);
     timing_end(p, QAX_K_SELF_ASSEMBLY);
     e = hipGetLastError();
   }

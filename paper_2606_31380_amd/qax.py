@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libqax.so")
 
 QAX_OK, QAX_ERR_ARG, QAX_ERR_DEVICE, QAX_ERR_NOMEM, QAX_ERR_NOCONV, QAX_ERR_STATE = range(6)
 QAX_FP64, QAX_MIXED = 0, 1
-QAX_DOUBLE_LAYER, QAX_COMBINED_FIELD = 0, 1
+QAX_DOUBLE_LAYER, QAX_COMBINED_FIELD, QAX_SINGLE_LAYER = 0, 1, 2
 STATUS_NAMES = {0: "QAX_OK", 1: "QAX_ERR_ARG", 2: "QAX_ERR_DEVICE", 3: "QAX_ERR_NOMEM",
                 4: "QAX_ERR_NOCONV", 5: "QAX_ERR_STATE"}
 
@@ -251,7 +251,8 @@ def qax_lattice(h, enable=True):
 
 
 def qax_set_formulation(h, formulation, eta=0.0):
-    """QAX_DOUBLE_LAYER or QAX_COMBINED_FIELD; eta > 0 fixed coupling, else k."""
+    """QAX_DOUBLE_LAYER, QAX_COMBINED_FIELD (eta > 0 fixed coupling, else k)
+    or QAX_SINGLE_LAYER."""
     _check(h, lib().qax_set_formulation(h, int(formulation), float(eta)))
 
 

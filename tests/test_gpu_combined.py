@@ -9,7 +9,10 @@
 * a sound-soft sphere at an interior Neumann eigenvalue, where the double
   layer alone is singular: the far field against the Mie series;
 * point sources inside bent bodies (artificial solutions), FP64 and mixed;
-* switching formulations on an assembled handle, and argument errors.
+* switching formulations on an assembled handle, and argument errors;
+* the first-kind single-layer equation S mu = -u_inc (QAX_SINGLE_LAYER):
+  self-block rows, pair sums, near and far field against the oracle, the
+  sphere's Mie far field, artificial solutions, and the lattice apply.
 """
 import math
 
@@ -228,6 +231,113 @@ def test_formulation_argument_errors():
     s = lattice(1, 8)
     with qax.Problem(s) as P:
         with pytest.raises(qax.QaxError):
-            qax.qax_set_formulation(P.h, 2, 1.0)
+            qax.qax_set_formulation(P.h, 3, 1.0)
         with pytest.raises(qax.QaxError):
             qax.qax_set_formulation(P.h, CF, float("nan"))
+
+
+# ---------------------------------------------------------------- single layer
+SL = qax.QAX_SINGLE_LAYER
+
+
+def test_single_layer_self_block_rows():
+    k = 4.0
+    s = two_shapes(k)
+    d = geo.discretize(s)
+    cases = ((0, np.array([0, 200, 767])), (1, np.array([40, 530, 1023])))
+    with qax.Problem(s, formulation=SL) as P:
+        qax.qax_assemble_self(P.h)
+        for bi, rows in cases:
+            nb = d.bodies[bi].n
+            t = torch.zeros(nb * nb, dtype=torch.complex128, device=DEV)
+            qax.qax_self_block(P.h, bi, t)
+            got = t.cpu().numpy().reshape(nb, nb)[rows]
+            want = oself.self_block(d.bodies[bi], k, rows=rows, kind="sl")
+            scale = np.abs(want).max(axis=1, keepdims=True)
+            assert (np.abs(got - want) / scale).max() < 2e-11, bi
+
+
+def test_single_layer_pair_sums_and_fields():
+    a = lattice(1, 12, k=2.0)
+    b = lattice(1, 10, k=4.5, problem=1, shift=0.4)
+    s = sc.Scenario("two", np.concatenate([a.bodies, b.bodies]), np.array([2.0, 4.5]), a.dirs)
+    d = geo.discretize(s)
+    n = d.pos.shape[0]
+    rng = np.random.default_rng(11)
+    mu = rng.standard_normal((n, 2)) + 1j * rng.standard_normal((n, 2))
+    want = opair.pair_sum(d, s.k, mu, single=True)
+    with qax.Problem(s, formulation=SL) as P:
+        v = torch.from_numpy(np.ascontiguousarray(mu.ravel())).to(DEV)
+        out = P.vec(2)
+        qax.qax_pair_sum(P.h, qax.QAX_FP64, v, out, 2)
+        assert rel(out.cpu().numpy().reshape(n, 2), want) < 1e-12
+        qax.qax_pair_sum(P.h, qax.QAX_MIXED, v, out, 2)
+        assert rel(out.cpu().numpy().reshape(n, 2), want) < 1e-5
+        pts = shell_points(120, d.centres.mean(axis=0), 12.0, 4)
+        u = torch.zeros(pts.shape[0], dtype=torch.complex128, device=DEV)
+        m1 = torch.from_numpy(mu[:, 0].copy()).to(DEV)
+        qax.qax_nearfield(P.h, m1, pts, u, problem=1)
+        assert rel(u.cpu().numpy(), osolve.near_field(d, s.k, mu[:, 0], pts, problem=1, single=True)) < 1e-12
+    s1 = lattice(1, 12, k=3.0)
+    d1 = geo.discretize(s1)
+    m = np.exp(0.017j * np.arange(d1.pos.shape[0]))
+    c = d1.centres.mean(axis=0)
+    xhat = shell_points(80, np.zeros(3), 1.0, 8)
+    with qax.Problem(s1, formulation=SL) as P:
+        ff = torch.zeros(xhat.shape[0], dtype=torch.complex128, device=DEV)
+        qax.qax_farfield(P.h, torch.from_numpy(m).to(DEV), xhat, ff)
+        assert rel(ff.cpu().numpy(), osolve.far_field(d1, s1.k, m, xhat, single=True)) < 1e-12
+
+
+def test_single_layer_sphere_mie():
+    a, k = 0.5, 2.0
+    s = sc.single_sphere(a, 2, 16, k)
+    g = np.array([0.0, 0.7, math.pi / 2, 2.5, math.pi])
+    xh = np.stack([np.sin(g), 0 * g, np.cos(g)], axis=1)
+    with qax.Problem(s, formulation=SL) as P:
+        qax.qax_assemble_self(P.h)
+        x = P.vec()
+        info = qax.qax_solve(P.h, qax.QAX_FP64, s.dirs, x, 1, tol=1e-12, maxit=200)
+        assert info["rel_res"] <= 1e-12
+        ff = torch.zeros(len(g), dtype=torch.complex128, device=DEV)
+        qax.qax_farfield(P.h, x, xh, ff)
+        assert np.abs(ff.cpu().numpy() - mie_far(k, a, g)).max() < 1e-9
+
+
+def test_single_layer_artificial_solution():
+    s = lattice(2, 32)
+    k = float(s.k[0])
+    errs = {}
+    for prec, tol in ((qax.QAX_FP64, 1e-12), (qax.QAX_MIXED, 1e-8)):
+        with qax.Problem(s, formulation=SL) as P:
+            qax.qax_assemble_self(P.h)
+            pos = torch.zeros(P.N * 3, dtype=torch.float64, device=DEV)
+            aw = torch.zeros_like(pos)
+            qax.qax_nodes(P.h, pos, aw)
+            y = pos.cpu().numpy().reshape(-1, 3)
+            centres = np.stack([s.bodies["cx"], s.bodies["cy"], s.bodies["cz"]], 1)
+            z = centres + np.array([0.04, -0.03, 0.08])
+            b = torch.from_numpy(osolve.point_source_field(k, z, y)).to(DEV)
+            mu = P.vec()
+            info = qax.qax_solve_rhs(P.h, prec, b, mu, 1, tol=tol, maxit=500)
+            assert info["rel_res"] <= tol
+            c = centres.mean(axis=0)
+            pts = shell_points(200, c, np.abs(centres - c).max() + 6.0, 7)
+            u = torch.zeros(pts.shape[0], dtype=torch.complex128, device=DEV)
+            qax.qax_nearfield(P.h, mu, pts, u)
+            errs[prec] = rel(u.cpu().numpy(), osolve.point_source_field(k, z, pts))
+    assert errs[qax.QAX_FP64] < 1e-9 and errs[qax.QAX_MIXED] < 1e-7, errs
+
+
+def test_single_layer_lattice_apply():
+    from oracle import lattice as olat
+    s = sc.identical_array((2, 2, 3), (3.0, 2.5, 3.5), seed=2)
+    d = geo.discretize(s)
+    rng = np.random.default_rng(12)
+    mu = rng.standard_normal((d.pos.shape[0], 2)) + 1j * rng.standard_normal((d.pos.shape[0], 2))
+    want = olat.lattice_apply(d, 2.0, mu, single=True)
+    with qax.Problem(s, formulation=SL) as P:
+        qax.qax_lattice(P.h)
+        out = P.vec(2)
+        qax.qax_pair_sum(P.h, qax.QAX_FP64, torch.from_numpy(np.ascontiguousarray(mu.ravel())).to(DEV), out, 2)
+        assert rel(out.cpu().numpy().reshape(-1, 2), want) < 1e-12
