@@ -125,13 +125,17 @@ qax_status qax_nodes(const qax_problem* p, double* d_pos, double* d_aw);
 
 /* Assemble every distinct self block B = 1/2 I + D_bb in FP64 (Sections
  * 3.1-3.4: modal Green's functions by recurrence, FFT and convolution; product
- * integration in s), then its inverse in FP64 and an FP32 copy of the inverse
- * (the block-diagonal preconditioner of Section 6).  *t_setup_s (may be NULL)
- * receives the wall time. */
+ * integration in s), then its inverse computed in FP32 from B rounded to FP32
+ * (the block-diagonal preconditioner of Section 6 for the mixed path).  The
+ * FP64 inverse is computed by the first call that needs it after an
+ * assembly (qax_self_block with inverse, qax_block_apply with inverse in
+ * QAX_FP64, QAX_FP64 solves; outside their solve time).  *t_setup_s (may be
+ * NULL) receives the wall time. */
 qax_status qax_assemble_self(qax_problem* p, double* t_setup_s);
 
 /* Copy the self block of body `body` (n_b x n_b complex128, row-major: row =
- * target node, column = source node) into d_out.  inverse != 0 copies B^-1. */
+ * target node, column = source node) into d_out.  inverse != 0 copies the
+ * FP64 B^-1. */
 qax_status qax_self_block(const qax_problem* p, int32_t body, int32_t inverse, void* d_out);
 
 /* Inter-body pair sum only (Section 4): d_out = D_off d_mu, i.e. for every
@@ -141,8 +145,8 @@ qax_status qax_self_block(const qax_problem* p, int32_t body, int32_t inverse, v
 qax_status qax_pair_sum(qax_problem* p, qax_prec prec, const void* d_mu, void* d_out, int32_t nrhs);
 
 /* Block-diagonal apply: d_out_b = M_b d_v_b for every body, M_b = B_b
- * (inverse == 0) or B_b^-1 (inverse != 0); prec QAX_MIXED uses the FP32 copy
- * of B_b^-1 with FP64 accumulation.  N x nrhs complex128. */
+ * (inverse == 0) or B_b^-1 (inverse != 0); prec QAX_MIXED uses the FP32
+ * inverse with FP64 accumulation.  N x nrhs complex128. */
 qax_status qax_block_apply(qax_problem* p, int32_t inverse, qax_prec prec,
                            const void* d_v, void* d_out, int32_t nrhs);
 
@@ -263,7 +267,7 @@ typedef enum {
   QAX_K_SELF_ASSEMBLY = 3, /* self-block assembly                              */
   QAX_K_INVERT = 4,        /* self-block inversion (all of its launches)       */
   QAX_K_INVERT_UPDATE = 5, /* inversion: trailing update of one 64-column panel */
-  QAX_K_BLOCK_APPLY_F32 = 6, /* block-diagonal apply of the FP32 copy of B^-1   */
+  QAX_K_BLOCK_APPLY_F32 = 6, /* block-diagonal apply of the FP32 inverse of B   */
   QAX_K_LATTICE_F64 = 7,   /* lattice apply: per-frequency products, FP64 tables */
   QAX_K_LATTICE_F32 = 8,   /* lattice apply: per-frequency products, FP32 tables */
   QAX_K_COUNT = 9
@@ -283,7 +287,7 @@ qax_status qax_timing(const qax_problem* p, int32_t kernel, int64_t* launches, d
  *    several right-hand sides, right-hand sides per pass (2 ... 32), chosen
  *    together with the workgroup size for the largest class nrhs_max reaches;
  *  - block apply with one right-hand side, per storage precision: complex
- *    entries per lane and load (1, 2; 4 for the FP32 copy).
+ *    entries per lane and load (1, 2; 4 for the FP32 inverse).
  * Every candidate is timed on this problem's own data (HIP events, the
  * fastest of a few launches after a warm-up) and the fastest is kept for the
  * handle until the next qax_autotune.  Results do not depend on the choices
@@ -302,7 +306,7 @@ typedef struct {
   int32_t pair_tpb[2];        /* [0] FP64, [1] FP32 pair sum: workgroup size  */
   int32_t pair_slot_mult[2];  /* workgroups per CU of the source-chunk split  */
   int32_t pair_nrc[2][4];     /* RHS per pass for nrhs 2-4, 5-8, 9-16, > 16   */
-  int32_t gemv_vec[2];        /* block apply, 1 RHS: [0] FP64, [1] FP32 copy  */
+  int32_t gemv_vec[2];        /* block apply, 1 RHS: [0] FP64, [1] FP32 inverse*/
   double pair_ms[2];          /* chosen single-RHS pair sum, ms (timed runs)  */
   double default_pair_ms[2];  /* the built-in default choice, ms             */
 } qax_tuning_info;

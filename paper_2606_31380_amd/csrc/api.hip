@@ -434,6 +434,18 @@ extern "C" qax_status qax_nodes(const qax_problem* pc, double* d_pos, double* d_
 }
 
 // ---------------------------------------------------------------- self blocks
+// The FP64 inverse blocks, made on first use after each assembly (the mixed
+// path only needs the FP32 inverse, which assembly makes).  Not to be called
+// inside a stream capture.
+static qax_status ensure_inverse64(qax_problem* p) {
+  if (p->inv64_ready) return QAX_OK;
+  QBUF(work, double, "gj_work", invert_blocks_work_bytes(p));
+  QCHECK(launch_invert_blocks64(p, work), "invert_blocks (FP64)");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  p->inv64_ready = true;
+  return QAX_OK;
+}
+
 extern "C" qax_status qax_assemble_self(qax_problem* p, double* t_setup_s) {
   if (!p) return QAX_ERR_ARG;
   if (p->state < 1) return fail(p, QAX_ERR_STATE, "qax_assemble_self: call qax_build first");
@@ -463,6 +475,10 @@ extern "C" qax_status qax_self_block(const qax_problem* pc, int32_t body, int32_
   if (p->state < 2) return fail(p, QAX_ERR_STATE, "qax_self_block: call qax_assemble_self first");
   if (body < 0 || body >= p->n_bodies) return fail(p, QAX_ERR_ARG, "qax_self_block: bad body index");
   QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  if (inverse) {
+    const qax_status st = ensure_inverse64(p);
+    if (st != QAX_OK) return st;
+  }
   const BlockDev& K = p->hblocks[p->hbodies[body].block];
   const double* src = (inverse ? p->d_Binv : p->d_B) + 2 * K.elem_off;
   QCHECK(hipMemcpyAsync(d_out, src, (size_t)K.n * K.n * 16, hipMemcpyDeviceToDevice, p->stream),
@@ -502,6 +518,10 @@ extern "C" qax_status qax_block_apply(qax_problem* p, int32_t inverse, qax_prec 
   qax_status st = check_vec_call(p, d_v, d_out, nrhs, 2);
   if (st != QAX_OK) return st;
   QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  if (inverse && prec == QAX_FP64) {
+    st = ensure_inverse64(p);
+    if (st != QAX_OK) return st;
+  }
   QCHECK(launch_block_apply(p, inverse, prec, (const double*)d_v, (double*)d_out, nrhs, false),
          "block_apply");
   return sync(p, "qax_block_apply");
@@ -554,9 +574,12 @@ extern "C" qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrh
   for (int i = 0; i < 3 * n_dirs; ++i)
     if (!is_finite(xhat[i])) return fail(p, QAX_ERR_ARG, "qax_farfield: non-finite direction");
   QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  const int slots = farfield_slots(n_dirs, cu_count(p->device));
   QBUF(dx, double, "xhat", (size_t)n_dirs * 24);
+  QBUF(part, double, "ff_partial", (size_t)slots * n_dirs * nrhs * 16);
   QCHECK(hipMemcpyAsync(dx, xhat, (size_t)n_dirs * 24, hipMemcpyHostToDevice, p->stream), "copy xhat");
-  QCHECK(launch_farfield(p, (const double*)d_mu, nrhs, dx, n_dirs, (double*)d_u_inf), "farfield");
+  QCHECK(launch_farfield(p, (const double*)d_mu, nrhs, dx, n_dirs, slots, part, (double*)d_u_inf),
+         "farfield");
   return sync(p, "qax_farfield");
 }
 
@@ -663,6 +686,8 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
   if (!(tol > 0) || !is_finite(tol) || maxit < 1) return fail(p, QAX_ERR_ARG, "qax_solve: bad tol / maxit");
   QCHECK(hipSetDevice(p->device), "hipSetDevice");
   QCHECK(hipStreamSynchronize(p->stream), "sync");
+  // set-up outside the solve time: the FP64 preconditioner on first FP64 use
+  if (prec == QAX_FP64 && (st = ensure_inverse64(p)) != QAX_OK) return st;
   auto t0 = std::chrono::steady_clock::now();
 
   const int64_t N = p->N;
@@ -1138,7 +1163,10 @@ extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char*
       for (int vec : {1, 2, 4}) {
         if (pi == 0 && vec == 4) continue;
         p->tune.gemv_vec[pi] = vec;
-        const double ms = time_best(p, 3, [&] { return launch_block_apply(p, 1, prec, mu, out, 1, false); }, &err);
+        // FP64: timed on B (same layout and bytes as the FP64 inverse, which
+        // may not have been made yet)
+        const int inv = prec == QAX_FP64 ? 0 : 1;
+        const double ms = time_best(p, 3, [&] { return launch_block_apply(p, inv, prec, mu, out, 1, false); }, &err);
         QCHECK(err, "autotune block apply");
         if (ms < best) {
           best = ms;

@@ -334,19 +334,35 @@ struct MatDesc {
   int32_t n;
 };
 
+// Complex element type of the inversion: FP64 (V) or FP32 (float2).
+template <typename T>
+struct Cx;
+template <>
+struct Cx<double> {
+  typedef double2 V;
+  static __device__ __forceinline__ double2 make(double a, double b) { return make_double2(a, b); }
+};
+template <>
+struct Cx<float> {
+  typedef float2 V;
+  static __device__ __forceinline__ float2 make(float a, float b) { return make_float2(a, b); }
+};
+
 // Undo the row interchanges as column interchanges, last step first.
-__global__ void gj_unpivot_kernel(const MatDesc* __restrict__ mats, double2* __restrict__ pool,
+template <typename T>
+__global__ void gj_unpivot_kernel(const MatDesc* __restrict__ mats, typename Cx<T>::V* __restrict__ pool,
                                   const int32_t* __restrict__ piv, int nmax) {
+  typedef typename Cx<T>::V V;
   const MatDesc M = mats[blockIdx.y];
   const int n = M.n;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double2* row = pool + M.elem_off + (int64_t)i * n;
+  V* row = pool + M.elem_off + (int64_t)i * n;
   const int32_t* pv = piv + (int64_t)blockIdx.y * nmax;
   for (int k = n - 1; k >= 0; --k) {
     const int p = pv[k];
     if (p != k) {
-      const double2 t = row[k];
+      const V t = row[k];
       row[k] = row[p];
       row[p] = t;
     }
@@ -371,39 +387,40 @@ constexpr int GJB = 64;
 // lower row), then one LDS exchange that carries both the pivot row scaled
 // by its owner and the row it displaces, and the rank-1 elimination of the
 // other rows: two barriers per column.
-template <int R, int WL>
+template <typename T, int R, int WL>
 __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restrict__ mats,
-                                                        double2* __restrict__ pool, int c0,
+                                                        typename Cx<T>::V* __restrict__ pool, int c0,
                                                         int wcols, int32_t* __restrict__ piv,
                                                         int nmax) {
+  typedef typename Cx<T>::V V;
   const MatDesc M = mats[blockIdx.x];
   const int n = M.n;
   if (c0 >= n) return;
-  double2* A = pool + M.elem_off;
+  V* A = pool + M.elem_off;
   const int w = min(c0 + wcols, n) - c0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double red_v[16];
+  __shared__ T red_v[16];
   __shared__ int red_i[16];
-  __shared__ double2 swap_buf[1][WL];
-  __shared__ double2 rowk[WL];
-  double2 a[R][WL];
+  __shared__ V swap_buf[1][WL];
+  __shared__ V rowk[WL];
+  V a[R][WL];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = tid + 1024 * r;
 #pragma unroll
     for (int c = 0; c < WL; ++c)
-      a[r][c] = (i < n && c < w) ? A[(int64_t)i * n + c0 + c] : make_double2(0.0, 0.0);
+      a[r][c] = (i < n && c < w) ? A[(int64_t)i * n + c0 + c] : Cx<T>::make(0.0, 0.0);
   }
 #pragma unroll
   for (int kk = 0; kk < WL; ++kk) {
     if (kk >= w) break;
     const int k = c0 + kk;
-    double bv = -1.0;
+    T bv = -1;
     int bi = n;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = tid + 1024 * r;
-      const double m = a[r][kk].x * a[r][kk].x + a[r][kk].y * a[r][kk].y;
+      const T m = a[r][kk].x * a[r][kk].x + a[r][kk].y * a[r][kk].y;
       if (i >= k && i < n && m > bv) {
         bv = m;
         bi = i;
@@ -411,7 +428,7 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
+      const T ov = __shfl_xor(bv, off);
       const int oi = __shfl_xor(bi, off);
       if (ov > bv || (ov == bv && oi < bi)) {
         bv = ov;
@@ -427,7 +444,7 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
     bi = red_i[0];
 #pragma unroll
     for (int q = 1; q < 16; ++q) {
-      const double ov = red_v[q];
+      const T ov = red_v[q];
       const int oi = red_i[q];
       if (ov > bv || (ov == bv && oi < bi)) {
         bv = ov;
@@ -443,13 +460,13 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
     for (int r = 0; r < R; ++r) {
       const int i = tid + 1024 * r;
       if (i == pr) {
-        const double2 d = a[r][kk];
-        const double den = d.x * d.x + d.y * d.y;
-        const double2 inv = make_double2(d.x / den, -d.y / den);
+        const V d = a[r][kk];
+        const T den = d.x * d.x + d.y * d.y;
+        const V inv = Cx<T>::make(d.x / den, -d.y / den);
 #pragma unroll
         for (int c = 0; c < WL; ++c) {
-          const double2 x = (c == kk) ? make_double2(1.0, 0.0) : a[r][c];
-          rowk[c] = make_double2(x.x * inv.x - x.y * inv.y, x.x * inv.y + x.y * inv.x);
+          const V x = (c == kk) ? Cx<T>::make(1.0, 0.0) : a[r][c];
+          rowk[c] = Cx<T>::make(x.x * inv.x - x.y * inv.y, x.x * inv.y + x.y * inv.x);
         }
       }
       if (i == k && pr != k)
@@ -467,12 +484,12 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
         if (i == pr)
 #pragma unroll
           for (int c = 0; c < WL; ++c) a[r][c] = swap_buf[0][c];
-        const double2 f = a[r][kk];
+        const V f = a[r][kk];
 #pragma unroll
         for (int c = 0; c < WL; ++c) {
-          const double2 x = (c == kk) ? make_double2(0.0, 0.0) : a[r][c];
-          const double2 rk = rowk[c];
-          a[r][c] = make_double2(x.x - (f.x * rk.x - f.y * rk.y), x.y - (f.x * rk.y + f.y * rk.x));
+          const V x = (c == kk) ? Cx<T>::make(0.0, 0.0) : a[r][c];
+          const V rk = rowk[c];
+          a[r][c] = Cx<T>::make(x.x - (f.x * rk.x - f.y * rk.y), x.y - (f.x * rk.y + f.y * rk.x));
         }
       }
     }
@@ -491,22 +508,24 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
 // [s0, s0 + ws) (already eliminated) applied to the sibling columns
 // [d0, d0 + wd): (1) their row interchanges, then the pivot rows copied to W;
 // (2) A[i][d0+j] = (i in [s0, s0+ws) ? 0 : A[i][d0+j]) + sum_p A[i][s0+p] W[p][j].
-__global__ void gjn_swap_copy_kernel(const MatDesc* __restrict__ mats, double2* __restrict__ pool,
+template <typename T>
+__global__ void gjn_swap_copy_kernel(const MatDesc* __restrict__ mats, typename Cx<T>::V* __restrict__ pool,
                                      int s0, int ws, int d0, int wd,
                                      const int32_t* __restrict__ piv, int nmax,
-                                     double2* __restrict__ W) {
+                                     typename Cx<T>::V* __restrict__ W) {
+  typedef typename Cx<T>::V V;
   const MatDesc M = mats[blockIdx.x];
   const int n = M.n;
   const int j = d0 + threadIdx.x;
   if (s0 >= n || threadIdx.x >= wd || j >= n) return;
-  double2* A = pool + M.elem_off;
-  double2* Wm = W + (int64_t)blockIdx.x * GJB * GJB;
+  V* A = pool + M.elem_off;
+  V* Wm = W + (int64_t)blockIdx.x * GJB * GJB;
   const int send = min(s0 + ws, n);
   const int32_t* pv = piv + (int64_t)blockIdx.x * nmax;
   for (int k = s0; k < send; ++k) {
     const int pr = pv[k];
     if (pr != k) {
-      const double2 t = A[(int64_t)k * n + j];
+      const V t = A[(int64_t)k * n + j];
       A[(int64_t)k * n + j] = A[(int64_t)pr * n + j];
       A[(int64_t)pr * n + j] = t;
     }
@@ -514,65 +533,69 @@ __global__ void gjn_swap_copy_kernel(const MatDesc* __restrict__ mats, double2* 
   for (int k = s0; k < send; ++k) Wm[(k - s0) * GJB + threadIdx.x] = A[(int64_t)k * n + j];
 }
 
+template <typename T>
 __global__ __launch_bounds__(256) void gjn_update_kernel(const MatDesc* __restrict__ mats,
-                                                         double2* __restrict__ pool, int s0,
+                                                         typename Cx<T>::V* __restrict__ pool, int s0,
                                                          int ws, int d0, int wd,
-                                                         const double2* __restrict__ W) {
+                                                         const typename Cx<T>::V* __restrict__ W) {
+  typedef typename Cx<T>::V V;
   const MatDesc M = mats[blockIdx.y];
   const int n = M.n;
   if (s0 >= n) return;
   const int send = min(s0 + ws, n);
   const int wsv = send - s0;
   const int wdv = min(d0 + wd, n) - d0;
-  __shared__ double2 Ws[GJB / 2][GJB / 2];
-  const double2* Wm = W + (int64_t)blockIdx.y * GJB * GJB;
+  __shared__ V Ws[GJB / 2][GJB / 2];
+  const V* Wm = W + (int64_t)blockIdx.y * GJB * GJB;
   for (int e = threadIdx.x; e < wsv * wdv; e += 256) Ws[e / wdv][e % wdv] = Wm[(e / wdv) * GJB + e % wdv];
   __syncthreads();
   const int rows = 256 / wd;
   const int i = blockIdx.x * rows + threadIdx.x / wd;
   const int j = threadIdx.x % wd;
   if (i >= n || j >= wdv) return;
-  double2* A = pool + M.elem_off;
-  const double2* ar = A + (int64_t)i * n + s0;
-  double2 acc = make_double2(0.0, 0.0);
+  V* A = pool + M.elem_off;
+  const V* ar = A + (int64_t)i * n + s0;
+  V acc = Cx<T>::make(0.0, 0.0);
   for (int p = 0; p < wsv; ++p) {
-    const double2 a = ar[p], w = Ws[p][j];
+    const V a = ar[p], w = Ws[p][j];
     acc.x = fma(a.x, w.x, fma(-a.y, w.y, acc.x));
     acc.y = fma(a.x, w.y, fma(a.y, w.x, acc.y));
   }
-  double2* cptr = A + (int64_t)i * n + d0 + j;
+  V* cptr = A + (int64_t)i * n + d0 + j;
   const bool prow = i >= s0 && i < send;
-  const double2 base = prow ? make_double2(0.0, 0.0) : *cptr;
-  *cptr = make_double2(base.x + acc.x, base.y + acc.y);
+  const V base = prow ? Cx<T>::make(0.0, 0.0) : *cptr;
+  *cptr = Cx<T>::make(base.x + acc.x, base.y + acc.y);
 }
 
 // Row interchanges of the panel applied to the other columns, then the panel
 // rows copied to W (w x n per matrix).
-__global__ void gjb_swap_copy_kernel(const MatDesc* __restrict__ mats, double2* __restrict__ pool,
+template <typename T>
+__global__ void gjb_swap_copy_kernel(const MatDesc* __restrict__ mats, typename Cx<T>::V* __restrict__ pool,
                                      int k0, const int32_t* __restrict__ piv, int nmax,
-                                     double2* __restrict__ W) {
+                                     typename Cx<T>::V* __restrict__ W) {
+  typedef typename Cx<T>::V V;
   const MatDesc M = mats[blockIdx.y];
   const int n = M.n;
   if (k0 >= n) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int kend = min(k0 + GJB, n);
-  double2* A = pool + M.elem_off;
-  double2* Wm = W + (int64_t)blockIdx.y * GJB * nmax;
+  V* A = pool + M.elem_off;
+  V* Wm = W + (int64_t)blockIdx.y * GJB * nmax;
   const bool in_panel = j >= k0 && j < kend;
   if (!in_panel) {
     const int32_t* pv = piv + (int64_t)blockIdx.y * nmax;
     for (int k = k0; k < kend; ++k) {
       const int pr = pv[k];
       if (pr != k) {
-        const double2 t = A[(int64_t)k * n + j];
+        const V t = A[(int64_t)k * n + j];
         A[(int64_t)k * n + j] = A[(int64_t)pr * n + j];
         A[(int64_t)pr * n + j] = t;
       }
     }
   }
   for (int k = k0; k < kend; ++k)
-    Wm[(int64_t)(k - k0) * nmax + j] = in_panel ? make_double2(0.0, 0.0) : A[(int64_t)k * n + j];
+    Wm[(int64_t)(k - k0) * nmax + j] = in_panel ? Cx<T>::make(0.0, 0.0) : A[(int64_t)k * n + j];
 }
 
 // A[i][j] = (i in panel ? 0 : A[i][j]) + sum_p A[i][k0+p] W[p][j] for j outside
@@ -581,10 +604,12 @@ __global__ void gjb_swap_copy_kernel(const MatDesc* __restrict__ mats, double2* 
 // 64 x 64 complex output tile per workgroup (64 x 128 real); each of the four
 // wavefronts owns 32 rows x 64 real columns (2 x 4 MFMA tiles); the panel
 // columns and rows are staged through LDS 16 complex columns at a time.
+template <typename T>
 __global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restrict__ mats,
-                                                         double2* __restrict__ pool, int k0,
-                                                         const double2* __restrict__ W, int nmax) {
-  typedef MfmaAcc<double>::v4 v4;
+                                                         typename Cx<T>::V* __restrict__ pool, int k0,
+                                                         const typename Cx<T>::V* __restrict__ W, int nmax) {
+  typedef typename Cx<T>::V V;
+  typedef typename MfmaAcc<T>::v4 v4;
   const MatDesc M = mats[blockIdx.z];
   const int n = M.n;
   if (k0 >= n) return;
@@ -593,10 +618,10 @@ __global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restri
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
   if (i0 >= n || j0 >= n) return;
   if (j0 >= k0 && j0 + 64 <= kend) return;  // tile inside the panel columns
-  double2* A = pool + M.elem_off;
-  const double2* Wm = W + (int64_t)blockIdx.z * GJB * nmax;
-  __shared__ double As[32][64 + 1];   // real k x rows
-  __shared__ double Bs[32][128 + 1];  // real k x real columns
+  V* A = pool + M.elem_off;
+  const V* Wm = W + (int64_t)blockIdx.z * GJB * nmax;
+  __shared__ T As[32][64 + 1];   // real k x rows
+  __shared__ T Bs[32][128 + 1];  // real k x real columns
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 64;
   // accumulators start from the tile of A (zero on the panel rows and for
@@ -606,29 +631,29 @@ __global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restri
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int i = i0 + wr + 16 * x + MfmaAcc<double>::row(lane, e);
+      const int i = i0 + wr + 16 * x + MfmaAcc<T>::row(lane, e);
       const bool prow = i >= k0 && i < kend;
 #pragma unroll
       for (int y = 0; y < 4; ++y) {
         const int c = wc + 16 * y + (lane & 15);
         const int j = j0 + (c >> 1);
         const bool keep = i < n && j < n && !(j >= k0 && j < kend) && !prow;
-        acc[x][y][e] = keep ? ((const double*)(A + (int64_t)i * n + j))[c & 1] : 0.0;
+        acc[x][y][e] = keep ? ((const T*)(A + (int64_t)i * n + j))[c & 1] : (T)0;
       }
     }
   // panel columns of A and rows of W, 16 at a time, the next chunk loaded into
   // registers while the current one is multiplied
-  double2 ra[4], rw[4];
+  V ra[4], rw[4];
   auto load_chunk = [&](int p0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int rr = e >> 4, pp = e & 15;
       const int i = i0 + rr, pc = p0 + pp;
-      ra[q] = (i < n && pc < w) ? A[(int64_t)i * n + k0 + pc] : make_double2(0.0, 0.0);
+      ra[q] = (i < n && pc < w) ? A[(int64_t)i * n + k0 + pc] : Cx<T>::make(0.0, 0.0);
       const int pw = e >> 6, jj = e & 63;
       const int j = j0 + jj, pcw = p0 + pw;
-      rw[q] = (j < n && pcw < w) ? Wm[(int64_t)pcw * nmax + j] : make_double2(0.0, 0.0);
+      rw[q] = (j < n && pcw < w) ? Wm[(int64_t)pcw * nmax + j] : Cx<T>::make(0.0, 0.0);
     }
   };
   load_chunk(0);
@@ -650,7 +675,7 @@ __global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restri
 #pragma unroll
     for (int kk = 0; kk < 32; kk += 4) {
       const int kr = kk + (lane >> 4), ci = lane & 15;
-      double af[2], bf[4];
+      T af[2], bf[4];
 #pragma unroll
       for (int x = 0; x < 2; ++x) af[x] = As[kr][wr + 16 * x + ci];
 #pragma unroll
@@ -658,7 +683,7 @@ __global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restri
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = MfmaAcc<double>::mma(af[x], bf[y], acc[x][y]);
+        for (int y = 0; y < 4; ++y) acc[x][y] = MfmaAcc<T>::mma(af[x], bf[y], acc[x][y]);
     }
     __syncthreads();
   }
@@ -666,14 +691,14 @@ __global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restri
   for (int x = 0; x < 2; ++x)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int i = i0 + wr + 16 * x + MfmaAcc<double>::row(lane, e);
+      const int i = i0 + wr + 16 * x + MfmaAcc<T>::row(lane, e);
       if (i >= n) continue;
 #pragma unroll
       for (int y = 0; y < 4; ++y) {
         const int c = wc + 16 * y + (lane & 15);   // real column in the tile
         const int j = j0 + (c >> 1);
         if (j >= n || (j >= k0 && j < kend)) continue;
-        ((double*)(A + (int64_t)i * n + j))[c & 1] = acc[x][y][e];
+        ((T*)(A + (int64_t)i * n + j))[c & 1] = acc[x][y][e];
       }
     }
 }
@@ -688,20 +713,21 @@ static int gj_leaf_rows(int nmax) {
 
 static int gj_leaf_cols(int nmax) { return gj_leaf_rows(nmax) == 1 ? 8 : 16 / gj_leaf_rows(nmax); }
 
-static void launch_leaf(hipStream_t s, double2* pool, const MatDesc* d_mats, int batch, int nmax,
-                        int c0, int w, int32_t* piv) {
+template <typename T>
+static void launch_leaf(hipStream_t s, typename Cx<T>::V* pool, const MatDesc* d_mats, int batch,
+                        int nmax, int c0, int w, int32_t* piv) {
   switch (gj_leaf_rows(nmax)) {
     case 1:
-      hipLaunchKernelGGL((gjr_leaf_kernel<1, 8>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      hipLaunchKernelGGL((gjr_leaf_kernel<T, 1, 8>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
       break;
     case 2:
-      hipLaunchKernelGGL((gjr_leaf_kernel<2, 8>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      hipLaunchKernelGGL((gjr_leaf_kernel<T, 2, 8>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
       break;
     case 4:
-      hipLaunchKernelGGL((gjr_leaf_kernel<4, 4>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      hipLaunchKernelGGL((gjr_leaf_kernel<T, 4, 4>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
       break;
     default:
-      hipLaunchKernelGGL((gjr_leaf_kernel<8, 2>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      hipLaunchKernelGGL((gjr_leaf_kernel<T, 8, 2>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
       break;
   }
 }
@@ -709,48 +735,52 @@ static void launch_leaf(hipStream_t s, double2* pool, const MatDesc* d_mats, int
 // Factor the panel columns [c0, c0 + w) (w a power of two, <= GJB) by halves:
 // left half, its row operations on the right half, right half, its row
 // operations on the left half; leaves of gj_leaf_cols columns run unblocked.
-static void gj_factor_panel(hipStream_t s, double2* pool, const MatDesc* d_mats, int batch, int nmax,
-                            int c0, int w, int32_t* piv, double2* Wn) {
+template <typename T>
+static void gj_factor_panel(hipStream_t s, typename Cx<T>::V* pool, const MatDesc* d_mats, int batch,
+                            int nmax, int c0, int w, int32_t* piv, typename Cx<T>::V* Wn) {
   if (w <= gj_leaf_cols(nmax)) {
-    launch_leaf(s, pool, d_mats, batch, nmax, c0, w, piv);
+    launch_leaf<T>(s, pool, d_mats, batch, nmax, c0, w, piv);
     return;
   }
   const int h = w / 2;
   const unsigned rows_blocks = (unsigned)((nmax + (256 / h) - 1) / (256 / h));
-  gj_factor_panel(s, pool, d_mats, batch, nmax, c0, h, piv, Wn);
-  hipLaunchKernelGGL(gjn_swap_copy_kernel, dim3(batch), dim3(h), 0, s, d_mats, pool, c0, h, c0 + h,
-                     h, piv, nmax, Wn);
-  hipLaunchKernelGGL(gjn_update_kernel, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool, c0,
-                     h, c0 + h, h, Wn);
-  gj_factor_panel(s, pool, d_mats, batch, nmax, c0 + h, h, piv, Wn);
-  hipLaunchKernelGGL(gjn_swap_copy_kernel, dim3(batch), dim3(h), 0, s, d_mats, pool, c0 + h, h, c0,
-                     h, piv, nmax, Wn);
-  hipLaunchKernelGGL(gjn_update_kernel, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool,
+  gj_factor_panel<T>(s, pool, d_mats, batch, nmax, c0, h, piv, Wn);
+  hipLaunchKernelGGL(gjn_swap_copy_kernel<T>, dim3(batch), dim3(h), 0, s, d_mats, pool, c0, h,
+                     c0 + h, h, piv, nmax, Wn);
+  hipLaunchKernelGGL(gjn_update_kernel<T>, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool,
+                     c0, h, c0 + h, h, Wn);
+  gj_factor_panel<T>(s, pool, d_mats, batch, nmax, c0 + h, h, piv, Wn);
+  hipLaunchKernelGGL(gjn_swap_copy_kernel<T>, dim3(batch), dim3(h), 0, s, d_mats, pool, c0 + h, h,
+                     c0, h, piv, nmax, Wn);
+  hipLaunchKernelGGL(gjn_update_kernel<T>, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool,
                      c0 + h, h, c0, h, Wn);
 }
 
-// In-place inversion of `batch` matrices described on the device by `mats`
-// (orders up to nmax, at most 8192).  work: see gj_work_bytes.  With tp set,
-// the trailing updates are timed on tp's counters.
-hipError_t gj_invert(hipStream_t s, double* pool, const MatDesc* d_mats, int batch, int nmax,
+// In-place inversion of `batch` matrices of complex T (interleaved, pool in
+// units of T) described on the device by `mats` (orders up to nmax, at most
+// 8192).  work: see gj_work_bytes.  With tp set, the trailing updates are
+// timed on tp's counters.
+template <typename T>
+hipError_t gj_invert(hipStream_t s, T* pool, const MatDesc* d_mats, int batch, int nmax,
                      double* work, qax_problem* tp) {
+  typedef typename Cx<T>::V V;
   if (nmax > 8192) return hipErrorInvalidValue;
-  double2* W = (double2*)work;
+  V* W = (V*)work;
   int32_t* piv = (int32_t*)(W + (int64_t)GJB * nmax * batch);
   const size_t piv_bytes = (((size_t)nmax * batch * sizeof(int32_t)) + 255) / 256 * 256;
-  double2* Wn = (double2*)((char*)piv + piv_bytes);
+  V* Wn = (V*)((char*)piv + piv_bytes);
   const unsigned tiles = (unsigned)((nmax + 63) / 64);
   for (int k0 = 0; k0 < nmax; k0 += GJB) {
-    gj_factor_panel(s, (double2*)pool, d_mats, batch, nmax, k0, GJB, piv, Wn);
-    hipLaunchKernelGGL(gjb_swap_copy_kernel, dim3((nmax + 255) / 256, batch), dim3(256), 0, s,
-                       d_mats, (double2*)pool, k0, piv, nmax, W);
+    gj_factor_panel<T>(s, (V*)pool, d_mats, batch, nmax, k0, GJB, piv, Wn);
+    hipLaunchKernelGGL(gjb_swap_copy_kernel<T>, dim3((nmax + 255) / 256, batch), dim3(256), 0, s,
+                       d_mats, (V*)pool, k0, piv, nmax, W);
     if (tp) timing_begin(tp, QAX_K_INVERT_UPDATE);
-    hipLaunchKernelGGL(gjm_update_kernel, dim3(tiles, tiles, batch), dim3(256), 0, s, d_mats,
-                       (double2*)pool, k0, W, nmax);
+    hipLaunchKernelGGL(gjm_update_kernel<T>, dim3(tiles, tiles, batch), dim3(256), 0, s, d_mats,
+                       (V*)pool, k0, W, nmax);
     if (tp) timing_end(tp, QAX_K_INVERT_UPDATE);
   }
-  hipLaunchKernelGGL(gj_unpivot_kernel, dim3((nmax + 255) / 256, batch), dim3(256), 0, s, d_mats,
-                     (double2*)pool, piv, nmax);
+  hipLaunchKernelGGL(gj_unpivot_kernel<T>, dim3((nmax + 255) / 256, batch), dim3(256), 0, s, d_mats,
+                     (V*)pool, piv, nmax);
   return hipGetLastError();
 }
 
@@ -760,29 +790,50 @@ size_t gj_work_bytes(int batch, int nmax) {
          (size_t)batch * GJB * GJB * sizeof(double2);
 }
 
-// Invert every distinct self block: copy B into Binv, invert in place, make
-// the FP32 copy.
-hipError_t launch_invert_blocks(qax_problem* p, double* work) {
+// Invert every distinct self block for the mixed path: B rounded to FP32,
+// inverted in place in FP32 (matrix cores at the FP32 rate).  The FP64
+// inverse is made on demand by launch_invert_blocks64.
+static hipError_t upload_mats(qax_problem* p, double* work, MatDesc** d_md, double** w2, int* nmax) {
   const int nbk = (int)p->hblocks.size();
-  int nmax = 0;
   std::vector<MatDesc> md(nbk);
+  *nmax = 0;
   for (int i = 0; i < nbk; ++i) {
     md[i].elem_off = p->hblocks[i].elem_off;
     md[i].n = p->hblocks[i].n;
-    nmax = std::max(nmax, md[i].n);
+    *nmax = std::max(*nmax, md[i].n);
   }
-  hipError_t e = hipMemcpyAsync(p->d_Binv, p->d_B, (size_t)p->block_elems * 16,
-                                hipMemcpyDeviceToDevice, p->stream);
-  if (e != hipSuccess) return e;
-  MatDesc* d_md = (MatDesc*)work;
-  double* w2 = (double*)((char*)work + ((nbk * sizeof(MatDesc) + 255) / 256) * 256);
-  e = hipMemcpyAsync(d_md, md.data(), nbk * sizeof(MatDesc), hipMemcpyHostToDevice, p->stream);
+  *d_md = (MatDesc*)work;
+  *w2 = (double*)((char*)work + ((nbk * sizeof(MatDesc) + 255) / 256) * 256);
+  return hipMemcpyAsync(*d_md, md.data(), nbk * sizeof(MatDesc), hipMemcpyHostToDevice, p->stream);
+}
+
+hipError_t launch_invert_blocks(qax_problem* p, double* work) {
+  MatDesc* d_md;
+  double* w2;
+  int nmax;
+  p->inv64_ready = false;
+  hipError_t e = launch_convert_f32(p->stream, p->d_B, p->d_Binv32, p->block_elems * 2);
+  if (e == hipSuccess) e = upload_mats(p, work, &d_md, &w2, &nmax);
   if (e != hipSuccess) return e;
   timing_begin(p, QAX_K_INVERT);
-  e = gj_invert(p->stream, p->d_Binv, d_md, nbk, nmax, w2, p);
+  e = gj_invert<float>(p->stream, p->d_Binv32, d_md, (int)p->hblocks.size(), nmax, w2, p);
   timing_end(p, QAX_K_INVERT);
+  return e;
+}
+
+// FP64 inverse: copy B into Binv and invert in place in FP64.
+hipError_t launch_invert_blocks64(qax_problem* p, double* work) {
+  MatDesc* d_md;
+  double* w2;
+  int nmax;
+  hipError_t e = hipMemcpyAsync(p->d_Binv, p->d_B, (size_t)p->block_elems * 16,
+                                hipMemcpyDeviceToDevice, p->stream);
+  if (e == hipSuccess) e = upload_mats(p, work, &d_md, &w2, &nmax);
   if (e != hipSuccess) return e;
-  return launch_convert_f32(p->stream, p->d_Binv, p->d_Binv32, p->block_elems * 2);
+  timing_begin(p, QAX_K_INVERT);
+  e = gj_invert<double>(p->stream, p->d_Binv, d_md, (int)p->hblocks.size(), nmax, w2, p);
+  timing_end(p, QAX_K_INVERT);
+  return e;
 }
 
 size_t invert_blocks_work_bytes(qax_problem* p) {
@@ -878,7 +929,7 @@ hipError_t launch_dense_solve(qax_problem* p, double* A, const double* b, int nr
   double* w2 = (double*)((char*)work + 256);
   hipError_t e = hipMemcpyAsync(d_md, &md, sizeof(MatDesc), hipMemcpyHostToDevice, p->stream);
   if (e != hipSuccess) return e;
-  e = gj_invert(p->stream, A, d_md, 1, (int)p->N, w2, nullptr);
+  e = gj_invert<double>(p->stream, A, d_md, 1, (int)p->N, w2, nullptr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(dense_matvec_kernel, dim3((unsigned)((p->N + 3) / 4), (unsigned)nrhs),
                      dim3(256), 0, p->stream, (const double2*)A, p->N, (const double2*)b, nrhs,

@@ -118,6 +118,7 @@ struct qax_problem {
   // self blocks (complex128 / complex64 pools)
   double* d_B = nullptr;
   double* d_Binv = nullptr;
+  bool inv64_ready = false;     // d_Binv holds the inverse of the current blocks
   float* d_Binv32 = nullptr;
 
   // pair-sum task tables per precision
@@ -227,7 +228,8 @@ hipError_t ensure_gemm_tasks(qax_problem* p);
 // dense.hip
 hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,
                               int nrhs, bool accumulate);
-hipError_t launch_invert_blocks(qax_problem* p, double* work);
+hipError_t launch_invert_blocks(qax_problem* p, double* work);     // FP32 inverse (mixed path)
+hipError_t launch_invert_blocks64(qax_problem* p, double* work);   // FP64 inverse
 hipError_t launch_convert_f32(hipStream_t s, const double* src, float* dst, int64_t count);
 hipError_t launch_dense_offdiag(qax_problem* p, double* A);
 
@@ -239,7 +241,8 @@ hipError_t launch_modal_modes(hipStream_t s, int n, const double* r, const doubl
 
 // krylov.hip
 hipError_t launch_rhs(qax_problem* p, const double* dirs_dev, int nrhs, double* out);
+int farfield_slots(int64_t M, int cu_count);
 hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const double* xhat_dev,
-                           int ndir, double* out);
+                           int ndir, int slots, double* partial, double* out);
 
 }  // namespace qax

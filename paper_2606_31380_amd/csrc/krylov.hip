@@ -10,6 +10,8 @@
 // reduced in a fixed order so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fastmath.h"
 #include "internal.h"
 #include "krylov.h"
@@ -40,59 +42,85 @@ hipError_t launch_rhs(qax_problem* p, const double* dirs_dev, int nrhs, double* 
   return hipGetLastError();
 }
 
+// out[e] = sum_s partial[s][e] (fixed order), from the pair-sum translation unit
+__global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slots, int64_t count,
+                                    double2* __restrict__ out, int accumulate);
+
 // u_inf[dir][r] = (1/4pi) sum_{n in problem 0} (-i k xhat.aw_n) e^{-i k xhat.y_n} mu[n][r]
-__global__ __launch_bounds__(256) void farfield_kernel(const double* __restrict__ pos,
-                                                       const double* __restrict__ aw,
-                                                       const double* __restrict__ ew, int form,
-                                                       int64_t N, int64_t n0, double k,
-                                                       const double2* __restrict__ mu, int nrhs,
-                                                       const double* __restrict__ xhat,
-                                                       double2* __restrict__ out) {
-  const int dir = blockIdx.x;
-  const int r = blockIdx.y;
-  const double hx = xhat[3 * dir], hy = xhat[3 * dir + 1], hz = xhat[3 * dir + 2];
+// (combined field: plus -i eta |aw_n| e^{...}; single layer: |aw_n| e^{...}
+// alone).  One direction per thread, node tiles staged in LDS and read by
+// broadcast, the node range cut into `slots` chunks (blockIdx.y) whose
+// partial sums are added in a fixed order afterwards; right-hand side
+// blockIdx.z.
+template <int TPB>
+__global__ __launch_bounds__(TPB) void farfield_kernel(
+    const double* __restrict__ xhat, int64_t M, const double* __restrict__ pos,
+    const double* __restrict__ aw, const double* __restrict__ ew, int form, int64_t N, int64_t n0,
+    int slots, double k, const double2* __restrict__ mu, int nrhs, double2* __restrict__ partial) {
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * TPB + tid;
+  const bool active = i < M;
+  const int r = blockIdx.z;
+  const double hx = active ? xhat[3 * i] : 0.0, hy = active ? xhat[3 * i + 1] : 0.0,
+               hz = active ? xhat[3 * i + 2] : 0.0;
+  const int64_t c0 = n0 * blockIdx.y / slots, c1 = n0 * (blockIdx.y + 1) / slots;
+  __shared__ double sx[TPB], sy[TPB], sz[TPB], sax[TPB], say[TPB], saz[TPB], sew[TPB];
+  __shared__ double2 smu[TPB];
   double ar = 0.0, ai = 0.0;
-  for (int64_t n = threadIdx.x; n < n0; n += 256) {
-    const double ph = -k * (hx * pos[n] + hy * pos[N + n] + hz * pos[2 * N + n]);
-    double s, c;
-    sincos_cw(ph, &s, &c);
-    const double nd = hx * aw[n] + hy * aw[N + n] + hz * aw[2 * N + n];
-    // (-i k nd) (c + i s) = k nd s - i k nd c; combined field adds
-    // (-i eta |aw|)(c + i s) = eta |aw| s - i eta |aw| c
-    // single layer: |aw| (c + i s)
-    double fr = k * nd * s, fi = -k * nd * c;
-    if (form == 2) {
-      fr = ew[n] * c;
-      fi = ew[n] * s;
-    } else if (form == 1) {
-      fr = fma(ew[n], s, fr);
-      fi = fma(-ew[n], c, fi);
-    }
-    const double2 m = mu[n * nrhs + r];
-    ar += fr * m.x - fi * m.y;
-    ai += fr * m.y + fi * m.x;
-  }
-  __shared__ double sr[256], si[256];
-  sr[threadIdx.x] = ar;
-  si[threadIdx.x] = ai;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sr[threadIdx.x] += sr[threadIdx.x + s];
-      si[threadIdx.x] += si[threadIdx.x + s];
+  for (int64_t base = c0; base < c1; base += TPB) {
+    const int cnt = (int)min((int64_t)TPB, c1 - base);
+    __syncthreads();
+    if (tid < cnt) {
+      const int64_t j = base + tid;
+      sx[tid] = pos[j]; sy[tid] = pos[N + j]; sz[tid] = pos[2 * N + j];
+      sax[tid] = aw[j]; say[tid] = aw[N + j]; saz[tid] = aw[2 * N + j];
+      sew[tid] = form ? ew[j] : 0.0;
+      smu[tid] = mu[j * nrhs + r];
     }
     __syncthreads();
+    for (int jj = 0; jj < cnt; ++jj) {
+      const double ph = -k * (hx * sx[jj] + hy * sy[jj] + hz * sz[jj]);
+      double s, c;
+      sincos_cw(ph, &s, &c);
+      double fr, fi;
+      if (form == 2) {
+        fr = sew[jj] * c;
+        fi = sew[jj] * s;
+      } else {
+        // (-i k nd)(c + i s) = k nd s - i k nd c; combined field adds
+        // (-i eta |aw|)(c + i s) = eta |aw| s - i eta |aw| c
+        const double nd = hx * sax[jj] + hy * say[jj] + hz * saz[jj];
+        fr = fma(k * nd, s, sew[jj] * s);
+        fi = -fma(k * nd, c, sew[jj] * c);
+      }
+      const double2 m = smu[jj];
+      ar += fr * m.x - fi * m.y;
+      ai += fr * m.y + fi * m.x;
+    }
   }
-  if (threadIdx.x == 0)
-    out[(int64_t)dir * nrhs + r] = make_double2(sr[0] * INV_FOUR_PI_K, si[0] * INV_FOUR_PI_K);
+  if (active)
+    partial[((int64_t)blockIdx.y * M + i) * nrhs + r] = make_double2(ar * INV_FOUR_PI_K, ai * INV_FOUR_PI_K);
 }
 
+int farfield_slots(int64_t M, int cu_count) {
+  const int64_t blocks = (M + 255) / 256;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(64, (8LL * cu_count + blocks - 1) / blocks));
+}
+
+// out[dir][r] (directions xhat_dev, 3 doubles each); partial: farfield_slots
+// x ndir x nrhs complex128.
 hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const double* xhat_dev,
-                           int ndir, double* out) {
+                           int ndir, int slots, double* partial, double* out) {
   const int64_t n0 = p->off[p->prob_body0[1]];
-  hipLaunchKernelGGL(farfield_kernel, dim3(ndir, nrhs), dim3(256), 0, p->stream, p->d_pos, p->d_aw,
-                     p->d_ew, p->form(), p->N, n0, p->k[0],
-                     (const double2*)mu, nrhs, xhat_dev, (double2*)out);
+  dim3 grid((unsigned)((ndir + 255) / 256), (unsigned)slots, (unsigned)nrhs);
+  hipLaunchKernelGGL((farfield_kernel<256>), grid, dim3(256), 0, p->stream, xhat_dev, (int64_t)ndir,
+                     p->d_pos, p->d_aw, p->d_ew, p->form(), p->N, n0, slots, p->k[0],
+                     (const double2*)mu, nrhs, (double2*)partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t count = (int64_t)ndir * nrhs;
+  hipLaunchKernelGGL(reduce_slots_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                     p->stream, (const double2*)partial, slots, count, (double2*)out, 0);
   return hipGetLastError();
 }
 

@@ -51,7 +51,12 @@ constexpr int NTH_MAX = 64;                   // largest n_theta
 constexpr int MQ_CAP = NTH_MAX / 2 + 2 + NF_CAP;   // highest Q index kept (82)
 constexpr int QB = 32;                        // nodes per recurrence batch
 constexpr int LD = 256;                       // direct-route azimuthal samples (FFT length)
-constexpr int NGO = 64;                       // outer Gauss-Legendre order
+// outer Gauss-Legendre order per side of the target: 48 on two or more
+// uniform panels (self-block entries converged to ~1e-14 there), 64 on a
+// single panel (the self panel is the whole curve) and on dyadically
+// refined curves (small end panels next to panels twice their length)
+constexpr int NGO = 64;
+constexpr int NGO_UNIFORM = 48;
 constexpr double CHI_SPLIT = 0.02;
 constexpr double NEAR_EXP = 40.0;   // smooth rule where 2N acosh(chi) >= 40 on the whole panel
 constexpr double INV_4PI = 0.0795774715459476678844;
@@ -574,8 +579,8 @@ __device__ __forceinline__ double lagrange_lane(double x, double xl, double bl) 
 }
 
 struct OuterRule {
-  double x[NGO];
-  double w[NGO];
+  double x[2][NGO];   // [0]: NGO_UNIFORM nodes (rest unused), [1]: NGO nodes
+  double w[2][NGO];
 };
 
 // Inverse DFT of the accumulated mode slots (S.acc) onto the Lagrange basis
@@ -732,10 +737,13 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   }
   const int nsides = (ip == pT) ? 2 : 1;
   for (int side = 0; side < nsides; ++side) {
-    // outer node `lane`: offset dl from tT and weight (u^5 substitution)
+    // outer node `lane` (lanes >= the rule's order idle): offset dl from tT
+    // and weight (u^5 substitution)
+    const int rk = (B.n_ref > 0 || B.n_uni < 2) ? 1 : 0;
+    const bool onode = lane < (rk ? NGO : NGO_UNIFORM);
     double dl, w;
     {
-      const double u = orule->x[lane], wu = orule->w[lane];
+      const double u = onode ? orule->x[rk][lane] : 0.5, wu = onode ? orule->w[rk][lane] : 0.0;
       const double u4 = u * u * u * u;
       if (ip == pT) {
         const double ell = (side == 0 ? e0 : e1) - tT;
@@ -751,7 +759,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     bool modal, wide;
     {
       const NodeLoc L = node_local(shape, a, cc, kappa, TG, dl);
-      modal = L.chim1 < CHI_SPLIT;
+      modal = onode && L.chim1 < CHI_SPLIT;
       // direct route: modes decay like e^{-acosh(chi) |m|} beyond the width of
       // the oscillatory factor (about k rho_max); 128 samples when the aliased
       // modes |m| >= 128 - N are below 1e-17 of the leading ones
@@ -792,7 +800,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     }
     // ---- direct route: trapezoidal rule on L azimuths of the kernel itself,
     // its modes by FFT
-    const unsigned long long dmask = ~mmask;
+    const unsigned long long dmask = ~mmask & __ballot(onode);
     const unsigned long long wmask = __ballot(wide);
     for (int q = 0; q < 64; ++q) {
       if (!((dmask >> q) & 1ull)) continue;
@@ -895,11 +903,14 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
 
 // ---------------------------------------------------------------- launch
 static void outer_rule_host(OuterRule& R) {
-  double x[NGO], w[NGO];
-  gauss_legendre_host(NGO, x, w);
-  for (int i = 0; i < NGO; ++i) {
-    R.x[i] = 0.5 * (x[i] + 1.0);
-    R.w[i] = 0.5 * w[i];
+  const int orders[2] = {NGO_UNIFORM, NGO};
+  for (int q = 0; q < 2; ++q) {
+    double x[NGO], w[NGO];
+    gauss_legendre_host(orders[q], x, w);
+    for (int i = 0; i < NGO; ++i) {
+      R.x[q][i] = i < orders[q] ? 0.5 * (x[i] + 1.0) : 0.5;
+      R.w[q][i] = i < orders[q] ? 0.5 * w[i] : 0.0;
+    }
   }
 }
 
