@@ -5,7 +5,8 @@ summary used by bench.py (HBM traffic per launch) and the markdown table.
 
 <dir> holds the sub-directories trace/ (--kernel-trace --stats), fetch/
 (--pmc FETCH_SIZE), write/ (--pmc WRITE_SIZE), valu32/ (F32 VALU instruction
-counters) and valu64/ (F64 VALU and MFMA counters), each with run_*.csv.  The
+counters), valu64/ (F64 VALU and MFMA counters) and, when present, mfma32/
+(SQ_INSTS_VALU_MFMA_MOPS_F32), each with run_*.csv.  The
 memory counters are scaled by what they read for the calibration kernel
 (y = 2 x over 2^27 doubles: 1 GiB read and 1 GiB written).  FLOP counts take
 64 lanes per VALU instruction and two flops per FMA; MFMA MOPS count 512
@@ -32,7 +33,7 @@ KINDS = {
     "block_apply": (r"qax::block_gemv_kernel<double, 1, \d>", "paper_2606_31380_amd/csrc/dense.hip"),
     "block_apply_f32": (r"qax::block_gemv_kernel<float, 1, \d>", "paper_2606_31380_amd/csrc/dense.hip"),
     "self_assembly": (r"qax::assemble_self_kernel<0>", "paper_2606_31380_amd/csrc/selfblock.hip"),
-    "invert_update": (r"qax::gjm_update_kernel", "paper_2606_31380_amd/csrc/dense.hip"),
+    "invert_update": (r"qax::gjm_update_kernel<float>", "paper_2606_31380_amd/csrc/dense.hip"),
 }
 
 
@@ -66,6 +67,8 @@ def main(d, out_json, out_md):
     write = load_counters(os.path.join(d, "write", "run_counter_collection.csv"))
     v32 = load_counters(os.path.join(d, "valu32", "run_counter_collection.csv"))
     v64 = load_counters(os.path.join(d, "valu64", "run_counter_collection.csv"))
+    m32_path = os.path.join(d, "mfma32", "run_counter_collection.csv")
+    m32 = load_counters(m32_path) if os.path.exists(m32_path) else {}
     cal = next(k for k in fetch if "MulFunctor" in k)
     f_fetch = CAL_BYTES / (fetch[cal]["FETCH_SIZE"] * 1024)
     f_write = CAL_BYTES / (write[cal]["WRITE_SIZE"] * 1024)
@@ -84,6 +87,7 @@ def main(d, out_json, out_md):
             "valu_insts": g.get("SQ_INSTS_VALU", 0.0), "valu_trans_f32": g.get("SQ_INSTS_VALU_TRANS_F32", 0.0),
             "f32_flop": f32, "f64_flop": f64,
             "mfma_f64_flop": 512 * h.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0),
+            "mfma_f32_flop": 512 * m32.get(k, {}).get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0),
         }
 
     out = {"calibration": {"kernel": cal, "bytes_read": CAL_BYTES, "bytes_written": CAL_BYTES,
@@ -98,15 +102,15 @@ def main(d, out_json, out_md):
     with open(out_json, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
-    lines = ["| kernel | calls | avg us | HBM read MB | HBM write MB | VALU insts | F32 flop | F64 flop | MFMA F64 flop |",
-             "|---|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    lines = ["| kernel | calls | avg us | HBM read MB | HBM write MB | VALU insts | F32 flop | F64 flop | MFMA F64 flop | MFMA F32 flop |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
     for k in sorted(trace, key=lambda k: -trace[k][0] * trace[k][1]):
         if k not in fetch:
             continue
         r = row(k)
         lines.append(f"| `{k[:70]}` | {r['calls']} | {r['avg_us']:.1f} | {r['fetch_bytes'] / 1e6:.2f} | "
                      f"{r['write_bytes'] / 1e6:.2f} | {r['valu_insts']:.3e} | {r['f32_flop']:.3e} | "
-                     f"{r['f64_flop']:.3e} | {r['mfma_f64_flop']:.3e} |")
+                     f"{r['f64_flop']:.3e} | {r['mfma_f64_flop']:.3e} | {r['mfma_f32_flop']:.3e} |")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(f"calibration factors: FETCH_SIZE x{f_fetch:.4f}, WRITE_SIZE x{f_write:.4f}")
