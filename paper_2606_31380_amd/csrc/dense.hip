@@ -19,17 +19,18 @@
 namespace qax {
 
 // ---------------------------------------------------------------- block apply
-// One wavefront per row; each lane loads VEC consecutive complex entries per
-// step (block orders are multiples of 16, so rows split evenly).
-template <typename MT, int NRC, int VEC>
+// LPR lanes per row (64: one wavefront per row; 32 or 16 for short rows, two
+// or four rows per wavefront); each lane loads VEC consecutive complex entries
+// per step (block orders are multiples of 16).
+template <typename MT, int NRC, int VEC, int LPR = 64>
 __global__ __launch_bounds__(256) void block_gemv_kernel(
     const BodyDev* __restrict__ bodies, const BlockDev* __restrict__ blocks,
     const int32_t* __restrict__ node_body, const MT* __restrict__ pool, int64_t N,
     const double2* __restrict__ v, int nrhs, double2* __restrict__ out, int accumulate,
     const int32_t* __restrict__ seg_active) {
   typedef MT vec_t __attribute__((ext_vector_type(2 * VEC)));
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & (LPR - 1);
+  const int64_t row = (int64_t)blockIdx.x * (256 / LPR) + (threadIdx.x / LPR);
   const int rc0 = blockIdx.y * NRC;
   if (row >= N) return;
   const int b = node_body[row];
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(256) void block_gemv_kernel(
   double ar[NRC], ai[NRC];
 #pragma unroll
   for (int r = 0; r < NRC; ++r) { ar[r] = 0.0; ai[r] = 0.0; }
-  for (int j0 = lane * VEC; j0 < n; j0 += 64 * VEC) {
+  for (int j0 = lane * VEC; j0 < n; j0 += LPR * VEC) {
     const vec_t av = *(const vec_t*)(a + 2 * j0);
 #pragma unroll
     for (int q = 0; q < VEC; ++q) {
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(256) void block_gemv_kernel(
 #pragma unroll
   for (int r = 0; r < NRC; ++r) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int off = LPR / 2; off > 0; off >>= 1) {
       ar[r] += __shfl_xor(ar[r], off);
       ai[r] += __shfl_xor(ai[r], off);
     }
@@ -276,28 +277,40 @@ hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double
 // Block-diagonal products over caller-built tables (the lattice apply's
 // per-frequency matrices): rows = sum of the orders, every order a multiple
 // of 16.
+template <typename MT, int NRC, int VEC, int LPR>
+static void gemv_tables_launch(hipStream_t s, const BodyDev* bodies, const BlockDev* blocks,
+                               const int32_t* node_body, const void* pool, int64_t rows,
+                               const double2* v, int nrhs, double2* out, int acc) {
+  dim3 grid((unsigned)((rows + 256 / LPR - 1) / (256 / LPR)), (unsigned)((nrhs + NRC - 1) / NRC));
+  hipLaunchKernelGGL((block_gemv_kernel<MT, NRC, VEC, LPR>), grid, dim3(256), 0, s, bodies, blocks,
+                     node_body, (const MT*)pool, rows, v, nrhs, out, acc, nullptr);
+}
+
+template <typename MT, int NRC, int VEC>
+static void gemv_tables_lpr(hipStream_t s, const BodyDev* bodies, const BlockDev* blocks,
+                            const int32_t* node_body, const void* pool, int64_t rows, int order,
+                            const double2* v, int nrhs, double2* out, int acc) {
+  // short rows: up to four loads per lane, several rows per wavefront
+  if (order <= 64 * VEC)
+    gemv_tables_launch<MT, NRC, VEC, 16>(s, bodies, blocks, node_body, pool, rows, v, nrhs, out, acc);
+  else if (order <= 128 * VEC)
+    gemv_tables_launch<MT, NRC, VEC, 32>(s, bodies, blocks, node_body, pool, rows, v, nrhs, out, acc);
+  else
+    gemv_tables_launch<MT, NRC, VEC, 64>(s, bodies, blocks, node_body, pool, rows, v, nrhs, out, acc);
+}
+
 hipError_t launch_gemv_tables(hipStream_t s, const BodyDev* bodies, const BlockDev* blocks,
                               const int32_t* node_body, const void* pool, bool f32, int64_t rows,
-                              const double* v, int nrhs, double* out, bool accumulate) {
-  const int nrc = nrhs == 1 ? 1 : 4;
-  dim3 grid((unsigned)((rows + 3) / 4), (unsigned)((nrhs + nrc - 1) / nrc));
+                              int order, const double* v, int nrhs, double* out, bool accumulate) {
   const double2* vv = (const double2*)v;
   double2* oo = (double2*)out;
   const int acc = accumulate ? 1 : 0;
   if (f32) {
-    if (nrc == 1)
-      hipLaunchKernelGGL((block_gemv_kernel<float, 1, 2>), grid, dim3(256), 0, s, bodies, blocks,
-                         node_body, (const float*)pool, rows, vv, nrhs, oo, acc, nullptr);
-    else
-      hipLaunchKernelGGL((block_gemv_kernel<float, 4, 1>), grid, dim3(256), 0, s, bodies, blocks,
-                         node_body, (const float*)pool, rows, vv, nrhs, oo, acc, nullptr);
+    if (nrhs == 1) gemv_tables_lpr<float, 1, 2>(s, bodies, blocks, node_body, pool, rows, order, vv, nrhs, oo, acc);
+    else gemv_tables_lpr<float, 4, 1>(s, bodies, blocks, node_body, pool, rows, order, vv, nrhs, oo, acc);
   } else {
-    if (nrc == 1)
-      hipLaunchKernelGGL((block_gemv_kernel<double, 1, 1>), grid, dim3(256), 0, s, bodies, blocks,
-                         node_body, (const double*)pool, rows, vv, nrhs, oo, acc, nullptr);
-    else
-      hipLaunchKernelGGL((block_gemv_kernel<double, 4, 1>), grid, dim3(256), 0, s, bodies, blocks,
-                         node_body, (const double*)pool, rows, vv, nrhs, oo, acc, nullptr);
+    if (nrhs == 1) gemv_tables_lpr<double, 1, 1>(s, bodies, blocks, node_body, pool, rows, order, vv, nrhs, oo, acc);
+    else gemv_tables_lpr<double, 4, 1>(s, bodies, blocks, node_body, pool, rows, order, vv, nrhs, oo, acc);
   }
   return hipGetLastError();
 }

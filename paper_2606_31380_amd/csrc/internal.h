@@ -206,7 +206,7 @@ size_t lattice_work_bytes(const qax_problem* p, int nrhs);
 // dense.hip: block-diagonal products over explicit tables
 hipError_t launch_gemv_tables(hipStream_t s, const BodyDev* bodies, const BlockDev* blocks,
                               const int32_t* node_body, const void* pool, bool f32, int64_t rows,
-                              const double* v, int nrhs, double* out, bool accumulate);
+                              int order, const double* v, int nrhs, double* out, bool accumulate);
 hipError_t launch_gemm_tables(hipStream_t s, const GemmTask* tasks, int ntasks,
                               const BodyDev* bodies, const BlockDev* blocks, const void* pool,
                               bool f32, const double* v, int nrhs, double* out, bool accumulate);

@@ -329,7 +329,7 @@ hipError_t launch_lattice_apply(qax_problem* p, int prec, const double* mu, doub
     e = launch_gemm_tables(s, t.d_ftasks, t.nftasks, t.d_fbodies, t.d_fblocks, pool, f32,
                            (const double*)W1, nrhs, (double*)W2, false);
   else
-    e = launch_gemv_tables(s, t.d_fbodies, t.d_fblocks, t.d_frow, pool, f32, t.F * t.nb,
+    e = launch_gemv_tables(s, t.d_fbodies, t.d_fblocks, t.d_frow, pool, f32, t.F * t.nb, t.nb,
                            (const double*)W1, nrhs, (double*)W2, false);
   timing_end(p, kind);
   if (e != hipSuccess) return e;
