@@ -91,6 +91,84 @@ __global__ __launch_bounds__(256) void block_gemv_kernel(
   }
 }
 
+// FP32 matrix, one right-hand side: GV_ROWS rows of one block per workgroup
+// (four per wavefront), the block's input vector staged in LDS in chunks of
+// GV_CH entries and shared by those rows.  The matrix streams from HBM once;
+// the FP64 vector (twice the bytes of an FP32 matrix entry) is read once per
+// GV_ROWS rows instead of once per row.  Blocks (orders multiples of 16) and
+// their offsets are multiples of GV_ROWS, so a workgroup never spans two.
+constexpr int GV_ROWS = 16, GV_CH = 2048;
+
+template <int VEC>
+__global__ __launch_bounds__(256) void block_gemv_f32_lds_kernel(
+    const BodyDev* __restrict__ bodies, const BlockDev* __restrict__ blocks,
+    const int32_t* __restrict__ node_body, const float* __restrict__ pool, int64_t N,
+    const double2* __restrict__ v, double2* __restrict__ out, int accumulate,
+    const int32_t* __restrict__ seg_active) {
+  typedef float vec_t __attribute__((ext_vector_type(2 * VEC)));
+  __shared__ double2 vs[GV_CH];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * GV_ROWS;
+  if (row0 >= N) return;
+  const BodyDev& B = bodies[node_body[row0]];
+  if (seg_active && seg_active[B.problem] == 0) {
+    // a converged lockstep segment: its input is zero, so is the output
+    if (!accumulate && threadIdx.x < GV_ROWS) out[row0 + threadIdx.x] = make_double2(0.0, 0.0);
+    return;
+  }
+  const BlockDev& K = blocks[B.block];
+  const int n = K.n;
+  const double2* vb = v + B.off;
+  double ar[GV_ROWS / 4], ai[GV_ROWS / 4];
+#pragma unroll
+  for (int q = 0; q < GV_ROWS / 4; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
+  for (int c0 = 0; c0 < n; c0 += GV_CH) {
+    const int cn = min(GV_CH, n - c0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < cn; q += 256) vs[q] = vb[c0 + q];
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < GV_ROWS / 4; ++rr) {
+      const int64_t lr = row0 + wave * (GV_ROWS / 4) + rr - B.off;
+      const float* a = pool + 2 * (K.elem_off + lr * n + c0);
+      for (int j0 = lane * VEC; j0 < cn; j0 += 64 * VEC) {
+        const vec_t av = *(const vec_t*)(a + 2 * j0);
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) {
+          const double mr = (double)av[2 * q], mi = (double)av[2 * q + 1];
+          const double2 x = vs[j0 + q];
+          ar[rr] += mr * x.x - mi * x.y;
+          ai[rr] += mr * x.y + mi * x.x;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int rr = 0; rr < GV_ROWS / 4; ++rr) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      ar[rr] += __shfl_xor(ar[rr], off);
+      ai[rr] += __shfl_xor(ai[rr], off);
+    }
+    if (lane == 0) {
+      const int64_t row = row0 + wave * (GV_ROWS / 4) + rr;
+      double2 o = accumulate ? out[row] : make_double2(0.0, 0.0);
+      o.x += ar[rr];
+      o.y += ai[rr];
+      out[row] = o;
+    }
+  }
+}
+
+template <int VEC>
+static void gemv_f32_lds_launch(hipStream_t s, const BodyDev* bodies, const BlockDev* blocks,
+                                const int32_t* node_body, const float* pool, int64_t N,
+                                const double* v, double* out, bool acc, const int32_t* seg_active) {
+  hipLaunchKernelGGL((block_gemv_f32_lds_kernel<VEC>), dim3((unsigned)((N + GV_ROWS - 1) / GV_ROWS)),
+                     dim3(256), 0, s, bodies, blocks, node_body, pool, N, (const double2*)v,
+                     (double2*)out, acc ? 1 : 0, seg_active);
+}
+
 template <typename MT, int NRC, int VEC>
 static void gemv_launch(qax_problem* p, const MT* pool, const double* v, double* out, int nrhs,
                         bool acc) {
@@ -117,9 +195,15 @@ hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const doubl
   if (inverse && prec == QAX_MIXED) {
     const float* pool = p->d_Binv32;
     if (nrhs > 1) gemv_launch<float, 4, 1>(p, pool, v, out, nrhs, accumulate);
-    else if (p->tune.gemv_vec[1] == 4) gemv_launch<float, 1, 4>(p, pool, v, out, nrhs, accumulate);
-    else if (p->tune.gemv_vec[1] == 2) gemv_launch<float, 1, 2>(p, pool, v, out, nrhs, accumulate);
-    else gemv_launch<float, 1, 1>(p, pool, v, out, nrhs, accumulate);
+    else if (p->tune.gemv_vec[1] == 4)
+      gemv_f32_lds_launch<4>(p->stream, p->d_bodies, p->d_blocks, p->d_node_body, pool, p->N, v, out,
+                             accumulate, p->seg_active);
+    else if (p->tune.gemv_vec[1] == 2)
+      gemv_f32_lds_launch<2>(p->stream, p->d_bodies, p->d_blocks, p->d_node_body, pool, p->N, v, out,
+                             accumulate, p->seg_active);
+    else
+      gemv_f32_lds_launch<1>(p->stream, p->d_bodies, p->d_blocks, p->d_node_body, pool, p->N, v, out,
+                             accumulate, p->seg_active);
   } else {
     const double* pool = inverse ? p->d_Binv : p->d_B;
     if (nrhs > 1) gemv_launch<double, 4, 1>(p, pool, v, out, nrhs, accumulate);
@@ -306,7 +390,10 @@ hipError_t launch_gemv_tables(hipStream_t s, const BodyDev* bodies, const BlockD
   double2* oo = (double2*)out;
   const int acc = accumulate ? 1 : 0;
   if (f32) {
-    if (nrhs == 1) gemv_tables_lpr<float, 1, 2>(s, bodies, blocks, node_body, pool, rows, order, vv, nrhs, oo, acc);
+    if (nrhs == 1 && order > 128 * 2)
+      gemv_f32_lds_launch<2>(s, bodies, blocks, node_body, (const float*)pool, rows, v, out, accumulate,
+                             nullptr);
+    else if (nrhs == 1) gemv_tables_lpr<float, 1, 2>(s, bodies, blocks, node_body, pool, rows, order, vv, nrhs, oo, acc);
     else gemv_tables_lpr<float, 4, 1>(s, bodies, blocks, node_body, pool, rows, order, vv, nrhs, oo, acc);
   } else {
     if (nrhs == 1) gemv_tables_lpr<double, 1, 1>(s, bodies, blocks, node_body, pool, rows, order, vv, nrhs, oo, acc);
