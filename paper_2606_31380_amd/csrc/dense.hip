@@ -513,7 +513,7 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
   }
 #pragma unroll
   for (int kk = 0; kk < WL; ++kk) {
-    if (kk >= w) break;
+    if (kk >= w) continue;   // (uniform; keeps the loop fully unrolled)
     const int k = c0 + kk;
     T bv = -1;
     int bi = n;
@@ -811,23 +811,29 @@ static int gj_leaf_rows(int nmax) {
   return r;
 }
 
-static int gj_leaf_cols(int nmax) { return gj_leaf_rows(nmax) == 1 ? 8 : 16 / gj_leaf_rows(nmax); }
+// FP32 leaves hold twice the columns in the same registers (fewer recursion
+// steps per panel)
+template <typename T>
+static int gj_leaf_cols(int nmax) {
+  const int c = gj_leaf_rows(nmax) == 1 ? 8 : 16 / gj_leaf_rows(nmax);
+  return sizeof(T) == 4 ? 2 * c : c;
+}
 
 template <typename T>
 static void launch_leaf(hipStream_t s, typename Cx<T>::V* pool, const MatDesc* d_mats, int batch,
                         int nmax, int c0, int w, int32_t* piv) {
   switch (gj_leaf_rows(nmax)) {
     case 1:
-      hipLaunchKernelGGL((gjr_leaf_kernel<T, 1, 8>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      hipLaunchKernelGGL((gjr_leaf_kernel<T, 1, sizeof(T) == 4 ? 16 : 8>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
       break;
     case 2:
-      hipLaunchKernelGGL((gjr_leaf_kernel<T, 2, 8>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      hipLaunchKernelGGL((gjr_leaf_kernel<T, 2, sizeof(T) == 4 ? 16 : 8>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
       break;
     case 4:
-      hipLaunchKernelGGL((gjr_leaf_kernel<T, 4, 4>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      hipLaunchKernelGGL((gjr_leaf_kernel<T, 4, sizeof(T) == 4 ? 8 : 4>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
       break;
     default:
-      hipLaunchKernelGGL((gjr_leaf_kernel<T, 8, 2>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
+      hipLaunchKernelGGL((gjr_leaf_kernel<T, 8, sizeof(T) == 4 ? 4 : 2>), dim3(batch), dim3(1024), 0, s, d_mats, pool, c0, w, piv, nmax);
       break;
   }
 }
@@ -838,7 +844,7 @@ static void launch_leaf(hipStream_t s, typename Cx<T>::V* pool, const MatDesc* d
 template <typename T>
 static void gj_factor_panel(hipStream_t s, typename Cx<T>::V* pool, const MatDesc* d_mats, int batch,
                             int nmax, int c0, int w, int32_t* piv, typename Cx<T>::V* Wn) {
-  if (w <= gj_leaf_cols(nmax)) {
+  if (w <= gj_leaf_cols<T>(nmax)) {
     launch_leaf<T>(s, pool, d_mats, batch, nmax, c0, w, piv);
     return;
   }
