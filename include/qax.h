@@ -146,7 +146,8 @@ qax_status qax_pair_sum(qax_problem* p, qax_prec prec, const void* d_mu, void* d
 
 /* Block-diagonal apply: d_out_b = M_b d_v_b for every body, M_b = B_b
  * (inverse == 0) or B_b^-1 (inverse != 0); prec QAX_MIXED uses the FP32
- * inverse with FP64 accumulation.  N x nrhs complex128. */
+ * blocks (B rounded to FP32, or the FP32 inverse) with FP64 accumulation.
+ * N x nrhs complex128. */
 qax_status qax_block_apply(qax_problem* p, int32_t inverse, qax_prec prec,
                            const void* d_v, void* d_out, int32_t nrhs);
 
@@ -161,7 +162,8 @@ qax_status qax_rhs(qax_problem* p, const double* dirs, int32_t nrhs, void* d_out
  * right-preconditioned restarted GMRES with the block-diagonal preconditioner
  * (Section 6).  QAX_FP64: FP64 throughout.  QAX_MIXED: FP64 iterative
  * refinement around an inner GMRES whose operator applies the FP32 pair sum
- * and the FP32 inverse blocks; residuals and orthogonalisation stay FP64.
+ * and the FP32 blocks (B and its inverse); residuals and orthogonalisation
+ * stay FP64.
  * Stops when ||b - A mu|| / ||b|| <= tol for every right-hand side and
  * problem; otherwise returns QAX_ERR_NOCONV after maxit inner iterations with
  * the best iterate in d_mu_out and info filled.  Single-problem, single-body

@@ -162,12 +162,13 @@ extern "C" qax_status qax_create(int device, void* hip_stream, qax_problem** out
 static void free_geometry(qax_problem* p) {
   void* ptrs[] = {p->d_bodies, p->d_blocks, p->d_node_body, p->d_pos,  p->d_aw,
                   p->d_loc32,  p->d_aw32,   p->d_gl,        p->d_B,    p->d_Binv,
-                  p->d_Binv32, p->d_tasks64, p->d_tasks32, p->d_ew, p->d_ew32};
+                  p->d_Binv32, p->d_tasks64, p->d_tasks32, p->d_ew, p->d_ew32, p->d_B32};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   p->d_bodies = nullptr; p->d_blocks = nullptr; p->d_node_body = nullptr;
   p->d_pos = nullptr; p->d_aw = nullptr; p->d_loc32 = nullptr; p->d_aw32 = nullptr;
   p->d_gl = nullptr; p->d_B = nullptr; p->d_Binv = nullptr; p->d_Binv32 = nullptr;
+  p->d_B32 = nullptr;
   p->d_tasks64 = nullptr; p->d_tasks32 = nullptr;
   p->d_ew = nullptr; p->d_ew32 = nullptr;
   if (p->d_gemm_tasks) (void)hipFree(p->d_gemm_tasks);
@@ -456,6 +457,7 @@ extern "C" qax_status qax_assemble_self(qax_problem* p, double* t_setup_s) {
     QCHECK(hipMalloc(&p->d_B, (size_t)p->block_elems * 16), "alloc self blocks");
     QCHECK(hipMalloc(&p->d_Binv, (size_t)p->block_elems * 16), "alloc inverse blocks");
     QCHECK(hipMalloc(&p->d_Binv32, (size_t)p->block_elems * 8), "alloc inverse blocks fp32");
+    QCHECK(hipMalloc(&p->d_B32, (size_t)p->block_elems * 8), "alloc self blocks fp32");
   }
   QCHECK(launch_assemble_self(p), "assemble_self");
   QBUF(work, double, "gj_work", invert_blocks_work_bytes(p));
@@ -762,22 +764,31 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
   std::vector<double> bnorm(nseg);
   for (int s = 0; s < nseg; ++s) bnorm[s] = std::sqrt(std::max(hh[s].real(), 0.0));
 
-  // One Arnoldi step j for all segments: z = M^-1 v_j, w = v_j + D_off z,
+  // One Arnoldi step j for all segments: z = M^-1 v_j, w = v_j + D_off z
+  // (mixed, cycles that must reduce the residual by more than 1e3: w = B z +
+  // D_off z with the FP32 copies, since the FP32 inverse is only accurate to
+  // ~1e-5 and B M^-1 v = v would cap the cycle's gain there),
   // classical Gram-Schmidt twice, |w|^2, the Givens update on the device,
   // v_{j+1} = w / h_{j+1,j}, and the step's count of unconverged segments
   // copied to pinned host memory.  Enqueued directly, or captured once per j
   // into an executable graph and replayed.
   double* h1 = hd;
   double* h2 = hd + (size_t)(m + 2) * nseg * 2;
+  bool exact_op = false;
   auto enqueue_step = [&](int j) -> hipError_t {
     double* Vj = V + (size_t)j * vs;
     double* Vn = V + (size_t)(j + 1) * vs;
     p->seg_active = G.active;   // operator work of stopped segments is skipped
     hipError_t e = launch_block_apply(p, 1, inner_prec, Vj, t, nrhs, false);
-    if (e == hipSuccess) e = launch_pair_sum(p, inner_prec, t, w, nrhs, ppart, false);
+    if (exact_op) {
+      if (e == hipSuccess) e = launch_block_apply(p, 0, QAX_MIXED, t, w, nrhs, false);
+      if (e == hipSuccess) e = launch_pair_sum(p, inner_prec, t, w, nrhs, ppart, true);
+    } else {
+      if (e == hipSuccess) e = launch_pair_sum(p, inner_prec, t, w, nrhs, ppart, false);
+    }
     p->seg_active = nullptr;
     if (e != hipSuccess) return e;
-    K.axpby(1.0, w, 1.0, Vj, w);
+    if (!exact_op) K.axpby(1.0, w, 1.0, Vj, w);
     K.dots(V, vs, j + 1, w, h1);
     K.orth(V, vs, j + 1, h1, w);
     K.dots(V, vs, j + 1, w, h2);
@@ -803,14 +814,16 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
       p->graphs.clear();
       p->graph_key = key;
     }
-    if ((int)p->graphs.size() < m) p->graphs.resize(m, nullptr);
+    // one graph per step index and operator form
+    if ((int)p->graphs.size() < 2 * m) p->graphs.resize(2 * m, nullptr);
   }
   auto run_step = [&](int j) -> qax_status {
     if (!graphs) {
       QCHECK(enqueue_step(j), "gmres step");
       return QAX_OK;
     }
-    if (!p->graphs[j]) {
+    const int gi = (exact_op ? m : 0) + j;
+    if (!p->graphs[gi]) {
       // capture on the handle's own stream (the caller's may be the legacy
       // default stream, which cannot be captured); replays go to the caller's
       if (!p->cap_stream)
@@ -829,9 +842,9 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
       const hipError_t e3 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
       (void)hipGraphDestroy(gr);
       QCHECK(e3, "instantiate graph");
-      p->graphs[j] = ex;
+      p->graphs[gi] = ex;
     }
-    QCHECK(hipGraphLaunch(p->graphs[j], p->stream), "graph launch");
+    QCHECK(hipGraphLaunch(p->graphs[gi], p->stream), "graph launch");
     return QAX_OK;
   };
 
@@ -865,9 +878,11 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
     std::vector<double> par(2 * nseg);
     std::vector<int32_t> fz(3 * nseg + m + 1, 0);   // frozen, active, kconv, notdone
     std::vector<cplx> g0((size_t)nseg * (m + 1), 0.0), scl(nseg);
+    double min_need = 1.0;
     for (int s = 0; s < nseg; ++s) {
       const bool frozen = !(rn[s] > 0) || (bnorm[s] > 0 && rn[s] <= tol * bnorm[s]);
       const double need = bnorm[s] > 0 && rn[s] > 0 ? 0.5 * tol * bnorm[s] / rn[s] : 1.0;
+      if (!frozen) min_need = std::min(min_need, need);
       par[s] = rn[s];
       par[nseg + s] = prec == QAX_MIXED ? std::max(need, 2e-5) : need;
       fz[s] = frozen ? 1 : 0;
@@ -880,6 +895,9 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
     QCHECK(hipMemcpyAsync(G.g, g0.data(), g0.size() * 16, hipMemcpyHostToDevice, p->stream), "copy");
     QCHECK(hipMemcpyAsync(G.scl, scl.data(), nseg * 16, hipMemcpyHostToDevice, p->stream), "copy");
     K.scale(r, (const double*)G.scl, V);
+    // the first cycle aims at the FP32 floor anyway; later ones that must
+    // gain more than 1e3 use the exact operator form
+    exact_op = prec == QAX_MIXED && outer > 0 && min_need < 1e-3;
     int j = 0;
     for (; j < m && total_its < maxit; ++j) {
       if ((st = run_step(j)) != QAX_OK) return st;

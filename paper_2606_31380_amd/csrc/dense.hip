@@ -183,7 +183,7 @@ hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double
 
 hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,
                               int nrhs, bool accumulate) {
-  const int kind = (inverse && prec == QAX_MIXED) ? QAX_K_BLOCK_APPLY_F32 : QAX_K_BLOCK_APPLY;
+  const int kind = prec == QAX_MIXED ? QAX_K_BLOCK_APPLY_F32 : QAX_K_BLOCK_APPLY;
   if (nrhs >= 4) {
     // several right-hand sides: batched complex GEMM on the matrix cores
     timing_begin(p, kind);
@@ -192,8 +192,8 @@ hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const doubl
     return e;
   }
   timing_begin(p, kind);
-  if (inverse && prec == QAX_MIXED) {
-    const float* pool = p->d_Binv32;
+  if (prec == QAX_MIXED) {
+    const float* pool = inverse ? p->d_Binv32 : p->d_B32;
     if (nrhs > 1) gemv_launch<float, 4, 1>(p, pool, v, out, nrhs, accumulate);
     else if (p->tune.gemv_vec[1] == 4)
       gemv_f32_lds_launch<4>(p->stream, p->d_bodies, p->d_blocks, p->d_node_body, pool, p->N, v, out,
@@ -349,9 +349,9 @@ hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double
   if (e != hipSuccess) return e;
   dim3 grid((unsigned)p->gemm_tasks.size(), (unsigned)((2 * nrhs + 63) / 64));
   const GemmTask* t = (const GemmTask*)p->d_gemm_tasks;
-  if (inverse && prec == QAX_MIXED)
+  if (prec == QAX_MIXED)
     hipLaunchKernelGGL(block_gemm_kernel<float>, grid, dim3(256), 0, p->stream, t, p->d_bodies,
-                       p->d_blocks, p->d_Binv32, v, nrhs, out, accumulate ? 1 : 0);
+                       p->d_blocks, inverse ? p->d_Binv32 : p->d_B32, v, nrhs, out, accumulate ? 1 : 0);
   else
     hipLaunchKernelGGL(block_gemm_kernel<double>, grid, dim3(256), 0, p->stream, t, p->d_bodies,
                        p->d_blocks, inverse ? p->d_Binv : p->d_B, v, nrhs, out, accumulate ? 1 : 0);
@@ -918,7 +918,10 @@ hipError_t launch_invert_blocks(qax_problem* p, double* work) {
   double* w2;
   int nmax;
   p->inv64_ready = false;
-  hipError_t e = launch_convert_f32(p->stream, p->d_B, p->d_Binv32, p->block_elems * 2);
+  hipError_t e = launch_convert_f32(p->stream, p->d_B, p->d_B32, p->block_elems * 2);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->d_Binv32, p->d_B32, (size_t)p->block_elems * 8, hipMemcpyDeviceToDevice,
+                       p->stream);
   if (e == hipSuccess) e = upload_mats(p, work, &d_md, &w2, &nmax);
   if (e != hipSuccess) return e;
   timing_begin(p, QAX_K_INVERT);

@@ -120,6 +120,7 @@ struct qax_problem {
   double* d_Binv = nullptr;
   bool inv64_ready = false;     // d_Binv holds the inverse of the current blocks
   float* d_Binv32 = nullptr;
+  float* d_B32 = nullptr;       // B rounded to FP32 (the mixed path's operator blocks)
 
   // pair-sum task tables per precision
   std::vector<qax::PairTask> tasks64, tasks32;
