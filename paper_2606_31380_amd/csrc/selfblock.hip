@@ -550,6 +550,19 @@ __device__ NodeLoc node_local(int shape, double a, double c, double kappa, const
   return L;
 }
 
+// The node held by lane `src` (uniform), broadcast to the wavefront.
+__device__ __forceinline__ NodeLoc read_node(const NodeLoc& v, int src) {
+  NodeLoc o;
+  o.r = readlane_f64(v.r, src); o.dr = readlane_f64(v.dr, src); o.dz = readlane_f64(v.dz, src);
+  o.dp = readlane_f64(v.dp, src); o.dq = readlane_f64(v.dq, src); o.rt = readlane_f64(v.rt, src);
+  o.alpha = readlane_f64(v.alpha, src); o.c = readlane_f64(v.c, src);
+  o.chim1 = readlane_f64(v.chim1, src); o.rmrt = readlane_f64(v.rmrt, src);
+  o.z = readlane_f64(v.z, src); o.p = readlane_f64(v.p, src); o.q = readlane_f64(v.q, src);
+  o.w = 0.0;
+  o.s = readlane_f64(v.s, src);
+  return o;
+}
+
 __device__ __forceinline__ NodeLoc shfl_node(const NodeLoc& v, int src) {
   NodeLoc o;
   o.r = __shfl(v.r, src); o.dr = __shfl(v.dr, src); o.dz = __shfl(v.dz, src);
@@ -756,9 +769,12 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         w = fabs(far - end) * 5.0 * u4 * wu;
       }
     }
+    // the lane's own node, computed once and broadcast to the wavefront when
+    // the node is processed
+    const NodeLoc Lme = node_local(shape, a, cc, kappa, TG, dl);
     bool modal, wide;
     {
-      const NodeLoc L = node_local(shape, a, cc, kappa, TG, dl);
+      const NodeLoc& L = Lme;
       modal = onode && L.chim1 < CHI_SPLIT;
       // direct route: modes decay like e^{-acosh(chi) |m|} beyond the width of
       // the oscillatory factor (about k rho_max); 128 samples when the aliased
@@ -778,17 +794,15 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     for (int b0 = 0; b0 < nmodal; b0 += QB) {
       const bool qlane = lane < QB && b0 + lane < nmodal;
       const int src = qlane ? S.modal_idx[b0 + lane] : 0;
-      const double dls = __shfl(dl, src);
-      double qchim1 = 1.0;
-      if (qlane) qchim1 = node_local(shape, a, cc, kappa, TG, dls).chim1;
+      const double cm1 = __shfl(Lme.chim1, src);
+      const double qchim1 = qlane ? cm1 : 1.0;
       toroidal_q_batch(qlane, 1.0 + qchim1, qchim1, MQ_CAP, S.Q, lane & (QB - 1));
       __syncthreads();
       const int cnt = min(QB, nmodal - b0);
       for (int q = 0; q < cnt; ++q) {
-        const int sl = S.modal_idx[b0 + q];
-        const double dlq = __shfl(dl, sl);
-        const double wq = __shfl(w, sl);
-        const NodeLoc Ln = node_local(shape, a, cc, kappa, TG, dlq);
+        const int sl = __builtin_amdgcn_readfirstlane(S.modal_idx[b0 + q]);
+        const double wq = readlane_f64(w, sl);
+        const NodeLoc Ln = read_node(Lme, sl);
         modal_modes<CF>(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.tw);
         double2 ks;
         const double2 Kq = modal_slot<CF>(N, Ln, S.u.m, ks);
@@ -807,10 +821,12 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       const bool w256 = (wmask >> q) & 1ull;
       const int L = w256 ? LD : LD / 2;
       const int tstep = LD / L;
-      const double dlq = __shfl(dl, q);
-      const double wq = __shfl(w, q);
-      const double sq = tT + dlq;
-      const Curve cv = curve_eval(shape, a, cc, kappa, sq);
+      const double wq = readlane_f64(w, q);
+      const NodeLoc Lq = read_node(Lme, q);
+      const double sq = Lq.s;   // = tT + dl of node q
+      Curve cv;
+      cv.r = Lq.r; cv.dr = Lq.dr; cv.z = Lq.z; cv.dz = Lq.dz;
+      cv.p = Lq.p; cv.dp = Lq.dp; cv.q = Lq.q; cv.dq = Lq.dq;
 #pragma unroll
       for (int hh = 0; hh < LD / 64; ++hh) {
         const int l = lane + 64 * hh;
