@@ -500,11 +500,12 @@ __device__ __forceinline__ double2 modal_slot(int N, const NodeLoc& L, const Mod
   return out;
 }
 
-// acc[l] += P_l(s_q) w_q K (lane l < 16 holds pw = P_l(s_q) w_q)
-__device__ __forceinline__ void accumulate_modes(double2 (&acc)[GL_ORDER], double pw, double2 K) {
+// acc[l] += P_l(s_q) w_q K with P_l(s_q) held by lane q (uniform) in P[l]
+__device__ __forceinline__ void accumulate_node(double2 (&acc)[GL_ORDER], const double (&P)[GL_ORDER],
+                                                int q, double wq, double2 K) {
 #pragma unroll
   for (int l = 0; l < GL_ORDER; ++l) {
-    const double p = readlane_f64(pw, l);
+    const double p = readlane_f64(P[l], q) * wq;
     acc[l].x = fma(p, K.x, acc[l].x);
     acc[l].y = fma(p, K.y, acc[l].y);
   }
@@ -574,23 +575,6 @@ __device__ __forceinline__ NodeLoc shfl_node(const NodeLoc& v, int src) {
 }
 
 // ---------------------------------------------------------------- assembly kernel
-// Lagrange basis polynomial P_l(x) on the 16 Gauss-Legendre nodes x_m of
-// [-1, 1] for l = lane < 16 (0 in the other lanes): with barycentric weight
-// b_l = 1 / prod_{m != l}(x_l - x_m), P_l(x) = b_l prod_m (x - x_m) / (x - x_l);
-// the product over the 16 lanes by xor-shuffles; x on a node gives the unit
-// vector.  xl, bl: the lane's node and weight (registers).
-__device__ __forceinline__ double lagrange_lane(double x, double xl, double bl) {
-  const int lane = threadIdx.x;
-  const double d = lane < GL_ORDER ? x - xl : 1.0;
-  double prod = d;
-#pragma unroll
-  for (int off = 1; off < GL_ORDER; off <<= 1) prod *= __shfl_xor(prod, off);
-  const unsigned long long hit = __ballot(lane < GL_ORDER && d == 0.0);
-  if (lane >= GL_ORDER) return 0.0;
-  if (hit) return d == 0.0 ? 1.0 : 0.0;
-  return bl * prod / d;
-}
-
 struct OuterRule {
   double x[2][NGO];   // [0]: NGO_UNIFORM nodes (rest unused), [1]: NGO nodes
   double w[2][NGO];
@@ -735,9 +719,6 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   }
   __syncthreads();
 
-  // GL node and barycentric weight of lane l < 16
-  const double glx = lane < GL_ORDER ? gl16[lane] : 0.0;
-  const double glb = lane < GL_ORDER ? gl16[32 + lane] : 0.0;
   // lane s < 2N accumulates sum_q w_q P_l(s_q) K_{s-N}(s_q), l < 16
   // (CF: the single-layer modes in acs)
   double2 acc[GL_ORDER];
@@ -772,6 +753,24 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     // the lane's own node, computed once and broadcast to the wavefront when
     // the node is processed
     const NodeLoc Lme = node_local(shape, a, cc, kappa, TG, dl);
+    // and its Lagrange weights P_l(s) on the 16 GL nodes of the panel:
+    // b_l prod_{m != l} (x - x_m) by prefix and suffix products
+    double P[GL_ORDER];
+    {
+      const double x = 2.0 * (Lme.s - e0) / h - 1.0;
+      double pre = 1.0;
+#pragma unroll
+      for (int l = 0; l < GL_ORDER; ++l) {
+        P[l] = pre;
+        pre *= x - gl16[l];
+      }
+      double suf = 1.0;
+#pragma unroll
+      for (int l = GL_ORDER - 1; l >= 0; --l) {
+        P[l] *= suf * gl16[32 + l];
+        suf *= x - gl16[l];
+      }
+    }
     bool modal, wide;
     {
       const NodeLoc& L = Lme;
@@ -806,9 +805,8 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         modal_modes<CF>(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.tw);
         double2 ks;
         const double2 Kq = modal_slot<CF>(N, Ln, S.u.m, ks);
-        const double pw = lagrange_lane(2.0 * (Ln.s - e0) / h - 1.0, glx, glb) * wq;
-        accumulate_modes(acc, pw, Kq);
-        if constexpr (CF) accumulate_modes(acs, pw, ks);
+        accumulate_node(acc, P, sl, wq, Kq);
+        if constexpr (CF) accumulate_node(acs, P, sl, wq, ks);
         __syncthreads();
       }
     }
@@ -823,7 +821,6 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       const int tstep = LD / L;
       const double wq = readlane_f64(w, q);
       const NodeLoc Lq = read_node(Lme, q);
-      const double sq = Lq.s;   // = tT + dl of node q
       Curve cv;
       cv.r = Lq.r; cv.dr = Lq.dr; cv.z = Lq.z; cv.dz = Lq.dz;
       cv.p = Lq.p; cv.dp = Lq.dp; cv.q = Lq.q; cv.dq = Lq.dq;
@@ -847,7 +844,6 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
           if constexpr (CF) S.u.K[CF ? 1 : 0][l] = make_double2(c * ir * INV_4PI, s * ir * INV_4PI);
         }
       }
-      const double pw = lagrange_lane(2.0 * (sq - e0) / h - 1.0, glx, glb) * wq;
       __syncthreads();
       if (w256) fft256(S.u.K[0], S.tw); else fft128(S.u.K[0], S.tw);
       if constexpr (CF) {
@@ -868,8 +864,8 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
           Kq.x *= f;
           Kq.y *= f;
         }
-        if (part == 0) accumulate_modes(acc, pw, Kq);
-        else if constexpr (CF) accumulate_modes(acs, pw, Kq);
+        if (part == 0) accumulate_node(acc, P, q, wq, Kq);
+        else if constexpr (CF) accumulate_node(acs, P, q, wq, Kq);
       }
       __syncthreads();
     }
