@@ -211,7 +211,45 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
         }
       }
       __syncthreads();
-      if (!own) {
+      if (!own && NRC == 1 && FORM != 2) {
+        // one right-hand side: with e = e^{ikr}, z = e mu and r ir = 1 the
+        // double-layer term is (ikr - 1) e (aw . (y - x)) / r^3 mu
+        // = -sc z + i k u z, sc = dot ir^3, u = dot ir^2, so the tile sums
+        // S1 = sum sc z and S2 = sum u z need neither r nor kr
+        // (combined-field: - i eta G |aw| mu = - i t z, t = eta |aw| ir)
+        float ar = 0.0f, ai = 0.0f, br = 0.0f, bi = 0.0f, er = 0.0f, ei = 0.0f;
+#pragma unroll 4
+        for (int jj = 0; jj < cnt; ++jj) {
+          const float4 yl = sloc[jj];
+          const float4 a4 = saw[jj];
+          const float num = fmaf(dx2, yl.x, fmaf(dy2, yl.y, fmaf(dz2, yl.z, yl.w)));
+          const float r2 = d2f + num;
+          const float ir = __builtin_amdgcn_rsqf(r2);
+          // delta = r - |D| = num / (r + |D|), r + |D| = r^2 ir + |D|
+          const float delta = num * __builtin_amdgcn_rcpf(fmaf(r2, ir, dnf));
+          const float ph = fmaf(delta, k2pi, ph0);
+          const float s = __builtin_amdgcn_sinf(ph);
+          const float c = __builtin_amdgcn_cosf(ph);
+          const float2 m = smu[jj];
+          const float zr = fmaf(c, m.x, -s * m.y);
+          const float zi = fmaf(c, m.y, s * m.x);
+          const float dot = fmaf(a4.x, dxf, fmaf(a4.y, dyf, fmaf(a4.z, dzf, a4.w)));
+          const float u = dot * ir * ir;
+          const float sc = u * ir;
+          ar = fmaf(sc, zr, ar);
+          ai = fmaf(sc, zi, ai);
+          br = fmaf(u, zr, br);
+          bi = fmaf(u, zi, bi);
+          if constexpr (FORM == 1) {
+            const float t = sew[jj] * ir;
+            er = fmaf(t, zr, er);
+            ei = fmaf(t, zi, ei);
+          }
+        }
+        // -S1 + i k S2 (- i S3)
+        two_sum(sr[0], cr[0], fmaf(-kf, bi, ei - ar));
+        two_sum(si[0], ci[0], fmaf(kf, br, -ai - er));
+      } else if (!own) {
         float tr[NRC], ti[NRC];
 #pragma unroll
         for (int r = 0; r < NRC; ++r) { tr[r] = 0.0f; ti[r] = 0.0f; }
