@@ -479,48 +479,64 @@ __global__ void gj_unpivot_kernel(const MatDesc* __restrict__ mats, typename Cx<
 // row interchanges at the end.
 constexpr int GJB = 64;
 
-// Unblocked elimination with partial pivoting on the columns [c0, c0 + wcols)
-// only (pivot rows >= k; row interchanges applied to these columns only), one
-// workgroup of 1024 threads per matrix with the columns held in registers:
-// thread t owns rows t + 1024 r, r < R, and WL <= 16 / R columns.  Per column:
-// arg-max of |a_ik|^2 by wavefront shuffles and one LDS pass (ties to the
-// lower row), then one LDS exchange that carries both the pivot row scaled
-// by its owner and the row it displaces, and the rank-1 elimination of the
-// other rows: two barriers per column.
-template <typename T, int R, int WL>
-__global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restrict__ mats,
-                                                        typename Cx<T>::V* __restrict__ pool, int c0,
-                                                        int wcols, int32_t* __restrict__ piv,
-                                                        int nmax) {
-  typedef typename Cx<T>::V V;
-  const MatDesc M = mats[blockIdx.x];
-  const int n = M.n;
-  if (c0 >= n) return;
-  V* A = pool + M.elem_off;
-  const int w = min(c0 + wcols, n) - c0;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ T red_v[16];
-  __shared__ int red_i[16];
-  __shared__ V swap_buf[1][WL];
-  __shared__ V rowk[WL];
-  V a[R][WL];
+// Wavefront maximum of a 64-bit key by DPP row shifts and row broadcasts
+// (lane 15 of each row of 16 ends with its row's maximum, lane 63 with the
+// wavefront's), read back from lane 63.
+template <int CTRL, int ROWM>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROWM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROWM, 0xf, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ unsigned long long max_u64(unsigned long long a, unsigned long long b) {
+  return a > b ? a : b;
+}
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int l) {
+  const unsigned lo = __builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = __builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+template <bool WHOLE_WAVE>
+__device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long v) {
+  v = max_u64(v, dpp_u64<0x111, 0xf>(v));   // row_shr:1
+  v = max_u64(v, dpp_u64<0x112, 0xf>(v));   // row_shr:2
+  v = max_u64(v, dpp_u64<0x114, 0xf>(v));   // row_shr:4
+  v = max_u64(v, dpp_u64<0x118, 0xf>(v));   // row_shr:8
+  if (!WHOLE_WAVE) return readlane_u64(v, 15);
+  v = max_u64(v, dpp_u64<0x142, 0xa>(v));   // row_bcast:15 into rows 1, 3
+  v = max_u64(v, dpp_u64<0x143, 0xc>(v));   // row_bcast:31 into rows 2, 3
+  return readlane_u64(v, 63);
+}
+
+// Pivot row of column k: the row i in [k, n) of largest |a_ik|^2, ties to the
+// lower row.  col[r] is the thread's entry in row tid + 1024 r.  FP32: one
+// 64-bit key (magnitude bits, which order like the non-negative values, then
+// the complemented row) reduced by DPP; FP64: value and row by shuffles.
+template <typename T, int R>
+__device__ __forceinline__ int leaf_pivot(const typename Cx<T>::V (&col)[R], int tid, int k, int n,
+                                          T* red_v, int* red_i, unsigned long long* red_k) {
+  const int lane = tid & 63, wave = tid >> 6;
+  if constexpr (sizeof(T) == 4) {
+    unsigned long long key = 0;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int i = tid + 1024 * r;
-#pragma unroll
-    for (int c = 0; c < WL; ++c)
-      a[r][c] = (i < n && c < w) ? A[(int64_t)i * n + c0 + c] : Cx<T>::make(0.0, 0.0);
-  }
-#pragma unroll
-  for (int kk = 0; kk < WL; ++kk) {
-    if (kk >= w) continue;   // (uniform; keeps the loop fully unrolled)
-    const int k = c0 + kk;
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 1024 * r;
+      const float m = col[r].x * col[r].x + col[r].y * col[r].y;
+      const unsigned long long ki = ((unsigned long long)__float_as_uint(m) << 32) | (unsigned)~i;
+      if (i >= k && i < n) key = max_u64(key, ki);
+    }
+    key = dpp_max_u64<true>(key);
+    if (lane == 0) red_k[wave] = key;
+    __syncthreads();
+    key = dpp_max_u64<false>(red_k[lane & 15]);
+    return (int)~(unsigned)key;
+  } else {
     T bv = -1;
     int bi = n;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = tid + 1024 * r;
-      const T m = a[r][kk].x * a[r][kk].x + a[r][kk].y * a[r][kk].y;
+      const T m = col[r].x * col[r].x + col[r].y * col[r].y;
       if (i >= k && i < n && m > bv) {
         bv = m;
         bi = i;
@@ -551,56 +567,167 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
         bi = oi;
       }
     }
-    const int pr = bi;
-    if (tid == 0) piv[(int64_t)blockIdx.x * nmax + k] = pr;
-    // one exchange through LDS: the owner of row pr publishes the scaled
-    // pivot row (it becomes row k), the owner of row k its old row (it
-    // becomes row pr)
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = tid + 1024 * r;
-      if (i == pr) {
-        const V d = a[r][kk];
-        const T den = d.x * d.x + d.y * d.y;
-        const V inv = Cx<T>::make(d.x / den, -d.y / den);
-#pragma unroll
-        for (int c = 0; c < WL; ++c) {
-          const V x = (c == kk) ? Cx<T>::make(1.0, 0.0) : a[r][c];
-          rowk[c] = Cx<T>::make(x.x * inv.x - x.y * inv.y, x.x * inv.y + x.y * inv.x);
-        }
-      }
-      if (i == k && pr != k)
-#pragma unroll
-        for (int c = 0; c < WL; ++c) swap_buf[0][c] = a[r][c];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = tid + 1024 * r;
-      if (i == k) {
-#pragma unroll
-        for (int c = 0; c < WL; ++c) a[r][c] = rowk[c];
-      } else if (i < n) {
-        if (i == pr)
-#pragma unroll
-          for (int c = 0; c < WL; ++c) a[r][c] = swap_buf[0][c];
-        const V f = a[r][kk];
-#pragma unroll
-        for (int c = 0; c < WL; ++c) {
-          const V x = (c == kk) ? Cx<T>::make(0.0, 0.0) : a[r][c];
-          const V rk = rowk[c];
-          a[r][c] = Cx<T>::make(x.x - (f.x * rk.x - f.y * rk.y), x.y - (f.x * rk.y + f.y * rk.x));
-        }
-      }
-    }
+    return bi;
   }
+}
+
+// Unblocked elimination with partial pivoting on the columns [c0, c0 + wcols)
+// only (pivot rows >= k; row interchanges applied to these columns only), one
+// workgroup of 1024 threads per matrix with the columns held in registers:
+// thread t owns rows t + 1024 r, r < R, and WL <= 16 / R columns.  Per column:
+// the pivot row (leaf_pivot), then one LDS exchange that carries both the
+// pivot row scaled by its owner and the row it displaces, and the rank-1
+// elimination of the other rows: two barriers per column.  The column loop is
+// unrolled by groups of U columns only (at most 4 in FP32, 1 in FP64; the
+// body stays small in the instruction cache): the group is always register
+// columns [0, U) and the register columns rotate by U after each group, so
+// they end in their original order.
+template <typename T, int R, int WL>
+__global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restrict__ mats,
+                                                        typename Cx<T>::V* __restrict__ pool, int c0,
+                                                        int wcols, int32_t* __restrict__ piv,
+                                                        int nmax) {
+  typedef typename Cx<T>::V V;
+  const MatDesc M = mats[blockIdx.x];
+  const int n = M.n;
+  if (c0 >= n) return;
+  V* A = pool + M.elem_off;
+  const int w = min(c0 + wcols, n) - c0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ T red_v[16];
+  __shared__ int red_i[16];
+  __shared__ unsigned long long red_k[16];
+  __shared__ V swap_buf[WL];
+  __shared__ V rowk[WL];
+  // staging of a full-width panel through LDS: wave q moves its 64 rows
+  // 1024 r + 64 q + [0, 64) with 16-byte loads and stores that cover whole
+  // row segments (LPR lanes per row), padded by 16 bytes per row so the
+  // per-lane row reads spread over the banks
+  constexpr int LPR = WL * (int)sizeof(V) / 16;   // 16-byte chunks per row
+  constexpr int SROW = LPR + 1;
+  constexpr int RPI = 64 / LPR;                   // rows per wave instruction
+  constexpr int VPC = 16 / (int)sizeof(V);        // complex per chunk
+  __shared__ float4 stage[16 * 64 * SROW];
+  float4* st = stage + wave * 64 * SROW;
+  const bool staged = w == WL && (M.elem_off + c0) % VPC == 0 && n % VPC == 0;
+  V a[R][WL];
+  if (staged) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int i = tid + 1024 * r;
-    if (i < n)
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int q = 0; q < LPR; ++q) {
+        const int rr = q * RPI + lane / LPR, ch = lane % LPR;
+        const int i = 1024 * r + 64 * wave + rr;
+        st[rr * SROW + ch] = i < n ? reinterpret_cast<const float4*>(A + (int64_t)i * n + c0)[ch]
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      __syncthreads();
+      const V* row = reinterpret_cast<const V*>(st + lane * SROW);
+#pragma unroll
+      for (int c = 0; c < WL; ++c) a[r][c] = row[c];
+      __syncthreads();
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 1024 * r;
 #pragma unroll
       for (int c = 0; c < WL; ++c)
-        if (c < w) A[(int64_t)i * n + c0 + c] = a[r][c];
+        a[r][c] = (i < n && c < w) ? A[(int64_t)i * n + c0 + c] : Cx<T>::make(0.0, 0.0);
+    }
+  }
+  // columns of one unrolled group; the register columns rotate by U after
+  // each group (WL / U groups in all)
+  constexpr int U = sizeof(T) == 8 ? 1 : (WL < 4 ? WL : 4);
+#pragma unroll 1
+  for (int g0 = 0; g0 < WL; g0 += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int kk = g0 + u;
+      if (kk < w) {   // (uniform)
+        const int k = c0 + kk;
+        V col[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) col[r] = a[r][u];
+        const int pr = leaf_pivot<T, R>(col, tid, k, n, red_v, red_i, red_k);
+        if (tid == 0) piv[(int64_t)blockIdx.x * nmax + k] = pr;
+        // one exchange through LDS: the owner of row pr publishes the scaled
+        // pivot row (it becomes row k), the owner of row k its old row (it
+        // becomes row pr)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = tid + 1024 * r;
+          if (i == pr) {
+            const V d = a[r][u];
+            const T den = d.x * d.x + d.y * d.y;
+            const V inv = Cx<T>::make(d.x / den, -d.y / den);
+#pragma unroll
+            for (int c = 0; c < WL; ++c) {
+              const V x = (c == u) ? Cx<T>::make(1.0, 0.0) : a[r][c];
+              rowk[c] = Cx<T>::make(fma(x.x, inv.x, -x.y * inv.y), fma(x.x, inv.y, x.y * inv.x));
+            }
+          }
+          if (i == k && pr != k)
+#pragma unroll
+            for (int c = 0; c < WL; ++c) swap_buf[c] = a[r][c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = tid + 1024 * r;
+          if (i == k) {
+#pragma unroll
+            for (int c = 0; c < WL; ++c) a[r][c] = rowk[c];
+          } else if (i < n) {
+            if (i == pr)
+#pragma unroll
+              for (int c = 0; c < WL; ++c) a[r][c] = swap_buf[c];
+            const V f = a[r][u];
+#pragma unroll
+            for (int c = 0; c < WL; ++c) {
+              // x - f rk, with x = 0 in the pivot column
+              const V x = (c == u) ? Cx<T>::make(0.0, 0.0) : a[r][c];
+              const V rk = rowk[c];
+              a[r][c] = Cx<T>::make(fma(-f.x, rk.x, fma(f.y, rk.y, x.x)), fma(-f.x, rk.y, fma(-f.y, rk.x, x.y)));
+            }
+          }
+        }
+      }
+    }
+    // rotate: the next group to register columns [0, U)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      V t[WL];
+#pragma unroll
+      for (int c = 0; c < WL; ++c) t[c] = a[r][(c + U) % WL];
+#pragma unroll
+      for (int c = 0; c < WL; ++c) a[r][c] = t[c];
+    }
+  }
+  if (staged) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      V* row = reinterpret_cast<V*>(st + lane * SROW);
+#pragma unroll
+      for (int c = 0; c < WL; ++c) row[c] = a[r][c];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < LPR; ++q) {
+        const int rr = q * RPI + lane / LPR, ch = lane % LPR;
+        const int i = 1024 * r + 64 * wave + rr;
+        if (i < n) reinterpret_cast<float4*>(A + (int64_t)i * n + c0)[ch] = st[rr * SROW + ch];
+      }
+      __syncthreads();
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 1024 * r;
+      if (i < n)
+#pragma unroll
+        for (int c = 0; c < WL; ++c)
+          if (c < w) A[(int64_t)i * n + c0 + c] = a[r][c];
+    }
   }
 }
 
@@ -864,13 +991,14 @@ static void gj_factor_panel(hipStream_t s, typename Cx<T>::V* pool, const MatDes
 
 // In-place inversion of `batch` matrices of complex T (interleaved, pool in
 // units of T) described on the device by `mats` (orders up to nmax, at most
-// 8192).  work: see gj_work_bytes.  With tp set, the trailing updates are
-// timed on tp's counters.
+// 8192), on p->stream.  work: see gj_work_bytes.  With timed set, the trailing
+// updates are timed on p's counters.
 template <typename T>
-hipError_t gj_invert(hipStream_t s, T* pool, const MatDesc* d_mats, int batch, int nmax,
-                     double* work, qax_problem* tp) {
+hipError_t gj_invert(qax_problem* p, T* pool, const MatDesc* d_mats, int batch, int nmax,
+                     double* work, bool timed) {
   typedef typename Cx<T>::V V;
   if (nmax > 8192) return hipErrorInvalidValue;
+  const hipStream_t s = p->stream;
   V* W = (V*)work;
   int32_t* piv = (int32_t*)(W + (int64_t)GJB * nmax * batch);
   const size_t piv_bytes = (((size_t)nmax * batch * sizeof(int32_t)) + 255) / 256 * 256;
@@ -880,10 +1008,10 @@ hipError_t gj_invert(hipStream_t s, T* pool, const MatDesc* d_mats, int batch, i
     gj_factor_panel<T>(s, (V*)pool, d_mats, batch, nmax, k0, GJB, piv, Wn);
     hipLaunchKernelGGL(gjb_swap_copy_kernel<T>, dim3((nmax + 255) / 256, batch), dim3(256), 0, s,
                        d_mats, (V*)pool, k0, piv, nmax, W);
-    if (tp) timing_begin(tp, QAX_K_INVERT_UPDATE);
+    if (timed) timing_begin(p, QAX_K_INVERT_UPDATE);
     hipLaunchKernelGGL(gjm_update_kernel<T>, dim3(tiles, tiles, batch), dim3(256), 0, s, d_mats,
                        (V*)pool, k0, W, nmax);
-    if (tp) timing_end(tp, QAX_K_INVERT_UPDATE);
+    if (timed) timing_end(p, QAX_K_INVERT_UPDATE);
   }
   hipLaunchKernelGGL(gj_unpivot_kernel<T>, dim3((nmax + 255) / 256, batch), dim3(256), 0, s, d_mats,
                      (V*)pool, piv, nmax);
@@ -925,7 +1053,7 @@ hipError_t launch_invert_blocks(qax_problem* p, double* work) {
   if (e == hipSuccess) e = upload_mats(p, work, &d_md, &w2, &nmax);
   if (e != hipSuccess) return e;
   timing_begin(p, QAX_K_INVERT);
-  e = gj_invert<float>(p->stream, p->d_Binv32, d_md, (int)p->hblocks.size(), nmax, w2, p);
+  e = gj_invert<float>(p, p->d_Binv32, d_md, (int)p->hblocks.size(), nmax, w2, true);
   timing_end(p, QAX_K_INVERT);
   return e;
 }
@@ -940,7 +1068,7 @@ hipError_t launch_invert_blocks64(qax_problem* p, double* work) {
   if (e == hipSuccess) e = upload_mats(p, work, &d_md, &w2, &nmax);
   if (e != hipSuccess) return e;
   timing_begin(p, QAX_K_INVERT);
-  e = gj_invert<double>(p->stream, p->d_Binv, d_md, (int)p->hblocks.size(), nmax, w2, p);
+  e = gj_invert<double>(p, p->d_Binv, d_md, (int)p->hblocks.size(), nmax, w2, true);
   timing_end(p, QAX_K_INVERT);
   return e;
 }
@@ -1038,7 +1166,7 @@ hipError_t launch_dense_solve(qax_problem* p, double* A, const double* b, int nr
   double* w2 = (double*)((char*)work + 256);
   hipError_t e = hipMemcpyAsync(d_md, &md, sizeof(MatDesc), hipMemcpyHostToDevice, p->stream);
   if (e != hipSuccess) return e;
-  e = gj_invert<double>(p->stream, A, d_md, 1, (int)p->N, w2, nullptr);
+  e = gj_invert<double>(p, A, d_md, 1, (int)p->N, w2, false);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(dense_matvec_kernel, dim3((unsigned)((p->N + 3) / 4), (unsigned)nrhs),
                      dim3(256), 0, p->stream, (const double2*)A, p->N, (const double2*)b, nrhs,
