@@ -30,8 +30,8 @@ CAL_BYTES = 1 << 30
 KINDS = {
     "pair_sum_fp32": (r"qax::pair_sum_f32_kernel<\d+, 1, 0>", "paper_2606_31380_amd/csrc/pairsum.hip"),
     "pair_sum_fp64": (r"qax::pair_sum_f64_kernel<\d+, 1, 0>", "paper_2606_31380_amd/csrc/pairsum.hip"),
-    "block_apply": (r"qax::block_gemv_kernel<double, 1, \d>", "paper_2606_31380_amd/csrc/dense.hip"),
-    "block_apply_f32": (r"qax::block_gemv_kernel<float, 1, \d>", "paper_2606_31380_amd/csrc/dense.hip"),
+    "block_apply": (r"qax::block_gemv_kernel<double, 1, \d, \d+>", "paper_2606_31380_amd/csrc/dense.hip"),
+    "block_apply_f32": (r"qax::block_gemv_f32_lds_kernel<\d>", "paper_2606_31380_amd/csrc/dense.hip"),
     "self_assembly": (r"qax::assemble_self_kernel<0>", "paper_2606_31380_amd/csrc/selfblock.hip"),
     "invert_update": (r"qax::gjm_update_kernel<float>", "paper_2606_31380_amd/csrc/dense.hip"),
 }
