@@ -827,12 +827,13 @@ __global__ void gjb_swap_copy_kernel(const MatDesc* __restrict__ mats, typename 
 
 // A[i][j] = (i in panel ? 0 : A[i][j]) + sum_p A[i][k0+p] W[p][j] for j outside
 // the panel, on the matrix cores: the complex product as a real one,
-// [Re a, Im a] x [[Re w, Im w], [-Im w, Re w]], with v_mfma_f64_16x16x4f64.
-// 64 x 64 complex output tile per workgroup (64 x 128 real); each of the four
-// wavefronts owns 32 rows x 64 real columns (2 x 4 MFMA tiles); the panel
-// columns and rows are staged through LDS 16 complex columns at a time.
+// [Re a, Im a] x [[Re w, Im w], [-Im w, Re w]], with v_mfma_f64_16x16x4f64
+// (v_mfma_f32_16x16x4f32 in FP32, four workgroups per CU).  64 x 64 complex
+// output tile per workgroup (64 x 128 real); each of the four wavefronts owns
+// 32 rows x 64 real columns (2 x 4 MFMA tiles); the panel columns and rows
+// are staged through LDS 16 complex columns at a time.
 template <typename T>
-__global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restrict__ mats,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gjm_update_kernel(const MatDesc* __restrict__ mats,
                                                          typename Cx<T>::V* __restrict__ pool, int k0,
                                                          const typename Cx<T>::V* __restrict__ W, int nmax) {
   typedef typename Cx<T>::V V;
@@ -847,8 +848,13 @@ __global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restri
   if (j0 >= k0 && j0 + 64 <= kend) return;  // tile inside the panel columns
   V* A = pool + M.elem_off;
   const V* Wm = W + (int64_t)blockIdx.z * GJB * nmax;
-  __shared__ T As[32][64 + 1];   // real k x rows
-  __shared__ T Bs[32][128 + 1];  // real k x real columns
+  // A chunk as rows x real k, B chunk as real k x real columns; the row
+  // strides keep both the 8-byte writes and the operand reads of a
+  // half-wavefront (16 rows or columns x two k) on distinct banks
+  constexpr int AS = sizeof(T) == 4 ? 34 : 33;
+  constexpr int BS = sizeof(T) == 4 ? 144 : 136;
+  __shared__ T As[64][AS];
+  __shared__ T Bs[32][BS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 64;
   // accumulators start from the tile of A (zero on the panel rows and for
@@ -889,8 +895,8 @@ __global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restri
     for (int q = 0; q < 4; ++q) {
       const int e = tid + 256 * q;
       const int rr = e >> 4, pp = e & 15;
-      As[2 * pp][rr] = ra[q].x;
-      As[2 * pp + 1][rr] = ra[q].y;
+      As[rr][2 * pp] = ra[q].x;
+      As[rr][2 * pp + 1] = ra[q].y;
       const int pw = e >> 6, jj = e & 63;
       Bs[2 * pw][2 * jj] = rw[q].x;
       Bs[2 * pw][2 * jj + 1] = rw[q].y;
@@ -904,7 +910,7 @@ __global__ __launch_bounds__(256) void gjm_update_kernel(const MatDesc* __restri
       const int kr = kk + (lane >> 4), ci = lane & 15;
       T af[2], bf[4];
 #pragma unroll
-      for (int x = 0; x < 2; ++x) af[x] = As[kr][wr + 16 * x + ci];
+      for (int x = 0; x < 2; ++x) af[x] = As[wr + 16 * x + ci][kr];
 #pragma unroll
       for (int y = 0; y < 4; ++y) bf[y] = Bs[kr][wc + 16 * y + ci];
 #pragma unroll
