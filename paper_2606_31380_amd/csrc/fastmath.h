@@ -1,4 +1,5 @@
 // FP64 sine and cosine for the kernels' moderate arguments (|x| < 2^20).
+// (sincos_2pi and rsqrt_pos below: the pair-sum variants.)
 //
 // Cody-Waite reduction x = q (pi/2) + r, |r| <= pi/4, with pi/2 split into
 // three doubles (the products q * P_i are exact inside fused multiply-adds),
@@ -44,6 +45,54 @@ __device__ __forceinline__ void sincos_cw(double x, double* sp, double* cp) {
   if ((n + 1) & 2) c = -c;
   *sp = s;
   *cp = c;
+}
+
+// sin(2 pi t) and cos(2 pi t) for |t| < 2^50 (t in revolutions).  With
+// n = rint(2 t) the remainder g = t - n / 2 is exact and |g| <= 1/4, so
+// sin(2 pi t) = (-1)^n sin(2 pi g) and cos(2 pi t) = (-1)^n cos(2 pi g): one
+// sign for both, no quadrant swap.  Taylor series in g: sin(2 pi g) through
+// g^21 and cos(2 pi g) through g^22, truncation below 2e-18 on |g| <= 1/4
+// (the coefficients (-1)^k (2 pi)^m / m! rounded to double).
+__device__ __forceinline__ void sincos_2pi(double t, double* sp, double* cp) {
+  const double n = rint(t + t);
+  const double g = fma(n, -0.5, t);
+  const double g2 = g * g;
+  double ps = 0.0011309237482517963;
+  ps = fma(ps, g2, -0.012031585942120627);
+  ps = fma(ps, g2, 0.10422916220813984);
+  ps = fma(ps, g2, -0.7181223017785006);
+  ps = fma(ps, g2, 3.819952584848282);
+  ps = fma(ps, g2, -15.09464257682299);
+  ps = fma(ps, g2, 42.058693944897655);
+  ps = fma(ps, g2, -76.70585975306139);
+  ps = fma(ps, g2, 81.60524927607506);
+  ps = fma(ps, g2, -41.34170224039976);
+  ps = fma(ps, g2, 6.283185307179586);
+  double pc = -0.0003229910672070978;
+  pc = fma(pc, g2, 0.0037798342006800396);
+  pc = fma(pc, g2, -0.03638284114254567);
+  pc = fma(pc, g2, 0.28200596845579123);
+  pc = fma(pc, g2, -1.714390711088672);
+  pc = fma(pc, g2, 7.903536371318469);
+  pc = fma(pc, g2, -26.4262567833744);
+  pc = fma(pc, g2, 60.24464137187666);
+  pc = fma(pc, g2, -85.45681720669373);
+  pc = fma(pc, g2, 64.9393940226683);
+  pc = fma(pc, g2, -19.739208802178716);
+  pc = fma(pc, g2, 1.0);
+  const int sgn = ((int)n & 1) << 31;
+  const double S = g * ps;
+  *sp = __hiloint2double(__double2hiint(S) ^ sgn, __double2loint(S));
+  *cp = __hiloint2double(__double2hiint(pc) ^ sgn, __double2loint(pc));
+}
+
+// 1 / sqrt(x) for finite x > 0: the hardware estimate (relative error about
+// 2^-23) and one third-order correction y (1 + e/2 + 3 e^2 / 8),
+// e = 1 - x y^2, leaving an error of order e^3 (no special-case handling).
+__device__ __forceinline__ double rsqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-(x * y), y, 1.0);
+  return fma(y * e, fma(e, 0.375, 0.5), y);
 }
 
 }  // namespace qax

@@ -78,6 +78,9 @@ __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
   double accr[NRC], acci[NRC];
 #pragma unroll
   for (int r = 0; r < NRC; ++r) { accr[r] = 0.0; acci[r] = 0.0; }
+  // one right-hand side: S1 = sum sc z, S2 = sum u z (S3 = sum t z), see below
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0, er = 0.0, ei = 0.0;
+  const double k2pi = k / TWO_PI;
 
   for (int b = T.b0; b < T.b1; ++b) {
     if (T.tbody_lo == b && T.tbody_hi == b) continue;  // every target is in body b
@@ -97,11 +100,38 @@ __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
           smu[tid * NRC + r] = (rc0 + r < nrhs) ? mu[j * nrhs + rc0 + r] : make_double2(0.0, 0.0);
       }
       __syncthreads();
-      if (!own) {
+      if (!own && NRC == 1 && FORM != 2) {
+        // with e = e^{ikr}, z = e mu and r ir = 1 the double-layer term is
+        // (ikr - 1) e (aw . (y - x)) / r^3 mu = -sc z + i k u z, sc = dot ir^3,
+        // u = dot ir^2; the phase kr / 2 pi = r^2 ir k / 2 pi in revolutions
+        // (combined field: - i eta G |aw| mu = - i t z, t = eta |aw| ir)
         for (int jj = 0; jj < cnt; ++jj) {
           const double dx = sx[jj] - xi, dy = sy[jj] - yi, dz = sz[jj] - zi;
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          const double ir = rsqrt(r2);
+          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          const double ir = rsqrt_pos(r2);
+          double s, c;
+          sincos_2pi(r2 * ir * k2pi, &s, &c);
+          const double2 m = smu[jj];
+          const double zr = fma(c, m.x, -s * m.y);
+          const double zi = fma(c, m.y, s * m.x);
+          const double dot = fma(sax[jj], dx, fma(say[jj], dy, saz[jj] * dz));
+          const double u = dot * ir * ir;
+          const double sc = u * ir;
+          ar = fma(sc, zr, ar);
+          ai = fma(sc, zi, ai);
+          br = fma(u, zr, br);
+          bi = fma(u, zi, bi);
+          if constexpr (FORM == 1) {
+            const double t = sew[jj] * ir;
+            er = fma(t, zr, er);
+            ei = fma(t, zi, ei);
+          }
+        }
+      } else if (!own) {
+        for (int jj = 0; jj < cnt; ++jj) {
+          const double dx = sx[jj] - xi, dy = sy[jj] - yi, dz = sz[jj] - zi;
+          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          const double ir = rsqrt_pos(r2);
           const double r = r2 * ir;
           const double kr = k * r;
           double s, c;
@@ -125,12 +155,16 @@ __global__ __launch_bounds__(TPB) void pair_sum_f64_kernel(
 #pragma unroll
           for (int r_ = 0; r_ < NRC; ++r_) {
             const double2 m = smu[jj * NRC + r_];
-            accr[r_] += re * m.x - im * m.y;
-            acci[r_] += re * m.y + im * m.x;
+            accr[r_] = fma(re, m.x, fma(-im, m.y, accr[r_]));
+            acci[r_] = fma(re, m.y, fma(im, m.x, acci[r_]));
           }
         }
       }
     }
+  }
+  if (NRC == 1 && FORM != 2) {   // -S1 + i k S2 (- i S3)
+    accr[0] += fma(-k, bi, ei - ar);
+    acci[0] += fma(k, br, -ai - er);
   }
   if (active) {
     double2* dst = partial + (int64_t)T.slot * N * nrhs;
