@@ -245,8 +245,9 @@ def main():
     self_flop = float(np.sum(nb * ((2 * g + g * adj) * per_node + (1 + adj) * per_item)))
     # the inversion of the mixed path runs in FP32 (matrix cores at the FP32 rate)
     inv_flop = float(np.sum(8.0 * nb ** 3))
-    # one trailing update of the inversion: rank-64 complex update of every block
-    upd_flop = float(np.sum(8.0 * nb * nb * 64))
+    # one trailing update of the inversion: rank-128 complex update of every
+    # block (128-column panels)
+    upd_flop = float(np.sum(8.0 * nb * nb * 128))
     work = {"pair_sum_fp32": ("alu", FLOP_PER_PAIR * P, PEAK["fp32"], "TFLOP/s"),
             "pair_sum_fp64": ("alu", FLOP_PER_PAIR * P, PEAK["fp64"], "TFLOP/s"),
             "block_apply": ("hbm", float(np.sum(nb * nb)) * 16.0, PEAK["hbm"], "GB/s"),

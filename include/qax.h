@@ -268,7 +268,7 @@ typedef enum {
   QAX_K_BLOCK_APPLY = 2,   /* block-diagonal apply, FP64 (B or B^-1)           */
   QAX_K_SELF_ASSEMBLY = 3, /* self-block assembly                              */
   QAX_K_INVERT = 4,        /* self-block inversion (all of its launches)       */
-  QAX_K_INVERT_UPDATE = 5, /* inversion: trailing update of one 64-column panel */
+  QAX_K_INVERT_UPDATE = 5, /* inversion: trailing update of one 128-column panel */
   QAX_K_BLOCK_APPLY_F32 = 6, /* block-diagonal apply of the FP32 inverse of B   */
   QAX_K_LATTICE_F64 = 7,   /* lattice apply: per-frequency products, FP64 tables */
   QAX_K_LATTICE_F32 = 8,   /* lattice apply: per-frequency products, FP32 tables */

@@ -477,7 +477,7 @@ __global__ void gj_unpivot_kernel(const MatDesc* __restrict__ mats, typename Cx<
 // column is updated, A[i][j] = (i in panel ? 0 : A[i][j]) + sum_p A[i][k0+p] W[p][j]
 // (the block form of the same row operations).  Column interchanges undo the
 // row interchanges at the end.
-constexpr int GJB = 64;
+constexpr int GJB = 128;
 
 // Wavefront maximum of a 64-bit key by DPP row shifts and row broadcasts
 // (lane 15 of each row of 16 ends with its row's maximum, lane 63 with the
@@ -772,7 +772,7 @@ __global__ __launch_bounds__(256) void gjn_update_kernel(const MatDesc* __restri
   const int send = min(s0 + ws, n);
   const int wsv = send - s0;
   const int wdv = min(d0 + wd, n) - d0;
-  __shared__ V Ws[GJB / 2][GJB / 2];
+  __shared__ V Ws[32][32];   // halves of at most 32 columns (wider ones: gjm_update_kernel)
   const V* Wm = W + (int64_t)blockIdx.y * GJB * GJB;
   for (int e = threadIdx.x; e < wsv * wdv; e += 256) Ws[e / wdv][e % wdv] = Wm[(e / wdv) * GJB + e % wdv];
   __syncthreads();
@@ -832,22 +832,29 @@ __global__ void gjb_swap_copy_kernel(const MatDesc* __restrict__ mats, typename 
 // output tile per workgroup (64 x 128 real); each of the four wavefronts owns
 // 32 rows x 64 real columns (2 x 4 MFMA tiles); the panel columns and rows
 // are staged through LDS 16 complex columns at a time.
+// The eliminated columns are [k0, k0 + ws); the output columns start at
+// jbase (tiles of 64); row p of W holds the pivot row's entries of the output
+// columns from wcol0 on (leading dimension ldw, matrix stride wstride): the
+// trailing update of a panel (jbase = wcol0 = 0, W is GJB x nmax) and, inside
+// the recursive panel factorization, the update of one half by the other
+// (W is the half's pivot rows, GJB x GJB).
 template <typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gjm_update_kernel(const MatDesc* __restrict__ mats,
-                                                         typename Cx<T>::V* __restrict__ pool, int k0,
-                                                         const typename Cx<T>::V* __restrict__ W, int nmax) {
+                                                         typename Cx<T>::V* __restrict__ pool, int k0, int ws,
+                                                         const typename Cx<T>::V* __restrict__ W, int ldw,
+                                                         int64_t wstride, int jbase, int wcol0) {
   typedef typename Cx<T>::V V;
   typedef typename MfmaAcc<T>::v4 v4;
   const MatDesc M = mats[blockIdx.z];
   const int n = M.n;
   if (k0 >= n) return;
-  const int kend = min(k0 + GJB, n);
+  const int kend = min(k0 + ws, n);
   const int w = kend - k0;
-  const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+  const int i0 = blockIdx.y * 64, j0 = jbase + blockIdx.x * 64;
   if (i0 >= n || j0 >= n) return;
   if (j0 >= k0 && j0 + 64 <= kend) return;  // tile inside the panel columns
   V* A = pool + M.elem_off;
-  const V* Wm = W + (int64_t)blockIdx.z * GJB * nmax;
+  const V* Wm = W + (int64_t)blockIdx.z * wstride;
   // A chunk as rows x real k, B chunk as real k x real columns; the row
   // strides keep both the 8-byte writes and the operand reads of a
   // half-wavefront (16 rows or columns x two k) on distinct banks
@@ -886,7 +893,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
       ra[q] = (i < n && pc < w) ? A[(int64_t)i * n + k0 + pc] : Cx<T>::make(0.0, 0.0);
       const int pw = e >> 6, jj = e & 63;
       const int j = j0 + jj, pcw = p0 + pw;
-      rw[q] = (j < n && pcw < w) ? Wm[(int64_t)pcw * nmax + j] : Cx<T>::make(0.0, 0.0);
+      rw[q] = (j < n && pcw < w) ? Wm[(int64_t)pcw * ldw + (j - wcol0)] : Cx<T>::make(0.0, 0.0);
     }
   };
   load_chunk(0);
@@ -971,6 +978,24 @@ static void launch_leaf(hipStream_t s, typename Cx<T>::V* pool, const MatDesc* d
   }
 }
 
+// The row operations of the eliminated half [s0, s0 + h) applied to its
+// sibling half [d0, d0 + h): halves of 64 columns or more on the matrix cores
+// (one column of 64-wide tiles per 64 columns), narrower ones on the vector
+// ALUs.
+template <typename T>
+static void launch_half_update(hipStream_t s, typename Cx<T>::V* pool, const MatDesc* d_mats, int batch,
+                               int nmax, int s0, int h, int d0, typename Cx<T>::V* Wn,
+                               unsigned rows_blocks) {
+  if (h >= 64) {
+    const unsigned tiles = (unsigned)((nmax + 63) / 64);
+    hipLaunchKernelGGL(gjm_update_kernel<T>, dim3((unsigned)(h / 64), tiles, batch), dim3(256), 0, s,
+                       d_mats, pool, s0, h, Wn, GJB, (int64_t)GJB * GJB, d0, d0);
+  } else {
+    hipLaunchKernelGGL(gjn_update_kernel<T>, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool,
+                       s0, h, d0, h, Wn);
+  }
+}
+
 // Factor the panel columns [c0, c0 + w) (w a power of two, <= GJB) by halves:
 // left half, its row operations on the right half, right half, its row
 // operations on the left half; leaves of gj_leaf_cols columns run unblocked.
@@ -986,13 +1011,11 @@ static void gj_factor_panel(hipStream_t s, typename Cx<T>::V* pool, const MatDes
   gj_factor_panel<T>(s, pool, d_mats, batch, nmax, c0, h, piv, Wn);
   hipLaunchKernelGGL(gjn_swap_copy_kernel<T>, dim3(batch), dim3(h), 0, s, d_mats, pool, c0, h,
                      c0 + h, h, piv, nmax, Wn);
-  hipLaunchKernelGGL(gjn_update_kernel<T>, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool,
-                     c0, h, c0 + h, h, Wn);
+  launch_half_update<T>(s, pool, d_mats, batch, nmax, c0, h, c0 + h, Wn, rows_blocks);
   gj_factor_panel<T>(s, pool, d_mats, batch, nmax, c0 + h, h, piv, Wn);
   hipLaunchKernelGGL(gjn_swap_copy_kernel<T>, dim3(batch), dim3(h), 0, s, d_mats, pool, c0 + h, h,
                      c0, h, piv, nmax, Wn);
-  hipLaunchKernelGGL(gjn_update_kernel<T>, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool,
-                     c0 + h, h, c0, h, Wn);
+  launch_half_update<T>(s, pool, d_mats, batch, nmax, c0 + h, h, c0, Wn, rows_blocks);
 }
 
 // In-place inversion of `batch` matrices of complex T (interleaved, pool in
@@ -1016,7 +1039,7 @@ hipError_t gj_invert(qax_problem* p, T* pool, const MatDesc* d_mats, int batch, 
                        d_mats, (V*)pool, k0, piv, nmax, W);
     if (timed) timing_begin(p, QAX_K_INVERT_UPDATE);
     hipLaunchKernelGGL(gjm_update_kernel<T>, dim3(tiles, tiles, batch), dim3(256), 0, s, d_mats,
-                       (V*)pool, k0, W, nmax);
+                       (V*)pool, k0, GJB, W, nmax, (int64_t)GJB * nmax, 0, 0);
     if (timed) timing_end(p, QAX_K_INVERT_UPDATE);
   }
   hipLaunchKernelGGL(gj_unpivot_kernel<T>, dim3((nmax + 255) / 256, batch), dim3(256), 0, s, d_mats,

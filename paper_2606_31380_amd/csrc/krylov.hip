@@ -63,6 +63,10 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
   const int r = blockIdx.z;
   const double hx = active ? xhat[3 * i] : 0.0, hy = active ? xhat[3 * i + 1] : 0.0,
                hz = active ? xhat[3 * i + 2] : 0.0;
+  // phase -k x.y / 2 pi in revolutions and k x, per direction
+  const double kr = -k / TWO_PI;
+  const double px = kr * hx, py = kr * hy, pz = kr * hz;
+  const double qx = k * hx, qy = k * hy, qz = k * hz;
   const int64_t c0 = n0 * blockIdx.y / slots, c1 = n0 * (blockIdx.y + 1) / slots;
   __shared__ double sx[TPB], sy[TPB], sz[TPB], sax[TPB], say[TPB], saz[TPB], sew[TPB];
   __shared__ double2 smu[TPB];
@@ -78,24 +82,27 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
       smu[tid] = mu[j * nrhs + r];
     }
     __syncthreads();
-    for (int jj = 0; jj < cnt; ++jj) {
-      const double ph = -k * (hx * sx[jj] + hy * sy[jj] + hz * sz[jj]);
-      double s, c;
-      sincos_cw(ph, &s, &c);
-      double fr, fi;
-      if (form == 2) {
-        fr = sew[jj] * c;
-        fi = sew[jj] * s;
-      } else {
-        // (-i k nd)(c + i s) = k nd s - i k nd c; combined field adds
-        // (-i eta |aw|)(c + i s) = eta |aw| s - i eta |aw| c
-        const double nd = hx * sax[jj] + hy * say[jj] + hz * saz[jj];
-        fr = fma(k * nd, s, sew[jj] * s);
-        fi = -fma(k * nd, c, sew[jj] * c);
+    if (form == 2) {
+      for (int jj = 0; jj < cnt; ++jj) {
+        double s, c;
+        sincos_2pi(fma(px, sx[jj], fma(py, sy[jj], pz * sz[jj])), &s, &c);
+        const double fr = sew[jj] * c, fi = sew[jj] * s;
+        const double2 m = smu[jj];
+        ar = fma(fr, m.x, fma(-fi, m.y, ar));
+        ai = fma(fr, m.y, fma(fi, m.x, ai));
       }
-      const double2 m = smu[jj];
-      ar += fr * m.x - fi * m.y;
-      ai += fr * m.y + fi * m.x;
+    } else {
+      for (int jj = 0; jj < cnt; ++jj) {
+        double s, c;
+        sincos_2pi(fma(px, sx[jj], fma(py, sy[jj], pz * sz[jj])), &s, &c);
+        // (-i k nd)(c + i s) = k nd s - i k nd c; combined field adds
+        // (-i eta |aw|)(c + i s) = eta |aw| s - i eta |aw| c (ew = 0 otherwise)
+        const double a = fma(qx, sax[jj], fma(qy, say[jj], fma(qz, saz[jj], sew[jj])));
+        const double fr = a * s, fi = -a * c;
+        const double2 m = smu[jj];
+        ar = fma(fr, m.x, fma(-fi, m.y, ar));
+        ai = fma(fr, m.y, fma(fi, m.x, ai));
+      }
     }
   }
   if (active)
