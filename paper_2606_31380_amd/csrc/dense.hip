@@ -127,18 +127,21 @@ __global__ __launch_bounds__(256) void block_gemv_f32_lds_kernel(
     __syncthreads();
     for (int q = threadIdx.x; q < cn; q += 256) vs[q] = vb[c0 + q];
     __syncthreads();
+    // the wavefront's rows side by side: their loads in flight together and
+    // each staged entry of the vector read once for all of them
+    const float* a = pool + 2 * (K.elem_off + (row0 + wave * (GV_ROWS / 4) - B.off) * n + c0);
+    for (int j0 = lane * VEC; j0 < cn; j0 += 64 * VEC) {
+      vec_t av[GV_ROWS / 4];
 #pragma unroll
-    for (int rr = 0; rr < GV_ROWS / 4; ++rr) {
-      const int64_t lr = row0 + wave * (GV_ROWS / 4) + rr - B.off;
-      const float* a = pool + 2 * (K.elem_off + lr * n + c0);
-      for (int j0 = lane * VEC; j0 < cn; j0 += 64 * VEC) {
-        const vec_t av = *(const vec_t*)(a + 2 * j0);
+      for (int rr = 0; rr < GV_ROWS / 4; ++rr) av[rr] = *(const vec_t*)(a + 2 * ((int64_t)rr * n + j0));
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) {
-          const double mr = (double)av[2 * q], mi = (double)av[2 * q + 1];
-          const double2 x = vs[j0 + q];
-          ar[rr] += mr * x.x - mi * x.y;
-          ai[rr] += mr * x.y + mi * x.x;
+      for (int q = 0; q < VEC; ++q) {
+        const double2 x = vs[j0 + q];
+#pragma unroll
+        for (int rr = 0; rr < GV_ROWS / 4; ++rr) {
+          const double mr = (double)av[rr][2 * q], mi = (double)av[rr][2 * q + 1];
+          ar[rr] = fma(mr, x.x, fma(-mi, x.y, ar[rr]));
+          ai[rr] = fma(mr, x.y, fma(mi, x.x, ai[rr]));
         }
       }
     }

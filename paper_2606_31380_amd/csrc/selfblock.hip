@@ -141,19 +141,44 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Coefficients of the recurrence leg_recur with the division folded in,
+// exact ratios rounded once at compile time; the index n is the same in every
+// lane, so the kernels read them with scalar loads:
+//   forward   Q_{n+1/2} = chi fa[n] Q_{n-1/2} - fb[n] Q_{n-3/2},
+//             fa[n] = 4n / (2n + 1), fb[n] = (2n - 1) / (2n + 1)   (f[n]);
+//   backward  Q_{n-3/2} = chi ba[n] Q_{n-1/2} - bb[n] Q_{n+1/2},
+//             ba[n] = 4n / (2n - 1), bb[n] = (2n + 1) / (2n - 1)   (b[n]).
+constexpr int QREC_MAX = 1024;
+struct QRecTables {
+  double2 f[QREC_MAX + 1];   // (fa, fb)
+  double2 b[QREC_MAX + 1];   // (ba, bb)
+};
+constexpr QRecTables make_qrec() {
+  QRecTables t{};
+  for (int n = 1; n <= QREC_MAX; ++n) {
+    const double d = n;
+    t.f[n].x = 4.0 * d / (2.0 * d + 1.0);
+    t.f[n].y = (2.0 * d - 1.0) / (2.0 * d + 1.0);
+    t.b[n].x = 4.0 * d / (2.0 * d - 1.0);
+    t.b[n].y = (2.0 * d + 1.0) / (2.0 * d - 1.0);
+  }
+  return t;
+}
+__constant__ QRecTables qrec = make_qrec();
+
 // Q[n][col] = Q_{n-1/2}(chi), n = 0..mq, for the node of each lane with `act`
 // (one batch of nodes, one node per lane).  Starting values Q_{-1/2} = mu K,
 // Q_{1/2} = chi mu K - sqrt(2 (chi + 1)) E (K, E of modulus mu by the AGM).
 // Where m acosh(chi) stays small the recurrence leg_recur runs forward; else
 // Miller's backward recurrence from one common start index for the batch
 // (20 / acosh(chi) + 10 beyond mq for the slowest-decaying lane, which only
-// adds accuracy for the others; values above 1e150 are rescaled while no
-// entry is stored yet), normalised by Q_{-1/2}.  The recurrence index is the
-// same in every lane, so the reciprocals 1/(2n +- 1) are computed 64 at a time
-// across lanes and read back with v_readlane.
-__device__ void toroidal_q_batch(bool act, double chi, double chim1, int mq, double (*Q)[QB],
-                                 int col) {
-  const int lane = threadIdx.x;
+// adds accuracy for the others; at most 9 mq + 19 since backward lanes have
+// acosh(chi) > 2.5 / (mq + 1); values above 1e150 are rescaled while no entry
+// is stored yet), normalised by Q_{-1/2}.  One dependent fma per step: the
+// coefficients come from qrec and the older term's product is formed a step
+// ahead.
+__device__ __forceinline__ void toroidal_q_batch(bool act, double chi, double chim1, int mq,
+                                                 double (*Q)[QB], int col) {
   if (!act) {
     chi = 2.0;
     chim1 = 1.0;
@@ -172,47 +197,50 @@ __device__ void toroidal_q_batch(bool act, double chi, double chim1, int mq, dou
       Q[0][col] = q0;
       Q[1][col] = q1;
     }
-    double qm = q0, qn = q1, dn = 1.0;
-    // 1/(2n + 1) for 64 consecutive n at a time, one per lane, read back
-    // lane by lane (the index is the same in every lane)
-    for (int nb = 1; nb < mq; nb += 64) {
-      const double invl = recip(2.0 * (nb + lane) + 1.0);
-      const int cnt = min(64, mq - nb);
-      for (int q = 0; q < cnt; ++q) {
-        const double qp = (4.0 * dn * chi * qn - (2.0 * dn - 1.0) * qm) * readlane_f64(invl, q);
-        if (fwd) Q[nb + q + 1][col] = qp;
-        qm = qn;
-        qn = qp;
-        dn += 1.0;
-      }
+    double qm = q0, qn = q1;
+    const double2* tf = qrec.f;
+#pragma unroll 4
+    for (int n = 1; n < mq; ++n) {
+      const double2 c = tf[n];
+      const double qp = fma(chi * c.x, qn, -c.y * qm);
+      if (fwd) Q[n + 1][col] = qp;
+      qm = qn;
+      qn = qp;
     }
   }
-  // backward lanes: a > 2.5 / (mq + 1), so 20 / a + 10 < 8 (mq + 1) + 10
   int start = bwd ? mq + (int)ceil(20.0 / a) + 10 : 0;
-  start = wave_max_int(start);
+  start = __builtin_amdgcn_readfirstlane(min(wave_max_int(start), QREC_MAX));
   if (start > 0) {
-    double hi = 0.0, lo = 1e-200, dn = start;
-    for (int nb = start; nb >= 1; nb -= 64) {
-      // 1/(2n - 1) for n = nb, nb - 1, ..., one per lane
-      const double invl = recip(2.0 * (nb - lane) - 1.0);
-      const int cnt = min(64, nb);
-      for (int q = 0; q < cnt; ++q) {
-        const int n = nb - q;
-        if (n <= mq && bwd) Q[n][col] = lo;
-        const double nw = (4.0 * dn * chi * lo - (2.0 * dn + 1.0) * hi) * readlane_f64(invl, q);
-        hi = lo;
-        lo = nw;
-        dn -= 1.0;
-      }
-      if (nb - cnt > mq && fabs(lo) > 1e150) {   // nothing stored yet: rescale
+    double hi = 0.0, lo = 1e-200;
+    const double2* tb = qrec.b;
+    auto step = [&](double2 c) {
+      const double nw = fma(chi * c.x, lo, -c.y * hi);
+      hi = lo;
+      lo = nw;
+    };
+    int n = start;
+    // no entry stored yet: 16 steps between checks for rescaling, their
+    // coefficients loaded first
+    for (; n > mq + 16; n -= 16) {
+      double2 c[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) c[u] = tb[n - u];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) step(c[u]);
+      if (fabs(lo) > 1e150) {
         lo *= 1e-150;
         hi *= 1e-150;
       }
     }
+    for (; n > mq; --n) step(tb[n]);
+    for (; n >= 1; --n) {
+      if (bwd) Q[n][col] = lo;
+      step(tb[n]);
+    }
     if (bwd) {
       const double scale = q0 / lo;
       Q[0][col] = q0;
-      for (int n = 1; n <= mq; ++n) Q[n][col] *= scale;
+      for (int m = 1; m <= mq; ++m) Q[m][col] *= scale;
     }
   }
 }
