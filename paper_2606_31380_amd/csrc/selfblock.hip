@@ -346,10 +346,11 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// Hs = (x cos x - sin x)/(4 pi rho^3), x = k rho, given sx = sin x, cx = cos x;
+// Hs = (x cos x - sin x)/(4 pi rho^3), x = k rho, given irho = 1 / rho,
+// sx = sin x, cx = cos x;
 // for x < 0.5 the Taylor series sum_{j>=1} (-1)^j 2j/(2j+1)! x^{2j-2} (times
 // k^3 / 4 pi), which avoids the cancellation.
-__device__ __forceinline__ double smooth_h(double k, double rho, double sx, double cx) {
+__device__ __forceinline__ double smooth_h(double k, double rho, double irho, double sx, double cx) {
   const double x = k * rho;
   if (x < 0.5) {
     const double x2 = x * x;
@@ -367,8 +368,7 @@ __device__ __forceinline__ double smooth_h(double k, double rho, double sx, doub
     p = fma(p, x2, -0.3333333333333333);
     return k * k * k * INV_4PI * p;
   }
-  const double ir = 1.0 / rho;
-  return (x * cx - sx) * INV_4PI * ir * ir * ir;
+  return (x * cx - sx) * INV_4PI * irho * irho * irho;
 }
 
 // phi-frame modes m = 0..nmax of A = dr G, B = dz G for one node (all lanes),
@@ -384,16 +384,19 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
   const double chi = 1.0 + chim1;
   int nf = 0;
   if (k != 0.0) {
+    const double k2pi = k / TWO_PI;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int l = lane + 64 * h;
       // sin(phi/2) with phi = 2 pi l / LM from the table e^{-2 pi i q / LD}
       const double sh = -tw[l * (LD / (2 * LM))].y;
-      const double rho = sqrt(2.0 * r * rt * (chim1 + 2.0 * sh * sh));
+      const double rho2 = 2.0 * r * rt * (chim1 + 2.0 * sh * sh);
+      const double irho = rsqrt_pos(rho2);
+      const double rho = rho2 * irho;
       double sk, ck;
-      sincos_cw(k * rho, &sk, &ck);
+      sincos_2pi(rho * k2pi, &sk, &ck);
       const double F = ck + k * rho * sk;
-      const double Hs = smooth_h(k, rho, sk, ck);
+      const double Hs = smooth_h(k, rho, irho, sk, ck);
       const double cphi = 1.0 - 2.0 * sh * sh;
       M.fa[l] = make_double2(F, Hs);
       M.fb[l] = make_double2(Hs * (r - rt * cphi), CF ? ck : 0.0);
@@ -448,6 +451,7 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
     } else {
       // F^ is even in n: (F^ * g)_m = F^_0 g_m + sum_{n>=1} F^_n (g_{|m-n|} + g_{m+n})
       double ar = M.Fh[0] * ab.x, br = M.Fh[0] * ab.y;
+#pragma unroll 4
       for (int n = 1; n <= nf; ++n) {
         const double f = M.Fh[n];
         const double2 u = M.AB0[abs(lane - n)], v = M.AB0[lane + n];
@@ -458,6 +462,7 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
       M.Bm[lane] = make_double2(br * (1.0 / TWO_PI), -c * M.Hh[lane]);
       if constexpr (CF) {
         double gr = M.Ch[0] * M.G0[lane];
+#pragma unroll 4
         for (int n = 1; n <= nf; ++n) gr = fma(M.Ch[n], M.G0[abs(lane - n)] + M.G0[lane + n], gr);
         M.Gm[lane] = make_double2(gr * (1.0 / TWO_PI), M.Sh[lane]);
       }
@@ -841,6 +846,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     // ---- direct route: trapezoidal rule on L azimuths of the kernel itself,
     // its modes by FFT
     const unsigned long long dmask = ~mmask & __ballot(onode);
+    const double k2pi = k / TWO_PI;
     const unsigned long long wmask = __ballot(wide);
     for (int q = 0; q < 64; ++q) {
       if (!((dmask >> q) & 1ull)) continue;
@@ -862,11 +868,11 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
           const double dx = cv.r * cth + cv.p - xT, dy = cv.r * sth + cv.q - yT, dz = cv.z - zT;
           const double nx = cv.r * cv.dz * cth, ny = cv.r * cv.dz * sth;
           const double nz = -cv.r * (cv.dr + cv.dp * cth + cv.dq * sth);
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          const double ir = rsqrt(r2);
+          const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+          const double ir = rsqrt_pos(r2);
           const double rr = r2 * ir;
           double s, c;
-          sincos_cw(k * rr, &s, &c);
+          sincos_2pi(rr * k2pi, &s, &c);
           const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI;
           S.u.K[0][l] = make_double2(-fma(k * rr, s, c) * sc, fma(k * rr, c, -s) * sc);
           if constexpr (CF) S.u.K[CF ? 1 : 0][l] = make_double2(c * ir * INV_4PI, s * ir * INV_4PI);
