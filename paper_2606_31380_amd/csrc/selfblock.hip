@@ -270,22 +270,31 @@ __device__ __forceinline__ void dft4(double2& a0, double2& a1, double2& a2, doub
 }
 
 // One radix-4 pass of an L-point transform; butterfly j in lanes with `active`.
-template <int L>
-__device__ __forceinline__ void r4_pass(double2* x, int j, int Ns, bool active, const double2* tw) {
-  double2 a0, a1, a2, a3;
+// The twiddles (a read-only table) are read together with the data, before
+// the barrier; the first pass (Ns = 1) has none.
+template <int L, int Ns>
+__device__ __forceinline__ void r4_pass(double2* x, int j, bool active, const double2* tw) {
+  double2 a0, a1, a2, a3, w1, w2, w3;
+  const int k = j & (Ns - 1);
   if (active) {
     a0 = x[j];
     a1 = x[j + L / 4];
     a2 = x[j + L / 2];
     a3 = x[j + 3 * L / 4];
+    if (Ns > 1) {
+      constexpr int step = LD / (4 * Ns);
+      w1 = tw[k * step];
+      w2 = tw[2 * k * step];
+      w3 = tw[3 * k * step];
+    }
   }
   __syncthreads();
   if (active) {
-    const int k = j & (Ns - 1);
-    const int step = LD / (4 * Ns);
-    a1 = cmul(a1, tw[k * step]);
-    a2 = cmul(a2, tw[2 * k * step]);
-    a3 = cmul(a3, tw[3 * k * step]);
+    if (Ns > 1) {
+      a1 = cmul(a1, w1);
+      a2 = cmul(a2, w2);
+      a3 = cmul(a3, w3);
+    }
     dft4(a0, a1, a2, a3);
     const int o = 4 * (j - k) + k;
     x[o] = a0;
@@ -311,9 +320,9 @@ __device__ void fft128x2(double2* xa, double2* xb, const double2* tw) {
   const int lane = threadIdx.x;
   double2* x = lane < 32 ? xa : xb;
   const int j = lane & 31;
-  r4_pass<128>(x, j, 1, true, tw);
-  r4_pass<128>(x, j, 4, true, tw);
-  r4_pass<128>(x, j, 16, true, tw);
+  r4_pass<128, 1>(x, j, true, tw);
+  r4_pass<128, 4>(x, j, true, tw);
+  r4_pass<128, 16>(x, j, true, tw);
   r2_last128(xa, lane, tw);
   r2_last128(xb, lane, tw);
   __syncthreads();
@@ -321,19 +330,19 @@ __device__ void fft128x2(double2* xa, double2* xb, const double2* tw) {
 
 __device__ void fft128(double2* x, const double2* tw) {
   const int lane = threadIdx.x;
-  r4_pass<128>(x, lane, 1, lane < 32, tw);
-  r4_pass<128>(x, lane, 4, lane < 32, tw);
-  r4_pass<128>(x, lane, 16, lane < 32, tw);
+  r4_pass<128, 1>(x, lane, lane < 32, tw);
+  r4_pass<128, 4>(x, lane, lane < 32, tw);
+  r4_pass<128, 16>(x, lane, lane < 32, tw);
   r2_last128(x, lane, tw);
   __syncthreads();
 }
 
 __device__ void fft256(double2* x, const double2* tw) {
   const int lane = threadIdx.x;
-  r4_pass<256>(x, lane, 1, true, tw);
-  r4_pass<256>(x, lane, 4, true, tw);
-  r4_pass<256>(x, lane, 16, true, tw);
-  r4_pass<256>(x, lane, 64, true, tw);
+  r4_pass<256, 1>(x, lane, true, tw);
+  r4_pass<256, 4>(x, lane, true, tw);
+  r4_pass<256, 16>(x, lane, true, tw);
+  r4_pass<256, 64>(x, lane, true, tw);
 }
 
 __device__ __forceinline__ double wave_min(double v) {
