@@ -6,7 +6,8 @@ summary used by bench.py (HBM traffic per launch) and the markdown table.
 <dir> holds the sub-directories trace/ (--kernel-trace --stats), fetch/
 (--pmc FETCH_SIZE), write/ (--pmc WRITE_SIZE), valu32/ (F32 VALU instruction
 counters), valu64/ (F64 VALU and MFMA counters) and, when present, mfma32/
-(SQ_INSTS_VALU_MFMA_MOPS_F32), each with run_*.csv.  The
+(SQ_INSTS_VALU_MFMA_MOPS_F32), each with run_*.csv (trace/ also with
+run_kernel_trace.csv).  The
 memory counters are scaled by what they read for the calibration kernel
 (y = 2 x over 2^27 doubles: 1 GiB read and 1 GiB written).  FLOP counts take
 64 lanes per VALU instruction and two flops per FMA; MFMA MOPS count 512
@@ -25,15 +26,18 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CAL_BYTES = 1 << 30
 
-# timing kind -> (kernel name pattern as rocprofv3 prints it, source file); the
-# single-right-hand-side instance with the most launches is taken
+# timing kind -> (kernel name pattern as rocprofv3 prints it, source file,
+# largest grids only); the single-right-hand-side instance with the most
+# launches is taken.  The inversion's update kernel also runs the small
+# updates inside the panel factorization: the trailing updates are its
+# dispatches with the largest grid.
 KINDS = {
-    "pair_sum_fp32": (r"qax::pair_sum_f32_kernel<\d+, 1, 0>", "paper_2606_31380_amd/csrc/pairsum.hip"),
-    "pair_sum_fp64": (r"qax::pair_sum_f64_kernel<\d+, 1, 0>", "paper_2606_31380_amd/csrc/pairsum.hip"),
-    "block_apply": (r"qax::block_gemv_kernel<double, 1, \d, \d+>", "paper_2606_31380_amd/csrc/dense.hip"),
-    "block_apply_f32": (r"qax::block_gemv_f32_lds_kernel<\d>", "paper_2606_31380_amd/csrc/dense.hip"),
-    "self_assembly": (r"qax::assemble_self_kernel<0>", "paper_2606_31380_amd/csrc/selfblock.hip"),
-    "invert_update": (r"qax::gjm_update_kernel<float>", "paper_2606_31380_amd/csrc/dense.hip"),
+    "pair_sum_fp32": (r"qax::pair_sum_f32_kernel<\d+, 1, 0>", "paper_2606_31380_amd/csrc/pairsum.hip", False),
+    "pair_sum_fp64": (r"qax::pair_sum_f64_kernel<\d+, 1, 0>", "paper_2606_31380_amd/csrc/pairsum.hip", False),
+    "block_apply": (r"qax::block_gemv_kernel<double, 1, \d, \d+>", "paper_2606_31380_amd/csrc/dense.hip", False),
+    "block_apply_f32": (r"qax::block_gemv_f32_lds_kernel<\d>", "paper_2606_31380_amd/csrc/dense.hip", False),
+    "self_assembly": (r"qax::assemble_self_kernel<0>", "paper_2606_31380_amd/csrc/selfblock.hip", False),
+    "invert_update": (r"qax::gjm_update_kernel<float>", "paper_2606_31380_amd/csrc/dense.hip", True),
 }
 
 
@@ -42,15 +46,39 @@ def short(name: str) -> str:
     return name.replace("void ", "").strip()
 
 
-def load_counters(path):
-    agg = collections.defaultdict(lambda: collections.defaultdict(float))
-    disp = collections.defaultdict(set)
+def load_counters(path, largest=False):
+    """Per kernel name: counter values averaged over its dispatches (with
+    largest, over the dispatches of its largest grid only)."""
+    rows = collections.defaultdict(list)
     with open(path) as f:
         for r in csv.DictReader(f):
-            k = short(r["Kernel_Name"])
-            agg[k][r["Counter_Name"]] += float(r["Counter_Value"])
-            disp[k].add(r["Dispatch_Id"])
-    return {k: {c: v / len(disp[k]) for c, v in d.items()} for k, d in agg.items()}
+            rows[short(r["Kernel_Name"])].append(r)
+    out = {}
+    for k, rs in rows.items():
+        if largest:
+            g = max(int(r["Grid_Size"]) for r in rs)
+            rs = [r for r in rs if int(r["Grid_Size"]) == g]
+        agg = collections.defaultdict(float)
+        for r in rs:
+            agg[r["Counter_Name"]] += float(r["Counter_Value"])
+        n = len({r["Dispatch_Id"] for r in rs})
+        out[k] = {c: v / n for c, v in agg.items()}
+    return out
+
+
+def trace_largest(path):
+    """Per kernel name: (calls, average us) over the dispatches of its largest grid."""
+    d = collections.defaultdict(list)
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            d[short(r["Kernel_Name"])].append((g, int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    out = {}
+    for k, v in d.items():
+        g = max(x[0] for x in v)
+        ts = [x[1] for x in v if x[0] == g]
+        out[k] = (len(ts), sum(ts) / len(ts) / 1e3)
+    return out
 
 
 def sha256(rel):
@@ -63,17 +91,22 @@ def main(d, out_json, out_md):
     with open(os.path.join(d, "trace", "run_kernel_stats.csv")) as f:
         for r in csv.DictReader(f):
             trace[short(r["Name"])] = (int(r["Calls"]), float(r["AverageNs"]) / 1e3)
-    fetch = load_counters(os.path.join(d, "fetch", "run_counter_collection.csv"))
-    write = load_counters(os.path.join(d, "write", "run_counter_collection.csv"))
-    v32 = load_counters(os.path.join(d, "valu32", "run_counter_collection.csv"))
-    v64 = load_counters(os.path.join(d, "valu64", "run_counter_collection.csv"))
-    m32_path = os.path.join(d, "mfma32", "run_counter_collection.csv")
-    m32 = load_counters(m32_path) if os.path.exists(m32_path) else {}
+    passes = {"fetch": "fetch", "write": "write", "v32": "valu32", "v64": "valu64", "m32": "mfma32"}
+    cnt = {}
+    for largest in (False, True):
+        for key, sub in passes.items():
+            path = os.path.join(d, sub, "run_counter_collection.csv")
+            cnt[key, largest] = load_counters(path, largest) if os.path.exists(path) else {}
+    fetch, write = cnt["fetch", False], cnt["write", False]
+    tlarge = trace_largest(os.path.join(d, "trace", "run_kernel_trace.csv"))
     cal = next(k for k in fetch if "MulFunctor" in k)
     f_fetch = CAL_BYTES / (fetch[cal]["FETCH_SIZE"] * 1024)
     f_write = CAL_BYTES / (write[cal]["WRITE_SIZE"] * 1024)
 
-    def row(k):
+    def row(k, largest=False):
+        fetch, write = cnt["fetch", largest], cnt["write", largest]
+        v32, v64, m32 = cnt["v32", largest], cnt["v64", largest], cnt["m32", largest]
+        tr = tlarge if largest else trace
         g = v32.get(k, {})
         h = v64.get(k, {})
         f32 = 64 * (g.get("SQ_INSTS_VALU_ADD_F32", 0) + g.get("SQ_INSTS_VALU_MUL_F32", 0)
@@ -81,7 +114,7 @@ def main(d, out_json, out_md):
         f64 = 64 * (h.get("SQ_INSTS_VALU_ADD_F64", 0) + h.get("SQ_INSTS_VALU_MUL_F64", 0)
                     + h.get("SQ_INSTS_VALU_TRANS_F64", 0) + 2 * h.get("SQ_INSTS_VALU_FMA_F64", 0))
         return {
-            "calls": trace.get(k, (0, 0.0))[0], "avg_us": trace.get(k, (0, 0.0))[1],
+            "calls": tr.get(k, (0, 0.0))[0], "avg_us": tr.get(k, (0, 0.0))[1],
             "fetch_bytes": fetch.get(k, {}).get("FETCH_SIZE", 0.0) * 1024 * f_fetch,
             "write_bytes": write.get(k, {}).get("WRITE_SIZE", 0.0) * 1024 * f_write,
             "valu_insts": g.get("SQ_INSTS_VALU", 0.0), "valu_trans_f32": g.get("SQ_INSTS_VALU_TRANS_F32", 0.0),
@@ -94,11 +127,12 @@ def main(d, out_json, out_md):
                            "fetch_size_kib": fetch[cal]["FETCH_SIZE"], "write_size_kib": write[cal]["WRITE_SIZE"],
                            "fetch_factor": f_fetch, "write_factor": f_write},
            "kernels": {}}
-    for kind, (pattern, src) in KINDS.items():
+    for kind, (pattern, src, largest) in KINDS.items():
         names = [k for k in fetch if re.fullmatch(pattern, k)]
         if names:
             kname = max(names, key=lambda k: trace.get(k, (0, 0.0))[0])
-            out["kernels"][kind] = dict(row(kname), kernel=kname, source=src, source_sha256=sha256(src))
+            out["kernels"][kind] = dict(row(kname, largest), kernel=kname, source=src,
+                                        source_sha256=sha256(src), largest_grid_only=largest)
     with open(out_json, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
