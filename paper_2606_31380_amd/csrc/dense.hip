@@ -738,29 +738,69 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
 // [s0, s0 + ws) (already eliminated) applied to the sibling columns
 // [d0, d0 + wd): (1) their row interchanges, then the pivot rows copied to W;
 // (2) A[i][d0+j] = (i in [s0, s0+ws) ? 0 : A[i][d0+j]) + sum_p A[i][s0+p] W[p][j].
+//
+// (1) without a chain of dependent swaps: the interchanges P_k (rows k and
+// piv[k], k = s0, ..., s0 + ws - 1, in that order) leave in row p the row
+// sigma(p) = P_s0(P_s0+1(... P_last(p))), so each touched row p (the ws panel
+// rows and every other pivot row, once) is gathered from sigma(p) through LDS
+// and stored back, 16 columns at a time.  ws, wd <= 64.
+constexpr int GJN_SWAP_TPB = 256;
 template <typename T>
-__global__ void gjn_swap_copy_kernel(const MatDesc* __restrict__ mats, typename Cx<T>::V* __restrict__ pool,
-                                     int s0, int ws, int d0, int wd,
-                                     const int32_t* __restrict__ piv, int nmax,
-                                     typename Cx<T>::V* __restrict__ W) {
+__global__ __launch_bounds__(GJN_SWAP_TPB) void gjn_swap_copy_kernel(
+    const MatDesc* __restrict__ mats, typename Cx<T>::V* __restrict__ pool, int s0, int ws, int d0,
+    int wd, const int32_t* __restrict__ piv, int nmax, typename Cx<T>::V* __restrict__ W) {
   typedef typename Cx<T>::V V;
   const MatDesc M = mats[blockIdx.x];
   const int n = M.n;
-  const int j = d0 + threadIdx.x;
-  if (s0 >= n || threadIdx.x >= wd || j >= n) return;
+  if (s0 >= n) return;
   V* A = pool + M.elem_off;
   V* Wm = W + (int64_t)blockIdx.x * GJB * GJB;
-  const int send = min(s0 + ws, n);
+  const int send = min(s0 + ws, n), wsv = send - s0;
+  const int wdv = min(d0 + wd, n) - d0;
   const int32_t* pv = piv + (int64_t)blockIdx.x * nmax;
-  for (int k = s0; k < send; ++k) {
-    const int pr = pv[k];
-    if (pr != k) {
-      const V t = A[(int64_t)k * n + j];
-      A[(int64_t)k * n + j] = A[(int64_t)pr * n + j];
-      A[(int64_t)pr * n + j] = t;
+  const int tid = threadIdx.x;
+  __shared__ int ps[64];
+  __shared__ int dst[128], src[128];   // touched rows (-1: none) and their sources
+  __shared__ V buf[128][16];
+  if (tid < wsv) ps[tid] = pv[s0 + tid];
+  __syncthreads();
+  if (tid < 2 * wsv) {
+    int p;
+    bool use = true;
+    if (tid < wsv) {
+      p = s0 + tid;                       // a panel row
+    } else {
+      const int q = tid - wsv;            // pivot row q, unless in the panel or seen before
+      p = ps[q];
+      use = p < s0 || p >= send;
+      for (int q2 = 0; q2 < q; ++q2) use = use && ps[q2] != p;
     }
+    int sg = p;
+    for (int kk = wsv - 1; kk >= 0; --kk) {
+      const int k = s0 + kk, pr = ps[kk];
+      sg = sg == k ? pr : (sg == pr ? k : sg);
+    }
+    dst[tid] = use ? p : -1;
+    src[tid] = sg;
   }
-  for (int k = s0; k < send; ++k) Wm[(k - s0) * GJB + threadIdx.x] = A[(int64_t)k * n + j];
+  __syncthreads();
+  const int np = 2 * wsv;
+  for (int c0 = 0; c0 < wdv; c0 += 16) {
+    const int cn = min(16, wdv - c0);
+    for (int e = tid; e < np * 16; e += GJN_SWAP_TPB) {
+      const int q = e >> 4, c = e & 15;
+      if (c < cn && dst[q] >= 0) buf[q][c] = A[(int64_t)src[q] * n + d0 + c0 + c];
+    }
+    __syncthreads();
+    for (int e = tid; e < np * 16; e += GJN_SWAP_TPB) {
+      const int q = e >> 4, c = e & 15;
+      if (c < cn && dst[q] >= 0) {
+        A[(int64_t)dst[q] * n + d0 + c0 + c] = buf[q][c];
+        if (q < wsv) Wm[q * GJB + c0 + c] = buf[q][c];
+      }
+    }
+    __syncthreads();
+  }
 }
 
 template <typename T>
@@ -1012,11 +1052,11 @@ static void gj_factor_panel(hipStream_t s, typename Cx<T>::V* pool, const MatDes
   const int h = w / 2;
   const unsigned rows_blocks = (unsigned)((nmax + (256 / h) - 1) / (256 / h));
   gj_factor_panel<T>(s, pool, d_mats, batch, nmax, c0, h, piv, Wn);
-  hipLaunchKernelGGL(gjn_swap_copy_kernel<T>, dim3(batch), dim3(h), 0, s, d_mats, pool, c0, h,
+  hipLaunchKernelGGL(gjn_swap_copy_kernel<T>, dim3(batch), dim3(GJN_SWAP_TPB), 0, s, d_mats, pool, c0, h,
                      c0 + h, h, piv, nmax, Wn);
   launch_half_update<T>(s, pool, d_mats, batch, nmax, c0, h, c0 + h, Wn, rows_blocks);
   gj_factor_panel<T>(s, pool, d_mats, batch, nmax, c0 + h, h, piv, Wn);
-  hipLaunchKernelGGL(gjn_swap_copy_kernel<T>, dim3(batch), dim3(h), 0, s, d_mats, pool, c0 + h, h,
+  hipLaunchKernelGGL(gjn_swap_copy_kernel<T>, dim3(batch), dim3(GJN_SWAP_TPB), 0, s, d_mats, pool, c0 + h, h,
                      c0, h, piv, nmax, Wn);
   launch_half_update<T>(s, pool, d_mats, batch, nmax, c0 + h, h, c0, Wn, rows_blocks);
 }
