@@ -650,11 +650,75 @@ __device__ __forceinline__ void slots_to_nodes(const SelfShared<CF>& S, int N,
 }
 
 template <bool CF>
-__device__ __forceinline__ void store_slots(SelfShared<CF>& S, const double2 (&acc)[GL_ORDER]) {
+__device__ __forceinline__ void store_slots(SelfShared<CF>& S, const double2 (&acc)[GL_ORDER], bool conj) {
   const int lane = threadIdx.x;
   const double f = lane == 0 ? 0.5 : 1.0;
+  const double fy = conj ? -f : f;
 #pragma unroll
-  for (int l = 0; l < GL_ORDER; ++l) S.acc[l][lane] = make_double2(acc[l].x * f, acc[l].y * f);
+  for (int l = 0; l < GL_ORDER; ++l) S.acc[l][lane] = make_double2(acc[l].x * f, acc[l].y * fy);
+}
+
+// One radix-4 Stockham pass (as r4_pass) over the NR rows X[l][0..L) at once:
+// NR L / 4 butterflies, NR L / 256 per lane, read before the barrier, written
+// after it.
+template <int L, int Ns, int NR>
+__device__ __forceinline__ void r4_pass_rows(double2 (*X)[64], const double2* tw) {
+  constexpr int NB = L / 4, NBT = NR * NB, PER = NBT >= 64 ? NBT / 64 : 1;
+  const int lane = threadIdx.x;
+  const bool act = NBT >= 64 || lane < NBT;
+  double2 a[PER][4], w[PER][3];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = lane + 64 * u, row = e / NB, j = e % NB;
+    if (!act) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[u][i] = X[row][j + i * NB];
+    if (Ns > 1) {
+      constexpr int step = LD / (4 * Ns);
+      const int k = j & (Ns - 1);
+#pragma unroll
+      for (int i = 1; i < 4; ++i) w[u][i - 1] = tw[i * k * step];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = lane + 64 * u, row = e / NB, j = e % NB;
+    if (!act) continue;
+    const int k = j & (Ns - 1);
+    if (Ns > 1) {
+#pragma unroll
+      for (int i = 1; i < 4; ++i) a[u][i] = cmul(a[u][i], w[u][i - 1]);
+    }
+    dft4(a[u][0], a[u][1], a[u][2], a[u][3]);
+    const int o = 4 * (j - k) + k;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) X[row][o + i * Ns] = a[u][i];
+  }
+  __syncthreads();
+}
+
+// slots_to_nodes for 2N = 16 or 64 (powers of 4): the inverse DFT of every
+// row as conj(FFT(conj(row))) (the rows were stored conjugated), then the
+// same scale and sign.
+template <int L>
+__device__ __forceinline__ void fft_rows(double2 (*X)[64], const double2* tw) {
+  r4_pass_rows<L, 1, GL_ORDER>(X, tw);
+  r4_pass_rows<L, 4, GL_ORDER>(X, tw);
+  if constexpr (L == 64) r4_pass_rows<L, 16, GL_ORDER>(X, tw);
+}
+
+template <bool CF>
+__device__ __forceinline__ void slots_to_nodes_fft(SelfShared<CF>& S, int N, double2 (&g)[GL_ORDER]) {
+  const int lane = threadIdx.x;
+  if (2 * N == 64) fft_rows<64>(S.acc, S.tw);
+  else fft_rows<16>(S.acc, S.tw);
+  const double scale = ((lane & 1) ? -1.0 : 1.0) / (2 * N);
+#pragma unroll
+  for (int l = 0; l < GL_ORDER; ++l) {
+    const double2 v = lane < 2 * N ? S.acc[l][lane] : make_double2(0.0, 0.0);
+    g[l] = make_double2(v.x * scale, -v.y * scale);
+  }
 }
 
 // One work item = one target row T and one source panel ip of a block.
@@ -914,19 +978,23 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     }
   }
   __syncthreads();   // the recurrence batches are done with S.Q (shares S.acc)
-  store_slots(S, acc);
+  // inverse DFT over the 2N slots: radix-4 FFT passes when 2N is 16 or 64
+  const bool fft_inv = 2 * N == 64 || 2 * N == 16;
+  store_slots(S, acc, fft_inv);
   __syncthreads();
   double2 g[GL_ORDER];
-  if (lane < 2 * N) slots_to_nodes(S, N, g);
+  if (fft_inv) slots_to_nodes_fft(S, N, g);
+  else if (lane < 2 * N) slots_to_nodes(S, N, g);
   if constexpr (CF) {
     // single layer: second inverse DFT, then - i eta |J| (combined field) or
     // |J| (single layer) at the column node
     __syncthreads();
-    store_slots(S, acs);
+    store_slots(S, acs, fft_inv);
     __syncthreads();
+    double2 gs[GL_ORDER];
+    if (fft_inv) slots_to_nodes_fft(S, N, gs);
+    else if (lane < 2 * N) slots_to_nodes(S, N, gs);
     if (lane < 2 * N) {
-      double2 gs[GL_ORDER];
-      slots_to_nodes(S, N, gs);
       double sj, cj;
       sincos_cw(lane * PI / N, &sj, &cj);
 #pragma unroll
