@@ -921,12 +921,9 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     const unsigned long long dmask = ~mmask & __ballot(onode);
     const double k2pi = k / TWO_PI;
     const unsigned long long wmask = __ballot(wide);
-    for (int q = 0; q < 64; ++q) {
-      if (!((dmask >> q) & 1ull)) continue;
-      const bool w256 = (wmask >> q) & 1ull;
-      const int L = w256 ? LD : LD / 2;
+    // samples of node q at L azimuths into S.u.K[part][base + l]
+    auto sample = [&](int q, int L, int base) {
       const int tstep = LD / L;
-      const double wq = readlane_f64(w, q);
       const NodeLoc Lq = read_node(Lme, q);
       Curve cv;
       cv.r = Lq.r; cv.dr = Lq.dr; cv.z = Lq.z; cv.dz = Lq.dz;
@@ -947,23 +944,23 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
           double s, c;
           sincos_2pi(rr * k2pi, &s, &c);
           const double sc = (dx * nx + dy * ny + dz * nz) * ir * ir * ir * INV_4PI;
-          S.u.K[0][l] = make_double2(-fma(k * rr, s, c) * sc, fma(k * rr, c, -s) * sc);
-          if constexpr (CF) S.u.K[CF ? 1 : 0][l] = make_double2(c * ir * INV_4PI, s * ir * INV_4PI);
+          S.u.K[0][base + l] = make_double2(-fma(k * rr, s, c) * sc, fma(k * rr, c, -s) * sc);
+          if constexpr (CF)
+            S.u.K[CF ? 1 : 0][base + l] = make_double2(c * ir * INV_4PI, s * ir * INV_4PI);
         }
       }
-      __syncthreads();
-      if (w256) fft256(S.u.K[0], S.tw); else fft128(S.u.K[0], S.tw);
-      if constexpr (CF) {
-        if (w256) fft256(S.u.K[CF ? 1 : 0], S.tw); else fft128(S.u.K[CF ? 1 : 0], S.tw);
-      }
-      // mode slot s = lane: m = s - N (slot 0 also takes m = +N), K_m = (2 pi / L) X[m mod L]
+    };
+    // mode slot s = lane of node q: m = s - N (slot 0 also takes m = +N),
+    // K_m = (2 pi / L) X[m mod L], accumulated with the node's weights
+    auto gather = [&](int q, int L, int base) {
+      const double wq = readlane_f64(w, q);
 #pragma unroll
       for (int part = 0; part < (CF ? 2 : 1); ++part) {
         double2 Kq = make_double2(0.0, 0.0);
         if (lane < 2 * N) {
-          Kq = S.u.K[part][(lane - N + L) & (L - 1)];
+          Kq = S.u.K[part][base + ((lane - N + L) & (L - 1))];
           if (lane == 0) {
-            const double2 v = S.u.K[part][N];
+            const double2 v = S.u.K[part][base + N];
             Kq.x += v.x;
             Kq.y += v.y;
           }
@@ -974,6 +971,32 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         if (part == 0) accumulate_node(acc, P, q, wq, Kq);
         else if constexpr (CF) accumulate_node(acs, P, q, wq, Kq);
       }
+    };
+    // nodes with 256 samples one at a time
+    for (unsigned long long dm = dmask & wmask; dm; dm &= dm - 1) {
+      const int q = __ffsll(dm) - 1;
+      sample(q, LD, 0);
+      __syncthreads();
+      fft256(S.u.K[0], S.tw);
+      if constexpr (CF) fft256(S.u.K[CF ? 1 : 0], S.tw);
+      gather(q, LD, 0);
+      __syncthreads();
+    }
+    // nodes with 128 samples two at a time, in the two halves of the buffer
+    // through one pair of interleaved transforms (an odd last node leaves the
+    // second half's result unused)
+    for (unsigned long long dm = dmask & ~wmask; dm;) {
+      const int q1 = __ffsll(dm) - 1;
+      dm &= dm - 1;
+      const int q2 = dm ? __ffsll(dm) - 1 : -1;
+      if (dm) dm &= dm - 1;
+      sample(q1, LD / 2, 0);
+      if (q2 >= 0) sample(q2, LD / 2, LD / 2);
+      __syncthreads();
+      fft128x2(S.u.K[0], S.u.K[0] + LD / 2, S.tw);
+      if constexpr (CF) fft128x2(S.u.K[CF ? 1 : 0], S.u.K[CF ? 1 : 0] + LD / 2, S.tw);
+      gather(q1, LD / 2, 0);
+      if (q2 >= 0) gather(q2, LD / 2, LD / 2);
       __syncthreads();
     }
   }
