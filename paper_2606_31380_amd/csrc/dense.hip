@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void block_gemv_kernel(
 // the FP64 vector (twice the bytes of an FP32 matrix entry) is read once per
 // GV_ROWS rows instead of once per row.  Blocks (orders multiples of 16) and
 // their offsets are multiples of GV_ROWS, so a workgroup never spans two.
-constexpr int GV_ROWS = 16, GV_CH = 2048;
+constexpr int GV_ROWS = 16, GV_CH = 1024;
 
 template <int VEC>
 __global__ __launch_bounds__(256) void block_gemv_f32_lds_kernel(

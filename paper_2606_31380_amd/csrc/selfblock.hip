@@ -520,12 +520,13 @@ __device__ __forceinline__ double2 modal_slot(int N, const NodeLoc& L, const Mod
   const int lane = threadIdx.x;
   double2 out = make_double2(0.0, 0.0);
   ks = make_double2(0.0, 0.0);
+  const double arev = L.alpha * (1.0 / TWO_PI);   // alpha in revolutions
   double sa, ca;
-  sincos_cw(L.alpha, &sa, &ca);
+  sincos_2pi(arev, &sa, &ca);
   if (lane < 2 * N) {
     const int m = lane - N;
     double s0, c0;
-    sincos_cw(-m * L.alpha, &s0, &c0);
+    sincos_2pi(-m * arev, &s0, &c0);
     out = theta_mode(m, c0, s0, ca, sa, L, M);
     if constexpr (CF) ks = cmul(make_double2(c0, s0), M.Gm[abs(m)]);
     if (lane == 0) {
