@@ -87,7 +87,8 @@ struct ModalScratch {
 template <bool CF>
 struct SelfShared {
   union {
-    double Q[MQ_CAP + 1][QB];     // toroidal functions of one recurrence batch
+    double Q[QB][MQ_CAP + 1];     // toroidal functions of one recurrence batch, node-major
+                                  // (odd row stride: conflict-free rows and columns)
     double2 acc[GL_ORDER][64];    // accumulated modes (final inverse DFT)
   };
   double2 tw[LD];               // e^{-2 pi i q / LD} (FFT twiddles, azimuth table)
@@ -166,7 +167,7 @@ constexpr QRecTables make_qrec() {
 }
 __constant__ QRecTables qrec = make_qrec();
 
-// Q[n][col] = Q_{n-1/2}(chi), n = 0..mq, for the node of each lane with `act`
+// Q[col][n] = Q_{n-1/2}(chi), n = 0..mq, for the node of each lane with `act`
 // (one batch of nodes, one node per lane).  Starting values Q_{-1/2} = mu K,
 // Q_{1/2} = chi mu K - sqrt(2 (chi + 1)) E (K, E of modulus mu by the AGM).
 // Where m acosh(chi) stays small the recurrence leg_recur runs forward; else
@@ -178,7 +179,7 @@ __constant__ QRecTables qrec = make_qrec();
 // coefficients come from qrec and the older term's product is formed a step
 // ahead.
 __device__ __forceinline__ void toroidal_q_batch(bool act, double chi, double chim1, int mq,
-                                                 double (*Q)[QB], int col) {
+                                                 double (*Q)[MQ_CAP + 1], int col) {
   if (!act) {
     chi = 2.0;
     chim1 = 1.0;
@@ -194,8 +195,8 @@ __device__ __forceinline__ void toroidal_q_batch(bool act, double chi, double ch
   const bool bwd = act && !fwd;
   if (__ballot(fwd)) {
     if (fwd) {
-      Q[0][col] = q0;
-      Q[1][col] = q1;
+      Q[col][0] = q0;
+      Q[col][1] = q1;
     }
     double qm = q0, qn = q1;
     const double2* tf = qrec.f;
@@ -203,7 +204,7 @@ __device__ __forceinline__ void toroidal_q_batch(bool act, double chi, double ch
     for (int n = 1; n < mq; ++n) {
       const double2 c = tf[n];
       const double qp = fma(chi * c.x, qn, -c.y * qm);
-      if (fwd) Q[n + 1][col] = qp;
+      if (fwd) Q[col][n + 1] = qp;
       qm = qn;
       qn = qp;
     }
@@ -234,13 +235,13 @@ __device__ __forceinline__ void toroidal_q_batch(bool act, double chi, double ch
     }
     for (; n > mq; --n) step(tb[n]);
     for (; n >= 1; --n) {
-      if (bwd) Q[n][col] = lo;
+      if (bwd) Q[col][n] = lo;
       step(tb[n]);
     }
     if (bwd) {
       const double scale = q0 / lo;
-      Q[0][col] = q0;
-      for (int m = 1; m <= mq; ++m) Q[m][col] *= scale;
+      Q[col][0] = q0;
+      for (int m = 1; m <= mq; ++m) Q[col][m] *= scale;
     }
   }
 }
@@ -387,7 +388,7 @@ __device__ __forceinline__ double smooth_h(double k, double rho, double irho, do
 // i times the modes of sin(k rho) / (4 pi rho).
 template <bool CF>
 __device__ void modal_modes(double k, double r, double rt, double c, double chim1, double rmrt,
-                            int nmax, const double (*Q)[QB], int col, ModalScratch<CF>& M,
+                            int nmax, const double (*Q)[MQ_CAP + 1], int col, ModalScratch<CF>& M,
                             const double2* tw) {
   const int lane = threadIdx.x;
   const double chi = 1.0 + chim1;
@@ -444,8 +445,8 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
   const double drchi = (rmrt * (r + rt) - c * c) * 0.5 * irt * ir * ir;
   const double dzchi = -c * ir * irt;
   for (int n = lane; n <= mtot; n += 64) {
-    const double qn = Q[n][col];
-    const double qm = n == 0 ? Q[1][col] : Q[n - 1][col];
+    const double qn = Q[col][n];
+    const double qm = n == 0 ? Q[col][1] : Q[col][n - 1];
     const double qp = (2.0 * n - 1.0) * half_inv_chi2m1 * (chi * qn - qm);
     M.AB0[n] = make_double2(pref * (drchi * qp - 0.5 * ir * qn), pref * dzchi * qp);
     if constexpr (CF) M.G0[n] = pref * qn;
