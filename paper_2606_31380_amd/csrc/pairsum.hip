@@ -229,6 +229,10 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
     const float dx2 = 2.0f * dxf, dy2 = 2.0f * dyf, dz2 = 2.0f * dzf;
     const float d2f = (float)D2;
     const float dnf = (float)Dn;
+    // scaled set-up of the one-right-hand-side loop (k > 0): kappa = 2 pi / k
+    const double kap = k > 0.0 ? TWO_PI / k : 1.0;
+    const float kap2 = (float)(kap * kap), d2s = (float)(kap * kap * D2), dns = (float)(kap * Dn);
+    const float ck1 = (float)kap, ck2 = (float)(k * kap * kap), ck3 = (float)(kap * kap * kap);
     const float ph0 = (float)ph0d;
     for (int base = 0; base < nb; base += TPB) {
       const int cnt = min(TPB, nb - base);
@@ -245,44 +249,69 @@ __global__ __launch_bounds__(TPB) void pair_sum_f32_kernel(
         }
       }
       __syncthreads();
-      if (!own && NRC == 1 && FORM != 2) {
+      if (!own && NRC == 1 && FORM != 2 && k == 0.0) {
+        // Laplace (e = 1): -S1 (- i S3) with S1 = sum dot ir^3 mu
+        float ar = 0.0f, ai = 0.0f, er = 0.0f, ei = 0.0f;
+#pragma unroll 4
+        for (int jj = 0; jj < cnt; ++jj) {
+          const float4 yl = sloc[jj];
+          const float4 a4 = saw[jj];
+          const float num = fmaf(dx2, yl.x, fmaf(dy2, yl.y, fmaf(dz2, yl.z, yl.w)));
+          const float ir = __builtin_amdgcn_rsqf(d2f + num);
+          const float2 m = smu[jj];
+          const float dot = fmaf(a4.x, dxf, fmaf(a4.y, dyf, fmaf(a4.z, dzf, a4.w)));
+          const float sc = dot * ir * ir * ir;
+          ar = fmaf(sc, m.x, ar);
+          ai = fmaf(sc, m.y, ai);
+          if constexpr (FORM == 1) {
+            const float t = sew[jj] * ir;
+            er = fmaf(t, m.x, er);
+            ei = fmaf(t, m.y, ei);
+          }
+        }
+        two_sum(sr[0], cr[0], ei - ar);
+        two_sum(si[0], ci[0], -ai - er);
+      } else if (!own && NRC == 1 && FORM != 2) {
         // one right-hand side: with e = e^{ikr}, z = e mu and r ir = 1 the
         // double-layer term is (ikr - 1) e (aw . (y - x)) / r^3 mu
         // = -sc z + i k u z, sc = dot ir^3, u = dot ir^2, so the tile sums
         // S1 = sum sc z and S2 = sum u z need neither r nor kr
-        // (combined-field: - i eta G |aw| mu = - i t z, t = eta |aw| ir)
+        // (combined-field: - i eta G |aw| mu = - i t z, t = eta |aw| ir).
+        // Distances scaled by kappa = 2 pi / k: r'^2 = kappa^2 (|D|^2 + num),
+        // ir' = ir / kappa, r'^2 ir' + kappa |D| = kappa (r + |D|), so the
+        // phase increment k delta / 2 pi = num / (kappa (r + |D|)) is one fma;
+        // the sums carry kappa^-3 (S1), kappa^-2 (S2), kappa^-1 (S3), undone
+        // per tile
         float ar = 0.0f, ai = 0.0f, br = 0.0f, bi = 0.0f, er = 0.0f, ei = 0.0f;
 #pragma unroll 4
         for (int jj = 0; jj < cnt; ++jj) {
           const float4 yl = sloc[jj];
           const float4 a4 = saw[jj];
           const float num = fmaf(dx2, yl.x, fmaf(dy2, yl.y, fmaf(dz2, yl.z, yl.w)));
-          const float r2 = d2f + num;
-          const float ir = __builtin_amdgcn_rsqf(r2);
-          // delta = r - |D| = num / (r + |D|), r + |D| = r^2 ir + |D|
-          const float delta = num * __builtin_amdgcn_rcpf(fmaf(r2, ir, dnf));
-          const float ph = fmaf(delta, k2pi, ph0);
+          const float r2s = fmaf(kap2, num, d2s);
+          const float irs = __builtin_amdgcn_rsqf(r2s);
+          const float ph = fmaf(num, __builtin_amdgcn_rcpf(fmaf(r2s, irs, dns)), ph0);
           const float s = __builtin_amdgcn_sinf(ph);
           const float c = __builtin_amdgcn_cosf(ph);
           const float2 m = smu[jj];
           const float zr = fmaf(c, m.x, -s * m.y);
           const float zi = fmaf(c, m.y, s * m.x);
           const float dot = fmaf(a4.x, dxf, fmaf(a4.y, dyf, fmaf(a4.z, dzf, a4.w)));
-          const float u = dot * ir * ir;
-          const float sc = u * ir;
+          const float u = dot * irs * irs;
+          const float sc = u * irs;
           ar = fmaf(sc, zr, ar);
           ai = fmaf(sc, zi, ai);
           br = fmaf(u, zr, br);
           bi = fmaf(u, zi, bi);
           if constexpr (FORM == 1) {
-            const float t = sew[jj] * ir;
+            const float t = sew[jj] * irs;
             er = fmaf(t, zr, er);
             ei = fmaf(t, zi, ei);
           }
         }
         // -S1 + i k S2 (- i S3)
-        two_sum(sr[0], cr[0], fmaf(-kf, bi, ei - ar));
-        two_sum(si[0], ci[0], fmaf(kf, br, -ai - er));
+        two_sum(sr[0], cr[0], fmaf(-ck2, bi, fmaf(ck1, ei, -ck3 * ar)));
+        two_sum(si[0], ci[0], fmaf(ck2, br, fmaf(-ck1, er, -ck3 * ai)));
       } else if (!own) {
         float tr[NRC], ti[NRC];
 #pragma unroll
