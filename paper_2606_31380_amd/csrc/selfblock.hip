@@ -91,7 +91,7 @@ struct SelfShared {
                                   // (odd row stride: conflict-free rows and columns)
     double2 acc[GL_ORDER][64];    // accumulated modes (final inverse DFT)
   };
-  double2 tw[LD];               // e^{-2 pi i q / LD} (FFT twiddles, azimuth table)
+  double2 tw[LD + LD / 16];     // e^{-2 pi i q / LD} at twi(q) (FFT twiddles, azimuth table)
   double2 tw2n[NTH_MAX];        // e^{i pi m / N}
   int modal_idx[64];
   union {
@@ -246,6 +246,9 @@ __device__ __forceinline__ void toroidal_q_batch(bool act, double chi, double ch
   }
 }
 
+// position of twiddle q in the padded table (see below)
+__device__ __forceinline__ int twi(int q) { return q + (q >> 4); }
+
 // ---------------------------------------------------------------- FFT in LDS
 // Forward DFT X_q = sum_l x_l e^{-2 pi i q l / L}, in place, natural order in
 // and out: Stockham self-sorting passes.  A pass over sub-transforms of length
@@ -253,7 +256,9 @@ __device__ __forceinline__ void toroidal_q_batch(bool act, double chi, double ch
 // e^{-2 pi i i (j mod Ns) / (r Ns)}, applies the r-point DFT and stores output i
 // at (j - j mod Ns) r + (j mod Ns) + i Ns.  Every lane reads its inputs before a
 // barrier and writes after it, so one buffer serves as source and target.
-// tw[q] = e^{-2 pi i q / LD}, q < LD.
+// tw[twi(q)] = e^{-2 pi i q / LD}, q < LD: one padding entry after every 16,
+// so the strided twiddle reads of a pass (q = 16 k or 4 k across lanes) fall
+// on different LDS banks.
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -284,9 +289,9 @@ __device__ __forceinline__ void r4_pass(double2* x, int j, bool active, const do
     a3 = x[j + 3 * L / 4];
     if (Ns > 1) {
       constexpr int step = LD / (4 * Ns);
-      w1 = tw[k * step];
-      w2 = tw[2 * k * step];
-      w3 = tw[3 * k * step];
+      w1 = tw[twi(k * step)];
+      w2 = tw[twi(2 * k * step)];
+      w3 = tw[twi(3 * k * step)];
     }
   }
   __syncthreads();
@@ -310,7 +315,7 @@ __device__ __forceinline__ void r4_pass(double2* x, int j, bool active, const do
 // reads and writes x[j], x[j + 64] only.
 __device__ __forceinline__ void r2_last128(double2* x, int j, const double2* tw) {
   const double2 a0 = x[j];
-  const double2 a1 = cmul(x[j + 64], tw[2 * j]);
+  const double2 a1 = cmul(x[j + 64], tw[twi(2 * j)]);
   x[j] = make_double2(a0.x + a1.x, a0.y + a1.y);
   x[j + 64] = make_double2(a0.x - a1.x, a0.y - a1.y);
 }
@@ -399,7 +404,7 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
     for (int h = 0; h < 2; ++h) {
       const int l = lane + 64 * h;
       // sin(phi/2) with phi = 2 pi l / LM from the table e^{-2 pi i q / LD}
-      const double sh = -tw[l * (LD / (2 * LM))].y;
+      const double sh = -tw[twi(l * (LD / (2 * LM)))].y;
       const double rho2 = 2.0 * r * rt * (chim1 + 2.0 * sh * sh);
       const double irho = rsqrt_pos(rho2);
       const double rho = rho2 * irho;
@@ -679,7 +684,7 @@ __device__ __forceinline__ void r4_pass_rows(double2 (*X)[64], const double2* tw
       constexpr int step = LD / (4 * Ns);
       const int k = j & (Ns - 1);
 #pragma unroll
-      for (int i = 1; i < 4; ++i) w[u][i - 1] = tw[i * k * step];
+      for (int i = 1; i < 4; ++i) w[u][i - 1] = tw[twi(i * k * step)];
     }
   }
   __syncthreads();
@@ -818,7 +823,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   for (int q = lane; q < LD; q += 64) {
     double s, c;
     sincos_cw(-TWO_PI * q / LD, &s, &c);
-    S.tw[q] = make_double2(c, s);
+    S.tw[twi(q)] = make_double2(c, s);
   }
   for (int q = lane; q < 2 * N; q += 64) {
     double s, c;
@@ -935,7 +940,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         const int l = lane + 64 * hh;
         if (l < L) {
           // (cos, sin)(2 pi l / L) from the twiddle table
-          const double2 t = S.tw[l * tstep];
+          const double2 t = S.tw[twi(l * tstep)];
           const double cth = t.x, sth = -t.y;
           const double dx = cv.r * cth + cv.p - xT, dy = cv.r * sth + cv.q - yT, dz = cv.z - zT;
           const double nx = cv.r * cv.dz * cth, ny = cv.r * cv.dz * sth;
@@ -1109,7 +1114,7 @@ __global__ __launch_bounds__(64) void modal_modes_kernel(const double* __restric
   for (int q = lane; q < LD; q += 64) {
     double s, cc;
     sincos_cw(-TWO_PI * q / LD, &s, &cc);
-    S.tw[q] = make_double2(cc, s);
+    S.tw[twi(q)] = make_double2(cc, s);
   }
   toroidal_q_batch(lane == 0, 1.0 + chim1[pt], chim1[pt], MQ_CAP, S.Q, lane & (QB - 1));
   __syncthreads();
