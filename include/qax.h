@@ -180,6 +180,19 @@ qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dirs, int32_t 
 qax_status qax_solve_rhs(qax_problem* p, qax_prec prec, const void* d_rhs, int32_t nrhs,
                          double tol, int32_t maxit, void* d_mu_out, qax_info* info);
 
+/* Batched in-place inversion of caller matrices with the Gauss-Jordan
+ * elimination (partial pivoting, 128-column panels) that inverts the self
+ * blocks for the block-diagonal preconditioner of the hybrid solver (Section 6):
+ * d_mats holds `count` complex128 matrices, orders[i] x orders[i] each
+ * (host array, orders in [1, 8192]), row-major, stored one after another;
+ * each is replaced by its inverse.  prec QAX_FP64 inverts in FP64;
+ * QAX_MIXED rounds to complex64, inverts in FP32 (the mixed path's
+ * preconditioner) and widens the result back.  Needs only a created handle
+ * (no build).  Singular matrices give non-finite entries (no error).
+ * Synchronises the handle's stream. */
+qax_status qax_invert(qax_problem* p, qax_prec prec, int32_t count, const int32_t* orders,
+                      void* d_mats);
+
 /* Dense direct solve of the full system (all blocks assembled on the device,
  * Gauss-Jordan inversion in FP64) for N <= 8192; d_mu_out N x nrhs. */
 qax_status qax_solve_dense(qax_problem* p, const double* dirs, int32_t nrhs, void* d_mu_out);

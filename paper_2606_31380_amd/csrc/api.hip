@@ -27,6 +27,9 @@ hipError_t launch_dense_system(qax_problem* p, double* A);
 hipError_t launch_dense_solve(qax_problem* p, double* A, const double* b, int nrhs, double* x,
                               double* work);
 size_t dense_solve_work_bytes(int64_t N);
+size_t invert_matrices_work_bytes(int count, int nmax, int64_t total_elems, bool f32);
+hipError_t launch_invert_matrices(qax_problem* p, bool f32, int count, const int32_t* orders,
+                                  double* mats, double* work);
 size_t invert_blocks_work_bytes(qax_problem* p);
 }  // namespace qax
 
@@ -624,6 +627,28 @@ extern "C" qax_status qax_modal_modes(qax_problem* p, int32_t n_pts, const doubl
 }
 
 // ---------------------------------------------------------------- dense solve
+extern "C" qax_status qax_invert(qax_problem* p, qax_prec prec, int32_t count, const int32_t* orders,
+                                 void* d_mats) {
+  if (!p) return QAX_ERR_ARG;
+  if (prec != QAX_FP64 && prec != QAX_MIXED) return fail(p, QAX_ERR_ARG, "qax_invert: bad precision");
+  if (count < 0 || (count > 0 && (!orders || !d_mats)))
+    return fail(p, QAX_ERR_ARG, "qax_invert: bad count or null pointer");
+  if (count == 0) return QAX_OK;
+  int nmax = 0;
+  int64_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    if (orders[i] < 1 || orders[i] > 8192)
+      return fail(p, QAX_ERR_ARG, "qax_invert: matrix orders must be in [1, 8192]");
+    nmax = std::max(nmax, (int)orders[i]);
+    total += (int64_t)orders[i] * orders[i];
+  }
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  const bool f32 = prec == QAX_MIXED;
+  QBUF(work, double, "invert_work", invert_matrices_work_bytes(count, nmax, total, f32));
+  QCHECK(launch_invert_matrices(p, f32, count, orders, (double*)d_mats, work), "invert");
+  return sync(p, "qax_invert");
+}
+
 extern "C" qax_status qax_solve_dense(qax_problem* p, const double* dirs, int32_t nrhs, void* d_mu_out) {
   if (!p) return QAX_ERR_ARG;
   qax_status st = check_vec_call(p, dirs, d_mu_out, nrhs, 2);

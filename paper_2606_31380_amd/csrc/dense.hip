@@ -431,6 +431,12 @@ hipError_t launch_convert_f32(hipStream_t s, const double* src, float* dst, int6
   return hipGetLastError();
 }
 
+__global__ void convert_f64_kernel(const float* __restrict__ src, double* __restrict__ dst,
+                                   int64_t count) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) dst[e] = (double)src[e];
+}
+
 // ---------------------------------------------------------------- Gauss-Jordan
 struct MatDesc {
   int64_t elem_off;  // complex elements
@@ -1094,6 +1100,39 @@ size_t gj_work_bytes(int batch, int nmax) {
   return (size_t)nmax * batch * sizeof(double2) * GJB +
          (((size_t)nmax * batch * sizeof(int32_t)) + 255) / 256 * 256 +
          (size_t)batch * GJB * GJB * sizeof(double2);
+}
+
+// Caller matrices: `count` complex128 matrices of the given orders stored one
+// after another (row-major), inverted in place; FP64, or (mixed) rounded to
+// FP32, inverted in FP32 and widened back.  work: invert_matrices_work_bytes.
+size_t invert_matrices_work_bytes(int count, int nmax, int64_t total_elems, bool f32) {
+  return ((count * sizeof(MatDesc) + 255) / 256) * 256 + gj_work_bytes(count, nmax) +
+         (f32 ? (size_t)total_elems * 8 : 0);
+}
+
+hipError_t launch_invert_matrices(qax_problem* p, bool f32, int count, const int32_t* orders,
+                                  double* mats, double* work) {
+  std::vector<MatDesc> md(count);
+  int nmax = 0;
+  int64_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    md[i].elem_off = off;
+    md[i].n = orders[i];
+    nmax = std::max(nmax, orders[i]);
+    off += (int64_t)orders[i] * orders[i];
+  }
+  MatDesc* d_md = (MatDesc*)work;
+  double* w2 = (double*)((char*)work + ((count * sizeof(MatDesc) + 255) / 256) * 256);
+  hipError_t e = hipMemcpyAsync(d_md, md.data(), count * sizeof(MatDesc), hipMemcpyHostToDevice,
+                                p->stream);
+  if (e != hipSuccess) return e;
+  if (!f32) return gj_invert<double>(p, mats, d_md, count, nmax, w2, false);
+  float* pool = (float*)((char*)w2 + gj_work_bytes(count, nmax));
+  if ((e = launch_convert_f32(p->stream, mats, pool, 2 * off)) != hipSuccess) return e;
+  if ((e = gj_invert<float>(p, pool, d_md, count, nmax, w2, false)) != hipSuccess) return e;
+  hipLaunchKernelGGL(convert_f64_kernel, dim3((unsigned)((2 * off + 255) / 256)), dim3(256), 0,
+                     p->stream, pool, mats, 2 * off);
+  return hipGetLastError();
 }
 
 // Invert every distinct self block for the mixed path: B rounded to FP32,

@@ -52,7 +52,7 @@ EXPORTS = ["qax_create", "qax_destroy", "qax_last_error", "qax_build", "qax_size
            "qax_assemble_self", "qax_self_block", "qax_pair_sum", "qax_block_apply", "qax_apply",
            "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes",
            "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning", "qax_set_graphs",
-           "qax_solve_rhs", "qax_nearfield", "qax_set_formulation", "qax_lattice"]
+           "qax_solve_rhs", "qax_nearfield", "qax_set_formulation", "qax_lattice", "qax_invert"]
 (QAX_K_PAIRSUM_FP64, QAX_K_PAIRSUM_FP32, QAX_K_BLOCK_APPLY, QAX_K_SELF_ASSEMBLY, QAX_K_INVERT,
  QAX_K_INVERT_UPDATE, QAX_K_BLOCK_APPLY_F32, QAX_K_LATTICE_F64, QAX_K_LATTICE_F32) = range(9)
 KERNEL_NAMES = ["pair_sum_fp64", "pair_sum_fp32", "block_apply", "self_assembly", "invert",
@@ -87,6 +87,7 @@ def lib():
         "qax_rhs": (C.c_int, [vp, pd, i32, vp]),
         "qax_solve": (C.c_int, [vp, C.c_int, pd, i32, d, i32, vp, C.POINTER(qax_info)]),
         "qax_solve_dense": (C.c_int, [vp, pd, i32, vp]),
+        "qax_invert": (C.c_int, [vp, C.c_int, i32, C.POINTER(i32), vp]),
         "qax_solve_rhs": (C.c_int, [vp, C.c_int, vp, i32, d, i32, vp, C.POINTER(qax_info)]),
         "qax_nearfield": (C.c_int, [vp, vp, i32, pd, i64, i32, vp]),
         "qax_farfield": (C.c_int, [vp, vp, i32, pd, i32, vp]),
@@ -226,6 +227,14 @@ def qax_nearfield(h, mu, pts, u, nrhs=1, problem=0):
 def qax_solve_dense(h, dirs, mu_out, nrhs=1):
     d = np.ascontiguousarray(dirs, dtype=np.float64)
     _check(h, lib().qax_solve_dense(h, _dptr(d), int(nrhs), _ptr(mu_out)))
+
+
+def qax_invert(h, prec, orders, mats):
+    """Invert in place the complex128 matrices of the given orders stored one
+    after another in the device buffer `mats`."""
+    o = np.ascontiguousarray(orders, dtype=np.int32)
+    _check(h, lib().qax_invert(h, int(prec), int(o.size), o.ctypes.data_as(C.POINTER(C.c_int32)),
+                               _ptr(mats)))
 
 
 def qax_farfield(h, mu, xhat, u_inf, nrhs=1):
