@@ -176,6 +176,9 @@ static void free_geometry(qax_problem* p) {
   p->d_ew = nullptr; p->d_ew32 = nullptr;
   if (p->d_gemm_tasks) (void)hipFree(p->d_gemm_tasks);
   p->d_gemm_tasks = nullptr;
+  if (p->sym.d_mem) (void)hipFree(p->sym.d_mem);
+  p->sym.d_mem = nullptr;
+  p->sym.tasks.clear();
   p->gemm_tasks.clear();
   lattice_free(p);
 }
@@ -1089,6 +1092,10 @@ extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char*
     explicit LatticeOff(qax_problem* h) : q(h), on(h->lat.active) { h->lat.active = false; }
     ~LatticeOff() { q->lat.active = on; }
   } lattice_off(p);
+  struct SymOn {   // the reciprocal kernel is back on however tuning ends
+    qax_problem* q;
+    ~SymOn() { q->sym.enabled = true; }
+  } sym_on{p};
   QBUF(mu, double, "tune_mu", (size_t)p->N * nrhs_max * 16);
   QBUF(out, double, "tune_out", (size_t)p->N * nrhs_max * 16);
   QCHECK(hipMemsetAsync(mu, 0, (size_t)p->N * nrhs_max * 16, p->stream), "zero");
@@ -1097,10 +1104,12 @@ extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char*
   hipError_t err = hipSuccess;
   for (int pi = 0; pi < 2; ++pi) {
     const int prec = pi == 0 ? QAX_FP64 : QAX_MIXED;
+    // the per-target kernel's choices are timed with the reciprocal FP32
+    // kernel off (it serves one right-hand side whenever it applies)
+    p->sym.enabled = false;
     auto run = [&](int nrhs) -> hipError_t {
-      const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;
       qax_status s = QAX_OK;
-      double* part = (double*)dbuf(p, "pair_partial", (size_t)slots * p->N * nrhs * 16, &s);
+      double* part = (double*)dbuf(p, "pair_partial", pair_work_bytes(p, prec, nrhs), &s);
       if (!part) return hipErrorOutOfMemory;
       return launch_pair_sum(p, prec, mu, out, nrhs, part, false);
     };
@@ -1175,6 +1184,7 @@ extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char*
       p->tune.pair_tpb[pi] = btpb;
       p->tune.pair_mult[pi] = bmult;
       QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
+      p->sym.enabled = true;
       t.pair_ms[pi] = time_best(p, 2, [&] { return run(1); }, &err);
       QCHECK(err, "autotune pair sum");
     }

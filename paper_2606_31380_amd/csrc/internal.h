@@ -49,6 +49,19 @@ struct PairTask {
   double eta;                  // combined-field coupling of the problem (0: none)
 };
 
+// A chunk of the reciprocal FP32 pair sum: block [t0, t0 + nt) of body a
+// (targets held in registers) against block [s0, s0 + nb) of body b > a of
+// the same problem, both directions; blocks are SYM_T nodes from the start
+// of each body.  The task's target-side sums go to part[ioff + (i - t0)],
+// its source-side sums to part[joff + (j - s0)] (complex64).
+constexpr int SYM_T = 256;
+struct SymTask {
+  int64_t t0, s0;
+  int64_t ioff, joff;
+  int32_t nt, nb;
+  int32_t a, b;
+};
+
 // Row tile of the several-RHS block apply: 64 rows of one body from row0.
 struct GemmTask {
   int32_t body;
@@ -128,6 +141,22 @@ struct qax_problem {
   qax::PairTask* d_tasks32 = nullptr;
   int32_t slots64 = 1, slots32 = 1;
   int32_t plan_tpb[2] = {0, 0};       // workgroup size the task tables were planned for
+  // reciprocal FP32 pair sum (one right-hand side, k > 0 in every problem,
+  // double layer or combined field); the partial-sum lists of the final
+  // reduction are per target block (target side) and per body (source side)
+  struct Sym {
+    bool ok = false;                  // every problem has k > 0
+    bool enabled = true;              // off while the per-target kernel is tuned
+    std::vector<qax::SymTask> tasks;
+    void* d_mem = nullptr;            // one allocation for the arrays below
+    qax::SymTask* d_tasks = nullptr;
+    int32_t* d_blk_base = nullptr;    // first block of each body
+    int32_t* d_ptr = nullptr;         // per block: range in d_list
+    int64_t* d_list = nullptr;        // ioff - t0 / joff - s0 of the tasks touching the block
+    int64_t nparts = 0;               // complex64 partial sums
+    std::vector<int32_t> h_blk_base, h_ptr;
+    std::vector<int64_t> h_list;
+  } sym;
   qax::Tune tune;
 
   // block-Toeplitz apply of the inter-body sum on a regular array of

@@ -390,6 +390,345 @@ __global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slo
   out[e] = acc;
 }
 
+// ---------------------------------------------------------------------------
+// Reciprocal FP32 pair sum (one right-hand side, double layer or combined
+// field, k > 0).  For x_i on body a and y_j on body b != a, the distance r,
+// the phase and e^{ikr} are the same for the pair (target i, source j) and
+// the pair (target j, source i); only the double-layer dot products and the
+// densities differ.  Each unordered pair of bodies a < b is visited once, as
+// tasks of a block of SYM_T nodes of a against a block of SYM_T nodes of b,
+// so the shared part of a pair is computed once for both directions.  The
+// blocks keep tasks small enough that the workgroups fill the chip evenly.
+//
+// Coordinates are local to each body: x_i = c_a + x', y_j = c_b + y',
+// C = c_b - c_a.  With P_j = 2 C.y' + |y'|^2 and Q_i = |x'|^2 - 2 C.x',
+//   num = r^2 - |C|^2 = P_j + Q_i - 2 x'.y'
+// (no cancellation against |C|^2), delta = r - |C| = num / (r + |C|), and the
+// phase is frac(k |C| / 2 pi) + k delta / 2 pi, in the kappa-scaled form of
+// the per-target kernel.  The dot products are
+//   aw_j . (y_j - x_i) = A_j - aw_j . x',  A_j = aw_j . (C + y'),
+//   aw_i . (x_i - y_j) = B_i - aw_i . y',  B_i = aw_i . (x' - C).
+//
+// A workgroup is two wavefronts; lane l owns targets l and l + 64 of its
+// wavefront's 128.  Sources pass in chunks of 64; at step s lane l meets
+// source (l + s) mod 64 of the chunk, so the 64 lanes of a wavefront see 64
+// distinct sources at every step.  The chunk is staged twice over (indices
+// 0..127), which turns (l + s) mod 64 into l + s.  The target-side sums stay
+// in registers (FP32 per chunk, compensated across chunks).  The source-side
+// sums travel with their source: lane l holds the running sums of source
+// (l + s) mod 64 at step s, and the next step receives them from lane l + 1
+// (a wavefront rotation fused into the add), so after the chunk lane l holds
+// those of source (l + 63) mod 64.  The two wavefronts' sums of a source are
+// added through LDS (FP32 sums over the task's targets).  Both sides' task
+// sums are stored as complex64 and added in FP64 by the reduction.
+__device__ __forceinline__ float from_next_lane(float x) {
+  // DPP wavefront rotation: lane l reads lane (l + 1) mod 64
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x134, 0xf, 0xf, false));
+}
+
+template <int FORM>
+__global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
+    const SymTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
+    const float4* __restrict__ loc32, const float4* __restrict__ aw32,
+    const float* __restrict__ ew32, const double2* __restrict__ mu,
+    const int32_t* __restrict__ seg_active, float2* __restrict__ part) {
+  constexpr int NA = FORM ? 6 : 4;   // source-side sums: S1, S2 (, S3), re/im
+  const SymTask T = tasks[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const BodyDev& BA = bodies[T.a];
+  const BodyDev& BB = bodies[T.b];
+  if (seg_active && seg_active[BA.problem] == 0) {
+    for (int t = tid; t < T.nt; t += 128) part[T.ioff + t] = make_float2(0.0f, 0.0f);
+    for (int j = tid; j < T.nb; j += 128) part[T.joff + j] = make_float2(0.0f, 0.0f);
+    return;
+  }
+  const double k = BA.k;
+  const double Cx = BB.cen[0] - BA.cen[0], Cy = BB.cen[1] - BA.cen[1], Cz = BB.cen[2] - BA.cen[2];
+  const double C2 = Cx * Cx + Cy * Cy + Cz * Cz;
+  const double Cn = sqrt(C2);
+  double ph0d = k * Cn / TWO_PI;
+  ph0d -= floor(ph0d);
+  const double kap = TWO_PI / k;
+  const float kap2 = (float)(kap * kap), d2s = (float)(kap * kap * C2), dns = (float)(kap * Cn);
+  const float ck1 = (float)kap, ck2 = (float)(k * kap * kap), ck3 = (float)(kap * kap * kap);
+  const float ph0 = (float)ph0d;
+  const float cx = (float)Cx, cy = (float)Cy, cz = (float)Cz;
+
+  // the lane's two targets: -x', Q_i, -aw_i / 2, B_i, mu_i (0 past the block)
+  float mx[2], my[2], mz[2], q[2], hx[2], hy[2], hz[2], bv[2], mr[2], mi[2], ew[2];
+  float sr[2], si[2], cr[2], ci[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int loc = wv * 128 + t * 64 + lane;
+    const bool act = loc < T.nt;
+    const int64_t i = T.t0 + (act ? loc : 0);
+    const float4 x4 = loc32[i];
+    const float4 a4 = aw32[i];
+    mx[t] = -x4.x;
+    my[t] = -x4.y;
+    mz[t] = -x4.z;
+    q[t] = fmaf(-2.0f * cx, x4.x, fmaf(-2.0f * cy, x4.y, fmaf(-2.0f * cz, x4.z, x4.w)));
+    hx[t] = -0.5f * a4.x;
+    hy[t] = -0.5f * a4.y;
+    hz[t] = -0.5f * a4.z;
+    bv[t] = a4.w - fmaf(a4.x, cx, fmaf(a4.y, cy, a4.z * cz));
+    const double2 m = act ? mu[i] : make_double2(0.0, 0.0);
+    mr[t] = (float)m.x;
+    mi[t] = (float)m.y;
+    ew[t] = FORM ? ew32[i] : 0.0f;
+    sr[t] = si[t] = cr[t] = ci[t] = 0.0f;
+  }
+
+  __shared__ float4 sY[128];           // 2 y', P_j
+  __shared__ float4 sW[128];           // aw_j, A_j
+  __shared__ float4 sM[128];           // mu_j, eta |aw_j|
+  __shared__ float sX[NA][64];         // second wavefront's source-side sums
+
+  const int src = (lane + 63) & 63;    // source of the lane's sums after a chunk
+  const int nch = (T.nb + 63) / 64;
+  for (int c = 0; c < nch; ++c) {
+    if (tid < 64) {
+      const int jl = c * 64 + tid;
+      const bool act = jl < T.nb;
+      const int64_t j = T.s0 + (act ? jl : 0);
+      const float4 y4 = loc32[j];
+      const float4 b4 = aw32[j];
+      const double2 m = act ? mu[j] : make_double2(0.0, 0.0);
+      const float4 Y = make_float4(2.0f * y4.x, 2.0f * y4.y, 2.0f * y4.z,
+                                   fmaf(2.0f * cx, y4.x, fmaf(2.0f * cy, y4.y, fmaf(2.0f * cz, y4.z, y4.w))));
+      const float4 W = make_float4(b4.x, b4.y, b4.z, b4.w + fmaf(b4.x, cx, fmaf(b4.y, cy, b4.z * cz)));
+      const float4 M = make_float4((float)m.x, (float)m.y, FORM ? ew32[j] : 0.0f, 0.0f);
+      sY[tid] = Y;
+      sY[tid + 64] = Y;
+      sW[tid] = W;
+      sW[tid + 64] = W;
+      sM[tid] = M;
+      sM[tid + 64] = M;
+    }
+    __syncthreads();
+    float ar[2], ai[2], br[2], bi[2], er[2], ei[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) ar[t] = ai[t] = br[t] = bi[t] = er[t] = ei[t] = 0.0f;
+    float acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
+    const float4* pY = &sY[lane];
+    const float4* pW = &sW[lane];
+    const float4* pM = &sM[lane];
+#pragma unroll 4
+    for (int st = 0; st < 64; ++st) {
+      const float4 Y = pY[st];
+      const float4 W = pW[st];
+      const float4 M = pM[st];
+      float cn[NA];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        // shared: r, e^{ikr} (scaled as in the per-target kernel)
+        const float num = fmaf(mx[t], Y.x, fmaf(my[t], Y.y, fmaf(mz[t], Y.z, Y.w + q[t])));
+        const float r2s = fmaf(kap2, num, d2s);
+        const float irs = __builtin_amdgcn_rsqf(r2s);
+        const float ph = fmaf(num, __builtin_amdgcn_rcpf(fmaf(r2s, irs, dns)), ph0);
+        const float sn = __builtin_amdgcn_sinf(ph);
+        const float cs = __builtin_amdgcn_cosf(ph);
+        const float ir2 = irs * irs;
+        // target i, source j
+        {
+          const float zr = fmaf(cs, M.x, -sn * M.y);
+          const float zi = fmaf(cs, M.y, sn * M.x);
+          const float dot = fmaf(W.x, mx[t], fmaf(W.y, my[t], fmaf(W.z, mz[t], W.w)));
+          const float u = dot * ir2;
+          const float sc = u * irs;
+          ar[t] = fmaf(sc, zr, ar[t]);
+          ai[t] = fmaf(sc, zi, ai[t]);
+          br[t] = fmaf(u, zr, br[t]);
+          bi[t] = fmaf(u, zi, bi[t]);
+          if constexpr (FORM == 1) {
+            const float tt = M.z * irs;
+            er[t] = fmaf(tt, zr, er[t]);
+            ei[t] = fmaf(tt, zi, ei[t]);
+          }
+        }
+        // target j, source i
+        {
+          const float zr = fmaf(cs, mr[t], -sn * mi[t]);
+          const float zi = fmaf(cs, mi[t], sn * mr[t]);
+          const float dot = fmaf(hx[t], Y.x, fmaf(hy[t], Y.y, fmaf(hz[t], Y.z, bv[t])));
+          const float u = dot * ir2;
+          const float sc = u * irs;
+          const float tt = FORM ? ew[t] * irs : 0.0f;
+          if (t == 0) {
+            cn[0] = sc * zr;
+            cn[1] = sc * zi;
+            cn[2] = u * zr;
+            cn[3] = u * zi;
+            if constexpr (FORM == 1) {
+              cn[4] = tt * zr;
+              cn[5] = tt * zi;
+            }
+          } else {
+            cn[0] = fmaf(sc, zr, cn[0]);
+            cn[1] = fmaf(sc, zi, cn[1]);
+            cn[2] = fmaf(u, zr, cn[2]);
+            cn[3] = fmaf(u, zi, cn[3]);
+            if constexpr (FORM == 1) {
+              cn[4] = fmaf(tt, zr, cn[4]);
+              cn[5] = fmaf(tt, zi, cn[5]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < NA; ++a) acc[a] = from_next_lane(acc[a]) + cn[a];
+    }
+    // -S1 + i k S2 (- i S3), undoing the kappa scaling
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      two_sum(sr[t], cr[t], fmaf(-ck2, bi[t], fmaf(ck1, ei[t], -ck3 * ar[t])));
+      two_sum(si[t], ci[t], fmaf(ck2, br[t], fmaf(-ck1, er[t], -ck3 * ai[t])));
+    }
+    if (wv == 1) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) sX[a][lane] = acc[a];
+    }
+    __syncthreads();
+    if (wv == 0 && c * 64 + src < T.nb) {
+      float v[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) v[a] = acc[a] + sX[a][lane];
+      const float e3r = FORM ? v[4] : 0.0f, e3i = FORM ? v[5] : 0.0f;
+      const float vr = fmaf(-ck2, v[3], fmaf(ck1, e3i, -ck3 * v[0]));
+      const float vi = fmaf(ck2, v[2], fmaf(-ck1, e3r, -ck3 * v[1]));
+      part[T.joff + c * 64 + src] =
+          make_float2(vr * (float)INV_FOUR_PI, vi * (float)INV_FOUR_PI);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int loc = wv * 128 + t * 64 + lane;
+    if (loc < T.nt)
+      part[T.ioff + loc] = make_float2((float)(((double)sr[t] + (double)cr[t]) * INV_FOUR_PI),
+                                       (float)(((double)si[t] + (double)ci[t]) * INV_FOUR_PI));
+  }
+}
+
+// out[n] = (accumulate ? out[n] : 0) + the task sums of n's block.  A
+// workgroup takes 64 consecutive nodes; wavefront w adds the list entries
+// w, w + 4, ... of each node, and the four sums are added in wavefront order
+// (a fixed order).
+__global__ __launch_bounds__(256) void reduce_sym_kernel(
+    const float2* __restrict__ part, const int32_t* __restrict__ node_body,
+    const BodyDev* __restrict__ bodies, const int32_t* __restrict__ blk_base,
+    const int32_t* __restrict__ ptr, const int64_t* __restrict__ list, int64_t N,
+    double2* __restrict__ out, int accumulate) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t n = (int64_t)blockIdx.x * 64 + lane;
+  __shared__ double2 red[4][64];
+  double2 acc = make_double2(0.0, 0.0);
+  if (n < N) {
+    const int b = node_body[n];
+    const int blk = blk_base[b] + (int)((n - bodies[b].off) / SYM_T);
+    const int e1 = ptr[blk + 1];
+#pragma unroll 4
+    for (int e = ptr[blk] + w; e < e1; e += 4) {
+      const float2 v = part[list[e] + n];
+      acc.x += (double)v.x;
+      acc.y += (double)v.y;
+    }
+  }
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && n < N) {
+    double2 o = accumulate ? out[n] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      o.x += red[q][lane].x;
+      o.y += red[q][lane].y;
+    }
+    out[n] = o;
+  }
+}
+
+// Tasks of the reciprocal kernel: for every problem, every pair of bodies
+// a < b and every pair of blocks (one of a, one of b).  Partial-sum offsets
+// follow the order of construction; each block lists, in that order, the
+// tasks whose target or source block it is.  The table is then sorted by
+// decreasing cost.
+static void plan_sym(qax_problem* p) {
+  auto& S = p->sym;
+  S.tasks.clear();
+  S.ok = p->n_problems > 0;
+  for (int pr = 0; pr < p->n_problems; ++pr) S.ok = S.ok && p->k[pr] > 0.0;
+  const int nbody = (int)p->hbodies.size();
+  std::vector<int32_t> blk_base(nbody + 1, 0);
+  for (int b = 0; b < nbody; ++b)
+    blk_base[b + 1] = blk_base[b] + (p->hbodies[b].n + SYM_T - 1) / SYM_T;
+  std::vector<std::vector<int64_t>> lists(blk_base[nbody]);
+  int64_t off = 0;
+  for (int pr = 0; pr < p->n_problems; ++pr) {
+    const int b0 = (int)p->prob_body0[pr], b1 = (int)p->prob_body0[pr + 1];
+    for (int a = b0; a < b1; ++a)
+      for (int b = a + 1; b < b1; ++b)
+        for (int qa = 0; qa * SYM_T < p->hbodies[a].n; ++qa)
+          for (int qb = 0; qb * SYM_T < p->hbodies[b].n; ++qb) {
+            SymTask T;
+            T.t0 = p->hbodies[a].off + (int64_t)qa * SYM_T;
+            T.nt = std::min(SYM_T, p->hbodies[a].n - qa * SYM_T);
+            T.s0 = p->hbodies[b].off + (int64_t)qb * SYM_T;
+            T.nb = std::min(SYM_T, p->hbodies[b].n - qb * SYM_T);
+            T.a = a;
+            T.b = b;
+            T.ioff = off;
+            T.joff = off + T.nt;
+            lists[blk_base[a] + qa].push_back(T.ioff - T.t0);
+            lists[blk_base[b] + qb].push_back(T.joff - T.s0);
+            off += T.nt + T.nb;
+            S.tasks.push_back(T);
+          }
+  }
+  S.nparts = off;
+  std::stable_sort(S.tasks.begin(), S.tasks.end(), [](const SymTask& x, const SymTask& y) {
+    return (int64_t)x.nt * x.nb > (int64_t)y.nt * y.nb;
+  });
+  S.h_blk_base = blk_base;
+  S.h_ptr.assign(1, 0);
+  S.h_list.clear();
+  for (auto& v : lists) {
+    S.h_list.insert(S.h_list.end(), v.begin(), v.end());
+    S.h_ptr.push_back((int32_t)S.h_list.size());
+  }
+}
+
+static hipError_t upload_sym(qax_problem* p) {
+  auto& S = p->sym;
+  if (S.d_mem) {
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return e;
+    (void)hipFree(S.d_mem);
+    S.d_mem = nullptr;
+  }
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t bt = al(sizeof(SymTask) * std::max<size_t>(1, S.tasks.size()));
+  const size_t bb = al(sizeof(int32_t) * S.h_blk_base.size());
+  const size_t bp = al(sizeof(int32_t) * S.h_ptr.size());
+  const size_t bl = al(sizeof(int64_t) * std::max<size_t>(1, S.h_list.size()));
+  hipError_t e = hipMalloc(&S.d_mem, bt + bb + bp + bl);
+  if (e != hipSuccess) return e;
+  char* m = (char*)S.d_mem;
+  S.d_tasks = (SymTask*)m;
+  S.d_blk_base = (int32_t*)(m + bt);
+  S.d_ptr = (int32_t*)(m + bt + bb);
+  S.d_list = (int64_t*)(m + bt + bb + bp);
+  auto cp = [&](void* d, const void* h, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(d, h, n, hipMemcpyHostToDevice, p->stream);
+  };
+  cp(S.d_tasks, S.tasks.data(), sizeof(SymTask) * S.tasks.size());
+  cp(S.d_blk_base, S.h_blk_base.data(), sizeof(int32_t) * S.h_blk_base.size());
+  cp(S.d_ptr, S.h_ptr.data(), sizeof(int32_t) * S.h_ptr.size());
+  cp(S.d_list, S.h_list.data(), sizeof(int64_t) * S.h_list.size());
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(p->stream);
+}
+
 // Build the task table: target blocks of `tpb` rows inside one problem, each
 // paired with `slots` contiguous chunks of that problem's source bodies
 // (balanced by node count).  Sorted by decreasing cost so that the hardware
@@ -458,6 +797,12 @@ void plan_pair_sum(qax_problem* p, int prec, int cu_count) {
 
 hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count) {
   plan_pair_sum(p, prec, cu_count);
+  if (prec != QAX_FP64 && !p->sym.d_mem) {
+    // the reciprocal task table depends on the geometry only
+    plan_sym(p);
+    hipError_t e = upload_sym(p);
+    if (e != hipSuccess) return e;
+  }
   ++p->generation;   // captured solver steps hold the old launch sizes
   std::vector<PairTask>& t = prec == QAX_FP64 ? p->tasks64 : p->tasks32;
   PairTask*& d = prec == QAX_FP64 ? p->d_tasks64 : p->d_tasks32;
@@ -552,7 +897,15 @@ static void launch_any(qax_problem* p, bool f64, int tpb, int nrc, const double*
 // (clamped to a supported configuration).
 size_t pair_work_bytes(const qax_problem* p, int prec, int nrhs) {
   const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;
-  return std::max((size_t)slots * p->N * nrhs * 16, lattice_work_bytes(p, nrhs));
+  size_t b = std::max((size_t)slots * p->N * nrhs * 16, lattice_work_bytes(p, nrhs));
+  if (prec != QAX_FP64 && nrhs == 1 && p->sym.ok)
+    b = std::max(b, (size_t)p->sym.nparts * 8);
+  return b;
+}
+
+static bool use_sym(const qax_problem* p, int prec, int nrhs) {
+  return prec != QAX_FP64 && nrhs == 1 && p->sym.ok && p->sym.enabled && p->sym.d_mem &&
+         p->form() != 2;
 }
 
 hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
@@ -568,6 +921,29 @@ hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* o
   const bool f64 = prec == QAX_FP64;
   const int pi = f64 ? 0 : 1;
   const int kind = f64 ? QAX_K_PAIRSUM_FP64 : QAX_K_PAIRSUM_FP32;
+  if (use_sym(p, prec, nrhs)) {
+    auto& S = p->sym;
+    float2* part = (float2*)partial;
+    timing_begin(p, kind);
+    if (!S.tasks.empty()) {
+      const dim3 grid((unsigned)S.tasks.size());
+      if (p->form() == 1)
+        hipLaunchKernelGGL(pair_sum_f32_sym_kernel<1>, grid, dim3(128), 0, p->stream, S.d_tasks,
+                           p->d_bodies, (const float4*)p->d_loc32, (const float4*)p->d_aw32,
+                           p->d_ew32, (const double2*)mu, p->seg_active, part);
+      else
+        hipLaunchKernelGGL(pair_sum_f32_sym_kernel<0>, grid, dim3(128), 0, p->stream, S.d_tasks,
+                           p->d_bodies, (const float4*)p->d_loc32, (const float4*)p->d_aw32,
+                           p->d_ew32, (const double2*)mu, p->seg_active, part);
+    }
+    timing_end(p, kind);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_sym_kernel, dim3((unsigned)((p->N + 63) / 64)), dim3(256), 0,
+                       p->stream, part, p->d_node_body, p->d_bodies, S.d_blk_base, S.d_ptr, S.d_list,
+                       p->N, (double2*)out, accumulate ? 1 : 0);
+    return hipGetLastError();
+  }
   const int tpb = p->tune.pair_tpb[pi];
   int nrc = nrhs == 1 ? 1 : p->tune.pair_nrc[pi][nrhs_class(nrhs)];
   while (nrc > 1 && !pair_config_ok(prec, tpb, nrc)) nrc /= 2;

@@ -32,7 +32,7 @@ CAL_BYTES = 1 << 30
 # updates inside the panel factorization: the trailing updates are its
 # dispatches with the largest grid.
 KINDS = {
-    "pair_sum_fp32": (r"qax::pair_sum_f32_kernel<\d+, 1, 0>", "paper_2606_31380_amd/csrc/pairsum.hip", False),
+    "pair_sum_fp32": (r"qax::pair_sum_f32_sym_kernel<0>", "paper_2606_31380_amd/csrc/pairsum.hip", False),
     "pair_sum_fp64": (r"qax::pair_sum_f64_kernel<\d+, 1, 0>", "paper_2606_31380_amd/csrc/pairsum.hip", False),
     "block_apply": (r"qax::block_gemv_kernel<double, 1, \d, \d+>", "paper_2606_31380_amd/csrc/dense.hip", False),
     "block_apply_f32": (r"qax::block_gemv_f32_lds_kernel<\d>", "paper_2606_31380_amd/csrc/dense.hip", False),

@@ -122,6 +122,9 @@ def test_combined_pair_sums_two_problems():
             o1 = P.vec()
             qax.qax_pair_sum(P.h, qax.QAX_FP64, torch.from_numpy(mu[:, 1].copy()).to(DEV), o1)
             assert rel(o1.cpu().numpy(), want[:, 1]) < 1e-12
+            # FP32 with one right-hand side: the reciprocal kernel
+            qax.qax_pair_sum(P.h, qax.QAX_MIXED, torch.from_numpy(mu[:, 1].copy()).to(DEV), o1)
+            assert rel(o1.cpu().numpy(), want[:, 1]) < 1e-5
 
 
 def test_combined_near_and_far_field():

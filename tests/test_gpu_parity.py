@@ -135,6 +135,33 @@ def test_pair_sum_lattice27_full_size_sampled():
         assert rel(t2n(out)[tg], ref) < 1e-5
 
 
+def test_pair_sum_fp32_reciprocal_ragged_blocks():
+    # the FP32 one-right-hand-side pair sum evaluates each unordered pair once
+    # for both directions, on blocks of 256 nodes: bodies of 96 to 480 nodes
+    # (partial blocks and partial 64-source chunks), two problems with
+    # different k and a third problem with a single body (no pairs)
+    s = sc.tiny(n_bodies=6, n_theta=6, shapes=(0, 1, 2), k=3.0)
+    s.bodies["n_panels"] = [1, 5, 3, 2, 4, 1]
+    s.bodies["problem"] = [0, 0, 0, 1, 1, 2]
+    s.k = np.array([3.0, 6.5, 2.0])
+    d = geo.discretize(s)
+    mu = _mu(d.pos.shape[0], seed=9)[:, 0]
+    ref = opair.pair_sum(d, s.k, mu)
+    assert np.all(ref[d.problem == 2] == 0)
+    with qax.Problem(s) as P:
+        out = P.vec()
+        qax.qax_pair_sum(P.h, qax.QAX_MIXED, n2t(mu), out)
+        got = t2n(out)
+        assert rel(got, ref) < 1e-5
+        assert np.all(got[d.problem == 2] == 0)
+        for p in (0, 1):
+            sel = d.problem == p
+            assert rel(got[sel], ref[sel]) < 1e-5
+        # a fixed summation order: a second call gives the same bits
+        qax.qax_pair_sum(P.h, qax.QAX_MIXED, n2t(mu), out)
+        assert np.array_equal(t2n(out), got)
+
+
 def test_pair_sum_multi_rhs_and_problems():
     s = sc.tiny(n_bodies=4, n_theta=8, k=2.0)
     s.bodies["problem"] = [0, 0, 1, 1]
