@@ -611,12 +611,188 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
   }
 }
 
+// FP64 reciprocal pair sum: the same tasks, lane mapping and rotation of the
+// source-side sums as the FP32 kernel, in plain FP64 on absolute positions
+// (d = y_j - x_i, r^2 = |d|^2, phase r k / 2 pi in revolutions for
+// sincos_2pi); aw_j . (y_j - x_i) = aw_j . d and aw_i . (x_i - y_j) =
+// -aw_i . d.  Task sums are stored as complex128.
+__device__ __forceinline__ double from_next_lane(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffLL), 0x134, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x134, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int FORM>
+__global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
+    const SymTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
+    const double* __restrict__ pos, const double* __restrict__ aw,
+    const double* __restrict__ ew, int64_t N, const double2* __restrict__ mu,
+    const int32_t* __restrict__ seg_active, double2* __restrict__ part) {
+  constexpr int NA = FORM ? 6 : 4;   // source-side sums: S1, S2 (, S3), re/im
+  const SymTask T = tasks[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const BodyDev& BA = bodies[T.a];
+  if (seg_active && seg_active[BA.problem] == 0) {
+    for (int t = tid; t < T.nt; t += 128) part[T.ioff + t] = make_double2(0.0, 0.0);
+    for (int j = tid; j < T.nb; j += 128) part[T.joff + j] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double k = BA.k;
+  const double k2pi = k / TWO_PI;
+
+  // the lane's two targets: x_i, -aw_i, mu_i (0 past the block)
+  double xx[2], xy[2], xz[2], nx[2], ny[2], nz[2], mr[2], mi[2], ewi[2];
+  double ar[2], ai[2], br[2], bi[2], er[2], ei[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int loc = wv * 128 + t * 64 + lane;
+    const bool act = loc < T.nt;
+    const int64_t i = T.t0 + (act ? loc : 0);
+    xx[t] = pos[i];
+    xy[t] = pos[N + i];
+    xz[t] = pos[2 * N + i];
+    nx[t] = -aw[i];
+    ny[t] = -aw[N + i];
+    nz[t] = -aw[2 * N + i];
+    const double2 m = act ? mu[i] : make_double2(0.0, 0.0);
+    mr[t] = m.x;
+    mi[t] = m.y;
+    ewi[t] = FORM ? ew[i] : 0.0;
+    ar[t] = ai[t] = br[t] = bi[t] = er[t] = ei[t] = 0.0;
+  }
+
+  __shared__ double2 sQ0[128];         // y.x, y.y
+  __shared__ double2 sQ1[128];         // y.z, aw.z
+  __shared__ double2 sQ2[128];         // aw.x, aw.y
+  __shared__ double2 sM[128];          // mu_j
+  __shared__ double sE[FORM ? 128 : 1];
+  __shared__ double sX[NA][64];        // second wavefront's source-side sums
+
+  const int src = (lane + 63) & 63;    // source of the lane's sums after a chunk
+  const int nch = (T.nb + 63) / 64;
+  for (int c = 0; c < nch; ++c) {
+    if (tid < 64) {
+      const int jl = c * 64 + tid;
+      const bool act = jl < T.nb;
+      const int64_t j = T.s0 + (act ? jl : 0);
+      const double2 q0 = make_double2(pos[j], pos[N + j]);
+      const double2 q1 = make_double2(pos[2 * N + j], aw[2 * N + j]);
+      const double2 q2 = make_double2(aw[j], aw[N + j]);
+      const double2 m = act ? mu[j] : make_double2(0.0, 0.0);
+      sQ0[tid] = q0;
+      sQ0[tid + 64] = q0;
+      sQ1[tid] = q1;
+      sQ1[tid + 64] = q1;
+      sQ2[tid] = q2;
+      sQ2[tid + 64] = q2;
+      sM[tid] = m;
+      sM[tid + 64] = m;
+      if (FORM) {
+        sE[tid] = ew[j];
+        sE[tid + 64] = ew[j];
+      }
+    }
+    __syncthreads();
+    double acc[NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] = 0.0;
+#pragma unroll 2
+    for (int st = 0; st < 64; ++st) {
+      const double2 q0 = sQ0[lane + st];
+      const double2 q1 = sQ1[lane + st];
+      const double2 q2 = sQ2[lane + st];
+      const double2 m = sM[lane + st];
+      const double e = FORM ? sE[lane + st] : 0.0;
+      double cn[NA];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const double dx = q0.x - xx[t], dy = q0.y - xy[t], dz = q1.x - xz[t];
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const double ir = rsqrt_pos(r2);
+        double sn, cs;
+        sincos_2pi(r2 * ir * k2pi, &sn, &cs);
+        const double ir2 = ir * ir;
+        // target i, source j
+        {
+          const double zr = fma(cs, m.x, -sn * m.y);
+          const double zi = fma(cs, m.y, sn * m.x);
+          const double dot = fma(q2.x, dx, fma(q2.y, dy, q1.y * dz));
+          const double u = dot * ir2;
+          const double sc = u * ir;
+          ar[t] = fma(sc, zr, ar[t]);
+          ai[t] = fma(sc, zi, ai[t]);
+          br[t] = fma(u, zr, br[t]);
+          bi[t] = fma(u, zi, bi[t]);
+          if constexpr (FORM == 1) {
+            const double tt = e * ir;
+            er[t] = fma(tt, zr, er[t]);
+            ei[t] = fma(tt, zi, ei[t]);
+          }
+        }
+        // target j, source i
+        {
+          const double zr = fma(cs, mr[t], -sn * mi[t]);
+          const double zi = fma(cs, mi[t], sn * mr[t]);
+          const double dot = fma(nx[t], dx, fma(ny[t], dy, nz[t] * dz));
+          const double u = dot * ir2;
+          const double sc = u * ir;
+          const double tt = FORM ? ewi[t] * ir : 0.0;
+          if (t == 0) {
+            cn[0] = sc * zr;
+            cn[1] = sc * zi;
+            cn[2] = u * zr;
+            cn[3] = u * zi;
+            if constexpr (FORM == 1) {
+              cn[4] = tt * zr;
+              cn[5] = tt * zi;
+            }
+          } else {
+            cn[0] = fma(sc, zr, cn[0]);
+            cn[1] = fma(sc, zi, cn[1]);
+            cn[2] = fma(u, zr, cn[2]);
+            cn[3] = fma(u, zi, cn[3]);
+            if constexpr (FORM == 1) {
+              cn[4] = fma(tt, zr, cn[4]);
+              cn[5] = fma(tt, zi, cn[5]);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < NA; ++a) acc[a] = from_next_lane(acc[a]) + cn[a];
+    }
+    if (wv == 1) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a) sX[a][lane] = acc[a];
+    }
+    __syncthreads();
+    if (wv == 0 && c * 64 + src < T.nb) {
+      double v[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) v[a] = acc[a] + sX[a][lane];
+      const double e3r = FORM ? v[4] : 0.0, e3i = FORM ? v[5] : 0.0;
+      // -S1 + i k S2 (- i S3)
+      part[T.joff + c * 64 + src] = make_double2(fma(-k, v[3], e3i - v[0]) * INV_FOUR_PI,
+                                                 fma(k, v[2], -v[1] - e3r) * INV_FOUR_PI);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int loc = wv * 128 + t * 64 + lane;
+    if (loc < T.nt)
+      part[T.ioff + loc] = make_double2(fma(-k, bi[t], ei[t] - ar[t]) * INV_FOUR_PI,
+                                        fma(k, br[t], -ai[t] - er[t]) * INV_FOUR_PI);
+  }
+}
+
 // out[n] = (accumulate ? out[n] : 0) + the task sums of n's block.  A
 // workgroup takes 64 consecutive nodes; wavefront w adds the list entries
 // w, w + 4, ... of each node, and the four sums are added in wavefront order
 // (a fixed order).
+template <typename P>
 __global__ __launch_bounds__(256) void reduce_sym_kernel(
-    const float2* __restrict__ part, const int32_t* __restrict__ node_body,
+    const P* __restrict__ part, const int32_t* __restrict__ node_body,
     const BodyDev* __restrict__ bodies, const int32_t* __restrict__ blk_base,
     const int32_t* __restrict__ ptr, const int64_t* __restrict__ list, int64_t N,
     double2* __restrict__ out, int accumulate) {
@@ -630,7 +806,7 @@ __global__ __launch_bounds__(256) void reduce_sym_kernel(
     const int e1 = ptr[blk + 1];
 #pragma unroll 4
     for (int e = ptr[blk] + w; e < e1; e += 4) {
-      const float2 v = part[list[e] + n];
+      const P v = part[list[e] + n];
       acc.x += (double)v.x;
       acc.y += (double)v.y;
     }
@@ -797,7 +973,7 @@ void plan_pair_sum(qax_problem* p, int prec, int cu_count) {
 
 hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count) {
   plan_pair_sum(p, prec, cu_count);
-  if (prec != QAX_FP64 && !p->sym.d_mem) {
+  if (!p->sym.d_mem) {
     // the reciprocal task table depends on the geometry only
     plan_sym(p);
     hipError_t e = upload_sym(p);
@@ -898,14 +1074,13 @@ static void launch_any(qax_problem* p, bool f64, int tpb, int nrc, const double*
 size_t pair_work_bytes(const qax_problem* p, int prec, int nrhs) {
   const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;
   size_t b = std::max((size_t)slots * p->N * nrhs * 16, lattice_work_bytes(p, nrhs));
-  if (prec != QAX_FP64 && nrhs == 1 && p->sym.ok)
-    b = std::max(b, (size_t)p->sym.nparts * 8);
+  if (nrhs == 1 && p->sym.ok)
+    b = std::max(b, (size_t)p->sym.nparts * (prec == QAX_FP64 ? 16 : 8));
   return b;
 }
 
 static bool use_sym(const qax_problem* p, int prec, int nrhs) {
-  return prec != QAX_FP64 && nrhs == 1 && p->sym.ok && p->sym.enabled && p->sym.d_mem &&
-         p->form() != 2;
+  return nrhs == 1 && p->sym.ok && p->sym.enabled && p->sym.d_mem && p->form() != 2;
 }
 
 hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
@@ -923,25 +1098,44 @@ hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* o
   const int kind = f64 ? QAX_K_PAIRSUM_FP64 : QAX_K_PAIRSUM_FP32;
   if (use_sym(p, prec, nrhs)) {
     auto& S = p->sym;
-    float2* part = (float2*)partial;
+    const int form = p->form();
     timing_begin(p, kind);
     if (!S.tasks.empty()) {
       const dim3 grid((unsigned)S.tasks.size());
-      if (p->form() == 1)
-        hipLaunchKernelGGL(pair_sum_f32_sym_kernel<1>, grid, dim3(128), 0, p->stream, S.d_tasks,
-                           p->d_bodies, (const float4*)p->d_loc32, (const float4*)p->d_aw32,
-                           p->d_ew32, (const double2*)mu, p->seg_active, part);
-      else
-        hipLaunchKernelGGL(pair_sum_f32_sym_kernel<0>, grid, dim3(128), 0, p->stream, S.d_tasks,
-                           p->d_bodies, (const float4*)p->d_loc32, (const float4*)p->d_aw32,
-                           p->d_ew32, (const double2*)mu, p->seg_active, part);
+      if (f64) {
+        double2* part = (double2*)partial;
+        if (form == 1)
+          hipLaunchKernelGGL(pair_sum_f64_sym_kernel<1>, grid, dim3(128), 0, p->stream, S.d_tasks,
+                             p->d_bodies, p->d_pos, p->d_aw, p->d_ew, p->N, (const double2*)mu,
+                             p->seg_active, part);
+        else
+          hipLaunchKernelGGL(pair_sum_f64_sym_kernel<0>, grid, dim3(128), 0, p->stream, S.d_tasks,
+                             p->d_bodies, p->d_pos, p->d_aw, p->d_ew, p->N, (const double2*)mu,
+                             p->seg_active, part);
+      } else {
+        float2* part = (float2*)partial;
+        if (form == 1)
+          hipLaunchKernelGGL(pair_sum_f32_sym_kernel<1>, grid, dim3(128), 0, p->stream, S.d_tasks,
+                             p->d_bodies, (const float4*)p->d_loc32, (const float4*)p->d_aw32,
+                             p->d_ew32, (const double2*)mu, p->seg_active, part);
+        else
+          hipLaunchKernelGGL(pair_sum_f32_sym_kernel<0>, grid, dim3(128), 0, p->stream, S.d_tasks,
+                             p->d_bodies, (const float4*)p->d_loc32, (const float4*)p->d_aw32,
+                             p->d_ew32, (const double2*)mu, p->seg_active, part);
+      }
     }
     timing_end(p, kind);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_sym_kernel, dim3((unsigned)((p->N + 63) / 64)), dim3(256), 0,
-                       p->stream, part, p->d_node_body, p->d_bodies, S.d_blk_base, S.d_ptr, S.d_list,
-                       p->N, (double2*)out, accumulate ? 1 : 0);
+    const dim3 rgrid((unsigned)((p->N + 63) / 64));
+    if (f64)
+      hipLaunchKernelGGL(reduce_sym_kernel<double2>, rgrid, dim3(256), 0, p->stream,
+                         (const double2*)partial, p->d_node_body, p->d_bodies, S.d_blk_base,
+                         S.d_ptr, S.d_list, p->N, (double2*)out, accumulate ? 1 : 0);
+    else
+      hipLaunchKernelGGL(reduce_sym_kernel<float2>, rgrid, dim3(256), 0, p->stream,
+                         (const float2*)partial, p->d_node_body, p->d_bodies, S.d_blk_base,
+                         S.d_ptr, S.d_list, p->N, (double2*)out, accumulate ? 1 : 0);
     return hipGetLastError();
   }
   const int tpb = p->tune.pair_tpb[pi];
