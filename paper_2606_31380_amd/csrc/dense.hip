@@ -992,6 +992,125 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void g
     }
 }
 
+// FP32 variant of the same update with three real products per complex one:
+// with P = Re a Re w, Q = Im a Im w and S = (Re a + Im a)(Re w + Im w), the
+// product is P - Q + i (S - P - Q), so the three 64 x 64 real products
+// replace the 64 x 128 x 2 real product above (a quarter fewer MFMA
+// operations).  Each wavefront owns 32 rows x 32 complex columns (2 x 2 tiles
+// of each product); the tile of A is read when the sums are stored.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void gjm3_update_kernel(
+    const MatDesc* __restrict__ mats, float2* __restrict__ pool, int k0, int ws,
+    const float2* __restrict__ W, int ldw, int64_t wstride, int jbase, int wcol0) {
+  typedef MfmaAcc<float>::v4 v4;
+  const MatDesc M = mats[blockIdx.z];
+  const int n = M.n;
+  if (k0 >= n) return;
+  const int kend = min(k0 + ws, n);
+  const int w = kend - k0;
+  const int i0 = blockIdx.y * 64, j0 = jbase + blockIdx.x * 64;
+  if (i0 >= n || j0 >= n) return;
+  if (j0 >= k0 && j0 + 64 <= kend) return;  // tile inside the panel columns
+  float2* A = pool + M.elem_off;
+  const float2* Wm = W + (int64_t)blockIdx.z * wstride;
+  // Re, Im and Re + Im of the A chunk (rows x k) and of the W chunk (k x
+  // columns); row strides 18 and 80 keep the operand reads of a
+  // half-wavefront (16 rows or columns x two k) on distinct banks
+  __shared__ float As[3][64][18];
+  __shared__ float Bs[3][16][80];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  v4 P[2][2], Q[2][2], S[2][2];
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) P[x][y][e] = Q[x][y][e] = S[x][y][e] = 0.0f;
+  float2 ra[4], rw[4];
+  auto load_chunk = [&](int p0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e >> 4, pp = e & 15;
+      const int i = i0 + rr, pc = p0 + pp;
+      ra[q] = (i < n && pc < w) ? A[(int64_t)i * n + k0 + pc] : make_float2(0.0f, 0.0f);
+      const int pw = e >> 6, jj = e & 63;
+      const int j = j0 + jj, pcw = p0 + pw;
+      rw[q] = (j < n && pcw < w) ? Wm[(int64_t)pcw * ldw + (j - wcol0)] : make_float2(0.0f, 0.0f);
+    }
+  };
+  load_chunk(0);
+  for (int p0 = 0; p0 < w; p0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      const int rr = e >> 4, pp = e & 15;
+      As[0][rr][pp] = ra[q].x;
+      As[1][rr][pp] = ra[q].y;
+      As[2][rr][pp] = ra[q].x + ra[q].y;
+      const int pw = e >> 6, jj = e & 63;
+      Bs[0][pw][jj] = rw[q].x;
+      Bs[1][pw][jj] = rw[q].y;
+      Bs[2][pw][jj] = rw[q].x + rw[q].y;
+    }
+    __syncthreads();
+    if (p0 + 16 < w) load_chunk(p0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4), ci = lane & 15;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        float af[2], bf[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) af[x] = As[m][wr + 16 * x + ci][kr];
+#pragma unroll
+        for (int y = 0; y < 2; ++y) bf[y] = Bs[m][kr][wc + 16 * y + ci];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            if (m == 0) P[x][y] = MfmaAcc<float>::mma(af[x], bf[y], P[x][y]);
+            else if (m == 1) Q[x][y] = MfmaAcc<float>::mma(af[x], bf[y], Q[x][y]);
+            else S[x][y] = MfmaAcc<float>::mma(af[x], bf[y], S[x][y]);
+          }
+      }
+    }
+    __syncthreads();
+  }
+  // A[i][j] = (i in panel ? 0 : A[i][j]) + P - Q + i (S - P - Q), for j
+  // outside the panel columns
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = i0 + wr + 16 * x + MfmaAcc<float>::row(lane, e);
+      if (i >= n) continue;
+      const bool prow = i >= k0 && i < kend;
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        const int j = j0 + wc + 16 * y + (lane & 15);
+        if (j >= n || (j >= k0 && j < kend)) continue;
+        float2* dst = A + (int64_t)i * n + j;
+        const float2 a = prow ? make_float2(0.0f, 0.0f) : *dst;
+        const float p = P[x][y][e], qv = Q[x][y][e];
+        *dst = make_float2(a.x + (p - qv), a.y + (S[x][y][e] - (p + qv)));
+      }
+    }
+}
+
+// The matrix-core update for either element type (FP32: three products).
+template <typename T>
+static void launch_gjm(dim3 grid, hipStream_t s, const MatDesc* d_mats, typename Cx<T>::V* pool,
+                       int k0, int ws, const typename Cx<T>::V* W, int ldw, int64_t wstride,
+                       int jbase, int wcol0) {
+  if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL(gjm3_update_kernel, grid, dim3(256), 0, s, d_mats, pool, k0, ws, W, ldw,
+                       wstride, jbase, wcol0);
+  else
+    hipLaunchKernelGGL(gjm_update_kernel<T>, grid, dim3(256), 0, s, d_mats, pool, k0, ws, W, ldw,
+                       wstride, jbase, wcol0);
+}
+
 // Leaf shape of the recursive panel factorization for matrices of order <= nmax:
 // R rows per thread (1024 threads), WL = min(8, 16 / R) columns.
 static int gj_leaf_rows(int nmax) {
@@ -1037,8 +1156,8 @@ static void launch_half_update(hipStream_t s, typename Cx<T>::V* pool, const Mat
                                unsigned rows_blocks) {
   if (h >= 64) {
     const unsigned tiles = (unsigned)((nmax + 63) / 64);
-    hipLaunchKernelGGL(gjm_update_kernel<T>, dim3((unsigned)(h / 64), tiles, batch), dim3(256), 0, s,
-                       d_mats, pool, s0, h, Wn, GJB, (int64_t)GJB * GJB, d0, d0);
+    launch_gjm<T>(dim3((unsigned)(h / 64), tiles, batch), s, d_mats, pool, s0, h, Wn, GJB,
+                  (int64_t)GJB * GJB, d0, d0);
   } else {
     hipLaunchKernelGGL(gjn_update_kernel<T>, dim3(rows_blocks, batch), dim3(256), 0, s, d_mats, pool,
                        s0, h, d0, h, Wn);
@@ -1087,8 +1206,8 @@ hipError_t gj_invert(qax_problem* p, T* pool, const MatDesc* d_mats, int batch, 
     hipLaunchKernelGGL(gjb_swap_copy_kernel<T>, dim3((nmax + 255) / 256, batch), dim3(256), 0, s,
                        d_mats, (V*)pool, k0, piv, nmax, W);
     if (timed) timing_begin(p, QAX_K_INVERT_UPDATE);
-    hipLaunchKernelGGL(gjm_update_kernel<T>, dim3(tiles, tiles, batch), dim3(256), 0, s, d_mats,
-                       (V*)pool, k0, GJB, W, nmax, (int64_t)GJB * nmax, 0, 0);
+    launch_gjm<T>(dim3(tiles, tiles, batch), s, d_mats, (V*)pool, k0, GJB, W, nmax,
+                  (int64_t)GJB * nmax, 0, 0);
     if (timed) timing_end(p, QAX_K_INVERT_UPDATE);
   }
   hipLaunchKernelGGL(gj_unpivot_kernel<T>, dim3((nmax + 255) / 256, batch), dim3(256), 0, s, d_mats,
