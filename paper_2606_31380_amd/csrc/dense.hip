@@ -846,20 +846,22 @@ __global__ __launch_bounds__(256) void gjn_update_kernel(const MatDesc* __restri
 // Row interchanges of the panel applied to the other columns, then the panel
 // rows copied to W (w x n per matrix).
 template <typename T>
-__global__ void gjb_swap_copy_kernel(const MatDesc* __restrict__ mats, typename Cx<T>::V* __restrict__ pool,
-                                     int k0, const int32_t* __restrict__ piv, int nmax,
-                                     typename Cx<T>::V* __restrict__ W) {
+__global__ __launch_bounds__(256) void gjb_swap_copy_kernel(const MatDesc* __restrict__ mats,
+                                                            typename Cx<T>::V* __restrict__ pool,
+                                                            int k0, const int32_t* __restrict__ piv,
+                                                            int nmax, typename Cx<T>::V* __restrict__ W) {
   typedef typename Cx<T>::V V;
   const MatDesc M = mats[blockIdx.y];
   const int n = M.n;
-  if (k0 >= n) return;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  if (k0 >= n || (int)blockIdx.x * 64 >= n) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + lane;
   const int kend = min(k0 + GJB, n);
   V* A = pool + M.elem_off;
   V* Wm = W + (int64_t)blockIdx.y * GJB * nmax;
   const bool in_panel = j >= k0 && j < kend;
-  if (!in_panel) {
+  // the interchanges, in order, on the workgroup's 64 columns (first wavefront)
+  if (wv == 0 && j < n && !in_panel) {
     const int32_t* pv = piv + (int64_t)blockIdx.y * nmax;
     for (int k = k0; k < kend; ++k) {
       const int pr = pv[k];
@@ -870,8 +872,13 @@ __global__ void gjb_swap_copy_kernel(const MatDesc* __restrict__ mats, typename 
       }
     }
   }
-  for (int k = k0; k < kend; ++k)
-    Wm[(int64_t)(k - k0) * nmax + j] = in_panel ? Cx<T>::make(0.0, 0.0) : A[(int64_t)k * n + j];
+  __syncthreads();
+  // the panel rows into W, every fourth row per wavefront
+  if (j < n) {
+#pragma unroll 8
+    for (int k = k0 + wv; k < kend; k += 4)
+      Wm[(int64_t)(k - k0) * nmax + j] = in_panel ? Cx<T>::make(0.0, 0.0) : A[(int64_t)k * n + j];
+  }
 }
 
 // A[i][j] = (i in panel ? 0 : A[i][j]) + sum_p A[i][k0+p] W[p][j] for j outside
@@ -1203,7 +1210,7 @@ hipError_t gj_invert(qax_problem* p, T* pool, const MatDesc* d_mats, int batch, 
   const unsigned tiles = (unsigned)((nmax + 63) / 64);
   for (int k0 = 0; k0 < nmax; k0 += GJB) {
     gj_factor_panel<T>(s, (V*)pool, d_mats, batch, nmax, k0, GJB, piv, Wn);
-    hipLaunchKernelGGL(gjb_swap_copy_kernel<T>, dim3((nmax + 255) / 256, batch), dim3(256), 0, s,
+    hipLaunchKernelGGL(gjb_swap_copy_kernel<T>, dim3((nmax + 63) / 64, batch), dim3(256), 0, s,
                        d_mats, (V*)pool, k0, piv, nmax, W);
     if (timed) timing_begin(p, QAX_K_INVERT_UPDATE);
     launch_gjm<T>(dim3(tiles, tiles, batch), s, d_mats, (V*)pool, k0, GJB, W, nmax,
