@@ -81,6 +81,44 @@ static void* dbuf(qax_problem* p, const char* name, size_t bytes, qax_status* st
 
 void* scratch(qax_problem* p, size_t bytes, qax_status* st) { return dbuf(p, "scratch", bytes, st); }
 
+// A rebuild of the same geometry asks for the same sizes again: buffers it
+// released are handed back instead of freed and allocated anew (all work on
+// them is ordered on the handle's stream).
+void dev_drop_spare(qax_problem* p) {
+  for (auto& kv : p->spare) (void)hipFree(kv.second);
+  p->spare.clear();
+}
+
+hipError_t dev_alloc(qax_problem* p, void** ptr, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 256);
+  auto it = p->spare.find(bytes);
+  if (it != p->spare.end()) {
+    *ptr = it->second;
+    p->spare.erase(it);
+    p->live[*ptr] = bytes;
+    return hipSuccess;
+  }
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e == hipErrorOutOfMemory && !p->spare.empty()) {
+    (void)hipGetLastError();
+    dev_drop_spare(p);
+    e = hipMalloc(ptr, bytes);
+  }
+  if (e == hipSuccess) p->live[*ptr] = bytes;
+  return e;
+}
+
+void dev_release(qax_problem* p, void* q) {
+  if (!q) return;
+  auto it = p->live.find(q);
+  if (it == p->live.end()) {
+    (void)hipFree(q);
+    return;
+  }
+  p->spare.emplace(it->second, q);
+  p->live.erase(it);
+}
+
 static hipEvent_t take_event(qax_problem* p) {
   if (!p->event_pool.empty()) {
     hipEvent_t e = p->event_pool.back();
@@ -166,17 +204,16 @@ static void free_geometry(qax_problem* p) {
   void* ptrs[] = {p->d_bodies, p->d_blocks, p->d_node_body, p->d_pos,  p->d_aw,
                   p->d_loc32,  p->d_aw32,   p->d_gl,        p->d_B,    p->d_Binv,
                   p->d_Binv32, p->d_tasks64, p->d_tasks32, p->d_ew, p->d_ew32, p->d_B32};
-  for (void* q : ptrs)
-    if (q) (void)hipFree(q);
+  for (void* q : ptrs) dev_release(p, q);
   p->d_bodies = nullptr; p->d_blocks = nullptr; p->d_node_body = nullptr;
   p->d_pos = nullptr; p->d_aw = nullptr; p->d_loc32 = nullptr; p->d_aw32 = nullptr;
   p->d_gl = nullptr; p->d_B = nullptr; p->d_Binv = nullptr; p->d_Binv32 = nullptr;
   p->d_B32 = nullptr;
   p->d_tasks64 = nullptr; p->d_tasks32 = nullptr;
   p->d_ew = nullptr; p->d_ew32 = nullptr;
-  if (p->d_gemm_tasks) (void)hipFree(p->d_gemm_tasks);
+  dev_release(p, p->d_gemm_tasks);
   p->d_gemm_tasks = nullptr;
-  if (p->sym.d_mem) (void)hipFree(p->sym.d_mem);
+  dev_release(p, p->sym.d_mem);
   p->sym.d_mem = nullptr;
   p->sym.tasks.clear();
   p->gemm_tasks.clear();
@@ -196,6 +233,7 @@ extern "C" void qax_destroy(qax_problem* p) {
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   p->cap_stream = nullptr;
   free_geometry(p);
+  dev_drop_spare(p);
   collect_timing(p);
   for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
   auto it = registry().find(p);
@@ -383,16 +421,16 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
   p->N = p->off[n_bodies];
   p->block_elems = elems;
   const int64_t N = p->N;
-  QCHECK(hipMalloc(&p->d_bodies, sizeof(BodyDev) * n_bodies), "alloc bodies");
-  QCHECK(hipMalloc(&p->d_blocks, sizeof(BlockDev) * p->hblocks.size()), "alloc blocks");
-  QCHECK(hipMalloc(&p->d_node_body, sizeof(int32_t) * N), "alloc node_body");
-  QCHECK(hipMalloc(&p->d_pos, sizeof(double) * 3 * N), "alloc pos");
-  QCHECK(hipMalloc(&p->d_aw, sizeof(double) * 3 * N), "alloc aw");
-  QCHECK(hipMalloc(&p->d_loc32, sizeof(float) * 4 * N), "alloc loc32");
-  QCHECK(hipMalloc(&p->d_aw32, sizeof(float) * 4 * N), "alloc aw32");
-  QCHECK(hipMalloc(&p->d_ew, sizeof(double) * N), "alloc ew");
-  QCHECK(hipMalloc(&p->d_ew32, sizeof(float) * N), "alloc ew32");
-  QCHECK(hipMalloc(&p->d_gl, sizeof(double) * 3 * GL_ORDER), "alloc gl");
+  QCHECK(dev_alloc(p, (void**)&p->d_bodies, sizeof(BodyDev) * n_bodies), "alloc bodies");
+  QCHECK(dev_alloc(p, (void**)&p->d_blocks, sizeof(BlockDev) * p->hblocks.size()), "alloc blocks");
+  QCHECK(dev_alloc(p, (void**)&p->d_node_body, sizeof(int32_t) * N), "alloc node_body");
+  QCHECK(dev_alloc(p, (void**)&p->d_pos, sizeof(double) * 3 * N), "alloc pos");
+  QCHECK(dev_alloc(p, (void**)&p->d_aw, sizeof(double) * 3 * N), "alloc aw");
+  QCHECK(dev_alloc(p, (void**)&p->d_loc32, sizeof(float) * 4 * N), "alloc loc32");
+  QCHECK(dev_alloc(p, (void**)&p->d_aw32, sizeof(float) * 4 * N), "alloc aw32");
+  QCHECK(dev_alloc(p, (void**)&p->d_ew, sizeof(double) * N), "alloc ew");
+  QCHECK(dev_alloc(p, (void**)&p->d_ew32, sizeof(float) * N), "alloc ew32");
+  QCHECK(dev_alloc(p, (void**)&p->d_gl, sizeof(double) * 3 * GL_ORDER), "alloc gl");
   double gl[3 * GL_ORDER];   // nodes, weights, barycentric weights on [-1, 1]
   gauss_legendre_host(GL_ORDER, gl, gl + GL_ORDER);
   for (int l = 0; l < GL_ORDER; ++l) {
@@ -460,10 +498,10 @@ extern "C" qax_status qax_assemble_self(qax_problem* p, double* t_setup_s) {
   QCHECK(hipStreamSynchronize(p->stream), "sync");
   auto t0 = std::chrono::steady_clock::now();
   if (!p->d_B) {
-    QCHECK(hipMalloc(&p->d_B, (size_t)p->block_elems * 16), "alloc self blocks");
-    QCHECK(hipMalloc(&p->d_Binv, (size_t)p->block_elems * 16), "alloc inverse blocks");
-    QCHECK(hipMalloc(&p->d_Binv32, (size_t)p->block_elems * 8), "alloc inverse blocks fp32");
-    QCHECK(hipMalloc(&p->d_B32, (size_t)p->block_elems * 8), "alloc self blocks fp32");
+    QCHECK(dev_alloc(p, (void**)&p->d_B, (size_t)p->block_elems * 16), "alloc self blocks");
+    QCHECK(dev_alloc(p, (void**)&p->d_Binv, (size_t)p->block_elems * 16), "alloc inverse blocks");
+    QCHECK(dev_alloc(p, (void**)&p->d_Binv32, (size_t)p->block_elems * 8), "alloc inverse blocks fp32");
+    QCHECK(dev_alloc(p, (void**)&p->d_B32, (size_t)p->block_elems * 8), "alloc self blocks fp32");
   }
   QCHECK(launch_assemble_self(p), "assemble_self");
   QBUF(work, double, "gj_work", invert_blocks_work_bytes(p));

@@ -337,7 +337,7 @@ hipError_t ensure_gemm_tasks(qax_problem* p) {
   if (!p->gemm_tasks.empty()) return hipSuccess;
   for (int b = 0; b < p->n_bodies; ++b)
     for (int r0 = 0; r0 < p->hbodies[b].n; r0 += 64) p->gemm_tasks.push_back(GemmTask{b, r0});
-  hipError_t e = hipMalloc(&p->d_gemm_tasks, p->gemm_tasks.size() * sizeof(GemmTask));
+  hipError_t e = dev_alloc(p, &p->d_gemm_tasks, p->gemm_tasks.size() * sizeof(GemmTask));
   if (e != hipSuccess) {
     p->gemm_tasks.clear();
     return e;

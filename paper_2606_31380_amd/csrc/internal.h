@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <string>
 #include <vector>
 
@@ -115,6 +116,11 @@ struct qax_problem {
   std::vector<qax::BlockDev> hblocks;
   int64_t N = 0;
   int64_t block_elems = 0;            // sum of n^2 over distinct blocks
+
+  // device buffers released by a rebuild, kept for the next allocation of
+  // the same size (freed by qax_destroy, or when an allocation fails)
+  std::multimap<size_t, void*> spare;
+  std::map<void*, size_t> live;
 
   // device geometry
   qax::BodyDev* d_bodies = nullptr;
@@ -242,6 +248,10 @@ hipError_t launch_gemm_tables(hipStream_t s, const GemmTask* tasks, int ntasks,
                               bool f32, const double* v, int nrhs, double* out, bool accumulate);
 
 // pairsum.hip
+// Device allocation through the handle's cache of released buffers.
+hipError_t dev_alloc(qax_problem* p, void** ptr, size_t bytes);
+void dev_release(qax_problem* p, void* ptr);
+void dev_drop_spare(qax_problem* p);
 size_t pair_work_bytes(const qax_problem* p, int prec, int nrhs);
 hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
                            double* partial, bool accumulate);

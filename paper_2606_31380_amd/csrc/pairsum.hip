@@ -879,7 +879,7 @@ static hipError_t upload_sym(qax_problem* p) {
   if (S.d_mem) {
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return e;
-    (void)hipFree(S.d_mem);
+    dev_release(p, S.d_mem);
     S.d_mem = nullptr;
   }
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -887,7 +887,7 @@ static hipError_t upload_sym(qax_problem* p) {
   const size_t bb = al(sizeof(int32_t) * S.h_blk_base.size());
   const size_t bp = al(sizeof(int32_t) * S.h_ptr.size());
   const size_t bl = al(sizeof(int64_t) * std::max<size_t>(1, S.h_list.size()));
-  hipError_t e = hipMalloc(&S.d_mem, bt + bb + bp + bl);
+  hipError_t e = dev_alloc(p, &S.d_mem, bt + bb + bp + bl);
   if (e != hipSuccess) return e;
   char* m = (char*)S.d_mem;
   S.d_tasks = (SymTask*)m;
@@ -985,10 +985,10 @@ hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count) {
   if (d) {
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return e;
-    (void)hipFree(d);
+    dev_release(p, d);
     d = nullptr;
   }
-  hipError_t e = hipMalloc(&d, sizeof(PairTask) * t.size());
+  hipError_t e = dev_alloc(p, (void**)&d, sizeof(PairTask) * t.size());
   if (e != hipSuccess) return e;
   e = hipMemcpyAsync(d, t.data(), sizeof(PairTask) * t.size(), hipMemcpyHostToDevice, p->stream);
   if (e != hipSuccess) return e;
