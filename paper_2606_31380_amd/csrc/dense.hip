@@ -431,6 +431,18 @@ hipError_t launch_convert_f32(hipStream_t s, const double* src, float* dst, int6
   return hipGetLastError();
 }
 
+// B rounded to FP32 into both the FP32 blocks and the buffer the FP32
+// inverse is made in (one read of the FP64 blocks); two values per thread.
+__global__ void convert_f32_twice_kernel(const double2* __restrict__ src, float2* __restrict__ d0,
+                                         float2* __restrict__ d1, int64_t pairs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= pairs) return;
+  const double2 v = src[e];
+  const float2 f = make_float2((float)v.x, (float)v.y);
+  d0[e] = f;
+  d1[e] = f;
+}
+
 __global__ void convert_f64_kernel(const float* __restrict__ src, double* __restrict__ dst,
                                    int64_t count) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1283,10 +1295,11 @@ hipError_t launch_invert_blocks(qax_problem* p, double* work) {
   double* w2;
   int nmax;
   p->inv64_ready = false;
-  hipError_t e = launch_convert_f32(p->stream, p->d_B, p->d_B32, p->block_elems * 2);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(p->d_Binv32, p->d_B32, (size_t)p->block_elems * 8, hipMemcpyDeviceToDevice,
-                       p->stream);
+  // block_elems complex elements = block_elems (re, im) pairs
+  hipLaunchKernelGGL(convert_f32_twice_kernel, dim3((unsigned)((p->block_elems + 255) / 256)),
+                     dim3(256), 0, p->stream, (const double2*)p->d_B, (float2*)p->d_B32,
+                     (float2*)p->d_Binv32, p->block_elems);
+  hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = upload_mats(p, work, &d_md, &w2, &nmax);
   if (e != hipSuccess) return e;
   timing_begin(p, QAX_K_INVERT);

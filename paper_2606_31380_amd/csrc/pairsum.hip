@@ -862,9 +862,12 @@ static void plan_sym(qax_problem* p) {
           }
   }
   S.nparts = off;
-  std::stable_sort(S.tasks.begin(), S.tasks.end(), [](const SymTask& x, const SymTask& y) {
-    return (int64_t)x.nt * x.nb > (int64_t)y.nt * y.nb;
-  });
+  auto cost = [](const SymTask& x) { return (int64_t)x.nt * x.nb; };
+  bool uniform = true;
+  for (const SymTask& T : S.tasks) uniform = uniform && cost(T) == cost(S.tasks[0]);
+  if (!uniform)
+    std::stable_sort(S.tasks.begin(), S.tasks.end(),
+                     [&](const SymTask& x, const SymTask& y) { return cost(x) > cost(y); });
   S.h_blk_base = blk_base;
   S.h_ptr.assign(1, 0);
   S.h_list.clear();
