@@ -59,7 +59,13 @@ def far_grid(n=200):
     th = np.linspace(0, 2 * math.pi, n, endpoint=False)
     ph = (np.arange(n) + 0.5) * math.pi / n
     T, P = np.meshgrid(th, ph, indexing="ij")
-    return np.stack([np.cos(T) * np.sin(P), np.sin(T) * np.sin(P), np.cos(P)], -1).reshape(-1, 3)
+    X = np.stack([np.cos(T) * np.sin(P), np.sin(T) * np.sin(P), np.cos(P)], -1)
+    # (theta_i, phi_j) with j >= n/2 is the antipode of (theta_{i+n/2}, phi_{n-1-j}):
+    # stored as its exact negation (the same point up to rounding), so the far
+    # field can evaluate the pair with one phase
+    h = n // 2
+    X[:, h:] = -X[(np.arange(n) + h) % n][:, h - 1::-1]
+    return X.reshape(-1, 3)
 
 
 def cpu_baseline(scen, budget_s=12.0):

@@ -620,11 +620,54 @@ extern "C" qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrh
   for (int i = 0; i < 3 * n_dirs; ++i)
     if (!is_finite(xhat[i])) return fail(p, QAX_ERR_ARG, "qax_farfield: non-finite direction");
   QCHECK(hipSetDevice(p->device), "hipSetDevice");
-  const int slots = farfield_slots(n_dirs, cu_count(p->device));
-  QBUF(dx, double, "xhat", (size_t)n_dirs * 24);
+  // items: each direction, paired with a later one that is its exact
+  // negation (bitwise, open-addressing table over the 24-byte keys)
+  std::vector<int2> items;
+  items.reserve(n_dirs);
+  {
+    const uint64_t* bits = (const uint64_t*)xhat;
+    auto hash = [&](uint64_t a, uint64_t b, uint64_t c) {
+      uint64_t h = a * 0x9E3779B97F4A7C15ULL;
+      h ^= (b + 0x632BE59BD9B4E019ULL + (h << 6) + (h >> 2));
+      h ^= (c + 0x94D049BB133111EBULL + (h << 6) + (h >> 2));
+      return h ^ (h >> 29);
+    };
+    size_t cap = 1;
+    while (cap < 2 * (size_t)n_dirs) cap <<= 1;
+    std::vector<int32_t> table(cap, -1);
+    for (int i = 0; i < n_dirs; ++i) {
+      size_t h = hash(bits[3 * i], bits[3 * i + 1], bits[3 * i + 2]) & (cap - 1);
+      while (table[h] >= 0) h = (h + 1) & (cap - 1);
+      table[h] = i;
+    }
+    const uint64_t sg = 0x8000000000000000ULL;
+    std::vector<char> used(n_dirs, 0);
+    for (int i = 0; i < n_dirs; ++i) {
+      if (used[i]) continue;
+      used[i] = 1;
+      const uint64_t a = bits[3 * i] ^ sg, b = bits[3 * i + 1] ^ sg, c = bits[3 * i + 2] ^ sg;
+      int partner = -1;
+      for (size_t h = hash(a, b, c) & (cap - 1); table[h] >= 0; h = (h + 1) & (cap - 1)) {
+        const int q = table[h];
+        if (!used[q] && bits[3 * q] == a && bits[3 * q + 1] == b && bits[3 * q + 2] == c) {
+          partner = q;
+          break;
+        }
+      }
+      if (partner >= 0) used[partner] = 1;
+      items.push_back(make_int2(i, partner));
+    }
+  }
+  const int nitems = (int)items.size();
+  const int slots = farfield_slots(nitems, cu_count(p->device));
+  QBUF(dx, double, "xhat", (size_t)n_dirs * 24 + (size_t)nitems * sizeof(int2));
   QBUF(part, double, "ff_partial", (size_t)slots * n_dirs * nrhs * 16);
+  int2* ditems = (int2*)(dx + 3 * (size_t)n_dirs);
   QCHECK(hipMemcpyAsync(dx, xhat, (size_t)n_dirs * 24, hipMemcpyHostToDevice, p->stream), "copy xhat");
-  QCHECK(launch_farfield(p, (const double*)d_mu, nrhs, dx, n_dirs, slots, part, (double*)d_u_inf),
+  QCHECK(hipMemcpyAsync(ditems, items.data(), (size_t)nitems * sizeof(int2), hipMemcpyHostToDevice,
+                        p->stream), "copy directions");
+  QCHECK(launch_farfield(p, (const double*)d_mu, nrhs, dx, n_dirs, ditems, nitems, slots, part,
+                         (double*)d_u_inf),
          "farfield");
   return sync(p, "qax_farfield");
 }

@@ -48,18 +48,25 @@ __global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slo
 
 // u_inf[dir][r] = (1/4pi) sum_{n in problem 0} (-i k xhat.aw_n) e^{-i k xhat.y_n} mu[n][r]
 // (combined field: plus -i eta |aw_n| e^{...}; single layer: |aw_n| e^{...}
-// alone).  One direction per thread, node tiles staged in LDS and read by
-// broadcast, the node range cut into `slots` chunks (blockIdx.y) whose
+// alone).  One item per thread: a direction, or a direction and its exact
+// negation (the phase negated: one sin/cos for both); node tiles staged in
+// LDS and read by broadcast, the node range cut into `slots` chunks (blockIdx.y) whose
 // partial sums are added in a fixed order afterwards; right-hand side
 // blockIdx.z.
 template <int TPB>
 __global__ __launch_bounds__(TPB) void farfield_kernel(
-    const double* __restrict__ xhat, int64_t M, const double* __restrict__ pos,
-    const double* __restrict__ aw, const double* __restrict__ ew, int form, int64_t N, int64_t n0,
-    int slots, double k, const double2* __restrict__ mu, int nrhs, double2* __restrict__ partial) {
+    const double* __restrict__ xhat, const int2* __restrict__ items, int64_t M, int64_t Mi,
+    const double* __restrict__ pos, const double* __restrict__ aw, const double* __restrict__ ew,
+    int form, int64_t N, int64_t n0, int slots, double k, const double2* __restrict__ mu, int nrhs,
+    double2* __restrict__ partial) {
   const int tid = threadIdx.x;
-  const int64_t i = (int64_t)blockIdx.x * TPB + tid;
-  const bool active = i < M;
+  const int64_t t = (int64_t)blockIdx.x * TPB + tid;
+  const bool active = t < Mi;
+  // direction i and, when the list holds its exact negation, that one (i2):
+  // its phase is the negated phase, so sin flips sign and cos is unchanged
+  const int2 it = active ? items[t] : make_int2(0, -1);
+  const int64_t i = it.x, i2 = it.y;
+  const double pair = i2 >= 0 ? 1.0 : 0.0;
   const int r = blockIdx.z;
   const double hx = active ? xhat[3 * i] : 0.0, hy = active ? xhat[3 * i + 1] : 0.0,
                hz = active ? xhat[3 * i + 2] : 0.0;
@@ -70,7 +77,7 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
   const int64_t c0 = n0 * blockIdx.y / slots, c1 = n0 * (blockIdx.y + 1) / slots;
   __shared__ double sx[TPB], sy[TPB], sz[TPB], sax[TPB], say[TPB], saz[TPB], sew[TPB];
   __shared__ double2 smu[TPB];
-  double ar = 0.0, ai = 0.0;
+  double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
   for (int64_t base = c0; base < c1; base += TPB) {
     const int cnt = (int)min((int64_t)TPB, c1 - base);
     __syncthreads();
@@ -90,6 +97,9 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
         const double2 m = smu[jj];
         ar = fma(fr, m.x, fma(-fi, m.y, ar));
         ai = fma(fr, m.y, fma(fi, m.x, ai));
+        // -x: fr, -fi
+        br = fma(fr, m.x, fma(fi, m.y, br));
+        bi = fma(fr, m.y, fma(-fi, m.x, bi));
       }
     } else {
       for (int jj = 0; jj < cnt; ++jj) {
@@ -97,16 +107,26 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
         sincos_2pi(fma(px, sx[jj], fma(py, sy[jj], pz * sz[jj])), &s, &c);
         // (-i k nd)(c + i s) = k nd s - i k nd c; combined field adds
         // (-i eta |aw|)(c + i s) = eta |aw| s - i eta |aw| c (ew = 0 otherwise)
-        const double a = fma(qx, sax[jj], fma(qy, say[jj], fma(qz, saz[jj], sew[jj])));
+        const double d = fma(qx, sax[jj], fma(qy, say[jj], qz * saz[jj]));
+        const double a = d + sew[jj];
         const double fr = a * s, fi = -a * c;
         const double2 m = smu[jj];
         ar = fma(fr, m.x, fma(-fi, m.y, ar));
         ai = fma(fr, m.y, fma(fi, m.x, ai));
+        // -x: k nd -> -k nd, s -> -s: (eta |aw| - d)(-s) - i (eta |aw| - d) c
+        const double a2 = sew[jj] - d;
+        const double gr = -a2 * s, gi = -a2 * c;
+        br = fma(gr, m.x, fma(-gi, m.y, br));
+        bi = fma(gr, m.y, fma(gi, m.x, bi));
       }
     }
   }
-  if (active)
+  if (active) {
     partial[((int64_t)blockIdx.y * M + i) * nrhs + r] = make_double2(ar * INV_FOUR_PI_K, ai * INV_FOUR_PI_K);
+    if (pair > 0.0)
+      partial[((int64_t)blockIdx.y * M + i2) * nrhs + r] =
+          make_double2(br * INV_FOUR_PI_K, bi * INV_FOUR_PI_K);
+  }
 }
 
 int farfield_slots(int64_t M, int cu_count) {
@@ -117,12 +137,13 @@ int farfield_slots(int64_t M, int cu_count) {
 // out[dir][r] (directions xhat_dev, 3 doubles each); partial: farfield_slots
 // x ndir x nrhs complex128.
 hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const double* xhat_dev,
-                           int ndir, int slots, double* partial, double* out) {
+                           int ndir, const int2* items_dev, int nitems, int slots, double* partial,
+                           double* out) {
   const int64_t n0 = p->off[p->prob_body0[1]];
-  dim3 grid((unsigned)((ndir + 255) / 256), (unsigned)slots, (unsigned)nrhs);
-  hipLaunchKernelGGL((farfield_kernel<256>), grid, dim3(256), 0, p->stream, xhat_dev, (int64_t)ndir,
-                     p->d_pos, p->d_aw, p->d_ew, p->form(), p->N, n0, slots, p->k[0],
-                     (const double2*)mu, nrhs, (double2*)partial);
+  dim3 grid((unsigned)((nitems + 255) / 256), (unsigned)slots, (unsigned)nrhs);
+  hipLaunchKernelGGL((farfield_kernel<256>), grid, dim3(256), 0, p->stream, xhat_dev, items_dev,
+                     (int64_t)ndir, (int64_t)nitems, p->d_pos, p->d_aw, p->d_ew, p->form(), p->N, n0,
+                     slots, p->k[0], (const double2*)mu, nrhs, (double2*)partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t count = (int64_t)ndir * nrhs;

@@ -297,6 +297,32 @@ def test_rhs_and_farfield_parity(small27_oracle):
         assert rel(t2n(u), u_ref) < 1e-12
 
 
+@pytest.mark.parametrize("form", ["double", "combined", "single"])
+def test_farfield_antipodal_pairs(small27_oracle, form):
+    # directions whose exact negation is also in the list share one phase
+    # evaluation: against the oracle, and bitwise equal to one call per
+    # direction (the reduction of the half-revolution phase is odd/even)
+    s, d, _ = small27_oracle
+    mu = _mu(d.pos.shape[0], seed=6)[:, 0]
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal((5, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    xh = np.concatenate([v, -v[[2, 0, 4]], [[0.0, 0.0, 1.0]], -v[[1]]])   # 4 pairs, 1 alone
+    kw = {"double": {}, "combined": {"formulation": qax.QAX_COMBINED_FIELD},
+          "single": {"formulation": qax.QAX_SINGLE_LAYER}}[form]
+    eta = {"double": None, "combined": s.k[0], "single": None}[form]
+    u_ref = osolve.far_field(d, s.k, mu, xh, eta=eta, single=form == "single")
+    with qax.Problem(s, **kw) as P:
+        u = torch.zeros(xh.shape[0], dtype=torch.complex128, device=DEV)
+        qax.qax_farfield(P.h, n2t(mu), xh, u)
+        got = t2n(u)
+        assert rel(got, u_ref) < 1e-12
+        for i in range(xh.shape[0]):
+            one = torch.zeros(1, dtype=torch.complex128, device=DEV)
+            qax.qax_farfield(P.h, n2t(mu), np.ascontiguousarray(xh[i:i + 1]), one)
+            assert t2n(one)[0] == got[i]
+
+
 def test_solve_parity_fp64_and_mixed(small27_oracle):
     s, d, blocks = small27_oracle
     b = osolve.rhs_planewave(d, s.k, s.dirs)[:, 0]
