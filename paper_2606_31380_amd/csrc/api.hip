@@ -230,6 +230,8 @@ extern "C" void qax_destroy(qax_problem* p) {
   p->graphs.clear();
   if (p->h_flags) (void)hipHostFree(p->h_flags);
   p->h_flags = nullptr;
+  if (p->h_stage) (void)hipHostFree(p->h_stage);
+  p->h_stage = nullptr;
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   p->cap_stream = nullptr;
   free_geometry(p);
@@ -660,12 +662,21 @@ extern "C" qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrh
   }
   const int nitems = (int)items.size();
   const int slots = farfield_slots(nitems, cu_count(p->device));
-  QBUF(dx, double, "xhat", (size_t)n_dirs * 24 + (size_t)nitems * sizeof(int2));
+  const size_t up = (size_t)n_dirs * 24 + (size_t)nitems * sizeof(int2);
+  QBUF(dx, double, "xhat", up);
   QBUF(part, double, "ff_partial", (size_t)slots * n_dirs * nrhs * 16);
   int2* ditems = (int2*)(dx + 3 * (size_t)n_dirs);
-  QCHECK(hipMemcpyAsync(dx, xhat, (size_t)n_dirs * 24, hipMemcpyHostToDevice, p->stream), "copy xhat");
-  QCHECK(hipMemcpyAsync(ditems, items.data(), (size_t)nitems * sizeof(int2), hipMemcpyHostToDevice,
-                        p->stream), "copy directions");
+  // directions and items through pinned staging: one asynchronous copy
+  if (p->h_stage_bytes < up) {
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    p->h_stage = nullptr;
+    p->h_stage_bytes = 0;
+    QCHECK(hipHostMalloc(&p->h_stage, up, hipHostMallocDefault), "pinned staging");
+    p->h_stage_bytes = up;
+  }
+  std::memcpy(p->h_stage, xhat, (size_t)n_dirs * 24);
+  std::memcpy((char*)p->h_stage + (size_t)n_dirs * 24, items.data(), (size_t)nitems * sizeof(int2));
+  QCHECK(hipMemcpyAsync(dx, p->h_stage, up, hipMemcpyHostToDevice, p->stream), "copy directions");
   QCHECK(launch_farfield(p, (const double*)d_mu, nrhs, dx, n_dirs, ditems, nitems, slots, part,
                          (double*)d_u_inf),
          "farfield");

@@ -121,6 +121,10 @@ struct qax_problem {
   // the same size (freed by qax_destroy, or when an allocation fails)
   std::multimap<size_t, void*> spare;
   std::map<void*, size_t> live;
+  // pinned host staging for uploads of call arguments (grow-only; every call
+  // that uses it synchronises before returning)
+  void* h_stage = nullptr;
+  size_t h_stage_bytes = 0;
 
   // device geometry
   qax::BodyDev* d_bodies = nullptr;
