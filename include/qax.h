@@ -50,7 +50,8 @@ typedef enum {
 typedef enum {
   QAX_FP64 = 0,   /* every step in FP64                                        */
   QAX_MIXED = 1   /* inter-body pair sum in FP32 with compensated accumulation,
-                     preconditioner in FP32, inside FP64 iterative refinement  */
+                     self blocks and their inverses applied from FP32 copies,
+                     inside FP64 iterative refinement                          */
 } qax_prec;
 
 typedef enum {
@@ -125,13 +126,27 @@ qax_status qax_nodes(const qax_problem* p, double* d_pos, double* d_aw);
 
 /* Assemble every distinct self block B = 1/2 I + D_bb in FP64 (Sections
  * 3.1-3.4: modal Green's functions by recurrence, FFT and convolution; product
- * integration in s), then its inverse computed in FP32 from B rounded to FP32
- * (the block-diagonal preconditioner of Section 6 for the mixed path).  The
- * FP64 inverse is computed by the first call that needs it after an
- * assembly (qax_self_block with inverse, qax_block_apply with inverse in
- * QAX_FP64, QAX_FP64 solves; outside their solve time).  *t_setup_s (may be
- * NULL) receives the wall time. */
+ * integration in s), then factor it: by default its inverse is computed in
+ * FP64 (Gauss-Jordan with partial pivoting; the block-diagonal preconditioner
+ * of Section 6) and B and B^-1 are rounded to FP32 for the mixed path.  With
+ * qax_set_factorization(p, QAX_MIXED) the inverse is instead computed in FP32
+ * from B rounded to FP32, and the FP64 inverse is made by the first call that
+ * needs it (qax_self_block with inverse, qax_block_apply with inverse in
+ * QAX_FP64, QAX_FP64 solves; outside their solve time).  The quadrature
+ * rules are fixed (converged to about 1e-13 relative for the supported
+ * shapes and discretisations), so no accuracy argument is taken.
+ * *t_setup_s (may be NULL) receives the wall time of assembly and
+ * factorisation. */
 qax_status qax_assemble_self(qax_problem* p, double* t_setup_s);
+
+/* Precision of the factorisation made by qax_assemble_self: QAX_FP64 (the
+ * default: FP64 inverse, FP32 roundings of B and B^-1 for QAX_MIXED solves)
+ * or QAX_MIXED (B rounded to FP32 and inverted in FP32 on the FP32 matrix
+ * cores; the mixed solver then limits each refinement cycle to the FP32
+ * inverse's accuracy, about 1e-5, and evaluates later cycles with the FP32
+ * copy of B).  Changing it on an assembled handle drops the handle back to
+ * the built state (qax_assemble_self is needed again).  Errors: QAX_ERR_ARG. */
+qax_status qax_set_factorization(qax_problem* p, qax_prec prec);
 
 /* Copy the self block of body `body` (n_b x n_b complex128, row-major: row =
  * target node, column = source node) into d_out.  inverse != 0 copies the

@@ -507,13 +507,27 @@ extern "C" qax_status qax_assemble_self(qax_problem* p, double* t_setup_s) {
   }
   QCHECK(launch_assemble_self(p), "assemble_self");
   QBUF(work, double, "gj_work", invert_blocks_work_bytes(p));
-  QCHECK(launch_invert_blocks(p, work), "invert_blocks");
+  if (p->factor_prec == QAX_FP64) {
+    QCHECK(launch_factor_blocks64(p, work), "invert_blocks (FP64)");
+  } else {
+    QCHECK(launch_invert_blocks(p, work), "invert_blocks");
+  }
   qax_status st = sync(p, "qax_assemble_self");
   if (st != QAX_OK) return st;
+  p->inv64_ready = p->factor_prec == QAX_FP64;
   auto t1 = std::chrono::steady_clock::now();
   if (t_setup_s) *t_setup_s = std::chrono::duration<double>(t1 - t0).count();
   p->state = 2;
   ++p->generation;
+  return QAX_OK;
+}
+
+extern "C" qax_status qax_set_factorization(qax_problem* p, qax_prec prec) {
+  if (!p) return QAX_ERR_ARG;
+  if (prec != QAX_FP64 && prec != QAX_MIXED)
+    return fail(p, QAX_ERR_ARG, "qax_set_factorization: precision must be QAX_FP64 or QAX_MIXED");
+  if (p->factor_prec != prec && p->state >= 2) p->state = 1;   // blocks must be factored again
+  p->factor_prec = prec;
   return QAX_OK;
 }
 
@@ -1004,7 +1018,11 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
       const double need = bnorm[s] > 0 && rn[s] > 0 ? 0.5 * tol * bnorm[s] / rn[s] : 1.0;
       if (!frozen) min_need = std::min(min_need, need);
       par[s] = rn[s];
-      par[nseg + s] = prec == QAX_MIXED ? std::max(need, 2e-5) : need;
+      // mixed: with the FP32-computed inverse (accurate to ~1e-5) a cycle
+      // cannot gain much more than 1e-5; the rounded FP64 inverse and the
+      // compensated FP32 pair sum leave an operator error near 1e-7
+      const double floor32 = p->factor_prec == QAX_FP64 ? 2e-7 : 2e-5;
+      par[nseg + s] = prec == QAX_MIXED ? std::max(need, floor32) : need;
       fz[s] = frozen ? 1 : 0;
       fz[nseg + s] = frozen ? 0 : 1;
       g0[(size_t)s * (m + 1)] = rn[s];
@@ -1015,9 +1033,10 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
     QCHECK(hipMemcpyAsync(G.g, g0.data(), g0.size() * 16, hipMemcpyHostToDevice, p->stream), "copy");
     QCHECK(hipMemcpyAsync(G.scl, scl.data(), nseg * 16, hipMemcpyHostToDevice, p->stream), "copy");
     K.scale(r, (const double*)G.scl, V);
-    // the first cycle aims at the FP32 floor anyway; later ones that must
-    // gain more than 1e3 use the exact operator form
-    exact_op = prec == QAX_MIXED && outer > 0 && min_need < 1e-3;
+    // with the FP32-computed inverse the first cycle aims at the FP32 floor
+    // anyway; later ones that must gain more than 1e3 use the exact operator
+    // form (the rounded FP64 inverse needs no such form)
+    exact_op = prec == QAX_MIXED && p->factor_prec != QAX_FP64 && outer > 0 && min_need < 1e-3;
     int j = 0;
     for (; j < m && total_its < maxit; ++j) {
       if ((st = run_step(j)) != QAX_OK) return st;
@@ -1211,7 +1230,13 @@ extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char*
     };
     double best = 1e300;
     int btpb = t.pair_tpb[pi], bmult = t.pair_mult[pi];
-    if (nrhs_max == 1) {
+    // one right-hand side with the reciprocal kernel serving every such pair
+    // sum: the per-target kernel's choices are never used, nothing to time
+    const bool recip_only = nrhs_max == 1 && p->sym.ok && p->form() != 2;
+    if (recip_only) {
+      btpb = defaults.pair_tpb[pi];
+      bmult = defaults.pair_mult[pi];
+    } else if (nrhs_max == 1) {
       // workgroup size and source-chunk schedule for one right-hand side
       for (int tpb : {128, 256, 512}) {
         for (int mult : {4, 8, 16}) {
@@ -1267,7 +1292,14 @@ extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char*
     for (int c = 0; c < 4; ++c)
       p->tune.pair_nrc[pi][c] = t.pair_nrc[pi][c] = clamp_nrc(prec, btpb, t.pair_nrc[pi][c]);
     // single-right-hand-side times of the choice and of the default (report)
-    {
+    if (recip_only) {
+      p->tune.pair_tpb[pi] = btpb;
+      p->tune.pair_mult[pi] = bmult;
+      QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
+      p->sym.enabled = true;
+      t.pair_ms[pi] = t.default_pair_ms[pi] = time_best(p, 2, [&] { return run(1); }, &err);
+      QCHECK(err, "autotune pair sum");
+    } else {
       p->tune.pair_tpb[pi] = defaults.pair_tpb[pi];
       p->tune.pair_mult[pi] = defaults.pair_mult[pi];
       QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");

@@ -1308,6 +1308,29 @@ hipError_t launch_invert_blocks(qax_problem* p, double* work) {
   return e;
 }
 
+// B and its FP64 inverse rounded to FP32 (the mixed path's operator blocks
+// and preconditioner); two values per thread.
+__global__ void round_blocks_kernel(const double2* __restrict__ b, const double2* __restrict__ binv,
+                                    float2* __restrict__ b32, float2* __restrict__ binv32,
+                                    int64_t pairs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= pairs) return;
+  const double2 u = b[e], v = binv[e];
+  b32[e] = make_float2((float)u.x, (float)u.y);
+  binv32[e] = make_float2((float)v.x, (float)v.y);
+}
+
+// Factorisation in FP64 for both paths: the FP64 inverse (below), then B and
+// B^-1 rounded to FP32 for the mixed path.
+hipError_t launch_factor_blocks64(qax_problem* p, double* work) {
+  hipError_t e = launch_invert_blocks64(p, work);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(round_blocks_kernel, dim3((unsigned)((p->block_elems + 255) / 256)), dim3(256), 0,
+                     p->stream, (const double2*)p->d_B, (const double2*)p->d_Binv, (float2*)p->d_B32,
+                     (float2*)p->d_Binv32, p->block_elems);
+  return hipGetLastError();
+}
+
 // FP64 inverse: copy B into Binv and invert in place in FP64.
 hipError_t launch_invert_blocks64(qax_problem* p, double* work) {
   MatDesc* d_md;

@@ -142,6 +142,10 @@ struct qax_problem {
   double* d_B = nullptr;
   double* d_Binv = nullptr;
   bool inv64_ready = false;     // d_Binv holds the inverse of the current blocks
+  // precision of the factorisation made by qax_assemble_self: QAX_FP64 (the
+  // FP64 inverse, rounded to FP32 for the mixed path) or QAX_MIXED (B rounded
+  // to FP32 and inverted in FP32; the FP64 inverse made on first use)
+  int factor_prec = QAX_FP64;
   float* d_Binv32 = nullptr;
   float* d_B32 = nullptr;       // B rounded to FP32 (the mixed path's operator blocks)
 
@@ -274,6 +278,7 @@ hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const doubl
                               int nrhs, bool accumulate);
 hipError_t launch_invert_blocks(qax_problem* p, double* work);     // FP32 inverse (mixed path)
 hipError_t launch_invert_blocks64(qax_problem* p, double* work);   // FP64 inverse
+hipError_t launch_factor_blocks64(qax_problem* p, double* work);   // FP64 inverse + FP32 roundings
 hipError_t launch_convert_f32(hipStream_t s, const double* src, float* dst, int64_t count);
 hipError_t launch_dense_offdiag(qax_problem* p, double* A);
 

@@ -52,7 +52,8 @@ EXPORTS = ["qax_create", "qax_destroy", "qax_last_error", "qax_build", "qax_size
            "qax_assemble_self", "qax_self_block", "qax_pair_sum", "qax_block_apply", "qax_apply",
            "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes",
            "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning", "qax_set_graphs",
-           "qax_solve_rhs", "qax_nearfield", "qax_set_formulation", "qax_lattice", "qax_invert"]
+           "qax_solve_rhs", "qax_nearfield", "qax_set_formulation", "qax_lattice", "qax_invert",
+           "qax_set_factorization"]
 (QAX_K_PAIRSUM_FP64, QAX_K_PAIRSUM_FP32, QAX_K_BLOCK_APPLY, QAX_K_SELF_ASSEMBLY, QAX_K_INVERT,
  QAX_K_INVERT_UPDATE, QAX_K_BLOCK_APPLY_F32, QAX_K_LATTICE_F64, QAX_K_LATTICE_F32) = range(9)
 KERNEL_NAMES = ["pair_sum_fp64", "pair_sum_fp32", "block_apply", "self_assembly", "invert",
@@ -95,6 +96,7 @@ def lib():
         "qax_set_timing": (C.c_int, [vp, i32]),
         "qax_set_graphs": (C.c_int, [vp, i32]),
         "qax_set_formulation": (C.c_int, [vp, i32, C.c_double]),
+        "qax_set_factorization": (C.c_int, [vp, C.c_int]),
         "qax_lattice": (C.c_int, [vp, i32, C.POINTER(i32)]),
         "qax_timing": (C.c_int, [vp, i32, C.POINTER(i64), pd]),
         "qax_autotune": (C.c_int, [vp, i32, C.c_char_p]),
@@ -263,6 +265,12 @@ def qax_set_formulation(h, formulation, eta=0.0):
     """QAX_DOUBLE_LAYER, QAX_COMBINED_FIELD (eta > 0 fixed coupling, else k)
     or QAX_SINGLE_LAYER."""
     _check(h, lib().qax_set_formulation(h, int(formulation), float(eta)))
+
+
+def qax_set_factorization(h, prec):
+    """QAX_FP64 (default): FP64 inverse, rounded to FP32 for the mixed path;
+    QAX_MIXED: inverse computed in FP32."""
+    _check(h, lib().qax_set_factorization(h, int(prec)))
 
 
 def qax_set_timing(h, enable=True):
