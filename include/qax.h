@@ -317,7 +317,16 @@ qax_status qax_timing(const qax_problem* p, int32_t kernel, int64_t* launches, d
  *    several right-hand sides, right-hand sides per pass (2 ... 32), chosen
  *    together with the workgroup size for the largest class nrhs_max reaches;
  *  - block apply with one right-hand side, per storage precision: complex
- *    entries per lane and load (1, 2; 4 for the FP32 inverse).
+ *    entries per lane and load (1, 2; 4 for the FP32 inverse);
+ *  - the reciprocal pair sum (one right-hand side, k > 0, double layer or
+ *    combined field: each unordered pair of nodes evaluated once for both
+ *    directions), per precision: the number of 256-node block pairs per
+ *    side of the square of block pairs one workgroup evaluates (1, 2, 4, 8),
+ *    which sets the launch's workgroup count and the size of its partial
+ *    sums (about 2 N (N / 256) / s complex values, cut into launches of at
+ *    most 960 MB each).  With one right-hand side and the reciprocal kernel
+ *    serving every such pair sum, the per-target kernel's choices above are
+ *    not timed.
  * Every candidate is timed on this problem's own data (HIP events, the
  * fastest of a few launches after a warm-up) and the fastest is kept for the
  * handle until the next qax_autotune.  Results do not depend on the choices
@@ -339,6 +348,9 @@ typedef struct {
   int32_t gemv_vec[2];        /* block apply, 1 RHS: [0] FP64, [1] FP32 inverse*/
   double pair_ms[2];          /* chosen single-RHS pair sum, ms (timed runs)  */
   double default_pair_ms[2];  /* the built-in default choice, ms             */
+  int32_t pair_sym_s[2];      /* reciprocal one-RHS pair sum: block pairs per
+                                 super-task side (1, 2, 4, 8; 0 in
+                                 qax_set_tuning: the default for the problem) */
 } qax_tuning_info;
 
 /* Current launch choices (defaults before any qax_autotune). */
@@ -349,7 +361,7 @@ qax_status qax_tuning(const qax_problem* p, qax_tuning_info* out);
  * QAX_ERR_ARG if a choice is not one the kernels support (pair_tpb 128, 256
  * or 512; pair_slot_mult 1 ... 64; pair_nrc 1, 2, 4, 8 (FP64) or ... 32
  * (FP32) with the LDS of the workgroup within 64 KB; gemv_vec 1, 2 (FP64) or
- * 1, 2, 4 (FP32)). */
+ * 1, 2, 4 (FP32); pair_sym_s 0 ... 8). */
 qax_status qax_set_tuning(qax_problem* p, const qax_tuning_info* in);
 
 #ifdef __cplusplus

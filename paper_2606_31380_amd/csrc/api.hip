@@ -213,9 +213,15 @@ static void free_geometry(qax_problem* p) {
   p->d_ew = nullptr; p->d_ew32 = nullptr;
   dev_release(p, p->d_gemm_tasks);
   p->d_gemm_tasks = nullptr;
-  dev_release(p, p->sym.d_mem);
-  p->sym.d_mem = nullptr;
-  p->sym.tasks.clear();
+  dev_release(p, p->sym.d_bmem);
+  p->sym.d_bmem = nullptr;
+  for (auto& pl : p->sym.plan) {
+    dev_release(p, pl.d_mem);
+    pl.d_mem = nullptr;
+    pl.s = 0;
+    pl.supers.clear();
+  }
+  p->sym.blocks.clear();
   p->gemm_tasks.clear();
   lattice_free(p);
 }
@@ -1015,6 +1021,7 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
     double min_need = 1.0;
     for (int s = 0; s < nseg; ++s) {
       const bool frozen = !(rn[s] > 0) || (bnorm[s] > 0 && rn[s] <= tol * bnorm[s]);
+      // the inner cycle's reduction: half the way below the target
       const double need = bnorm[s] > 0 && rn[s] > 0 ? 0.5 * tol * bnorm[s] / rn[s] : 1.0;
       if (!frozen) min_need = std::min(min_need, need);
       par[s] = rn[s];
@@ -1104,7 +1111,7 @@ static std::string tune_key(qax_problem* p, int nrhs_max) {
   for (auto& b : p->hblocks) nmax = std::max(nmax, b.n);
   for (char& c : dev)
     if (c == ' ' || c == '|') c = '_';
-  return "qax-tune v1 dev=" + dev + " N=" + std::to_string(p->N) + " bodies=" +
+  return "qax-tune v2 dev=" + dev + " N=" + std::to_string(p->N) + " bodies=" +
          std::to_string(p->n_bodies) + " problems=" + std::to_string(p->n_problems) +
          " nmax=" + std::to_string(nmax) + " nrhs_max=" + std::to_string(nrhs_max) +
          " assembled=" + std::to_string(p->state >= 2 ? 1 : 0);
@@ -1114,11 +1121,12 @@ static std::string tune_value(const qax::Tune& t) {
   char buf[512];
   std::snprintf(buf, sizeof(buf),
                 "pair_tpb=%d,%d pair_mult=%d,%d pair_nrc=%d,%d,%d,%d;%d,%d,%d,%d gemv_vec=%d,%d "
-                "pair_ms=%.6g,%.6g default_ms=%.6g,%.6g",
+                "pair_ms=%.6g,%.6g default_ms=%.6g,%.6g sym_s=%d,%d",
                 t.pair_tpb[0], t.pair_tpb[1], t.pair_mult[0], t.pair_mult[1], t.pair_nrc[0][0],
                 t.pair_nrc[0][1], t.pair_nrc[0][2], t.pair_nrc[0][3], t.pair_nrc[1][0],
                 t.pair_nrc[1][1], t.pair_nrc[1][2], t.pair_nrc[1][3], t.gemv_vec[0], t.gemv_vec[1],
-                t.pair_ms[0], t.pair_ms[1], t.default_pair_ms[0], t.default_pair_ms[1]);
+                t.pair_ms[0], t.pair_ms[1], t.default_pair_ms[0], t.default_pair_ms[1], t.sym_s[0],
+                t.sym_s[1]);
   return buf;
 }
 
@@ -1131,14 +1139,16 @@ static bool parse_tune(const std::string& v, qax::Tune& t) {
   qax::Tune o;
   const int n = std::sscanf(v.c_str(),
                             "pair_tpb=%d,%d pair_mult=%d,%d pair_nrc=%d,%d,%d,%d;%d,%d,%d,%d "
-                            "gemv_vec=%d,%d pair_ms=%lf,%lf default_ms=%lf,%lf",
+                            "gemv_vec=%d,%d pair_ms=%lf,%lf default_ms=%lf,%lf sym_s=%d,%d",
                             &o.pair_tpb[0], &o.pair_tpb[1], &o.pair_mult[0], &o.pair_mult[1],
                             &o.pair_nrc[0][0], &o.pair_nrc[0][1], &o.pair_nrc[0][2],
                             &o.pair_nrc[0][3], &o.pair_nrc[1][0], &o.pair_nrc[1][1],
                             &o.pair_nrc[1][2], &o.pair_nrc[1][3], &o.gemv_vec[0], &o.gemv_vec[1],
                             &o.pair_ms[0], &o.pair_ms[1], &o.default_pair_ms[0],
-                            &o.default_pair_ms[1]);
-  if (n != 18) return false;
+                            &o.default_pair_ms[1], &o.sym_s[0], &o.sym_s[1]);
+  if (n != 20) return false;
+  for (int pi = 0; pi < 2; ++pi)
+    if (o.sym_s[pi] < 0 || o.sym_s[pi] > qax::SYM_SMAX) return false;
   for (int pi = 0; pi < 2; ++pi) {
     const int prec = pi == 0 ? QAX_FP64 : QAX_MIXED;
     if (!pair_config_ok(prec, o.pair_tpb[pi], 1) || o.pair_mult[pi] < 1 || o.pair_mult[pi] > 64)
@@ -1293,12 +1303,29 @@ extern "C" qax_status qax_autotune(qax_problem* p, int32_t nrhs_max, const char*
       p->tune.pair_nrc[pi][c] = t.pair_nrc[pi][c] = clamp_nrc(prec, btpb, t.pair_nrc[pi][c]);
     // single-right-hand-side times of the choice and of the default (report)
     if (recip_only) {
+      // the reciprocal kernel: block pairs per super-task side (1, 2, 4, 8;
+      // default chosen by the work per compute unit), timed on this problem
       p->tune.pair_tpb[pi] = btpb;
       p->tune.pair_mult[pi] = bmult;
-      QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
       p->sym.enabled = true;
-      t.pair_ms[pi] = t.default_pair_ms[pi] = time_best(p, 2, [&] { return run(1); }, &err);
-      QCHECK(err, "autotune pair sum");
+      const int s_def = sym_default_s(p, cus);
+      double best_s = 1e300;
+      int bs = s_def;
+      for (int sv : {s_def, 1, 2, 4, 8}) {
+        if (sv == s_def && best_s < 1e300) continue;
+        p->tune.sym_s[pi] = sv;
+        QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
+        const double ms = time_best(p, 2, [&] { return run(1); }, &err);
+        QCHECK(err, "autotune pair sum (reciprocal)");
+        if (sv == s_def) t.default_pair_ms[pi] = ms;
+        if (ms < best_s) {
+          best_s = ms;
+          bs = sv;
+        }
+      }
+      p->tune.sym_s[pi] = t.sym_s[pi] = bs;
+      QCHECK(upload_pair_plan(p, prec, cus), "pair-sum plan");
+      t.pair_ms[pi] = best_s;
     } else {
       p->tune.pair_tpb[pi] = defaults.pair_tpb[pi];
       p->tune.pair_mult[pi] = defaults.pair_mult[pi];
@@ -1383,6 +1410,7 @@ extern "C" qax_status qax_tuning(const qax_problem* pc, qax_tuning_info* out) {
     out->gemv_vec[pi] = t.gemv_vec[pi];
     out->pair_ms[pi] = t.pair_ms[pi];
     out->default_pair_ms[pi] = t.default_pair_ms[pi];
+    out->pair_sym_s[pi] = pc->sym.plan[pi].s;
   }
   return QAX_OK;
 }
@@ -1408,6 +1436,11 @@ extern "C" qax_status qax_set_tuning(qax_problem* p, const qax_tuning_info* in) 
     return fail(p, QAX_ERR_ARG, "qax_set_tuning: unsupported block-apply choice");
   t.gemv_vec[0] = in->gemv_vec[0];
   t.gemv_vec[1] = in->gemv_vec[1];
+  for (int pi = 0; pi < 2; ++pi) {
+    if (in->pair_sym_s[pi] < 0 || in->pair_sym_s[pi] > qax::SYM_SMAX)
+      return fail(p, QAX_ERR_ARG, "qax_set_tuning: reciprocal super-task size out of [0, 8]");
+    t.sym_s[pi] = in->pair_sym_s[pi];
+  }
   QCHECK(hipSetDevice(p->device), "hipSetDevice");
   QCHECK(hipStreamSynchronize(p->stream), "sync");
   p->tune = t;

@@ -50,17 +50,29 @@ struct PairTask {
   double eta;                  // combined-field coupling of the problem (0: none)
 };
 
-// A chunk of the reciprocal FP32 pair sum: block [t0, t0 + nt) of body a
-// (targets held in registers) against block [s0, s0 + nb) of body b > a of
-// the same problem, both directions; blocks are SYM_T nodes from the start
-// of each body.  The task's target-side sums go to part[ioff + (i - t0)],
-// its source-side sums to part[joff + (j - s0)] (complex64).
+// Reciprocal pair sums (one right-hand side): each problem's node range is
+// cut into blocks of SYM_T consecutive nodes (a block may straddle bodies); a
+// super-task is a square of up to SYM_SMAX x SYM_SMAX block pairs (I, J),
+// I <= J, of one problem, evaluated by one workgroup.  Its target-side sums go
+// to ni slots from part[toff], its source-side sums to nj slots from
+// part[soff] (SYM_T complex128 values per slot).
 constexpr int SYM_T = 256;
-struct SymTask {
-  int64_t t0, s0;
-  int64_t ioff, joff;
-  int32_t nt, nb;
-  int32_t a, b;
+constexpr int SYM_SMAX = 8;
+// largest workspace of one launch of the reciprocal kernels, complex values
+// (960 MB); more super-tasks are split into several launches
+constexpr int64_t SYM_SLOT_CAP = 60000000;
+struct SymBlock {
+  int64_t n0;          // first node
+  int32_t n;           // nodes, 1 .. SYM_T
+  int32_t problem;
+};
+struct SymSuper {
+  int32_t i0, ni, j0, nj;  // block rows [i0, i0 + ni) x columns [j0, j0 + nj)
+  int32_t diag;            // rows == columns: block pairs with J >= I only
+  int32_t problem;
+  double k;
+  uint64_t skip;           // bit ii * SYM_SMAX + jj: both blocks inside one body
+  int64_t toff, soff;      // first target / source slot
 };
 
 // Row tile of the several-RHS block apply: 64 rows of one body from row0.
@@ -86,6 +98,7 @@ struct Tune {
   int pair_mult[2] = {8, 8};       // workgroups per CU aimed at by the source-chunk split
   int pair_nrc[2][4] = {{4, 8, 8, 8}, {4, 8, 16, 16}};  // RHS per pass, nrhs in 2-4, 5-8, 9-16, >16
   int gemv_vec[2] = {1, 1};        // complex elements per lane and load, one RHS
+  int sym_s[2] = {0, 0};           // reciprocal pair sum: block pairs per super-task side (0: default)
   bool tuned = false, from_cache = false;
   double pair_ms[2] = {0.0, 0.0}, default_pair_ms[2] = {0.0, 0.0};
 };
@@ -155,21 +168,30 @@ struct qax_problem {
   qax::PairTask* d_tasks32 = nullptr;
   int32_t slots64 = 1, slots32 = 1;
   int32_t plan_tpb[2] = {0, 0};       // workgroup size the task tables were planned for
-  // reciprocal FP32 pair sum (one right-hand side, k > 0 in every problem,
-  // double layer or combined field); the partial-sum lists of the final
-  // reduction are per target block (target side) and per body (source side)
+  // reciprocal pair sums (one right-hand side, k > 0 in every problem,
+  // double layer or combined field): node blocks, and per precision the
+  // super-tasks, their launches and the per-launch reduction lists
   struct Sym {
     bool ok = false;                  // every problem has k > 0
     bool enabled = true;              // off while the per-target kernel is tuned
-    std::vector<qax::SymTask> tasks;
-    void* d_mem = nullptr;            // one allocation for the arrays below
-    qax::SymTask* d_tasks = nullptr;
-    int32_t* d_blk_base = nullptr;    // first block of each body
-    int32_t* d_ptr = nullptr;         // per block: range in d_list
-    int64_t* d_list = nullptr;        // ioff - t0 / joff - s0 of the tasks touching the block
-    int64_t nparts = 0;               // complex64 partial sums
-    std::vector<int32_t> h_blk_base, h_ptr;
-    std::vector<int64_t> h_list;
+    std::vector<qax::SymBlock> blocks;
+    std::vector<int32_t> prob_blk0;   // first block of each problem (n_problems + 1)
+    std::vector<int32_t> blk_body_lo, blk_body_hi;
+    void* d_bmem = nullptr;           // blocks and the block of each node
+    qax::SymBlock* d_blocks = nullptr;
+    int32_t* d_node_block = nullptr;
+    struct Plan {
+      int s = 0;                      // super-task size (block pairs per side)
+      std::vector<qax::SymSuper> supers;
+      std::vector<int64_t> launch_super;   // super-task range of each launch
+      std::vector<int64_t> lptr;           // per launch: n_blocks + 1 list offsets
+      std::vector<int64_t> list;           // slot offsets
+      int64_t max_slots = 0;               // complex values of the largest launch
+      void* d_mem = nullptr;
+      qax::SymSuper* d_supers = nullptr;
+      int64_t* d_lptr = nullptr;
+      int64_t* d_list = nullptr;
+    } plan[2];                        // [0] FP64, [1] FP32
   } sym;
   qax::Tune tune;
 
@@ -266,6 +288,10 @@ hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* o
 void plan_pair_sum(qax_problem* p, int prec, int cu_count);
 // plan_pair_sum + device copy of the task table (synchronous).
 hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count);
+// reciprocal pair sums: plan for precision index pi (0 FP64, 1 FP32) with
+// super-tasks of s x s block pairs (s <= 0: the default for this problem)
+hipError_t plan_sym(qax_problem* p, int pi, int s, int cu_count);
+int sym_default_s(const qax_problem* p, int cu_count);
 // launch choices the kernels support (LDS within 64 KB)
 bool pair_config_ok(int prec, int tpb, int nrc);
 int nearfield_slots(int64_t M, int cu_count);

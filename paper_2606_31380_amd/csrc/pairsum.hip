@@ -391,231 +391,50 @@ __global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slo
 }
 
 // ---------------------------------------------------------------------------
-// Reciprocal FP32 pair sum (one right-hand side, double layer or combined
-// field, k > 0).  For x_i on body a and y_j on body b != a, the distance r,
-// the phase and e^{ikr} are the same for the pair (target i, source j) and
-// the pair (target j, source i); only the double-layer dot products and the
-// densities differ.  Each unordered pair of bodies a < b is visited once, as
-// tasks of a block of SYM_T nodes of a against a block of SYM_T nodes of b,
-// so the shared part of a pair is computed once for both directions.  The
-// blocks keep tasks small enough that the workgroups fill the chip evenly.
+// Reciprocal pair sums (one right-hand side, double layer or combined field,
+// k > 0).  For x_i on body a and y_j on body b != a, the distance r, the phase
+// and e^{ikr} are the same for the pair (target i, source j) and the pair
+// (target j, source i); only the double-layer dot products and the densities
+// differ, so each unordered pair of nodes is evaluated once for both
+// directions.
 //
-// Coordinates are local to each body: x_i = c_a + x', y_j = c_b + y',
-// C = c_b - c_a.  With P_j = 2 C.y' + |y'|^2 and Q_i = |x'|^2 - 2 C.x',
-//   num = r^2 - |C|^2 = P_j + Q_i - 2 x'.y'
-// (no cancellation against |C|^2), delta = r - |C| = num / (r + |C|), and the
-// phase is frac(k |C| / 2 pi) + k delta / 2 pi, in the kappa-scaled form of
-// the per-target kernel.  The dot products are
-//   aw_j . (y_j - x_i) = A_j - aw_j . x',  A_j = aw_j . (C + y'),
-//   aw_i . (x_i - y_j) = B_i - aw_i . y',  B_i = aw_i . (x' - C).
+// Work layout.  Each problem's node range is cut into blocks of SYM_T
+// consecutive nodes (a block may hold the end of one body and the start of
+// the next).  A task is a pair of blocks (I, J), I <= J, of one problem: for
+// I < J every pair (i in I, j in J) on different bodies is taken in both
+// directions; for I == J every ordered pair on different bodies is taken in
+// the target direction only.  Tasks are grouped into super-tasks of up to
+// S x S block pairs (block rows [i0, i0 + ni) x columns [j0, j0 + nj); on the
+// diagonal only J >= I), one workgroup each.  A super-task keeps the target
+// sums of its current row in registers across its columns and writes one
+// target slot per row; it accumulates the source sums of each column over
+// its rows in one source slot per column (read-modify-write by the thread
+// that owns the entry, in FP64).  Slots hold SYM_T complex128 values, so the
+// workspace is (ni + nj) SYM_T values per super-task, about 2 N nblk / S in
+// all; the super-tasks are split into launches whose slots fit a fixed cap,
+// each followed by a reduction that adds, per node, the slots of its block
+// in a fixed order (deterministic results).
 //
-// A workgroup is two wavefronts; lane l owns targets l and l + 64 of its
-// wavefront's 128.  Sources pass in chunks of 64; at step s lane l meets
-// source (l + s) mod 64 of the chunk, so the 64 lanes of a wavefront see 64
-// distinct sources at every step.  The chunk is staged twice over (indices
-// 0..127), which turns (l + s) mod 64 into l + s.  The target-side sums stay
-// in registers (FP32 per chunk, compensated across chunks).  The source-side
-// sums travel with their source: lane l holds the running sums of source
-// (l + s) mod 64 at step s, and the next step receives them from lane l + 1
-// (a wavefront rotation fused into the add), so after the chunk lane l holds
-// those of source (l + 63) mod 64.  The two wavefronts' sums of a source are
-// added through LDS (FP32 sums over the task's targets).  Both sides' task
-// sums are stored as complex64 and added in FP64 by the reduction.
+// Lanes.  A workgroup is two wavefronts; lane l of wavefront w owns targets
+// w 128 + l and w 128 + 64 + l of block I.  The sources of block J pass in
+// chunks of at most 64 nodes of one body (a chunk ends at a body's last
+// node), staged twice over in LDS; at step s lane l meets source
+// (l + s) mod 64 (index l + s), so the 64 lanes of a wavefront see 64
+// distinct sources at every step.  The target-side sums stay in registers.
+// The source-side sums travel with their source: each step adds lane l + 1's
+// running sums to lane l's contribution with a DPP wavefront rotation fused
+// into the add, so after the chunk lane l holds those of source
+// (l + 63) mod 64 (no LDS read-modify-write per step).  Since a chunk lies in
+// one body b, the exclusion of pairs on the same body is a per-lane choice
+// for the whole chunk: a lane whose target is on b (or past the end of the
+// block) gets a far-away stand-in target and a zero density, so its pairs are
+// finite and add nothing to the source sums, and its target sum of the chunk
+// is dropped.
 __device__ __forceinline__ float from_next_lane(float x) {
   // DPP wavefront rotation: lane l reads lane (l + 1) mod 64
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x134, 0xf, 0xf, false));
 }
 
-template <int FORM>
-__global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
-    const SymTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
-    const float4* __restrict__ loc32, const float4* __restrict__ aw32,
-    const float* __restrict__ ew32, const double2* __restrict__ mu,
-    const int32_t* __restrict__ seg_active, float2* __restrict__ part) {
-  constexpr int NA = FORM ? 6 : 4;   // source-side sums: S1, S2 (, S3), re/im
-  const SymTask T = tasks[blockIdx.x];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const BodyDev& BA = bodies[T.a];
-  const BodyDev& BB = bodies[T.b];
-  if (seg_active && seg_active[BA.problem] == 0) {
-    for (int t = tid; t < T.nt; t += 128) part[T.ioff + t] = make_float2(0.0f, 0.0f);
-    for (int j = tid; j < T.nb; j += 128) part[T.joff + j] = make_float2(0.0f, 0.0f);
-    return;
-  }
-  const double k = BA.k;
-  const double Cx = BB.cen[0] - BA.cen[0], Cy = BB.cen[1] - BA.cen[1], Cz = BB.cen[2] - BA.cen[2];
-  const double C2 = Cx * Cx + Cy * Cy + Cz * Cz;
-  const double Cn = sqrt(C2);
-  double ph0d = k * Cn / TWO_PI;
-  ph0d -= floor(ph0d);
-  const double kap = TWO_PI / k;
-  const float kap2 = (float)(kap * kap), d2s = (float)(kap * kap * C2), dns = (float)(kap * Cn);
-  const float ck1 = (float)kap, ck2 = (float)(k * kap * kap), ck3 = (float)(kap * kap * kap);
-  const float ph0 = (float)ph0d;
-  const float cx = (float)Cx, cy = (float)Cy, cz = (float)Cz;
-
-  // the lane's two targets: -x', Q_i, -aw_i / 2, B_i, mu_i (0 past the block)
-  float mx[2], my[2], mz[2], q[2], hx[2], hy[2], hz[2], bv[2], mr[2], mi[2], ew[2];
-  float sr[2], si[2], cr[2], ci[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int loc = wv * 128 + t * 64 + lane;
-    const bool act = loc < T.nt;
-    const int64_t i = T.t0 + (act ? loc : 0);
-    const float4 x4 = loc32[i];
-    const float4 a4 = aw32[i];
-    mx[t] = -x4.x;
-    my[t] = -x4.y;
-    mz[t] = -x4.z;
-    q[t] = fmaf(-2.0f * cx, x4.x, fmaf(-2.0f * cy, x4.y, fmaf(-2.0f * cz, x4.z, x4.w)));
-    hx[t] = -0.5f * a4.x;
-    hy[t] = -0.5f * a4.y;
-    hz[t] = -0.5f * a4.z;
-    bv[t] = a4.w - fmaf(a4.x, cx, fmaf(a4.y, cy, a4.z * cz));
-    const double2 m = act ? mu[i] : make_double2(0.0, 0.0);
-    mr[t] = (float)m.x;
-    mi[t] = (float)m.y;
-    ew[t] = FORM ? ew32[i] : 0.0f;
-    sr[t] = si[t] = cr[t] = ci[t] = 0.0f;
-  }
-
-  __shared__ float4 sY[128];           // 2 y', P_j
-  __shared__ float4 sW[128];           // aw_j, A_j
-  __shared__ float4 sM[128];           // mu_j, eta |aw_j|
-  __shared__ float sX[NA][64];         // second wavefront's source-side sums
-
-  const int src = (lane + 63) & 63;    // source of the lane's sums after a chunk
-  const int nch = (T.nb + 63) / 64;
-  for (int c = 0; c < nch; ++c) {
-    if (tid < 64) {
-      const int jl = c * 64 + tid;
-      const bool act = jl < T.nb;
-      const int64_t j = T.s0 + (act ? jl : 0);
-      const float4 y4 = loc32[j];
-      const float4 b4 = aw32[j];
-      const double2 m = act ? mu[j] : make_double2(0.0, 0.0);
-      const float4 Y = make_float4(2.0f * y4.x, 2.0f * y4.y, 2.0f * y4.z,
-                                   fmaf(2.0f * cx, y4.x, fmaf(2.0f * cy, y4.y, fmaf(2.0f * cz, y4.z, y4.w))));
-      const float4 W = make_float4(b4.x, b4.y, b4.z, b4.w + fmaf(b4.x, cx, fmaf(b4.y, cy, b4.z * cz)));
-      const float4 M = make_float4((float)m.x, (float)m.y, FORM ? ew32[j] : 0.0f, 0.0f);
-      sY[tid] = Y;
-      sY[tid + 64] = Y;
-      sW[tid] = W;
-      sW[tid + 64] = W;
-      sM[tid] = M;
-      sM[tid + 64] = M;
-    }
-    __syncthreads();
-    float ar[2], ai[2], br[2], bi[2], er[2], ei[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) ar[t] = ai[t] = br[t] = bi[t] = er[t] = ei[t] = 0.0f;
-    float acc[NA];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) acc[a] = 0.0f;
-    const float4* pY = &sY[lane];
-    const float4* pW = &sW[lane];
-    const float4* pM = &sM[lane];
-#pragma unroll 4
-    for (int st = 0; st < 64; ++st) {
-      const float4 Y = pY[st];
-      const float4 W = pW[st];
-      const float4 M = pM[st];
-      float cn[NA];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        // shared: r, e^{ikr} (scaled as in the per-target kernel)
-        const float num = fmaf(mx[t], Y.x, fmaf(my[t], Y.y, fmaf(mz[t], Y.z, Y.w + q[t])));
-        const float r2s = fmaf(kap2, num, d2s);
-        const float irs = __builtin_amdgcn_rsqf(r2s);
-        const float ph = fmaf(num, __builtin_amdgcn_rcpf(fmaf(r2s, irs, dns)), ph0);
-        const float sn = __builtin_amdgcn_sinf(ph);
-        const float cs = __builtin_amdgcn_cosf(ph);
-        const float ir2 = irs * irs;
-        // target i, source j
-        {
-          const float zr = fmaf(cs, M.x, -sn * M.y);
-          const float zi = fmaf(cs, M.y, sn * M.x);
-          const float dot = fmaf(W.x, mx[t], fmaf(W.y, my[t], fmaf(W.z, mz[t], W.w)));
-          const float u = dot * ir2;
-          const float sc = u * irs;
-          ar[t] = fmaf(sc, zr, ar[t]);
-          ai[t] = fmaf(sc, zi, ai[t]);
-          br[t] = fmaf(u, zr, br[t]);
-          bi[t] = fmaf(u, zi, bi[t]);
-          if constexpr (FORM == 1) {
-            const float tt = M.z * irs;
-            er[t] = fmaf(tt, zr, er[t]);
-            ei[t] = fmaf(tt, zi, ei[t]);
-          }
-        }
-        // target j, source i
-        {
-          const float zr = fmaf(cs, mr[t], -sn * mi[t]);
-          const float zi = fmaf(cs, mi[t], sn * mr[t]);
-          const float dot = fmaf(hx[t], Y.x, fmaf(hy[t], Y.y, fmaf(hz[t], Y.z, bv[t])));
-          const float u = dot * ir2;
-          const float sc = u * irs;
-          const float tt = FORM ? ew[t] * irs : 0.0f;
-          if (t == 0) {
-            cn[0] = sc * zr;
-            cn[1] = sc * zi;
-            cn[2] = u * zr;
-            cn[3] = u * zi;
-            if constexpr (FORM == 1) {
-              cn[4] = tt * zr;
-              cn[5] = tt * zi;
-            }
-          } else {
-            cn[0] = fmaf(sc, zr, cn[0]);
-            cn[1] = fmaf(sc, zi, cn[1]);
-            cn[2] = fmaf(u, zr, cn[2]);
-            cn[3] = fmaf(u, zi, cn[3]);
-            if constexpr (FORM == 1) {
-              cn[4] = fmaf(tt, zr, cn[4]);
-              cn[5] = fmaf(tt, zi, cn[5]);
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < NA; ++a) acc[a] = from_next_lane(acc[a]) + cn[a];
-    }
-    // -S1 + i k S2 (- i S3), undoing the kappa scaling
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      two_sum(sr[t], cr[t], fmaf(-ck2, bi[t], fmaf(ck1, ei[t], -ck3 * ar[t])));
-      two_sum(si[t], ci[t], fmaf(ck2, br[t], fmaf(-ck1, er[t], -ck3 * ai[t])));
-    }
-    if (wv == 1) {
-#pragma unroll
-      for (int a = 0; a < NA; ++a) sX[a][lane] = acc[a];
-    }
-    __syncthreads();
-    if (wv == 0 && c * 64 + src < T.nb) {
-      float v[NA];
-#pragma unroll
-      for (int a = 0; a < NA; ++a) v[a] = acc[a] + sX[a][lane];
-      const float e3r = FORM ? v[4] : 0.0f, e3i = FORM ? v[5] : 0.0f;
-      const float vr = fmaf(-ck2, v[3], fmaf(ck1, e3i, -ck3 * v[0]));
-      const float vi = fmaf(ck2, v[2], fmaf(-ck1, e3r, -ck3 * v[1]));
-      part[T.joff + c * 64 + src] =
-          make_float2(vr * (float)INV_FOUR_PI, vi * (float)INV_FOUR_PI);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int loc = wv * 128 + t * 64 + lane;
-    if (loc < T.nt)
-      part[T.ioff + loc] = make_float2((float)(((double)sr[t] + (double)cr[t]) * INV_FOUR_PI),
-                                       (float)(((double)si[t] + (double)ci[t]) * INV_FOUR_PI));
-  }
-}
-
-// FP64 reciprocal pair sum: the same tasks, lane mapping and rotation of the
-// source-side sums as the FP32 kernel, in plain FP64 on absolute positions
-// (d = y_j - x_i, r^2 = |d|^2, phase r k / 2 pi in revolutions for
-// sincos_2pi); aw_j . (y_j - x_i) = aw_j . d and aw_i . (x_i - y_j) =
-// -aw_i . d.  Task sums are stored as complex128.
 __device__ __forceinline__ double from_next_lane(double x) {
   const long long v = __double_as_longlong(x);
   const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffLL), 0x134, 0xf, 0xf, false);
@@ -623,198 +442,473 @@ __device__ __forceinline__ double from_next_lane(double x) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Rows of super-task T whose block pair (row ii, column jj) is evaluated.
+__device__ __forceinline__ uint32_t sym_row_mask(const SymSuper& T, int ii) {
+  uint32_t m = 0;
+  for (int jj = T.diag ? ii : 0; jj < T.nj; ++jj)
+    if (!((T.skip >> (ii * SYM_SMAX + jj)) & 1ull)) m |= 1u << jj;
+  return m;
+}
+
+// Inactive problem of a lockstep solve: the super-task's slots hold zeros.
+__device__ __forceinline__ bool sym_inactive(const SymSuper& T, const int32_t* __restrict__ seg_active,
+                                             double2* __restrict__ part) {
+  if (!seg_active || seg_active[T.problem] != 0) return false;
+  for (int e = threadIdx.x; e < (T.ni + T.nj) * SYM_T; e += blockDim.x)
+    part[T.toff + e] = make_double2(0.0, 0.0);
+  return true;
+}
+
+// FP32 reciprocal pair sum.  Coordinates are local to each body: x_i = c_a +
+// x', y_j = c_b + y', C = c_b - c_a.  With m = 2 (C - x') and
+// Q_i = |x'|^2 - 2 C.x' per target and chunk,
+//   num = r^2 - |C|^2 = m.y' + |y'|^2 + Q_i
+// carries no cancellation against |C|^2, delta = r - |C| = num / (r + |C|),
+// and the phase in revolutions is frac(k |C| / 2 pi) (from FP64, per target
+// and chunk) + k delta / 2 pi, so FP32 rounding enters relative to delta, not
+// to r.  Distances are scaled by kappa = 2 pi / k: r_s^2 = kappa^2 (|C|^2 +
+// num), irs = 1 / r_s and rcp(r_s^2 irs + kappa |C|) = (k / 2 pi) / (r + |C|).
+// The double-layer factor of a pair, (ik/r - 1/r^2) e^{ikr} / (4 pi r), is
+// kappa^3 / (4 pi) w with w = e^{ikr} irs^2 (i k / kappa - irs), shared by
+// both directions; the direction (i <- j) adds w aw_j.(y_j - x_i) mu_j and the
+// direction (j <- i) adds w aw_i.(x_i - y_j) mu_i, with
+//   aw_j.(y_j - x_i) = aw_j.y' + (aw_j / 2).m,
+//   aw_i.(x_i - y_j) = aw_i.(x' - C) - aw_i.y'.
+// The combined field adds - i eta e^{ikr} |aw| mu / (4 pi r) per direction,
+// i.e. - i (ew / kappa^2) irs e^{ikr} mu in the same scaling (ew = eta |aw|).
+// Real parts are accumulated negated (one sign flip per slot).  Target sums
+// are FP32 per chunk and compensated (TwoSum) across chunks and columns;
+// source sums are FP32 over the chunk's 128 targets of a wavefront, then FP64.
+template <int FORM>
+__global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
+    const SymSuper* __restrict__ supers, const SymBlock* __restrict__ blocks,
+    const BodyDev* __restrict__ bodies, const int32_t* __restrict__ node_body,
+    const float4* __restrict__ loc32, const float4* __restrict__ aw32,
+    const float* __restrict__ ew32, const double2* __restrict__ mu,
+    const int32_t* __restrict__ seg_active, double2* __restrict__ part) {
+  const SymSuper T = supers[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (sym_inactive(T, seg_active, part)) return;
+  const double k = T.k;
+  const double kap = TWO_PI / k;
+  const double sc3 = kap * kap * kap / FOUR_PI;
+  const float kap2 = (float)(kap * kap), ks = (float)(k / kap), ik2 = (float)(1.0 / (kap * kap));
+
+  __shared__ float4 sY[128];           // y', |y'|^2
+  __shared__ float4 sW[128];           // aw_j / 2, aw_j . y'
+  __shared__ float4 sM[128];           // mu_j, ew_j / kappa^2
+  __shared__ float sX[2][64];          // second wavefront's source-side sums
+  const int src = (lane + 63) & 63;    // source of the lane's sums after a chunk
+
+  uint32_t touched = 0;                // columns whose source slot holds a value
+  for (int ii = 0; ii < T.ni; ++ii) {
+    const uint32_t rowmask = sym_row_mask(T, ii);
+    if (!rowmask) continue;
+    const int I = T.i0 + ii;
+    const SymBlock BI = blocks[I];
+    // the lane's two targets
+    float xx[2], xy[2], xz[2], x2[2], nx[2], ny[2], nz[2], axd[2], mr[2], mi[2], ew[2];
+    int ab[2];
+    bool act[2];
+    float nsr[2], ncr[2], tsi[2], tci[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int loc = wv * 128 + t * 64 + lane;
+      act[t] = loc < BI.n;
+      const int64_t i = BI.n0 + (act[t] ? loc : 0);
+      const float4 x4 = loc32[i];
+      const float4 a4 = aw32[i];
+      xx[t] = x4.x; xy[t] = x4.y; xz[t] = x4.z; x2[t] = x4.w;
+      nx[t] = -a4.x; ny[t] = -a4.y; nz[t] = -a4.z; axd[t] = a4.w;
+      const double2 m = act[t] ? mu[i] : make_double2(0.0, 0.0);
+      mr[t] = (float)m.x;
+      mi[t] = (float)m.y;
+      ew[t] = FORM ? ew32[i] * ik2 : 0.0f;
+      ab[t] = node_body[i];
+      nsr[t] = ncr[t] = tsi[t] = tci[t] = 0.0f;
+    }
+    for (int jj = 0; jj < T.nj; ++jj) {
+      if (!((rowmask >> jj) & 1u)) continue;
+      const SymBlock BJ = blocks[T.j0 + jj];
+      const bool dtask = (T.j0 + jj) == I;    // diagonal block: target direction only
+      const bool first_src = !dtask && !((touched >> jj) & 1u);
+      if (!dtask) touched |= 1u << jj;
+      // per target and source body: m, Q, B, scaled |C|^2 and |C|, phase base
+      float mx[2], my[2], mz[2], q[2], bq[2], d2s[2], dns[2], ph0[2], mre[2], mie[2];
+      bool msk[2];
+      int cur_b = -1;
+      for (int cs = 0; cs < BJ.n;) {
+        const int64_t node = BJ.n0 + cs;
+        const int b = node_body[node];
+        const BodyDev& BB = bodies[b];
+        const int cl = (int)min((int64_t)min(64, BJ.n - cs), BB.off + BB.n - node);
+        if (b != cur_b) {
+          cur_b = b;
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            const BodyDev& BA = bodies[ab[t]];
+            const double Cx = BB.cen[0] - BA.cen[0], Cy = BB.cen[1] - BA.cen[1],
+                         Cz = BB.cen[2] - BA.cen[2];
+            const double C2 = fma(Cx, Cx, fma(Cy, Cy, Cz * Cz));
+            const double Cn = sqrt(C2);
+            double ph = k * Cn / TWO_PI;
+            ph -= floor(ph);
+            const float cx = (float)Cx, cy = (float)Cy, cz = (float)Cz;
+            msk[t] = !act[t] || ab[t] == b;
+            mx[t] = 2.0f * (cx - xx[t]);
+            my[t] = 2.0f * (cy - xy[t]);
+            mz[t] = 2.0f * (cz - xz[t]);
+            // a masked lane's stand-in target is far away: finite, negligible pairs
+            q[t] = msk[t] ? 1e12f
+                          : fmaf(-2.0f * cx, xx[t], fmaf(-2.0f * cy, xy[t], fmaf(-2.0f * cz, xz[t], x2[t])));
+            bq[t] = axd[t] + fmaf(nx[t], cx, fmaf(ny[t], cy, nz[t] * cz));
+            d2s[t] = (float)(kap * kap * C2);
+            dns[t] = (float)(kap * Cn);
+            ph0[t] = (float)ph;
+            mre[t] = msk[t] ? 0.0f : mr[t];
+            mie[t] = msk[t] ? 0.0f : mi[t];
+          }
+        }
+        __syncthreads();   // the previous chunk's LDS reads are done
+        if (tid < 64) {
+          const bool sact = tid < cl;
+          const int64_t j = node + (sact ? tid : 0);
+          const float4 y4 = loc32[j];
+          const float4 b4 = aw32[j];
+          const double2 m = sact ? mu[j] : make_double2(0.0, 0.0);
+          const float4 W = make_float4(0.5f * b4.x, 0.5f * b4.y, 0.5f * b4.z, b4.w);
+          const float4 M = make_float4((float)m.x, (float)m.y, FORM && sact ? ew32[j] * ik2 : 0.0f, 0.0f);
+          sY[tid] = y4;
+          sY[tid + 64] = y4;
+          sW[tid] = W;
+          sW[tid + 64] = W;
+          sM[tid] = M;
+          sM[tid + 64] = M;
+        }
+        __syncthreads();
+        float nar[2] = {0.0f, 0.0f}, tai[2] = {0.0f, 0.0f};
+        float acc0 = 0.0f, acc1 = 0.0f;
+        const float4* pY = &sY[lane];
+        const float4* pW = &sW[lane];
+        const float4* pM = &sM[lane];
+#pragma unroll 4
+        for (int st = 0; st < 64; ++st) {
+          const float4 Y = pY[st];
+          const float4 W = pW[st];
+          const float4 M = pM[st];
+          float cr = 0.0f, ci = 0.0f;
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            // shared by both directions: r, e^{ikr}, w
+            const float num = fmaf(mx[t], Y.x, fmaf(my[t], Y.y, fmaf(mz[t], Y.z, Y.w + q[t])));
+            const float r2s = fmaf(kap2, num, d2s[t]);
+            const float irs = __builtin_amdgcn_rsqf(r2s);
+            const float ph = fmaf(num, __builtin_amdgcn_rcpf(fmaf(r2s, irs, dns[t])), ph0[t]);
+            const float sn = __builtin_amdgcn_sinf(ph);
+            const float cs_ = __builtin_amdgcn_cosf(ph);
+            const float ir2 = irs * irs;
+            const float ir3 = ir2 * irs;
+            const float be = ks * ir2;
+            const float nwr = fmaf(sn, be, cs_ * ir3);   // -Re w
+            const float wi = fmaf(cs_, be, -(sn * ir3)); //  Im w
+            // target i, source j
+            {
+              const float d = fmaf(W.x, mx[t], fmaf(W.y, my[t], fmaf(W.z, mz[t], W.w)));
+              const float vr = d * M.x, vi = d * M.y;
+              nar[t] = fmaf(nwr, vr, fmaf(wi, vi, nar[t]));
+              tai[t] = fmaf(wi, vr, fmaf(-nwr, vi, tai[t]));
+              if constexpr (FORM == 1) {
+                const float g = M.z * irs;
+                const float p1 = fmaf(cs_, M.y, sn * M.x), p2 = fmaf(cs_, M.x, -(sn * M.y));
+                nar[t] = fmaf(-g, p1, nar[t]);
+                tai[t] = fmaf(-g, p2, tai[t]);
+              }
+            }
+            // target j, source i
+            {
+              const float d = fmaf(nx[t], Y.x, fmaf(ny[t], Y.y, fmaf(nz[t], Y.z, bq[t])));
+              const float ur = d * mre[t], ui = d * mie[t];
+              if (t == 0) {
+                cr = fmaf(nwr, ur, wi * ui);
+                ci = fmaf(wi, ur, -(nwr * ui));
+              } else {
+                cr = fmaf(nwr, ur, fmaf(wi, ui, cr));
+                ci = fmaf(wi, ur, fmaf(-nwr, ui, ci));
+              }
+              if constexpr (FORM == 1) {
+                const float g = ew[t] * irs;
+                const float p1 = fmaf(cs_, mie[t], sn * mre[t]), p2 = fmaf(cs_, mre[t], -(sn * mie[t]));
+                cr = fmaf(-g, p1, cr);
+                ci = fmaf(-g, p2, ci);
+              }
+            }
+          }
+          acc0 = from_next_lane(acc0) + cr;
+          acc1 = from_next_lane(acc1) + ci;
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          if (!msk[t]) {
+            two_sum(nsr[t], ncr[t], nar[t]);
+            two_sum(tsi[t], tci[t], tai[t]);
+          }
+        }
+        if (!dtask) {
+          if (wv == 1) {
+            sX[0][lane] = acc0;
+            sX[1][lane] = acc1;
+          }
+          __syncthreads();
+          if (wv == 0 && src < cl) {
+            const double vr = -((double)acc0 + (double)sX[0][lane]) * sc3;
+            const double vi = ((double)acc1 + (double)sX[1][lane]) * sc3;
+            double2* d = part + T.soff + (int64_t)jj * SYM_T + cs + src;
+            if (first_src) {
+              *d = make_double2(vr, vi);
+            } else {
+              const double2 o = *d;
+              *d = make_double2(o.x + vr, o.y + vi);
+            }
+          }
+        }
+        cs += cl;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int loc = wv * 128 + t * 64 + lane;
+      if (loc < BI.n)
+        part[T.toff + (int64_t)ii * SYM_T + loc] =
+            make_double2(-((double)nsr[t] + (double)ncr[t]) * sc3, ((double)tsi[t] + (double)tci[t]) * sc3);
+    }
+  }
+}
+
+// FP64 reciprocal pair sum: the same super-tasks, chunks, lane mapping and
+// rotation as the FP32 kernel, in plain FP64 on absolute positions
+// (d = y_j - x_i, r^2 = |d|^2, phase r k / 2 pi in revolutions for
+// sincos_2pi); w = e^{ikr} ir^2 (i k - ir) is shared by both directions,
+// aw_j.(y_j - x_i) = aw_j.d and aw_i.(x_i - y_j) = -aw_i.d.
 template <int FORM>
 __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
-    const SymTask* __restrict__ tasks, const BodyDev* __restrict__ bodies,
-    const double* __restrict__ pos, const double* __restrict__ aw,
-    const double* __restrict__ ew, int64_t N, const double2* __restrict__ mu,
-    const int32_t* __restrict__ seg_active, double2* __restrict__ part) {
-  constexpr int NA = FORM ? 6 : 4;   // source-side sums: S1, S2 (, S3), re/im
-  const SymTask T = tasks[blockIdx.x];
+    const SymSuper* __restrict__ supers, const SymBlock* __restrict__ blocks,
+    const BodyDev* __restrict__ bodies, const int32_t* __restrict__ node_body,
+    const double* __restrict__ pos, const double* __restrict__ aw, const double* __restrict__ ewp,
+    int64_t N, const double2* __restrict__ mu, const int32_t* __restrict__ seg_active,
+    double2* __restrict__ part) {
+  const SymSuper T = supers[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const BodyDev& BA = bodies[T.a];
-  if (seg_active && seg_active[BA.problem] == 0) {
-    for (int t = tid; t < T.nt; t += 128) part[T.ioff + t] = make_double2(0.0, 0.0);
-    for (int j = tid; j < T.nb; j += 128) part[T.joff + j] = make_double2(0.0, 0.0);
-    return;
-  }
-  const double k = BA.k;
+  if (sym_inactive(T, seg_active, part)) return;
+  const double k = T.k;
   const double k2pi = k / TWO_PI;
-
-  // the lane's two targets: x_i, -aw_i, mu_i (0 past the block)
-  double xx[2], xy[2], xz[2], nx[2], ny[2], nz[2], mr[2], mi[2], ewi[2];
-  double ar[2], ai[2], br[2], bi[2], er[2], ei[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int loc = wv * 128 + t * 64 + lane;
-    const bool act = loc < T.nt;
-    const int64_t i = T.t0 + (act ? loc : 0);
-    xx[t] = pos[i];
-    xy[t] = pos[N + i];
-    xz[t] = pos[2 * N + i];
-    nx[t] = -aw[i];
-    ny[t] = -aw[N + i];
-    nz[t] = -aw[2 * N + i];
-    const double2 m = act ? mu[i] : make_double2(0.0, 0.0);
-    mr[t] = m.x;
-    mi[t] = m.y;
-    ewi[t] = FORM ? ew[i] : 0.0;
-    ar[t] = ai[t] = br[t] = bi[t] = er[t] = ei[t] = 0.0;
-  }
 
   __shared__ double2 sQ0[128];         // y.x, y.y
   __shared__ double2 sQ1[128];         // y.z, aw.z
   __shared__ double2 sQ2[128];         // aw.x, aw.y
   __shared__ double2 sM[128];          // mu_j
   __shared__ double sE[FORM ? 128 : 1];
-  __shared__ double sX[NA][64];        // second wavefront's source-side sums
+  __shared__ double sX[2][64];         // second wavefront's source-side sums
+  const int src = (lane + 63) & 63;
 
-  const int src = (lane + 63) & 63;    // source of the lane's sums after a chunk
-  const int nch = (T.nb + 63) / 64;
-  for (int c = 0; c < nch; ++c) {
-    if (tid < 64) {
-      const int jl = c * 64 + tid;
-      const bool act = jl < T.nb;
-      const int64_t j = T.s0 + (act ? jl : 0);
-      const double2 q0 = make_double2(pos[j], pos[N + j]);
-      const double2 q1 = make_double2(pos[2 * N + j], aw[2 * N + j]);
-      const double2 q2 = make_double2(aw[j], aw[N + j]);
-      const double2 m = act ? mu[j] : make_double2(0.0, 0.0);
-      sQ0[tid] = q0;
-      sQ0[tid + 64] = q0;
-      sQ1[tid] = q1;
-      sQ1[tid + 64] = q1;
-      sQ2[tid] = q2;
-      sQ2[tid + 64] = q2;
-      sM[tid] = m;
-      sM[tid + 64] = m;
-      if (FORM) {
-        sE[tid] = ew[j];
-        sE[tid + 64] = ew[j];
-      }
-    }
-    __syncthreads();
-    double acc[NA];
+  uint32_t touched = 0;
+  for (int ii = 0; ii < T.ni; ++ii) {
+    const uint32_t rowmask = sym_row_mask(T, ii);
+    if (!rowmask) continue;
+    const int I = T.i0 + ii;
+    const SymBlock BI = blocks[I];
+    double xx[2], xy[2], xz[2], nx[2], ny[2], nz[2], mr[2], mi[2], ewi[2];
+    double sr[2], si[2];
+    int ab[2];
+    bool act[2];
 #pragma unroll
-    for (int a = 0; a < NA; ++a) acc[a] = 0.0;
+    for (int t = 0; t < 2; ++t) {
+      const int loc = wv * 128 + t * 64 + lane;
+      act[t] = loc < BI.n;
+      const int64_t i = BI.n0 + (act[t] ? loc : 0);
+      xx[t] = pos[i];
+      xy[t] = pos[N + i];
+      xz[t] = pos[2 * N + i];
+      nx[t] = -aw[i];
+      ny[t] = -aw[N + i];
+      nz[t] = -aw[2 * N + i];
+      const double2 m = act[t] ? mu[i] : make_double2(0.0, 0.0);
+      mr[t] = m.x;
+      mi[t] = m.y;
+      ewi[t] = FORM ? ewp[i] : 0.0;
+      ab[t] = node_body[i];
+      sr[t] = si[t] = 0.0;
+    }
+    for (int jj = 0; jj < T.nj; ++jj) {
+      if (!((rowmask >> jj) & 1u)) continue;
+      const SymBlock BJ = blocks[T.j0 + jj];
+      const bool dtask = (T.j0 + jj) == I;
+      const bool first_src = !dtask && !((touched >> jj) & 1u);
+      if (!dtask) touched |= 1u << jj;
+      double ex[2], ey[2], ez[2], mre[2], mie[2];
+      bool msk[2];
+      int cur_b = -1;
+      for (int cs = 0; cs < BJ.n;) {
+        const int64_t node = BJ.n0 + cs;
+        const int b = node_body[node];
+        const BodyDev& BB = bodies[b];
+        const int cl = (int)min((int64_t)min(64, BJ.n - cs), BB.off + BB.n - node);
+        if (b != cur_b) {
+          cur_b = b;
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            msk[t] = !act[t] || ab[t] == b;
+            // a masked lane's stand-in target is far away: finite, negligible pairs
+            ex[t] = msk[t] ? xx[t] + 1e10 : xx[t];
+            ey[t] = xy[t];
+            ez[t] = xz[t];
+            mre[t] = msk[t] ? 0.0 : mr[t];
+            mie[t] = msk[t] ? 0.0 : mi[t];
+          }
+        }
+        __syncthreads();
+        if (tid < 64) {
+          const bool sact = tid < cl;
+          const int64_t j = node + (sact ? tid : 0);
+          const double2 q0 = make_double2(pos[j], pos[N + j]);
+          const double2 q1 = make_double2(pos[2 * N + j], aw[2 * N + j]);
+          const double2 q2 = make_double2(aw[j], aw[N + j]);
+          const double2 m = sact ? mu[j] : make_double2(0.0, 0.0);
+          sQ0[tid] = q0;
+          sQ0[tid + 64] = q0;
+          sQ1[tid] = q1;
+          sQ1[tid + 64] = q1;
+          sQ2[tid] = q2;
+          sQ2[tid + 64] = q2;
+          sM[tid] = m;
+          sM[tid + 64] = m;
+          if (FORM) {
+            const double e = sact ? ewp[j] : 0.0;
+            sE[tid] = e;
+            sE[tid + 64] = e;
+          }
+        }
+        __syncthreads();
+        double ar[2] = {0.0, 0.0}, ai[2] = {0.0, 0.0};
+        double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll 2
-    for (int st = 0; st < 64; ++st) {
-      const double2 q0 = sQ0[lane + st];
-      const double2 q1 = sQ1[lane + st];
-      const double2 q2 = sQ2[lane + st];
-      const double2 m = sM[lane + st];
-      const double e = FORM ? sE[lane + st] : 0.0;
-      double cn[NA];
+        for (int st = 0; st < 64; ++st) {
+          const double2 q0 = sQ0[lane + st];
+          const double2 q1 = sQ1[lane + st];
+          const double2 q2 = sQ2[lane + st];
+          const double2 m = sM[lane + st];
+          const double e = FORM ? sE[lane + st] : 0.0;
+          double cr = 0.0, ci = 0.0;
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const double dx = q0.x - xx[t], dy = q0.y - xy[t], dz = q1.x - xz[t];
-        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        const double ir = rsqrt_pos(r2);
-        double sn, cs;
-        sincos_2pi(r2 * ir * k2pi, &sn, &cs);
-        const double ir2 = ir * ir;
-        // target i, source j
-        {
-          const double zr = fma(cs, m.x, -sn * m.y);
-          const double zi = fma(cs, m.y, sn * m.x);
-          const double dot = fma(q2.x, dx, fma(q2.y, dy, q1.y * dz));
-          const double u = dot * ir2;
-          const double sc = u * ir;
-          ar[t] = fma(sc, zr, ar[t]);
-          ai[t] = fma(sc, zi, ai[t]);
-          br[t] = fma(u, zr, br[t]);
-          bi[t] = fma(u, zi, bi[t]);
-          if constexpr (FORM == 1) {
-            const double tt = e * ir;
-            er[t] = fma(tt, zr, er[t]);
-            ei[t] = fma(tt, zi, ei[t]);
-          }
-        }
-        // target j, source i
-        {
-          const double zr = fma(cs, mr[t], -sn * mi[t]);
-          const double zi = fma(cs, mi[t], sn * mr[t]);
-          const double dot = fma(nx[t], dx, fma(ny[t], dy, nz[t] * dz));
-          const double u = dot * ir2;
-          const double sc = u * ir;
-          const double tt = FORM ? ewi[t] * ir : 0.0;
-          if (t == 0) {
-            cn[0] = sc * zr;
-            cn[1] = sc * zi;
-            cn[2] = u * zr;
-            cn[3] = u * zi;
-            if constexpr (FORM == 1) {
-              cn[4] = tt * zr;
-              cn[5] = tt * zi;
+          for (int t = 0; t < 2; ++t) {
+            const double dx = q0.x - ex[t], dy = q0.y - ey[t], dz = q1.x - ez[t];
+            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            const double ir = rsqrt_pos(r2);
+            double sn, cs_;
+            sincos_2pi(r2 * ir * k2pi, &sn, &cs_);
+            const double ir2 = ir * ir;
+            const double ir3 = ir2 * ir;
+            const double be = k * ir2;
+            const double wr = -fma(sn, be, cs_ * ir3);
+            const double wi = fma(cs_, be, -(sn * ir3));
+            // target i, source j
+            {
+              const double d = fma(q2.x, dx, fma(q2.y, dy, q1.y * dz));
+              const double vr = d * m.x, vi = d * m.y;
+              ar[t] = fma(wr, vr, fma(-wi, vi, ar[t]));
+              ai[t] = fma(wi, vr, fma(wr, vi, ai[t]));
+              if constexpr (FORM == 1) {
+                const double g = e * ir;
+                ar[t] = fma(g, fma(cs_, m.y, sn * m.x), ar[t]);
+                ai[t] = fma(-g, fma(cs_, m.x, -(sn * m.y)), ai[t]);
+              }
             }
-          } else {
-            cn[0] = fma(sc, zr, cn[0]);
-            cn[1] = fma(sc, zi, cn[1]);
-            cn[2] = fma(u, zr, cn[2]);
-            cn[3] = fma(u, zi, cn[3]);
-            if constexpr (FORM == 1) {
-              cn[4] = fma(tt, zr, cn[4]);
-              cn[5] = fma(tt, zi, cn[5]);
+            // target j, source i
+            {
+              const double d = fma(nx[t], dx, fma(ny[t], dy, nz[t] * dz));
+              const double ur = d * mre[t], ui = d * mie[t];
+              if (t == 0) {
+                cr = fma(wr, ur, -(wi * ui));
+                ci = fma(wi, ur, wr * ui);
+              } else {
+                cr = fma(wr, ur, fma(-wi, ui, cr));
+                ci = fma(wi, ur, fma(wr, ui, ci));
+              }
+              if constexpr (FORM == 1) {
+                const double g = ewi[t] * ir;
+                cr = fma(g, fma(cs_, mie[t], sn * mre[t]), cr);
+                ci = fma(-g, fma(cs_, mre[t], -(sn * mie[t])), ci);
+              }
             }
           }
+          acc0 = from_next_lane(acc0) + cr;
+          acc1 = from_next_lane(acc1) + ci;
         }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          if (!msk[t]) {
+            sr[t] += ar[t];
+            si[t] += ai[t];
+          }
+        }
+        if (!dtask) {
+          if (wv == 1) {
+            sX[0][lane] = acc0;
+            sX[1][lane] = acc1;
+          }
+          __syncthreads();
+          if (wv == 0 && src < cl) {
+            const double vr = (acc0 + sX[0][lane]) * INV_FOUR_PI;
+            const double vi = (acc1 + sX[1][lane]) * INV_FOUR_PI;
+            double2* d = part + T.soff + (int64_t)jj * SYM_T + cs + src;
+            if (first_src) {
+              *d = make_double2(vr, vi);
+            } else {
+              const double2 o = *d;
+              *d = make_double2(o.x + vr, o.y + vi);
+            }
+          }
+        }
+        cs += cl;
       }
-#pragma unroll
-      for (int a = 0; a < NA; ++a) acc[a] = from_next_lane(acc[a]) + cn[a];
     }
-    if (wv == 1) {
 #pragma unroll
-      for (int a = 0; a < NA; ++a) sX[a][lane] = acc[a];
+    for (int t = 0; t < 2; ++t) {
+      const int loc = wv * 128 + t * 64 + lane;
+      if (loc < BI.n)
+        part[T.toff + (int64_t)ii * SYM_T + loc] = make_double2(sr[t] * INV_FOUR_PI, si[t] * INV_FOUR_PI);
     }
-    __syncthreads();
-    if (wv == 0 && c * 64 + src < T.nb) {
-      double v[NA];
-#pragma unroll
-      for (int a = 0; a < NA; ++a) v[a] = acc[a] + sX[a][lane];
-      const double e3r = FORM ? v[4] : 0.0, e3i = FORM ? v[5] : 0.0;
-      // -S1 + i k S2 (- i S3)
-      part[T.joff + c * 64 + src] = make_double2(fma(-k, v[3], e3i - v[0]) * INV_FOUR_PI,
-                                                 fma(k, v[2], -v[1] - e3r) * INV_FOUR_PI);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int loc = wv * 128 + t * 64 + lane;
-    if (loc < T.nt)
-      part[T.ioff + loc] = make_double2(fma(-k, bi[t], ei[t] - ar[t]) * INV_FOUR_PI,
-                                        fma(k, br[t], -ai[t] - er[t]) * INV_FOUR_PI);
   }
 }
 
-// out[n] = (accumulate ? out[n] : 0) + the task sums of n's block.  A
-// workgroup takes 64 consecutive nodes; wavefront w adds the list entries
-// w, w + 4, ... of each node, and the four sums are added in wavefront order
-// (a fixed order).
-template <typename P>
+// out[n] (+)= the slots of n's block in this launch.  A workgroup takes 64
+// consecutive nodes; wavefront w adds the list entries w, w + 4, ... of each
+// node, and the four sums are added in wavefront order (a fixed order).
+// mode 0: out = sum, 1: out += sum.
 __global__ __launch_bounds__(256) void reduce_sym_kernel(
-    const P* __restrict__ part, const int32_t* __restrict__ node_body,
-    const BodyDev* __restrict__ bodies, const int32_t* __restrict__ blk_base,
-    const int32_t* __restrict__ ptr, const int64_t* __restrict__ list, int64_t N,
-    double2* __restrict__ out, int accumulate) {
+    const double2* __restrict__ part, const int32_t* __restrict__ node_block,
+    const SymBlock* __restrict__ blocks, const int64_t* __restrict__ lptr,
+    const int64_t* __restrict__ list, int64_t N, double2* __restrict__ out, int mode) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t n = (int64_t)blockIdx.x * 64 + lane;
   __shared__ double2 red[4][64];
   double2 acc = make_double2(0.0, 0.0);
+  int64_t e0 = 0, e1 = 0;
   if (n < N) {
-    const int b = node_body[n];
-    const int blk = blk_base[b] + (int)((n - bodies[b].off) / SYM_T);
-    const int e1 = ptr[blk + 1];
+    const int blk = node_block[n];
+    e0 = lptr[blk];
+    e1 = lptr[blk + 1];
+    const int64_t rel = n - blocks[blk].n0;
 #pragma unroll 4
-    for (int e = ptr[blk] + w; e < e1; e += 4) {
-      const P v = part[list[e] + n];
-      acc.x += (double)v.x;
-      acc.y += (double)v.y;
+    for (int64_t e = e0 + w; e < e1; e += 4) {
+      const double2 v = part[list[e] + rel];
+      acc.x += v.x;
+      acc.y += v.y;
     }
   }
   red[w][lane] = acc;
   __syncthreads();
-  if (w == 0 && n < N) {
-    double2 o = accumulate ? out[n] : make_double2(0.0, 0.0);
+  if (w == 0 && n < N && (mode == 0 || e1 > e0)) {
+    double2 o = mode ? out[n] : make_double2(0.0, 0.0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       o.x += red[q][lane].x;
@@ -824,88 +918,222 @@ __global__ __launch_bounds__(256) void reduce_sym_kernel(
   }
 }
 
-// Tasks of the reciprocal kernel: for every problem, every pair of bodies
-// a < b and every pair of blocks (one of a, one of b).  Partial-sum offsets
-// follow the order of construction; each block lists, in that order, the
-// tasks whose target or source block it is.  The table is then sorted by
-// decreasing cost.
-static void plan_sym(qax_problem* p) {
+// Blocks of SYM_T consecutive nodes per problem, and the block of each node.
+static void plan_sym_blocks(qax_problem* p) {
   auto& S = p->sym;
-  S.tasks.clear();
   S.ok = p->n_problems > 0;
   for (int pr = 0; pr < p->n_problems; ++pr) S.ok = S.ok && p->k[pr] > 0.0;
-  const int nbody = (int)p->hbodies.size();
-  std::vector<int32_t> blk_base(nbody + 1, 0);
-  for (int b = 0; b < nbody; ++b)
-    blk_base[b + 1] = blk_base[b] + (p->hbodies[b].n + SYM_T - 1) / SYM_T;
-  std::vector<std::vector<int64_t>> lists(blk_base[nbody]);
-  int64_t off = 0;
+  S.blocks.clear();
+  S.prob_blk0.assign(p->n_problems + 1, 0);
+  S.blk_body_lo.clear();
+  S.blk_body_hi.clear();
   for (int pr = 0; pr < p->n_problems; ++pr) {
+    S.prob_blk0[pr] = (int32_t)S.blocks.size();
     const int b0 = (int)p->prob_body0[pr], b1 = (int)p->prob_body0[pr + 1];
-    for (int a = b0; a < b1; ++a)
-      for (int b = a + 1; b < b1; ++b)
-        for (int qa = 0; qa * SYM_T < p->hbodies[a].n; ++qa)
-          for (int qb = 0; qb * SYM_T < p->hbodies[b].n; ++qb) {
-            SymTask T;
-            T.t0 = p->hbodies[a].off + (int64_t)qa * SYM_T;
-            T.nt = std::min(SYM_T, p->hbodies[a].n - qa * SYM_T);
-            T.s0 = p->hbodies[b].off + (int64_t)qb * SYM_T;
-            T.nb = std::min(SYM_T, p->hbodies[b].n - qb * SYM_T);
-            T.a = a;
-            T.b = b;
-            T.ioff = off;
-            T.joff = off + T.nt;
-            lists[blk_base[a] + qa].push_back(T.ioff - T.t0);
-            lists[blk_base[b] + qb].push_back(T.joff - T.s0);
-            off += T.nt + T.nb;
-            S.tasks.push_back(T);
-          }
+    const int64_t n0 = p->off[b0], n1 = p->off[b1];
+    int lo = b0;
+    for (int64_t a = n0; a < n1; a += SYM_T) {
+      SymBlock B;
+      B.n0 = a;
+      B.n = (int32_t)std::min<int64_t>(SYM_T, n1 - a);
+      B.problem = pr;
+      while (lo + 1 < b1 && p->off[lo + 1] <= a) ++lo;
+      int hi = lo;
+      while (hi + 1 < b1 && p->off[hi + 1] <= a + B.n - 1) ++hi;
+      S.blocks.push_back(B);
+      S.blk_body_lo.push_back(lo);
+      S.blk_body_hi.push_back(hi);
+    }
   }
-  S.nparts = off;
-  auto cost = [](const SymTask& x) { return (int64_t)x.nt * x.nb; };
-  bool uniform = true;
-  for (const SymTask& T : S.tasks) uniform = uniform && cost(T) == cost(S.tasks[0]);
-  if (!uniform)
-    std::stable_sort(S.tasks.begin(), S.tasks.end(),
-                     [&](const SymTask& x, const SymTask& y) { return cost(x) > cost(y); });
-  S.h_blk_base = blk_base;
-  S.h_ptr.assign(1, 0);
-  S.h_list.clear();
-  for (auto& v : lists) {
-    S.h_list.insert(S.h_list.end(), v.begin(), v.end());
-    S.h_ptr.push_back((int32_t)S.h_list.size());
-  }
+  S.prob_blk0[p->n_problems] = (int32_t)S.blocks.size();
 }
 
-static hipError_t upload_sym(qax_problem* p) {
+// Super-tasks of s x s block pairs, sorted by decreasing cost, cut into
+// launches whose slots fit `cap` complex values; per launch and block, the
+// slots that hold sums of the block's nodes (in super-task order).
+static void plan_sym_supers(qax_problem* p, int pi, int s, int64_t cap) {
   auto& S = p->sym;
-  if (S.d_mem) {
+  auto& P = S.plan[pi];
+  P.supers.clear();
+  const int nblk = (int)S.blocks.size();
+  auto same_body = [&](int I, int J) {
+    return S.blk_body_lo[I] == S.blk_body_hi[I] && S.blk_body_lo[J] == S.blk_body_hi[J] &&
+           S.blk_body_lo[I] == S.blk_body_lo[J];
+  };
+  std::vector<double> cost;
+  for (int pr = 0; pr < p->n_problems; ++pr) {
+    const int g0 = S.prob_blk0[pr], g1 = S.prob_blk0[pr + 1];
+    for (int r0 = g0; r0 < g1; r0 += s)
+      for (int c0 = r0; c0 < g1; c0 += s) {
+        SymSuper T;
+        T.i0 = r0;
+        T.ni = std::min(s, g1 - r0);
+        T.j0 = c0;
+        T.nj = std::min(s, g1 - c0);
+        T.diag = r0 == c0 ? 1 : 0;
+        T.problem = pr;
+        T.k = p->k[pr];
+        T.skip = 0;
+        double c = 0.0;
+        int visits = 0;
+        for (int ii = 0; ii < T.ni; ++ii)
+          for (int jj = T.diag ? ii : 0; jj < T.nj; ++jj) {
+            const int I = r0 + ii, J = c0 + jj;
+            if (same_body(I, J)) {
+              T.skip |= 1ull << (ii * SYM_SMAX + jj);
+              continue;
+            }
+            ++visits;
+            c += (double)S.blocks[I].n * S.blocks[J].n;
+          }
+        if (!visits) continue;
+        T.toff = T.soff = 0;
+        P.supers.push_back(T);
+        cost.push_back(c);
+      }
+  }
+  // decreasing cost (stable: ties keep the construction order)
+  std::vector<int64_t> ord(P.supers.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int64_t)i;
+  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+  std::vector<SymSuper> sorted;
+  sorted.reserve(ord.size());
+  for (int64_t i : ord) sorted.push_back(P.supers[i]);
+  P.supers.swap(sorted);
+  // launches and slot offsets
+  P.launch_super.assign(1, 0);
+  P.max_slots = 0;
+  int64_t used = 0;
+  for (size_t i = 0; i < P.supers.size(); ++i) {
+    SymSuper& T = P.supers[i];
+    const int64_t need = (int64_t)(T.ni + T.nj) * SYM_T;
+    if (used > 0 && used + need > cap) {
+      P.launch_super.push_back((int64_t)i);
+      used = 0;
+    }
+    T.toff = used;
+    T.soff = used + (int64_t)T.ni * SYM_T;
+    used += need;
+    P.max_slots = std::max(P.max_slots, used);
+  }
+  P.launch_super.push_back((int64_t)P.supers.size());
+  const int nl = (int)P.launch_super.size() - 1;
+  // lists: per launch, per block
+  P.lptr.assign((size_t)nl * (nblk + 1), 0);
+  P.list.clear();
+  std::vector<std::vector<int64_t>> lists(nblk);
+  for (int l = 0; l < nl; ++l) {
+    for (auto& v : lists) v.clear();
+    for (int64_t i = P.launch_super[l]; i < P.launch_super[l + 1]; ++i) {
+      const SymSuper& T = P.supers[i];
+      uint32_t colseen = 0;
+      for (int ii = 0; ii < T.ni; ++ii) {
+        bool row = false;
+        for (int jj = T.diag ? ii : 0; jj < T.nj; ++jj) {
+          if ((T.skip >> (ii * SYM_SMAX + jj)) & 1ull) continue;
+          row = true;
+          if (T.i0 + ii != T.j0 + jj) colseen |= 1u << jj;
+        }
+        if (row) lists[T.i0 + ii].push_back(T.toff + (int64_t)ii * SYM_T);
+      }
+      for (int jj = 0; jj < T.nj; ++jj)
+        if ((colseen >> jj) & 1u) lists[T.j0 + jj].push_back(T.soff + (int64_t)jj * SYM_T);
+    }
+    int64_t* lp = P.lptr.data() + (size_t)l * (nblk + 1);
+    for (int b = 0; b < nblk; ++b) {
+      lp[b] = (int64_t)P.list.size();
+      P.list.insert(P.list.end(), lists[b].begin(), lists[b].end());
+    }
+    lp[nblk] = (int64_t)P.list.size();
+  }
+  P.s = s;
+}
+
+static hipError_t upload_sym_blocks(qax_problem* p) {
+  auto& S = p->sym;
+  if (S.d_bmem) {
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return e;
-    dev_release(p, S.d_mem);
-    S.d_mem = nullptr;
+    dev_release(p, S.d_bmem);
+    S.d_bmem = nullptr;
   }
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
-  const size_t bt = al(sizeof(SymTask) * std::max<size_t>(1, S.tasks.size()));
-  const size_t bb = al(sizeof(int32_t) * S.h_blk_base.size());
-  const size_t bp = al(sizeof(int32_t) * S.h_ptr.size());
-  const size_t bl = al(sizeof(int64_t) * std::max<size_t>(1, S.h_list.size()));
-  hipError_t e = dev_alloc(p, &S.d_mem, bt + bb + bp + bl);
+  const size_t bb = al(sizeof(SymBlock) * std::max<size_t>(1, S.blocks.size()));
+  const size_t bn = al(sizeof(int32_t) * std::max<int64_t>(1, p->N));
+  hipError_t e = dev_alloc(p, &S.d_bmem, bb + bn);
   if (e != hipSuccess) return e;
-  char* m = (char*)S.d_mem;
-  S.d_tasks = (SymTask*)m;
-  S.d_blk_base = (int32_t*)(m + bt);
-  S.d_ptr = (int32_t*)(m + bt + bb);
-  S.d_list = (int64_t*)(m + bt + bb + bp);
+  S.d_blocks = (SymBlock*)S.d_bmem;
+  S.d_node_block = (int32_t*)((char*)S.d_bmem + bb);
+  std::vector<int32_t> nb(p->N);
+  for (size_t b = 0; b < S.blocks.size(); ++b)
+    for (int t = 0; t < S.blocks[b].n; ++t) nb[S.blocks[b].n0 + t] = (int32_t)b;
+  if (!S.blocks.empty())
+    e = hipMemcpyAsync(S.d_blocks, S.blocks.data(), sizeof(SymBlock) * S.blocks.size(),
+                       hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess && p->N)
+    e = hipMemcpyAsync(S.d_node_block, nb.data(), sizeof(int32_t) * p->N, hipMemcpyHostToDevice, p->stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(p->stream);
+}
+
+static hipError_t upload_sym_plan(qax_problem* p, int pi) {
+  auto& P = p->sym.plan[pi];
+  if (P.d_mem) {
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return e;
+    dev_release(p, P.d_mem);
+    P.d_mem = nullptr;
+  }
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t bs = al(sizeof(SymSuper) * std::max<size_t>(1, P.supers.size()));
+  const size_t bp = al(sizeof(int64_t) * std::max<size_t>(1, P.lptr.size()));
+  const size_t bl = al(sizeof(int64_t) * std::max<size_t>(1, P.list.size()));
+  hipError_t e = dev_alloc(p, &P.d_mem, bs + bp + bl);
+  if (e != hipSuccess) return e;
+  char* m = (char*)P.d_mem;
+  P.d_supers = (SymSuper*)m;
+  P.d_lptr = (int64_t*)(m + bs);
+  P.d_list = (int64_t*)(m + bs + bp);
   auto cp = [&](void* d, const void* h, size_t n) {
     if (e == hipSuccess && n) e = hipMemcpyAsync(d, h, n, hipMemcpyHostToDevice, p->stream);
   };
-  cp(S.d_tasks, S.tasks.data(), sizeof(SymTask) * S.tasks.size());
-  cp(S.d_blk_base, S.h_blk_base.data(), sizeof(int32_t) * S.h_blk_base.size());
-  cp(S.d_ptr, S.h_ptr.data(), sizeof(int32_t) * S.h_ptr.size());
-  cp(S.d_list, S.h_list.data(), sizeof(int64_t) * S.h_list.size());
+  cp(P.d_supers, P.supers.data(), sizeof(SymSuper) * P.supers.size());
+  cp(P.d_lptr, P.lptr.data(), sizeof(int64_t) * P.lptr.size());
+  cp(P.d_list, P.list.data(), sizeof(int64_t) * P.list.size());
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(p->stream);
+}
+
+// Default super-task size: the largest of 8, 4, 2, 1 that still gives every
+// compute unit 16 super-tasks.
+int sym_default_s(const qax_problem* p, int cu_count) {
+  const auto& S = p->sym;
+  for (int s : {8, 4, 2}) {
+    int64_t n = 0;
+    for (int pr = 0; pr < p->n_problems; ++pr) {
+      const int64_t r = (S.prob_blk0[pr + 1] - S.prob_blk0[pr] + s - 1) / s;
+      n += r * (r + 1) / 2;
+    }
+    if (n >= 16LL * cu_count) return s;
+  }
+  return 1;
+}
+
+// (Re)plan the reciprocal kernels for super-tasks of s x s block pairs
+// (s <= 0: the default), precision index pi (0 FP64, 1 FP32).
+hipError_t plan_sym(qax_problem* p, int pi, int s, int cu_count) {
+  auto& S = p->sym;
+  if (!S.d_bmem) {
+    plan_sym_blocks(p);
+    hipError_t e = upload_sym_blocks(p);
+    if (e != hipSuccess) return e;
+  }
+  if (s <= 0) s = sym_default_s(p, cu_count);
+  s = std::max(1, std::min(SYM_SMAX, s));
+  if (S.plan[pi].d_mem && S.plan[pi].s == s) return hipSuccess;
+  plan_sym_supers(p, pi, s, SYM_SLOT_CAP);
+  ++p->generation;   // captured solver steps hold the old launch sizes
+  return upload_sym_plan(p, pi);
 }
 
 // Build the task table: target blocks of `tpb` rows inside one problem, each
@@ -976,10 +1204,10 @@ void plan_pair_sum(qax_problem* p, int prec, int cu_count) {
 
 hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count) {
   plan_pair_sum(p, prec, cu_count);
-  if (!p->sym.d_mem) {
-    // the reciprocal task table depends on the geometry only
-    plan_sym(p);
-    hipError_t e = upload_sym(p);
+  {
+    // the reciprocal kernels' super-tasks (kept while the geometry and the
+    // super-task size are unchanged)
+    hipError_t e = plan_sym(p, prec == QAX_FP64 ? 0 : 1, p->tune.sym_s[prec == QAX_FP64 ? 0 : 1], cu_count);
     if (e != hipSuccess) return e;
   }
   ++p->generation;   // captured solver steps hold the old launch sizes
@@ -1078,12 +1306,13 @@ size_t pair_work_bytes(const qax_problem* p, int prec, int nrhs) {
   const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;
   size_t b = std::max((size_t)slots * p->N * nrhs * 16, lattice_work_bytes(p, nrhs));
   if (nrhs == 1 && p->sym.ok)
-    b = std::max(b, (size_t)p->sym.nparts * (prec == QAX_FP64 ? 16 : 8));
+    b = std::max(b, (size_t)p->sym.plan[prec == QAX_FP64 ? 0 : 1].max_slots * 16);
   return b;
 }
 
 static bool use_sym(const qax_problem* p, int prec, int nrhs) {
-  return nrhs == 1 && p->sym.ok && p->sym.enabled && p->sym.d_mem && p->form() != 2;
+  return nrhs == 1 && p->sym.ok && p->sym.enabled && p->sym.plan[prec == QAX_FP64 ? 0 : 1].d_mem &&
+         p->form() != 2;
 }
 
 hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* out, int nrhs,
@@ -1101,45 +1330,47 @@ hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* o
   const int kind = f64 ? QAX_K_PAIRSUM_FP64 : QAX_K_PAIRSUM_FP32;
   if (use_sym(p, prec, nrhs)) {
     auto& S = p->sym;
+    auto& P = S.plan[pi];
     const int form = p->form();
-    timing_begin(p, kind);
-    if (!S.tasks.empty()) {
-      const dim3 grid((unsigned)S.tasks.size());
-      if (f64) {
-        double2* part = (double2*)partial;
-        if (form == 1)
-          hipLaunchKernelGGL(pair_sum_f64_sym_kernel<1>, grid, dim3(128), 0, p->stream, S.d_tasks,
-                             p->d_bodies, p->d_pos, p->d_aw, p->d_ew, p->N, (const double2*)mu,
-                             p->seg_active, part);
-        else
-          hipLaunchKernelGGL(pair_sum_f64_sym_kernel<0>, grid, dim3(128), 0, p->stream, S.d_tasks,
-                             p->d_bodies, p->d_pos, p->d_aw, p->d_ew, p->N, (const double2*)mu,
-                             p->seg_active, part);
-      } else {
-        float2* part = (float2*)partial;
-        if (form == 1)
-          hipLaunchKernelGGL(pair_sum_f32_sym_kernel<1>, grid, dim3(128), 0, p->stream, S.d_tasks,
-                             p->d_bodies, (const float4*)p->d_loc32, (const float4*)p->d_aw32,
-                             p->d_ew32, (const double2*)mu, p->seg_active, part);
-        else
-          hipLaunchKernelGGL(pair_sum_f32_sym_kernel<0>, grid, dim3(128), 0, p->stream, S.d_tasks,
-                             p->d_bodies, (const float4*)p->d_loc32, (const float4*)p->d_aw32,
-                             p->d_ew32, (const double2*)mu, p->seg_active, part);
-      }
-    }
-    timing_end(p, kind);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    double2* part = (double2*)partial;
+    const int nblk = (int)S.blocks.size();
+    const int nl = (int)P.launch_super.size() - 1;
     const dim3 rgrid((unsigned)((p->N + 63) / 64));
-    if (f64)
-      hipLaunchKernelGGL(reduce_sym_kernel<double2>, rgrid, dim3(256), 0, p->stream,
-                         (const double2*)partial, p->d_node_body, p->d_bodies, S.d_blk_base,
-                         S.d_ptr, S.d_list, p->N, (double2*)out, accumulate ? 1 : 0);
-    else
-      hipLaunchKernelGGL(reduce_sym_kernel<float2>, rgrid, dim3(256), 0, p->stream,
-                         (const float2*)partial, p->d_node_body, p->d_bodies, S.d_blk_base,
-                         S.d_ptr, S.d_list, p->N, (double2*)out, accumulate ? 1 : 0);
-    return hipGetLastError();
+    for (int l = 0; l < nl; ++l) {
+      const int64_t s0 = P.launch_super[l], s1 = P.launch_super[l + 1];
+      if (s1 > s0) {
+        const dim3 grid((unsigned)(s1 - s0));
+        timing_begin(p, kind);
+        if (f64) {
+          if (form == 1)
+            hipLaunchKernelGGL(pair_sum_f64_sym_kernel<1>, grid, dim3(128), 0, p->stream, P.d_supers + s0,
+                               S.d_blocks, p->d_bodies, p->d_node_body, p->d_pos, p->d_aw, p->d_ew, p->N,
+                               (const double2*)mu, p->seg_active, part);
+          else
+            hipLaunchKernelGGL(pair_sum_f64_sym_kernel<0>, grid, dim3(128), 0, p->stream, P.d_supers + s0,
+                               S.d_blocks, p->d_bodies, p->d_node_body, p->d_pos, p->d_aw, p->d_ew, p->N,
+                               (const double2*)mu, p->seg_active, part);
+        } else {
+          if (form == 1)
+            hipLaunchKernelGGL(pair_sum_f32_sym_kernel<1>, grid, dim3(128), 0, p->stream, P.d_supers + s0,
+                               S.d_blocks, p->d_bodies, p->d_node_body, (const float4*)p->d_loc32,
+                               (const float4*)p->d_aw32, p->d_ew32, (const double2*)mu, p->seg_active, part);
+          else
+            hipLaunchKernelGGL(pair_sum_f32_sym_kernel<0>, grid, dim3(128), 0, p->stream, P.d_supers + s0,
+                               S.d_blocks, p->d_bodies, p->d_node_body, (const float4*)p->d_loc32,
+                               (const float4*)p->d_aw32, p->d_ew32, (const double2*)mu, p->seg_active, part);
+        }
+        timing_end(p, kind);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+      hipLaunchKernelGGL(reduce_sym_kernel, rgrid, dim3(256), 0, p->stream, (const double2*)part,
+                         S.d_node_block, S.d_blocks, P.d_lptr + (size_t)l * (nblk + 1), P.d_list, p->N,
+                         (double2*)out, l == 0 ? (accumulate ? 1 : 0) : 1);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
   const int tpb = p->tune.pair_tpb[pi];
   int nrc = nrhs == 1 ? 1 : p->tune.pair_nrc[pi][nrhs_class(nrhs)];

@@ -38,7 +38,7 @@ class qax_tuning_info(C.Structure):
     _fields_ = [("tuned", C.c_int32), ("from_cache", C.c_int32), ("pair_tpb", C.c_int32 * 2),
                 ("pair_slot_mult", C.c_int32 * 2), ("pair_nrc", (C.c_int32 * 4) * 2),
                 ("gemv_vec", C.c_int32 * 2), ("pair_ms", C.c_double * 2),
-                ("default_pair_ms", C.c_double * 2)]
+                ("default_pair_ms", C.c_double * 2), ("pair_sym_s", C.c_int32 * 2)]
 
 
 class QaxError(RuntimeError):
@@ -298,11 +298,12 @@ def qax_tuning(h):
             "pair_nrc": {"fp64": list(t.pair_nrc[0]), "fp32": list(t.pair_nrc[1])},
             "gemv_vec": {"fp64": t.gemv_vec[0], "fp32": t.gemv_vec[1]},
             "pair_ms": {"fp64": t.pair_ms[0], "fp32": t.pair_ms[1]},
-            "default_pair_ms": {"fp64": t.default_pair_ms[0], "fp32": t.default_pair_ms[1]}}
+            "default_pair_ms": {"fp64": t.default_pair_ms[0], "fp32": t.default_pair_ms[1]},
+            "pair_sym_s": {"fp64": t.pair_sym_s[0], "fp32": t.pair_sym_s[1]}}
 
 
 def qax_set_tuning(h, pair_tpb=(256, 256), pair_slot_mult=(8, 8),
-                   pair_nrc=((4, 8, 8, 8), (4, 8, 16, 16)), gemv_vec=(1, 1)):
+                   pair_nrc=((4, 8, 8, 8), (4, 8, 16, 16)), gemv_vec=(1, 1), pair_sym_s=(0, 0)):
     """Set the launch choices by hand ([FP64, FP32] pairs, as qax_tuning reports)."""
     t = qax_tuning_info()
     for i in range(2):
@@ -311,6 +312,7 @@ def qax_set_tuning(h, pair_tpb=(256, 256), pair_slot_mult=(8, 8),
         for c in range(4):
             t.pair_nrc[i][c] = int(pair_nrc[i][c])
         t.gemv_vec[i] = int(gemv_vec[i])
+        t.pair_sym_s[i] = int(pair_sym_s[i])
     _check(h, lib().qax_set_tuning(h, C.byref(t)))
 
 

@@ -73,6 +73,24 @@ def test_pair_sum_every_schedule(ref, tpb, mult):
         assert rel(got[tg], want) < 1e-12
 
 
+def test_reciprocal_every_super_task_size(ref):
+    # one right-hand side: the reciprocal kernels with 1, 2, 4 and 8 block
+    # pairs per super-task side (different launch counts and slot layouts),
+    # each against the oracle, element by element
+    s, mu, tg, want = ref
+    with qax.Problem(s) as P:
+        for sv in (1, 2, 4, 8):
+            qax.qax_set_tuning(P.h, pair_sym_s=(sv, sv))
+            assert qax.qax_tuning(P.h)["pair_sym_s"] == {"fp64": sv, "fp32": sv}
+            got = run_pair(P, qax.QAX_FP64, mu[:, :1])[tg, 0]
+            assert np.abs(got - want[:, 0]).max() < 1e-12 * np.abs(want[:, 0]).max()
+            got = run_pair(P, qax.QAX_MIXED, mu[:, :1])[tg, 0]
+            assert rel(got, want[:, 0]) < 1e-5
+            assert np.abs(got - want[:, 0]).max() < 1e-5 * np.abs(want[:, 0]).max()
+        with pytest.raises(qax.QaxError):
+            qax.qax_set_tuning(P.h, pair_sym_s=(9, 1))
+
+
 @pytest.mark.parametrize("nrc", [1, 2, 4, 8, 16, 32])
 def test_pair_sum_every_rhs_pass(ref, nrc):
     s, mu, tg, want = ref
@@ -127,13 +145,13 @@ def test_autotune_and_cache(ref, tmp_path):
         assert t["pair_ms"]["fp32"] > 0 and t["default_pair_ms"]["fp32"] > 0
         assert rel(run_pair(P, qax.QAX_FP64, mu)[tg], want) < 1e-12
         assert rel(run_pair(P, qax.QAX_MIXED, mu)[tg], want) < 1e-5
-    assert cache.read_text().startswith("qax-tune v1 ")
+    assert cache.read_text().startswith("qax-tune v2 ")
     with qax.Problem(s) as P:
         qax.qax_assemble_self(P.h)     # same signature: built and assembled
         qax.qax_autotune(P.h, nrhs_max=5, cache_path=str(cache))
         t2 = qax.qax_tuning(P.h)
         assert t2["from_cache"]
-        for key in ("pair_tpb", "pair_slot_mult", "pair_nrc", "gemv_vec"):
+        for key in ("pair_tpb", "pair_slot_mult", "pair_nrc", "gemv_vec", "pair_sym_s"):
             assert t2[key] == t[key]
         assert rel(run_pair(P, qax.QAX_MIXED, mu)[tg], want) < 1e-5
 
@@ -145,6 +163,8 @@ def test_autotune_single_rhs_not_slower_than_default(ref):
         t = qax.qax_tuning(P.h)
         for prec in ("fp64", "fp32"):       # the default is one of the candidates
             assert t["pair_ms"][prec] <= 1.15 * t["default_pair_ms"][prec]
+            assert t["pair_sym_s"][prec] in (1, 2, 4, 8)
+        assert rel(run_pair(P, qax.QAX_MIXED, mu[:, :1])[tg, 0], want[:, 0]) < 1e-5
 
 
 def test_solve_after_tuning_matches_default():
