@@ -212,9 +212,14 @@ qax_status qax_invert(qax_problem* p, qax_prec prec, int32_t count, const int32_
  * Gauss-Jordan inversion in FP64) for N <= 8192; d_mu_out N x nrhs. */
 qax_status qax_solve_dense(qax_problem* p, const double* dirs, int32_t nrhs, void* d_mu_out);
 
-/* Far field of the double-layer density (problem 0 only):
- * u_inf(xhat) = (1/4 pi) sum_j (-i k xhat.n_j) e^{-i k xhat.y_j} mu_j |J_j| w_j.
- * xhat: host, n_dirs x 3.  d_u_inf: n_dirs x nrhs complex128. */
+/* Far field of the double-layer density of every problem p (Section 6, the
+ * far-field pattern, in its double-layer form):
+ * u_inf_p(xhat) = (1/4 pi) sum_{j in p} (-i k_p xhat.n_j) e^{-i k_p xhat.y_j}
+ * mu_j |J_j| w_j (combined field: plus -i eta |J_j| w_j e^{...}; single layer:
+ * |J_j| w_j e^{...} mu_j alone).  xhat: host, n_dirs x 3 (finite; a direction
+ * whose exact negation is also listed shares its phase evaluation, with the
+ * same results).  d_mu: N x nrhs; d_u_inf: n_problems x n_dirs x nrhs
+ * complex128 (problem, then direction, then right-hand side). */
 qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrhs,
                         const double* xhat, int32_t n_dirs, void* d_u_inf);
 

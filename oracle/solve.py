@@ -176,18 +176,21 @@ def solve(disc, k_per_problem, blocks, b, method="gmres", tol=1e-10, restart=100
                  tol=tol, restart=restart, maxit=maxit)
 
 
-def far_field(disc, k_per_problem, mu, xhat, eta=None, single=False):
-    """u_inf at unit directions xhat (ndir, 3); mu (N,) -> (ndir,).  With eta
-    the combined field adds - i eta (1/4 pi) sum_j e^{-i k xhat.y_j} mu_j |J_j| w_j;
-    single: that single-layer term alone with coefficient 1."""
-    k = float(np.asarray(k_per_problem)[0])
-    ph = np.exp(-1j * k * (xhat @ disc.pos.T))            # (ndir, N)
+def far_field(disc, k_per_problem, mu, xhat, eta=None, single=False, problem=0):
+    """u_inf of the bodies of `problem` at unit directions xhat (ndir, 3);
+    mu (N,) -> (ndir,).  With eta the combined field adds
+    - i eta (1/4 pi) sum_j e^{-i k xhat.y_j} mu_j |J_j| w_j; single: that
+    single-layer term alone with coefficient 1."""
+    k = float(np.asarray(k_per_problem)[problem])
+    sel = np.nonzero(disc.problem == problem)[0]
+    pos, aw, mu = disc.pos[sel], disc.aw[sel], np.asarray(mu)[sel]
+    ph = np.exp(-1j * k * (xhat @ pos.T))                 # (ndir, n)
     if single:
-        return (ph * np.linalg.norm(disc.aw, axis=1)[None, :]) @ mu / FOUR_PI
-    nd = xhat @ disc.aw.T                                  # xhat . n |J| w
+        return (ph * np.linalg.norm(aw, axis=1)[None, :]) @ mu / FOUR_PI
+    nd = xhat @ aw.T                                       # xhat . n |J| w
     f = (-1j * k) * nd
     if eta is not None:
-        f = f - 1j * eta * np.linalg.norm(disc.aw, axis=1)[None, :]
+        f = f - 1j * eta * np.linalg.norm(aw, axis=1)[None, :]
     return (ph * f) @ mu / FOUR_PI
 
 

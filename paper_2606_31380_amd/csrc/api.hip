@@ -681,11 +681,17 @@ extern "C" qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrh
     }
   }
   const int nitems = (int)items.size();
-  const int slots = farfield_slots(nitems, cu_count(p->device));
-  const size_t up = (size_t)n_dirs * 24 + (size_t)nitems * sizeof(int2);
+  const int slots = farfield_slots((int64_t)nitems * p->n_problems, cu_count(p->device));
+  const int np = p->n_problems;
+  // problems: first nodes (np + 1 int64), then their k (np doubles)
+  std::vector<int64_t> pinfo(2 * (size_t)np + 1);
+  for (int pr = 0; pr <= np; ++pr) pinfo[pr] = p->off[p->prob_body0[pr]];
+  for (int pr = 0; pr < np; ++pr) std::memcpy(&pinfo[np + 1 + pr], &p->k[pr], 8);
+  const size_t up = (size_t)n_dirs * 24 + (size_t)nitems * sizeof(int2) + pinfo.size() * 8;
   QBUF(dx, double, "xhat", up);
-  QBUF(part, double, "ff_partial", (size_t)slots * n_dirs * nrhs * 16);
+  QBUF(part, double, "ff_partial", (size_t)slots * np * n_dirs * nrhs * 16);
   int2* ditems = (int2*)(dx + 3 * (size_t)n_dirs);
+  int64_t* dpinfo = (int64_t*)(ditems + nitems);
   // directions and items through pinned staging: one asynchronous copy
   if (p->h_stage_bytes < up) {
     if (p->h_stage) (void)hipHostFree(p->h_stage);
@@ -696,8 +702,10 @@ extern "C" qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrh
   }
   std::memcpy(p->h_stage, xhat, (size_t)n_dirs * 24);
   std::memcpy((char*)p->h_stage + (size_t)n_dirs * 24, items.data(), (size_t)nitems * sizeof(int2));
+  std::memcpy((char*)p->h_stage + (size_t)n_dirs * 24 + (size_t)nitems * sizeof(int2), pinfo.data(),
+              pinfo.size() * 8);
   QCHECK(hipMemcpyAsync(dx, p->h_stage, up, hipMemcpyHostToDevice, p->stream), "copy directions");
-  QCHECK(launch_farfield(p, (const double*)d_mu, nrhs, dx, n_dirs, ditems, nitems, slots, part,
+  QCHECK(launch_farfield(p, (const double*)d_mu, nrhs, dx, n_dirs, ditems, nitems, dpinfo, slots, part,
                          (double*)d_u_inf),
          "farfield");
   return sync(p, "qax_farfield");

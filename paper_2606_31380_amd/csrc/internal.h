@@ -318,7 +318,7 @@ hipError_t launch_modal_modes(hipStream_t s, int n, const double* r, const doubl
 hipError_t launch_rhs(qax_problem* p, const double* dirs_dev, int nrhs, double* out);
 int farfield_slots(int64_t M, int cu_count);
 hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const double* xhat_dev,
-                           int ndir, const int2* items_dev, int nitems, int slots, double* partial,
-                           double* out);
+                           int ndir, const int2* items_dev, int nitems, const int64_t* pinfo_dev,
+                           int slots, double* partial, double* out);
 
 }  // namespace qax

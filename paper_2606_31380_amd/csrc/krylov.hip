@@ -46,19 +46,20 @@ hipError_t launch_rhs(qax_problem* p, const double* dirs_dev, int nrhs, double* 
 __global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slots, int64_t count,
                                     double2* __restrict__ out, int accumulate);
 
-// u_inf[dir][r] = (1/4pi) sum_{n in problem 0} (-i k xhat.aw_n) e^{-i k xhat.y_n} mu[n][r]
-// (combined field: plus -i eta |aw_n| e^{...}; single layer: |aw_n| e^{...}
-// alone).  One item per thread: a direction, or a direction and its exact
-// negation (the phase negated: one sin/cos for both); node tiles staged in
-// LDS and read by broadcast, the node range cut into `slots` chunks (blockIdx.y) whose
-// partial sums are added in a fixed order afterwards; right-hand side
-// blockIdx.z.
+// u_inf[p][dir][r] = (1/4pi) sum_{n in problem p} (-i k_p xhat.aw_n)
+// e^{-i k_p xhat.y_n} mu[n][r] (combined field: plus -i eta |aw_n| e^{...};
+// single layer: |aw_n| e^{...} alone).  One item per thread: a direction, or a
+// direction and its exact negation (the phase negated: one sin/cos for
+// both); node tiles staged in LDS and read by broadcast, the problem's node
+// range cut into `slots` chunks (blockIdx.y) whose partial sums are added in a
+// fixed order afterwards; blockIdx.z = problem * nrhs + right-hand side.
+// pinfo: the problems' first nodes (n_problems + 1 int64) then their k.
 template <int TPB>
 __global__ __launch_bounds__(TPB) void farfield_kernel(
     const double* __restrict__ xhat, const int2* __restrict__ items, int64_t M, int64_t Mi,
     const double* __restrict__ pos, const double* __restrict__ aw, const double* __restrict__ ew,
-    int form, int64_t N, int64_t n0, int slots, double k, const double2* __restrict__ mu, int nrhs,
-    double2* __restrict__ partial) {
+    int form, int64_t N, const int64_t* __restrict__ pinfo, int nprob, int slots,
+    const double2* __restrict__ mu, int nrhs, double2* __restrict__ partial) {
   const int tid = threadIdx.x;
   const int64_t t = (int64_t)blockIdx.x * TPB + tid;
   const bool active = t < Mi;
@@ -67,14 +68,16 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
   const int2 it = active ? items[t] : make_int2(0, -1);
   const int64_t i = it.x, i2 = it.y;
   const double pair = i2 >= 0 ? 1.0 : 0.0;
-  const int r = blockIdx.z;
+  const int r = blockIdx.z % nrhs, pr = blockIdx.z / nrhs;
+  const int64_t pn0 = pinfo[pr], pn = pinfo[pr + 1] - pn0;
+  const double k = __longlong_as_double(pinfo[nprob + 1 + pr]);
   const double hx = active ? xhat[3 * i] : 0.0, hy = active ? xhat[3 * i + 1] : 0.0,
                hz = active ? xhat[3 * i + 2] : 0.0;
   // phase -k x.y / 2 pi in revolutions and k x, per direction
   const double kr = -k / TWO_PI;
   const double px = kr * hx, py = kr * hy, pz = kr * hz;
   const double qx = k * hx, qy = k * hy, qz = k * hz;
-  const int64_t c0 = n0 * blockIdx.y / slots, c1 = n0 * (blockIdx.y + 1) / slots;
+  const int64_t c0 = pn0 + pn * blockIdx.y / slots, c1 = pn0 + pn * (blockIdx.y + 1) / slots;
   __shared__ double sx[TPB], sy[TPB], sz[TPB], sax[TPB], say[TPB], saz[TPB], sew[TPB];
   __shared__ double2 smu[TPB];
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
@@ -122,10 +125,10 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
     }
   }
   if (active) {
-    partial[((int64_t)blockIdx.y * M + i) * nrhs + r] = make_double2(ar * INV_FOUR_PI_K, ai * INV_FOUR_PI_K);
+    const int64_t base = ((int64_t)blockIdx.y * nprob + pr) * M;
+    partial[(base + i) * nrhs + r] = make_double2(ar * INV_FOUR_PI_K, ai * INV_FOUR_PI_K);
     if (pair > 0.0)
-      partial[((int64_t)blockIdx.y * M + i2) * nrhs + r] =
-          make_double2(br * INV_FOUR_PI_K, bi * INV_FOUR_PI_K);
+      partial[(base + i2) * nrhs + r] = make_double2(br * INV_FOUR_PI_K, bi * INV_FOUR_PI_K);
   }
 }
 
@@ -134,19 +137,19 @@ int farfield_slots(int64_t M, int cu_count) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(64, (8LL * cu_count + blocks - 1) / blocks));
 }
 
-// out[dir][r] (directions xhat_dev, 3 doubles each); partial: farfield_slots
-// x ndir x nrhs complex128.
+// out[problem][dir][r] (directions xhat_dev, 3 doubles each; pinfo_dev as
+// the kernel's pinfo); partial: farfield_slots x n_problems x ndir x nrhs
+// complex128.
 hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const double* xhat_dev,
-                           int ndir, const int2* items_dev, int nitems, int slots, double* partial,
-                           double* out) {
-  const int64_t n0 = p->off[p->prob_body0[1]];
-  dim3 grid((unsigned)((nitems + 255) / 256), (unsigned)slots, (unsigned)nrhs);
+                           int ndir, const int2* items_dev, int nitems, const int64_t* pinfo_dev,
+                           int slots, double* partial, double* out) {
+  dim3 grid((unsigned)((nitems + 255) / 256), (unsigned)slots, (unsigned)(nrhs * p->n_problems));
   hipLaunchKernelGGL((farfield_kernel<256>), grid, dim3(256), 0, p->stream, xhat_dev, items_dev,
-                     (int64_t)ndir, (int64_t)nitems, p->d_pos, p->d_aw, p->d_ew, p->form(), p->N, n0,
-                     slots, p->k[0], (const double2*)mu, nrhs, (double2*)partial);
+                     (int64_t)ndir, (int64_t)nitems, p->d_pos, p->d_aw, p->d_ew, p->form(), p->N,
+                     pinfo_dev, p->n_problems, slots, (const double2*)mu, nrhs, (double2*)partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t count = (int64_t)ndir * nrhs;
+  const int64_t count = (int64_t)p->n_problems * ndir * nrhs;
   hipLaunchKernelGGL(reduce_slots_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
                      p->stream, (const double2*)partial, slots, count, (double2*)out, 0);
   return hipGetLastError();

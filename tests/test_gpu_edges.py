@@ -61,14 +61,14 @@ def test_largest_body(spec):
         qax.qax_self_block(P.h, 0, t)
         got = t.cpu().numpy().reshape(n, n)[rows]
         scale = np.abs(want).max(axis=1, keepdims=True)
-        assert (np.abs(got - want) / scale).max() < 2e-11
+        assert (np.abs(got - want) / scale).max() < 1e-12
         del t
         v = torch.from_numpy(mu).to(DEV)
         bv = P.vec()
         qax.qax_block_apply(P.h, 0, qax.QAX_FP64, v, bv)
         back = P.vec()
         qax.qax_block_apply(P.h, 1, qax.QAX_FP64, bv, back)
-        assert rel(back.cpu().numpy(), mu) < 1e-10
+        assert rel(back.cpu().numpy(), mu) < 1e-11
         qax.qax_block_apply(P.h, 1, qax.QAX_MIXED, bv, back)
         assert rel(back.cpu().numpy(), mu) < 1e-4
         out = P.vec()
@@ -89,7 +89,7 @@ def test_fewest_azimuths_and_single_panel():
             t = torch.zeros(n * n, dtype=torch.complex128, device=DEV)
             qax.qax_self_block(P.h, bi, t)
             got = t.cpu().numpy().reshape(n, n)[rows]
-            assert (np.abs(got - want) / np.abs(want).max(axis=1, keepdims=True)).max() < 2e-11
+            assert (np.abs(got - want) / np.abs(want).max(axis=1, keepdims=True)).max() < 1e-12
 
 
 def test_single_body_and_laplace_next_to_helmholtz():
@@ -115,6 +115,7 @@ def test_single_body_and_laplace_next_to_helmholtz():
         assert rel(out.cpu().numpy(), want) < 1e-12
         qax.qax_pair_sum(P.h, qax.QAX_MIXED, v, out)
         assert rel(out.cpu().numpy(), want) < 1e-5
+        assert np.abs(out.cpu().numpy() - want).max() < 1e-5 * np.abs(want).max()
 
 
 def test_most_right_hand_sides():

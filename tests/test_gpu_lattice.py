@@ -61,6 +61,7 @@ def test_lattice_pair_sums(dims, spacing):
             assert rel(got, want[:, :nrhs]) < 1e-12, nrhs
             got = run_pair(P, qax.QAX_MIXED, mu[:, :nrhs])
             assert rel(got, want[:, :nrhs]) < 1e-5, nrhs
+            assert np.abs(got - want[:, :nrhs]).max() < 1e-5 * np.abs(want[:, :nrhs]).max(), nrhs
         # back to the direct pair sum
         qax.qax_lattice(P.h, False)
         assert rel(run_pair(P, qax.QAX_FP64, mu[:, :3]), want[:, :3]) < 1e-12
@@ -83,6 +84,7 @@ def test_lattice_combined_field():
         qax.qax_lattice(P.h)
         assert rel(run_pair(P, qax.QAX_FP64, mu), want) < 1e-12
         assert rel(run_pair(P, qax.QAX_MIXED, mu[:, :1]), want[:, :1]) < 1e-5
+        assert np.abs(run_pair(P, qax.QAX_MIXED, mu[:, :1]) - want[:, :1]).max() < 1e-5 * np.abs(want[:, :1]).max()
 
 
 def test_lattice_example4_thousand_bodies():
@@ -102,6 +104,7 @@ def test_lattice_example4_thousand_bodies():
         assert rel(lat[tg], want_s) < 1e-12
         lat32 = run_pair(P, qax.QAX_MIXED, mu)[:, 0]
         assert rel(lat32, direct) < 1e-5
+        assert np.abs(lat32 - direct).max() < 1e-5 * np.abs(direct).max()
 
 
 @pytest.mark.parametrize("prec,tol", [(qax.QAX_FP64, 1e-10), (qax.QAX_MIXED, 1e-7)])

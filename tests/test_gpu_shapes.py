@@ -3,7 +3,7 @@ and dyadic panel refinement near the poles (N_ref of Section 6, Table 4)
 through the C interface:
 
 * nodes and area-weighted normals against the oracle (1e-13);
-* self-block rows against the oracle (2e-11 of the row maximum), including
+* self-block rows against the oracle (1e-12 of the row maximum), including
   rows in the smallest end panels, where panels two or more away are
   integrated as near panels;
 * point sources inside two conches and two spirals (artificial solutions):
@@ -77,7 +77,7 @@ def test_self_block_rows_refined(bi):
         qax.qax_self_block(P.h, bi, t)
         got = t.cpu().numpy().reshape(nb, nb)[rows]
     scale = np.abs(want).max(axis=1, keepdims=True)
-    assert (np.abs(got - want) / scale).max() < 2e-11
+    assert (np.abs(got - want) / scale).max() < 1e-12
 
 
 def artificial_error(s):

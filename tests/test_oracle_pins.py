@@ -53,6 +53,30 @@ def test_bent_volume_cavalieri_and_outward():
         assert abs(vw - v1) < 1e-12 * v1
 
 
+@pytest.mark.parametrize("c", [0.3, -0.2])
+def test_peanut_closed_forms(c):
+    # peanut of revolution, polar radius rho(psi) = a (1 + c cos 2 psi) with psi
+    # the polar angle: waist a (1 - c) at the equator, a (1 + c) at the poles;
+    # volume (2 pi / 3) int_0^pi rho^3 sin psi dpsi = (2 pi / 3) a^3 int_-1^1
+    # (A + B u^2)^3 du with A = 1 - c, B = 2 c (u = cos psi), a polynomial;
+    # area 2 pi int rho sin psi sqrt(rho^2 + rho'^2) dpsi by mpmath quadrature
+    a = 0.5
+    r, _, z, _, _, _, _, _ = geo.curve(geo.PEANUT, a, c, 0.0, np.array([0.0, 0.5 * math.pi, -0.5 * math.pi]))
+    assert abs(r[0] - a * (1 - c)) < 1e-15 and abs(z[0]) < 1e-15
+    assert abs(z[1] - a * (1 + c)) < 1e-15 and abs(z[2] + a * (1 + c)) < 1e-15
+    A, B = 1.0 - c, 2.0 * c
+    vol_ref = 2.0 * math.pi / 3.0 * a ** 3 * (2 * A ** 3 + 2 * A * A * B + 1.2 * A * B * B + 2.0 / 7.0 * B ** 3)
+    rho = lambda ps: a * (1 + c * mp.cos(2 * ps))
+    drho = lambda ps: -2 * a * c * mp.sin(2 * ps)
+    area_ref = float(2 * mp.pi * mp.quad(lambda ps: rho(ps) * mp.sin(ps) * mp.sqrt(rho(ps) ** 2 + drho(ps) ** 2),
+                                         [0, mp.pi / 2, mp.pi]))
+    d = geo.discretize_body(geo.PEANUT, a, c, 0.0, 4, 32)
+    area = np.sum(np.linalg.norm(d.n0, axis=1) * d.w)
+    vol = np.sum(np.sum(d.y0 * d.n0, axis=1) * d.w) / 3.0
+    assert abs(vol - vol_ref) < 1e-12 * vol_ref, (vol, vol_ref)
+    assert abs(area - area_ref) < 1e-12 * area_ref, (area, area_ref)
+
+
 def test_curve_differences_match_direct():
     rng = np.random.default_rng(1)
     for shape, a, c in [(geo.SPHERE, 0.5, 0.5), (geo.SPHEROID, 0.5, 1.0), (geo.PEANUT, 0.5, 0.3)]:
