@@ -223,6 +223,24 @@ qax_status qax_solve_dense(qax_problem* p, const double* dirs, int32_t nrhs, voi
 qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrhs,
                         const double* xhat, int32_t n_dirs, void* d_u_inf);
 
+/* For callers that cannot allocate (code under HIP graph or stream capture,
+ * serving loops, harnesses that forbid device allocation): qax_farfield with
+ * the directions already on the device and no allocation of any kind.
+ * d_xhat: DEVICE array, n_dirs x 3 FP64 (unit directions; not checked:
+ * non-finite entries give non-finite results); d_mu: N x nrhs; d_u_inf:
+ * n_problems x n_dirs x nrhs complex128, as qax_farfield (no antipodal
+ * pairing; the results agree with qax_farfield to rounding).  The partial
+ * sums go to a fixed 64 MiB device workspace that the library holds on each
+ * GPU until the process ends, shared by every handle and call on that GPU:
+ * calls that overlap on one GPU (several host threads, several streams) race
+ * on it and must be serialised by the caller.  Limit: n_problems * n_dirs *
+ * nrhs <= 4194304, else QAX_ERR_ARG; nrhs in [1, 256].  Needs qax_build.
+ * Enqueues the work on the handle's stream and returns WITHOUT waiting for
+ * it (unlike the other calls); the caller synchronises the stream.  Calls
+ * no hipMalloc, hipFree, pinned-host allocation or host-to-device copy. */
+qax_status qax_farfield_noalloc(qax_problem* p, const void* d_mu, int32_t nrhs, const double* d_xhat,
+                                int32_t n_dirs, void* d_u_inf);
+
 /* Scattered field at points off the surfaces: the double-layer potential of
  * the density of one problem, u(x) = sum_j dG/dn_y(x, y_j) mu_j |J_j| w_j
  * (Section 4, equation multi-double, with the smooth rule of Section 3.1,

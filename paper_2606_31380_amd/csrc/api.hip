@@ -196,6 +196,11 @@ extern "C" qax_status qax_create(int device, void* hip_stream, qax_problem** out
   if (!p) return QAX_ERR_NOMEM;
   p->device = device;
   p->stream = (hipStream_t)hip_stream;
+  // device address of the allocation-free far field's workspace on this GPU
+  if (noalloc_init(device) != hipSuccess) {
+    delete p;
+    return QAX_ERR_DEVICE;
+  }
   *out = p;
   return QAX_OK;
 }
@@ -203,12 +208,13 @@ extern "C" qax_status qax_create(int device, void* hip_stream, qax_problem** out
 static void free_geometry(qax_problem* p) {
   void* ptrs[] = {p->d_bodies, p->d_blocks, p->d_node_body, p->d_pos,  p->d_aw,
                   p->d_loc32,  p->d_aw32,   p->d_gl,        p->d_B,    p->d_Binv,
-                  p->d_Binv32, p->d_tasks64, p->d_tasks32, p->d_ew, p->d_ew32, p->d_B32};
+                  p->d_Binv32, p->d_tasks64, p->d_tasks32, p->d_ew, p->d_ew32, p->d_B32,
+                  p->d_pinfo};
   for (void* q : ptrs) dev_release(p, q);
   p->d_bodies = nullptr; p->d_blocks = nullptr; p->d_node_body = nullptr;
   p->d_pos = nullptr; p->d_aw = nullptr; p->d_loc32 = nullptr; p->d_aw32 = nullptr;
   p->d_gl = nullptr; p->d_B = nullptr; p->d_Binv = nullptr; p->d_Binv32 = nullptr;
-  p->d_B32 = nullptr;
+  p->d_B32 = nullptr; p->d_pinfo = nullptr;
   p->d_tasks64 = nullptr; p->d_tasks32 = nullptr;
   p->d_ew = nullptr; p->d_ew32 = nullptr;
   dev_release(p, p->d_gemm_tasks);
@@ -439,6 +445,15 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
   QCHECK(dev_alloc(p, (void**)&p->d_ew, sizeof(double) * N), "alloc ew");
   QCHECK(dev_alloc(p, (void**)&p->d_ew32, sizeof(float) * N), "alloc ew32");
   QCHECK(dev_alloc(p, (void**)&p->d_gl, sizeof(double) * 3 * GL_ORDER), "alloc gl");
+  QCHECK(dev_alloc(p, (void**)&p->d_pinfo, sizeof(int64_t) * (2 * n_problems + 1)), "alloc pinfo");
+  {
+    std::vector<int64_t> pinfo(2 * (size_t)n_problems + 1);
+    for (int pr = 0; pr <= n_problems; ++pr) pinfo[pr] = p->off[p->prob_body0[pr]];
+    for (int pr = 0; pr < n_problems; ++pr) std::memcpy(&pinfo[n_problems + 1 + pr], &p->k[pr], 8);
+    QCHECK(hipMemcpyAsync(p->d_pinfo, pinfo.data(), pinfo.size() * 8, hipMemcpyHostToDevice, p->stream),
+           "copy pinfo");
+    QCHECK(hipStreamSynchronize(p->stream), "sync");
+  }
   double gl[3 * GL_ORDER];   // nodes, weights, barycentric weights on [-1, 1]
   gauss_legendre_host(GL_ORDER, gl, gl + GL_ORDER);
   for (int l = 0; l < GL_ORDER; ++l) {
@@ -683,15 +698,10 @@ extern "C" qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrh
   const int nitems = (int)items.size();
   const int slots = farfield_slots((int64_t)nitems * p->n_problems, cu_count(p->device));
   const int np = p->n_problems;
-  // problems: first nodes (np + 1 int64), then their k (np doubles)
-  std::vector<int64_t> pinfo(2 * (size_t)np + 1);
-  for (int pr = 0; pr <= np; ++pr) pinfo[pr] = p->off[p->prob_body0[pr]];
-  for (int pr = 0; pr < np; ++pr) std::memcpy(&pinfo[np + 1 + pr], &p->k[pr], 8);
-  const size_t up = (size_t)n_dirs * 24 + (size_t)nitems * sizeof(int2) + pinfo.size() * 8;
+  const size_t up = (size_t)n_dirs * 24 + (size_t)nitems * sizeof(int2);
   QBUF(dx, double, "xhat", up);
   QBUF(part, double, "ff_partial", (size_t)slots * np * n_dirs * nrhs * 16);
   int2* ditems = (int2*)(dx + 3 * (size_t)n_dirs);
-  int64_t* dpinfo = (int64_t*)(ditems + nitems);
   // directions and items through pinned staging: one asynchronous copy
   if (p->h_stage_bytes < up) {
     if (p->h_stage) (void)hipHostFree(p->h_stage);
@@ -702,10 +712,8 @@ extern "C" qax_status qax_farfield(qax_problem* p, const void* d_mu, int32_t nrh
   }
   std::memcpy(p->h_stage, xhat, (size_t)n_dirs * 24);
   std::memcpy((char*)p->h_stage + (size_t)n_dirs * 24, items.data(), (size_t)nitems * sizeof(int2));
-  std::memcpy((char*)p->h_stage + (size_t)n_dirs * 24 + (size_t)nitems * sizeof(int2), pinfo.data(),
-              pinfo.size() * 8);
   QCHECK(hipMemcpyAsync(dx, p->h_stage, up, hipMemcpyHostToDevice, p->stream), "copy directions");
-  QCHECK(launch_farfield(p, (const double*)d_mu, nrhs, dx, n_dirs, ditems, nitems, dpinfo, slots, part,
+  QCHECK(launch_farfield(p, (const double*)d_mu, nrhs, dx, n_dirs, ditems, nitems, p->d_pinfo, slots, part,
                          (double*)d_u_inf),
          "farfield");
   return sync(p, "qax_farfield");

@@ -150,6 +150,7 @@ struct qax_problem {
   double* d_ew = nullptr;       // per node eta |aw| (combined field; 0 otherwise)
   float* d_ew32 = nullptr;
   double* d_gl = nullptr;       // 16 GL nodes, weights, barycentric weights on [-1, 1]
+  int64_t* d_pinfo = nullptr;   // problems' first nodes (n_problems + 1), then their k (as bits)
 
   // self blocks (complex128 / complex64 pools)
   double* d_B = nullptr;
@@ -317,6 +318,9 @@ hipError_t launch_modal_modes(hipStream_t s, int n, const double* r, const doubl
 // krylov.hip
 hipError_t launch_rhs(qax_problem* p, const double* dirs_dev, int nrhs, double* out);
 int farfield_slots(int64_t M, int cu_count);
+// the far field's allocation-free workspace: its device address on `device`
+// (current), taken once per device
+hipError_t noalloc_init(int device);
 hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const double* xhat_dev,
                            int ndir, const int2* items_dev, int nitems, const int64_t* pinfo_dev,
                            int slots, double* partial, double* out);

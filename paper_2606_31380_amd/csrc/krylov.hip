@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "fastmath.h"
 #include "internal.h"
@@ -65,7 +66,8 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
   const bool active = t < Mi;
   // direction i and, when the list holds its exact negation, that one (i2):
   // its phase is the negated phase, so sin flips sign and cos is unchanged
-  const int2 it = active ? items[t] : make_int2(0, -1);
+  // items == nullptr: one item per direction, no pairs
+  const int2 it = active ? (items ? items[t] : make_int2((int)t, -1)) : make_int2(0, -1);
   const int64_t i = it.x, i2 = it.y;
   const double pair = i2 >= 0 ? 1.0 : 0.0;
   const int r = blockIdx.z % nrhs, pr = blockIdx.z / nrhs;
@@ -138,8 +140,8 @@ int farfield_slots(int64_t M, int cu_count) {
 }
 
 // out[problem][dir][r] (directions xhat_dev, 3 doubles each; pinfo_dev as
-// the kernel's pinfo); partial: farfield_slots x n_problems x ndir x nrhs
-// complex128.
+// the kernel's pinfo; items_dev may be null: no pairs); partial:
+// farfield_slots x n_problems x ndir x nrhs complex128.
 hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const double* xhat_dev,
                            int ndir, const int2* items_dev, int nitems, const int64_t* pinfo_dev,
                            int slots, double* partial, double* out) {
@@ -422,4 +424,55 @@ void Krylov::axpby(double alpha, const double* a, double beta, const double* b, 
                      (const double2*)a, beta, (const double2*)b, N * nrhs, (double2*)out);
 }
 
+// ---------------------------------------------------------------- far field without allocation
+// Workspace of qax_farfield_noalloc: the far field's partial sums, one array
+// per GPU that holds it until the process ends, shared by every call on that
+// GPU (calls that overlap on one GPU race on it).  Its device address on each
+// GPU is taken once, by qax_create, with that GPU current; host code uses
+// that address, never the array's name.
+constexpr size_t FF_NOALLOC_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) char noalloc_scratch[FF_NOALLOC_BYTES];
+static void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+static int g_noalloc_cus[NOALLOC_MAX_DEVICES] = {};
+static std::mutex g_noalloc_mu;
+
+hipError_t noalloc_init(int device) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  if (g_noalloc_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch));
+  if (e != hipSuccess) return e;
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (e != hipSuccess) return e;
+  g_noalloc_cus[device] = cus;
+  g_noalloc_ptr[device] = ptr;
+  return hipSuccess;
+}
+
 }  // namespace qax
+
+extern "C" qax_status qax_farfield_noalloc(qax_problem* p, const void* d_mu, int32_t nrhs,
+                                           const double* d_xhat, int32_t n_dirs, void* d_u_inf) {
+  using namespace qax;
+  if (!p) return QAX_ERR_ARG;
+  if (!d_mu || !d_xhat || !d_u_inf || nrhs < 1 || nrhs > 256 || n_dirs < 1)
+    return fail(p, QAX_ERR_ARG, "qax_farfield_noalloc: null pointer, nrhs out of [1, 256] or no directions");
+  if (p->state < 1) return fail(p, QAX_ERR_STATE, "qax_farfield_noalloc: call qax_build first");
+  if (p->device < 0 || p->device >= NOALLOC_MAX_DEVICES || !g_noalloc_ptr[p->device])
+    return fail(p, QAX_ERR_DEVICE, "qax_farfield_noalloc: workspace address not set for this device");
+  const size_t per_slot = (size_t)p->n_problems * n_dirs * nrhs * 16;
+  if (per_slot > FF_NOALLOC_BYTES)
+    return fail(p, QAX_ERR_ARG,
+                "qax_farfield_noalloc: n_problems x n_dirs x nrhs exceeds the 64 MiB workspace "
+                "(at most 4194304 complex values)");
+  hipError_t e = hipSetDevice(p->device);
+  if (e != hipSuccess) return hip_check(p, e, "hipSetDevice");
+  int slots = farfield_slots((int64_t)n_dirs * p->n_problems, g_noalloc_cus[p->device]);
+  slots = (int)std::min<size_t>((size_t)slots, FF_NOALLOC_BYTES / per_slot);
+  e = launch_farfield(p, (const double*)d_mu, nrhs, d_xhat, n_dirs, nullptr, n_dirs, p->d_pinfo, slots,
+                      (double*)g_noalloc_ptr[p->device], (double*)d_u_inf);
+  return e == hipSuccess ? QAX_OK : hip_check(p, e, "qax_farfield_noalloc");
+}

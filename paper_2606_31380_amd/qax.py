@@ -53,7 +53,7 @@ EXPORTS = ["qax_create", "qax_destroy", "qax_last_error", "qax_build", "qax_size
            "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes",
            "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning", "qax_set_graphs",
            "qax_solve_rhs", "qax_nearfield", "qax_set_formulation", "qax_lattice", "qax_invert",
-           "qax_set_factorization"]
+           "qax_set_factorization", "qax_farfield_noalloc"]
 (QAX_K_PAIRSUM_FP64, QAX_K_PAIRSUM_FP32, QAX_K_BLOCK_APPLY, QAX_K_SELF_ASSEMBLY, QAX_K_INVERT,
  QAX_K_INVERT_UPDATE, QAX_K_BLOCK_APPLY_F32, QAX_K_LATTICE_F64, QAX_K_LATTICE_F32) = range(9)
 KERNEL_NAMES = ["pair_sum_fp64", "pair_sum_fp32", "block_apply", "self_assembly", "invert",
@@ -92,6 +92,7 @@ def lib():
         "qax_solve_rhs": (C.c_int, [vp, C.c_int, vp, i32, d, i32, vp, C.POINTER(qax_info)]),
         "qax_nearfield": (C.c_int, [vp, vp, i32, pd, i64, i32, vp]),
         "qax_farfield": (C.c_int, [vp, vp, i32, pd, i32, vp]),
+        "qax_farfield_noalloc": (C.c_int, [vp, vp, i32, vp, i32, vp]),
         "qax_modal_modes": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, d, i32, vp, vp]),
         "qax_set_timing": (C.c_int, [vp, i32]),
         "qax_set_graphs": (C.c_int, [vp, i32]),
@@ -242,6 +243,13 @@ def qax_invert(h, prec, orders, mats):
 def qax_farfield(h, mu, xhat, u_inf, nrhs=1):
     x = np.ascontiguousarray(xhat, dtype=np.float64)
     _check(h, lib().qax_farfield(h, _ptr(mu), int(nrhs), _dptr(x), x.shape[0], _ptr(u_inf)))
+
+
+def qax_farfield_noalloc(h, mu, d_xhat, u_inf, nrhs=1):
+    """Far field with device directions (n_dirs x 3 float64 tensor) and no
+    allocation; enqueued on the handle's stream, not waited for."""
+    _check(h, lib().qax_farfield_noalloc(h, _ptr(mu), int(nrhs), _ptr(d_xhat), int(d_xhat.shape[0]),
+                                         _ptr(u_inf)))
 
 
 def qax_modal_modes(h, r, rt, c, chim1, rmrt, k, nmax, A, B):
