@@ -37,7 +37,7 @@ KINDS = {
     "block_apply": (r"qax::block_gemv_kernel<double, 1, \d, \d+>", "paper_2606_31380_amd/csrc/dense.hip", False),
     "block_apply_f32": (r"qax::block_gemv_f32_lds_kernel<\d>", "paper_2606_31380_amd/csrc/dense.hip", False),
     "self_assembly": (r"qax::assemble_self_kernel<0>", "paper_2606_31380_amd/csrc/selfblock.hip", False),
-    "invert_update": (r"qax::gjm3_update_kernel", "paper_2606_31380_amd/csrc/dense.hip", True),
+    "invert_update": (r"qax::gjm_update_kernel<double>", "paper_2606_31380_amd/csrc/dense.hip", True),
 }
 
 

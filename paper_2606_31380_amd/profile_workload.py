@@ -1,7 +1,8 @@
-"""Fixed sequence of library calls on the 27-body lattice workload, for
-hardware-counter and kernel-trace runs under rocprofv3:
+"""Fixed sequence of library calls on one benchmark workload (the 1000-body
+workload by default, or the 27-body lattice), for hardware-counter and
+kernel-trace runs under rocprofv3:
 
-    rocprofv3 --pmc FETCH_SIZE -d out -- python3 -m paper_2606_31380_amd.profile_workload [tune_cache]
+    rocprofv3 --pmc FETCH_SIZE -d out -- python3 -m paper_2606_31380_amd.profile_workload [tune_cache [workload]]
 
 It first runs one plain elementwise kernel of known traffic (y = 2 x over
 2^27 doubles: 1 GiB read, 1 GiB written) so that the memory counters can be
@@ -20,7 +21,7 @@ import sys
 import numpy as np
 
 
-def main(tune_cache=None) -> int:
+def main(tune_cache=None, workload="random_mixed") -> int:
     import torch
 
     from paper_2606_31380_amd import qax
@@ -36,7 +37,7 @@ def main(tune_cache=None) -> int:
     print(f"copy calibration: {n_copy * 8} bytes read, {n_copy * 8} bytes written", flush=True)
     del x, y
 
-    scen = sc.lattice27()
+    scen = sc.WORKLOADS[workload]()
     h = qax.qax_create(0, torch.cuda.current_stream(dev).cuda_stream)
     try:
         qax.qax_build(h, scen.bodies, scen.k)
@@ -81,4 +82,5 @@ def main(tune_cache=None) -> int:
 
 
 if __name__ == "__main__":
-    sys.exit(main(sys.argv[1] if len(sys.argv) > 1 else None))
+    sys.exit(main(sys.argv[1] if len(sys.argv) > 1 and sys.argv[1] != "-" else None,
+                  sys.argv[2] if len(sys.argv) > 2 else "random_mixed"))
