@@ -187,6 +187,21 @@ qax_status qax_rhs(qax_problem* p, const double* dirs, int32_t nrhs, void* d_out
 qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dirs, int32_t nrhs,
                      double tol, int32_t maxit, void* d_mu_out, qax_info* info);
 
+/* Solver for several right-hand sides (qax_solve and qax_solve_rhs with
+ * nrhs > 1).  QAX_SOLVER_LOCKSTEP (default): an independent GMRES run per
+ * right-hand side and problem, all advancing together and sharing each
+ * operator apply.  QAX_SOLVER_BLOCK: block GMRES, one Krylov space shared by
+ * the nrhs right-hand sides (block Arnoldi with block Gram-Schmidt twice and
+ * Cholesky QR twice, the block Hessenberg least-squares problem by
+ * Householder reflections, restart after 40 block steps, right
+ * preconditioning with the block-diagonal preconditioner of Section 6;
+ * QAX_MIXED as FP64 iterative refinement around FP32 inner cycles); handles
+ * with one problem and at most 64 right-hand sides (else QAX_ERR_ARG at
+ * solve time).  One right-hand side always uses the lockstep solver.
+ * Errors: QAX_ERR_ARG. */
+typedef enum { QAX_SOLVER_LOCKSTEP = 0, QAX_SOLVER_BLOCK = 1 } qax_solver;
+qax_status qax_set_solver(qax_problem* p, int32_t solver);
+
 /* As qax_solve with the right-hand side given by the caller instead of plane
  * waves: d_rhs (device, N x nrhs complex128, not aliasing d_mu_out), e.g. the
  * boundary values of a known radiating field (the artificial solutions of

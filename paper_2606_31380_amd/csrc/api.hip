@@ -1466,10 +1466,304 @@ extern "C" qax_status qax_set_tuning(qax_problem* p, const qax_tuning_info* in) 
   return QAX_OK;
 }
 
+// ---------------------------------------------------------------- block GMRES
+// One Krylov space for all right-hand sides of a problem (block size p =
+// nrhs): block Arnoldi with classical block Gram-Schmidt twice and a
+// Cholesky QR done twice for the new block, the block upper Hessenberg
+// least-squares problem min ||E1 R0 - Hbar Y|| by Householder reflections on
+// the host (one reflection of length p + 1 per column), restarted, right
+// preconditioned like the lockstep solver; QAX_MIXED is again FP64 iterative
+// refinement around an inner cycle with the FP32 operator.
+
+// G = R^H R for Hermitian G (p x p, row-major); R upper triangular.  False
+// when a pivot is not positive beyond the rounding of its column.
+static bool chol_upper(const std::vector<cplx>& G, int p, std::vector<cplx>& R) {
+  R.assign((size_t)p * p, 0.0);
+  for (int j = 0; j < p; ++j) {
+    cplx s = G[(size_t)j * p + j];
+    for (int k = 0; k < j; ++k) s -= std::conj(R[(size_t)k * p + j]) * R[(size_t)k * p + j];
+    const double d = s.real();
+    if (!(d > 1e-26 * std::max(G[(size_t)j * p + j].real(), 1e-300))) return false;
+    const double r = std::sqrt(d);
+    R[(size_t)j * p + j] = r;
+    for (int i = j + 1; i < p; ++i) {
+      cplx t = G[(size_t)j * p + i];
+      for (int k = 0; k < j; ++k) t -= std::conj(R[(size_t)k * p + j]) * R[(size_t)k * p + i];
+      R[(size_t)j * p + i] = t / r;
+    }
+  }
+  return true;
+}
+
+// Inverse of an upper triangular p x p matrix (row-major).
+static std::vector<cplx> inv_upper(const std::vector<cplx>& R, int p) {
+  std::vector<cplx> X((size_t)p * p, 0.0);
+  for (int c = 0; c < p; ++c) {
+    X[(size_t)c * p + c] = 1.0 / R[(size_t)c * p + c];
+    for (int r = c - 1; r >= 0; --r) {
+      cplx t = 0.0;
+      for (int k = r + 1; k <= c; ++k) t += R[(size_t)r * p + k] * X[(size_t)k * p + c];
+      X[(size_t)r * p + c] = -t / R[(size_t)r * p + r];
+    }
+  }
+  return X;
+}
+
+// Least-squares state of a block GMRES cycle: the block Hessenberg matrix
+// (column-major, (m + 1) p rows), the transformed right-hand side E1 R0, and
+// one Householder reflection per column acting on rows c .. c + p.
+struct BlockLS {
+  int p = 0, m = 0, rows = 0;
+  std::vector<cplx> H, G, V, tau;
+  void init(int p_, int m_, const std::vector<cplx>& R0) {
+    p = p_;
+    m = m_;
+    rows = (m + 1) * p;
+    H.assign((size_t)rows * m * p, 0.0);
+    G.assign((size_t)rows * p, 0.0);
+    V.assign((size_t)m * p * (p + 1), 0.0);
+    tau.assign((size_t)m * p, 0.0);
+    for (int b = 0; b < p; ++b)
+      for (int a = 0; a < p; ++a) G[(size_t)a * rows + b] = R0[(size_t)b * p + a];
+  }
+  // y <- (I - conj(tau_c) v_c v_c^H) y on rows c .. c + p of a column
+  void reflect(int c, cplx* y) const {
+    const cplx* v = &V[(size_t)c * (p + 1)];
+    cplx w = 0.0;
+    for (int t = 0; t <= p; ++t) w += std::conj(v[t]) * y[c + t];
+    w *= std::conj(tau[c]);
+    for (int t = 0; t <= p; ++t) y[c + t] -= w * v[t];
+  }
+  // block column j from blocks hblk[i][b][a] (i <= j + 1); res: residual
+  // norm of every right-hand side after the step
+  void add_column(int j, const std::vector<cplx>& hblk, std::vector<double>& res) {
+    for (int a = 0; a < p; ++a) {
+      cplx* col = &H[(size_t)(j * p + a) * rows];
+      for (int r = 0; r < (j + 2) * p; ++r) col[r] = hblk[(size_t)(r / p) * p * p + (size_t)(r % p) * p + a];
+      for (int c = 0; c < j * p; ++c) reflect(c, col);
+    }
+    for (int a = 0; a < p; ++a) {
+      const int c = j * p + a;
+      cplx* col = &H[(size_t)c * rows];
+      // reflection with (I - tau v v^H)^H (alpha, x) = (beta, 0), beta real
+      const cplx alpha = col[c];
+      double xn2 = 0.0;
+      for (int t = 1; t <= p; ++t) xn2 += std::norm(col[c + t]);
+      cplx* v = &V[(size_t)c * (p + 1)];
+      v[0] = 1.0;
+      if (xn2 == 0.0 && alpha.imag() == 0.0) {
+        tau[c] = 0.0;
+        for (int t = 1; t <= p; ++t) v[t] = 0.0;
+      } else {
+        const double beta = -std::copysign(std::sqrt(std::norm(alpha) + xn2), alpha.real());
+        tau[c] = (beta - alpha) / beta;
+        const cplx scl = 1.0 / (alpha - beta);
+        for (int t = 1; t <= p; ++t) v[t] = col[c + t] * scl;
+        col[c] = beta;
+        for (int t = 1; t <= p; ++t) col[c + t] = 0.0;
+      }
+      for (int a2 = a + 1; a2 < p; ++a2) reflect(c, &H[(size_t)(j * p + a2) * rows]);
+      for (int r = 0; r < p; ++r) reflect(c, &G[(size_t)r * rows]);
+    }
+    res.assign(p, 0.0);
+    for (int r = 0; r < p; ++r) {
+      double s2 = 0.0;
+      for (int t = 0; t < p; ++t) s2 += std::norm(G[(size_t)r * rows + (j + 1) * p + t]);
+      res[r] = std::sqrt(s2);
+    }
+  }
+  // Y (k p x p, row-major) = T^-1 G[0 .. k p) with T the leading triangle
+  void solve(int k, std::vector<cplx>& Y) const {
+    const int n = k * p;
+    Y.assign((size_t)n * p, 0.0);
+    for (int r = 0; r < p; ++r) {
+      for (int i = n - 1; i >= 0; --i) {
+        cplx t = G[(size_t)r * rows + i];
+        for (int c = i + 1; c < n; ++c) t -= H[(size_t)c * rows + i] * Y[(size_t)c * p + r];
+        Y[(size_t)i * p + r] = t / H[(size_t)i * rows + i];
+      }
+    }
+  }
+};
+
+static qax_status solve_block(qax_problem* p, qax_prec prec, const double* dirs, const double* d_rhs,
+                              int32_t nrhs, double tol, int32_t maxit, void* d_mu_out, qax_info* info) {
+  qax_status st = check_vec_call(p, dirs ? (const void*)dirs : (const void*)d_rhs, d_mu_out, nrhs, 2);
+  if (st != QAX_OK) return st;
+  if (prec != QAX_FP64 && prec != QAX_MIXED) return fail(p, QAX_ERR_ARG, "bad precision");
+  if (!(tol > 0) || !is_finite(tol) || maxit < 1) return fail(p, QAX_ERR_ARG, "qax_solve: bad tol / maxit");
+  if (p->n_problems != 1) return fail(p, QAX_ERR_ARG, "block GMRES solves one problem per handle");
+  if (nrhs > 64) return fail(p, QAX_ERR_ARG, "block GMRES takes at most 64 right-hand sides");
+  QCHECK(hipSetDevice(p->device), "hipSetDevice");
+  QCHECK(hipStreamSynchronize(p->stream), "sync");
+  if (prec == QAX_FP64 && (st = ensure_inverse64(p)) != QAX_OK) return st;
+  auto t0 = std::chrono::steady_clock::now();
+  const int P = nrhs;
+  const int64_t N = p->N;
+  const int64_t vs = N * P * 2;   // doubles per block
+  const int m = std::min<int>(maxit, 40);
+  Krylov K;
+  st = setup_krylov(p, P, m, K);
+  if (st != QAX_OK) return st;
+  QBUF(V, double, "bk_V", (size_t)(m + 1) * vs * 8);
+  QBUF(W, double, "kry_w", (size_t)vs * 8);
+  QBUF(T, double, "kry_t", (size_t)vs * 8);
+  QBUF(R, double, "kry_r", (size_t)vs * 8);
+  QBUF(B, double, "kry_b", (size_t)vs * 8);
+  QBUF(hd, double, "bk_h", (size_t)(m + 1) * P * P * 16);
+  QBUF(cd, double, "bk_c", (size_t)(m + 1) * P * P * 16);
+  QBUF(dpart, double, "bk_dots", block_dots_work_bytes(N, m + 1));
+  const int inner_prec = prec;
+  QBUF(ppart, double, "pair_partial",
+       std::max(pair_work_bytes(p, inner_prec, P), pair_work_bytes(p, QAX_FP64, P)));
+  double* X = (double*)d_mu_out;
+  if (dirs) {
+    double* dd = nullptr;
+    st = upload_dirs(p, dirs, P, &dd);
+    if (st != QAX_OK) return st;
+    QCHECK(launch_rhs(p, dd, P, B), "rhs");
+  } else {
+    QCHECK(hipMemcpyAsync(B, d_rhs, (size_t)vs * 8, hipMemcpyDeviceToDevice, p->stream), "copy rhs");
+  }
+  QCHECK(hipMemsetAsync(X, 0, (size_t)vs * 8, p->stream), "zero x");
+  std::vector<cplx> hh((size_t)(m + 1) * P * P);
+  // Gram matrix of a block (or nb blocks against w) to the host
+  auto gram = [&](const double* Vb, int nb, const double* w) -> qax_status {
+    QCHECK(launch_block_dots(p->stream, Vb, vs, nb, w, N, P, dpart, hd), "block dots");
+    QCHECK(hipMemcpyAsync(hh.data(), hd, (size_t)nb * P * P * 16, hipMemcpyDeviceToHost, p->stream),
+           "copy h");
+    return sync(p, "block gmres");
+  };
+  auto upload_c = [&](const std::vector<cplx>& c) -> qax_status {
+    QCHECK(hipMemcpyAsync(cd, c.data(), c.size() * 16, hipMemcpyHostToDevice, p->stream), "copy c");
+    return QAX_OK;
+  };
+  // Cholesky QR twice: src (N x P) = dst Rq, dst orthonormal; false on
+  // numerical rank deficiency
+  std::vector<cplx> Gm, R1, R2, Rq;
+  auto cholqr2 = [&](const double* src, double* dst, bool* ok) -> qax_status {
+    *ok = false;
+    qax_status s2 = gram(src, 1, src);
+    if (s2 != QAX_OK) return s2;
+    Gm.assign(hh.begin(), hh.begin() + (size_t)P * P);
+    if (!chol_upper(Gm, P, R1)) return QAX_OK;
+    if ((s2 = upload_c(inv_upper(R1, P))) != QAX_OK) return s2;
+    QCHECK(launch_block_update(p->stream, src, vs, 1, cd, P, N, 1.0, 0.0, nullptr, T), "block update");
+    if ((s2 = gram(T, 1, T)) != QAX_OK) return s2;
+    Gm.assign(hh.begin(), hh.begin() + (size_t)P * P);
+    if (!chol_upper(Gm, P, R2)) return QAX_OK;
+    if ((s2 = upload_c(inv_upper(R2, P))) != QAX_OK) return s2;
+    QCHECK(launch_block_update(p->stream, T, vs, 1, cd, P, N, 1.0, 0.0, nullptr, dst), "block update");
+    Rq.assign((size_t)P * P, 0.0);
+    for (int r = 0; r < P; ++r)
+      for (int c = r; c < P; ++c) {
+        cplx t = 0.0;
+        for (int k = r; k <= c; ++k) t += R2[(size_t)r * P + k] * R1[(size_t)k * P + c];
+        Rq[(size_t)r * P + c] = t;
+      }
+    *ok = true;
+    return QAX_OK;
+  };
+
+  std::vector<double> bn(P), rn(P), need(P), res;
+  if ((st = gram(B, 1, B)) != QAX_OK) return st;
+  for (int c = 0; c < P; ++c) bn[c] = std::sqrt(std::max(hh[(size_t)c * P + c].real(), 0.0));
+  int total_its = 0, outer = 0;
+  double relres = 1.0;
+  qax_status result = QAX_ERR_NOCONV;
+  BlockLS ls;
+  std::vector<cplx> hblk, Y;
+  while (true) {
+    if (outer == 0) {
+      QCHECK(hipMemcpyAsync(R, B, (size_t)vs * 8, hipMemcpyDeviceToDevice, p->stream), "copy");
+    } else {
+      st = apply_full(p, QAX_FP64, X, W, P);
+      if (st != QAX_OK) return st;
+      K.axpby(1.0, B, -1.0, W, R);
+    }
+    if ((st = gram(R, 1, R)) != QAX_OK) return st;
+    relres = 0.0;
+    bool done = true;
+    for (int c = 0; c < P; ++c) {
+      rn[c] = std::sqrt(std::max(hh[(size_t)c * P + c].real(), 0.0));
+      const double rel = bn[c] > 0 ? rn[c] / bn[c] : 0.0;
+      relres = std::max(relres, rel);
+      done = done && rel <= tol;
+    }
+    if (done) {
+      result = QAX_OK;
+      break;
+    }
+    if (total_its >= maxit) break;
+    const double floor32 = p->factor_prec == QAX_FP64 ? 2e-7 : 2e-5;
+    for (int c = 0; c < P; ++c) {
+      const double nd = rn[c] > 0 ? 0.5 * tol * bn[c] / rn[c] : 1.0;
+      need[c] = prec == QAX_MIXED ? std::max(nd, floor32) : nd;
+    }
+    bool ok = false;
+    if ((st = cholqr2(R, V, &ok)) != QAX_OK) return st;
+    if (!ok) return fail(p, QAX_ERR_NOCONV, "block GMRES: residual block of numerically deficient rank");
+    ls.init(P, m, Rq);
+    int k = 0;
+    for (int j = 0; j < m && total_its < maxit; ++j) {
+      double* Vj = V + (size_t)j * vs;
+      QCHECK(launch_block_apply(p, 1, inner_prec, Vj, T, P, false), "block apply");
+      QCHECK(launch_pair_sum(p, inner_prec, T, W, P, ppart, false), "pair sum");
+      K.axpby(1.0, W, 1.0, Vj, W);
+      // block Gram-Schmidt twice against V_0 .. V_j
+      hblk.assign((size_t)(j + 2) * P * P, 0.0);
+      for (int pass = 0; pass < 2; ++pass) {
+        if ((st = gram(V, j + 1, W)) != QAX_OK) return st;
+        for (size_t e = 0; e < (size_t)(j + 1) * P * P; ++e) hblk[e] += hh[e];
+        QCHECK(launch_block_update(p->stream, V, vs, j + 1, hd, P, N, -1.0, 1.0, W, W), "block update");
+      }
+      ++total_its;
+      k = j + 1;
+      bool okq = false;
+      if ((st = cholqr2(W, V + (size_t)(j + 1) * vs, &okq)) != QAX_OK) return st;
+      if (okq)
+        for (int r = 0; r < P; ++r)
+          for (int c = 0; c < P; ++c) hblk[(size_t)(j + 1) * P * P + (size_t)r * P + c] = Rq[(size_t)r * P + c];
+      ls.add_column(j, hblk, res);
+      bool conv = true;
+      for (int c = 0; c < P; ++c) conv = conv && res[c] <= need[c] * rn[c];
+      if (conv || !okq) break;   // converged, or the new block is in the span
+    }
+    // d = M^-1 V Y;  x += d
+    ls.solve(k, Y);
+    if ((st = upload_c(Y)) != QAX_OK) return st;
+    QCHECK(launch_block_update(p->stream, V, vs, k, cd, P, N, 1.0, 0.0, nullptr, T), "block combine");
+    QCHECK(launch_block_apply(p, 1, inner_prec, T, X, P, true), "precond");
+    ++outer;
+  }
+  if ((st = sync(p, "qax_solve")) != QAX_OK) return st;
+  auto t1 = std::chrono::steady_clock::now();
+  if (info) {
+    info->iters = total_its;
+    info->outer_iters = outer;
+    info->rel_res = relres;
+    info->t_setup_s = 0.0;
+    info->t_solve_s = std::chrono::duration<double>(t1 - t0).count();
+  }
+  if (result != QAX_OK)
+    return fail(p, QAX_ERR_NOCONV, "qax_solve: tolerance not reached within maxit iterations");
+  return QAX_OK;
+}
+
+extern "C" qax_status qax_set_solver(qax_problem* p, int32_t solver) {
+  if (!p) return QAX_ERR_ARG;
+  if (solver != QAX_SOLVER_LOCKSTEP && solver != QAX_SOLVER_BLOCK)
+    return fail(p, QAX_ERR_ARG, "qax_set_solver: QAX_SOLVER_LOCKSTEP or QAX_SOLVER_BLOCK");
+  p->solver = solver;
+  return QAX_OK;
+}
+
 extern "C" qax_status qax_solve(qax_problem* p, qax_prec prec, const double* dirs, int32_t nrhs,
                                 double tol, int32_t maxit, void* d_mu_out, qax_info* info) {
   if (!p) return QAX_ERR_ARG;
   if (!dirs) return fail(p, QAX_ERR_ARG, "qax_solve: null directions");
+  if (p->solver == QAX_SOLVER_BLOCK && nrhs > 1)
+    return solve_block(p, prec, dirs, nullptr, nrhs, tol, maxit, d_mu_out, info);
   return solve_core(p, prec, dirs, nullptr, nrhs, tol, maxit, d_mu_out, info);
 }
 
@@ -1478,5 +1772,7 @@ extern "C" qax_status qax_solve_rhs(qax_problem* p, qax_prec prec, const void* d
   if (!p) return QAX_ERR_ARG;
   if (!d_rhs) return fail(p, QAX_ERR_ARG, "qax_solve_rhs: null right-hand side");
   if (d_rhs == d_mu_out) return fail(p, QAX_ERR_ARG, "qax_solve_rhs: rhs and solution must not alias");
+  if (p->solver == QAX_SOLVER_BLOCK && nrhs > 1)
+    return solve_block(p, prec, nullptr, (const double*)d_rhs, nrhs, tol, maxit, d_mu_out, info);
   return solve_core(p, prec, nullptr, (const double*)d_rhs, nrhs, tol, maxit, d_mu_out, info);
 }

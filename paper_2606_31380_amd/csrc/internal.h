@@ -160,6 +160,7 @@ struct qax_problem {
   // FP64 inverse, rounded to FP32 for the mixed path) or QAX_MIXED (B rounded
   // to FP32 and inverted in FP32; the FP64 inverse made on first use)
   int factor_prec = QAX_FP64;
+  int solver = QAX_SOLVER_LOCKSTEP;   // several right-hand sides: lockstep or block GMRES
   float* d_Binv32 = nullptr;
   float* d_B32 = nullptr;       // B rounded to FP32 (the mixed path's operator blocks)
 
@@ -318,6 +319,17 @@ hipError_t launch_modal_modes(hipStream_t s, int n, const double* r, const doubl
 // krylov.hip
 hipError_t launch_rhs(qax_problem* p, const double* dirs_dev, int nrhs, double* out);
 int farfield_slots(int64_t M, int cu_count);
+// block GMRES products over N x p blocks (p <= 64, node-major, columns
+// fastest; vstride: doubles between consecutive blocks):
+// out[i][b][a] = sum_n conj(V_i[n][b]) W[n][a] for i < nb (partial:
+// block_dots_work_bytes(N, nb)), and
+// out = beta base + alpha sum_i V_i C_i (C: nb x p x p, row-major p x p each)
+size_t block_dots_work_bytes(int64_t N, int nb_max);
+hipError_t launch_block_dots(hipStream_t s, const double* V, int64_t vstride, int nb, const double* W,
+                             int64_t N, int p, double* partial, double* out);
+hipError_t launch_block_update(hipStream_t s, const double* V, int64_t vstride, int nb, const double* C,
+                               int p, int64_t N, double alpha, double beta, const double* base,
+                               double* out);
 // the far field's allocation-free workspace: its device address on `device`
 // (current), taken once per device
 hipError_t noalloc_init(int device);

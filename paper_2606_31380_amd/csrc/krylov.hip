@@ -424,6 +424,183 @@ void Krylov::axpby(double alpha, const double* a, double beta, const double* b, 
                      (const double2*)a, beta, (const double2*)b, N * nrhs, (double2*)out);
 }
 
+// ---------------------------------------------------------------- block Krylov products
+// Blocks of the block GMRES basis: N x p complex matrices stored node-major
+// with the p columns (right-hand sides) fastest, p <= 64.
+//
+// partial[chunk][i][b][a] = sum_{n in chunk} conj(V_i[n][b]) W[n][a] for the
+// nb blocks V_i = V + i vstride.  A workgroup takes one block i and one chunk
+// of rows; each thread owns a 4 x 4 tile of (b, a); rows pass through LDS 16
+// at a time.
+constexpr int BK_P = 64;
+constexpr int BK_KT = 16;
+
+__global__ __launch_bounds__(256) void block_dots_kernel(const double2* __restrict__ V, int64_t vstride,
+                                                         const double2* __restrict__ W, int64_t N, int p,
+                                                         int64_t rows_per_chunk, double2* __restrict__ partial) {
+  const int tid = threadIdx.x, tb = tid >> 4, ta = tid & 15;
+  const int i = blockIdx.y, chunk = blockIdx.x, nb = gridDim.y;
+  const double2* Vi = V + (int64_t)i * vstride / 2;
+  const int64_t k0 = (int64_t)chunk * rows_per_chunk, k1 = min(N, k0 + rows_per_chunk);
+  __shared__ double2 sV[BK_KT][BK_P];
+  __shared__ double2 sW[BK_KT][BK_P];
+  double ar[4][4], ai[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) ar[x][y] = ai[x][y] = 0.0;
+  for (int64_t base = k0; base < k1; base += BK_KT) {
+    __syncthreads();
+    for (int e = tid; e < BK_KT * BK_P; e += 256) {
+      const int kk = e / BK_P, c = e % BK_P;
+      const int64_t n = base + kk;
+      const bool ok = n < k1 && c < p;
+      sV[kk][c] = ok ? Vi[n * p + c] : make_double2(0.0, 0.0);
+      sW[kk][c] = ok ? W[n * p + c] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < BK_KT; ++kk) {
+      double2 v[4], w[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) v[x] = sV[kk][tb * 4 + x];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) w[y] = sW[kk][ta * 4 + y];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          // conj(v) w
+          ar[x][y] = fma(v[x].x, w[y].x, fma(v[x].y, w[y].y, ar[x][y]));
+          ai[x][y] = fma(v[x].x, w[y].y, fma(-v[x].y, w[y].x, ai[x][y]));
+        }
+    }
+  }
+  double2* out = partial + ((int64_t)chunk * nb + i) * BK_P * BK_P;
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) out[(tb * 4 + x) * BK_P + ta * 4 + y] = make_double2(ar[x][y], ai[x][y]);
+}
+
+// out[i][b][a] = sum over chunks of partial (a fixed order), b, a < p.
+__global__ void block_dots_reduce_kernel(const double2* __restrict__ partial, int nchunks, int nb, int p,
+                                         double2* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nb * p * p;
+  if (e >= total) return;
+  const int i = (int)(e / (p * p)), b = (int)(e / p % p), a = (int)(e % p);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int c = 0; c < nchunks; ++c) {
+    const double2 v = partial[((int64_t)c * nb + i) * BK_P * BK_P + b * BK_P + a];
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  out[e] = acc;
+}
+
+// out[n][a] = beta base[n][a] + alpha sum_{i < nb} sum_b V_i[n][b] C[i][b][a]
+// (C: nb x p x p, row b, column a; base may be out or null when beta = 0).
+// A workgroup takes 64 rows and all p columns; each thread a 4 x 4 tile of
+// (row, column); the products' inner index passes through LDS 16 at a time.
+__global__ __launch_bounds__(256) void block_update_kernel(const double2* __restrict__ V, int64_t vstride,
+                                                           int nb, const double2* __restrict__ C, int p,
+                                                           int64_t N, double alpha, double beta,
+                                                           const double2* base, double2* out) {
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  __shared__ double2 sV[64][BK_KT + 1];
+  __shared__ double2 sC[BK_KT][BK_P];
+  double sr[4][4], si[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) sr[x][y] = si[x][y] = 0.0;
+  const int K = nb * p;
+  for (int k0 = 0; k0 < K; k0 += BK_KT) {
+    __syncthreads();
+    for (int e = tid; e < 64 * BK_KT; e += 256) {
+      const int r = e / BK_KT, kk = e % BK_KT;
+      const int k = k0 + kk;
+      const int64_t n = r0 + r;
+      double2 v = make_double2(0.0, 0.0);
+      if (k < K && n < N) {
+        const int i = k / p, b = k % p;
+        v = V[(int64_t)i * vstride / 2 + n * p + b];
+      }
+      sV[r][kk] = v;
+    }
+    for (int e = tid; e < BK_KT * BK_P; e += 256) {
+      const int kk = e / BK_P, a = e % BK_P;
+      const int k = k0 + kk;
+      sC[kk][a] = (k < K && a < p) ? C[(int64_t)k * p + a] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < BK_KT; ++kk) {
+      double2 v[4], c[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) v[x] = sV[tr * 4 + x][kk];
+#pragma unroll
+      for (int y = 0; y < 4; ++y) c[y] = sC[kk][tc * 4 + y];
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          sr[x][y] = fma(v[x].x, c[y].x, fma(-v[x].y, c[y].y, sr[x][y]));
+          si[x][y] = fma(v[x].x, c[y].y, fma(v[x].y, c[y].x, si[x][y]));
+        }
+    }
+  }
+#pragma unroll
+  for (int x = 0; x < 4; ++x) {
+    const int64_t n = r0 + tr * 4 + x;
+    if (n >= N) continue;
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+      const int a = tc * 4 + y;
+      if (a >= p) continue;
+      double2 o = make_double2(alpha * sr[x][y], alpha * si[x][y]);
+      if (beta != 0.0) {
+        const double2 b0 = base[n * p + a];
+        o.x = fma(beta, b0.x, o.x);
+        o.y = fma(beta, b0.y, o.y);
+      }
+      out[n * p + a] = o;
+    }
+  }
+}
+
+// chunks x blocks <= ceil(1024 / nb) nb <= 1024 + nb_max for every nb <= nb_max
+size_t block_dots_work_bytes(int64_t N, int nb_max) {
+  const int64_t cells = std::min<int64_t>((N + 1023) / 1024 * nb_max, 1024 + (int64_t)nb_max);
+  return (size_t)std::max<int64_t>(cells, nb_max) * BK_P * BK_P * 16;
+}
+
+hipError_t launch_block_dots(hipStream_t s, const double* V, int64_t vstride, int nb, const double* W,
+                             int64_t N, int p, double* partial, double* out) {
+  // enough chunks for about 1024 workgroups, at least 1024 rows each
+  const int64_t nch = std::max<int64_t>(1, std::min<int64_t>((N + 1023) / 1024, (1024 + nb - 1) / nb));
+  const int64_t rows = (N + nch - 1) / nch;
+  hipLaunchKernelGGL(block_dots_kernel, dim3((unsigned)nch, (unsigned)nb), dim3(256), 0, s,
+                     (const double2*)V, vstride, (const double2*)W, N, p, rows, (double2*)partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)nb * p * p;
+  hipLaunchKernelGGL(block_dots_reduce_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                     (const double2*)partial, (int)nch, nb, p, (double2*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_update(hipStream_t s, const double* V, int64_t vstride, int nb, const double* C,
+                               int p, int64_t N, double alpha, double beta, const double* base,
+                               double* out) {
+  hipLaunchKernelGGL(block_update_kernel, dim3((unsigned)((N + 63) / 64)), dim3(256), 0, s,
+                     (const double2*)V, vstride, nb, (const double2*)C, p, N, alpha, beta,
+                     (const double2*)base, (double2*)out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- far field without allocation
 // Workspace of qax_farfield_noalloc: the far field's partial sums, one array
 // per GPU that holds it until the process ends, shared by every call on that

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libqax.so")
 QAX_OK, QAX_ERR_ARG, QAX_ERR_DEVICE, QAX_ERR_NOMEM, QAX_ERR_NOCONV, QAX_ERR_STATE = range(6)
 QAX_FP64, QAX_MIXED = 0, 1
 QAX_DOUBLE_LAYER, QAX_COMBINED_FIELD, QAX_SINGLE_LAYER = 0, 1, 2
+QAX_SOLVER_LOCKSTEP, QAX_SOLVER_BLOCK = 0, 1
 STATUS_NAMES = {0: "QAX_OK", 1: "QAX_ERR_ARG", 2: "QAX_ERR_DEVICE", 3: "QAX_ERR_NOMEM",
                 4: "QAX_ERR_NOCONV", 5: "QAX_ERR_STATE"}
 
@@ -53,7 +54,7 @@ EXPORTS = ["qax_create", "qax_destroy", "qax_last_error", "qax_build", "qax_size
            "qax_rhs", "qax_solve", "qax_solve_dense", "qax_farfield", "qax_modal_modes",
            "qax_set_timing", "qax_timing", "qax_autotune", "qax_tuning", "qax_set_tuning", "qax_set_graphs",
            "qax_solve_rhs", "qax_nearfield", "qax_set_formulation", "qax_lattice", "qax_invert",
-           "qax_set_factorization", "qax_farfield_noalloc"]
+           "qax_set_factorization", "qax_farfield_noalloc", "qax_set_solver"]
 (QAX_K_PAIRSUM_FP64, QAX_K_PAIRSUM_FP32, QAX_K_BLOCK_APPLY, QAX_K_SELF_ASSEMBLY, QAX_K_INVERT,
  QAX_K_INVERT_UPDATE, QAX_K_BLOCK_APPLY_F32, QAX_K_LATTICE_F64, QAX_K_LATTICE_F32) = range(9)
 KERNEL_NAMES = ["pair_sum_fp64", "pair_sum_fp32", "block_apply", "self_assembly", "invert",
@@ -98,6 +99,7 @@ def lib():
         "qax_set_graphs": (C.c_int, [vp, i32]),
         "qax_set_formulation": (C.c_int, [vp, i32, C.c_double]),
         "qax_set_factorization": (C.c_int, [vp, C.c_int]),
+        "qax_set_solver": (C.c_int, [vp, i32]),
         "qax_lattice": (C.c_int, [vp, i32, C.POINTER(i32)]),
         "qax_timing": (C.c_int, [vp, i32, C.POINTER(i64), pd]),
         "qax_autotune": (C.c_int, [vp, i32, C.c_char_p]),
@@ -279,6 +281,12 @@ def qax_set_factorization(h, prec):
     """QAX_FP64 (default): FP64 inverse, rounded to FP32 for the mixed path;
     QAX_MIXED: inverse computed in FP32."""
     _check(h, lib().qax_set_factorization(h, int(prec)))
+
+
+def qax_set_solver(h, solver):
+    """QAX_SOLVER_LOCKSTEP (default) or QAX_SOLVER_BLOCK (block GMRES) for
+    several right-hand sides."""
+    _check(h, lib().qax_set_solver(h, int(solver)))
 
 
 def qax_set_timing(h, enable=True):
