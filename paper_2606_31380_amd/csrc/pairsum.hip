@@ -420,7 +420,9 @@ __global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slo
 // chunks of at most 64 nodes of one body (a chunk ends at a body's last
 // node), staged twice over in LDS; at step s lane l meets source
 // (l + s) mod 64 (index l + s), so the 64 lanes of a wavefront see 64
-// distinct sources at every step.  The target-side sums stay in registers.
+// distinct sources at every step.  A chunk of at most 32 sources (the end of
+// a body part; node counts are multiples of 32) takes 32 steps with each
+// source in two slots l and l + 32, whose sums are added at the end.  The target-side sums stay in registers.
 // The source-side sums travel with their source: each step adds lane l + 1's
 // running sums to lane l's contribution with a DPP wavefront rotation fused
 // into the add, so after the chunk lane l holds those of source
@@ -460,22 +462,24 @@ __device__ __forceinline__ bool sym_inactive(const SymSuper& T, const int32_t* _
 }
 
 // FP32 reciprocal pair sum.  Coordinates are local to each body: x_i = c_a +
-// x', y_j = c_b + y', C = c_b - c_a.  With m = 2 (C - x') and
-// Q_i = |x'|^2 - 2 C.x' per target and chunk,
-//   num = r^2 - |C|^2 = m.y' + |y'|^2 + Q_i
-// carries no cancellation against |C|^2, delta = r - |C| = num / (r + |C|),
-// and the phase in revolutions is frac(k |C| / 2 pi) (from FP64, per target
-// and chunk) + k delta / 2 pi, so FP32 rounding enters relative to delta, not
-// to r.  Distances are scaled by kappa = 2 pi / k: r_s^2 = kappa^2 (|C|^2 +
-// num), irs = 1 / r_s and rcp(r_s^2 irs + kappa |C|) = (k / 2 pi) / (r + |C|).
-// The double-layer factor of a pair, (ik/r - 1/r^2) e^{ikr} / (4 pi r), is
-// kappa^3 / (4 pi) w with w = e^{ikr} irs^2 (i k / kappa - irs), shared by
-// both directions; the direction (i <- j) adds w aw_j.(y_j - x_i) mu_j and the
+// x', y_j = c_b + y', C = c_b - c_a.  With c = k^2 / 2 pi, m = 2 c (C - x')
+// and Q_i = c (|x'|^2 - 2 C.x') per target and chunk,
+//   num = c (r^2 - |C|^2) = m.y' + c |y'|^2 + Q_i
+// carries no cancellation against |C|^2 (c |y'|^2 is staged with the
+// source), delta = r - |C| = (r^2 - |C|^2) / (r + |C|), and the phase in
+// revolutions is frac(k |C| / 2 pi) (from FP64, per target and chunk) +
+// k delta / 2 pi, so FP32 rounding enters relative to delta, not to r.
+// Distances are scaled by k: r_s^2 = k^2 r^2 = 2 pi num + k^2 |C|^2,
+// irs = 1 / (k r) and num rcp(r_s^2 irs + k |C|) = k delta / 2 pi.  The
+// double-layer factor of a pair, (ik/r - 1/r^2) e^{ikr} / (4 pi r), is
+// k^3 / (4 pi) w with w = e^{ikr} irs^2 (i - irs), shared by both
+// directions; the direction (i <- j) adds w aw_j.(y_j - x_i) mu_j and the
 // direction (j <- i) adds w aw_i.(x_i - y_j) mu_i, with
-//   aw_j.(y_j - x_i) = aw_j.y' + (aw_j / 2).m,
-//   aw_i.(x_i - y_j) = aw_i.(x' - C) - aw_i.y'.
-// The combined field adds - i eta e^{ikr} |aw| mu / (4 pi r) per direction,
-// i.e. - i (ew / kappa^2) irs e^{ikr} mu in the same scaling (ew = eta |aw|).
+//   aw_j.(y_j - x_i) = aw_j.y' + (aw_j / 2 c).m,
+//   aw_i.(x_i - y_j) = aw_i.(x' - C) - aw_i.y'
+// (aw_j / 2 c staged with the source).  The combined field adds
+// - i eta e^{ikr} |aw| mu / (4 pi r) per direction, i.e.
+// - i (ew / k^2) irs e^{ikr} mu in the same scaling (ew = eta |aw|).
 // Real parts are accumulated negated (one sign flip per slot).  Target sums
 // are FP32 per chunk and compensated (TwoSum) across chunks and columns;
 // source sums are FP32 over the chunk's 128 targets of a wavefront, then FP64.
@@ -490,12 +494,13 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (sym_inactive(T, seg_active, part)) return;
   const double k = T.k;
-  const double kap = TWO_PI / k;
-  const double sc3 = kap * kap * kap / FOUR_PI;
-  const float kap2 = (float)(kap * kap), ks = (float)(k / kap), ik2 = (float)(1.0 / (kap * kap));
+  const double cnum = k * k / TWO_PI;  // scale of num
+  const double sc3 = k * k * k / FOUR_PI;
+  const float c32 = (float)cnum, hw = (float)(0.5 / cnum), ik2 = (float)(1.0 / (k * k));
+  const float twopi = (float)TWO_PI;
 
-  __shared__ float4 sY[128];           // y', |y'|^2
-  __shared__ float4 sW[128];           // aw_j / 2, aw_j . y'
+  __shared__ float4 sY[128];           // y', c |y'|^2
+  __shared__ float4 sW[128];           // aw_j / 2 c, aw_j . y'
   __shared__ float4 sM[128];           // mu_j, ew_j / kappa^2
   __shared__ float sX[2][64];          // second wavefront's source-side sums
   const int src = (lane + 63) & 63;    // source of the lane's sums after a chunk
@@ -555,28 +560,35 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
             ph -= floor(ph);
             const float cx = (float)Cx, cy = (float)Cy, cz = (float)Cz;
             msk[t] = !act[t] || ab[t] == b;
-            mx[t] = 2.0f * (cx - xx[t]);
-            my[t] = 2.0f * (cy - xy[t]);
-            mz[t] = 2.0f * (cz - xz[t]);
+            const float c2 = 2.0f * c32;
+            mx[t] = c2 * (cx - xx[t]);
+            my[t] = c2 * (cy - xy[t]);
+            mz[t] = c2 * (cz - xz[t]);
             // a masked lane's stand-in target is far away: finite, negligible pairs
             q[t] = msk[t] ? 1e12f
-                          : fmaf(-2.0f * cx, xx[t], fmaf(-2.0f * cy, xy[t], fmaf(-2.0f * cz, xz[t], x2[t])));
+                          : c32 * fmaf(-2.0f * cx, xx[t], fmaf(-2.0f * cy, xy[t], fmaf(-2.0f * cz, xz[t], x2[t])));
             bq[t] = axd[t] + fmaf(nx[t], cx, fmaf(ny[t], cy, nz[t] * cz));
-            d2s[t] = (float)(kap * kap * C2);
-            dns[t] = (float)(kap * Cn);
+            d2s[t] = (float)(k * k * C2);
+            dns[t] = (float)(k * Cn);
             ph0[t] = (float)ph;
             mre[t] = msk[t] ? 0.0f : mr[t];
             mie[t] = msk[t] ? 0.0f : mi[t];
           }
         }
+        // a chunk of at most 32 sources takes 32 steps, each source staged in
+        // two slots of the rotation (lanes l and l + 32 then hold its sums)
+        const bool half = cl <= 32;
+        const int nst = half ? 32 : 64;
         __syncthreads();   // the previous chunk's LDS reads are done
         if (tid < 64) {
-          const bool sact = tid < cl;
-          const int64_t j = node + (sact ? tid : 0);
-          const float4 y4 = loc32[j];
+          const int sl = half ? (tid & 31) : tid;
+          const bool sact = sl < cl;
+          const int64_t j = node + (sact ? sl : 0);
+          float4 y4 = loc32[j];
+          y4.w *= c32;
           const float4 b4 = aw32[j];
           const double2 m = sact ? mu[j] : make_double2(0.0, 0.0);
-          const float4 W = make_float4(0.5f * b4.x, 0.5f * b4.y, 0.5f * b4.z, b4.w);
+          const float4 W = make_float4(hw * b4.x, hw * b4.y, hw * b4.z, b4.w);
           const float4 M = make_float4((float)m.x, (float)m.y, FORM && sact ? ew32[j] * ik2 : 0.0f, 0.0f);
           sY[tid] = y4;
           sY[tid + 64] = y4;
@@ -591,8 +603,9 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
         const float4* pY = &sY[lane];
         const float4* pW = &sW[lane];
         const float4* pM = &sM[lane];
-#pragma unroll 4
-        for (int st = 0; st < 64; ++st) {
+        for (int st0 = 0; st0 < nst; st0 += 4)
+#pragma unroll
+        for (int st = st0; st < st0 + 4; ++st) {
           const float4 Y = pY[st];
           const float4 W = pW[st];
           const float4 M = pM[st];
@@ -601,16 +614,15 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
           for (int t = 0; t < 2; ++t) {
             // shared by both directions: r, e^{ikr}, w
             const float num = fmaf(mx[t], Y.x, fmaf(my[t], Y.y, fmaf(mz[t], Y.z, Y.w + q[t])));
-            const float r2s = fmaf(kap2, num, d2s[t]);
+            const float r2s = fmaf(twopi, num, d2s[t]);
             const float irs = __builtin_amdgcn_rsqf(r2s);
             const float ph = fmaf(num, __builtin_amdgcn_rcpf(fmaf(r2s, irs, dns[t])), ph0[t]);
             const float sn = __builtin_amdgcn_sinf(ph);
             const float cs_ = __builtin_amdgcn_cosf(ph);
             const float ir2 = irs * irs;
             const float ir3 = ir2 * irs;
-            const float be = ks * ir2;
-            const float nwr = fmaf(sn, be, cs_ * ir3);   // -Re w
-            const float wi = fmaf(cs_, be, -(sn * ir3)); //  Im w
+            const float nwr = fmaf(sn, ir2, cs_ * ir3);   // -Re w
+            const float wi = fmaf(cs_, ir2, -(sn * ir3)); //  Im w
             // target i, source j
             {
               const float d = fmaf(W.x, mx[t], fmaf(W.y, my[t], fmaf(W.z, mz[t], W.w)));
@@ -654,15 +666,20 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
           }
         }
         if (!dtask) {
+          if (half) {   // the two slots of a source: lanes l and l + 32
+            acc0 += __shfl_xor(acc0, 32);
+            acc1 += __shfl_xor(acc1, 32);
+          }
           if (wv == 1) {
             sX[0][lane] = acc0;
             sX[1][lane] = acc1;
           }
           __syncthreads();
-          if (wv == 0 && src < cl) {
+          const int sj = half ? ((lane + 31) & 31) : src;
+          if (wv == 0 && (!half || lane < 32) && sj < cl) {
             const double vr = -((double)acc0 + (double)sX[0][lane]) * sc3;
             const double vi = ((double)acc1 + (double)sX[1][lane]) * sc3;
-            double2* d = part + T.soff + (int64_t)jj * SYM_T + cs + src;
+            double2* d = part + T.soff + (int64_t)jj * SYM_T + cs + sj;
             if (first_src) {
               *d = make_double2(vr, vi);
             } else {
@@ -686,9 +703,11 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
 
 // FP64 reciprocal pair sum: the same super-tasks, chunks, lane mapping and
 // rotation as the FP32 kernel, in plain FP64 on absolute positions
-// (d = y_j - x_i, r^2 = |d|^2, phase r k / 2 pi in revolutions for
-// sincos_2pi); w = e^{ikr} ir^2 (i k - ir) is shared by both directions,
-// aw_j.(y_j - x_i) = aw_j.d and aw_i.(x_i - y_j) = -aw_i.d.
+// scaled by k (d = k (y_j - x_i), r^2 = |d|^2 = (k r)^2, phase k r / 2 pi in
+// revolutions for sincos_2pi); w = e^{ikr} ir^2 (i - ir) with ir = 1/(k r)
+// is shared by both directions, aw_j.d and -aw_i.d are k aw_j.(y_j - x_i)
+// and k aw_i.(x_i - y_j), and the sums carry the factor k^2 / 4 pi (the
+// combined field's eta |aw| staged divided by k).
 template <int FORM>
 __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
     const SymSuper* __restrict__ supers, const SymBlock* __restrict__ blocks,
@@ -700,7 +719,8 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (sym_inactive(T, seg_active, part)) return;
   const double k = T.k;
-  const double k2pi = k / TWO_PI;
+  const double inv2pi = 1.0 / TWO_PI;
+  const double sc2 = k * k * INV_FOUR_PI;   // positions scaled by k: k^2 w dot mu / 4 pi
 
   __shared__ double2 sQ0[128];         // y.x, y.y
   __shared__ double2 sQ1[128];         // y.z, aw.z
@@ -725,16 +745,16 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
       const int loc = wv * 128 + t * 64 + lane;
       act[t] = loc < BI.n;
       const int64_t i = BI.n0 + (act[t] ? loc : 0);
-      xx[t] = pos[i];
-      xy[t] = pos[N + i];
-      xz[t] = pos[2 * N + i];
+      xx[t] = k * pos[i];
+      xy[t] = k * pos[N + i];
+      xz[t] = k * pos[2 * N + i];
       nx[t] = -aw[i];
       ny[t] = -aw[N + i];
       nz[t] = -aw[2 * N + i];
       const double2 m = act[t] ? mu[i] : make_double2(0.0, 0.0);
       mr[t] = m.x;
       mi[t] = m.y;
-      ewi[t] = FORM ? ewp[i] : 0.0;
+      ewi[t] = FORM ? ewp[i] / k : 0.0;
       ab[t] = node_body[i];
       sr[t] = si[t] = 0.0;
     }
@@ -765,12 +785,15 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
             mie[t] = msk[t] ? 0.0 : mi[t];
           }
         }
+        const bool half = cl <= 32;   // 32 steps, each source in two slots
+        const int nst = half ? 32 : 64;
         __syncthreads();
         if (tid < 64) {
-          const bool sact = tid < cl;
-          const int64_t j = node + (sact ? tid : 0);
-          const double2 q0 = make_double2(pos[j], pos[N + j]);
-          const double2 q1 = make_double2(pos[2 * N + j], aw[2 * N + j]);
+          const int sl = half ? (tid & 31) : tid;
+          const bool sact = sl < cl;
+          const int64_t j = node + (sact ? sl : 0);
+          const double2 q0 = make_double2(k * pos[j], k * pos[N + j]);
+          const double2 q1 = make_double2(k * pos[2 * N + j], aw[2 * N + j]);
           const double2 q2 = make_double2(aw[j], aw[N + j]);
           const double2 m = sact ? mu[j] : make_double2(0.0, 0.0);
           sQ0[tid] = q0;
@@ -782,7 +805,7 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
           sM[tid] = m;
           sM[tid + 64] = m;
           if (FORM) {
-            const double e = sact ? ewp[j] : 0.0;
+            const double e = sact ? ewp[j] / k : 0.0;
             sE[tid] = e;
             sE[tid + 64] = e;
           }
@@ -790,8 +813,9 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
         __syncthreads();
         double ar[2] = {0.0, 0.0}, ai[2] = {0.0, 0.0};
         double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll 2
-        for (int st = 0; st < 64; ++st) {
+        for (int st0 = 0; st0 < nst; st0 += 2)
+#pragma unroll
+        for (int st = st0; st < st0 + 2; ++st) {
           const double2 q0 = sQ0[lane + st];
           const double2 q1 = sQ1[lane + st];
           const double2 q2 = sQ2[lane + st];
@@ -804,12 +828,11 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             const double ir = rsqrt_pos(r2);
             double sn, cs_;
-            sincos_2pi(r2 * ir * k2pi, &sn, &cs_);
+            sincos_2pi(r2 * ir * inv2pi, &sn, &cs_);
             const double ir2 = ir * ir;
             const double ir3 = ir2 * ir;
-            const double be = k * ir2;
-            const double wr = -fma(sn, be, cs_ * ir3);
-            const double wi = fma(cs_, be, -(sn * ir3));
+            const double wr = -fma(sn, ir2, cs_ * ir3);
+            const double wi = fma(cs_, ir2, -(sn * ir3));
             // target i, source j
             {
               const double d = fma(q2.x, dx, fma(q2.y, dy, q1.y * dz));
@@ -851,15 +874,20 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
           }
         }
         if (!dtask) {
+          if (half) {   // the two slots of a source: lanes l and l + 32
+            acc0 += __shfl_xor(acc0, 32);
+            acc1 += __shfl_xor(acc1, 32);
+          }
           if (wv == 1) {
             sX[0][lane] = acc0;
             sX[1][lane] = acc1;
           }
           __syncthreads();
-          if (wv == 0 && src < cl) {
-            const double vr = (acc0 + sX[0][lane]) * INV_FOUR_PI;
-            const double vi = (acc1 + sX[1][lane]) * INV_FOUR_PI;
-            double2* d = part + T.soff + (int64_t)jj * SYM_T + cs + src;
+          const int sj = half ? ((lane + 31) & 31) : src;
+          if (wv == 0 && (!half || lane < 32) && sj < cl) {
+            const double vr = (acc0 + sX[0][lane]) * sc2;
+            const double vi = (acc1 + sX[1][lane]) * sc2;
+            double2* d = part + T.soff + (int64_t)jj * SYM_T + cs + sj;
             if (first_src) {
               *d = make_double2(vr, vi);
             } else {
@@ -875,7 +903,7 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
     for (int t = 0; t < 2; ++t) {
       const int loc = wv * 128 + t * 64 + lane;
       if (loc < BI.n)
-        part[T.toff + (int64_t)ii * SYM_T + loc] = make_double2(sr[t] * INV_FOUR_PI, si[t] * INV_FOUR_PI);
+        part[T.toff + (int64_t)ii * SYM_T + loc] = make_double2(sr[t] * sc2, si[t] * sc2);
     }
   }
 }
