@@ -619,10 +619,10 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
             const float ph = fmaf(num, __builtin_amdgcn_rcpf(fmaf(r2s, irs, dns[t])), ph0[t]);
             const float sn = __builtin_amdgcn_sinf(ph);
             const float cs_ = __builtin_amdgcn_cosf(ph);
+            // w = irs^2 e^{i ph} (i - irs)
             const float ir2 = irs * irs;
-            const float ir3 = ir2 * irs;
-            const float nwr = fmaf(sn, ir2, cs_ * ir3);   // -Re w
-            const float wi = fmaf(cs_, ir2, -(sn * ir3)); //  Im w
+            const float nwr = fmaf(cs_, irs, sn) * ir2;    // -Re w
+            const float wi = fmaf(-sn, irs, cs_) * ir2;    //  Im w
             // target i, source j
             {
               const float d = fmaf(W.x, mx[t], fmaf(W.y, my[t], fmaf(W.z, mz[t], W.w)));
@@ -703,8 +703,9 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
 
 // FP64 reciprocal pair sum: the same super-tasks, chunks, lane mapping and
 // rotation as the FP32 kernel, in plain FP64 on absolute positions
-// scaled by k (d = k (y_j - x_i), r^2 = |d|^2 = (k r)^2, phase k r / 2 pi in
-// revolutions for sincos_2pi); w = e^{ikr} ir^2 (i - ir) with ir = 1/(k r)
+// scaled by k (d = k (y_j - x_i), r^2 = |d|^2 = (k r)^2, phase k r in 256ths
+// of a revolution for sincos_tab256, whose table each workgroup fills in LDS);
+// w = e^{ikr} ir^2 (i - ir) with ir = 1/(k r)
 // is shared by both directions, aw_j.d and -aw_i.d are k aw_j.(y_j - x_i)
 // and k aw_i.(x_i - y_j), and the sums carry the factor k^2 / 4 pi (the
 // combined field's eta |aw| staged divided by k).
@@ -719,7 +720,7 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (sym_inactive(T, seg_active, part)) return;
   const double k = T.k;
-  const double inv2pi = 1.0 / TWO_PI;
+  const double u256 = 256.0 / TWO_PI;      // k r in 256ths of a revolution
   const double sc2 = k * k * INV_FOUR_PI;   // positions scaled by k: k^2 w dot mu / 4 pi
 
   __shared__ double2 sQ0[128];         // y.x, y.y
@@ -728,7 +729,9 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
   __shared__ double2 sM[128];          // mu_j
   __shared__ double sE[FORM ? 128 : 1];
   __shared__ double sX[2][64];         // second wavefront's source-side sums
+  __shared__ double2 sTab[256];        // (sin, cos)(2 pi i / 256)
   const int src = (lane + 63) & 63;
+  fill_tab256(sTab, tid, 128);         // ordered by the first chunk's barrier
 
   uint32_t touched = 0;
   for (int ii = 0; ii < T.ni; ++ii) {
@@ -828,11 +831,10 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
             const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
             const double ir = rsqrt_pos(r2);
             double sn, cs_;
-            sincos_2pi(r2 * ir * inv2pi, &sn, &cs_);
+            sincos_tab256(r2 * ir * u256, sTab, &sn, &cs_);
             const double ir2 = ir * ir;
-            const double ir3 = ir2 * ir;
-            const double wr = -fma(sn, ir2, cs_ * ir3);
-            const double wi = fma(cs_, ir2, -(sn * ir3));
+            const double wr = -(fma(cs_, ir, sn) * ir2);
+            const double wi = fma(-sn, ir, cs_) * ir2;
             // target i, source j
             {
               const double d = fma(q2.x, dx, fma(q2.y, dy, q1.y * dz));
