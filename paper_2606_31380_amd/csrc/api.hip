@@ -836,6 +836,20 @@ static qax_status setup_krylov(qax_problem* p, int nrhs, int mmax, Krylov& K) {
 
 // Solve with the plane-wave right-hand sides of `dirs` (host) or, when dirs is
 // null, the caller's device right-hand side d_rhs.
+// Smallest residual reduction one mixed refinement cycle aims at.  The FP32
+// operator (FP32 pair sum, FP32 copy of the inverse) is accurate to a few
+// 1e-7 per apply, and the implicit GMRES residual stops tracking the true one
+// near 1e-6 of the cycle's right-hand side; a cycle pushed further only adds
+// steps that the next FP64 residual undoes.  Restarting costs no steps here
+// (the preconditioned operator is the identity plus a compact part, so GMRES
+// converges at a nearly fixed rate): on the 1000-body workload at 1e-6 a first
+// cycle aimed at 5e-7 took 39 FP32 steps in all, one aimed at 3e-6 ... 1e-3
+// took 36, as many as the FP64 solver.  With the inverse computed in FP32
+// (accurate to ~1e-5) a cycle cannot gain more than that.
+static double mixed_cycle_floor(const qax_problem* p) {
+  return p->factor_prec == QAX_FP64 ? 1e-5 : 2e-5;
+}
+
 static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, const double* d_rhs,
                              int32_t nrhs, double tol, int32_t maxit, void* d_mu_out, qax_info* info) {
   qax_status st = check_vec_call(p, dirs ? (const void*)dirs : (const void*)d_rhs, d_mu_out, nrhs, 2);
@@ -1041,11 +1055,7 @@ static qax_status solve_core(qax_problem* p, qax_prec prec, const double* dirs, 
       const double need = bnorm[s] > 0 && rn[s] > 0 ? 0.5 * tol * bnorm[s] / rn[s] : 1.0;
       if (!frozen) min_need = std::min(min_need, need);
       par[s] = rn[s];
-      // mixed: with the FP32-computed inverse (accurate to ~1e-5) a cycle
-      // cannot gain much more than 1e-5; the rounded FP64 inverse and the
-      // compensated FP32 pair sum leave an operator error near 1e-7
-      const double floor32 = p->factor_prec == QAX_FP64 ? 2e-7 : 2e-5;
-      par[nseg + s] = prec == QAX_MIXED ? std::max(need, floor32) : need;
+      par[nseg + s] = prec == QAX_MIXED ? std::max(need, mixed_cycle_floor(p)) : need;
       fz[s] = frozen ? 1 : 0;
       fz[nseg + s] = frozen ? 0 : 1;
       g0[(size_t)s * (m + 1)] = rn[s];
@@ -1695,7 +1705,7 @@ static qax_status solve_block(qax_problem* p, qax_prec prec, const double* dirs,
       break;
     }
     if (total_its >= maxit) break;
-    const double floor32 = p->factor_prec == QAX_FP64 ? 2e-7 : 2e-5;
+    const double floor32 = mixed_cycle_floor(p);
     for (int c = 0; c < P; ++c) {
       const double nd = rn[c] > 0 ? 0.5 * tol * bn[c] / rn[c] : 1.0;
       need[c] = prec == QAX_MIXED ? std::max(nd, floor32) : nd;
