@@ -221,12 +221,7 @@ static void free_geometry(qax_problem* p) {
   p->d_gemm_tasks = nullptr;
   dev_release(p, p->sym.d_bmem);
   p->sym.d_bmem = nullptr;
-  for (auto& pl : p->sym.plan) {
-    dev_release(p, pl.d_mem);
-    pl.d_mem = nullptr;
-    pl.s = 0;
-    pl.supers.clear();
-  }
+  for (int pi = 0; pi < 2; ++pi) (void)release_sym_plan(p, pi);
   p->sym.blocks.clear();
   p->gemm_tasks.clear();
   lattice_free(p);

@@ -189,6 +189,7 @@ struct qax_problem {
       std::vector<int64_t> lptr;           // per launch: n_blocks + 1 list offsets
       std::vector<int64_t> list;           // slot offsets
       int64_t max_slots = 0;               // complex values of the largest launch
+      bool alias = false;                  // device arrays owned by the other precision's plan
       void* d_mem = nullptr;
       qax::SymSuper* d_supers = nullptr;
       int64_t* d_lptr = nullptr;
@@ -293,6 +294,7 @@ hipError_t upload_pair_plan(qax_problem* p, int prec, int cu_count);
 // reciprocal pair sums: plan for precision index pi (0 FP64, 1 FP32) with
 // super-tasks of s x s block pairs (s <= 0: the default for this problem)
 hipError_t plan_sym(qax_problem* p, int pi, int s, int cu_count);
+hipError_t release_sym_plan(qax_problem* p, int pi);
 int sym_default_s(const qax_problem* p, int cu_count);
 // launch choices the kernels support (LDS within 64 KB)
 bool pair_config_ok(int prec, int tpb, int nrc);

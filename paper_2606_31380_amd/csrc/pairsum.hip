@@ -24,6 +24,7 @@
 // accumulation).
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <vector>
 
 #include "fastmath.h"
@@ -461,22 +462,23 @@ __device__ __forceinline__ bool sym_inactive(const SymSuper& T, const int32_t* _
   return true;
 }
 
-// FP32 reciprocal pair sum.  Coordinates are local to each body: x_i = c_a +
-// x', y_j = c_b + y', C = c_b - c_a.  With c = k^2 / 2 pi, m = 2 c (C - x')
-// and Q_i = c (|x'|^2 - 2 C.x') per target and chunk,
-//   num = c (r^2 - |C|^2) = m.y' + c |y'|^2 + Q_i
-// carries no cancellation against |C|^2 (c |y'|^2 is staged with the
-// source), delta = r - |C| = (r^2 - |C|^2) / (r + |C|), and the phase in
-// revolutions is frac(k |C| / 2 pi) (from FP64, per target and chunk) +
-// k delta / 2 pi, so FP32 rounding enters relative to delta, not to r.
-// Distances are scaled by k: r_s^2 = k^2 r^2 = 2 pi num + k^2 |C|^2,
-// irs = 1 / (k r) and num rcp(r_s^2 irs + k |C|) = k delta / 2 pi.  The
-// double-layer factor of a pair, (ik/r - 1/r^2) e^{ikr} / (4 pi r), is
-// k^3 / (4 pi) w with w = e^{ikr} irs^2 (i - irs), shared by both
-// directions; the direction (i <- j) adds w aw_j.(y_j - x_i) mu_j and the
-// direction (j <- i) adds w aw_i.(x_i - y_j) mu_i, with
+// FP32 reciprocal pair sum.  Source coordinates are local to their body,
+// y_j = c_b + y'; per target and source body, D = c_b - x_i, |D| and
+// frac(k |D| / 2 pi) are formed in FP64 (from the centres and the target's
+// local coordinates) and, with c = k^2 / 2 pi, m = 2 c D in FP32, so that
+//   num = c (r^2 - |D|^2) = m.y' + c |y'|^2
+// is three fmas with no cancellation against |D|^2 (c |y'|^2 is staged with
+// the source), delta = r - |D| = (r^2 - |D|^2) / (r + |D|), and the phase in
+// revolutions is frac(k |D| / 2 pi) + k delta / 2 pi, so FP32 rounding enters
+// relative to delta, not to r.  Distances are scaled by k:
+// r_s^2 = k^2 r^2 = 2 pi num + k^2 |D|^2, irs = 1 / (k r) and
+// num rcp(r_s^2 irs + k |D|) = k delta / 2 pi.  The double-layer factor of a
+// pair, (ik/r - 1/r^2) e^{ikr} / (4 pi r), is k^3 / (4 pi) w with
+// w = e^{ikr} irs^2 (i - irs), shared by both directions; the direction
+// (i <- j) adds w aw_j.(y_j - x_i) mu_j and the direction (j <- i) adds
+// w aw_i.(x_i - y_j) mu_i, with
 //   aw_j.(y_j - x_i) = aw_j.y' + (aw_j / 2 c).m,
-//   aw_i.(x_i - y_j) = aw_i.(x' - C) - aw_i.y'
+//   aw_i.(x_i - y_j) = -aw_i.D - aw_i.y'
 // (aw_j / 2 c staged with the source).  The combined field adds
 // - i eta e^{ikr} |aw| mu / (4 pi r) per direction, i.e.
 // - i (ew / k^2) irs e^{ikr} mu in the same scaling (ew = eta |aw|).
@@ -512,7 +514,7 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
     const int I = T.i0 + ii;
     const SymBlock BI = blocks[I];
     // the lane's two targets
-    float xx[2], xy[2], xz[2], x2[2], nx[2], ny[2], nz[2], axd[2], mr[2], mi[2], ew[2];
+    float xx[2], xy[2], xz[2], nx[2], ny[2], nz[2], mr[2], mi[2], ew[2];
     int ab[2];
     bool act[2];
     float nsr[2], ncr[2], tsi[2], tci[2];
@@ -523,8 +525,8 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
       const int64_t i = BI.n0 + (act[t] ? loc : 0);
       const float4 x4 = loc32[i];
       const float4 a4 = aw32[i];
-      xx[t] = x4.x; xy[t] = x4.y; xz[t] = x4.z; x2[t] = x4.w;
-      nx[t] = -a4.x; ny[t] = -a4.y; nz[t] = -a4.z; axd[t] = a4.w;
+      xx[t] = x4.x; xy[t] = x4.y; xz[t] = x4.z;
+      nx[t] = -a4.x; ny[t] = -a4.y; nz[t] = -a4.z;
       const double2 m = act[t] ? mu[i] : make_double2(0.0, 0.0);
       mr[t] = (float)m.x;
       mi[t] = (float)m.y;
@@ -539,7 +541,7 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
       const bool first_src = !dtask && !((touched >> jj) & 1u);
       if (!dtask) touched |= 1u << jj;
       // per target and source body: m, Q, B, scaled |C|^2 and |C|, phase base
-      float mx[2], my[2], mz[2], q[2], bq[2], d2s[2], dns[2], ph0[2], mre[2], mie[2];
+      float mx[2], my[2], mz[2], bq[2], d2s[2], dns[2], ph0[2], mre[2], mie[2];
       bool msk[2];
       int cur_b = -1;
       for (int cs = 0; cs < BJ.n;) {
@@ -552,25 +554,31 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
             const BodyDev& BA = bodies[ab[t]];
-            const double Cx = BB.cen[0] - BA.cen[0], Cy = BB.cen[1] - BA.cen[1],
-                         Cz = BB.cen[2] - BA.cen[2];
-            const double C2 = fma(Cx, Cx, fma(Cy, Cy, Cz * Cz));
-            const double Cn = sqrt(C2);
-            double ph = k * Cn / TWO_PI;
-            ph -= floor(ph);
-            const float cx = (float)Cx, cy = (float)Cy, cz = (float)Cz;
             msk[t] = !act[t] || ab[t] == b;
-            const float c2 = 2.0f * c32;
-            mx[t] = c2 * (cx - xx[t]);
-            my[t] = c2 * (cy - xy[t]);
-            mz[t] = c2 * (cz - xz[t]);
-            // a masked lane's stand-in target is far away: finite, negligible pairs
-            q[t] = msk[t] ? 1e12f
-                          : c32 * fmaf(-2.0f * cx, xx[t], fmaf(-2.0f * cy, xy[t], fmaf(-2.0f * cz, xz[t], x2[t])));
-            bq[t] = axd[t] + fmaf(nx[t], cx, fmaf(ny[t], cy, nz[t] * cz));
-            d2s[t] = (float)(k * k * C2);
-            dns[t] = (float)(k * Cn);
-            ph0[t] = (float)ph;
+            // D = c_b - x_i in FP64 from the centres and the local coordinates
+            const double Dx = (BB.cen[0] - BA.cen[0]) - (double)xx[t];
+            const double Dy = (BB.cen[1] - BA.cen[1]) - (double)xy[t];
+            const double Dz = (BB.cen[2] - BA.cen[2]) - (double)xz[t];
+            const double D2 = fma(Dx, Dx, fma(Dy, Dy, Dz * Dz));
+            const double Dn = sqrt(D2);
+            double ph = k * Dn / TWO_PI;
+            ph -= floor(ph);
+            if (msk[t]) {
+              // stand-in target 1e6 away: finite, negligible pairs
+              mx[t] = (float)(2.0 * cnum * 1e6);
+              my[t] = mz[t] = bq[t] = 0.0f;
+              d2s[t] = (float)(k * k * 1e12);
+              dns[t] = (float)(k * 1e6);
+              ph0[t] = 0.0f;
+            } else {
+              mx[t] = (float)(2.0 * cnum * Dx);
+              my[t] = (float)(2.0 * cnum * Dy);
+              mz[t] = (float)(2.0 * cnum * Dz);
+              bq[t] = (float)((double)nx[t] * Dx + (double)ny[t] * Dy + (double)nz[t] * Dz);
+              d2s[t] = (float)(k * k * D2);
+              dns[t] = (float)(k * Dn);
+              ph0[t] = (float)ph;
+            }
             mre[t] = msk[t] ? 0.0f : mr[t];
             mie[t] = msk[t] ? 0.0f : mi[t];
           }
@@ -613,7 +621,7 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
             // shared by both directions: r, e^{ikr}, w
-            const float num = fmaf(mx[t], Y.x, fmaf(my[t], Y.y, fmaf(mz[t], Y.z, Y.w + q[t])));
+            const float num = fmaf(mx[t], Y.x, fmaf(my[t], Y.y, fmaf(mz[t], Y.z, Y.w)));
             const float r2s = fmaf(twopi, num, d2s[t]);
             const float irs = __builtin_amdgcn_rsqf(r2s);
             const float ph = fmaf(num, __builtin_amdgcn_rcpf(fmaf(r2s, irs, dns[t])), ph0[t]);
@@ -1022,10 +1030,31 @@ static void plan_sym_supers(qax_problem* p, int pi, int s, int64_t cap) {
         cost.push_back(c);
       }
   }
-  // decreasing cost (stable: ties keep the construction order)
-  std::vector<int64_t> ord(P.supers.size());
-  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int64_t)i;
-  std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+  // decreasing cost (stable: ties keep the construction order); the costs
+  // take few distinct values (products of block sizes), so the order is
+  // built by buckets of equal cost, which is the stable sort's order
+  std::vector<int64_t> ord;
+  {
+    std::vector<double> uniq(cost);
+    std::sort(uniq.begin(), uniq.end(), std::greater<double>());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    ord.reserve(cost.size());
+    if (uniq.size() <= 256) {
+      std::vector<int64_t> cnt(uniq.size() + 1, 0);
+      std::vector<int32_t> bucket(cost.size());
+      for (size_t i = 0; i < cost.size(); ++i) {
+        bucket[i] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), cost[i], std::greater<double>()) -
+                              uniq.begin());
+        ++cnt[bucket[i] + 1];
+      }
+      for (size_t b = 1; b < cnt.size(); ++b) cnt[b] += cnt[b - 1];
+      ord.resize(cost.size());
+      for (size_t i = 0; i < cost.size(); ++i) ord[cnt[bucket[i]]++] = (int64_t)i;
+    } else {
+      for (size_t i = 0; i < cost.size(); ++i) ord.push_back((int64_t)i);
+      std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) { return cost[a] > cost[b]; });
+    }
+  }
   std::vector<SymSuper> sorted;
   sorted.reserve(ord.size());
   for (int64_t i : ord) sorted.push_back(P.supers[i]);
@@ -1048,33 +1077,47 @@ static void plan_sym_supers(qax_problem* p, int pi, int s, int64_t cap) {
   }
   P.launch_super.push_back((int64_t)P.supers.size());
   const int nl = (int)P.launch_super.size() - 1;
-  // lists: per launch, per block
+  // lists: per launch, per block, the slots in super-task order (counted,
+  // then filled)
   P.lptr.assign((size_t)nl * (nblk + 1), 0);
   P.list.clear();
-  std::vector<std::vector<int64_t>> lists(nblk);
-  for (int l = 0; l < nl; ++l) {
-    for (auto& v : lists) v.clear();
-    for (int64_t i = P.launch_super[l]; i < P.launch_super[l + 1]; ++i) {
-      const SymSuper& T = P.supers[i];
-      uint32_t colseen = 0;
-      for (int ii = 0; ii < T.ni; ++ii) {
-        bool row = false;
-        for (int jj = T.diag ? ii : 0; jj < T.nj; ++jj) {
-          if ((T.skip >> (ii * SYM_SMAX + jj)) & 1ull) continue;
-          row = true;
-          if (T.i0 + ii != T.j0 + jj) colseen |= 1u << jj;
+  std::vector<int64_t> fill(nblk + 1);
+  for (int pass = 0; pass < 2; ++pass) {
+    int64_t base = 0;
+    for (int l = 0; l < nl; ++l) {
+      int64_t* lp = P.lptr.data() + (size_t)l * (nblk + 1);
+      if (pass == 0) std::fill(fill.begin(), fill.end(), 0);
+      else std::copy(lp, lp + nblk + 1, fill.begin());
+      for (int64_t i = P.launch_super[l]; i < P.launch_super[l + 1]; ++i) {
+        const SymSuper& T = P.supers[i];
+        uint32_t colseen = 0;
+        for (int ii = 0; ii < T.ni; ++ii) {
+          bool row = false;
+          for (int jj = T.diag ? ii : 0; jj < T.nj; ++jj) {
+            if ((T.skip >> (ii * SYM_SMAX + jj)) & 1ull) continue;
+            row = true;
+            if (T.i0 + ii != T.j0 + jj) colseen |= 1u << jj;
+          }
+          if (row) {
+            if (pass == 0) ++fill[T.i0 + ii];
+            else P.list[fill[T.i0 + ii]++] = T.toff + (int64_t)ii * SYM_T;
+          }
         }
-        if (row) lists[T.i0 + ii].push_back(T.toff + (int64_t)ii * SYM_T);
+        for (int jj = 0; jj < T.nj; ++jj)
+          if ((colseen >> jj) & 1u) {
+            if (pass == 0) ++fill[T.j0 + jj];
+            else P.list[fill[T.j0 + jj]++] = T.soff + (int64_t)jj * SYM_T;
+          }
       }
-      for (int jj = 0; jj < T.nj; ++jj)
-        if ((colseen >> jj) & 1u) lists[T.j0 + jj].push_back(T.soff + (int64_t)jj * SYM_T);
+      if (pass == 0) {
+        for (int b = 0; b < nblk; ++b) {
+          lp[b] = base;
+          base += fill[b];
+        }
+        lp[nblk] = base;
+      }
     }
-    int64_t* lp = P.lptr.data() + (size_t)l * (nblk + 1);
-    for (int b = 0; b < nblk; ++b) {
-      lp[b] = (int64_t)P.list.size();
-      P.list.insert(P.list.end(), lists[b].begin(), lists[b].end());
-    }
-    lp[nblk] = (int64_t)P.list.size();
+    if (pass == 0) P.list.assign((size_t)base, 0);
   }
   P.s = s;
 }
@@ -1106,14 +1149,33 @@ static hipError_t upload_sym_blocks(qax_problem* p) {
   return hipStreamSynchronize(p->stream);
 }
 
-static hipError_t upload_sym_plan(qax_problem* p, int pi) {
+// Drop plan pi's device arrays (after the stream has drained); arrays shared
+// with the other precision's plan pass to that plan.
+hipError_t release_sym_plan(qax_problem* p, int pi) {
   auto& P = p->sym.plan[pi];
+  auto& O = p->sym.plan[1 - pi];
   if (P.d_mem) {
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return e;
-    dev_release(p, P.d_mem);
-    P.d_mem = nullptr;
+    if (O.d_mem == P.d_mem) O.alias = false;
+    else if (!P.alias) dev_release(p, P.d_mem);
   }
+  P.d_mem = nullptr;
+  P.d_supers = nullptr;
+  P.d_lptr = nullptr;
+  P.d_list = nullptr;
+  P.alias = false;
+  P.s = 0;
+  P.supers.clear();
+  P.launch_super.clear();
+  P.lptr.clear();
+  P.list.clear();
+  P.max_slots = 0;
+  return hipSuccess;
+}
+
+static hipError_t upload_sym_plan(qax_problem* p, int pi) {
+  auto& P = p->sym.plan[pi];
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
   const size_t bs = al(sizeof(SymSuper) * std::max<size_t>(1, P.supers.size()));
   const size_t bp = al(sizeof(int64_t) * std::max<size_t>(1, P.lptr.size()));
@@ -1131,7 +1193,12 @@ static hipError_t upload_sym_plan(qax_problem* p, int pi) {
   cp(P.d_lptr, P.lptr.data(), sizeof(int64_t) * P.lptr.size());
   cp(P.d_list, P.list.data(), sizeof(int64_t) * P.list.size());
   if (e != hipSuccess) return e;
-  return hipStreamSynchronize(p->stream);
+  e = hipStreamSynchronize(p->stream);
+  // the launches need only the launch ranges on the host
+  std::vector<SymSuper>().swap(P.supers);
+  std::vector<int64_t>().swap(P.lptr);
+  std::vector<int64_t>().swap(P.list);
+  return e;
 }
 
 // Default super-task size: the largest of 8, 4, 2, 1 that still gives every
@@ -1161,8 +1228,24 @@ hipError_t plan_sym(qax_problem* p, int pi, int s, int cu_count) {
   if (s <= 0) s = sym_default_s(p, cu_count);
   s = std::max(1, std::min(SYM_SMAX, s));
   if (S.plan[pi].d_mem && S.plan[pi].s == s) return hipSuccess;
-  plan_sym_supers(p, pi, s, SYM_SLOT_CAP);
+  hipError_t e = release_sym_plan(p, pi);
+  if (e != hipSuccess) return e;
   ++p->generation;   // captured solver steps hold the old launch sizes
+  const auto& O = S.plan[1 - pi];
+  if (O.d_mem && O.s == s) {
+    // the other precision's kernels run the same squares: share its plan
+    auto& P = S.plan[pi];
+    P.s = s;
+    P.launch_super = O.launch_super;
+    P.max_slots = O.max_slots;
+    P.d_mem = O.d_mem;
+    P.d_supers = O.d_supers;
+    P.d_lptr = O.d_lptr;
+    P.d_list = O.d_list;
+    P.alias = true;
+    return hipSuccess;
+  }
+  plan_sym_supers(p, pi, s, SYM_SLOT_CAP);
   return upload_sym_plan(p, pi);
 }
 
