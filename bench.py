@@ -19,7 +19,8 @@ time-to-solve at 1e-6 for the mixed and the plain FP64 solver (solve alone
 and with assembly + factorisation), their errors against an FP64 solve at
 1e-10, the mixed solve with an FP32 factorisation, per-kernel timings (HIP
 events on the library stream), the roofline of the dominant kernel, a short
-run of the 27-body lattice workload, and the CPU oracle timed on the host.
+run of the 27-body lattice workload, 32 independent problems solved in one
+handle against one handle each, and the CPU oracle timed on the host.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload random_mixed|lattice27]
 """
@@ -356,6 +357,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="random_mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 32-problem batched-vs-sequential comparison")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (read if it has this problem, else written)")
     args = ap.parse_args()
@@ -377,11 +380,6 @@ def main():
     dom = max((k for k in roofs if k != "invert"), key=lambda k: roofs[k]["ms_per_step"])
     roof = {k: v for k, v in roofs[dom].items() if k != "ms_per_step"}
     roof["kernel"] = dom
-    if dom == "pair_sum_fp32":
-        # packed FP32 instructions are disabled in this build: one FP32 FMA per
-        # lane and cycle, 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
-        roof["peak_without_packed_fp32"] = PEAK["fp32"] / 2 / 1e12
-        roof["frac_without_packed_fp32"] = roof["achieved"] / roof["peak_without_packed_fp32"]
     out = {
         "metric": "Helmholtz pair-interactions/s + time-to-solve @1e-6 rel err, mixed vs FP64",
         "value": r["value"], "unit": "pair-interactions/s", "n_gpus": 1,
@@ -409,6 +407,13 @@ def main():
             "time_to_solve_1e-6": r2["time_to_solve_1e-6"], "pair_sum_kernel": r2["pair_sum_kernel"],
             "kernel_ms_per_step": r2["kernel_ms_per_step"],
             "pair_sum_fp32_roofline": r2["rooflines"].get("pair_sum_fp32")}}
+    if args.workload != "lattice27" and not args.no_secondary and not args.no_batch:
+        # 32 independent problems in one handle against 32 handles one after
+        # the other (time to solve to 1e-6); its progress lines go to stderr
+        import contextlib
+        from paper_2606_31380_amd import batching_bench
+        with contextlib.redirect_stdout(sys.stderr):
+            out.setdefault("secondary", {})["uneven_batch"] = batching_bench.batch()
     if not args.no_cpu_baseline:
         applies = int(round(r["solver_per_step"]["fp32_pair_sums"] + r["solver_per_step"]["fp64_pair_sums"]))
         out["cpu_baseline"] = cpu_baseline(args.workload, applies)

@@ -1,6 +1,7 @@
 """Build libqax.so (HIP for gfx950) in-tree with hipcc.
 
-    python -m paper_2606_31380_amd.build
+    python -m paper_2606_31380_amd.build          (the library)
+    python -m paper_2606_31380_amd.build probe    (the issue-cost microbenchmark)
 
 Every HIP translation unit is compiled for gfx950 only, with the packed-FP32
 instruction forms disabled, and linked into one shared library next to this
@@ -58,6 +59,19 @@ def build(jobs: int = 6) -> str:
     return LIB
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "issue_probe.hip")
+PROBE_BIN = os.path.join(HERE, "probe", "issue_probe")
+
+
+def build_probe() -> str:
+    """The issue-cost microbenchmark (a standalone gfx950 program)."""
+    cmd = [hipcc()] + flags() + ["-Wno-unused-result", PROBE_SRC, "-o", PROBE_BIN]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for the probe:\n{r.stderr[-6000:]}")
+    return PROBE_BIN
+
+
 if __name__ == "__main__":
-    print(build())
+    print(build_probe() if sys.argv[1:] == ["probe"] else build())
     sys.exit(0)
