@@ -1,5 +1,5 @@
 // FP64 sine and cosine for the kernels' moderate arguments (|x| < 2^20).
-// (sincos_2pi, sincos_tab256 and rsqrt_pos below: the pair-sum variants.)
+// (sincos_2pi, sincos_tab512 and rsqrt_pos below: the pair-sum variants.)
 //
 // Cody-Waite reduction x = q (pi/2) + r, |r| <= pi/4, with pi/2 split into
 // three doubles (the products q * P_i are exact inside fused multiply-adds),
@@ -86,30 +86,32 @@ __device__ __forceinline__ void sincos_2pi(double t, double* sp, double* cp) {
   *cp = __hiloint2double(__double2hiint(pc) ^ sgn, __double2loint(pc));
 }
 
-// sin and cos of 2 pi u / 256 (u in 256ths of a revolution, |u| < 2^31) from
-// a table of (sin, cos)(2 pi i / 256), i = 0..255: with m = rint(u) the
+// sin and cos of 2 pi u / 512 (u in 512ths of a revolution, |u| < 2^31) from
+// a table of (sin, cos)(2 pi i / 512), i = 0..511: with m = rint(u) the
 // remainder g = u - m is exact and |g| <= 1/2, so the Taylor series of
-// sin(2 pi g / 256) through g^5 and of cos(2 pi g / 256) - 1 through g^6
-// (truncation below 1e-17) and the angle-addition formulas with the table
-// entry of m mod 256 give both.  The coefficients are (-1)^k (2 pi / 256)^m / m!
-// rounded to double; the error is a few units in the last place.
-__device__ __forceinline__ void sincos_tab256(double u, const double2* tab, double* sp, double* cp) {
+// sin(2 pi g / 512) through g^5 (the next term is below 7e-20) and of
+// cos(2 pi g / 512) - 1 through g^4 (the next term is below 7.5e-17, under
+// half a unit in the last place of 1) and the angle-addition formulas with
+// the table entry of m mod 512 give both.  The coefficients are
+// (-1)^k (2 pi / 512)^m / m! rounded to double; the error is a few units in
+// the last place.
+__device__ __forceinline__ void sincos_tab512(double u, const double2* tab, double* sp, double* cp) {
   const double m = rint(u);
   const double g = u - m;
-  const double2 T = tab[(int)m & 255];
+  const double2 T = tab[(int)m & 511];
   const double g2 = g * g;
-  const double S = g * fma(fma(g2, 7.421954185344935e-11, -2.4641574764489986e-06), g2, 0.02454369260617026);
-  const double Cm1 = g2 * fma(fma(g2, -3.036036034369748e-13, 1.5119880908790113e-08), g2, -0.0003011964233730883);
+  const double S = g * fma(fma(g2, 2.3193606829202922e-12, -3.080196845561248e-07), g2, 0.01227184630308513);
+  const double Cm1 = g2 * fma(g2, 9.44992556799382e-10, -7.529910584327208e-05);
   *sp = fma(T.x, Cm1, fma(T.y, S, T.x));
   *cp = fma(T.y, Cm1, fma(-T.x, S, T.y));
 }
 
-// The table for sincos_tab256: (sin, cos)(2 pi i / 256) in tab[i], filled by
+// The table for sincos_tab512: (sin, cos)(2 pi i / 512) in tab[i], filled by
 // the `nthreads` threads of a workgroup (a barrier must follow before use).
-__device__ __forceinline__ void fill_tab256(double2* tab, int tid, int nthreads) {
-  for (int i = tid; i < 256; i += nthreads) {
+__device__ __forceinline__ void fill_tab512(double2* tab, int tid, int nthreads) {
+  for (int i = tid; i < 512; i += nthreads) {
     double s, c;
-    sincos_2pi(i * (1.0 / 256.0), &s, &c);
+    sincos_2pi(i * (1.0 / 512.0), &s, &c);
     tab[i] = make_double2(s, c);
   }
 }

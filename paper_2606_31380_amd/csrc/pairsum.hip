@@ -710,9 +710,11 @@ __global__ __launch_bounds__(128) void pair_sum_f32_sym_kernel(
 }
 
 // FP64 reciprocal pair sum: the same super-tasks, chunks, lane mapping and
-// rotation as the FP32 kernel, in plain FP64 on absolute positions
-// scaled by k (d = k (y_j - x_i), r^2 = |d|^2 = (k r)^2, phase k r in 256ths
-// of a revolution for sincos_tab256, whose table each workgroup fills in LDS);
+// rotation as the FP32 kernel, in plain FP64 on positions scaled by k: the
+// sources local to their body, y' = k (y_j - c_b), D = k (c_b - x_i) per
+// target and source body, so (k r)^2 = |D|^2 + 2 D.y' + |y'|^2 is four fmas
+// with |y'|^2 / 2 staged (phase k r in 512ths of a revolution for
+// sincos_tab512, whose table each workgroup fills in LDS);
 // w = e^{ikr} ir^2 (i - ir) with ir = 1/(k r)
 // is shared by both directions, aw_j.d and -aw_i.d are k aw_j.(y_j - x_i)
 // and k aw_i.(x_i - y_j), and the sums carry the factor k^2 / 4 pi (the
@@ -728,18 +730,19 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (sym_inactive(T, seg_active, part)) return;
   const double k = T.k;
-  const double u256 = 256.0 / TWO_PI;      // k r in 256ths of a revolution
+  const double u512 = 512.0 / TWO_PI;      // k r in 512ths of a revolution
   const double sc2 = k * k * INV_FOUR_PI;   // positions scaled by k: k^2 w dot mu / 4 pi
 
-  __shared__ double2 sQ0[128];         // y.x, y.y
-  __shared__ double2 sQ1[128];         // y.z, aw.z
+  __shared__ double2 sQ0[128];         // y'.x, y'.y   (y' = k (y - c_b))
+  __shared__ double2 sQ1[128];         // y'.z, |y'|^2 / 2
   __shared__ double2 sQ2[128];         // aw.x, aw.y
+  __shared__ double2 sQ3[128];         // aw.z, aw.y'
   __shared__ double2 sM[128];          // mu_j
   __shared__ double sE[FORM ? 128 : 1];
   __shared__ double sX[2][64];         // second wavefront's source-side sums
-  __shared__ double2 sTab[256];        // (sin, cos)(2 pi i / 256)
+  __shared__ double2 sTab[512];        // (sin, cos)(2 pi i / 512)
   const int src = (lane + 63) & 63;
-  fill_tab256(sTab, tid, 128);         // ordered by the first chunk's barrier
+  fill_tab512(sTab, tid, 128);         // ordered by the first chunk's barrier
 
   uint32_t touched = 0;
   for (int ii = 0; ii < T.ni; ++ii) {
@@ -775,7 +778,7 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
       const bool dtask = (T.j0 + jj) == I;
       const bool first_src = !dtask && !((touched >> jj) & 1u);
       if (!dtask) touched |= 1u << jj;
-      double ex[2], ey[2], ez[2], mre[2], mie[2];
+      double Dx[2], Dy[2], Dz[2], d2[2], bq[2], mre[2], mie[2];
       bool msk[2];
       int cur_b = -1;
       for (int cs = 0; cs < BJ.n;) {
@@ -788,10 +791,13 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
             msk[t] = !act[t] || ab[t] == b;
-            // a masked lane's stand-in target is far away: finite, negligible pairs
-            ex[t] = msk[t] ? xx[t] + 1e10 : xx[t];
-            ey[t] = xy[t];
-            ez[t] = xz[t];
+            // D = k (c_b - x_i); a masked lane's stand-in target is far away:
+            // finite, negligible pairs
+            Dx[t] = msk[t] ? 1e10 : k * BB.cen[0] - xx[t];
+            Dy[t] = msk[t] ? 0.0 : k * BB.cen[1] - xy[t];
+            Dz[t] = msk[t] ? 0.0 : k * BB.cen[2] - xz[t];
+            d2[t] = fma(Dx[t], Dx[t], fma(Dy[t], Dy[t], Dz[t] * Dz[t]));
+            bq[t] = fma(nx[t], Dx[t], fma(ny[t], Dy[t], nz[t] * Dz[t]));
             mre[t] = msk[t] ? 0.0 : mr[t];
             mie[t] = msk[t] ? 0.0 : mi[t];
           }
@@ -803,9 +809,13 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
           const int sl = half ? (tid & 31) : tid;
           const bool sact = sl < cl;
           const int64_t j = node + (sact ? sl : 0);
-          const double2 q0 = make_double2(k * pos[j], k * pos[N + j]);
-          const double2 q1 = make_double2(k * pos[2 * N + j], aw[2 * N + j]);
-          const double2 q2 = make_double2(aw[j], aw[N + j]);
+          const double yx = k * (pos[j] - BB.cen[0]), yy = k * (pos[N + j] - BB.cen[1]),
+                       yz = k * (pos[2 * N + j] - BB.cen[2]);
+          const double ax = aw[j], ay = aw[N + j], az = aw[2 * N + j];
+          const double2 q0 = make_double2(yx, yy);
+          const double2 q1 = make_double2(yz, 0.5 * fma(yx, yx, fma(yy, yy, yz * yz)));
+          const double2 q2 = make_double2(ax, ay);
+          const double2 q3 = make_double2(az, fma(ax, yx, fma(ay, yy, az * yz)));
           const double2 m = sact ? mu[j] : make_double2(0.0, 0.0);
           sQ0[tid] = q0;
           sQ0[tid + 64] = q0;
@@ -813,6 +823,8 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
           sQ1[tid + 64] = q1;
           sQ2[tid] = q2;
           sQ2[tid + 64] = q2;
+          sQ3[tid] = q3;
+          sQ3[tid + 64] = q3;
           sM[tid] = m;
           sM[tid + 64] = m;
           if (FORM) {
@@ -830,22 +842,25 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
           const double2 q0 = sQ0[lane + st];
           const double2 q1 = sQ1[lane + st];
           const double2 q2 = sQ2[lane + st];
+          const double2 q3 = sQ3[lane + st];
           const double2 m = sM[lane + st];
           const double e = FORM ? sE[lane + st] : 0.0;
           double cr = 0.0, ci = 0.0;
 #pragma unroll
           for (int t = 0; t < 2; ++t) {
-            const double dx = q0.x - ex[t], dy = q0.y - ey[t], dz = q1.x - ez[t];
-            const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+            // k^2 r^2 = |D|^2 + 2 D.y' + |y'|^2
+            const double nh = fma(Dx[t], q0.x, fma(Dy[t], q0.y, fma(Dz[t], q1.x, q1.y)));
+            const double r2 = fma(2.0, nh, d2[t]);
             const double ir = rsqrt_pos(r2);
             double sn, cs_;
-            sincos_tab256(r2 * ir * u256, sTab, &sn, &cs_);
+            sincos_tab512(r2 * ir * u512, sTab, &sn, &cs_);
             const double ir2 = ir * ir;
             const double wr = -(fma(cs_, ir, sn) * ir2);
             const double wi = fma(-sn, ir, cs_) * ir2;
             // target i, source j
             {
-              const double d = fma(q2.x, dx, fma(q2.y, dy, q1.y * dz));
+              // k aw_j.(y_j - x_i) = aw_j.y' + aw_j.D
+              const double d = fma(q2.x, Dx[t], fma(q2.y, Dy[t], fma(q3.x, Dz[t], q3.y)));
               const double vr = d * m.x, vi = d * m.y;
               ar[t] = fma(wr, vr, fma(-wi, vi, ar[t]));
               ai[t] = fma(wi, vr, fma(wr, vi, ai[t]));
@@ -857,7 +872,8 @@ __global__ __launch_bounds__(128) void pair_sum_f64_sym_kernel(
             }
             // target j, source i
             {
-              const double d = fma(nx[t], dx, fma(ny[t], dy, nz[t] * dz));
+              // k aw_i.(x_i - y_j) = -aw_i.D - aw_i.y'
+              const double d = fma(nx[t], q0.x, fma(ny[t], q0.y, fma(nz[t], q1.x, bq[t])));
               const double ur = d * mre[t], ui = d * mie[t];
               if (t == 0) {
                 cr = fma(wr, ur, -(wi * ui));
