@@ -529,67 +529,30 @@ __device__ __forceinline__ unsigned long long dpp_max_u64(unsigned long long v) 
   return readlane_u64(v, 63);
 }
 
-// Pivot row of column k: the row i in [k, n) of largest |a_ik|^2, ties to the
-// lower row.  col[r] is the thread's entry in row tid + 1024 r.  FP32: one
-// 64-bit key (magnitude bits, which order like the non-negative values, then
-// the complemented row) reduced by DPP; FP64: value and row by shuffles.
+// Pivot row of column k: the row i in [k, n) of largest |a_ik|^2 (compared
+// after rounding to FP32 in the FP64 elimination: candidates within FP32
+// rounding of each other are equally good pivots), ties to the lower row.
+// col[r] is the thread's entry in row tid + 1024 r.  One 64-bit key per
+// thread (the FP32 magnitude bits, which order like the non-negative values,
+// then the complemented row) reduced by DPP within each wavefront and over
+// the 16 wavefronts through LDS.
 template <typename T, int R>
 __device__ __forceinline__ int leaf_pivot(const typename Cx<T>::V (&col)[R], int tid, int k, int n,
-                                          T* red_v, int* red_i, unsigned long long* red_k) {
+                                          unsigned long long* red_k) {
   const int lane = tid & 63, wave = tid >> 6;
-  if constexpr (sizeof(T) == 4) {
-    unsigned long long key = 0;
+  unsigned long long key = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = tid + 1024 * r;
-      const float m = col[r].x * col[r].x + col[r].y * col[r].y;
-      const unsigned long long ki = ((unsigned long long)__float_as_uint(m) << 32) | (unsigned)~i;
-      if (i >= k && i < n) key = max_u64(key, ki);
-    }
-    key = dpp_max_u64<true>(key);
-    if (lane == 0) red_k[wave] = key;
-    __syncthreads();
-    key = dpp_max_u64<false>(red_k[lane & 15]);
-    return (int)~(unsigned)key;
-  } else {
-    T bv = -1;
-    int bi = n;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const int i = tid + 1024 * r;
-      const T m = col[r].x * col[r].x + col[r].y * col[r].y;
-      if (i >= k && i < n && m > bv) {
-        bv = m;
-        bi = i;
-      }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const T ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      red_v[wave] = bv;
-      red_i[wave] = bi;
-    }
-    __syncthreads();
-    bv = red_v[0];
-    bi = red_i[0];
-#pragma unroll
-    for (int q = 1; q < 16; ++q) {
-      const T ov = red_v[q];
-      const int oi = red_i[q];
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
-    return bi;
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + 1024 * r;
+    const float m = (float)(col[r].x * col[r].x + col[r].y * col[r].y);
+    const unsigned long long ki = ((unsigned long long)__float_as_uint(m) << 32) | (unsigned)~i;
+    if (i >= k && i < n) key = max_u64(key, ki);
   }
+  key = dpp_max_u64<true>(key);
+  if (lane == 0) red_k[wave] = key;
+  __syncthreads();
+  key = dpp_max_u64<false>(red_k[lane & 15]);
+  return (int)~(unsigned)key;
 }
 
 // Unblocked elimination with partial pivoting on the columns [c0, c0 + wcols)
@@ -615,8 +578,6 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
   V* A = pool + M.elem_off;
   const int w = min(c0 + wcols, n) - c0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ T red_v[16];
-  __shared__ int red_i[16];
   __shared__ unsigned long long red_k[16];
   __shared__ V swap_buf[WL];
   __shared__ V rowk[WL];
@@ -670,7 +631,7 @@ __global__ __launch_bounds__(1024) void gjr_leaf_kernel(const MatDesc* __restric
         V col[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) col[r] = a[r][u];
-        const int pr = leaf_pivot<T, R>(col, tid, k, n, red_v, red_i, red_k);
+        const int pr = leaf_pivot<T, R>(col, tid, k, n, red_k);
         if (tid == 0) piv[(int64_t)blockIdx.x * nmax + k] = pr;
         // one exchange through LDS: the owner of row pr publishes the scaled
         // pivot row (it becomes row k), the owner of row k its old row (it
