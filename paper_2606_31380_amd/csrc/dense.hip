@@ -794,11 +794,12 @@ __global__ __launch_bounds__(256) void gjn_update_kernel(const MatDesc* __restri
   const int send = min(s0 + ws, n);
   const int wsv = send - s0;
   const int wdv = min(d0 + wd, n) - d0;
+  const int rows = 256 / wd;
+  if ((int)blockIdx.x * rows >= n || wdv <= 0) return;   // no row of this matrix (uniform)
   __shared__ V Ws[32][32];   // halves of at most 32 columns (wider ones: gjm_update_kernel)
   const V* Wm = W + (int64_t)blockIdx.y * GJB * GJB;
   for (int e = threadIdx.x; e < wsv * wdv; e += 256) Ws[e / wdv][e % wdv] = Wm[(e / wdv) * GJB + e % wdv];
   __syncthreads();
-  const int rows = 256 / wd;
   const int i = blockIdx.x * rows + threadIdx.x / wd;
   const int j = threadIdx.x % wd;
   if (i >= n || j >= wdv) return;
