@@ -205,7 +205,17 @@ extern "C" qax_status qax_create(int device, void* hip_stream, qax_problem** out
   return QAX_OK;
 }
 
-static void free_geometry(qax_problem* p) {
+// The reciprocal pair sums' blocks and plans (a function of the node ranges
+// of the bodies and problems and of the wavenumbers only).
+static void free_pair_plans(qax_problem* p) {
+  dev_release(p, p->sym.d_bmem);
+  p->sym.d_bmem = nullptr;
+  for (int pi = 0; pi < 2; ++pi) (void)release_sym_plan(p, pi);
+  p->sym.blocks.clear();
+  p->sym.key.clear();
+}
+
+static void free_geometry(qax_problem* p, bool keep_plans = false) {
   void* ptrs[] = {p->d_bodies, p->d_blocks, p->d_node_body, p->d_pos,  p->d_aw,
                   p->d_loc32,  p->d_aw32,   p->d_gl,        p->d_B,    p->d_Binv,
                   p->d_Binv32, p->d_tasks64, p->d_tasks32, p->d_ew, p->d_ew32, p->d_B32,
@@ -219,10 +229,7 @@ static void free_geometry(qax_problem* p) {
   p->d_ew = nullptr; p->d_ew32 = nullptr;
   dev_release(p, p->d_gemm_tasks);
   p->d_gemm_tasks = nullptr;
-  dev_release(p, p->sym.d_bmem);
-  p->sym.d_bmem = nullptr;
-  for (int pi = 0; pi < 2; ++pi) (void)release_sym_plan(p, pi);
-  p->sym.blocks.clear();
+  if (!keep_plans) free_pair_plans(p);
   p->gemm_tasks.clear();
   lattice_free(p);
 }
@@ -381,7 +388,9 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
   }
   if (prev != n_problems - 1) return fail(p, QAX_ERR_ARG, "qax_build: a problem has no bodies");
   QCHECK(hipSetDevice(p->device), "hipSetDevice");
-  free_geometry(p);
+  // the pair-sum plans are kept when the new geometry has the same node
+  // ranges and wavenumbers (a rebuild of moved or reshaped bodies)
+  free_geometry(p, true);
   p->state = 0;
   p->n_bodies = n_bodies;
   p->n_problems = n_problems;
@@ -427,6 +436,20 @@ extern "C" qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t 
     }
   }
   p->prob_body0[n_problems] = n_bodies;
+  {
+    std::vector<int64_t> key(p->off.begin(), p->off.end());
+    key.insert(key.end(), p->prob_body0.begin(), p->prob_body0.end());
+    for (double kv : p->k) {
+      int64_t b;
+      std::memcpy(&b, &kv, 8);
+      key.push_back(b);
+    }
+    if (key != p->sym.key) {
+      QCHECK(hipStreamSynchronize(p->stream), "sync");
+      free_pair_plans(p);
+      p->sym.key = key;
+    }
+  }
   p->N = p->off[n_bodies];
   p->block_elems = elems;
   const int64_t N = p->N;

@@ -179,6 +179,7 @@ struct qax_problem {
     std::vector<qax::SymBlock> blocks;
     std::vector<int32_t> prob_blk0;   // first block of each problem (n_problems + 1)
     std::vector<int32_t> blk_body_lo, blk_body_hi;
+    std::vector<int64_t> key;         // node ranges, problem bounds and k the plans were made for
     void* d_bmem = nullptr;           // blocks and the block of each node
     qax::SymBlock* d_blocks = nullptr;
     int32_t* d_node_block = nullptr;

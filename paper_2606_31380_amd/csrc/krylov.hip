@@ -55,7 +55,10 @@ __global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slo
 // range cut into `slots` chunks (blockIdx.y) whose partial sums are added in a
 // fixed order afterwards; blockIdx.z = problem * nrhs + right-hand side.
 // pinfo: the problems' first nodes (n_problems + 1 int64) then their k.
-template <int TPB>
+// The phase is taken in 512ths of a revolution for sincos_tab512 (table in
+// LDS per workgroup); PAIRS: the list holds negated pairs (else the second
+// direction's sums are not formed).
+template <int TPB, bool PAIRS>
 __global__ __launch_bounds__(TPB) void farfield_kernel(
     const double* __restrict__ xhat, const int2* __restrict__ items, int64_t M, int64_t Mi,
     const double* __restrict__ pos, const double* __restrict__ aw, const double* __restrict__ ew,
@@ -75,13 +78,15 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
   const double k = __longlong_as_double(pinfo[nprob + 1 + pr]);
   const double hx = active ? xhat[3 * i] : 0.0, hy = active ? xhat[3 * i + 1] : 0.0,
                hz = active ? xhat[3 * i + 2] : 0.0;
-  // phase -k x.y / 2 pi in revolutions and k x, per direction
-  const double kr = -k / TWO_PI;
+  // phase -k x.y / 2 pi in 512ths of a revolution and k x, per direction
+  const double kr = -k * (512.0 / TWO_PI);
   const double px = kr * hx, py = kr * hy, pz = kr * hz;
   const double qx = k * hx, qy = k * hy, qz = k * hz;
   const int64_t c0 = pn0 + pn * blockIdx.y / slots, c1 = pn0 + pn * (blockIdx.y + 1) / slots;
   __shared__ double sx[TPB], sy[TPB], sz[TPB], sax[TPB], say[TPB], saz[TPB], sew[TPB];
   __shared__ double2 smu[TPB];
+  __shared__ double2 sTab[512];
+  fill_tab512(sTab, tid, TPB);   // ordered by the first tile's barrier
   double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
   for (int64_t base = c0; base < c1; base += TPB) {
     const int cnt = (int)min((int64_t)TPB, c1 - base);
@@ -97,19 +102,21 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
     if (form == 2) {
       for (int jj = 0; jj < cnt; ++jj) {
         double s, c;
-        sincos_2pi(fma(px, sx[jj], fma(py, sy[jj], pz * sz[jj])), &s, &c);
+        sincos_tab512(fma(px, sx[jj], fma(py, sy[jj], pz * sz[jj])), sTab, &s, &c);
         const double fr = sew[jj] * c, fi = sew[jj] * s;
         const double2 m = smu[jj];
         ar = fma(fr, m.x, fma(-fi, m.y, ar));
         ai = fma(fr, m.y, fma(fi, m.x, ai));
-        // -x: fr, -fi
-        br = fma(fr, m.x, fma(fi, m.y, br));
-        bi = fma(fr, m.y, fma(-fi, m.x, bi));
+        if constexpr (PAIRS) {
+          // -x: fr, -fi
+          br = fma(fr, m.x, fma(fi, m.y, br));
+          bi = fma(fr, m.y, fma(-fi, m.x, bi));
+        }
       }
     } else {
       for (int jj = 0; jj < cnt; ++jj) {
         double s, c;
-        sincos_2pi(fma(px, sx[jj], fma(py, sy[jj], pz * sz[jj])), &s, &c);
+        sincos_tab512(fma(px, sx[jj], fma(py, sy[jj], pz * sz[jj])), sTab, &s, &c);
         // (-i k nd)(c + i s) = k nd s - i k nd c; combined field adds
         // (-i eta |aw|)(c + i s) = eta |aw| s - i eta |aw| c (ew = 0 otherwise)
         const double d = fma(qx, sax[jj], fma(qy, say[jj], qz * saz[jj]));
@@ -118,11 +125,13 @@ __global__ __launch_bounds__(TPB) void farfield_kernel(
         const double2 m = smu[jj];
         ar = fma(fr, m.x, fma(-fi, m.y, ar));
         ai = fma(fr, m.y, fma(fi, m.x, ai));
-        // -x: k nd -> -k nd, s -> -s: (eta |aw| - d)(-s) - i (eta |aw| - d) c
-        const double a2 = sew[jj] - d;
-        const double gr = -a2 * s, gi = -a2 * c;
-        br = fma(gr, m.x, fma(-gi, m.y, br));
-        bi = fma(gr, m.y, fma(gi, m.x, bi));
+        if constexpr (PAIRS) {
+          // -x: k nd -> -k nd, s -> -s: (eta |aw| - d)(-s) - i (eta |aw| - d) c
+          const double a2 = sew[jj] - d;
+          const double gr = -a2 * s, gi = -a2 * c;
+          br = fma(gr, m.x, fma(-gi, m.y, br));
+          bi = fma(gr, m.y, fma(gi, m.x, bi));
+        }
       }
     }
   }
@@ -146,7 +155,10 @@ hipError_t launch_farfield(qax_problem* p, const double* mu, int nrhs, const dou
                            int ndir, const int2* items_dev, int nitems, const int64_t* pinfo_dev,
                            int slots, double* partial, double* out) {
   dim3 grid((unsigned)((nitems + 255) / 256), (unsigned)slots, (unsigned)(nrhs * p->n_problems));
-  hipLaunchKernelGGL((farfield_kernel<256>), grid, dim3(256), 0, p->stream, xhat_dev, items_dev,
+  // items pair a direction with its negation only when there are fewer
+  // items than directions
+  auto kern = nitems < ndir ? farfield_kernel<256, true> : farfield_kernel<256, false>;
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, p->stream, xhat_dev, items_dev,
                      (int64_t)ndir, (int64_t)nitems, p->d_pos, p->d_aw, p->d_ew, p->form(), p->N,
                      pinfo_dev, p->n_problems, slots, (const double2*)mu, nrhs, (double2*)partial);
   hipError_t e = hipGetLastError();
