@@ -129,9 +129,41 @@ __device__ __forceinline__ double recip(double x) {
   return y;
 }
 
+// Wavefront maxima by DPP row shifts and row broadcasts (lane 15 of each row
+// of 16 ends with its row's maximum, lane 63 with the wavefront's), read
+// back from lane 63: of a non-negative int, and of a non-negative double
+// (whose bits order like its values).  Lanes without a DPP source read 0.
+template <int CTRL, int ROWM>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWM, 0xf, false);
+}
 __device__ __forceinline__ int wave_max_int(int v) {
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-  return v;
+  v = max(v, dpp_i32<0x111, 0xf>(v));   // row_shr:1
+  v = max(v, dpp_i32<0x112, 0xf>(v));   // row_shr:2
+  v = max(v, dpp_i32<0x114, 0xf>(v));   // row_shr:4
+  v = max(v, dpp_i32<0x118, 0xf>(v));   // row_shr:8
+  v = max(v, dpp_i32<0x142, 0xa>(v));   // row_bcast:15 into rows 1, 3
+  v = max(v, dpp_i32<0x143, 0xc>(v));   // row_bcast:31 into rows 2, 3
+  return __builtin_amdgcn_readlane(v, 63);
+}
+template <int CTRL, int ROWM>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, ROWM, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, ROWM, 0xf, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
+}
+__device__ __forceinline__ double wave_max_nonneg(double x) {
+  unsigned long long v = (unsigned long long)__double_as_longlong(x);
+  auto mx = [](unsigned long long a, unsigned long long b) { return a > b ? a : b; };
+  v = mx(v, dpp_u64<0x111, 0xf>(v));
+  v = mx(v, dpp_u64<0x112, 0xf>(v));
+  v = mx(v, dpp_u64<0x114, 0xf>(v));
+  v = mx(v, dpp_u64<0x118, 0xf>(v));
+  v = mx(v, dpp_u64<0x142, 0xa>(v));
+  v = mx(v, dpp_u64<0x143, 0xc>(v));
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 // Uniform copy of lane l's value (v_readlane on both halves); l uniform.
@@ -434,7 +466,7 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
       if constexpr (CF) M.Sh[lane] = M.fc[lane].x * sc;
     }
     const double mag = fabs(M.fa[lane].x * sc);
-    const double mx = wave_max(mag);
+    const double mx = wave_max_nonneg(mag);
     const bool above = mag > 1e-15 * mx;
     const unsigned long long bal = __ballot(above);
     nf = bal ? 63 - __clzll(bal) : 0;
@@ -457,7 +489,41 @@ __device__ void modal_modes(double k, double r, double rt, double c, double chim
     if constexpr (CF) M.G0[n] = pref * qn;
   }
   __syncthreads();
-  if (lane <= nmax) {
+  if (k != 0.0 && nmax < 32) {
+    // the convolution's sum over n split between the wavefront's halves
+    // (lanes m and m + 32 take n <= nf / 2 and n > nf / 2 for mode m), the
+    // halves' sums added across: half the dependent chain
+    const int m = lane & 31, hf = lane >> 5, nh = nf / 2;
+    const int n0 = hf ? nh + 1 : 1, n1 = hf ? nf : nh;
+    double ar = 0.0, br = 0.0, gr = 0.0;
+    if (m <= nmax) {
+      if (!hf) {
+        const double2 ab = M.AB0[m];
+        ar = M.Fh[0] * ab.x;
+        br = M.Fh[0] * ab.y;
+        if constexpr (CF) gr = M.Ch[0] * M.G0[m];
+      }
+#pragma unroll 4
+      for (int n = n0; n <= n1; ++n) {
+        const double f = M.Fh[n];
+        const double2 u = M.AB0[abs(m - n)], v = M.AB0[m + n];
+        ar = fma(f, u.x + v.x, ar);
+        br = fma(f, u.y + v.y, br);
+      }
+      if constexpr (CF) {
+#pragma unroll 4
+        for (int n = n0; n <= n1; ++n) gr = fma(M.Ch[n], M.G0[abs(m - n)] + M.G0[m + n], gr);
+      }
+    }
+    ar += __shfl_xor(ar, 32);
+    br += __shfl_xor(br, 32);
+    if constexpr (CF) gr += __shfl_xor(gr, 32);
+    if (!hf && m <= nmax) {
+      M.Am[m] = make_double2(ar * (1.0 / TWO_PI), M.Hrh[m]);
+      M.Bm[m] = make_double2(br * (1.0 / TWO_PI), -c * M.Hh[m]);
+      if constexpr (CF) M.Gm[m] = make_double2(gr * (1.0 / TWO_PI), M.Sh[m]);
+    }
+  } else if (lane <= nmax) {
     const double2 ab = M.AB0[lane];
     if (k == 0.0) {
       M.Am[lane] = make_double2(ab.x, 0.0);
@@ -549,12 +615,12 @@ __device__ __forceinline__ double2 modal_slot(int N, const NodeLoc& L, const Mod
   return out;
 }
 
-// acc[l] += P_l(s_q) w_q K with P_l(s_q) held by lane q (uniform) in P[l]
+// acc[l] += w_q P_l(s_q) K with w_q P_l(s_q) held by lane q (uniform) in P[l]
 __device__ __forceinline__ void accumulate_node(double2 (&acc)[GL_ORDER], const double (&P)[GL_ORDER],
-                                                int q, double wq, double2 K) {
+                                                int q, double2 K) {
 #pragma unroll
   for (int l = 0; l < GL_ORDER; ++l) {
-    const double p = readlane_f64(P[l], q) * wq;
+    const double p = readlane_f64(P[l], q);
     acc[l].x = fma(p, K.x, acc[l].x);
     acc[l].y = fma(p, K.y, acc[l].y);
   }
@@ -880,7 +946,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       double suf = 1.0;
 #pragma unroll
       for (int l = GL_ORDER - 1; l >= 0; --l) {
-        P[l] *= suf * gl16[32 + l];
+        P[l] *= suf * gl16[32 + l] * w;   // with the node's weight
         suf *= x - gl16[l];
       }
     }
@@ -913,13 +979,12 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
       const int cnt = min(QB, nmodal - b0);
       for (int q = 0; q < cnt; ++q) {
         const int sl = __builtin_amdgcn_readfirstlane(S.modal_idx[b0 + q]);
-        const double wq = readlane_f64(w, sl);
         const NodeLoc Ln = read_node(Lme, sl);
         modal_modes<CF>(k, Ln.r, Ln.rt, Ln.c, Ln.chim1, Ln.rmrt, N + 1, S.Q, q, S.u.m, S.tw);
         double2 ks;
         const double2 Kq = modal_slot<CF>(N, Ln, S.u.m, ks);
-        accumulate_node(acc, P, sl, wq, Kq);
-        if constexpr (CF) accumulate_node(acs, P, sl, wq, ks);
+        accumulate_node(acc, P, sl, Kq);
+        if constexpr (CF) accumulate_node(acs, P, sl, ks);
         __syncthreads();
       }
     }
@@ -960,7 +1025,6 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     // mode slot s = lane of node q: m = s - N (slot 0 also takes m = +N),
     // K_m = (2 pi / L) X[m mod L], accumulated with the node's weights
     auto gather = [&](int q, int L, int base) {
-      const double wq = readlane_f64(w, q);
 #pragma unroll
       for (int part = 0; part < (CF ? 2 : 1); ++part) {
         double2 Kq = make_double2(0.0, 0.0);
@@ -975,8 +1039,8 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
           Kq.x *= f;
           Kq.y *= f;
         }
-        if (part == 0) accumulate_node(acc, P, q, wq, Kq);
-        else if constexpr (CF) accumulate_node(acs, P, q, wq, Kq);
+        if (part == 0) accumulate_node(acc, P, q, Kq);
+        else if constexpr (CF) accumulate_node(acs, P, q, Kq);
       }
     };
     // nodes with 256 samples one at a time
