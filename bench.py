@@ -45,6 +45,20 @@ sys.path.insert(0, ROOT)
 FLOP_PER_PAIR = 35
 PEAK = {"fp32": 157.3e12, "fp64": 78.6e12, "hbm": 8.0e12}
 
+# The paper's own timings, as context (MATLAB on an Intel Xeon server with
+# 256 GB of RAM, FP64, dense direct solves except where noted; other
+# discretisations and another algorithm, so not a target)
+PAPER_CONTEXT = {
+    "hardware": "MATLAB, Intel Xeon server, 256 GB RAM, FP64 (the paper's numerical section)",
+    "table8_27_bodies_k5": {"N_tot": 69120, "T_ker_s": 97.48, "T_mat_s": 751.03, "T_solve_s": 680.02,
+                            "error": 6.61e-12, "solver": "dense direct (mldivide)"},
+    "table7_1000_bodies_k5": {"N_tot": 96000, "T_ker_s": 0.57, "T_mat_s": 220.16, "T_solve_s": 307.51,
+                              "error": 2.09e-9, "solver": "GMRES with the block-diagonal preconditioner, "
+                                                          "identical bodies on a cubic array"},
+    "table6_8_bodies_k5": {"N_tot": 102400, "T_ker_s": 273.63, "T_mat_s": 1076.73, "T_solve_s": 2575.58,
+                           "error": 5.41e-12, "solver": "dense direct (mldivide)"},
+}
+
 WORKLOADS = {
     "random_mixed": ("random_mixed: 1000 bodies (sphere r=0.5 / spheroid (0.5,0.5,1) / peanut "
                      "0.5(1+0.3cos2psi)), kappa~U[0,0.3], cube side 40, 16-32 GL x 16-32 azimuths, "
@@ -395,6 +409,7 @@ def main():
         "roofline": roof,
         "tuning": r["tuning"],
         "kernel_rooflines": roofs,
+        "paper_context": PAPER_CONTEXT,
     }
     if "time_to_solve_tol" in r:
         out["time_to_solve_tol"] = r["time_to_solve_tol"]
