@@ -111,7 +111,11 @@ const char* qax_last_error(const qax_problem* p);
  * (Sections 2, 3.1; rigid motions of Section 6.2).  k_per_problem[n_problems]
  * are the wavenumbers (k >= 0).  Bodies with identical shape, discretisation
  * and wavenumber share one self block (Section 4: congruent bodies have equal
- * diagonal blocks whatever their rigid motion). */
+ * diagonal blocks whatever their rigid motion).  A handle may be built again:
+ * the earlier geometry and self blocks are dropped (assemble again); the
+ * pair sums' work plans are kept when the bodies' node counts, their split
+ * into problems and the wavenumbers are unchanged (bodies moved, rotated or
+ * reshaped), and made again otherwise. */
 qax_status qax_build(qax_problem* p, const qax_body* bodies, int32_t n_bodies,
                      const double* k_per_problem, int32_t n_problems);
 
