@@ -206,28 +206,62 @@ def rooflines(ktimes, scen, P, factor_fp64, steps, applies):
     duration.  A pair sum may take several dispatches (its work split into
     launches of bounded workspace): the work per dispatch is then the work of
     the step's pair sums (applies[kind] of P pairs) over its dispatches."""
-    nb = scen.nodes_per_body().astype(np.float64)
-    nth = scen.bodies["n_theta"].astype(np.float64)
-    npan = scen.bodies["n_panels"].astype(np.float64)
+    # distinct self blocks (equal shape, curvature, discretisation and k)
+    bb = scen.bodies
+    kb = np.asarray(scen.k)[bb["problem"]]
+    keys = {}
+    for i in range(len(bb)):
+        c = float(bb["c"][i]) if int(bb["shape"][i]) < 3 else 0.0
+        key = (int(bb["shape"][i]), float(bb["a"][i]), c, float(bb["kappa"][i]), int(bb["n_panels"][i]),
+               int(bb["n_ref"][i]), int(bb["n_theta"][i]), float(kb[i]))
+        keys.setdefault(key, i)
+    first = np.array(sorted(keys.values()))
+    nb_all = scen.nodes_per_body().astype(np.float64)   # every body's block is read per apply
+    nb = nb_all[first]
+    nth = bb["n_theta"].astype(np.float64)[first]
+    npan = (bb["n_panels"] + 2 * bb["n_ref"]).astype(np.float64)[first]
+    # mirror-symmetric bodies (sphere, spheroid, peanut, quasi-ellipsoid):
+    # the rows s < n_s / 2, j <= N are assembled, (N + 1) / (4 N) of them, and
+    # B is inverted through four blocks of orders (n_s / 2)(N +- 1)
+    sym = bb["shape"][first] <= 3
+    Nh = nth / 2
+    rows_frac = np.where(sym, (Nh + 1) / (4 * Nh), 1.0)
     # self-block assembly: per (target row, outer node) the azimuthal modes of
     # the kernel at the minimal grid (L = 128 samples at 35 flop, a 128-point
     # FFT at 5 L log2 L) and the 16 x 2N weighted accumulation (8 flop per
     # term); per (row, panel) one 2N x 2N inverse DFT for 16 functions; outer
     # nodes per row: 2 g on the own panel + g per adjacent panel, with the
     # outer rule's order g = 48 on two or more panels, else 64.  Counted once
-    # per distinct block.
+    # per distinct block, over the rows assembled.
     per_node = 35 * 128 + 5 * 128 * 7 + 8 * 16 * nth
     per_item = 8 * 16 * nth * nth
     adj = np.where(npan > 1, np.where(npan > 2, 2.0 - 2.0 / npan, 1.0), 0.0)
     g = np.where(npan >= 2, 48.0, 64.0)
-    self_flop = float(np.sum(nb * ((2 * g + g * adj) * per_node + (1 + adj) * per_item)))
-    inv_flop = float(np.sum(8.0 * nb ** 3))
-    upd_flop = float(np.sum(8.0 * nb * nb * 128))
+    self_flop = float(np.sum(rows_frac * nb * ((2 * g + g * adj) * per_node + (1 + adj) * per_item)))
+    # inversion: 8 m^3 per matrix of order m inverted; a trailing update of
+    # the 128 columns at k0 is 8 m (m - w) w, w = min(128, m - k0), and the
+    # dispatches are one per 128 columns of the largest matrix of each batch
+    # (symmetric reduced blocks, other blocks)
+    half = npan * 16 / 2
+    orders, batches = [], [[], []]
+    for i in range(len(nb)):
+        ms = [half[i] * (Nh[i] + 1)] * 2 + [half[i] * (Nh[i] - 1)] * 2 if sym[i] else [nb[i]]
+        orders += ms
+        batches[0 if sym[i] else 1] += ms
+    orders = np.array(orders)
+    inv_flop = float(np.sum(8.0 * orders ** 3))
+    upd_tot = 0.0
+    for m in orders:
+        for k0 in np.arange(0, m, 128):
+            w = min(128.0, m - k0)
+            upd_tot += 8.0 * m * (m - w) * w
+    upd_disp = sum(int(np.ceil(max(b) / 128)) for b in batches if b)
+    upd_flop = float(upd_tot / max(upd_disp, 1))
     inv_peak = PEAK["fp64"] if factor_fp64 else PEAK["fp32"]
     work = {"pair_sum_fp32": ("alu", FLOP_PER_PAIR * P, PEAK["fp32"], "TFLOP/s"),
             "pair_sum_fp64": ("alu", FLOP_PER_PAIR * P, PEAK["fp64"], "TFLOP/s"),
-            "block_apply": ("hbm", float(np.sum(nb * nb)) * 16.0, PEAK["hbm"], "GB/s"),
-            "block_apply_f32": ("hbm", float(np.sum(nb * nb)) * 8.0, PEAK["hbm"], "GB/s"),
+            "block_apply": ("hbm", float(np.sum(nb_all * nb_all)) * 16.0, PEAK["hbm"], "GB/s"),
+            "block_apply_f32": ("hbm", float(np.sum(nb_all * nb_all)) * 8.0, PEAK["hbm"], "GB/s"),
             "self_assembly": ("alu", self_flop, PEAK["fp64"], "TFLOP/s"),
             "invert": ("mfma", inv_flop, inv_peak, "TFLOP/s"),
             "invert_update": ("mfma", upd_flop, inv_peak, "TFLOP/s")}

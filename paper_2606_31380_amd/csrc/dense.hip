@@ -15,6 +15,7 @@
 
 #include "fastmath.h"
 #include "internal.h"
+#include "shapes.h"
 
 namespace qax {
 
@@ -1238,39 +1239,230 @@ hipError_t launch_invert_matrices(qax_problem* p, bool f32, int count, const int
   return hipGetLastError();
 }
 
-// Invert every distinct self block for the mixed path: B rounded to FP32,
-// inverted in place in FP32 (matrix cores at the FP32 rate).  The FP64
-// inverse is made on demand by launch_invert_blocks64.
-static hipError_t upload_mats(qax_problem* p, double* work, MatDesc** d_md, double** w2, int* nmax) {
-  const int nbk = (int)p->hblocks.size();
-  std::vector<MatDesc> md(nbk);
-  *nmax = 0;
-  for (int i = 0; i < nbk; ++i) {
-    md[i].elem_off = p->hblocks[i].elem_off;
-    md[i].n = p->hblocks[i].n;
-    *nmax = std::max(*nmax, md[i].n);
+// ---------------------------------------------------------------- mirror-symmetric blocks
+// The self block of a mirror-symmetric body (mirror_symmetric) commutes with
+// the node permutations of the reflections R_h (theta -> -theta) and R_t
+// (t -> -t).  Orbit o = (s, j), s < n_s / 2, j <= N: its nodes g(o) for the
+// group elements g = R_h^a R_t^b (two nodes where j is 0 or N, which R_h
+// fixes).  With the characters chi_c(g) = (-1)^(c_h a + c_t b), c = c_h + 2 c_t,
+// B splits into four blocks
+//   M_c[o1, o2] = sum over the distinct nodes g(o2) of chi_c(g) B[o1, g(o2)]
+// (orbits with j = 0 or N only in the blocks with c_h = 0), of orders
+// (n_s / 2)(N + 1) and (n_s / 2)(N - 1), and
+//   B^-1[g1(o1), g2(o2)] = (1 / |orbit of o2|) sum_c chi_c(g1) chi_c(g2) M_c^-1[o1, o2]
+// over the blocks that hold both orbits: four inversions of about a quarter
+// of the order, 1/16 of the elimination work.  Orbit index in block c:
+// s (N + 1) + j for c_h = 0, s (N - 1) + j - 1 for c_h = 1.
+struct SymInvDesc {
+  int64_t b_off;      // complex offset of B and B^-1 in the block pools
+  int64_t m_off[4];   // complex offset of M_c in the reduced pool
+  int32_t ns, nth;    // Gauss-Legendre nodes along the curve, azimuths
+};
+
+struct SymInvRow {
+  int32_t blk;   // index into the descriptors
+  int32_t o1;    // orbit of the row, numbered s (N + 1) + j
+};
+
+// Host plan: descriptors, one row item per orbit of every symmetric block,
+// the reduced matrices and the blocks inverted as they are.
+struct SymInvPlan {
+  std::vector<SymInvDesc> desc;
+  std::vector<SymInvRow> rows;
+  std::vector<MatDesc> red, plain;
+  int nmax_red = 0, nmax_plain = 0;
+  int64_t red_elems = 0;
+  size_t off_red = 0, off_plain = 0, off_desc = 0, off_rows = 0, off_gj = 0, off_pool = 0, bytes = 0;
+};
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+static void plan_sym_inverse(const qax_problem* p, size_t elem_bytes, SymInvPlan& P) {
+  for (const BlockDev& bk : p->hblocks) {
+    const BodyDev& B = p->hbodies[bk.rep_body];
+    if (!mirror_symmetric(B.shape)) {
+      P.plain.push_back(MatDesc{bk.elem_off, bk.n});
+      P.nmax_plain = std::max(P.nmax_plain, bk.n);
+      continue;
+    }
+    const int nth = B.n_theta, N = nth / 2, ns = bk.n / nth, half = ns / 2;
+    SymInvDesc d;
+    d.b_off = bk.elem_off;
+    d.ns = ns;
+    d.nth = nth;
+    for (int c = 0; c < 4; ++c) {
+      const int m = half * ((c & 1) ? N - 1 : N + 1);
+      d.m_off[c] = P.red_elems;
+      P.red_elems += (int64_t)m * m;
+      P.red.push_back(MatDesc{d.m_off[c], m});
+      P.nmax_red = std::max(P.nmax_red, m);
+    }
+    const int blk = (int)P.desc.size();
+    P.desc.push_back(d);
+    for (int o = 0; o < half * (N + 1); ++o) P.rows.push_back(SymInvRow{blk, o});
   }
-  *d_md = (MatDesc*)work;
-  *w2 = (double*)((char*)work + ((nbk * sizeof(MatDesc) + 255) / 256) * 256);
-  return hipMemcpyAsync(*d_md, md.data(), nbk * sizeof(MatDesc), hipMemcpyHostToDevice, p->stream);
+  P.off_red = 0;
+  P.off_plain = align256(P.red.size() * sizeof(MatDesc));
+  P.off_desc = P.off_plain + align256(P.plain.size() * sizeof(MatDesc));
+  P.off_rows = P.off_desc + align256(P.desc.size() * sizeof(SymInvDesc));
+  P.off_gj = P.off_rows + align256(P.rows.size() * sizeof(SymInvRow));
+  const size_t gj = std::max(P.red.empty() ? 0 : gj_work_bytes((int)P.red.size(), P.nmax_red),
+                             P.plain.empty() ? 0 : gj_work_bytes((int)P.plain.size(), P.nmax_plain));
+  P.off_pool = P.off_gj + align256(gj);
+  P.bytes = P.off_pool + (size_t)P.red_elems * elem_bytes;
 }
 
-hipError_t launch_invert_blocks(qax_problem* p, double* work) {
-  MatDesc* d_md;
-  double* w2;
-  int nmax;
-  p->inv64_ready = false;
-  // block_elems complex elements = block_elems (re, im) pairs
-  hipLaunchKernelGGL(convert_f32_twice_kernel, dim3((unsigned)((p->block_elems + 255) / 256)),
-                     dim3(256), 0, p->stream, (const double2*)p->d_B, (float2*)p->d_B32,
-                     (float2*)p->d_Binv32, p->block_elems);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = upload_mats(p, work, &d_md, &w2, &nmax);
+// M_c from B for one orbit row (o1) per workgroup, columns o2 over the threads.
+template <typename T>
+__global__ __launch_bounds__(256) void sym_reduce_kernel(const SymInvRow* __restrict__ rows,
+                                                         const SymInvDesc* __restrict__ descs,
+                                                         const double2* __restrict__ B,
+                                                         typename Cx<T>::V* __restrict__ M) {
+  const SymInvRow R = rows[blockIdx.x];
+  const SymInvDesc D = descs[R.blk];
+  const int nth = D.nth, N = nth / 2, ns = D.ns, n = ns * nth, half = ns / 2;
+  const int np = N + 1, nm = N - 1;
+  const int s1 = R.o1 / np, j1 = R.o1 % np;
+  const bool fix1 = j1 == 0 || j1 == N;
+  const double2* brow = B + D.b_off + (int64_t)(s1 * nth + j1) * n;
+  const int64_t r0 = (int64_t)R.o1 * (half * np), r1 = (int64_t)(s1 * nm + j1 - 1) * (half * nm);
+  for (int o2 = threadIdx.x; o2 < half * np; o2 += blockDim.x) {
+    const int s2 = o2 / np, j2 = o2 % np, s2m = ns - 1 - s2;
+    const double2 b0 = brow[s2 * nth + j2], bt = brow[s2m * nth + j2];
+    const bool fix2 = j2 == 0 || j2 == N;
+    double2 bh = make_double2(0.0, 0.0), bht = make_double2(0.0, 0.0);
+    if (!fix2) {
+      bh = brow[s2 * nth + nth - j2];
+      bht = brow[s2m * nth + nth - j2];
+    }
+    // c_h = 0: b0 + bh +- (bt + bht)
+    const double2 e0 = make_double2(b0.x + bh.x, b0.y + bh.y), et = make_double2(bt.x + bht.x, bt.y + bht.y);
+    M[D.m_off[0] + r0 + o2] = Cx<T>::make((T)(e0.x + et.x), (T)(e0.y + et.y));
+    M[D.m_off[2] + r0 + o2] = Cx<T>::make((T)(e0.x - et.x), (T)(e0.y - et.y));
+    if (!fix1 && !fix2) {
+      // c_h = 1: b0 - bh +- (bt - bht)
+      const double2 d0 = make_double2(b0.x - bh.x, b0.y - bh.y), dt = make_double2(bt.x - bht.x, bt.y - bht.y);
+      const int64_t c1 = s2 * nm + j2 - 1;
+      M[D.m_off[1] + r1 + c1] = Cx<T>::make((T)(d0.x + dt.x), (T)(d0.y + dt.y));
+      M[D.m_off[3] + r1 + c1] = Cx<T>::make((T)(d0.x - dt.x), (T)(d0.y - dt.y));
+    }
+  }
+}
+
+// B^-1 from the inverses M_c^-1: every pair of images of (o1, o2).
+template <typename T>
+__global__ __launch_bounds__(256) void sym_expand_kernel(const SymInvRow* __restrict__ rows,
+                                                         const SymInvDesc* __restrict__ descs,
+                                                         const typename Cx<T>::V* __restrict__ M,
+                                                         typename Cx<T>::V* __restrict__ Binv) {
+  typedef typename Cx<T>::V V;
+  const SymInvRow R = rows[blockIdx.x];
+  const SymInvDesc D = descs[R.blk];
+  const int nth = D.nth, N = nth / 2, ns = D.ns, n = ns * nth, half = ns / 2;
+  const int np = N + 1, nm = N - 1;
+  const int s1 = R.o1 / np, j1 = R.o1 % np;
+  const bool fix1 = j1 == 0 || j1 == N;
+  const int64_t r0 = (int64_t)R.o1 * (half * np), r1 = (int64_t)(s1 * nm + j1 - 1) * (half * nm);
+  // rows of the images: [a_t][a_h] (a_h = 1 only where R_h moves the orbit)
+  V* rw[2][2];
+  for (int at = 0; at < 2; ++at)
+    for (int ah = 0; ah < 2; ++ah) {
+      const int s = at ? ns - 1 - s1 : s1, j = ah ? (nth - j1) % nth : j1;
+      rw[at][ah] = Binv + D.b_off + (int64_t)(s * nth + j) * n;
+    }
+  for (int o2 = threadIdx.x; o2 < half * np; o2 += blockDim.x) {
+    const int s2 = o2 / np, j2 = o2 % np;
+    const bool fix2 = j2 == 0 || j2 == N;
+    const V m0 = M[D.m_off[0] + r0 + o2], m2 = M[D.m_off[2] + r0 + o2];
+    V m1 = Cx<T>::make(0, 0), m3 = Cx<T>::make(0, 0);
+    if (!fix1 && !fix2) {
+      const int64_t c1 = s2 * nm + j2 - 1;
+      m1 = M[D.m_off[1] + r1 + c1];
+      m3 = M[D.m_off[3] + r1 + c1];
+    }
+    const T w = fix2 ? (T)0.5 : (T)0.25;
+    // same t image (p_t = +1): m0 + m2 +- (m1 + m3); other: m0 - m2 +- (m1 - m3)
+    const V ap = Cx<T>::make((m0.x + m2.x) * w, (m0.y + m2.y) * w);
+    const V am = Cx<T>::make((m0.x - m2.x) * w, (m0.y - m2.y) * w);
+    const V cp = Cx<T>::make((m1.x + m3.x) * w, (m1.y + m3.y) * w);
+    const V cm = Cx<T>::make((m1.x - m3.x) * w, (m1.y - m3.y) * w);
+    const int col[2] = {s2 * nth, (ns - 1 - s2) * nth};   // column slice of the t images
+    const int jj[2] = {j2, (nth - j2) % nth};
+    for (int at = 0; at < 2; ++at)
+      for (int ah = 0; ah < (fix1 ? 1 : 2); ++ah)
+        for (int bt = 0; bt < 2; ++bt) {
+          const V a = at == bt ? ap : am, c = at == bt ? cp : cm;
+          for (int bh = 0; bh < (fix2 ? 1 : 2); ++bh) {
+            const T sg = ah == bh ? (T)1 : (T)-1;
+            rw[at][ah][col[bt] + jj[bh]] = Cx<T>::make(a.x + sg * c.x, a.y + sg * c.y);
+          }
+        }
+  }
+}
+
+// Symmetric blocks: B -> M_c (reduced pool), inverted there, B^-1 (FP64 into
+// d_Binv, FP32 into d_Binv32); the others inverted in place in the inverse
+// pool of their precision.  The inverse pool of a non-symmetric block holds
+// a copy of B (FP64) or B rounded to FP32 on entry.
+template <typename T>
+static hipError_t invert_blocks_sym(qax_problem* p, const SymInvPlan& P, char* work,
+                                    typename Cx<T>::V* inv_pool) {
+  const hipStream_t s = p->stream;
+  MatDesc* d_red = (MatDesc*)(work + P.off_red);
+  MatDesc* d_plain = (MatDesc*)(work + P.off_plain);
+  SymInvDesc* d_desc = (SymInvDesc*)(work + P.off_desc);
+  SymInvRow* d_rows = (SymInvRow*)(work + P.off_rows);
+  double* gjw = (double*)(work + P.off_gj);
+  T* pool = (T*)(work + P.off_pool);
+  hipError_t e = hipSuccess;
+  if (!P.red.empty()) {
+    e = hipMemcpyAsync(d_red, P.red.data(), P.red.size() * sizeof(MatDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_desc, P.desc.data(), P.desc.size() * sizeof(SymInvDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_rows, P.rows.data(), P.rows.size() * sizeof(SymInvRow), hipMemcpyHostToDevice, s);
+  }
+  if (e == hipSuccess && !P.plain.empty())
+    e = hipMemcpyAsync(d_plain, P.plain.data(), P.plain.size() * sizeof(MatDesc), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
   timing_begin(p, QAX_K_INVERT);
-  e = gj_invert<float>(p, p->d_Binv32, d_md, (int)p->hblocks.size(), nmax, w2, true);
+  if (!P.red.empty()) {
+    hipLaunchKernelGGL(sym_reduce_kernel<T>, dim3((unsigned)P.rows.size()), dim3(256), 0, s, d_rows,
+                       d_desc, (const double2*)p->d_B, (typename Cx<T>::V*)pool);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = gj_invert<T>(p, pool, d_red, (int)P.red.size(), P.nmax_red, gjw, true);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(sym_expand_kernel<T>, dim3((unsigned)P.rows.size()), dim3(256), 0, s, d_rows,
+                         d_desc, (const typename Cx<T>::V*)pool, inv_pool);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess && !P.plain.empty())
+    e = gj_invert<T>(p, (T*)inv_pool, d_plain, (int)P.plain.size(), P.nmax_plain, gjw, true);
   timing_end(p, QAX_K_INVERT);
   return e;
+}
+
+// Every distinct self block inverted in FP32 for the mixed path (matrix cores
+// at the FP32 rate); the FP64 inverse is made on demand by
+// launch_invert_blocks64.
+hipError_t launch_invert_blocks(qax_problem* p, double* work) {
+  p->inv64_ready = false;
+  SymInvPlan P;
+  plan_sym_inverse(p, sizeof(float2), P);
+  // block_elems complex elements = block_elems (re, im) pairs; B rounded to
+  // FP32 (and into the inverse pool where a block is inverted as it is)
+  if (P.plain.empty()) {
+    hipError_t e = launch_convert_f32(p->stream, p->d_B, (float*)p->d_B32, 2 * p->block_elems);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(convert_f32_twice_kernel, dim3((unsigned)((p->block_elems + 255) / 256)),
+                       dim3(256), 0, p->stream, (const double2*)p->d_B, (float2*)p->d_B32,
+                       (float2*)p->d_Binv32, p->block_elems);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return invert_blocks_sym<float>(p, P, (char*)work, (float2*)p->d_Binv32);
 }
 
 // B and its FP64 inverse rounded to FP32 (the mixed path's operator blocks
@@ -1296,26 +1488,30 @@ hipError_t launch_factor_blocks64(qax_problem* p, double* work) {
   return hipGetLastError();
 }
 
-// FP64 inverse: copy B into Binv and invert in place in FP64.
+// FP64 inverse: symmetric blocks through their four reduced blocks, the
+// others copied into Binv and inverted in place.
 hipError_t launch_invert_blocks64(qax_problem* p, double* work) {
-  MatDesc* d_md;
-  double* w2;
-  int nmax;
-  hipError_t e = hipMemcpyAsync(p->d_Binv, p->d_B, (size_t)p->block_elems * 16,
-                                hipMemcpyDeviceToDevice, p->stream);
-  if (e == hipSuccess) e = upload_mats(p, work, &d_md, &w2, &nmax);
-  if (e != hipSuccess) return e;
-  timing_begin(p, QAX_K_INVERT);
-  e = gj_invert<double>(p, p->d_Binv, d_md, (int)p->hblocks.size(), nmax, w2, true);
-  timing_end(p, QAX_K_INVERT);
-  return e;
+  SymInvPlan P;
+  plan_sym_inverse(p, sizeof(double2), P);
+  if (P.red.empty()) {
+    hipError_t e = hipMemcpyAsync(p->d_Binv, p->d_B, (size_t)p->block_elems * 16,
+                                  hipMemcpyDeviceToDevice, p->stream);
+    if (e != hipSuccess) return e;
+  } else {
+    for (const MatDesc& m : P.plain) {
+      hipError_t e = hipMemcpyAsync(p->d_Binv + 2 * m.elem_off, p->d_B + 2 * m.elem_off,
+                                    (size_t)m.n * m.n * 16, hipMemcpyDeviceToDevice, p->stream);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return invert_blocks_sym<double>(p, P, (char*)work, (double2*)p->d_Binv);
 }
 
 size_t invert_blocks_work_bytes(qax_problem* p) {
-  int nmax = 0;
-  for (auto& b : p->hblocks) nmax = std::max(nmax, b.n);
-  const int nbk = (int)p->hblocks.size();
-  return ((nbk * sizeof(MatDesc) + 255) / 256) * 256 + gj_work_bytes(nbk, nmax);
+  SymInvPlan P64, P32;
+  plan_sym_inverse(p, sizeof(double2), P64);
+  plan_sym_inverse(p, sizeof(float2), P32);
+  return std::max(P64.bytes, P32.bytes);
 }
 
 // ---------------------------------------------------------------- dense system

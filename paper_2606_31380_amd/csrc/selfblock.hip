@@ -826,6 +826,30 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
   const double h = e1 - e0;
   const double thT = jT * PI / N;
   double2* row = pool + K.elem_off + (int64_t)T * n;
+  // Mirror-symmetric bodies: only the rows with s < n_s / 2 and j <= N are
+  // work items, and each entry (T, (s, j)) is also stored at the images of
+  // the pair: ((n_s - 1 - s_T, j_T), (n_s - 1 - s, j)) always, and, where
+  // the row's azimuth is neither 0 nor N (other rows are their own theta
+  // image), ((s_T, 2N - j_T), (s, -j)) and ((n_s - 1 - s_T, 2N - j_T), (n_s - 1 - s, -j)).
+  const int ns = GL_ORDER * B.n_panels, sT = T / nth;
+  const bool mir = mirror_symmetric(shape);
+  const bool mth = mir && jT != 0 && jT != N;
+  double2* row_t = pool + K.elem_off + (int64_t)((ns - 1 - sT) * nth + jT) * n;
+  double2* row_h = pool + K.elem_off + (int64_t)(sT * nth + (nth - jT) % nth) * n;
+  double2* row_ht = pool + K.elem_off + (int64_t)((ns - 1 - sT) * nth + (nth - jT) % nth) * n;
+  auto put = [&](int l, int j, double2 v) {
+    const int sc = ip * GL_ORDER + l;
+    row[(int64_t)sc * nth + j] = v;
+    if (mir) {
+      const int jm = j ? nth - j : 0;
+      const int64_t cm = (int64_t)(ns - 1 - sc) * nth;
+      row_t[cm + j] = v;
+      if (mth) {
+        row_h[(int64_t)sc * nth + jm] = v;
+        row_ht[cm + jm] = v;
+      }
+    }
+  };
 
   // target point (body frame)
   TargetGeom TG;
@@ -880,7 +904,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
         const double g = sqrt(nx * nx + ny * ny + nz * nz) * ir * INV_4PI * wq;
         v = make_double2(c * g, s * g);
       }
-      row[(int64_t)(ip * GL_ORDER + l) * nth + j] = v;
+      put(l, j, v);
     }
     return;
   }
@@ -1113,7 +1137,7 @@ __global__ __launch_bounds__(64) void assemble_self_kernel(
     for (int l = 0; l < GL_ORDER; ++l) {
       double2 v = g[l];
       if (diag && l == lT) v.x += 0.5;     // 1/2 I (second-kind formulations)
-      row[(int64_t)(ip * GL_ORDER + l) * nth + lane] = v;
+      put(l, lane, v);
     }
   }
 }
@@ -1135,8 +1159,14 @@ hipError_t launch_assemble_self(qax_problem* p) {
   std::vector<SelfTask> tasks;
   for (int bk = 0; bk < (int)p->hblocks.size(); ++bk) {
     const BodyDev& B = p->hbodies[p->hblocks[bk].rep_body];
-    for (int row = 0; row < p->hblocks[bk].n; ++row)
+    const int n = p->hblocks[bk].n, nth = B.n_theta, ns = n / nth;
+    // mirror-symmetric bodies: the rows s < n_s / 2, j <= N (the kernel
+    // stores the others as their images)
+    const bool mir = mirror_symmetric(B.shape);
+    for (int row = 0; row < n; ++row) {
+      if (mir && (row / nth >= ns / 2 || row % nth > nth / 2)) continue;
       for (int pan = 0; pan < B.n_panels; ++pan) tasks.push_back(SelfTask{bk, row, pan});
+    }
   }
   OuterRule R;
   outer_rule_host(R);

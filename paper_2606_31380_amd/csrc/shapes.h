@@ -40,6 +40,18 @@ __host__ __device__ __forceinline__ double panel_edge(int n_uni, int n_ref, int 
 
 constexpr double FOUR_PI_SHAPE = 12.566370614359172954;
 
+// Bodies mapped onto themselves by the reflections y -> -y (theta -> -theta)
+// and z -> -z (t -> -t): r and p even in t, z odd, q = 0 (the sphere,
+// spheroid and peanut, bent or not, and the quasi-ellipsoid; the panels and
+// their Gauss-Legendre nodes are symmetric about t = 0).  Node (s, j), s the
+// Gauss-Legendre node along the curve (panel * 16 + index, n_s in all) and j
+// the azimuth, has the images (s, (2N - j) mod 2N) and (n_s - 1 - s, j), and
+// every self-block entry is the same for a pair of nodes and for its images.
+__host__ __device__ __forceinline__ bool mirror_symmetric(int shape) {
+  return shape == QAX_SPHERE || shape == QAX_SPHEROID || shape == QAX_PEANUT ||
+         shape == QAX_QUASI_ELLIPSOID;
+}
+
 // Curve at parameter t, given st = sin t, ct = cos t.
 __device__ __forceinline__ Curve curve_from_sincos(int shape, double a, double c, double kappa,
                                                    double t, double st, double ct) {

@@ -1,0 +1,141 @@
+"""Self blocks of mirror-symmetric bodies (sphere, spheroid, peanut, bent or
+not, and the quasi-ellipsoid of Section 6.1): the bodies are mapped onto
+themselves by the reflections theta -> -theta and t -> -t, which permute the
+nodes, and the library assembles a quarter of the rows of B and inverts B
+through its four symmetry-reduced blocks.  Checked through the C interface:
+
+* the rows stored as images against the oracle (1e-12 of the row maximum);
+* B and B^-1 invariant under both node permutations (the t-reflection
+  bitwise: its rows are copies);
+* B^-1 against numpy's inverse of the GPU's B (1e-12), for symmetric bodies
+  and, in the same problem, bodies without the symmetry (spiral, conch);
+* the FP32 factorisation (reduced blocks inverted in FP32): B (B^-1)_32 v = v
+  to FP32 accuracy;
+* the mixed solver with the FP32 factorisation against the FP64 solver.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import geometry as geo
+from oracle import selfblock as oself
+from paper_2606_31380_amd import scenarios as sc
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2606_31380_amd import qax  # noqa: E402
+
+DEV = torch.device("cuda", 0)
+
+
+def bodies(specs, spacing=4.0):
+    b = sc.make_bodies(len(specs))
+    for i, (shape, a, c, kap, npan, nref, nth, t1, t2) in enumerate(specs):
+        b[i]["shape"], b[i]["a"], b[i]["c"], b[i]["kappa"] = shape, a, c, kap
+        b[i]["n_panels"], b[i]["n_ref"], b[i]["n_theta"] = npan, nref, nth
+        b[i]["theta1"], b[i]["theta2"] = t1, t2
+        b[i]["cx"], b[i]["cy"], b[i]["cz"] = spacing * i, 0.3 * i, -0.2 * i
+    return b
+
+
+# (shape, a, c, kappa, panels, refinements, n_theta, theta1, theta2)
+SYM = [(sc.SPHEROID, 0.5, 1.0, 0.25, 3, 0, 12, 0.7, 2.2),
+       (sc.PEANUT, 0.5, 0.3, 0.2, 2, 1, 16, 1.1, 0.4),
+       (sc.SPHERE, 0.5, 0.5, 0.0, 1, 0, 4, 0.0, 0.0),
+       (sc.QUASI_ELLIPSOID, 0.3, 1.0, 0.0, 2, 0, 10, 2.0, 1.3)]
+PLAIN = [(sc.CONCH, 0.6, 1.0, 0.0, 2, 0, 12, 1.1, 0.4),
+         (sc.SPIRAL, 0.5, 1.0, 0.0, 2, 1, 8, 0.3, 0.8)]
+
+
+def perms(n, nth):
+    """Node permutations of the two reflections and of their product."""
+    ns = n // nth
+    i = np.arange(n)
+    s, j = i // nth, i % nth
+    jm = (nth - j) % nth
+    return s * nth + jm, (ns - 1 - s) * nth + j, (ns - 1 - s) * nth + jm
+
+
+def fetch(P, bi, n, inverse=False):
+    t = torch.zeros(n * n, dtype=torch.complex128, device=DEV)
+    qax.qax_self_block(P.h, bi, t, inverse=inverse)
+    return t.cpu().numpy().reshape(n, n)
+
+
+@pytest.mark.parametrize("bi", range(len(SYM)))
+def test_image_rows_match_oracle(bi):
+    k = 3.0
+    s = sc.Scenario("sym", bodies(SYM), np.array([k]), sc.paper_direction())
+    body = geo.discretize(s).bodies[bi]
+    n, nth = body.n, body.n_theta
+    ph, pt, pht = perms(n, nth)
+    base = np.array([1, nth + 2, 5 * nth + nth // 2 - 1])     # rows assembled directly
+    rows = np.unique(np.concatenate([base, ph[base], pt[base], pht[base], [n - 1, n - nth]]))
+    want = oself.self_block(body, k, rows=rows)
+    with qax.Problem(s) as P:
+        qax.qax_assemble_self(P.h)
+        got = fetch(P, bi, n)[rows]
+    scale = np.abs(want).max(axis=1, keepdims=True)
+    assert (np.abs(got - want) / scale).max() < 1e-12
+
+
+def test_blocks_and_inverses_are_symmetric():
+    s = sc.Scenario("sym", bodies(SYM + PLAIN), np.array([2.5]), sc.paper_direction())
+    d = geo.discretize(s)
+    with qax.Problem(s) as P:
+        qax.qax_assemble_self(P.h)
+        for bi, body in enumerate(d.bodies):
+            n = body.n
+            B = fetch(P, bi, n)
+            Bi = fetch(P, bi, n, inverse=True)
+            ref = np.linalg.inv(B)
+            # the inverse of the block the GPU assembled, by numpy
+            assert np.abs(Bi - ref).max() < 1e-12 * np.abs(ref).max(), bi
+            assert np.abs(Bi @ B - np.eye(n)).max() < 1e-12, bi
+            if bi >= len(SYM):
+                continue
+            ph, pt, pht = perms(n, body.n_theta)
+            assert np.array_equal(B[np.ix_(pt, pt)], B), bi
+            for p in (ph, pht):
+                assert np.abs(B[np.ix_(p, p)] - B).max() <= 1e-15 * np.abs(B).max(), bi
+                assert np.abs(Bi[np.ix_(p, p)] - Bi).max() <= 1e-14 * np.abs(Bi).max(), bi
+            assert np.abs(Bi[np.ix_(pt, pt)] - Bi).max() <= 1e-14 * np.abs(Bi).max(), bi
+
+
+def test_fp32_factorisation_inverse():
+    s = sc.Scenario("sym", bodies(SYM + PLAIN), np.array([2.5]), sc.paper_direction())
+    with qax.Problem(s) as P:
+        qax.qax_set_factorization(P.h, qax.QAX_MIXED)
+        qax.qax_assemble_self(P.h)
+        rng = np.random.default_rng(3)
+        v = rng.standard_normal(P.N) + 1j * rng.standard_normal(P.N)
+        vt = torch.from_numpy(v).to(DEV)
+        y = P.vec()
+        qax.qax_block_apply(P.h, 1, qax.QAX_MIXED, vt, y)
+        z = P.vec()
+        qax.qax_block_apply(P.h, 0, qax.QAX_FP64, y, z)
+        back = z.cpu().numpy()
+        off = [int(x) for x in P.offsets]
+    for b in range(len(off) - 1):
+        sl = slice(off[b], off[b + 1])
+        err = np.linalg.norm(back[sl] - v[sl]) / np.linalg.norm(v[sl])
+        assert err < 1e-4, (b, err)
+
+
+def test_mixed_solve_with_fp32_factorisation():
+    s = sc.Scenario("sym", bodies(SYM + PLAIN), np.array([2.5]), sc.paper_direction())
+    with qax.Problem(s) as P:
+        qax.qax_assemble_self(P.h)
+        x64 = P.vec()
+        qax.qax_solve(P.h, qax.QAX_FP64, s.dirs, x64, 1, tol=1e-12)
+        qax.qax_set_factorization(P.h, qax.QAX_MIXED)
+        qax.qax_assemble_self(P.h)
+        xm = P.vec()
+        info = qax.qax_solve(P.h, qax.QAX_MIXED, s.dirs, xm, 1, tol=1e-10)
+        a, b = x64.cpu().numpy(), xm.cpu().numpy()
+    assert info["rel_res"] <= 1e-10
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-9
