@@ -58,8 +58,9 @@ struct PairTask {
 // part[soff] (SYM_T complex128 values per slot).
 constexpr int SYM_T = 256;
 constexpr int SYM_SMAX = 8;
-// largest workspace of one launch of the reciprocal kernels, complex values
-// (960 MB); more super-tasks are split into several launches
+// largest workspace of one launch of the reciprocal kernels, complex128
+// values (960 MB; twice as many complex64 slots of the FP32 kernel); more
+// super-tasks are split into several launches
 constexpr int64_t SYM_SLOT_CAP = 60000000;
 struct SymBlock {
   int64_t n0;          // first node
@@ -190,7 +191,6 @@ struct qax_problem {
       std::vector<int64_t> lptr;           // per launch: n_blocks + 1 list offsets
       std::vector<int64_t> list;           // slot offsets
       int64_t max_slots = 0;               // complex values of the largest launch
-      bool alias = false;                  // device arrays owned by the other precision's plan
       void* d_mem = nullptr;
       qax::SymSuper* d_supers = nullptr;
       int64_t* d_lptr = nullptr;

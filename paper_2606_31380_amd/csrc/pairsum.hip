@@ -454,11 +454,14 @@ __device__ __forceinline__ uint32_t sym_row_mask(const SymSuper& T, int ii) {
 }
 
 // Inactive problem of a lockstep solve: the super-task's slots hold zeros.
+template <typename S2>
 __device__ __forceinline__ bool sym_inactive(const SymSuper& T, const int32_t* __restrict__ seg_active,
-                                             double2* __restrict__ part) {
+                                             S2* __restrict__ part) {
   if (!seg_active || seg_active[T.problem] != 0) return false;
-  for (int e = threadIdx.x; e < (T.ni + T.nj) * SYM_T; e += blockDim.x)
-    part[T.toff + e] = make_double2(0.0, 0.0);
+  for (int e = threadIdx.x; e < (T.ni + T.nj) * SYM_T; e += blockDim.x) {
+    part[T.toff + e].x = 0;
+    part[T.toff + e].y = 0;
+  }
   return true;
 }
 
@@ -485,6 +488,9 @@ __device__ __forceinline__ bool sym_inactive(const SymSuper& T, const int32_t* _
 // Real parts are accumulated negated (one sign flip per slot).  Target sums
 // are FP32 per chunk and compensated (TwoSum) across chunks and columns;
 // source sums are FP32 over the chunk's 128 targets of a wavefront, then FP64.
+// A square's sums are stored rounded to complex64 slots (half the bytes of
+// complex128, so a launch holds twice the squares in the same workspace) and
+// the reduction adds the slots in FP64.
 // Five wavefronts per SIMD (at most 102 registers; the few spills are outside
 // the pair loop): 1.4 % faster than the four the unconstrained allocation
 // allows, on the 1000-body workload.
@@ -494,7 +500,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5))) void p
     const BodyDev* __restrict__ bodies, const int32_t* __restrict__ node_body,
     const float4* __restrict__ loc32, const float4* __restrict__ aw32,
     const float* __restrict__ ew32, const double2* __restrict__ mu,
-    const int32_t* __restrict__ seg_active, double2* __restrict__ part) {
+    const int32_t* __restrict__ seg_active, float2* __restrict__ part) {
   const SymSuper T = supers[blockIdx.x];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (sym_inactive(T, seg_active, part)) return;
@@ -690,12 +696,12 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5))) void p
           if (wv == 0 && (!half || lane < 32) && sj < cl) {
             const double vr = -((double)acc0 + (double)sX[0][lane]) * sc3;
             const double vi = ((double)acc1 + (double)sX[1][lane]) * sc3;
-            double2* d = part + T.soff + (int64_t)jj * SYM_T + cs + sj;
+            float2* d = part + T.soff + (int64_t)jj * SYM_T + cs + sj;
             if (first_src) {
-              *d = make_double2(vr, vi);
+              *d = make_float2((float)vr, (float)vi);
             } else {
-              const double2 o = *d;
-              *d = make_double2(o.x + vr, o.y + vi);
+              const float2 o = *d;
+              *d = make_float2((float)(o.x + vr), (float)(o.y + vi));
             }
           }
         }
@@ -707,7 +713,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5))) void p
       const int loc = wv * 128 + t * 64 + lane;
       if (loc < BI.n)
         part[T.toff + (int64_t)ii * SYM_T + loc] =
-            make_double2(-((double)nsr[t] + (double)ncr[t]) * sc3, ((double)tsi[t] + (double)tci[t]) * sc3);
+            make_float2((float)(-((double)nsr[t] + (double)ncr[t]) * sc3),
+                        (float)(((double)tsi[t] + (double)tci[t]) * sc3));
     }
   }
 }
@@ -944,8 +951,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) void p
 // consecutive nodes; wavefront w adds the list entries w, w + 4, ... of each
 // node, and the four sums are added in wavefront order (a fixed order).
 // mode 0: out = sum, 1: out += sum.
+template <typename S2>
 __global__ __launch_bounds__(256) void reduce_sym_kernel(
-    const double2* __restrict__ part, const int32_t* __restrict__ node_block,
+    const S2* __restrict__ part, const int32_t* __restrict__ node_block,
     const SymBlock* __restrict__ blocks, const int64_t* __restrict__ lptr,
     const int64_t* __restrict__ list, int64_t N, double2* __restrict__ out, int mode) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -960,9 +968,9 @@ __global__ __launch_bounds__(256) void reduce_sym_kernel(
     const int64_t rel = n - blocks[blk].n0;
 #pragma unroll 4
     for (int64_t e = e0 + w; e < e1; e += 4) {
-      const double2 v = part[list[e] + rel];
-      acc.x += v.x;
-      acc.y += v.y;
+      const S2 v = part[list[e] + rel];
+      acc.x += (double)v.x;
+      acc.y += (double)v.y;
     }
   }
   red[w][lane] = acc;
@@ -1171,22 +1179,18 @@ static hipError_t upload_sym_blocks(qax_problem* p) {
   return hipStreamSynchronize(p->stream);
 }
 
-// Drop plan pi's device arrays (after the stream has drained); arrays shared
-// with the other precision's plan pass to that plan.
+// Drop plan pi's device arrays (after the stream has drained).
 hipError_t release_sym_plan(qax_problem* p, int pi) {
   auto& P = p->sym.plan[pi];
-  auto& O = p->sym.plan[1 - pi];
   if (P.d_mem) {
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return e;
-    if (O.d_mem == P.d_mem) O.alias = false;
-    else if (!P.alias) dev_release(p, P.d_mem);
+    dev_release(p, P.d_mem);
   }
   P.d_mem = nullptr;
   P.d_supers = nullptr;
   P.d_lptr = nullptr;
   P.d_list = nullptr;
-  P.alias = false;
   P.s = 0;
   P.supers.clear();
   P.launch_super.clear();
@@ -1253,21 +1257,8 @@ hipError_t plan_sym(qax_problem* p, int pi, int s, int cu_count) {
   hipError_t e = release_sym_plan(p, pi);
   if (e != hipSuccess) return e;
   ++p->generation;   // captured solver steps hold the old launch sizes
-  const auto& O = S.plan[1 - pi];
-  if (O.d_mem && O.s == s) {
-    // the other precision's kernels run the same squares: share its plan
-    auto& P = S.plan[pi];
-    P.s = s;
-    P.launch_super = O.launch_super;
-    P.max_slots = O.max_slots;
-    P.d_mem = O.d_mem;
-    P.d_supers = O.d_supers;
-    P.d_lptr = O.d_lptr;
-    P.d_list = O.d_list;
-    P.alias = true;
-    return hipSuccess;
-  }
-  plan_sym_supers(p, pi, s, SYM_SLOT_CAP);
+  // the FP32 slots are complex64: twice as many fit the same workspace
+  plan_sym_supers(p, pi, s, SYM_SLOT_CAP * (pi == 1 ? 2 : 1));
   return upload_sym_plan(p, pi);
 }
 
@@ -1441,7 +1432,7 @@ size_t pair_work_bytes(const qax_problem* p, int prec, int nrhs) {
   const int slots = prec == QAX_FP64 ? p->slots64 : p->slots32;
   size_t b = std::max((size_t)slots * p->N * nrhs * 16, lattice_work_bytes(p, nrhs));
   if (nrhs == 1 && p->sym.ok)
-    b = std::max(b, (size_t)p->sym.plan[prec == QAX_FP64 ? 0 : 1].max_slots * 16);
+    b = std::max(b, (size_t)p->sym.plan[prec == QAX_FP64 ? 0 : 1].max_slots * (prec == QAX_FP64 ? 16 : 8));
   return b;
 }
 
@@ -1489,19 +1480,27 @@ hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* o
           if (form == 1)
             hipLaunchKernelGGL(pair_sum_f32_sym_kernel<1>, grid, dim3(128), 0, p->stream, P.d_supers + s0,
                                S.d_blocks, p->d_bodies, p->d_node_body, (const float4*)p->d_loc32,
-                               (const float4*)p->d_aw32, p->d_ew32, (const double2*)mu, p->seg_active, part);
+                               (const float4*)p->d_aw32, p->d_ew32, (const double2*)mu, p->seg_active,
+                               (float2*)partial);
           else
             hipLaunchKernelGGL(pair_sum_f32_sym_kernel<0>, grid, dim3(128), 0, p->stream, P.d_supers + s0,
                                S.d_blocks, p->d_bodies, p->d_node_body, (const float4*)p->d_loc32,
-                               (const float4*)p->d_aw32, p->d_ew32, (const double2*)mu, p->seg_active, part);
+                               (const float4*)p->d_aw32, p->d_ew32, (const double2*)mu, p->seg_active,
+                               (float2*)partial);
         }
         timing_end(p, kind);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
       }
-      hipLaunchKernelGGL(reduce_sym_kernel, rgrid, dim3(256), 0, p->stream, (const double2*)part,
-                         S.d_node_block, S.d_blocks, P.d_lptr + (size_t)l * (nblk + 1), P.d_list, p->N,
-                         (double2*)out, l == 0 ? (accumulate ? 1 : 0) : 1);
+      const int mode = l == 0 ? (accumulate ? 1 : 0) : 1;
+      if (f64)
+        hipLaunchKernelGGL(reduce_sym_kernel<double2>, rgrid, dim3(256), 0, p->stream, (const double2*)part,
+                           S.d_node_block, S.d_blocks, P.d_lptr + (size_t)l * (nblk + 1), P.d_list, p->N,
+                           (double2*)out, mode);
+      else
+        hipLaunchKernelGGL(reduce_sym_kernel<float2>, rgrid, dim3(256), 0, p->stream, (const float2*)partial,
+                           S.d_node_block, S.d_blocks, P.d_lptr + (size_t)l * (nblk + 1), P.d_list, p->N,
+                           (double2*)out, mode);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
