@@ -951,9 +951,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(4))) void p
 // consecutive nodes; wavefront w adds the list entries w, w + 4, ... of each
 // node, and the four sums are added in wavefront order (a fixed order).
 // mode 0: out = sum, 1: out += sum.
-template <typename S2>
 __global__ __launch_bounds__(256) void reduce_sym_kernel(
-    const S2* __restrict__ part, const int32_t* __restrict__ node_block,
+    const double2* __restrict__ part, const int32_t* __restrict__ node_block,
     const SymBlock* __restrict__ blocks, const int64_t* __restrict__ lptr,
     const int64_t* __restrict__ list, int64_t N, double2* __restrict__ out, int mode) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -968,9 +967,9 @@ __global__ __launch_bounds__(256) void reduce_sym_kernel(
     const int64_t rel = n - blocks[blk].n0;
 #pragma unroll 4
     for (int64_t e = e0 + w; e < e1; e += 4) {
-      const S2 v = part[list[e] + rel];
-      acc.x += (double)v.x;
-      acc.y += (double)v.y;
+      const double2 v = part[list[e] + rel];
+      acc.x += v.x;
+      acc.y += v.y;
     }
   }
   red[w][lane] = acc;
@@ -983,6 +982,49 @@ __global__ __launch_bounds__(256) void reduce_sym_kernel(
       o.y += red[q][lane].y;
     }
     out[n] = o;
+  }
+}
+
+// The same for complex64 slots, two nodes per lane (16-byte loads): a
+// workgroup takes 128 consecutive nodes.  Block starts and lengths are even
+// (node counts are multiples of 32), so both nodes of a lane share a block.
+__global__ __launch_bounds__(256) void reduce_sym32_kernel(
+    const float4* __restrict__ part, const int32_t* __restrict__ node_block,
+    const SymBlock* __restrict__ blocks, const int64_t* __restrict__ lptr,
+    const int64_t* __restrict__ list, int64_t N, double2* __restrict__ out, int mode) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t n = (int64_t)blockIdx.x * 128 + 2 * lane;
+  __shared__ double4 red[4][64];
+  double4 acc = make_double4(0.0, 0.0, 0.0, 0.0);
+  int64_t e0 = 0, e1 = 0;
+  if (n < N) {
+    const int blk = node_block[n];
+    e0 = lptr[blk];
+    e1 = lptr[blk + 1];
+    const int64_t rel2 = (n - blocks[blk].n0) >> 1;   // pair index within a slot
+#pragma unroll 4
+    for (int64_t e = e0 + w; e < e1; e += 4) {
+      const float4 v = part[(list[e] >> 1) + rel2];
+      acc.x += (double)v.x;
+      acc.y += (double)v.y;
+      acc.z += (double)v.z;
+      acc.w += (double)v.w;
+    }
+  }
+  red[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && n < N && (mode == 0 || e1 > e0)) {
+    double2 o0 = mode ? out[n] : make_double2(0.0, 0.0);
+    double2 o1 = mode ? out[n + 1] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      o0.x += red[q][lane].x;
+      o0.y += red[q][lane].y;
+      o1.x += red[q][lane].z;
+      o1.y += red[q][lane].w;
+    }
+    out[n] = o0;
+    out[n + 1] = o1;
   }
 }
 
@@ -1494,13 +1536,13 @@ hipError_t launch_pair_sum(qax_problem* p, int prec, const double* mu, double* o
       }
       const int mode = l == 0 ? (accumulate ? 1 : 0) : 1;
       if (f64)
-        hipLaunchKernelGGL(reduce_sym_kernel<double2>, rgrid, dim3(256), 0, p->stream, (const double2*)part,
+        hipLaunchKernelGGL(reduce_sym_kernel, rgrid, dim3(256), 0, p->stream, (const double2*)part,
                            S.d_node_block, S.d_blocks, P.d_lptr + (size_t)l * (nblk + 1), P.d_list, p->N,
                            (double2*)out, mode);
       else
-        hipLaunchKernelGGL(reduce_sym_kernel<float2>, rgrid, dim3(256), 0, p->stream, (const float2*)partial,
-                           S.d_node_block, S.d_blocks, P.d_lptr + (size_t)l * (nblk + 1), P.d_list, p->N,
-                           (double2*)out, mode);
+        hipLaunchKernelGGL(reduce_sym32_kernel, dim3((unsigned)((p->N + 127) / 128)), dim3(256), 0, p->stream,
+                           (const float4*)partial, S.d_node_block, S.d_blocks, P.d_lptr + (size_t)l * (nblk + 1),
+                           P.d_list, p->N, (double2*)out, mode);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
