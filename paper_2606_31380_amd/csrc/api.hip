@@ -230,6 +230,7 @@ static void free_geometry(qax_problem* p, bool keep_plans = false) {
   dev_release(p, p->d_gemm_tasks);
   p->d_gemm_tasks = nullptr;
   if (!keep_plans) free_pair_plans(p);
+  free_sym_apply(p);
   p->gemm_tasks.clear();
   lattice_free(p);
 }
@@ -544,6 +545,7 @@ extern "C" qax_status qax_assemble_self(qax_problem* p, double* t_setup_s) {
     QCHECK(dev_alloc(p, (void**)&p->d_Binv32, (size_t)p->block_elems * 8), "alloc inverse blocks fp32");
     QCHECK(dev_alloc(p, (void**)&p->d_B32, (size_t)p->block_elems * 8), "alloc self blocks fp32");
   }
+  QCHECK(setup_sym_apply(p), "reduced inverses");
   QCHECK(launch_assemble_self(p), "assemble_self");
   QBUF(work, double, "gj_work", invert_blocks_work_bytes(p));
   if (p->factor_prec == QAX_FP64) {

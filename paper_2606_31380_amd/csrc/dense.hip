@@ -185,9 +185,18 @@ static void gemv_launch(qax_problem* p, const MT* pool, const double* v, double*
 hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double* v, double* out,
                              int nrhs, bool accumulate);
 
+static void launch_sym_apply(qax_problem* p, int prec, const double* v, double* out, bool accumulate);
+
 hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,
                               int nrhs, bool accumulate) {
   const int kind = prec == QAX_MIXED ? QAX_K_BLOCK_APPLY_F32 : QAX_K_BLOCK_APPLY;
+  if (inverse && nrhs == 1 && p->symap.on && (prec == QAX_MIXED || p->inv64_ready)) {
+    // every block mirror-symmetric: through the four reduced inverses
+    timing_begin(p, kind);
+    launch_sym_apply(p, prec, v, out, accumulate);
+    timing_end(p, kind);
+    return hipGetLastError();
+  }
   if (nrhs >= 4) {
     // several right-hand sides: batched complex GEMM on the matrix cores
     timing_begin(p, kind);
@@ -1309,7 +1318,8 @@ static void plan_sym_inverse(const qax_problem* p, size_t elem_bytes, SymInvPlan
   const size_t gj = std::max(P.red.empty() ? 0 : gj_work_bytes((int)P.red.size(), P.nmax_red),
                              P.plain.empty() ? 0 : gj_work_bytes((int)P.plain.size(), P.nmax_plain));
   P.off_pool = P.off_gj + align256(gj);
-  P.bytes = P.off_pool + (size_t)P.red_elems * elem_bytes;
+  // the reduced blocks live in the workspace unless the handle keeps them
+  P.bytes = P.off_pool + (p->symap.on ? 0 : (size_t)P.red_elems * elem_bytes);
 }
 
 // M_c from B for one orbit row (o1) per workgroup, columns o2 over the threads.
@@ -1400,6 +1410,150 @@ __global__ __launch_bounds__(256) void sym_expand_kernel(const SymInvRow* __rest
   }
 }
 
+// ---- one right-hand side through the reduced inverses (every block
+// mirror-symmetric).  With v = sum_c sum_o u_c[o] e_c(o), e_c(o) the vector
+// with chi_c(g) at the nodes g(o) of orbit o,
+//   u_c[o] = |orbit|^-1 sum over the distinct nodes g(o) of chi_c(g) v[g(o)],
+// B^-1 v = sum_c sum_o (M_c^-1 u_c)[o] e_c(o).  Per body the reduced vectors
+// hold the four segments c = 0, 1, 2, 3 (lengths (n_s/2)(N + 1),
+// (n_s/2)(N - 1), (n_s/2)(N + 1), (n_s/2)(N - 1)) at the body's node offset.
+__global__ __launch_bounds__(256) void sym_vec_reduce_kernel(const SymBody* __restrict__ bodies,
+                                                             const double2* __restrict__ v,
+                                                             double2* __restrict__ u,
+                                                             const int32_t* __restrict__ seg_active) {
+  const SymBody B = bodies[blockIdx.x];
+  if (seg_active && seg_active[B.problem] == 0) return;
+  const int nth = B.nth, N = nth / 2, ns = B.ns, half = ns / 2, np = N + 1, nm = N - 1;
+  const int64_t lp = (int64_t)half * np, lm = (int64_t)half * nm;
+  const double2* vb = v + B.off;
+  double2* ub = u + B.off;
+  for (int o = threadIdx.x; o < half * np; o += blockDim.x) {
+    const int s = o / np, j = o % np, sm = ns - 1 - s;
+    const double2 a = vb[s * nth + j], at = vb[sm * nth + j];
+    if (j == 0 || j == N) {
+      ub[o] = make_double2(0.5 * (a.x + at.x), 0.5 * (a.y + at.y));
+      ub[lp + lm + o] = make_double2(0.5 * (a.x - at.x), 0.5 * (a.y - at.y));
+    } else {
+      const double2 ah = vb[s * nth + nth - j], aht = vb[sm * nth + nth - j];
+      const int64_t o1 = (int64_t)s * nm + j - 1;
+      ub[o] = make_double2(0.25 * (a.x + ah.x + at.x + aht.x), 0.25 * (a.y + ah.y + at.y + aht.y));
+      ub[lp + o1] = make_double2(0.25 * (a.x - ah.x + at.x - aht.x), 0.25 * (a.y - ah.y + at.y - aht.y));
+      ub[lp + lm + o] = make_double2(0.25 * (a.x + ah.x - at.x - aht.x), 0.25 * (a.y + ah.y - at.y - aht.y));
+      ub[2 * lp + lm + o1] =
+          make_double2(0.25 * (a.x - ah.x - at.x + aht.x), 0.25 * (a.y - ah.y - at.y + aht.y));
+    }
+  }
+}
+
+// w = M_c^-1 u per segment: 16 rows per workgroup (four per wavefront), the
+// segment's input staged in LDS, FP64 accumulation (as block_gemv_f32_lds_kernel).
+template <typename MT, int VEC>
+__global__ __launch_bounds__(256) void sym_seg_gemv_kernel(const SymSeg* __restrict__ segs,
+                                                           const int2* __restrict__ groups,
+                                                           const MT* __restrict__ pool,
+                                                           const double2* __restrict__ u,
+                                                           double2* __restrict__ w,
+                                                           const int32_t* __restrict__ seg_active) {
+  typedef MT vec_t __attribute__((ext_vector_type(2 * VEC)));
+  __shared__ double2 vs[GV_CH];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int2 G = groups[blockIdx.x];
+  const SymSeg S = segs[G.x];
+  if (seg_active && seg_active[S.problem] == 0) return;
+  const int n = S.n, r0 = G.y + wave * (GV_ROWS / 4);
+  const double2* ub = u + S.voff;
+  double ar[GV_ROWS / 4], ai[GV_ROWS / 4];
+#pragma unroll
+  for (int q = 0; q < GV_ROWS / 4; ++q) { ar[q] = 0.0; ai[q] = 0.0; }
+  for (int c0 = 0; c0 < n; c0 += GV_CH) {
+    const int cn = min(GV_CH, n - c0);
+    __syncthreads();
+    for (int q = threadIdx.x; q < cn; q += 256) vs[q] = ub[c0 + q];
+    __syncthreads();
+    const MT* a = pool + 2 * (S.moff + (int64_t)r0 * n + c0);
+    for (int j0 = lane * VEC; j0 < cn; j0 += 64 * VEC) {
+      vec_t av[GV_ROWS / 4];
+#pragma unroll
+      for (int rr = 0; rr < GV_ROWS / 4; ++rr) {
+        if (r0 + rr < n) av[rr] = *(const vec_t*)(a + 2 * ((int64_t)rr * n + j0));
+        else av[rr] = (vec_t)0;
+      }
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        const double2 x = vs[j0 + q];
+#pragma unroll
+        for (int rr = 0; rr < GV_ROWS / 4; ++rr) {
+          const double mr = (double)av[rr][2 * q], mi = (double)av[rr][2 * q + 1];
+          ar[rr] = fma(mr, x.x, fma(-mi, x.y, ar[rr]));
+          ai[rr] = fma(mr, x.y, fma(mi, x.x, ai[rr]));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int rr = 0; rr < GV_ROWS / 4; ++rr) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      ar[rr] += __shfl_xor(ar[rr], off);
+      ai[rr] += __shfl_xor(ai[rr], off);
+    }
+    if (lane == 0 && r0 + rr < n) w[S.voff + r0 + rr] = make_double2(ar[rr], ai[rr]);
+  }
+}
+
+// y (+)= sum_c chi_c(g) w_c[o] at the nodes g(o).
+__global__ __launch_bounds__(256) void sym_vec_expand_kernel(const SymBody* __restrict__ bodies,
+                                                             const double2* __restrict__ w,
+                                                             double2* __restrict__ y, int accumulate,
+                                                             const int32_t* __restrict__ seg_active) {
+  const SymBody B = bodies[blockIdx.x];
+  const int nth = B.nth, N = nth / 2, ns = B.ns, half = ns / 2, np = N + 1, nm = N - 1;
+  double2* yb = y + B.off;
+  if (seg_active && seg_active[B.problem] == 0) {
+    // a converged lockstep segment: its input is zero, so is the output
+    if (!accumulate)
+      for (int e = threadIdx.x; e < ns * nth; e += blockDim.x) yb[e] = make_double2(0.0, 0.0);
+    return;
+  }
+  const int64_t lp = (int64_t)half * np, lm = (int64_t)half * nm;
+  const double2* wb = w + B.off;
+  auto put = [&](int e, double re, double im) {
+    double2 o = accumulate ? yb[e] : make_double2(0.0, 0.0);
+    o.x += re;
+    o.y += im;
+    yb[e] = o;
+  };
+  for (int o = threadIdx.x; o < half * np; o += blockDim.x) {
+    const int s = o / np, j = o % np, sm = ns - 1 - s;
+    const double2 m0 = wb[o], m2 = wb[lp + lm + o];
+    if (j == 0 || j == N) {
+      put(s * nth + j, m0.x + m2.x, m0.y + m2.y);
+      put(sm * nth + j, m0.x - m2.x, m0.y - m2.y);
+    } else {
+      const int64_t o1 = (int64_t)s * nm + j - 1;
+      const double2 m1 = wb[lp + o1], m3 = wb[2 * lp + lm + o1];
+      put(s * nth + j, m0.x + m1.x + m2.x + m3.x, m0.y + m1.y + m2.y + m3.y);
+      put(sm * nth + j, m0.x + m1.x - m2.x - m3.x, m0.y + m1.y - m2.y - m3.y);
+      put(s * nth + nth - j, m0.x - m1.x + m2.x - m3.x, m0.y - m1.y + m2.y - m3.y);
+      put(sm * nth + nth - j, m0.x - m1.x - m2.x + m3.x, m0.y - m1.y - m2.y + m3.y);
+    }
+  }
+}
+
+static void launch_sym_apply(qax_problem* p, int prec, const double* v, double* out, bool accumulate) {
+  auto& A = p->symap;
+  hipLaunchKernelGGL(sym_vec_reduce_kernel, dim3((unsigned)A.n_bodies), dim3(256), 0, p->stream, A.d_bodies,
+                     (const double2*)v, (double2*)A.d_u, p->seg_active);
+  if (prec == QAX_MIXED)
+    hipLaunchKernelGGL((sym_seg_gemv_kernel<float, 4>), dim3((unsigned)A.n_groups), dim3(256), 0, p->stream,
+                       A.d_segs, A.d_groups, A.d_Minv32, (const double2*)A.d_u, (double2*)A.d_w, p->seg_active);
+  else
+    hipLaunchKernelGGL((sym_seg_gemv_kernel<double, 2>), dim3((unsigned)A.n_groups), dim3(256), 0, p->stream,
+                       A.d_segs, A.d_groups, A.d_Minv, (const double2*)A.d_u, (double2*)A.d_w, p->seg_active);
+  hipLaunchKernelGGL(sym_vec_expand_kernel, dim3((unsigned)A.n_bodies), dim3(256), 0, p->stream, A.d_bodies,
+                     (const double2*)A.d_w, (double2*)out, accumulate ? 1 : 0, p->seg_active);
+}
+
 // Symmetric blocks: B -> M_c (reduced pool), inverted there, B^-1 (FP64 into
 // d_Binv, FP32 into d_Binv32); the others inverted in place in the inverse
 // pool of their precision.  The inverse pool of a non-symmetric block holds
@@ -1414,6 +1568,7 @@ static hipError_t invert_blocks_sym(qax_problem* p, const SymInvPlan& P, char* w
   SymInvRow* d_rows = (SymInvRow*)(work + P.off_rows);
   double* gjw = (double*)(work + P.off_gj);
   T* pool = (T*)(work + P.off_pool);
+  if (p->symap.on) pool = sizeof(T) == 8 ? (T*)p->symap.d_Minv : (T*)p->symap.d_Minv32;
   hipError_t e = hipSuccess;
   if (!P.red.empty()) {
     e = hipMemcpyAsync(d_red, P.red.data(), P.red.size() * sizeof(MatDesc), hipMemcpyHostToDevice, s);
@@ -1482,6 +1637,10 @@ __global__ void round_blocks_kernel(const double2* __restrict__ b, const double2
 hipError_t launch_factor_blocks64(qax_problem* p, double* work) {
   hipError_t e = launch_invert_blocks64(p, work);
   if (e != hipSuccess) return e;
+  if (p->symap.on) {
+    e = launch_convert_f32(p->stream, p->symap.d_Minv, p->symap.d_Minv32, 2 * p->symap.elems);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(round_blocks_kernel, dim3((unsigned)((p->block_elems + 255) / 256)), dim3(256), 0,
                      p->stream, (const double2*)p->d_B, (const double2*)p->d_Binv, (float2*)p->d_B32,
                      (float2*)p->d_Binv32, p->block_elems);
@@ -1505,6 +1664,75 @@ hipError_t launch_invert_blocks64(qax_problem* p, double* work) {
     }
   }
   return invert_blocks_sym<double>(p, P, (char*)work, (double2*)p->d_Binv);
+}
+
+// The reduced inverses and the tables of the one-right-hand-side apply, when
+// every block is mirror-symmetric (after qax_build, before the first
+// factorisation).
+void free_sym_apply(qax_problem* p) {
+  auto& A = p->symap;
+  dev_release(p, A.d_Minv);
+  dev_release(p, A.d_Minv32);
+  dev_release(p, A.d_mem);
+  A = qax_problem::SymApply{};
+}
+
+hipError_t setup_sym_apply(qax_problem* p) {
+  if (p->symap.on) return hipSuccess;
+  for (const BlockDev& bk : p->hblocks)
+    if (!mirror_symmetric(p->hbodies[bk.rep_body].shape)) return hipSuccess;
+  if (p->hblocks.empty()) return hipSuccess;
+  SymInvPlan P;
+  plan_sym_inverse(p, sizeof(double2), P);   // m_off of every block (all symmetric: desc = block)
+  std::vector<SymSeg> segs;
+  std::vector<int2> groups;
+  std::vector<SymBody> bodies;
+  for (int b = 0; b < p->n_bodies; ++b) {
+    const BodyDev& B = p->hbodies[b];
+    const SymInvDesc& D = P.desc[B.block];
+    const int nth = B.n_theta, N = nth / 2, ns = D.ns, half = ns / 2;
+    bodies.push_back(SymBody{B.off, ns, nth, B.problem});
+    int64_t start = 0;
+    for (int c = 0; c < 4; ++c) {
+      const int m = half * ((c & 1) ? N - 1 : N + 1);
+      const int si = (int)segs.size();
+      segs.push_back(SymSeg{B.off + start, D.m_off[c], m, B.problem});
+      for (int r = 0; r < m; r += GV_ROWS) groups.push_back(make_int2(si, r));
+      start += m;
+    }
+  }
+  auto& A = p->symap;
+  A.elems = P.red_elems;
+  A.n_groups = (int)groups.size();
+  A.n_bodies = (int)bodies.size();
+  const size_t bs = align256(segs.size() * sizeof(SymSeg)), bg = align256(groups.size() * sizeof(int2)),
+               bb = align256(bodies.size() * sizeof(SymBody)), bv = align256((size_t)p->N * 16);
+  hipError_t e = dev_alloc(p, (void**)&A.d_Minv, (size_t)A.elems * 16);
+  if (e == hipSuccess) e = dev_alloc(p, (void**)&A.d_Minv32, (size_t)A.elems * 8);
+  if (e == hipSuccess) e = dev_alloc(p, &A.d_mem, bs + bg + bb + 2 * bv);
+  if (e != hipSuccess) {
+    free_sym_apply(p);
+    return e;
+  }
+  char* m = (char*)A.d_mem;
+  A.d_segs = (SymSeg*)m;
+  A.d_groups = (int2*)(m + bs);
+  A.d_bodies = (SymBody*)(m + bs + bg);
+  A.d_u = (double*)(m + bs + bg + bb);
+  A.d_w = (double*)(m + bs + bg + bb + bv);
+  e = hipMemcpyAsync(A.d_segs, segs.data(), segs.size() * sizeof(SymSeg), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(A.d_groups, groups.data(), groups.size() * sizeof(int2), hipMemcpyHostToDevice, p->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(A.d_bodies, bodies.data(), bodies.size() * sizeof(SymBody), hipMemcpyHostToDevice,
+                       p->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) {
+    free_sym_apply(p);
+    return e;
+  }
+  A.on = true;
+  return hipSuccess;
 }
 
 size_t invert_blocks_work_bytes(qax_problem* p) {

@@ -82,6 +82,22 @@ struct GemmTask {
   int32_t row0;
 };
 
+// One right-hand side through the symmetry-reduced inverses (every block
+// mirror-symmetric): segment c of a body, the rows of its reduced inverse
+// M_c^-1 (order n) applied to the segment of the reduced vector at voff.
+struct SymSeg {
+  int64_t voff;      // first entry of the segment in the reduced vectors (node offset of the body + start)
+  int64_t moff;      // complex offset of M_c^-1 in the reduced pools
+  int32_t n;         // order
+  int32_t problem;
+};
+// A symmetric body for the vector transforms.
+struct SymBody {
+  int64_t off;       // first node
+  int32_t ns, nth;   // Gauss-Legendre nodes along the curve, azimuths
+  int32_t problem;
+};
+
 // Work item of the self-block assembly: one target row x one near panel.
 struct SelfTask {
   int32_t block;   // distinct block
@@ -164,6 +180,22 @@ struct qax_problem {
   int solver = QAX_SOLVER_LOCKSTEP;   // several right-hand sides: lockstep or block GMRES
   float* d_Binv32 = nullptr;
   float* d_B32 = nullptr;       // B rounded to FP32 (the mixed path's operator blocks)
+  // every block mirror-symmetric: the inverses also as their four reduced
+  // blocks (complex128 valid with inv64_ready, complex64 after every
+  // assembly), and the tables of the one-right-hand-side apply through them
+  struct SymApply {
+    bool on = false;
+    double* d_Minv = nullptr;
+    float* d_Minv32 = nullptr;
+    int64_t elems = 0;                 // complex entries of the reduced pools
+    void* d_mem = nullptr;             // the tables and the reduced vectors
+    qax::SymSeg* d_segs = nullptr;
+    int2* d_groups = nullptr;          // (segment, first row) of 16-row groups
+    qax::SymBody* d_bodies = nullptr;
+    double* d_u = nullptr;             // reduced input vector (N complex)
+    double* d_w = nullptr;             // reduced output vector (N complex)
+    int n_groups = 0, n_bodies = 0;
+  } symap;
 
   // pair-sum task tables per precision
   std::vector<qax::PairTask> tasks64, tasks32;
@@ -310,6 +342,10 @@ hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const doubl
 hipError_t launch_invert_blocks(qax_problem* p, double* work);     // FP32 inverse (mixed path)
 hipError_t launch_invert_blocks64(qax_problem* p, double* work);   // FP64 inverse
 hipError_t launch_factor_blocks64(qax_problem* p, double* work);   // FP64 inverse + FP32 roundings
+// every block mirror-symmetric: reduced inverses and the one-right-hand-side
+// apply through them (no-op otherwise); freed with the geometry
+hipError_t setup_sym_apply(qax_problem* p);
+void free_sym_apply(qax_problem* p);
 hipError_t launch_convert_f32(hipStream_t s, const double* src, float* dst, int64_t count);
 hipError_t launch_dense_offdiag(qax_problem* p, double* A);
 

@@ -11,7 +11,9 @@ through its four symmetry-reduced blocks.  Checked through the C interface:
   and, in the same problem, bodies without the symmetry (spiral, conch);
 * the FP32 factorisation (reduced blocks inverted in FP32): B (B^-1)_32 v = v
   to FP32 accuracy;
-* the mixed solver with the FP32 factorisation against the FP64 solver.
+* the mixed solver with the FP32 factorisation against the FP64 solver;
+* the inverse applied through the reduced blocks (every block symmetric)
+  against the expanded B^-1, FP64 (1e-13) and FP32.
 """
 
 import numpy as np
@@ -139,3 +141,31 @@ def test_mixed_solve_with_fp32_factorisation():
         a, b = x64.cpu().numpy(), xm.cpu().numpy()
     assert info["rel_res"] <= 1e-10
     assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-9
+
+
+def test_inverse_apply_through_reduced_blocks():
+    # every block symmetric: qax_block_apply with the inverse runs through the
+    # four reduced inverses; against the expanded B^-1 of each body (two
+    # bodies share a block), FP64 and FP32, and with the FP32 factorisation
+    specs = SYM + [SYM[0]]
+    s = sc.Scenario("sym", bodies(specs), np.array([2.5]), sc.paper_direction())
+    d = geo.discretize(s)
+    rng = np.random.default_rng(11)
+    for fact in (qax.QAX_FP64, qax.QAX_MIXED):
+        with qax.Problem(s) as P:
+            qax.qax_set_factorization(P.h, fact)
+            qax.qax_assemble_self(P.h)
+            v = rng.standard_normal(P.N) + 1j * rng.standard_normal(P.N)
+            vt = torch.from_numpy(v).to(DEV)
+            got = {}
+            for prec in (qax.QAX_MIXED, qax.QAX_FP64):
+                y = P.vec()
+                qax.qax_block_apply(P.h, 1, prec, vt, y)
+                got[prec] = y.cpu().numpy()
+            off = [int(x) for x in P.offsets]
+            for bi, body in enumerate(d.bodies):
+                sl = slice(off[bi], off[bi + 1])
+                ref = fetch(P, bi, body.n, inverse=True) @ v[sl]
+                scale = np.abs(ref).max()
+                assert np.abs(got[qax.QAX_FP64][sl] - ref).max() < 1e-13 * scale, (fact, bi)
+                assert np.abs(got[qax.QAX_MIXED][sl] - ref).max() < 1e-4 * scale, (fact, bi)
