@@ -410,11 +410,12 @@ __global__ void reduce_slots_kernel(const double2* __restrict__ partial, int slo
 // sums of its current row in registers across its columns and writes one
 // target slot per row; it accumulates the source sums of each column over
 // its rows in one source slot per column (read-modify-write by the thread
-// that owns the entry, in FP64).  Slots hold SYM_T complex128 values, so the
-// workspace is (ni + nj) SYM_T values per super-task, about 2 N nblk / S in
-// all; the super-tasks are split into launches whose slots fit a fixed cap,
-// each followed by a reduction that adds, per node, the slots of its block
-// in a fixed order (deterministic results).
+// that owns the entry).  Slots hold SYM_T complex values (complex128 for the
+// FP64 kernel, complex64 for the FP32 kernel), so the workspace is
+// (ni + nj) SYM_T values per super-task, N nblk / S in all; the super-tasks
+// are split into launches whose slots fit a fixed cap, each followed by a
+// reduction that adds, per node, the slots of its block in FP64 in a fixed
+// order (deterministic results).
 //
 // Lanes.  A workgroup is two wavefronts; lane l of wavefront w owns targets
 // w 128 + l and w 128 + 64 + l of block I.  The sources of block J pass in
