@@ -28,14 +28,16 @@ CAL_BYTES = 1 << 30
 
 # timing kind -> (kernel name pattern as rocprofv3 prints it, source file,
 # largest grids only); the single-right-hand-side instance with the most
-# launches is taken.  The inversion's update kernel also runs the 64-column
+# launches is taken (the FP32 preconditioner apply: the reduced-inverse
+# product when every block is mirror-symmetric).  The inversion's update kernel also runs the 64-column
 # sibling updates inside the panel factorization: the trailing updates are its
 # dispatches with the largest grid.
 KINDS = {
     "pair_sum_fp32": (r"qax::pair_sum_f32_sym_kernel<0>", "paper_2606_31380_amd/csrc/pairsum.hip", False),
     "pair_sum_fp64": (r"qax::pair_sum_f64_sym_kernel<0>", "paper_2606_31380_amd/csrc/pairsum.hip", False),
     "block_apply": (r"qax::block_gemv_kernel<double, 1, \d, \d+>", "paper_2606_31380_amd/csrc/dense.hip", False),
-    "block_apply_f32": (r"qax::block_gemv_f32_lds_kernel<\d>", "paper_2606_31380_amd/csrc/dense.hip", False),
+    "block_apply_f32": (r"qax::(block_gemv_f32_lds_kernel<\d>|sym_seg_gemv_kernel<float, 4>)",
+                        "paper_2606_31380_amd/csrc/dense.hip", False),
     "self_assembly": (r"qax::assemble_self_kernel<0>", "paper_2606_31380_amd/csrc/selfblock.hip", False),
     "invert_update": (r"qax::gjm_update_kernel<double>", "paper_2606_31380_amd/csrc/dense.hip", True),
 }
