@@ -487,8 +487,9 @@ __device__ __forceinline__ bool sym_inactive(const SymSuper& T, const int32_t* _
 // - i eta e^{ikr} |aw| mu / (4 pi r) per direction, i.e.
 // - i (ew / k^2) irs e^{ikr} mu in the same scaling (ew = eta |aw|).
 // Real parts are accumulated negated (one sign flip per slot).  Target sums
-// are FP32 per chunk and compensated (TwoSum) across chunks and columns;
-// source sums are FP32 over the chunk's 128 targets of a wavefront, then FP64.
+// are FP32 per chunk of at most 64 sources and FP64 across chunks and
+// columns; source sums are FP32 over the chunk's 128 targets of a
+// wavefront, then FP64.
 // A square's sums are stored rounded to complex64 slots (half the bytes of
 // complex128, so a launch holds twice the squares in the same workspace) and
 // the reduction adds the slots in FP64.
@@ -527,7 +528,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5))) void p
     float xx[2], xy[2], xz[2], nx[2], ny[2], nz[2], mr[2], mi[2], ew[2];
     int ab[2];
     bool act[2];
-    float nsr[2], ncr[2], tsi[2], tci[2];
+    double nsr[2], tsi[2];   // target sums of the row, FP64 across chunks and columns
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       const int loc = wv * 128 + t * 64 + lane;
@@ -542,7 +543,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5))) void p
       mi[t] = (float)m.y;
       ew[t] = FORM ? ew32[i] * ik2 : 0.0f;
       ab[t] = node_body[i];
-      nsr[t] = ncr[t] = tsi[t] = tci[t] = 0.0f;
+      nsr[t] = tsi[t] = 0.0;
     }
     for (int jj = 0; jj < T.nj; ++jj) {
       if (!((rowmask >> jj) & 1u)) continue;
@@ -621,9 +622,9 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5))) void p
         const float4* pY = &sY[lane];
         const float4* pW = &sW[lane];
         const float4* pM = &sM[lane];
-        for (int st0 = 0; st0 < nst; st0 += 4)
+        for (int st0 = 0; st0 < nst; st0 += 8)
 #pragma unroll
-        for (int st = st0; st < st0 + 4; ++st) {
+        for (int st = st0; st < st0 + 8; ++st) {
           const float4 Y = pY[st];
           const float4 W = pW[st];
           const float4 M = pM[st];
@@ -679,8 +680,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5))) void p
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
           if (!msk[t]) {
-            two_sum(nsr[t], ncr[t], nar[t]);
-            two_sum(tsi[t], tci[t], tai[t]);
+            nsr[t] += (double)nar[t];
+            tsi[t] += (double)tai[t];
           }
         }
         if (!dtask) {
@@ -714,8 +715,7 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(5))) void p
       const int loc = wv * 128 + t * 64 + lane;
       if (loc < BI.n)
         part[T.toff + (int64_t)ii * SYM_T + loc] =
-            make_float2((float)(-((double)nsr[t] + (double)ncr[t]) * sc3),
-                        (float)(((double)tsi[t] + (double)tci[t]) * sc3));
+            make_float2((float)(-nsr[t] * sc3), (float)(tsi[t] * sc3));
     }
   }
 }
