@@ -187,9 +187,22 @@ hipError_t launch_block_gemm(qax_problem* p, int inverse, int prec, const double
 
 static void launch_sym_apply(qax_problem* p, int prec, const double* v, double* out, bool accumulate);
 
+// B rounded to FP32 on first use after an FP64 factorisation (the FP32
+// factorisation makes it; solves with the FP64 factorisation never read it).
+static hipError_t ensure_b32(qax_problem* p) {
+  if (p->b32_ready) return hipSuccess;
+  hipError_t e = launch_convert_f32(p->stream, p->d_B, p->d_B32, 2 * p->block_elems);
+  if (e == hipSuccess) p->b32_ready = true;
+  return e;
+}
+
 hipError_t launch_block_apply(qax_problem* p, int inverse, int prec, const double* v, double* out,
                               int nrhs, bool accumulate) {
   const int kind = prec == QAX_MIXED ? QAX_K_BLOCK_APPLY_F32 : QAX_K_BLOCK_APPLY;
+  if (!inverse && prec == QAX_MIXED) {
+    hipError_t e = ensure_b32(p);
+    if (e != hipSuccess) return e;
+  }
   if (inverse && nrhs == 1 && p->symap.on && (prec == QAX_MIXED || p->inv64_ready)) {
     // every block mirror-symmetric: through the four reduced inverses
     timing_begin(p, kind);
@@ -1607,6 +1620,7 @@ hipError_t launch_invert_blocks(qax_problem* p, double* work) {
   plan_sym_inverse(p, sizeof(float2), P);
   // block_elems complex elements = block_elems (re, im) pairs; B rounded to
   // FP32 (and into the inverse pool where a block is inverted as it is)
+  p->b32_ready = true;
   if (P.plain.empty()) {
     hipError_t e = launch_convert_f32(p->stream, p->d_B, (float*)p->d_B32, 2 * p->block_elems);
     if (e != hipSuccess) return e;
@@ -1620,20 +1634,8 @@ hipError_t launch_invert_blocks(qax_problem* p, double* work) {
   return invert_blocks_sym<float>(p, P, (char*)work, (float2*)p->d_Binv32);
 }
 
-// B and its FP64 inverse rounded to FP32 (the mixed path's operator blocks
-// and preconditioner); two values per thread.
-__global__ void round_blocks_kernel(const double2* __restrict__ b, const double2* __restrict__ binv,
-                                    float2* __restrict__ b32, float2* __restrict__ binv32,
-                                    int64_t pairs) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= pairs) return;
-  const double2 u = b[e], v = binv[e];
-  b32[e] = make_float2((float)u.x, (float)u.y);
-  binv32[e] = make_float2((float)v.x, (float)v.y);
-}
-
-// Factorisation in FP64 for both paths: the FP64 inverse (below), then B and
-// B^-1 rounded to FP32 for the mixed path.
+// Factorisation in FP64 for both paths: the FP64 inverse (below), then B^-1
+// rounded to FP32 for the mixed path.
 hipError_t launch_factor_blocks64(qax_problem* p, double* work) {
   hipError_t e = launch_invert_blocks64(p, work);
   if (e != hipSuccess) return e;
@@ -1641,10 +1643,10 @@ hipError_t launch_factor_blocks64(qax_problem* p, double* work) {
     e = launch_convert_f32(p->stream, p->symap.d_Minv, p->symap.d_Minv32, 2 * p->symap.elems);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(round_blocks_kernel, dim3((unsigned)((p->block_elems + 255) / 256)), dim3(256), 0,
-                     p->stream, (const double2*)p->d_B, (const double2*)p->d_Binv, (float2*)p->d_B32,
-                     (float2*)p->d_Binv32, p->block_elems);
-  return hipGetLastError();
+  // B^-1 rounded to FP32 (the mixed path's preconditioner); B itself on
+  // first use (ensure_b32)
+  p->b32_ready = false;
+  return launch_convert_f32(p->stream, p->d_Binv, (float*)p->d_Binv32, 2 * p->block_elems);
 }
 
 // FP64 inverse: symmetric blocks through their four reduced blocks, the

@@ -180,6 +180,7 @@ struct qax_problem {
   int solver = QAX_SOLVER_LOCKSTEP;   // several right-hand sides: lockstep or block GMRES
   float* d_Binv32 = nullptr;
   float* d_B32 = nullptr;       // B rounded to FP32 (the mixed path's operator blocks)
+  bool b32_ready = false;       // d_B32 holds the current blocks (rounded on first use after an FP64 factorisation)
   // every block mirror-symmetric: the inverses also as their four reduced
   // blocks (complex128 valid with inv64_ready, complex64 after every
   // assembly), and the tables of the one-right-hand-side apply through them
