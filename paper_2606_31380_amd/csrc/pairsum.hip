@@ -440,9 +440,12 @@ __device__ __forceinline__ float from_next_lane(float x) {
 }
 
 __device__ __forceinline__ double from_next_lane(double x) {
+  // the rotation writes every lane, so the "old" operand is never used; with
+  // the source itself as old the move needs no zeroed destination first
   const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffLL), 0x134, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0x134, 0xf, 0xf, false);
+  const int vl = (int)(v & 0xffffffffLL), vh = (int)(v >> 32);
+  const int lo = __builtin_amdgcn_update_dpp(vl, vl, 0x134, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(vh, vh, 0x134, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
