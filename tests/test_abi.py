@@ -39,3 +39,14 @@ def test_binding_loads_and_matches_header():
     for n in declared():
         assert hasattr(L, n), n
     assert sorted(qax.EXPORTS) == declared()
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # no fallback: without the built library every entry point raises
+    from paper_2606_31380_amd import qax
+    monkeypatch.setattr(qax, "LIB_PATH", str(tmp_path / "libqax.so"))
+    monkeypatch.setattr(qax, "_LIB", None)
+    with pytest.raises(RuntimeError, match="not built"):
+        qax.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        qax.qax_create(0, 0)
