@@ -418,8 +418,8 @@ def main():
                     help="autotuner cache file (read if it has this problem, else written)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); how the solver would shard "
-              "over several GPUs is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
+              "multi-GPU path (sharding by bodies is designed, not built).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -287,7 +287,8 @@ def cubic_array(P=10, n_panels=1, n_theta=6, k=2.0, spacing=3.0) -> Scenario:
     """Regular cubic array of P^3 identical bent spheroids (0.5, 0.5, 1.0),
     kappa = 0.2, one orientation, spacing 3 (gap >= 1): the block-reuse
     configuration of Example 4 (1000 bodies, 16 x 6 = 96 nodes per body),
-    with bodies of this build's shape family."""
+    with bodies of the library's shape family (the quasi-ellipsoid of the
+    example replaced by a bent spheroid)."""
     return identical_array((P, P, P), (spacing,) * 3, n_panels=n_panels, n_theta=n_theta, k=k,
                            shuffle=False)
 
