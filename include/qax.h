@@ -132,7 +132,14 @@ qax_status qax_nodes(const qax_problem* p, double* d_pos, double* d_aw);
  * 3.1-3.4: modal Green's functions by recurrence, FFT and convolution; product
  * integration in s), then factor it: by default its inverse is computed in
  * FP64 (Gauss-Jordan with partial pivoting; the block-diagonal preconditioner
- * of Section 6) and B and B^-1 are rounded to FP32 for the mixed path.  With
+ * of Section 6) and B^-1 is rounded to FP32 for the mixed path (B itself is
+ * rounded to FP32 by the first call that applies it in FP32).  Bodies mapped
+ * onto themselves by both reflections theta -> -theta and t -> -t (sphere,
+ * spheroid and peanut, bent or not, and the quasi-ellipsoid) have a quarter of their rows assembled
+ * and the rest stored as images, and are inverted through four
+ * symmetry-reduced blocks; when every body is such, the handle also keeps
+ * the reduced inverses (FP64 and FP32, about a quarter of the inverse blocks'
+ * entries) and applies B^-1 to one right-hand side through them.  With
  * qax_set_factorization(p, QAX_MIXED) the inverse is instead computed in FP32
  * from B rounded to FP32, and the FP64 inverse is made by the first call that
  * needs it (qax_self_block with inverse, qax_block_apply with inverse in
